@@ -1,0 +1,265 @@
+"""Pins of the FP64 CPU oracle against things other than itself: LAPACK
+SVDs, matrices with prescribed singular values, closed-form sparse families,
+the spectrum of the augmented matrix (eq. B_Augmented), the stage-1 bracket
+(Section 3.1), the eq. (res) and orthonormality invariants, and published
+SplitMix64 outputs."""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import oracle.phsvds as P
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _lapack(A):
+    return np.linalg.svd(A.toarray(), full_matrices=False)
+
+
+def _check_triplets(A, sig, U, V, rn, ref_sig, tol, rel=1e-12):
+    Ad = A.toarray()
+    normA = np.linalg.norm(Ad, 2)
+    k = sig.size
+    assert np.max(np.abs(sig - ref_sig) / ref_sig) <= rel
+    # eq. (res) recomputed here from its definition
+    r = np.sqrt(np.linalg.norm(Ad @ V - U * sig, axis=0) ** 2 + np.linalg.norm(Ad.T @ U - V * sig, axis=0) ** 2)
+    assert np.all(r <= tol * normA * 1.000001)
+    assert np.allclose(r, rn, rtol=1e-6, atol=1e-3 * tol * normA)
+    assert np.abs(U.T @ U - np.eye(k)).max() <= 1e-12
+    assert np.abs(V.T @ V - np.eye(k)).max() <= 1e-12
+
+
+def test_splitmix64_published_outputs():
+    want = [int(l, 16) for l in open(os.path.join(GOLDEN, "splitmix64.txt")) if l.strip() and not l.startswith("#")]
+    got = oracle.counter_uniform(0, 0, 3, 1)[:, 0]
+    expect = np.array([(w >> 11) * 2.0 ** -53 - 0.5 for w in want])
+    assert np.array_equal(got, expect)
+
+
+def test_operators_follow_definitions():
+    rng = np.random.default_rng(0)
+    A = sp.random(7, 4, density=0.6, random_state=1, format="csr")
+    ops = P.Operators(A)
+    Ad = A.toarray()
+    X = rng.standard_normal((4, 3))
+    assert np.allclose(ops.C(X), Ad.T @ Ad @ X, rtol=1e-14, atol=1e-14)
+    Bd = np.block([[np.zeros((4, 4)), Ad.T], [Ad, np.zeros((7, 7))]])
+    Z = rng.standard_normal((11, 2))
+    assert np.allclose(ops.B(Z), Bd @ Z, rtol=1e-14, atol=1e-14)
+    assert ops.mv == 3 * 2 + 2 * 2
+
+
+def test_augmented_spectrum():
+    """eig(B) = {+sigma_i, -sigma_i, (m-n) zeros}, eigenvectors [v; +-u]/sqrt(2)."""
+    A = synth.random_uniform_rows(9, 5, 3, seed=4)
+    ops = P.Operators(A)
+    Bd = ops.B(np.eye(14))
+    lam = np.sort(np.linalg.eigvalsh(0.5 * (Bd + Bd.T)))
+    s = np.linalg.svd(A.toarray(), compute_uv=False)
+    want = np.sort(np.concatenate([s, -s, np.zeros(4)]))
+    assert np.allclose(lam, want, atol=1e-13)
+    Uf, sf, Vt = np.linalg.svd(A.toarray(), full_matrices=False)
+    x = np.concatenate([Vt[0], Uf[:, 0]]) / math.sqrt(2)
+    assert np.allclose(Bd @ x, sf[0] * x, atol=1e-13)
+
+
+def test_jacobi_diag_is_column_norms():
+    A = synth.config1()
+    assert np.allclose(oracle.jacobi_diag(A), np.sum(A.toarray() ** 2, axis=0), rtol=1e-14)
+
+
+def test_ortho_block_identity_and_breakdown():
+    rng = np.random.default_rng(2)
+    Q0, _ = np.linalg.qr(rng.standard_normal((200, 6)))
+    T = rng.standard_normal((200, 3))
+    Q, R, C = oracle.ortho_block(T, [Q0])
+    assert np.abs(Q.T @ Q - np.eye(3)).max() < 1e-14
+    assert np.abs(Q0.T @ Q).max() < 1e-14
+    assert np.allclose(Q0 @ C + Q @ R, T, atol=1e-13)
+    # a column that lies in the span and a duplicated column get replaced
+    T2 = np.column_stack([Q0[:, 1] * 3.0, T[:, 0], T[:, 0]])
+    cnt = {"c": 0}
+
+    def fresh(c):
+        cnt["c"] += 1
+        return oracle.counter_uniform(5, 100 + cnt["c"], 200, c)
+
+    Q2, _, _ = oracle.ortho_block(T2, [Q0], fresh)
+    assert cnt["c"] >= 1
+    assert np.abs(Q2.T @ Q2 - np.eye(3)).max() < 1e-14
+    assert np.abs(Q0.T @ Q2).max() < 1e-14
+
+
+def test_norm_estimate():
+    A = synth.config1()
+    ops = P.Operators(A)
+    est = oracle.estimate_norm(ops, seed=3)
+    true = np.linalg.norm(A.toarray(), 2)
+    assert est <= true * (1 + 1e-12)
+    assert abs(est - true) / true < 1e-6
+
+
+@pytest.mark.parametrize("target", ["largest", "smallest"])
+@pytest.mark.parametrize("force2", [False, True])
+def test_config1_against_lapack(target, force2):
+    A = synth.config1()
+    _, s, _ = _lapack(A)
+    ref = s[:5] if target == "largest" else np.sort(s)[:5]
+    sig, U, V, rn, st = oracle.svds(A, 5, target, 1e-10, max_basis=15, min_restart=6, block=1,
+                                    seed=11, force_stage2=force2)
+    assert st["converged"]
+    assert st["stage_exit"] == (2 if force2 else 1)
+    _check_triplets(A, sig, U, V, rn, ref, 1e-10)
+    # singular vectors against LAPACK (well separated here)
+    Uf, sf, Vt = _lapack(A)
+    idx = [int(np.argmin(np.abs(sf - x))) for x in sig]
+    assert np.all(np.abs(np.abs(np.sum(V * Vt[idx].T, axis=0)) - 1) < 1e-9)
+
+
+def test_sign_convention():
+    A = synth.config1()
+    _, _, V, _, _ = oracle.svds(A, 3, "largest", 1e-10, seed=1)
+    for j in range(3):
+        i = np.argmax(np.abs(V[:, j]))
+        assert V[i, j] > 0
+
+
+def test_prescribed_dense_double_singular_value():
+    n = 160
+    sig = np.linspace(0.5, 3.0, n)
+    sig[-2] = sig[-1]  # a double singular value at the top
+    A, s, Pm, Qm = synth.prescribed_dense(240, n, sig, seed=9)
+    out_sig, U, V, rn, st = oracle.svds(A, 4, "largest", 1e-10, block=2, seed=3)
+    ref = s[::-1][:4]
+    _check_triplets(A, out_sig, U, V, rn, ref, 1e-10, rel=1e-11)
+    # both vectors of the double value span the prescribed subspace
+    Qtop = Qm[:, np.argsort(sig)[::-1][:2]]
+    cosines = np.linalg.svd(Qtop.T @ V[:, :2], compute_uv=False)
+    assert np.all(cosines > 1 - 1e-10)
+
+
+def test_prescribed_givens_largest_at_scale():
+    n = 2000
+    rng = np.random.default_rng(5)
+    sig = np.sort(rng.uniform(0.1, 1.0, n))
+    sig[-6:] = [1.5, 1.7, 2.0, 2.4, 3.0, 4.0]
+    A, s = synth.prescribed_givens(4000, n, sig, seed=6)
+    out, U, V, rn, st = oracle.svds(A, 5, "largest", 1e-10, block=2, seed=2)
+    _check_triplets(A, out, U, V, rn, s[::-1][:5], 1e-10, rel=1e-12)
+
+
+def test_one_per_row_smallest_closed_form():
+    A = synth.one_per_row(3000, 1500, seed=8)
+    colnorm = np.sqrt(np.asarray(A.multiply(A).sum(axis=0)).ravel())
+    ref = np.sort(colnorm)[:5]
+    out, U, V, rn, st = oracle.svds(A, 5, "smallest", 1e-10, block=1, seed=2, precond="jacobi")
+    assert st["converged"]
+    assert np.max(np.abs(out - ref) / ref) < 1e-12
+
+
+def test_block_diagonal_union_of_block_svds():
+    A, blocks = synth.block_diagonal(400, 4, 2, seed=12)
+    ref = np.sort(np.concatenate([np.linalg.svd(b, compute_uv=False) for b in blocks]))[::-1][:6]
+    out, U, V, rn, st = oracle.svds(A, 6, "largest", 1e-10, block=2, seed=4)
+    assert st["converged"]
+    assert np.max(np.abs(out - ref) / ref) < 1e-12
+
+
+def test_wide_matrix_uses_smaller_gram():
+    A = synth.random_uniform_rows(300, 600, 12, seed=21)
+    _, s, _ = _lapack(A)
+    out, U, V, rn, st = oracle.svds(A, 4, "largest", 1e-10, seed=3)
+    assert U.shape == (300, 4) and V.shape == (600, 4)
+    _check_triplets(A, out, U, V, rn, s[:4], 1e-10)
+
+
+@pytest.mark.parametrize("target", ["largest", "smallest"])
+def test_stage2_refines_loose_stage1(target):
+    A = synth.config1()
+    _, s, _ = _lapack(A)
+    ref = s[:5] if target == "largest" else np.sort(s)[:5]
+    out, U, V, rn, st = oracle.svds(A, 5, target, 1e-10, max_basis=15, min_restart=6, seed=5,
+                                    stage1_tol=1e-4)
+    assert st["stage_exit"] == 2 and st["converged"]
+    assert st["iters"][1] > 0
+    _check_triplets(A, out, U, V, rn, ref, 1e-10)
+
+
+def test_stage2_needed_for_ill_conditioned_smallest():
+    """kappa ~ 2e6: the stage-1 criterion holds but eq. (res) does not, so
+    Algorithm 1 moves to stage 2 (steps 6-9)."""
+    A = synth.banded_scaled(300, 150, seed=1, log_lo=-6)
+    _, s, _ = _lapack(A)
+    out, U, V, rn, st = oracle.svds(A, 3, "smallest", 1e-10, block=1, seed=7, precond="jacobi")
+    assert st["stage_exit"] == 2 and st["converged"]
+    _check_triplets(A, out, U, V, rn, np.sort(s)[:3], 1e-10, rel=1e-9)
+
+
+def test_stage1_bracket():
+    """sigma_i in [sigma~ - sqrt(2)||r^C||/sigma~, sigma~] after stage 1
+    (Section 3.1), with ||r^C|| = sigma~ ||A^T u - sigma~ v||."""
+    A = synth.config1()
+    _, s, _ = _lapack(A)
+    ops = P.Operators(A)
+    st = {"iters": [0, 0], "restarts": [0, 0], "resets": 0}
+    normA = s[0]
+    Xk, _, _ = P._stage1(ops, 5, "smallest", 1e-5, normA, 35, 14, 1, 1, 3, None, 10**6, st, {"count": 0})
+    sig, U, V, rn = P._final_rr(ops, Xk, "smallest")
+    true = np.sort(s)[:5]
+    lower = sig - math.sqrt(2.0) * rn
+    assert np.all(true <= sig * (1 + 1e-14))
+    assert np.all(true >= lower)
+
+
+def test_null_space_vector_rejected():
+    """A null-space eigenvector [0; u_perp] of B has a tiny B-residual but
+    fails eq. (res) on its normalised halves (Section 3.1)."""
+    A = synth.random_uniform_rows(40, 10, 4, seed=3)
+    Uf, _, _ = np.linalg.svd(A.toarray(), full_matrices=True)
+    uperp = Uf[:, -1]
+    x = np.concatenate([np.zeros(10), uperp])
+    w = P.Operators(A).B(x[:, None])[:, 0]
+    assert np.linalg.norm(w) < 1e-13
+    assert P._halves_residual(x, w, 0.0, 10) == np.inf
+    x2 = np.concatenate([1e-9 * np.ones(10) / math.sqrt(10), uperp])
+    w2 = P.Operators(A).B(x2[:, None])[:, 0]
+    assert P._halves_residual(x2, w2, float(x2 @ w2), 10) > 1e-3
+
+
+def test_budget_exhaustion_reports_not_converged():
+    A = synth.config1()
+    out, U, V, rn, st = oracle.svds(A, 5, "smallest", 1e-10, max_matvecs=60, seed=1)
+    assert not st["converged"]
+    assert st["nconv"] < 5
+    assert out.shape == (5,) and np.all(np.isfinite(out))
+
+
+def test_fig1_example_shape():
+    """The C example of Fig. 1: 1000 x 100, four smallest, eps = 1e-12."""
+    A = synth.random_uniform_rows(1000, 100, 10, seed=31)
+    _, s, _ = _lapack(A)
+    out, U, V, rn, st = oracle.svds(A, 4, "smallest", 1e-12, seed=1)
+    assert st["converged"]
+    _check_triplets(A, out, U, V, rn, np.sort(s)[:4], 1e-12)
+
+
+def test_deterministic():
+    A = synth.config1()
+    a = oracle.svds(A, 3, "smallest", 1e-10, seed=9)
+    b = oracle.svds(A, 3, "smallest", 1e-10, seed=9)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+def test_rejects_bad_arguments():
+    A = synth.config1()
+    with pytest.raises(ValueError):
+        oracle.svds(A, 0, "largest")
+    with pytest.raises(ValueError):
+        oracle.svds(A, 3, "middle")
+    with pytest.raises(ValueError):
+        oracle.svds(A, 3, "largest", max_basis=8, min_restart=6, block=2)
