@@ -414,7 +414,7 @@ def _stage1(ops, k, target, tol, normA, g, r, b, p, seed, precond, budget, stats
             y_prev = None
             continue
         Yb = Y[:, block]
-        if S.g + len(block) > g:
+        if S.g + (len(block) if block else b) > g:
             # per-position stagnation bookkeeping, once per restart cycle
             improved = rn < 0.5 * best[:nc]
             best[:nc] = np.where(improved, rn, best[:nc])
@@ -682,8 +682,9 @@ def svds(A, k, target="largest", tol=1e-10, *, max_basis=None, min_restart=None,
     if not (1 <= k <= n):
         raise ValueError("k out of range")
     g, r, b, p = default_params(k, target, max_basis, min_restart, block, prev_retain)
-    if not (b >= 1 and g >= r + p + b and r >= 1 and g >= k + b):
-        raise ValueError("need max_basis >= min_restart + prev_retain + block and >= k + block")
+    if not (b >= 1 and g >= r + p + b and r >= 1 and min(g, n) >= k + b):
+        raise ValueError("need max_basis >= min_restart + prev_retain + block, and k + block "
+                         "within the basis and the smaller dimension")
     budget = max_matvecs if max_matvecs else 2_000_000
     stats = {"iters": [0, 0], "restarts": [0, 0], "resets": 0, "matvecs": [0, 0],
              "stage_exit": 1, "stage1_status": None, "norm_A_used": None, "nconv": 0,

@@ -1,0 +1,27 @@
+"""MI355X (gfx950) two-stage hybrid partial SVD (PHSVDS) -- Python binding.
+
+The binding only marshals arguments: device tensors (PyTorch is used for
+device memory and streams) are passed as raw pointers to the C ABI declared in
+include/svds.h, and every step of the solver runs in the library's HIP
+kernels.  If the built library is missing, importing the entry points raises.
+"""
+from ._lib import (  # noqa: F401
+    LARGEST,
+    SMALLEST,
+    FP64,
+    MIXED,
+    PC_NONE,
+    PC_JACOBI,
+    SvdsError,
+    Opts,
+    Stats,
+    library_path,
+    load_library,
+    opts_init,
+    error_string,
+    Matrix,
+    solve,
+    svds,
+    small_eig,
+    small_svd,
+)

@@ -1,0 +1,240 @@
+"""ctypes view of include/svds.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+LARGEST, SMALLEST = 0, 1
+FP64, MIXED = 0, 1
+PC_NONE, PC_JACOBI = 0, 1
+
+_STATUS = {0: "ok", 1: "not converged", -1: "invalid argument", -2: "malformed CSR",
+           -3: "device out of memory", -4: "HIP runtime error", -5: "numerical breakdown"}
+
+
+class SvdsError(RuntimeError):
+    def __init__(self, code, what=""):
+        super().__init__(f"svds status {code} ({_STATUS.get(code, 'unknown')}) {what}".strip())
+        self.code = code
+
+
+class Csr(C.Structure):
+    _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("nnz", C.c_int64),
+                ("rowptr", C.c_void_p), ("colind", C.c_void_p), ("values", C.c_void_p)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("max_basis_size", C.c_int), ("min_restart_size", C.c_int),
+                ("block_size", C.c_int), ("max_prev_retain", C.c_int),
+                ("max_matvecs", C.c_int64), ("norm_A", C.c_double), ("stage1_tol", C.c_double),
+                ("seed", C.c_uint64), ("precision", C.c_int), ("precond", C.c_int),
+                ("force_stage2", C.c_int), ("two_sided_cleanup", C.c_int),
+                ("print_level", C.c_int)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("nconv", C.c_int), ("stage_exit", C.c_int), ("stage1_status", C.c_int),
+                ("pad_", C.c_int), ("matvecs", C.c_int64 * 2), ("iters", C.c_int64 * 2),
+                ("restarts", C.c_int64 * 2), ("resets", C.c_int64), ("breakdowns", C.c_int64),
+                ("seconds", C.c_double * 2), ("setup_seconds", C.c_double),
+                ("norm_A_used", C.c_double)]
+
+    def to_dict(self):
+        return {"nconv": self.nconv, "stage_exit": self.stage_exit,
+                "stage1_status": ["converged", "floor", "budget"][self.stage1_status],
+                "matvecs": list(self.matvecs), "iters": list(self.iters),
+                "restarts": list(self.restarts), "resets": self.resets,
+                "breakdowns": self.breakdowns, "seconds": list(self.seconds),
+                "setup_seconds": self.setup_seconds, "norm_A_used": self.norm_A_used}
+
+
+_lib = None
+
+
+def library_path():
+    return os.environ.get("SVDS_LIBRARY", os.path.join(HERE, "libsvds_hip.so"))
+
+
+def load_library():
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} (run paper_1607_01404_amd.build)")
+    lib = C.CDLL(path)
+    vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int, C.c_double
+    lib.svds_opts_init.argtypes = [C.POINTER(Opts)]
+    lib.svds_error_string.argtypes = [i32]
+    lib.svds_error_string.restype = C.c_char_p
+    lib.svds_matrix_create.argtypes = [C.POINTER(Csr), C.POINTER(vp), vp]
+    lib.svds_matrix_destroy.argtypes = [vp]
+    lib.svds_matrix_spmm.argtypes = [vp, i32, i32, vp, vp, vp]
+    lib.svds_solve.argtypes = [C.POINTER(Csr), i32, i32, dbl, C.POINTER(Opts), vp, vp, i64, vp,
+                               i64, vp, C.POINTER(Stats), vp]
+    lib.svds_solve_prepared.argtypes = [vp, i32, i32, dbl, C.POINTER(Opts), vp, vp, i64, vp,
+                                        i64, vp, C.POINTER(Stats), vp]
+    lib.svds_small_eig.argtypes = [i32, vp, i64, i32, vp, vp, i64, vp]
+    lib.svds_small_svd.argtypes = [i32, vp, i64, vp, vp, i64, vp]
+    _lib = lib
+    return lib
+
+
+def _check(rc, what=""):
+    if rc < 0:
+        raise SvdsError(rc, what)
+    return rc
+
+
+def error_string(code):
+    return load_library().svds_error_string(code).decode()
+
+
+def opts_init(**kw):
+    o = Opts()
+    _check(load_library().svds_opts_init(C.byref(o)))
+    for key, val in kw.items():
+        if not hasattr(o, key):
+            raise TypeError(f"unknown option {key}")
+        setattr(o, key, val)
+    return o
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _csr(indptr, indices, data, m, n):
+    import torch
+    assert indptr.is_cuda and indices.is_cuda and data.is_cuda
+    assert indptr.dtype == torch.int64 and indices.dtype == torch.int32 and data.dtype == torch.float64
+    assert indptr.is_contiguous() and indices.is_contiguous() and data.is_contiguous()
+    return Csr(m, n, int(indices.numel()), indptr.data_ptr(), indices.data_ptr(), data.data_ptr())
+
+
+def to_device(A, device="cuda"):
+    """Upload a scipy CSR matrix (int64 indptr, int32 indices, float64 data)."""
+    import numpy as np
+    import torch
+    indptr = torch.from_numpy(np.ascontiguousarray(A.indptr, dtype=np.int64)).to(device)
+    indices = torch.from_numpy(np.ascontiguousarray(A.indices, dtype=np.int32)).to(device)
+    data = torch.from_numpy(np.ascontiguousarray(A.data, dtype=np.float64)).to(device)
+    return indptr, indices, data
+
+
+class Matrix:
+    """A prepared matrix (svds_matrix_create) over device CSR tensors."""
+
+    def __init__(self, indptr, indices, data, m, n, stream=None):
+        self._keep = (indptr, indices, data)
+        self.m, self.n = int(m), int(n)
+        self.csr = _csr(indptr, indices, data, self.m, self.n)
+        lib = load_library()
+        h = C.c_void_p()
+        _check(lib.svds_matrix_create(C.byref(self.csr), C.byref(h), _stream(stream)), "create")
+        self.handle = h
+
+    @classmethod
+    def from_scipy(cls, A, device="cuda", stream=None):
+        ip, ix, dv = to_device(A, device)
+        return cls(ip, ix, dv, A.shape[0], A.shape[1], stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().svds_matrix_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def spmm(self, X, trans=False, stream=None):
+        """Y = A X (trans=False, X: n x b) or A^T X (X: m x b); row-major blocks."""
+        import torch
+        b = X.shape[1]
+        rows = self.n if trans else self.m
+        assert X.shape[0] == (self.m if trans else self.n) and X.is_contiguous()
+        Y = torch.empty((rows, b), dtype=torch.float64, device=X.device)
+        _check(load_library().svds_matrix_spmm(self.handle, int(trans), b, _ptr(X), _ptr(Y),
+                                               _stream(stream)), "spmm")
+        return Y
+
+    def solve(self, k, target="largest", tol=1e-10, stream=None, **opts):
+        return _solve(lambda *a: load_library().svds_solve_prepared(self.handle, *a),
+                      self.m, self.n, k, target, tol, stream, opts)
+
+
+def _solve(call, m, n, k, target, tol, stream, opts):
+    import torch
+    tgt = {"largest": LARGEST, "smallest": SMALLEST}[target] if isinstance(target, str) else target
+    o = opts_init(**opts)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    sigma = torch.empty(k, dtype=torch.float64, device=dev)
+    rnorm = torch.empty(k, dtype=torch.float64, device=dev)
+    # column-major outputs: allocate (k, m) row-major = (m, k) column-major
+    Ut = torch.empty((k, m), dtype=torch.float64, device=dev)
+    Vt = torch.empty((k, n), dtype=torch.float64, device=dev)
+    st = Stats()
+    rc = call(k, tgt, float(tol), C.byref(o), _ptr(sigma), _ptr(Ut), m, _ptr(Vt), n, _ptr(rnorm),
+              C.byref(st), _stream(stream))
+    _check(rc, "solve")
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    stats = st.to_dict()
+    stats["status"] = rc
+    stats["converged"] = rc == 0
+    return sigma, Ut.t(), Vt.t(), rnorm, stats
+
+
+def solve(indptr, indices, data, m, n, k, target="largest", tol=1e-10, stream=None, **opts):
+    """svds_solve on device CSR tensors.  Returns (sigma, U, V, rnorm, stats)
+    with U (m x k) and V (n x k) as column-major views."""
+    csr = _csr(indptr, indices, data, int(m), int(n))
+    return _solve(lambda *a: load_library().svds_solve(C.byref(csr), *a), int(m), int(n), k,
+                  target, tol, stream, opts)
+
+
+def svds(A, k, target="largest", tol=1e-10, device="cuda", **opts):
+    """Convenience: upload a scipy CSR matrix and solve."""
+    ip, ix, dv = to_device(A, device)
+    return solve(ip, ix, dv, A.shape[0], A.shape[1], k, target, tol, **opts)
+
+
+def small_eig(H, descending=False, stream=None):
+    """Device Jacobi eigensolver of a symmetric g x g matrix: eigenvalues in
+    ascending (or descending) order and eigenvectors as columns."""
+    import torch
+    g = H.shape[0]
+    Hcm = H.t().contiguous()  # column-major storage of H
+    theta = torch.empty(g, dtype=torch.float64, device=H.device)
+    Yt = torch.empty((g, g), dtype=torch.float64, device=H.device)
+    _check(load_library().svds_small_eig(g, _ptr(Hcm), g, int(descending), _ptr(theta), _ptr(Yt),
+                                         g, _stream(stream)), "small_eig")
+    torch.cuda.synchronize()
+    del Hcm
+    return theta, Yt.t()
+
+
+def small_svd(R, stream=None):
+    """Device one-sided Jacobi SVD of a g x g matrix: ascending singular values
+    and right singular vectors as columns."""
+    import torch
+    g = R.shape[0]
+    Rcm = R.t().contiguous()
+    s = torch.empty(g, dtype=torch.float64, device=R.device)
+    Yt = torch.empty((g, g), dtype=torch.float64, device=R.device)
+    _check(load_library().svds_small_svd(g, _ptr(Rcm), g, _ptr(s), _ptr(Yt), g, _stream(stream)),
+           "small_svd")
+    torch.cuda.synchronize()
+    del Rcm
+    return s, Yt.t()

@@ -1,0 +1,170 @@
+// Internal declarations shared by the HIP kernels and the host driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+#include "svds.h"
+
+namespace svds {
+
+// ---------------------------------------------------------------------------
+// errors: thrown inside the library, turned into status codes at the ABI
+// ---------------------------------------------------------------------------
+struct Error : public std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define SVDS_HIP(call)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      throw ::svds::Error(e_ == hipErrorOutOfMemory ? SVDS_ERR_OOM : SVDS_ERR_HIP,       \
+                          std::string(#call) + ": " + hipGetErrorString(e_));           \
+  } while (0)
+
+#define SVDS_LAUNCH_CHECK() SVDS_HIP(hipGetLastError())
+
+constexpr int kWave = 64;          // CDNA wavefront
+constexpr int kMaxBasis = 64;      // g <= 64 (small problems fit one workgroup)
+constexpr int kMaxBlock = 8;       // b <= 8
+constexpr int kSmallThreads = 256; // threads of the single-workgroup kernels
+
+// Thresholds shared with the decisions of the method (values, not code, are
+// common with the CPU reference: they are part of the method's definition).
+constexpr double kEps = 2.220446049250313e-16;  // FP64 machine precision
+constexpr double kBreakRatio = 1e-7;    // Cholesky pivot / column norm: dependent
+constexpr double kCollapse = 1e-12;     // norm after / before projection: in span
+constexpr double kPrevDrop = 1e-10;     // +k direction dropped below this norm
+constexpr int kStallRestarts = 3;       // restarts without halving = stalled
+constexpr double kFloorGate = 1e4;      // stalled below kFloorGate*eps*||Op||
+
+// Counter streams of the random vectors
+constexpr uint64_t kStreamInit = 0, kStreamNorm = 1, kStreamBreak = 2;
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+template <int L>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// MI355X dispatches consecutive workgroups round-robin over its 8 XCDs.  This
+// maps the hardware block index to a logical one so that logical neighbours
+// (adjacent row ranges, which share gathered vector entries) run on the same
+// XCD and share its L2.
+__device__ __forceinline__ int xcd_block(int bid, int nblocks) {
+  constexpr int kXcd = 8;
+  if (nblocks < kXcd || (nblocks % kXcd) != 0) return bid;
+  return (bid % kXcd) * (nblocks / kXcd) + bid / kXcd;
+}
+
+// SplitMix64 finaliser (Steele, Lea and Flood 2014) on seed + (counter+1)*gamma;
+// uniform in [-0.5, 0.5) from the top 53 bits.
+__host__ __device__ __forceinline__ double counter_uniform(uint64_t seed, uint64_t stream,
+                                                           uint64_t col, uint64_t row) {
+  uint64_t ctr = (stream << 40) + (col << 32) + row;
+  uint64_t z = seed + (ctr + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  return (double)(z >> 11) * 0x1.0p-53 - 0.5;
+}
+
+// ---------------------------------------------------------------------------
+// prepared matrix (device)
+// ---------------------------------------------------------------------------
+constexpr int kNumBins = 8;  // lanes per row 1,2,4,8,16,32,64, and 256 (workgroup)
+
+struct Csr32 {
+  int64_t rows = 0, cols = 0, nnz = 0;
+  int32_t* rp = nullptr;   // rows+1
+  int32_t* ci = nullptr;   // nnz
+  double* val = nullptr;   // nnz
+  float* val32 = nullptr;  // nnz, FP32 copy for the mixed-precision stage 1
+  int32_t* binrows = nullptr;       // rows, grouped by bin, row order kept
+  int64_t bin_off[kNumBins + 1] = {0};
+};
+
+}  // namespace svds
+
+struct svds_matrix {
+  int64_t m = 0, n = 0, nnz = 0;  // of the caller's A
+  bool transposed = false;         // true when m < n: work matrix is A^T
+  svds::Csr32 A;                   // work matrix (tall): rows >= cols
+  svds::Csr32 At;                  // its transpose
+  double* diagC = nullptr;         // diag(A_w^T A_w) (length A.cols)
+  int device = 0;
+};
+
+namespace svds {
+
+// ---------------------------------------------------------------------------
+// launchers (kernels live in the k_*.hip files)
+// ---------------------------------------------------------------------------
+// setup
+void check_csr(const svds_csr& A, int* d_flag, hipStream_t s);
+void rowptr_to32(const int64_t* rp, int32_t* rp32, int64_t m, hipStream_t s);
+void copy_csr_arrays(const svds_csr& A, Csr32& out, hipStream_t s);
+void transpose_csr(const Csr32& A, Csr32& T, int32_t* d_tmp_cursor, hipStream_t s);
+void build_bins(Csr32& A, hipStream_t s);
+void row_sqnorms(const Csr32& A, double* out, hipStream_t s);
+void to_fp32(const double* in, float* out, int64_t n, hipStream_t s);
+void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t s);
+void fill_random(double* X, int64_t ld, int64_t N, int ncols, uint64_t seed, uint64_t stream,
+                 int col0, hipStream_t s);
+
+// SpMM: Y (rows x b, row-major) = A X (cols x b, row-major)
+void spmm(const Csr32& A, int b, const double* X, double* Y, hipStream_t s);
+void spmm_f32(const Csr32& A, int b, const float* X, float* Y, hipStream_t s);
+
+// dense tall-skinny (column-major, FP64 unless noted)
+struct Seg {
+  const double* p;
+  int ncols;
+  int64_t ld;
+};
+int reduce_blocks(int64_t N);
+// C ((sum of seg cols) x b, col-major, ld = total) = [segs]^T T
+void tsgemm_tn(const Seg* segs, int nseg, int64_t N, const double* T, int64_t ldt, int b,
+               double* partial, double* C, hipStream_t s);
+// T -= [segs] C   (C: total x b, column-major with leading dimension ldc)
+void ts_update(const Seg* segs, int nseg, int64_t N, const double* C, int ldc, double* T,
+               int64_t ldt, int b, hipStream_t s);
+// Out (N x nout) = Q (N x nq) Y (nq x nout, ld ldy); Out may not alias Q
+void ts_gemm_nn(const double* Q, int64_t ldq, int nq, int64_t N, const double* Y, int64_t ldy,
+                int nout, double* Out, int64_t ldo, hipStream_t s);
+// T <- T Rinv (b x b upper), optionally also writes a row-major copy
+void ts_scale(double* T, int64_t ldt, int64_t N, int b, const double* Rinv, double* compact,
+              hipStream_t s);
+// fused residual for nc candidates: R = W Y - V Y diag(theta); per-candidate
+// sums (rows < nsplit | rows >= nsplit): ||r||^2, x.r, ||x||^2 each
+void ts_residual(const double* V, const double* W, int64_t ld, int64_t N, int64_t nsplit, int g,
+                 const double* Y, int64_t ldy, const double* theta, int nc, double* R,
+                 int64_t ldr, double* partial, double* sums, hipStream_t s);
+void pack_rows(const double* A, int64_t lda, const double* B, double beta, int64_t N, int b,
+               double* compact, hipStream_t s);  // compact = A + beta*B (B may be null)
+void unpack_rows(const double* compact, int64_t N, int b, double* A, int64_t lda, hipStream_t s);
+// T[:, j] = R[:, blk[j]] * dinv  (dinv may be null); blk on device
+void gather_precond(const double* R, int64_t ldr, const int* d_blk, int nb, const double* dinv,
+                    int64_t N, double* T, int64_t ldt, hipStream_t s);
+void scale_rows(double* T, int64_t ldt, int64_t N, int b, const double* dinv, hipStream_t s);
+void copy_cols(const double* A, int64_t lda, int64_t N, int b, double* B, int64_t ldb,
+               hipStream_t s);
+
+// small single-workgroup kernels (all on device, FP64)
+struct SmallState;  // defined in small.h
+}  // namespace svds

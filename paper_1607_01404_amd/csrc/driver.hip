@@ -1,0 +1,999 @@
+// Host driver of the two-stage hybrid SVD (Algorithm 1) and the C ABI.
+//
+// Everything numerical runs in the library's kernels on one GPU; the host
+// enqueues them on the caller's stream and reads back one small decision
+// record per iteration (the Ctl struct written by the control kernel), plus a
+// breakdown flag after each block orthogonalisation.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "small.h"
+
+namespace svds {
+
+// launchers defined in k_dense.hip / k_final.hip
+void col_residual2(const double* A, int64_t lda, const double* B, int64_t ldb, const double* sc,
+                   int64_t N, int k, double* partial, double* out, hipStream_t s);
+void col_scale(double* X, int64_t ld, int64_t N, int k, const double* f, hipStream_t s);
+void sign_factors(const double* V, int64_t ldv, int64_t N, int k, double* partial, double* f,
+                  hipStream_t s);
+void sigma_from_lambda(int k, const double* lam, double* sig, double* inv, hipStream_t s);
+void stage1_check(int k, const double* rl2, const double* rr2, const double* sig, double normA,
+                  double tol, double* rn, double* taus, int* ok, hipStream_t s);
+void sqrt_sum(int k, const double* a, const double* b, double* out, hipStream_t s);
+void inv_sqrt(int k, const double* x, double* f, hipStream_t s);
+void abs_vec(int k, const double* x, double* y, hipStream_t s);
+void cleanup_finish(int k, const double* s, const double* Yq, int ldy, const double* AVq,
+                    int ldav, int descending, double* sig, double* P, double* Q, int ldk,
+                    hipStream_t st);
+
+namespace {
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+template <typename T>
+T* dalloc(size_t n, hipStream_t s) {
+  T* p = nullptr;
+  if (n == 0) n = 1;
+  SVDS_HIP(hipMallocAsync((void**)&p, sizeof(T) * n, s));
+  return p;
+}
+
+struct DeviceBuffers {
+  std::vector<void*> ptrs;
+  hipStream_t s;
+  explicit DeviceBuffers(hipStream_t st) : s(st) {}
+  template <typename T>
+  T* get(size_t n) {
+    T* p = dalloc<T>(n, s);
+    ptrs.push_back(p);
+    return p;
+  }
+  ~DeviceBuffers() {
+    for (void* p : ptrs) (void)hipFreeAsync(p, s);
+  }
+};
+
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// The solver state of one svds call
+// ---------------------------------------------------------------------------
+class Solver {
+ public:
+  Solver(const svds_matrix* M, int k, int target, double tol, const svds_opts& o, hipStream_t s)
+      : M_(M), k_(k), target_(target), tol_(tol), o_(o), s_(s), buf_(s) {
+    m_ = M->A.rows;
+    n_ = M->A.cols;
+    largest_ = target == SVDS_LARGEST;
+    g_ = o.max_basis_size;
+    r_ = o.min_restart_size;
+    if (g_ <= 0 || r_ <= 0) {
+      const bool small = largest_ && k < 10;
+      if (g_ <= 0) g_ = small ? 15 : 35;
+      if (r_ <= 0) r_ = small ? 6 : 14;
+    }
+    b_ = o.block_size > 0 ? o.block_size : 1;
+    p_ = o.max_prev_retain >= 0 ? o.max_prev_retain : b_;
+    budget_ = o.max_matvecs > 0 ? o.max_matvecs : 2000000;
+    tol1_ = o.stage1_tol > 0 ? o.stage1_tol : tol;
+    if (b_ > kMaxBlock || g_ > kGmax || k > kKmax || g_ < r_ + p_ + b_ || g_ < k + b_ || r_ < 1 ||
+        p_ < 0)
+      throw Error(SVDS_ERR_ARG, "basis parameters out of range");
+    if (std::min<int64_t>(g_, n_) < k + b_)
+      throw Error(SVDS_ERR_ARG, "k + block size exceeds the smaller dimension or the basis");
+  }
+
+  int run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, double* rnorm,
+          svds_stats* st);
+
+ private:
+  // ---- configuration
+  const svds_matrix* M_;
+  int k_, target_;
+  double tol_, tol1_;
+  svds_opts o_;
+  hipStream_t s_;
+  DeviceBuffers buf_;
+  int64_t m_, n_;
+  bool largest_;
+  int g_, r_, b_, p_;
+  int64_t budget_;
+  double normA_ = 0.0;
+
+  // ---- per-stage state
+  int stage_ = 1;
+  int64_t N_ = 0;      // operator dimension
+  int gc_ = 0;         // basis size
+  int nlock_ = 0;
+  bool refined_ = false;
+  double tau_ = 0.0;
+  int64_t ld_ = 0;     // leading dimension of the basis arrays
+  int rand_count_ = 0;
+  int64_t mv_ = 0;     // matrix-vector products (columns times A or A^T)
+  int64_t breakdowns_ = 0;
+
+  // ---- device buffers
+  double *V_ = nullptr, *W_ = nullptr, *Vt_ = nullptr, *Wt_ = nullptr;
+  double *Q_ = nullptr, *Qt_ = nullptr, *X_ = nullptr, *R_ = nullptr, *Z_ = nullptr;
+  double *Tc_ = nullptr, *Yc_ = nullptr, *Wc_ = nullptr, *Zc_ = nullptr;
+  double* partial_ = nullptr;
+  double* dinv_ = nullptr;  // 1 / diag(A^T A) (ones where zero)
+  Small* d_ = nullptr;
+  Ctl* hctl_ = nullptr;     // pinned
+  int* hbad_ = nullptr;     // pinned
+  double* vec_ = nullptr;   // small device vectors (k-sized)
+
+  // ---- operators -----------------------------------------------------------
+  const Csr32& A() const { return M_->A; }
+  const Csr32& At() const { return M_->At; }
+
+  // W block (compact, N x nb) = Op T block (compact)
+  void apply_op(const double* Tc, double* Wc, int nb) {
+    if (stage_ == 1) {
+      spmm(A(), nb, Tc, Yc_, s_);   // m x nb
+      spmm(At(), nb, Yc_, Wc, s_);  // n x nb
+    } else {
+      spmm(At(), nb, Tc + n_ * nb, Wc, s_);  // v-half: A^T x_u
+      spmm(A(), nb, Tc, Wc + n_ * nb, s_);   // u-half: A x_v
+    }
+    mv_ += 2 * nb;
+  }
+
+  // ---- orthogonalisation: CGS twice against segs, Cholesky QR twice ----------
+  int ortho_once(double* T, int64_t ldt, int nb, const Seg* segs, int nseg, double* compact) {
+    int total = 0;
+    for (int i = 0; i < nseg; ++i) total += segs[i].ncols;
+    SVDS_HIP(hipMemsetAsync(&d_->bad, 0, sizeof(int), s_));
+    Seg s1[3];
+    int n1 = 0;
+    for (int i = 0; i < nseg; ++i)
+      if (segs[i].ncols > 0) s1[n1++] = segs[i];
+    Seg sb[3];
+    for (int i = 0; i < n1; ++i) sb[i] = s1[i];
+    s1[n1] = Seg{T, nb, ldt};
+    // pass 1 with the block's own Gram (pre-projection norms) appended
+    tsgemm_tn(s1, n1 + 1, N_, T, ldt, nb, partial_, d_->C0, s_);
+    if (total > 0) {
+      ts_update(sb, n1, N_, d_->C0, total + nb, T, ldt, nb, s_);
+      tsgemm_tn(sb, n1, N_, T, ldt, nb, partial_, d_->C1, s_);
+      ts_update(sb, n1, N_, d_->C1, total, T, ldt, nb, s_);
+    }
+    Seg st{T, nb, ldt};
+    tsgemm_tn(&st, 1, N_, T, ldt, nb, partial_, d_->G, s_);
+    small_chol(d_, nb, 1, total, s_);
+    ts_scale(T, ldt, N_, nb, d_->R1inv, nullptr, s_);
+    tsgemm_tn(&st, 1, N_, T, ldt, nb, partial_, d_->G, s_);
+    small_chol(d_, nb, 2, total, s_);
+    ts_scale(T, ldt, N_, nb, d_->R2inv, compact, s_);
+    SVDS_HIP(hipMemcpyAsync(hbad_, &d_->bad, sizeof(int), hipMemcpyDeviceToHost, s_));
+    SVDS_HIP(hipStreamSynchronize(s_));
+    return *hbad_;
+  }
+
+  // with breakdown repair: dependent columns get fresh counter-based vectors
+  void ortho(double* T, int64_t ldt, int nb, const Seg* segs, int nseg, double* compact) {
+    for (int attempt = 0; attempt < 4; ++attempt) {
+      int bad = ortho_once(T, ldt, nb, segs, nseg, compact);
+      if (!bad) return;
+      ++breakdowns_;
+      const uint64_t stream = kStreamBreak + (uint64_t)rand_count_++;
+      int i = 0;
+      for (int j = 0; j < nb; ++j)
+        if (bad & (1 << j)) fill_random(T + j * ldt, ldt, N_, 1, o_.seed, stream, i++, s_);
+    }
+    throw Error(SVDS_ERR_BREAKDOWN, "repeated orthogonalisation breakdown");
+  }
+
+  // ---- basis expansion ---------------------------------------------------------
+  // V[:, gc:gc+nb] is orthonormal and Tc_ holds it row-major
+  void append(int nb) {
+    double* Tcol = V_ + gc_ * ld_;
+    apply_op(Tc_, Wc_, nb);
+    double* Wcol = W_ + gc_ * ld_;
+    unpack_rows(Wc_, N_, nb, Wcol, ld_, s_);
+    Seg sv{V_, gc_ + nb, ld_};
+    tsgemm_tn(&sv, 1, N_, Wcol, ld_, nb, partial_, d_->Hn, s_);
+    small_h_append(d_, gc_, nb, s_);
+    if (refined_) {
+      // Z = W_new - tau T, orthogonalised against Q: new columns of Rr
+      double* Zcol = Q_ + gc_ * ld_;
+      pack_rows(Wcol, ld_, Tcol, -tau_, N_, nb, Zc_, s_);
+      unpack_rows(Zc_, N_, nb, Zcol, ld_, s_);
+      Seg sq{Q_, gc_, ld_};
+      refined_ortho(Zcol, nb, &sq, gc_ > 0 ? 1 : 0);
+      small_rr_append(d_, gc_, nb, gc_, s_);
+    }
+    gc_ += nb;
+  }
+
+  // orthogonalisation of a Z block for the refined factor: a dependent
+  // column keeps its projection coefficients and gets a fresh orthogonal
+  // direction with a zero diagonal entry
+  void refined_ortho(double* Zcol, int nb, const Seg* sq, int nseg) {
+    int bad = ortho_once(Zcol, ld_, nb, sq, nseg, nullptr);
+    if (bad) {
+      ++breakdowns_;
+      throw Error(SVDS_ERR_BREAKDOWN, "refined factor breakdown");
+    }
+  }
+
+  void extract_stage() {
+    const int desc = (stage_ == 1) ? (largest_ ? 1 : 0) : 1;
+    small_extract(d_, gc_, desc, refined_ ? 1 : 0, s_);
+  }
+
+  void restart_basis(int nr) {
+    ts_gemm_nn(V_, ld_, gc_, N_, d_->Yr, kLd, nr, Vt_, ld_, s_);
+    ts_gemm_nn(W_, ld_, gc_, N_, d_->Yr, kLd, nr, Wt_, ld_, s_);
+    std::swap(V_, Vt_);
+    std::swap(W_, Wt_);
+    if (refined_) {
+      ts_gemm_nn(Q_, ld_, gc_, N_, d_->Qt, kLd, nr, Qt_, ld_, s_);
+      std::swap(Q_, Qt_);
+    }
+    gc_ = nr;
+  }
+
+  // rebuild Q, Rr of (W - tau V) for the current basis (after a lock or reset)
+  void rebuild_refined() {
+    for (int c0 = 0; c0 < gc_; c0 += kMaxBlock) {
+      const int nb = std::min(kMaxBlock, gc_ - c0);
+      double* Zcol = Q_ + c0 * ld_;
+      pack_rows(W_ + c0 * ld_, ld_, V_ + c0 * ld_, -tau_, N_, nb, Zc_, s_);
+      unpack_rows(Zc_, N_, nb, Zcol, ld_, s_);
+      Seg sq{Q_, c0, ld_};
+      refined_ortho(Zcol, nb, &sq, c0 > 0 ? 1 : 0);
+      small_rr_append(d_, c0, nb, c0, s_);
+    }
+  }
+
+  // re-orthonormalise V (against locked vectors) and recompute W, H (Section 3.2)
+  void reset() {
+    const int gold = gc_;
+    std::swap(V_, Vt_);  // old basis now in Vt_
+    gc_ = 0;
+    const bool was_refined = refined_;
+    refined_ = false;  // the refined factor is rebuilt afterwards
+    for (int c0 = 0; c0 < gold; c0 += kMaxBlock) {
+      const int nb = std::min(kMaxBlock, gold - c0);
+      double* T = V_ + gc_ * ld_;
+      copy_cols(Vt_ + c0 * ld_, ld_, N_, nb, T, ld_, s_);
+      Seg segs[2] = {Seg{X_, nlock_, ld_}, Seg{V_, gc_, ld_}};
+      ortho(T, ld_, nb, segs, 2, Tc_);
+      append(nb);
+    }
+    refined_ = was_refined;
+    if (refined_) rebuild_refined();
+  }
+
+  void residual(int nc, int64_t nsplit) {
+    ts_residual(V_, W_, ld_, N_, nsplit, gc_, d_->Y, kLd, d_->theta, nc, R_, ld_, partial_,
+                d_->sums, s_);
+  }
+
+  Ctl control(const CtlParams& p) {
+    small_control(d_, p, s_);
+    SVDS_HIP(hipMemcpyAsync(hctl_, &d_->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s_));
+    SVDS_HIP(hipStreamSynchronize(s_));
+    return *hctl_;
+  }
+
+  void trace(const char* what, int it, const Ctl& c, int nc) {
+    if (o_.print_level < 3) return;
+    std::fprintf(stderr, "[svds] stage %d %s it %d g %d act %d nb %d rs %d nr %d res0 %.3e maxres %.3e val0 %.12e mv %lld\n",
+                 stage_, what, it, gc_, c.action, c.nblock, c.restart, c.nr, nc > 0 ? c.res[0] : 0.0,
+                 c.maxres, nc > 0 ? c.val[0] : 0.0, (long long)mv_);
+  }
+
+  // preconditioner for the stage-2 block: [K A^T r_u; A K r_v] (pseudo-inverse
+  // of B with (A^T A)^-1 ~ K), or the identity
+  void precond_stage2(double* T, int nb) {
+    gather_precond(R_, ld_, d_->blk, nb, nullptr, N_, T, ld_, s_);
+    if (o_.precond != SVDS_PC_JACOBI) return;
+    scale_rows(T, ld_, n_, nb, dinv_, s_);                  // T_v <- K r_v
+    pack_rows(T, ld_, nullptr, 0.0, n_, nb, Tc_, s_);       // K r_v (n x nb)
+    pack_rows(T + n_, ld_, nullptr, 0.0, m_, nb, Yc_, s_);  // r_u (m x nb)
+    spmm(At(), nb, Yc_, Wc_, s_);                           // A^T r_u (n x nb)
+    spmm(A(), nb, Tc_, Yc_, s_);                            // A K r_v (m x nb)
+    unpack_rows(Wc_, n_, nb, T, ld_, s_);
+    scale_rows(T, ld_, n_, nb, dinv_, s_);                  // K A^T r_u
+    unpack_rows(Yc_, m_, nb, T + n_, ld_, s_);
+    mv_ += 2 * nb;
+  }
+
+  // ---- stages ------------------------------------------------------------------
+  int stage1(double* Vout /*n x k*/, double* Uout /*m x k*/, double* sig, double* rn, double* taus,
+             int* ok, int* status1, svds_stats* st);
+  int stage2(const double* taus_h, double* Vout, double* Uout, double* sig, int* nconv,
+             svds_stats* st);
+  void cleanup_and_output(double* Vw /*n x k*/, double* Uw /*m x k*/, double* sig, double* sigma,
+                          double* U, int64_t ldu, double* V, int64_t ldv, double* rnorm);
+  void estimate_norm();
+  void spmm_cols(const Csr32& Mx, const double* X, int64_t ldx, int64_t nin, int ncols, double* Y,
+                 int64_t ldy, int64_t nout) {
+    for (int c0 = 0; c0 < ncols; c0 += kMaxBlock) {
+      const int nb = std::min(kMaxBlock, ncols - c0);
+      pack_rows(X + c0 * ldx, ldx, nullptr, 0.0, nin, nb, Tc_, s_);
+      spmm(Mx, nb, Tc_, Yc_, s_);
+      unpack_rows(Yc_, nout, nb, Y + c0 * ldy, ldy, s_);
+      mv_ += nb;
+    }
+  }
+  // G (k x k, ld k) = X^T Y for N x k blocks
+  void gram(const double* X, int64_t ldx, const double* Yb, int64_t ldy, int64_t N, int k,
+            double* G) {
+    Seg sx{X, k, ldx};
+    for (int c0 = 0; c0 < k; c0 += kMaxBlock) {
+      const int nb = std::min(kMaxBlock, k - c0);
+      tsgemm_tn(&sx, 1, N, Yb + c0 * ldy, ldy, nb, partial_, G + (int64_t)c0 * k, s_);
+    }
+  }
+  // orthonormalise the k columns of X (N rows) in blocks of up to 8
+  void orthonormalise(double* X, int64_t ldx, int64_t N, int k) {
+    const int64_t Nsave = N_;
+    N_ = N;
+    for (int c0 = 0; c0 < k; c0 += kMaxBlock) {
+      const int nb = std::min(kMaxBlock, k - c0);
+      Seg sx{X, c0, ldx};
+      ortho(X + c0 * ldx, ldx, nb, &sx, c0 > 0 ? 1 : 0, nullptr);
+    }
+    N_ = Nsave;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// ||A|| estimate: sqrt of the largest Ritz value of C on a 30-dimensional
+// Krylov space with full reorthogonalisation (single-vector block)
+// ---------------------------------------------------------------------------
+void Solver::estimate_norm() {
+  stage_ = 1;
+  N_ = n_;
+  gc_ = 0;
+  refined_ = false;
+  const int steps = (int)std::min<int64_t>(std::min(30, kGmax), n_);
+  fill_random(V_, ld_, N_, 1, o_.seed, kStreamNorm, 0, s_);
+  ortho(V_, ld_, 1, nullptr, 0, Tc_);
+  append(1);
+  while (gc_ < steps) {
+    double* T = V_ + gc_ * ld_;
+    copy_cols(W_ + (gc_ - 1) * ld_, ld_, N_, 1, T, ld_, s_);
+    Seg sv{V_, gc_, ld_};
+    int bad = ortho_once(T, ld_, 1, &sv, 1, Tc_);
+    if (bad) break;  // invariant subspace
+    append(1);
+  }
+  small_extract(d_, gc_, 1, 0, s_);
+  double lam = 0.0;
+  SVDS_HIP(hipMemcpyAsync(&lam, d_->theta, sizeof(double), hipMemcpyDeviceToHost, s_));
+  SVDS_HIP(hipStreamSynchronize(s_));
+  normA_ = std::sqrt(std::max(lam, 0.0));
+}
+
+// ---------------------------------------------------------------------------
+// Stage 1: GD+k on C with soft locking (Algorithm 1, steps 1-8)
+// ---------------------------------------------------------------------------
+int Solver::stage1(double* V1, double* U1, double* sig, double* rn, double* taus, int* ok,
+                   int* status1, svds_stats* st) {
+  stage_ = 1;
+  N_ = n_;
+  gc_ = 0;
+  nlock_ = 0;
+  refined_ = false;
+  const double t0 = now();
+  const int64_t mv0 = mv_;
+  // reset the small state
+  SVDS_HIP(hipMemsetAsync(d_, 0, sizeof(Small), s_));
+  {
+    std::vector<double> best(kKmax + 8, INFINITY);
+    SVDS_HIP(hipMemcpyAsync(d_->best, best.data(), sizeof(double) * best.size(),
+                            hipMemcpyHostToDevice, s_));
+    double nc = normA_ * normA_;
+    SVDS_HIP(hipMemcpyAsync(&d_->normop, &nc, sizeof(double), hipMemcpyHostToDevice, s_));
+    SVDS_HIP(hipStreamSynchronize(s_));
+  }
+  const int g = (int)std::min<int64_t>(g_, n_);
+  const int r = std::min(r_, std::max(1, g - b_ - p_));
+  const int fill = std::min(std::max(r, k_ + b_), g - b_);
+  fill_random(V_, ld_, N_, b_, o_.seed, kStreamInit, 0, s_);
+  ortho(V_, ld_, b_, nullptr, 0, Tc_);
+  append(b_);
+  while (gc_ < fill && gc_ + b_ <= g) {
+    double* T = V_ + gc_ * ld_;
+    copy_cols(W_ + (gc_ - b_) * ld_, ld_, N_, b_, T, ld_, s_);
+    Seg sv{V_, gc_, ld_};
+    ortho(T, ld_, b_, &sv, 1, Tc_);
+    append(b_);
+  }
+  extract_stage();
+  int64_t iters = 0, restarts = 0, resets = 0;
+  int since_reset = 0, floor_resets = 0;
+  int status = 2;
+  for (;;) {
+    const int nc = std::min(gc_, k_ + b_);
+    residual(nc, N_);
+    CtlParams P{};
+    P.stage = 1;
+    P.gc = gc_;
+    P.g = g;
+    P.r = r;
+    P.p = p_;
+    P.b = b_;
+    P.k = k_;
+    P.nc = nc;
+    P.since_reset = since_reset;
+    P.floor_resets = floor_resets;
+    P.budget_hit = mv_ >= budget_;
+    P.tol = tol1_;
+    P.normA = normA_;
+    P.eps = kEps;
+    Ctl c = control(P);
+    trace("s1", (int)iters, c, nc);
+    if (c.action == kExitConverged || c.action == kExitFloor || c.action == kExitBudget) {
+      status = c.action == kExitConverged ? 0 : (c.action == kExitFloor ? 1 : 2);
+      normA_ = std::max(normA_, std::sqrt(c.normop));
+      break;
+    }
+    if (c.action == kReset) {
+      reset();
+      ++resets;
+      since_reset = 0;
+      floor_resets += c.floor_reset;
+      extract_stage();
+      continue;
+    }
+    if (c.restart) {
+      restart_basis(c.nr);
+      ++restarts;
+      ++since_reset;
+    }
+    int nb = c.nblock;
+    double* T = V_ + gc_ * ld_;
+    if (nb == 0) {
+      nb = b_;
+      fill_random(T, ld_, N_, nb, o_.seed, kStreamBreak + (uint64_t)rand_count_++, 0, s_);
+    } else {
+      gather_precond(R_, ld_, d_->blk, nb, o_.precond == SVDS_PC_JACOBI ? dinv_ : nullptr, N_, T,
+                     ld_, s_);
+    }
+    Seg sv{V_, gc_, ld_};
+    ortho(T, ld_, nb, &sv, 1, Tc_);
+    append(nb);
+    extract_stage();
+    ++iters;
+  }
+  // final Rayleigh-Ritz on A X (steps 4-5)
+  double* Xk = X_;  // n x k (ld ld_)
+  ts_gemm_nn(V_, ld_, gc_, N_, d_->Y, kLd, k_, Xk, ld_, s_);
+  double* AX = R_;  // m x k, ld ld_
+  spmm_cols(A(), Xk, ld_, n_, k_, AX, ld_, m_);
+  double* G = vec_;                 // k x k
+  double* lam = vec_ + kKmax * kKmax;
+  double* Z = lam + kKmax;          // k x k (ld kLd)
+  double* inv = Z + kLd * kLd;
+  double* rl2 = inv + kKmax;
+  double* rr2 = rl2 + kKmax;
+  gram(AX, ld_, AX, ld_, m_, k_, G);
+  small_eig(k_, G, k_, largest_ ? 1 : 0, lam, Z, kLd, s_);
+  ts_gemm_nn(Xk, ld_, k_, n_, Z, kLd, k_, V1, ld_, s_);      // v = X z
+  ts_gemm_nn(AX, ld_, k_, m_, Z, kLd, k_, Wt_, ld_, s_);     // A v
+  sigma_from_lambda(k_, lam, sig, inv, s_);
+  copy_cols(Wt_, ld_, m_, k_, U1, ld_, s_);
+  col_scale(U1, ld_, m_, k_, inv, s_);                      // u = A v / sigma
+  double* AtU = Vt_;
+  spmm_cols(At(), U1, ld_, m_, k_, AtU, ld_, n_);
+  col_residual2(Wt_, ld_, U1, ld_, sig, m_, k_, partial_, rl2, s_);   // ||A v - s u||^2
+  col_residual2(AtU, ld_, V1, ld_, sig, n_, k_, partial_, rr2, s_);   // ||A^T u - s v||^2
+  stage1_check(k_, rl2, rr2, sig, normA_, tol_, rn, taus, ok, s_);
+  SVDS_HIP(hipStreamSynchronize(s_));
+  st->iters[0] = iters;
+  st->restarts[0] = restarts;
+  st->resets += resets;
+  st->matvecs[0] = mv_ - mv0;
+  st->seconds[0] = now() - t0;
+  *status1 = status;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Stage 2: GD+k on B with hard locking and, for the smallest values, the
+// simplified refined projection (Algorithm 1, steps 9-18)
+// ---------------------------------------------------------------------------
+int Solver::stage2(const double* taus_h, double* V1, double* U1, double* sig, int* nconv,
+                   svds_stats* st) {
+  stage_ = 2;
+  N_ = n_ + m_;
+  gc_ = 0;
+  nlock_ = 0;
+  refined_ = !largest_;
+  tau_ = taus_h[0];
+  const double t0 = now();
+  const int64_t mv0 = mv_;
+  SVDS_HIP(hipMemsetAsync(d_, 0, sizeof(Small), s_));
+  {
+    double nb = normA_;
+    SVDS_HIP(hipMemcpyAsync(&d_->normop, &nb, sizeof(double), hipMemcpyHostToDevice, s_));
+  }
+  const int g = (int)std::min<int64_t>(g_, N_);
+  const int r = std::min(r_, std::max(1, g - b_ - p_));
+  // initial basis [v; u] (the 1/sqrt(2) is absorbed by the normalisation)
+  for (int c0 = 0; c0 < k_; c0 += kMaxBlock) {
+    const int nb = std::min(kMaxBlock, k_ - c0);
+    double* T = V_ + gc_ * ld_;
+    copy_cols(V1 + c0 * ld_, ld_, n_, nb, T, ld_, s_);
+    copy_cols(U1 + c0 * ld_, ld_, m_, nb, T + n_, ld_, s_);
+    Seg sv{V_, gc_, ld_};
+    ortho(T, ld_, nb, &sv, gc_ > 0 ? 1 : 0, Tc_);
+    append(nb);
+  }
+  extract_stage();
+  int64_t iters = 0, restarts = 0, resets = 0;
+  int since_reset = 0;
+  int exit_action = kExitBudget;
+  for (;;) {
+    const int nc = std::min(gc_, b_);
+    residual(nc, n_);
+    CtlParams P{};
+    P.stage = 2;
+    P.gc = gc_;
+    P.g = g;
+    P.r = r;
+    P.p = p_;
+    P.b = b_;
+    P.k = k_;
+    P.nc = nc;
+    P.nlock = nlock_;
+    P.since_reset = since_reset;
+    P.budget_hit = mv_ >= budget_;
+    P.refined = refined_ ? 1 : 0;
+    P.tol = tol_;
+    P.normA = normA_;
+    P.eps = kEps;
+    Ctl c = control(P);
+    trace("s2", (int)iters, c, nc);
+    if (c.nlockable > 0) {
+      // x = V y for the converged prefix -> locked vectors
+      ts_gemm_nn(V_, ld_, gc_, N_, d_->Y, kLd, c.nlockable, X_ + nlock_ * ld_, ld_, s_);
+      nlock_ += c.nlockable;
+    }
+    if (c.action == kExitConverged || c.action == kExitBudget) {
+      exit_action = c.action;
+      break;
+    }
+    if (c.action == kLock) {
+      restart_basis(c.nr);
+      ++restarts;
+      ++since_reset;
+      if (refined_) {
+        tau_ = taus_h[std::min(nlock_, k_ - 1)];
+        rebuild_refined();
+      }
+      extract_stage();
+      continue;
+    }
+    if (c.action == kReset) {
+      reset();
+      ++resets;
+      since_reset = 0;
+      extract_stage();
+      continue;
+    }
+    if (c.restart) {
+      restart_basis(c.nr);
+      ++restarts;
+      ++since_reset;
+    }
+    const int nb = c.nblock;
+    double* T = V_ + gc_ * ld_;
+    precond_stage2(T, nb);
+    Seg segs[2] = {Seg{X_, nlock_, ld_}, Seg{V_, gc_, ld_}};
+    ortho(T, ld_, nb, segs, 2, Tc_);
+    append(nb);
+    extract_stage();
+    ++iters;
+  }
+  *nconv = nlock_;
+  int have = nlock_;
+  if (have < k_) {  // budget: complete with the current best approximations
+    const int extra = std::min(k_ - have, gc_);
+    ts_gemm_nn(V_, ld_, gc_, N_, d_->Y, kLd, extra, X_ + have * ld_, ld_, s_);
+    SVDS_HIP(hipMemcpyAsync(d_->lockval + have, d_->theta, sizeof(double) * extra,
+                            hipMemcpyDeviceToDevice, s_));
+    have += extra;
+  }
+  // halves: v = x(1:n)/||.||, u = x(n+1:)/||.||, sigma = |lambda| (step 17)
+  double* nv = vec_;
+  double* nu = nv + kKmax;
+  double* fv = nu + kKmax;
+  double* fu = fv + kKmax;
+  copy_cols(X_, ld_, n_, have, V1, ld_, s_);
+  copy_cols(X_ + n_, ld_, m_, have, U1, ld_, s_);
+  col_residual2(V1, ld_, nullptr, 0, nullptr, n_, have, partial_, nv, s_);
+  col_residual2(U1, ld_, nullptr, 0, nullptr, m_, have, partial_, nu, s_);
+  inv_sqrt(have, nv, fv, s_);
+  inv_sqrt(have, nu, fu, s_);
+  col_scale(V1, ld_, n_, have, fv, s_);
+  col_scale(U1, ld_, m_, have, fu, s_);
+  abs_vec(have, d_->lockval, sig, s_);
+  SVDS_HIP(hipStreamSynchronize(s_));
+  st->iters[1] = iters;
+  st->restarts[1] = restarts;
+  st->resets += resets;
+  st->matvecs[1] = mv_ - mv0;
+  st->seconds[1] = now() - t0;
+  (void)exit_action;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// two-sided clean-up: orthonormalise U and V, SVD of U^T A V, rotate; then
+// eq. (res), sign convention and output in the caller's orientation
+// ---------------------------------------------------------------------------
+void Solver::cleanup_and_output(double* Vw, double* Uw, double* sig, double* sigma, double* U,
+                                int64_t ldu, double* V, int64_t ldv, double* rnorm) {
+  double* P = vec_;                    // k x k (ld kLd)
+  double* Qm = P + kLd * kLd;
+  double* sv = Qm + kLd * kLd;
+  double* Yq = sv + kLd;
+  double* AVq = Yq + kLd * kLd;
+  double* H2 = AVq + kLd * kLd;
+  double* rl2 = H2 + kLd * kLd;
+  double* rr2 = rl2 + kLd;
+  double* f = rr2 + kLd;
+  double* sgn = f + kLd;
+  double* U2 = Wt_;  // m x k
+  double* V2 = Vt_;  // n x k
+  double* AV = R_;   // m x k
+  double* AtU = Q_ ? Q_ : W_;
+  if (o_.two_sided_cleanup) {
+    orthonormalise(Uw, ld_, m_, k_);
+    orthonormalise(Vw, ld_, n_, k_);
+    spmm_cols(A(), Vw, ld_, n_, k_, AV, ld_, m_);
+    gram(Uw, ld_, AV, ld_, m_, k_, H2);  // H2 = U^T A V (k x k, ld k)
+    small_svd(k_, H2, k_, sv, Yq, kLd, AVq, kLd, s_);
+    cleanup_finish(k_, sv, Yq, kLd, AVq, kLd, largest_ ? 1 : 0, sig, P, Qm, kLd, s_);
+    ts_gemm_nn(Uw, ld_, k_, m_, P, kLd, k_, U2, ld_, s_);
+    ts_gemm_nn(Vw, ld_, k_, n_, Qm, kLd, k_, V2, ld_, s_);
+  } else {
+    copy_cols(Uw, ld_, m_, k_, U2, ld_, s_);
+    copy_cols(Vw, ld_, n_, k_, V2, ld_, s_);
+  }
+  // eq. (res)
+  spmm_cols(A(), V2, ld_, n_, k_, AV, ld_, m_);
+  spmm_cols(At(), U2, ld_, m_, k_, AtU, ld_, n_);
+  col_residual2(AV, ld_, U2, ld_, sig, m_, k_, partial_, rl2, s_);
+  col_residual2(AtU, ld_, V2, ld_, sig, n_, k_, partial_, rr2, s_);
+  sqrt_sum(k_, rl2, rr2, rnorm, s_);
+  // caller orientation: right vectors of the caller's A
+  double* Vc = M_->transposed ? U2 : V2;
+  double* Uc = M_->transposed ? V2 : U2;
+  const int64_t nV = M_->transposed ? m_ : n_;
+  const int64_t nU = M_->transposed ? n_ : m_;
+  sign_factors(Vc, ld_, nV, k_, partial_, sgn, s_);
+  col_scale(Vc, ld_, nV, k_, sgn, s_);
+  col_scale(Uc, ld_, nU, k_, sgn, s_);
+  copy_cols(Vc, ld_, nV, k_, V, ldv, s_);
+  copy_cols(Uc, ld_, nU, k_, U, ldu, s_);
+  SVDS_HIP(hipMemcpyAsync(sigma, sig, sizeof(double) * k_, hipMemcpyDeviceToDevice, s_));
+}
+
+int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, double* rnorm,
+                svds_stats* st) {
+  std::memset(st, 0, sizeof(*st));
+  const double t0 = now();
+  // ---- buffers
+  const int64_t Nmax = m_ + n_;
+  ld_ = round_up(Nmax, 64);
+  const size_t basis = (size_t)ld_ * kGmax;
+  V_ = buf_.get<double>(basis);
+  W_ = buf_.get<double>(basis);
+  Vt_ = buf_.get<double>(basis);
+  Wt_ = buf_.get<double>(basis);
+  if (!largest_) {
+    Q_ = buf_.get<double>(basis);
+    Qt_ = buf_.get<double>(basis);
+  }
+  X_ = buf_.get<double>((size_t)ld_ * std::max(kKmax, kLd));
+  R_ = buf_.get<double>((size_t)ld_ * std::max(kKmax + 8, kLd));
+  Tc_ = buf_.get<double>((size_t)ld_ * kMaxBlock);
+  Yc_ = buf_.get<double>((size_t)ld_ * kMaxBlock);
+  Wc_ = buf_.get<double>((size_t)ld_ * kMaxBlock);
+  Zc_ = buf_.get<double>((size_t)ld_ * kMaxBlock);
+  partial_ = buf_.get<double>((size_t)1024 * 264 * kMaxBlock + 1024);
+  d_ = buf_.get<Small>(1);
+  vec_ = buf_.get<double>(16 * kLd * kLd);
+  double* V1 = buf_.get<double>((size_t)ld_ * kKmax);
+  double* U1 = buf_.get<double>((size_t)ld_ * kKmax);
+  double* sig = buf_.get<double>(kKmax);
+  double* rn1 = buf_.get<double>(kKmax);
+  double* taus = buf_.get<double>(kKmax);
+  int* ok = buf_.get<int>(1);
+  SVDS_HIP(hipHostMalloc((void**)&hctl_, sizeof(Ctl), hipHostMallocDefault));
+  SVDS_HIP(hipHostMalloc((void**)&hbad_, sizeof(int), hipHostMallocDefault));
+  struct PinnedFree {
+    Ctl* c;
+    int* b;
+    ~PinnedFree() {
+      (void)hipHostFree(c);
+      (void)hipHostFree(b);
+    }
+  } pf{hctl_, hbad_};
+  if (o_.precond == SVDS_PC_JACOBI) {
+    dinv_ = buf_.get<double>(n_);
+    // 1/diag(C), with 1 where the column is empty
+    std::vector<double> hd(n_);
+    SVDS_HIP(hipMemcpyAsync(hd.data(), M_->diagC, sizeof(double) * n_, hipMemcpyDeviceToHost, s_));
+    SVDS_HIP(hipStreamSynchronize(s_));
+    for (auto& x : hd) x = x > 0 ? 1.0 / x : 1.0;
+    SVDS_HIP(hipMemcpyAsync(dinv_, hd.data(), sizeof(double) * n_, hipMemcpyHostToDevice, s_));
+  }
+  SVDS_HIP(hipMemsetAsync(d_, 0, sizeof(Small), s_));
+  // ---- ||A||
+  if (o_.norm_A > 0) {
+    normA_ = o_.norm_A;
+  } else {
+    estimate_norm();
+    mv_ = 0;
+  }
+  st->setup_seconds = now() - t0;
+  // ---- stage 1
+  int okh = 0, status1 = 2;
+  stage1(V1, U1, sig, rn1, taus, ok, &status1, st);
+  SVDS_HIP(hipMemcpyAsync(&okh, ok, sizeof(int), hipMemcpyDeviceToHost, s_));
+  SVDS_HIP(hipStreamSynchronize(s_));
+  st->stage1_status = status1;
+  st->stage_exit = 1;
+  int nconv = 0;
+  if (status1 != 2 && (o_.force_stage2 || !okh)) {
+    std::vector<double> th(k_);
+    SVDS_HIP(hipMemcpyAsync(th.data(), taus, sizeof(double) * k_, hipMemcpyDeviceToHost, s_));
+    SVDS_HIP(hipStreamSynchronize(s_));
+    stage2(th.data(), V1, U1, sig, &nconv, st);
+    st->stage_exit = 2;
+  }
+  cleanup_and_output(V1, U1, sig, sigma, U, ldu, V, ldv, rnorm);
+  std::vector<double> hr(k_);
+  SVDS_HIP(hipMemcpyAsync(hr.data(), rnorm, sizeof(double) * k_, hipMemcpyDeviceToHost, s_));
+  SVDS_HIP(hipStreamSynchronize(s_));
+  int good = 0;
+  bool finite = true;
+  for (double x : hr) {
+    good += x < normA_ * tol_;
+    finite = finite && std::isfinite(x);
+  }
+  st->nconv = good;
+  st->norm_A_used = normA_;
+  st->breakdowns = breakdowns_;
+  if (!finite && good == 0) return SVDS_ERR_BREAKDOWN;
+  return good >= k_ ? SVDS_OK : SVDS_NOT_CONVERGED;
+}
+
+}  // namespace svds
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+using svds::Error;
+
+namespace {
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    if (std::getenv("SVDS_DEBUG")) std::fprintf(stderr, "[svds] error %d: %s\n", e.code, e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    return SVDS_ERR_OOM;
+  } catch (...) {
+    return SVDS_ERR_HIP;
+  }
+}
+
+void free_csr(svds::Csr32& c) {
+  (void)hipFree(c.rp);
+  (void)hipFree(c.ci);
+  (void)hipFree(c.val);
+  (void)hipFree(c.val32);
+  (void)hipFree(c.binrows);
+  c = svds::Csr32{};
+}
+
+void alloc_csr(svds::Csr32& c, int64_t rows, int64_t cols, int64_t nnz) {
+  c.rows = rows;
+  c.cols = cols;
+  c.nnz = nnz;
+  SVDS_HIP(hipMalloc((void**)&c.rp, sizeof(int32_t) * (rows + 1)));
+  SVDS_HIP(hipMalloc((void**)&c.ci, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
+  SVDS_HIP(hipMalloc((void**)&c.val, sizeof(double) * std::max<int64_t>(nnz, 1)));
+  SVDS_HIP(hipMalloc((void**)&c.binrows, sizeof(int32_t) * std::max<int64_t>(rows, 1)));
+}
+
+int create_matrix(const svds_csr* A, svds_matrix** out, hipStream_t s) {
+  if (!A || !out) throw Error(SVDS_ERR_ARG, "null argument");
+  if (A->m <= 0 || A->n <= 0 || A->nnz < 0 || !A->rowptr || (A->nnz > 0 && (!A->colind || !A->values)))
+    throw Error(SVDS_ERR_ARG, "bad sizes or pointers");
+  if (A->nnz >= (int64_t)INT32_MAX || A->m >= (int64_t)INT32_MAX || A->n >= (int64_t)INT32_MAX)
+    throw Error(SVDS_ERR_ARG, "matrix too large for 32-bit indices");
+  // row pointer ends and the structure check
+  int64_t ends[2] = {0, 0};
+  SVDS_HIP(hipMemcpyAsync(&ends[0], A->rowptr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  SVDS_HIP(hipMemcpyAsync(&ends[1], A->rowptr + A->m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  int* dflag = nullptr;
+  SVDS_HIP(hipMallocAsync((void**)&dflag, sizeof(int), s));
+  SVDS_HIP(hipMemsetAsync(dflag, 0, sizeof(int), s));
+  svds::check_csr(*A, dflag, s);
+  int flag = 0;
+  SVDS_HIP(hipMemcpyAsync(&flag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+  SVDS_HIP(hipFreeAsync(dflag, s));
+  SVDS_HIP(hipStreamSynchronize(s));
+  if (ends[0] != 0 || ends[1] != A->nnz || flag) throw Error(SVDS_ERR_CSR, "malformed CSR");
+
+  auto* h = new svds_matrix();
+  try {
+    SVDS_HIP(hipGetDevice(&h->device));
+    h->m = A->m;
+    h->n = A->n;
+    h->nnz = A->nnz;
+    h->transposed = A->m < A->n;
+    svds::Csr32 a, at;
+    alloc_csr(a, A->m, A->n, A->nnz);
+    alloc_csr(at, A->n, A->m, A->nnz);
+    svds::copy_csr_arrays(*A, a, s);
+    int32_t* cursor = nullptr;
+    SVDS_HIP(hipMallocAsync((void**)&cursor, sizeof(int32_t) * (A->n + 1), s));
+    svds::transpose_csr(a, at, cursor, s);
+    SVDS_HIP(hipFreeAsync(cursor, s));
+    svds::build_bins(a, s);
+    svds::build_bins(at, s);
+    if (h->transposed) {
+      h->A = at;
+      h->At = a;
+    } else {
+      h->A = a;
+      h->At = at;
+    }
+    SVDS_HIP(hipMalloc((void**)&h->diagC, sizeof(double) * h->A.cols));
+    svds::row_sqnorms(h->At, h->diagC, s);  // rows of A_w^T = columns of A_w
+    SVDS_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    free_csr(h->A);
+    free_csr(h->At);
+    (void)hipFree(h->diagC);
+    delete h;
+    throw;
+  }
+  *out = h;
+  return SVDS_OK;
+}
+
+svds_opts default_opts() {
+  svds_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.max_prev_retain = -1;
+  o.two_sided_cleanup = 1;
+  return o;
+}
+
+int solve_prepared(const svds_matrix* h, int k, int target, double tol, const svds_opts* opts,
+                   double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, double* rnorm,
+                   svds_stats* stats, hipStream_t s) {
+  if (!h || !sigma || !U || !V || !rnorm) throw Error(SVDS_ERR_ARG, "null argument");
+  if (target != SVDS_LARGEST && target != SVDS_SMALLEST) throw Error(SVDS_ERR_ARG, "target");
+  if (!(tol > 0.0 && tol < 1.0)) throw Error(SVDS_ERR_ARG, "tol must be in (0, 1)");
+  const int64_t mn = std::min(h->m, h->n);
+  if (k < 1 || k > mn || k > svds::kKmax) throw Error(SVDS_ERR_ARG, "k out of range");
+  if (ldu < h->m || ldv < h->n) throw Error(SVDS_ERR_ARG, "leading dimension too small");
+  svds_opts o = opts ? *opts : default_opts();
+  if (o.precision != SVDS_FP64) throw Error(SVDS_ERR_ARG, "precision not available");
+  if (o.precond != SVDS_PC_NONE && o.precond != SVDS_PC_JACOBI) throw Error(SVDS_ERR_ARG, "precond");
+  svds_stats local;
+  svds_stats* st = stats ? stats : &local;
+  svds::Solver solver(h, k, target, tol, o, s);
+  return solver.run(sigma, U, ldu, V, ldv, rnorm, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+int svds_opts_init(svds_opts* opts) {
+  if (!opts) return SVDS_ERR_ARG;
+  *opts = default_opts();
+  return SVDS_OK;
+}
+
+const char* svds_error_string(int code) {
+  switch (code) {
+    case SVDS_OK: return "ok";
+    case SVDS_NOT_CONVERGED: return "not converged within the matrix-vector budget";
+    case SVDS_ERR_ARG: return "invalid argument";
+    case SVDS_ERR_CSR: return "malformed CSR matrix";
+    case SVDS_ERR_OOM: return "device out of memory";
+    case SVDS_ERR_HIP: return "HIP runtime error";
+    case SVDS_ERR_BREAKDOWN: return "numerical breakdown";
+    default: return "unknown status";
+  }
+}
+
+int svds_matrix_create(const svds_csr* A, svds_matrix** out, void* stream) {
+  return guarded([&] { return create_matrix(A, out, (hipStream_t)stream); });
+}
+
+int svds_matrix_destroy(svds_matrix* h) {
+  if (!h) return SVDS_OK;
+  free_csr(h->A);
+  free_csr(h->At);
+  (void)hipFree(h->diagC);
+  delete h;
+  return SVDS_OK;
+}
+
+int svds_matrix_spmm(const svds_matrix* h, int trans, int b, const double* X, double* Y,
+                     void* stream) {
+  return guarded([&] {
+    if (!h || !X || !Y || b < 1 || b > svds::kMaxBlock) throw Error(SVDS_ERR_ARG, "spmm args");
+    // the caller's A: A = A_w (not transposed) or A_w^T (transposed)
+    const bool use_w = (trans == 0) != h->transposed;
+    svds::spmm(use_w ? h->A : h->At, b, X, Y, (hipStream_t)stream);
+    return SVDS_OK;
+  });
+}
+
+int svds_solve_prepared(const svds_matrix* h, int k, int target, double tol,
+                        const svds_opts* opts, double* sigma, double* U, int64_t ldu, double* V,
+                        int64_t ldv, double* rnorm, svds_stats* stats, void* stream) {
+  return guarded([&] {
+    return solve_prepared(h, k, target, tol, opts, sigma, U, ldu, V, ldv, rnorm, stats,
+                          (hipStream_t)stream);
+  });
+}
+
+int svds_solve(const svds_csr* A, int k, int target, double tol, const svds_opts* opts,
+               double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, double* rnorm,
+               svds_stats* stats, void* stream) {
+  return guarded([&] {
+    const double t0 = svds::now();
+    svds_matrix* h = nullptr;
+    create_matrix(A, &h, (hipStream_t)stream);
+    struct Guard {
+      svds_matrix* h;
+      ~Guard() { svds_matrix_destroy(h); }
+    } g{h};
+    const double t1 = svds::now();
+    int rc = solve_prepared(h, k, target, tol, opts, sigma, U, ldu, V, ldv, rnorm, stats,
+                            (hipStream_t)stream);
+    if (stats) stats->setup_seconds += t1 - t0;
+    return rc;
+  });
+}
+
+int svds_small_eig(int g, const double* H, int64_t ldh, int descending, double* theta, double* Y,
+                   int64_t ldy, void* stream) {
+  return guarded([&] {
+    if (!H || !theta || !Y || ldh < g || ldy < g) throw Error(SVDS_ERR_ARG, "small_eig args");
+    svds::small_eig(g, H, (int)ldh, descending, theta, Y, (int)ldy, (hipStream_t)stream);
+    return SVDS_OK;
+  });
+}
+
+int svds_small_svd(int g, const double* R, int64_t ldr, double* s, double* Y, int64_t ldy,
+                   void* stream) {
+  return guarded([&] {
+    if (!R || !s || !Y || ldr < g || ldy < g) throw Error(SVDS_ERR_ARG, "small_svd args");
+    svds::small_svd(g, R, (int)ldr, s, Y, (int)ldy, nullptr, 0, (hipStream_t)stream);
+    return SVDS_OK;
+  });
+}
+
+}  // extern "C"

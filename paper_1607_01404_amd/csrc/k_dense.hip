@@ -1,0 +1,605 @@
+// Tall-skinny dense kernels of one GD+k iteration (Section 3.3, Table 3:
+// O((m+n) g) work per iteration, all of it HBM-bound).  Vectors are stored
+// column-major (column j of an N x g basis at p + j*ld), so that every load of
+// a wavefront is 64 consecutive doubles.  Reductions over the N rows are done
+// in two fixed-order phases (per-workgroup partials, then a column reduction)
+// so that results do not depend on scheduling.
+#include "common.h"
+
+namespace svds {
+
+constexpr int kThreads = 256;
+constexpr int kMaxSegCols = 256;  // columns of [X_lock V T] in one projection
+
+int reduce_blocks(int64_t N) {
+  int64_t nb = (N + 8 * kThreads - 1) / (8 * kThreads);
+  nb = std::max<int64_t>(1, std::min<int64_t>(nb, 1024));
+  if (nb >= 64) nb = (nb / 8) * 8;
+  return (int)nb;
+}
+
+struct Segs3 {
+  const double* p[3];
+  int64_t ld[3];
+  int n0, n1, n2;  // columns per segment
+};
+
+__device__ __forceinline__ const double* seg_col(const Segs3& s, int v) {
+  if (v < s.n0) return s.p[0] + (int64_t)v * s.ld[0];
+  v -= s.n0;
+  if (v < s.n1) return s.p[1] + (int64_t)v * s.ld[1];
+  v -= s.n1;
+  return s.p[2] + (int64_t)v * s.ld[2];
+}
+
+// sum over the block of acc[] (NA values per thread) -> out[0..NA) (thread 0..NA-1)
+template <int NA>
+__device__ __forceinline__ void block_reduce_store(double (&acc)[NA], double* sh, double* out,
+                                                   int64_t stride_out, int nvalid) {
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+#pragma unroll
+  for (int a = 0; a < NA; ++a) {
+    double v = wave_sum(acc[a]);
+    if (lane == 0) sh[w * NA + a] = v;
+  }
+  __syncthreads();
+  for (int a = threadIdx.x; a < NA; a += kThreads) {
+    if (a < nvalid) {
+      double v = ((sh[a] + sh[NA + a]) + sh[2 * NA + a]) + sh[3 * NA + a];
+      out[a * stride_out] = v;
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// C = [segs]^T T  (partials per workgroup)
+// ---------------------------------------------------------------------------
+constexpr int kJC = 8;
+
+template <int B>
+__global__ __launch_bounds__(kThreads) void k_tsgemm_tn(Segs3 segs, int total, int64_t N,
+                                                        const double* __restrict__ T,
+                                                        int64_t ldt,
+                                                        double* __restrict__ partial) {
+  __shared__ double sh[4 * kJC * B];
+  const int c0 = blockIdx.y * kJC;
+  const int ncol = min(kJC, total - c0);
+  const double* qp[kJC];
+#pragma unroll
+  for (int jj = 0; jj < kJC; ++jj) qp[jj] = seg_col(segs, min(c0 + jj, total - 1));
+  double acc[kJC * B];
+#pragma unroll
+  for (int a = 0; a < kJC * B; ++a) acc[a] = 0.0;
+  const int bid = xcd_block(blockIdx.x, gridDim.x);
+  for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kThreads) {
+    double t[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) t[c] = T[i + c * ldt];
+#pragma unroll
+    for (int jj = 0; jj < kJC; ++jj) {
+      if (jj < ncol) {
+        const double q = qp[jj][i];
+#pragma unroll
+        for (int c = 0; c < B; ++c) acc[jj * B + c] = fma(q, t[c], acc[jj * B + c]);
+      }
+    }
+  }
+  // partial layout: [block][c * total + col]
+  double* out = partial + (int64_t)blockIdx.x * total * B;
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+#pragma unroll
+  for (int a = 0; a < kJC * B; ++a) {
+    double v = wave_sum(acc[a]);
+    if (lane == 0) sh[w * kJC * B + a] = v;
+  }
+  __syncthreads();
+  for (int a = threadIdx.x; a < kJC * B; a += kThreads) {
+    int jj = a / B, c = a % B;
+    if (jj < ncol) {
+      double v = ((sh[a] + sh[kJC * B + a]) + sh[2 * kJC * B + a]) + sh[3 * kJC * B + a];
+      out[(int64_t)c * total + c0 + jj] = v;
+    }
+  }
+}
+
+__global__ void k_reduce_partials(const double* __restrict__ P, int nblk, int nout,
+                                  double* __restrict__ out) {
+  __shared__ double sh[4][64];
+  const int o = blockIdx.x * 64 + (threadIdx.x % 64);
+  const int part = threadIdx.x / 64;
+  double s = 0.0;
+  if (o < nout)
+    for (int b = part; b < nblk; b += 4) s += P[(int64_t)b * nout + o];
+  sh[part][threadIdx.x % 64] = s;
+  __syncthreads();
+  if (part == 0 && o < nout)
+    out[o] = ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) + sh[3][threadIdx.x];
+}
+
+static void reduce_partials(const double* P, int nblk, int nout, double* out, hipStream_t s) {
+  k_reduce_partials<<<(nout + 63) / 64, 256, 0, s>>>(P, nblk, nout, out);
+  SVDS_LAUNCH_CHECK();
+}
+
+static Segs3 make_segs(const Seg* segs, int nseg, int& total) {
+  if (nseg > 3) throw Error(SVDS_ERR_ARG, "at most 3 segments");
+  Segs3 s{};
+  int n[3] = {0, 0, 0};
+  for (int i = 0; i < 3; ++i) {
+    s.p[i] = i < nseg ? segs[i].p : nullptr;
+    s.ld[i] = i < nseg ? segs[i].ld : 0;
+    n[i] = i < nseg ? segs[i].ncols : 0;
+  }
+  s.n0 = n[0];
+  s.n1 = n[1];
+  s.n2 = n[2];
+  total = n[0] + n[1] + n[2];
+  // the last segment must be non-empty for the clamped column pointer
+  return s;
+}
+
+template <int B>
+static void tsgemm_b(const Segs3& sg, int total, int64_t N, const double* T, int64_t ldt,
+                     double* partial, double* C, hipStream_t s) {
+  int nb = reduce_blocks(N);
+  dim3 grid(nb, (total + kJC - 1) / kJC);
+  k_tsgemm_tn<B><<<grid, kThreads, 0, s>>>(sg, total, N, T, ldt, partial);
+  SVDS_LAUNCH_CHECK();
+  reduce_partials(partial, nb, total * B, C, s);
+}
+
+void tsgemm_tn(const Seg* segs, int nseg, int64_t N, const double* T, int64_t ldt, int b,
+               double* partial, double* C, hipStream_t s) {
+  int total = 0;
+  Segs3 sg = make_segs(segs, nseg, total);
+  if (total == 0) return;
+  if (total > kMaxSegCols) throw Error(SVDS_ERR_ARG, "projection too wide");
+  switch (b) {
+    case 1: tsgemm_b<1>(sg, total, N, T, ldt, partial, C, s); break;
+    case 2: tsgemm_b<2>(sg, total, N, T, ldt, partial, C, s); break;
+    case 3: tsgemm_b<3>(sg, total, N, T, ldt, partial, C, s); break;
+    case 4: tsgemm_b<4>(sg, total, N, T, ldt, partial, C, s); break;
+    case 5: tsgemm_b<5>(sg, total, N, T, ldt, partial, C, s); break;
+    case 6: tsgemm_b<6>(sg, total, N, T, ldt, partial, C, s); break;
+    case 7: tsgemm_b<7>(sg, total, N, T, ldt, partial, C, s); break;
+    case 8: tsgemm_b<8>(sg, total, N, T, ldt, partial, C, s); break;
+    default: throw Error(SVDS_ERR_ARG, "tsgemm: b must be 1..8");
+  }
+}
+
+// ---------------------------------------------------------------------------
+// T -= [segs] C      (C: total x b, column-major)
+// ---------------------------------------------------------------------------
+template <int B>
+__global__ __launch_bounds__(kThreads) void k_ts_update(Segs3 segs, int total, int64_t N,
+                                                        const double* __restrict__ C, int ldc,
+                                                        double* __restrict__ T, int64_t ldt) {
+  __shared__ double cs[kMaxSegCols * B];
+  for (int a = threadIdx.x; a < total * B; a += kThreads) {
+    int j = a / B, c = a % B;
+    cs[a] = C[(int64_t)c * ldc + j];
+  }
+  __syncthreads();
+  const int bid = xcd_block(blockIdx.x, gridDim.x);
+  for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kThreads) {
+    double t[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) t[c] = T[i + c * ldt];
+    for (int j = 0; j < total; ++j) {
+      const double q = seg_col(segs, j)[i];
+#pragma unroll
+      for (int c = 0; c < B; ++c) t[c] = fma(-q, cs[j * B + c], t[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < B; ++c) T[i + c * ldt] = t[c];
+  }
+}
+
+void ts_update(const Seg* segs, int nseg, int64_t N, const double* C, int ldc, double* T,
+               int64_t ldt, int b, hipStream_t s) {
+  int total = 0;
+  Segs3 sg = make_segs(segs, nseg, total);
+  if (total == 0) return;
+  if (total > kMaxSegCols) throw Error(SVDS_ERR_ARG, "update too wide");
+  int nb = reduce_blocks(N) * 2;
+  switch (b) {
+#define CASE(BB) \
+  case BB: k_ts_update<BB><<<nb, kThreads, 0, s>>>(sg, total, N, C, ldc, T, ldt); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: throw Error(SVDS_ERR_ARG, "ts_update: b must be 1..8");
+  }
+  SVDS_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Out = Q Y   (restart V <- V Y, W <- W Y, Q <- Q Q~, locking x = V y)
+// ---------------------------------------------------------------------------
+constexpr int kOC = 16;
+
+__global__ __launch_bounds__(kThreads) void k_gemm_nn(const double* __restrict__ Q, int64_t ldq,
+                                                      int nq, int64_t N,
+                                                      const double* __restrict__ Y, int64_t ldy,
+                                                      int nout, double* __restrict__ Out,
+                                                      int64_t ldo) {
+  __shared__ double ys[kMaxBasis * kOC];
+  const int o0 = blockIdx.y * kOC;
+  const int no = min(kOC, nout - o0);
+  for (int a = threadIdx.x; a < nq * kOC; a += kThreads) {
+    int j = a / kOC, o = a % kOC;
+    ys[a] = (o < no) ? Y[(int64_t)(o0 + o) * ldy + j] : 0.0;
+  }
+  __syncthreads();
+  const int bid = xcd_block(blockIdx.x, gridDim.x);
+  for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kThreads) {
+    double acc[kOC];
+#pragma unroll
+    for (int o = 0; o < kOC; ++o) acc[o] = 0.0;
+    for (int j = 0; j < nq; ++j) {
+      const double q = Q[i + (int64_t)j * ldq];
+#pragma unroll
+      for (int o = 0; o < kOC; ++o) acc[o] = fma(q, ys[j * kOC + o], acc[o]);
+    }
+#pragma unroll
+    for (int o = 0; o < kOC; ++o)
+      if (o < no) Out[i + (int64_t)(o0 + o) * ldo] = acc[o];
+  }
+}
+
+void ts_gemm_nn(const double* Q, int64_t ldq, int nq, int64_t N, const double* Y, int64_t ldy,
+                int nout, double* Out, int64_t ldo, hipStream_t s) {
+  if (nout <= 0 || N == 0) return;
+  if (nq > kMaxBasis) throw Error(SVDS_ERR_ARG, "gemm: inner dimension too large");
+  dim3 grid(reduce_blocks(N) * 2, (nout + kOC - 1) / kOC);
+  k_gemm_nn<<<grid, kThreads, 0, s>>>(Q, ldq, nq, N, Y, ldy, nout, Out, ldo);
+  SVDS_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// T <- T Rinv (upper triangular b x b, column-major), optional row-major copy
+// ---------------------------------------------------------------------------
+template <int B>
+__global__ __launch_bounds__(kThreads) void k_ts_scale(double* __restrict__ T, int64_t ldt,
+                                                       int64_t N, const double* __restrict__ Rinv,
+                                                       double* __restrict__ compact) {
+  __shared__ double r[B * B];
+  for (int a = threadIdx.x; a < B * B; a += kThreads) r[a] = Rinv[a];
+  __syncthreads();
+  const int bid = xcd_block(blockIdx.x, gridDim.x);
+  for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kThreads) {
+    double t[B], o[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) t[c] = T[i + c * ldt];
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j <= c; ++j) acc = fma(t[j], r[c * B + j], acc);
+      o[c] = acc;
+    }
+#pragma unroll
+    for (int c = 0; c < B; ++c) T[i + c * ldt] = o[c];
+    if (compact) {
+#pragma unroll
+      for (int c = 0; c < B; ++c) compact[i * B + c] = o[c];
+    }
+  }
+}
+
+void ts_scale(double* T, int64_t ldt, int64_t N, int b, const double* Rinv, double* compact,
+              hipStream_t s) {
+  int nb = reduce_blocks(N) * 2;
+  switch (b) {
+#define CASE(BB) \
+  case BB: k_ts_scale<BB><<<nb, kThreads, 0, s>>>(T, ldt, N, Rinv, compact); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: throw Error(SVDS_ERR_ARG, "ts_scale: b must be 1..8");
+  }
+  SVDS_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// fused residual: x = V y_c, r_c = W y_c - theta_c x  and the six sums per
+// candidate  [||r_lo||^2, x_lo.r_lo, ||x_lo||^2, ||r_hi||^2, x_hi.r_hi, ||x_hi||^2]
+// with lo = rows < nsplit (the v-half on B), hi = the rest (the u-half).
+// One pass over V and W (the "special kernels" of Section 3.3).
+// ---------------------------------------------------------------------------
+constexpr int kNCC = 8;  // candidates per workgroup column
+
+__global__ __launch_bounds__(kThreads) void k_residual(
+    const double* __restrict__ V, const double* __restrict__ W, int64_t ld, int64_t N,
+    int64_t nsplit, int g, const double* __restrict__ Y, int64_t ldy,
+    const double* __restrict__ theta, int nc, double* __restrict__ R, int64_t ldr,
+    double* __restrict__ partial) {
+  __shared__ double ys[kMaxBasis * kNCC];
+  __shared__ double th[kNCC];
+  __shared__ double sh[4 * 6 * kNCC];
+  const int c0 = blockIdx.y * kNCC;
+  const int ncc = min(kNCC, nc - c0);
+  for (int a = threadIdx.x; a < g * kNCC; a += kThreads) {
+    int j = a / kNCC, c = a % kNCC;
+    ys[a] = (c < ncc) ? Y[(int64_t)(c0 + c) * ldy + j] : 0.0;
+  }
+  if (threadIdx.x < kNCC) th[threadIdx.x] = (threadIdx.x < ncc) ? theta[c0 + threadIdx.x] : 0.0;
+  __syncthreads();
+  double acc[6 * kNCC];
+#pragma unroll
+  for (int a = 0; a < 6 * kNCC; ++a) acc[a] = 0.0;
+  const int bid = xcd_block(blockIdx.x, gridDim.x);
+  for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kThreads) {
+    double x[kNCC], w[kNCC];
+#pragma unroll
+    for (int c = 0; c < kNCC; ++c) x[c] = w[c] = 0.0;
+    for (int j = 0; j < g; ++j) {
+      const double v = V[i + (int64_t)j * ld];
+      const double ww = W[i + (int64_t)j * ld];
+#pragma unroll
+      for (int c = 0; c < kNCC; ++c) {
+        x[c] = fma(v, ys[j * kNCC + c], x[c]);
+        w[c] = fma(ww, ys[j * kNCC + c], w[c]);
+      }
+    }
+    const int off = (i < nsplit) ? 0 : 3;
+#pragma unroll
+    for (int c = 0; c < kNCC; ++c) {
+      const double r = fma(-th[c], x[c], w[c]);
+      if (c < ncc) R[i + (int64_t)(c0 + c) * ldr] = r;
+      // branch-free selection of the half
+      double* a6 = acc + 6 * c;
+      const double rr = r * r, xr = x[c] * r, xx = x[c] * x[c];
+      if (off == 0) {
+        a6[0] += rr; a6[1] += xr; a6[2] += xx;
+      } else {
+        a6[3] += rr; a6[4] += xr; a6[5] += xx;
+      }
+    }
+  }
+  // partial layout: [block][q * nc + cand]
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+#pragma unroll
+  for (int a = 0; a < 6 * kNCC; ++a) {
+    double v = wave_sum(acc[a]);
+    if (lane == 0) sh[w * 6 * kNCC + a] = v;
+  }
+  __syncthreads();
+  for (int a = threadIdx.x; a < 6 * kNCC; a += kThreads) {
+    const int c = a / 6, q = a % 6;
+    if (c < ncc) {
+      double v = ((sh[a] + sh[6 * kNCC + a]) + sh[12 * kNCC + a]) + sh[18 * kNCC + a];
+      partial[(int64_t)blockIdx.x * 6 * nc + q * nc + c0 + c] = v;
+    }
+  }
+}
+
+void ts_residual(const double* V, const double* W, int64_t ld, int64_t N, int64_t nsplit, int g,
+                 const double* Y, int64_t ldy, const double* theta, int nc, double* R,
+                 int64_t ldr, double* partial, double* sums, hipStream_t s) {
+  if (g > kMaxBasis) throw Error(SVDS_ERR_ARG, "residual: basis too large");
+  int nb = reduce_blocks(N);
+  dim3 grid(nb, (nc + kNCC - 1) / kNCC);
+  k_residual<<<grid, kThreads, 0, s>>>(V, W, ld, N, nsplit, g, Y, ldy, theta, nc, R, ldr,
+                                        partial);
+  SVDS_LAUNCH_CHECK();
+  reduce_partials(partial, nb, 6 * nc, sums, s);
+}
+
+// ---------------------------------------------------------------------------
+// small helpers: pack / unpack between column-major and row-major blocks,
+// preconditioned gather, row scaling, column copies
+// ---------------------------------------------------------------------------
+__global__ void k_pack(const double* __restrict__ A, int64_t lda, const double* __restrict__ Bm,
+                       double beta, int64_t N, int b, double* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < N; i += stride)
+    for (int c = 0; c < b; ++c) {
+      double v = A[i + c * lda];
+      if (Bm) v = fma(beta, Bm[i + c * lda], v);
+      out[i * b + c] = v;
+    }
+}
+
+void pack_rows(const double* A, int64_t lda, const double* B, double beta, int64_t N, int b,
+               double* compact, hipStream_t s) {
+  int blocks = (int)std::min<int64_t>(8192, (N + 255) / 256);
+  if (blocks < 1) return;
+  k_pack<<<blocks, 256, 0, s>>>(A, lda, B, beta, N, b, compact);
+  SVDS_LAUNCH_CHECK();
+}
+
+__global__ void k_unpack(const double* __restrict__ in, int64_t N, int b, double* __restrict__ A,
+                         int64_t lda) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < N; i += stride)
+    for (int c = 0; c < b; ++c) A[i + c * lda] = in[i * b + c];
+}
+
+void unpack_rows(const double* compact, int64_t N, int b, double* A, int64_t lda, hipStream_t s) {
+  int blocks = (int)std::min<int64_t>(8192, (N + 255) / 256);
+  if (blocks < 1) return;
+  k_unpack<<<blocks, 256, 0, s>>>(compact, N, b, A, lda);
+  SVDS_LAUNCH_CHECK();
+}
+
+__global__ void k_gather(const double* __restrict__ R, int64_t ldr, const int* __restrict__ blk,
+                         int nb, const double* __restrict__ dinv, int64_t N,
+                         double* __restrict__ T, int64_t ldt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < N; i += stride) {
+    const double d = dinv ? dinv[i] : 1.0;
+    for (int c = 0; c < nb; ++c) T[i + c * ldt] = R[i + (int64_t)blk[c] * ldr] * d;
+  }
+}
+
+void gather_precond(const double* R, int64_t ldr, const int* d_blk, int nb, const double* dinv,
+                    int64_t N, double* T, int64_t ldt, hipStream_t s) {
+  int blocks = (int)std::min<int64_t>(8192, (N + 255) / 256);
+  if (blocks < 1) return;
+  k_gather<<<blocks, 256, 0, s>>>(R, ldr, d_blk, nb, dinv, N, T, ldt);
+  SVDS_LAUNCH_CHECK();
+}
+
+__global__ void k_scale_rows(double* __restrict__ T, int64_t ldt, int64_t N, int b,
+                             const double* __restrict__ dinv) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < N; i += stride) {
+    const double d = dinv[i];
+    for (int c = 0; c < b; ++c) T[i + c * ldt] *= d;
+  }
+}
+
+void scale_rows(double* T, int64_t ldt, int64_t N, int b, const double* dinv, hipStream_t s) {
+  int blocks = (int)std::min<int64_t>(8192, (N + 255) / 256);
+  if (blocks < 1) return;
+  k_scale_rows<<<blocks, 256, 0, s>>>(T, ldt, N, b, dinv);
+  SVDS_LAUNCH_CHECK();
+}
+
+__global__ void k_copy_cols(const double* __restrict__ A, int64_t lda, int64_t N, int b,
+                            double* __restrict__ Bm, int64_t ldb) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < N; i += stride)
+    for (int c = 0; c < b; ++c) Bm[i + c * ldb] = A[i + c * lda];
+}
+
+void copy_cols(const double* A, int64_t lda, int64_t N, int b, double* B, int64_t ldb,
+               hipStream_t s) {
+  int blocks = (int)std::min<int64_t>(8192, (N + 255) / 256);
+  if (blocks < 1 || b < 1) return;
+  k_copy_cols<<<blocks, 256, 0, s>>>(A, lda, N, b, B, ldb);
+  SVDS_LAUNCH_CHECK();
+}
+
+}  // namespace svds
+
+namespace svds {
+
+// ---------------------------------------------------------------------------
+// per-column sums  out[c] = sum_i (A_ic - s_c B_ic)^2  (B may be null: norms)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_colres(const double* __restrict__ A, int64_t lda,
+                                                     const double* __restrict__ Bm, int64_t ldb,
+                                                     const double* __restrict__ sc, int64_t N,
+                                                     int k, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const int c = blockIdx.y;
+  const double s = (Bm && sc) ? sc[c] : 0.0;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kThreads) {
+    double v = A[i + c * lda];
+    if (Bm) v = fma(-s, Bm[i + c * ldb], v);
+    acc = fma(v, v, acc);
+  }
+  acc = wave_sum(acc);
+  if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * k + c] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+void col_residual2(const double* A, int64_t lda, const double* B, int64_t ldb, const double* sc,
+                   int64_t N, int k, double* partial, double* out, hipStream_t s) {
+  if (k <= 0) return;
+  int nb = reduce_blocks(N);
+  dim3 grid(nb, k);
+  k_colres<<<grid, kThreads, 0, s>>>(A, lda, B, ldb, sc, N, k, partial);
+  SVDS_LAUNCH_CHECK();
+  reduce_partials(partial, nb, k, out, s);
+}
+
+__global__ void k_col_scale(double* __restrict__ X, int64_t ld, int64_t N, int k,
+                            const double* __restrict__ f) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < N; i += stride)
+    for (int c = 0; c < k; ++c) X[i + c * ld] *= f[c];
+}
+
+void col_scale(double* X, int64_t ld, int64_t N, int k, const double* f, hipStream_t s) {
+  int blocks = (int)std::min<int64_t>(8192, (N + 255) / 256);
+  if (blocks < 1 || k < 1) return;
+  k_col_scale<<<blocks, 256, 0, s>>>(X, ld, N, k, f);
+  SVDS_LAUNCH_CHECK();
+}
+
+// per-column position of the largest |x| (first one on ties): partial pass
+__global__ __launch_bounds__(kThreads) void k_colargmax(const double* __restrict__ X, int64_t ld,
+                                                        int64_t N, int k,
+                                                        double* __restrict__ pval,
+                                                        int64_t* __restrict__ pidx) {
+  __shared__ double sv[kThreads];
+  __shared__ int64_t si[kThreads];
+  const int c = blockIdx.y;
+  double best = -1.0;
+  int64_t bi = INT64_MAX;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kThreads) {
+    const double v = fabs(X[i + c * ld]);
+    if (v > best) {  // rows visited in increasing order: keeps the first maximum
+      best = v;
+      bi = i;
+    }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      const double v2 = sv[threadIdx.x + off];
+      const int64_t i2 = si[threadIdx.x + off];
+      if (v2 > sv[threadIdx.x] || (v2 == sv[threadIdx.x] && i2 < si[threadIdx.x])) {
+        sv[threadIdx.x] = v2;
+        si[threadIdx.x] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    pval[(int64_t)blockIdx.x * k + c] = sv[0];
+    pidx[(int64_t)blockIdx.x * k + c] = si[0];
+  }
+}
+
+// flip (u_c, v_c) when the first largest-magnitude entry of v_c is negative
+__global__ void k_sign_flip(const double* __restrict__ pval, const int64_t* __restrict__ pidx,
+                            int nblk, int k, const double* __restrict__ Vv, int64_t ldv,
+                            double* __restrict__ f) {
+  const int c = threadIdx.x;
+  if (c >= k) return;
+  double best = -1.0;
+  int64_t bi = INT64_MAX;
+  for (int b = 0; b < nblk; ++b) {
+    const double v = pval[(int64_t)b * k + c];
+    const int64_t i = pidx[(int64_t)b * k + c];
+    if (v > best || (v == best && i < bi)) {
+      best = v;
+      bi = i;
+    }
+  }
+  f[c] = (bi != INT64_MAX && Vv[bi + c * ldv] < 0.0) ? -1.0 : 1.0;
+}
+
+void sign_factors(const double* V, int64_t ldv, int64_t N, int k, double* partial, double* f,
+                  hipStream_t s) {
+  int nb = reduce_blocks(N);
+  double* pval = partial;
+  int64_t* pidx = reinterpret_cast<int64_t*>(partial + (int64_t)nb * k);
+  dim3 grid(nb, k);
+  k_colargmax<<<grid, kThreads, 0, s>>>(V, ldv, N, k, pval, pidx);
+  SVDS_LAUNCH_CHECK();
+  k_sign_flip<<<1, 64, 0, s>>>(pval, pidx, nb, k, V, ldv, f);
+  SVDS_LAUNCH_CHECK();
+}
+
+}  // namespace svds

@@ -1,0 +1,750 @@
+// Single-workgroup FP64 kernels for the small replicated problems of the
+// eigensolver (Section 3.3: "the cost of small matrix operations ... is
+// negligible"): the projected eigenproblem (cyclic two-sided Jacobi), the
+// SVD of the refined R factor (one-sided Jacobi), Cholesky factors of block
+// Gram matrices, Householder QR for the refined restart (Section 3.2), and
+// the control step that applies the convergence tests, picks the block and
+// builds the GD+k restart coefficients.
+#include "small.h"
+
+namespace svds {
+
+constexpr int kT = kSmallThreads;
+constexpr int kLs = kLd + 1;  // padded leading dimension in LDS
+
+// round-robin pairing for np (even) indices, round r in [0, np-1)
+__device__ __forceinline__ void rr_pair(int np, int r, int k, int& p, int& q) {
+  if (k == 0) {
+    p = np - 1;
+    q = r;
+  } else {
+    p = (r + k) % (np - 1);
+    q = (r - k + np - 1) % (np - 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// symmetric eigenproblem by cyclic Jacobi; A (n x n, ld kLs) in LDS is
+// destroyed, Z receives the eigenvectors (unsorted), d the eigenvalues.
+// ---------------------------------------------------------------------------
+__device__ void jacobi_eig_lds(int n, double* A, double* Z, double* d, double* cs, double* sn,
+                               int* flag) {
+  const int t = threadIdx.x;
+  const int np = n + (n & 1);
+  for (int a = t; a < np * kLs; a += kT) Z[a] = 0.0;
+  __syncthreads();
+  if (n & 1) {  // padding index with a zero row and column
+    for (int j = t; j < np; j += kT) {
+      A[n * kLs + j] = 0.0;
+      A[j * kLs + n] = 0.0;
+    }
+  }
+  for (int j = t; j < np; j += kT) Z[j * kLs + j] = 1.0;
+  __shared__ double frob2;
+  if (t == 0) {
+    double f = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) f += A[i * kLs + j] * A[i * kLs + j];
+    frob2 = f;
+  }
+  __syncthreads();
+  const double thr = 0.1 * kEps * sqrt(frob2) / (double)max(n, 1);
+  for (int sweep = 0; sweep < 50 && np > 1; ++sweep) {
+    if (t == 0) *flag = 0;
+    __syncthreads();
+    for (int r = 0; r < np - 1; ++r) {
+      if (t < np / 2) {
+        int p, q;
+        rr_pair(np, r, t, p, q);
+        const double apq = A[p * kLs + q];
+        double c = 1.0, s = 0.0;
+        if (fabs(apq) > thr) {
+          const double app = A[p * kLs + p], aqq = A[q * kLs + q];
+          const double th = (aqq - app) / (2.0 * apq);
+          const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          c = 1.0 / sqrt(tt * tt + 1.0);
+          s = tt * c;
+          *flag = 1;
+        }
+        cs[t] = c;
+        sn[t] = s;
+      }
+      __syncthreads();
+      // rows p, q <- J^T rows
+      for (int a = t; a < (np / 2) * np; a += kT) {
+        const int k = a / np, j = a % np;
+        int p, q;
+        rr_pair(np, r, k, p, q);
+        const double c = cs[k], s = sn[k];
+        if (s != 0.0) {
+          const double x = A[p * kLs + j], y = A[q * kLs + j];
+          A[p * kLs + j] = c * x - s * y;
+          A[q * kLs + j] = s * x + c * y;
+        }
+      }
+      __syncthreads();
+      // columns p, q <- columns J; eigenvectors likewise
+      for (int a = t; a < (np / 2) * np; a += kT) {
+        const int k = a / np, j = a % np;
+        int p, q;
+        rr_pair(np, r, k, p, q);
+        const double c = cs[k], s = sn[k];
+        if (s != 0.0) {
+          double x = A[j * kLs + p], y = A[j * kLs + q];
+          A[j * kLs + p] = c * x - s * y;
+          A[j * kLs + q] = s * x + c * y;
+          x = Z[j * kLs + p];
+          y = Z[j * kLs + q];
+          Z[j * kLs + p] = c * x - s * y;
+          Z[j * kLs + q] = s * x + c * y;
+        }
+      }
+      __syncthreads();
+    }
+    if (*flag == 0) break;
+    __syncthreads();
+  }
+  for (int i = t; i < n; i += kT) d[i] = A[i * kLs + i];
+  __syncthreads();
+}
+
+// sort eigenpairs: theta[rank] = d[i], Y[:, rank] = Z[0:n, i]
+__device__ void sort_pairs(int n, const double* d, const double* Z, int descending,
+                           double* theta, double* Y, int ldy) {
+  const int t = threadIdx.x;
+  for (int i = t; i < n; i += kT) {
+    const double di = d[i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double dj = d[j];
+      const bool before = descending ? (dj > di || (dj == di && j < i)) : (dj < di || (dj == di && j < i));
+      rank += before;
+    }
+    theta[rank] = di;
+    for (int r = 0; r < n; ++r) Y[(int64_t)rank * ldy + r] = Z[r * kLs + i];
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kT) void k_eig(int g, const double* H, int ldh, int descending,
+                                            double* theta, double* Y, int ldy) {
+  __shared__ double A[kLd * kLs];
+  __shared__ double Z[kLd * kLs];
+  __shared__ double d[kLd], cs[kLd], sn[kLd];
+  __shared__ int flag;
+  for (int a = threadIdx.x; a < g * g; a += kT) {
+    const int i = a % g, j = a / g;
+    A[i * kLs + j] = 0.5 * (H[(int64_t)j * ldh + i] + H[(int64_t)i * ldh + j]);
+  }
+  __syncthreads();
+  jacobi_eig_lds(g, A, Z, d, cs, sn, &flag);
+  sort_pairs(g, d, Z, descending, theta, Y, ldy);
+}
+
+void small_eig(int g, const double* H, int ldh, int descending, double* theta, double* Y, int ldy,
+               hipStream_t s) {
+  if (g < 1 || g > kGmax) throw Error(SVDS_ERR_ARG, "small_eig: 1 <= g <= 48");
+  k_eig<<<1, kT, 0, s>>>(g, H, ldh, descending, theta, Y, ldy);
+  SVDS_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// one-sided Jacobi SVD of A (n x n, ld kLs, LDS): on return the columns of A
+// are U*Sigma (unsorted) and Vm the right singular vectors (unsorted)
+// ---------------------------------------------------------------------------
+__device__ void jacobi_svd_lds(int n, double* A, double* Vm, double* cs, double* sn, int* flag) {
+  const int t = threadIdx.x;
+  const int np = n + (n & 1);
+  for (int a = t; a < np * kLs; a += kT) Vm[a] = 0.0;
+  __syncthreads();
+  if (n & 1)
+    for (int j = t; j < np; j += kT) A[j * kLs + n] = 0.0;  // zero padding column
+  for (int j = t; j < np; j += kT) Vm[j * kLs + j] = 1.0;
+  __syncthreads();
+  const int npair = np / 2;
+  constexpr int G = 8;  // lanes per pair
+  for (int sweep = 0; sweep < 80 && np > 1; ++sweep) {
+    if (t == 0) *flag = 0;
+    __syncthreads();
+    for (int r = 0; r < np - 1; ++r) {
+      const int k = t / G, l = t % G;
+      double al = 0.0, be = 0.0, ga = 0.0;
+      int p = 0, q = 0;
+      if (k < npair) {
+        rr_pair(np, r, k, p, q);
+        for (int i = l; i < n; i += G) {
+          const double x = A[i * kLs + p], y = A[i * kLs + q];
+          al += x * x;
+          be += y * y;
+          ga += x * y;
+        }
+      }
+#pragma unroll
+      for (int off = G / 2; off > 0; off >>= 1) {
+        al += __shfl_xor(al, off, kWave);
+        be += __shfl_xor(be, off, kWave);
+        ga += __shfl_xor(ga, off, kWave);
+      }
+      if (k < npair && l == 0) {
+        double c = 1.0, s = 0.0;
+        if (fabs(ga) > kEps * sqrt(al * be) && ga != 0.0) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          c = 1.0 / sqrt(1.0 + tt * tt);
+          s = c * tt;
+          *flag = 1;
+        }
+        cs[k] = c;
+        sn[k] = s;
+      }
+      __syncthreads();
+      for (int a = t; a < npair * np; a += kT) {
+        const int kk = a / np, i = a % np;
+        int pp, qq;
+        rr_pair(np, r, kk, pp, qq);
+        const double c = cs[kk], s = sn[kk];
+        if (s != 0.0) {
+          double x = A[i * kLs + pp], y = A[i * kLs + qq];
+          A[i * kLs + pp] = c * x - s * y;
+          A[i * kLs + qq] = s * x + c * y;
+          x = Vm[i * kLs + pp];
+          y = Vm[i * kLs + qq];
+          Vm[i * kLs + pp] = c * x - s * y;
+          Vm[i * kLs + qq] = s * x + c * y;
+        }
+      }
+      __syncthreads();
+    }
+    if (*flag == 0) break;
+    __syncthreads();
+  }
+}
+
+// columns norms of A -> sv, sorted ascending; Y[:, rank] = Vm[:, j]; AV likewise
+__device__ void svd_finish(int n, const double* A, const double* Vm, double* sbuf, double* s,
+                           double* Y, int ldy, double* AV, int ldav) {
+  const int t = threadIdx.x;
+  for (int j = t; j < n; j += kT) {
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) acc += A[i * kLs + j] * A[i * kLs + j];
+    sbuf[j] = sqrt(acc);
+  }
+  __syncthreads();
+  for (int j = t; j < n; j += kT) {
+    const double sj = sbuf[j];
+    int rank = 0;
+    for (int i = 0; i < n; ++i) rank += (sbuf[i] < sj) || (sbuf[i] == sj && i < j);
+    s[rank] = sj;
+    for (int i = 0; i < n; ++i) Y[(int64_t)rank * ldy + i] = Vm[i * kLs + j];
+    if (AV)
+      for (int i = 0; i < n; ++i) AV[(int64_t)rank * ldav + i] = A[i * kLs + j];
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kT) void k_svd(int g, const double* R, int ldr, double* s, double* Y,
+                                            int ldy, double* AV, int ldav) {
+  __shared__ double A[kLd * kLs];
+  __shared__ double Vm[kLd * kLs];
+  __shared__ double cs[kLd], sn[kLd], sb[kLd];
+  __shared__ int flag;
+  for (int a = threadIdx.x; a < g * g; a += kT) {
+    const int i = a % g, j = a / g;
+    A[i * kLs + j] = R[(int64_t)j * ldr + i];
+  }
+  __syncthreads();
+  jacobi_svd_lds(g, A, Vm, cs, sn, &flag);
+  svd_finish(g, A, Vm, sb, s, Y, ldy, AV, ldav);
+}
+
+void small_svd(int g, const double* R, int ldr, double* s, double* Y, int ldy, double* AV,
+               int ldav, hipStream_t st) {
+  if (g < 1 || g > kGmax) throw Error(SVDS_ERR_ARG, "small_svd: 1 <= g <= 48");
+  k_svd<<<1, kT, 0, st>>>(g, R, ldr, s, Y, ldy, AV, ldav);
+  SVDS_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// projected matrix: append the new columns Hn ((gc+nb) x nb, ld gc+nb)
+// ---------------------------------------------------------------------------
+__global__ void k_h_append(Small* d, int gc, int nb) {
+  const int tot = gc + nb;
+  for (int a = threadIdx.x; a < tot * nb; a += blockDim.x) {
+    const int i = a % tot, c = a / tot;
+    const int j = gc + c;
+    double v = d->Hn[(int64_t)c * tot + i];
+    if (i >= gc) {  // symmetrise the new diagonal block
+      const int ci = i - gc;
+      v = 0.5 * (v + d->Hn[(int64_t)ci * tot + j]);
+    }
+    d->H[j * kLd + i] = v;
+    d->H[i * kLd + j] = v;
+  }
+}
+
+void small_h_append(Small* d, int gc, int nb, hipStream_t s) {
+  k_h_append<<<1, kT, 0, s>>>(d, gc, nb);
+  SVDS_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// extraction: Rayleigh-Ritz (eigenpairs of H in target order) or, for the
+// refined projection, right singular vectors of Rr in ascending order with
+// theta_j = y_j^T H y_j (Section 3.2)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kT) void k_extract(Small* d, int gc, int descending, int refined) {
+  __shared__ double A[kLd * kLs];
+  __shared__ double Z[kLd * kLs];
+  __shared__ double dd[kLd], cs[kLd], sn[kLd];
+  __shared__ int flag;
+  const int t = threadIdx.x;
+  if (!refined) {
+    for (int a = t; a < gc * gc; a += kT) {
+      const int i = a % gc, j = a / gc;
+      A[i * kLs + j] = 0.5 * (d->H[j * kLd + i] + d->H[i * kLd + j]);
+    }
+    __syncthreads();
+    jacobi_eig_lds(gc, A, Z, dd, cs, sn, &flag);
+    sort_pairs(gc, dd, Z, descending, d->theta, d->Y, kLd);
+  } else {
+    for (int a = t; a < gc * gc; a += kT) {
+      const int i = a % gc, j = a / gc;
+      A[i * kLs + j] = (i <= j) ? d->Rr[j * kLd + i] : 0.0;
+    }
+    __syncthreads();
+    jacobi_svd_lds(gc, A, Z, cs, sn, &flag);
+    svd_finish(gc, A, Z, dd, d->sv, d->Y, kLd, nullptr, 0);
+    // theta_j = y_j^T H y_j
+    for (int j = t; j < gc; j += kT) {
+      double acc = 0.0;
+      for (int r = 0; r < gc; ++r) {
+        double hy = 0.0;
+        for (int c = 0; c < gc; ++c) hy += d->H[c * kLd + r] * d->Y[j * kLd + c];
+        acc += d->Y[j * kLd + r] * hy;
+      }
+      d->theta[j] = acc;
+    }
+  }
+}
+
+void small_extract(Small* d, int gc, int descending, int refined, hipStream_t s) {
+  if (gc < 1 || gc > kGmax) throw Error(SVDS_ERR_ARG, "extract: basis size");
+  k_extract<<<1, kT, 0, s>>>(d, gc, descending, refined);
+  SVDS_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky QR factor of the block Gram matrix G (nb x nb) with a named-column
+// breakdown test; which = 1 writes R1/R1inv (and checks for columns that
+// collapsed during projection against the pre-projection norms stored as the
+// last nb rows of C0), which = 2 writes R2/R2inv.
+// ---------------------------------------------------------------------------
+__global__ void k_chol(Small* d, int nb, int which, int total) {
+  if (threadIdx.x != 0) return;
+  double R[kMaxBlock * kMaxBlock], Ri[kMaxBlock * kMaxBlock];
+  const double* G = d->G;
+  int bad = 0;
+  for (int a = 0; a < nb * nb; ++a) R[a] = Ri[a] = 0.0;
+  for (int j = 0; j < nb; ++j) {
+    const double gjj = G[j * nb + j];
+    const double dj = sqrt(fmax(gjj, 0.0));
+    double s = gjj;
+    for (int i = 0; i < j; ++i) s -= R[j * nb + i] * R[j * nb + i];
+    bool ok = (s > (kBreakRatio * dj) * (kBreakRatio * dj)) && dj > 0.0;
+    if (which == 1 && ok) {
+      const int ld0 = total + nb;
+      const double g0 = d->C0[(int64_t)j * ld0 + total + j];  // ||t_j||^2 before projection
+      ok = (gjj > (kCollapse * kCollapse) * g0) && g0 > 0.0;
+    }
+    if (!ok) {
+      bad |= 1 << j;
+      R[j * nb + j] = 1.0;  // keep the factor finite; the block is redone
+      continue;
+    }
+    const double rjj = sqrt(s);
+    R[j * nb + j] = rjj;
+    for (int c = j + 1; c < nb; ++c) {
+      double v = 0.5 * (G[c * nb + j] + G[j * nb + c]);
+      for (int i = 0; i < j; ++i) v -= R[j * nb + i] * R[c * nb + i];
+      R[c * nb + j] = v / rjj;  // column-major: R(j, c) at c*nb + j
+    }
+  }
+  // inverse of the upper triangular R (column-major)
+  for (int c = 0; c < nb; ++c) {
+    Ri[c * nb + c] = 1.0 / R[c * nb + c];
+    for (int i = c - 1; i >= 0; --i) {
+      double v = 0.0;
+      for (int j = i + 1; j <= c; ++j) v += R[j * nb + i] * Ri[c * nb + j];
+      Ri[c * nb + i] = -v / R[i * nb + i];
+    }
+  }
+  double* Ro = which == 1 ? d->R1 : d->R2;
+  double* Rio = which == 1 ? d->R1inv : d->R2inv;
+  for (int a = 0; a < nb * nb; ++a) {
+    Ro[a] = R[a];
+    Rio[a] = Ri[a];
+  }
+  d->bad |= bad;
+}
+
+void small_chol(Small* d, int nb, int which, int total, hipStream_t s) {
+  k_chol<<<1, 64, 0, s>>>(d, nb, which, total);
+  SVDS_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// refined factor: Rr[0:gc, gc:gc+nb] = C0 + C1 (projection coefficients),
+// Rr[gc:, gc:] = R2 R1, below-diagonal entries zero
+// ---------------------------------------------------------------------------
+__global__ void k_rr_append(Small* d, int gc, int nb) {
+  const int ld0 = gc + nb;
+  for (int a = threadIdx.x; a < (gc + nb) * nb; a += blockDim.x) {
+    const int i = a % (gc + nb), c = a / (gc + nb);
+    double v;
+    if (i < gc) {
+      v = d->C0[(int64_t)c * ld0 + i] + d->C1[(int64_t)c * gc + i];
+    } else {
+      const int ii = i - gc;
+      v = 0.0;
+      for (int j = ii; j <= c; ++j) v += d->R2[j * nb + ii] * d->R1[c * nb + j];
+    }
+    d->Rr[(gc + c) * kLd + i] = v;
+    if (i < gc) d->Rr[i * kLd + gc + c] = 0.0;
+  }
+}
+
+void small_rr_append(Small* d, int gc, int nb, int total, hipStream_t s) {
+  (void)total;
+  k_rr_append<<<1, kT, 0, s>>>(d, gc, nb);
+  SVDS_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// control step
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double halves_res(const double* sums, int nc, int c, double theta) {
+  // eq. (res) of the normalised halves from the fused sums (see k_residual):
+  // A v - s u = r_u/a + x_u (theta/a - s/c),  A^T u - s v = r_v/c + x_v (theta/c - s/a)
+  const double rv2 = sums[0 * nc + c], xrv = sums[1 * nc + c], xv2 = sums[2 * nc + c];
+  const double ru2 = sums[3 * nc + c], xru = sums[4 * nc + c], xu2 = sums[5 * nc + c];
+  const double a = sqrt(fmax(xv2, 0.0)), cc = sqrt(fmax(xu2, 0.0));
+  if (!(a > 0.0) || !(cc > 0.0)) return INFINITY;
+  const double s = fabs(theta);
+  const double e1 = theta / a - s / cc;
+  const double e2 = theta / cc - s / a;
+  const double t1 = ru2 / (a * a) + 2.0 * e1 * xru / a + e1 * e1 * xu2;
+  const double t2 = rv2 / (cc * cc) + 2.0 * e2 * xrv / cc + e2 * e2 * xv2;
+  return sqrt(fmax(t1, 0.0) + fmax(t2, 0.0));
+}
+
+__global__ __launch_bounds__(kT) void k_control(Small* d, CtlParams P) {
+  __shared__ int s_action, s_nblock, s_restart, s_reff, s_off, s_peff, s_nr, s_lock;
+  __shared__ int s_blk[kMaxBlock];
+  __shared__ double Yr[kLd * kLs];
+  __shared__ double M[kLd * kLs];
+  const int t = threadIdx.x;
+  const int gc = P.gc, nc = P.nc;
+  if (t == 0) {
+    Ctl& C = d->ctl;
+    double mx = 0.0;
+    for (int j = 0; j < gc; ++j) mx = fmax(mx, fabs(d->theta[j]));
+    d->normop = fmax(d->normop, mx);
+    const double nop = d->normop;
+    bool conv[kKmax + 8], done[kKmax + 8];
+    double rn[kKmax + 8];
+    int ncv = 0, npc = 0;
+    for (int c = 0; c < nc; ++c) {
+      rn[c] = sqrt(fmax(d->sums[0 * nc + c] + d->sums[3 * nc + c], 0.0));
+      C.res[c] = rn[c];
+      C.val[c] = d->theta[c];
+      if (P.stage == 1) {
+        const double thr = fmax(sqrt(fabs(d->theta[c]) * nop) * P.tol, P.eps * nop);
+        conv[c] = rn[c] <= thr;
+        const bool pc = !conv[c] && d->stall[c] >= kStallRestarts && rn[c] <= kFloorGate * P.eps * nop;
+        done[c] = conv[c] || pc;
+        npc += pc;
+      } else {
+        conv[c] = false;
+        if (rn[c] <= 1.4142135623730951 * nop * P.tol)
+          conv[c] = halves_res(d->sums, nc, c, d->theta[c]) < P.normA * P.tol;
+        done[c] = conv[c];
+      }
+      ncv += conv[c];
+    }
+    int action = kExpand, nblock = 0, restart = 0, reff = 0, off = 0, peff = 0, lock = 0;
+    int floor_reset = 0;
+    double maxres = 0.0, minres = INFINITY;
+    const int kk = min(P.k, nc);
+    for (int c = 0; c < kk; ++c) maxres = fmax(maxres, rn[c]);
+    if (P.stage == 1) {
+      bool all = (kk == P.k);
+      bool anypc = false;
+      for (int c = 0; c < kk; ++c) {
+        all = all && done[c];
+        anypc = anypc || (done[c] && !conv[c]);
+      }
+      if (all) {
+        if (anypc && P.floor_resets < 1) {
+          action = kReset;
+          floor_reset = 1;
+          for (int c = 0; c < kKmax + 8; ++c) {
+            d->best[c] = INFINITY;
+            d->stall[c] = 0;
+          }
+        } else {
+          action = anypc ? kExitFloor : kExitConverged;
+        }
+      } else if (P.budget_hit) {
+        action = kExitBudget;
+      } else {
+        for (int c = 0; c < nc && nblock < P.b; ++c)
+          if (!done[c]) s_blk[nblock++] = c;
+        for (int j = 0; j < nblock; ++j) minres = fmin(minres, rn[s_blk[j]]);
+        if (nblock > 0 && P.since_reset > 0 && minres < sqrt((double)P.since_reset) * nop * P.eps) {
+          action = kReset;
+        } else {
+          const int nb_next = nblock > 0 ? nblock : P.b;
+          if (gc + nb_next > P.g) {
+            restart = 1;
+            for (int c = 0; c < nc; ++c) {
+              if (rn[c] < 0.5 * d->best[c]) {
+                d->best[c] = rn[c];
+                d->stall[c] = 0;
+              } else {
+                d->stall[c] += 1;
+              }
+            }
+            int nd = 0;
+            for (int c = 0; c < nc; ++c) nd += done[c];
+            reff = min(max(P.r, nd + P.b), P.g - P.b);
+            off = 0;
+          }
+        }
+      }
+    } else {
+      int L = 0;
+      while (L < nc && conv[L]) ++L;
+      if (L > 0) {
+        for (int i = 0; i < L; ++i) d->lockval[P.nlock + i] = d->theta[i];
+        lock = L;
+        if (P.nlock + L >= P.k) {
+          action = kExitConverged;
+        } else {
+          action = kLock;
+          restart = 1;
+          reff = min(P.r, gc - L);
+          off = L;
+        }
+      } else if (P.budget_hit) {
+        action = kExitBudget;
+      } else {
+        for (int c = 0; c < nc; ++c) s_blk[nblock++] = c;
+        for (int j = 0; j < nblock; ++j) minres = fmin(minres, rn[s_blk[j]]);
+        if (P.since_reset > 0 && minres < sqrt((double)P.since_reset) * nop * P.eps) {
+          action = kReset;
+        } else if (gc + nblock > P.g) {
+          restart = 1;
+          reff = min(P.r, gc);
+          off = 0;
+        }
+      }
+    }
+    if (restart) {
+      const int room = max(0, P.g - P.b - reff);
+      peff = (P.p > 0) ? min(min(P.p, d->nprev), room) : 0;
+    }
+    if (action == kReset) d->nprev = 0;
+    s_action = action;
+    s_nblock = nblock;
+    s_restart = restart;
+    s_reff = reff;
+    s_off = off;
+    s_peff = peff;
+    s_lock = lock;
+    C.action = action;
+    C.nblock = nblock;
+    C.nlockable = lock;
+    C.nconv = ncv;
+    C.npc = npc;
+    C.floor_reset = floor_reset;
+    C.normop = nop;
+    C.maxres = maxres;
+    C.minres = minres;
+  }
+  __syncthreads();
+  const int action = s_action;
+  const int nblock = s_nblock;
+  if (s_restart) {
+    const int reff = s_reff, off = s_off, peff = s_peff;
+    // retained extraction vectors
+    for (int a = t; a < gc * reff; a += kT) {
+      const int i = a % gc, j = a / gc;
+      Yr[i * kLs + j] = d->Y[(off + j) * kLd + i];
+    }
+    __syncthreads();
+    // +k: previous block coefficient vectors (zero padded), Gram-Schmidt
+    // twice against Y[:, 0:off+reff] and the accepted ones, in wave 0
+    int nr = reff;
+    if (t < kWave) {
+      const int lane = t;
+      for (int pv = 0; pv < peff; ++pv) {
+        double y = (lane < d->gprev) ? d->yprev[pv * kLd + lane] : 0.0;
+        if (lane >= gc) y = 0.0;
+        for (int rep = 0; rep < 2; ++rep) {
+          for (int q = 0; q < off; ++q) {
+            const double yq = (lane < gc) ? d->Y[q * kLd + lane] : 0.0;
+            const double dot = wave_sum(y * yq);
+            y -= dot * yq;
+          }
+          for (int q = 0; q < nr; ++q) {
+            const double yq = (lane < gc) ? Yr[lane * kLs + q] : 0.0;
+            const double dot = wave_sum(y * yq);
+            y -= dot * yq;
+          }
+        }
+        const double ny = sqrt(wave_sum(y * y));
+        if (ny > kPrevDrop) {
+          if (lane < gc) Yr[lane * kLs + nr] = y / ny;
+          ++nr;
+        }
+      }
+      if (lane == 0) s_nr = nr;
+    }
+    __syncthreads();
+    nr = s_nr;
+    // H <- Yr^T H Yr  (M = H Yr first)
+    for (int a = t; a < gc * nr; a += kT) {
+      const int i = a % gc, j = a / gc;
+      double acc = 0.0;
+      for (int c = 0; c < gc; ++c) acc += d->H[c * kLd + i] * Yr[c * kLs + j];
+      M[i * kLs + j] = acc;
+    }
+    __syncthreads();
+    for (int a = t; a < nr * nr; a += kT) {
+      const int i = a % nr, j = a / nr;
+      double acc = 0.0;
+      for (int c = 0; c < gc; ++c) acc += Yr[c * kLs + i] * M[c * kLs + j];
+      d->Qt[j * kLd + i] = acc;  // staged; symmetrised below
+    }
+    __syncthreads();
+    for (int a = t; a < nr * nr; a += kT) {
+      const int i = a % nr, j = a / nr;
+      d->H[j * kLd + i] = 0.5 * (d->Qt[j * kLd + i] + d->Qt[i * kLd + j]);
+    }
+    __syncthreads();
+    // next +k vectors: the block's coefficients in the new basis
+    if (action == kExpand) {
+      for (int a = t; a < nr * nblock; a += kT) {
+        const int i = a % nr, c = a / nr;
+        double acc = 0.0;
+        for (int r = 0; r < gc; ++r) acc += Yr[r * kLs + i] * d->Y[s_blk[c] * kLd + r];
+        d->yprev[c * kLd + i] = acc;
+      }
+    }
+    // refined factor restart: Rr Yr = Qt Rt (Householder), Rr <- Rt
+    if (P.refined) {
+      for (int a = t; a < gc * nr; a += kT) {
+        const int i = a % gc, j = a / gc;
+        double acc = 0.0;
+        for (int c = i; c < gc; ++c) acc += d->Rr[c * kLd + i] * Yr[c * kLs + j];
+        M[i * kLs + j] = acc;
+      }
+      __syncthreads();
+      // Householder QR of M (gc x nr); reflectors kept below the diagonal
+      __shared__ double vnorm2[kLd];
+      __shared__ double diag[kLd];
+      for (int j = 0; j < nr; ++j) {
+        if (t == 0) {
+          double s2 = 0.0;
+          for (int i = j; i < gc; ++i) s2 += M[i * kLs + j] * M[i * kLs + j];
+          const double x0 = M[j * kLs + j];
+          const double nx = sqrt(s2);
+          const double alpha = (x0 >= 0.0) ? -nx : nx;
+          M[j * kLs + j] = x0 - alpha;  // v_j (v = x - alpha e1)
+          const double v2 = s2 - x0 * x0 + (x0 - alpha) * (x0 - alpha);
+          vnorm2[j] = v2;
+          diag[j] = alpha;
+        }
+        __syncthreads();
+        const double v2 = vnorm2[j];
+        for (int c = j + 1 + t; c < nr; c += kT) {
+          if (v2 > 0.0) {
+            double w = 0.0;
+            for (int i = j; i < gc; ++i) w += M[i * kLs + j] * M[i * kLs + c];
+            const double f = 2.0 * w / v2;
+            for (int i = j; i < gc; ++i) M[i * kLs + c] -= f * M[i * kLs + j];
+          }
+        }
+        __syncthreads();
+      }
+      // Qt = H_0 ... H_{nr-1} I[:, 0:nr]; columns independent
+      for (int c = t; c < nr; c += kT) {
+        for (int i = 0; i < gc; ++i) d->Qt[c * kLd + i] = (i == c) ? 1.0 : 0.0;
+        for (int j = nr - 1; j >= 0; --j) {
+          const double v2 = vnorm2[j];
+          if (!(v2 > 0.0)) continue;
+          double w = 0.0;
+          for (int i = j; i < gc; ++i) w += M[i * kLs + j] * d->Qt[c * kLd + i];
+          const double f = 2.0 * w / v2;
+          for (int i = j; i < gc; ++i) d->Qt[c * kLd + i] -= f * M[i * kLs + j];
+        }
+      }
+      __syncthreads();
+      for (int a = t; a < nr * nr; a += kT) {
+        const int i = a % nr, j = a / nr;
+        double v = 0.0;
+        if (i == j) v = diag[j];
+        else if (i < j) v = M[i * kLs + j];
+        d->Rr[j * kLd + i] = v;
+      }
+    }
+    __syncthreads();
+    // restart coefficients for the host's V <- V Yr
+    for (int a = t; a < gc * nr; a += kT) {
+      const int i = a % gc, j = a / gc;
+      d->Yr[j * kLd + i] = Yr[i * kLs + j];
+    }
+    if (t == 0) {
+      d->ctl.restart = 1;
+      d->ctl.nr = nr;
+      if (action == kExpand) {
+        d->nprev = nblock;
+        d->gprev = nr;
+      } else {
+        d->nprev = 0;
+      }
+    }
+  } else {
+    if (action == kExpand) {
+      for (int a = t; a < gc * nblock; a += kT) {
+        const int i = a % gc, c = a / gc;
+        d->yprev[c * kLd + i] = d->Y[s_blk[c] * kLd + i];
+      }
+    }
+    if (t == 0) {
+      d->ctl.restart = 0;
+      d->ctl.nr = gc;
+      if (action == kExpand) {
+        d->nprev = nblock;
+        d->gprev = gc;
+      }
+    }
+  }
+  if (t < kMaxBlock) d->blk[t] = (t < nblock) ? s_blk[t] : 0;
+}
+
+void small_control(Small* d, const CtlParams& p, hipStream_t s) {
+  if (p.nc > kKmax + 8 || p.gc > kGmax) throw Error(SVDS_ERR_ARG, "control: sizes");
+  k_control<<<1, kT, 0, s>>>(d, p);
+  SVDS_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// stage-1 final Rayleigh-Ritz on A X: eigenpairs of the k x k Gram matrix
+// ---------------------------------------------------------------------------
+void small_final_rr(int k, double* G, int ldg, int descending, double* lam, double* Z, int ldz,
+                    hipStream_t s) {
+  small_eig(k, G, ldg, descending, lam, Z, ldz, s);
+}
+
+}  // namespace svds

@@ -1,0 +1,148 @@
+// Block CSR SpMM Y = A X for the products with A and A^T of Section 3.3
+// (the user matrixMatvec of Section 3.4, here on the device).
+//
+// Rows are grouped into bins by length; each bin runs a kernel in which a
+// group of L lanes (L = 1 ... 64, or a whole workgroup for very long rows)
+// shares one row, each lane striding over the row's nonzeros and
+// accumulating all b columns of the row-major block X (one contiguous b-wide
+// gather per nonzero), followed by a shuffle reduction inside the group.
+// Every row is summed by one group in a fixed order: no atomics, results are
+// bitwise reproducible.
+#include "common.h"
+
+namespace svds {
+
+template <typename TV, int B, int L>
+__global__ __launch_bounds__(256) void k_spmm_group(const int32_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ ci,
+                                                    const TV* __restrict__ val,
+                                                    const int32_t* __restrict__ rows,
+                                                    int64_t nrows, const TV* __restrict__ X,
+                                                    TV* __restrict__ Y) {
+  constexpr int RPB = 256 / L;
+  const int grp = threadIdx.x / L;
+  const int lane = threadIdx.x % L;
+  const int bid = xcd_block(blockIdx.x, gridDim.x);
+  for (int64_t slot = (int64_t)bid * RPB + grp; slot < nrows; slot += (int64_t)gridDim.x * RPB) {
+    const int32_t row = rows[slot];
+    const int32_t a = rp[row], e = rp[row + 1];
+    TV acc[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) acc[j] = TV(0);
+    for (int32_t k = a + lane; k < e; k += L) {
+      const int32_t c = ci[k];
+      const TV v = val[k];
+      const TV* __restrict__ x = X + (int64_t)c * B;
+#pragma unroll
+      for (int j = 0; j < B; ++j) acc[j] = fma(v, x[j], acc[j]);
+    }
+    if constexpr (L > 1) {
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+#pragma unroll
+        for (int off = L / 2; off > 0; off >>= 1) acc[j] += __shfl_xor(acc[j], off, kWave);
+      }
+    }
+    if (lane == 0) {
+      TV* __restrict__ y = Y + (int64_t)row * B;
+#pragma unroll
+      for (int j = 0; j < B; ++j) y[j] = acc[j];
+    }
+  }
+}
+
+// one workgroup (256 lanes) per row, for rows longer than 4096
+template <typename TV, int B>
+__global__ __launch_bounds__(256) void k_spmm_wg(const int32_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ ci,
+                                                 const TV* __restrict__ val,
+                                                 const int32_t* __restrict__ rows, int64_t nrows,
+                                                 const TV* __restrict__ X, TV* __restrict__ Y) {
+  __shared__ TV part[4][B];
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  for (int64_t slot = blockIdx.x; slot < nrows; slot += gridDim.x) {
+    const int32_t row = rows[slot];
+    const int32_t a = rp[row], e = rp[row + 1];
+    TV acc[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) acc[j] = TV(0);
+    for (int32_t k = a + threadIdx.x; k < e; k += 256) {
+      const int32_t c = ci[k];
+      const TV v = val[k];
+#pragma unroll
+      for (int j = 0; j < B; ++j) acc[j] = fma(v, X[(int64_t)c * B + j], acc[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) acc[j] += __shfl_xor(acc[j], off, kWave);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < B; ++j) part[w][j] = acc[j];
+    }
+    __syncthreads();
+    if (threadIdx.x < B) {
+      int j = threadIdx.x;
+      Y[(int64_t)row * B + j] = ((part[0][j] + part[1][j]) + part[2][j]) + part[3][j];
+    }
+    __syncthreads();
+  }
+}
+
+template <typename TV, int B>
+static void spmm_b(const Csr32& A, const TV* val, const TV* X, TV* Y, hipStream_t s) {
+  for (int bn = 0; bn < kNumBins; ++bn) {
+    int64_t r0 = A.bin_off[bn], r1 = A.bin_off[bn + 1];
+    int64_t nr = r1 - r0;
+    if (nr <= 0) continue;
+    const int32_t* rows = A.binrows + r0;
+    if (bn == kNumBins - 1) {
+      int blocks = (int)std::min<int64_t>(nr, 8192);
+      k_spmm_wg<TV, B><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, rows, nr, X, Y);
+    } else {
+      const int L = 1 << bn;
+      const int64_t rpb = 256 / L;
+      int64_t need = (nr + rpb - 1) / rpb;
+      int blocks = (int)std::min<int64_t>(need, 16384);
+      if (blocks >= 64) blocks = (blocks / 8) * 8;  // whole XCD rounds for the remap
+      switch (bn) {
+        case 0: k_spmm_group<TV, B, 1><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, rows, nr, X, Y); break;
+        case 1: k_spmm_group<TV, B, 2><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, rows, nr, X, Y); break;
+        case 2: k_spmm_group<TV, B, 4><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, rows, nr, X, Y); break;
+        case 3: k_spmm_group<TV, B, 8><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, rows, nr, X, Y); break;
+        case 4: k_spmm_group<TV, B, 16><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, rows, nr, X, Y); break;
+        case 5: k_spmm_group<TV, B, 32><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, rows, nr, X, Y); break;
+        default: k_spmm_group<TV, B, 64><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, rows, nr, X, Y); break;
+      }
+    }
+    SVDS_LAUNCH_CHECK();
+  }
+}
+
+template <typename TV>
+static void spmm_dispatch(const Csr32& A, int b, const TV* val, const TV* X, TV* Y,
+                          hipStream_t s) {
+  switch (b) {
+    case 1: spmm_b<TV, 1>(A, val, X, Y, s); break;
+    case 2: spmm_b<TV, 2>(A, val, X, Y, s); break;
+    case 3: spmm_b<TV, 3>(A, val, X, Y, s); break;
+    case 4: spmm_b<TV, 4>(A, val, X, Y, s); break;
+    case 5: spmm_b<TV, 5>(A, val, X, Y, s); break;
+    case 6: spmm_b<TV, 6>(A, val, X, Y, s); break;
+    case 7: spmm_b<TV, 7>(A, val, X, Y, s); break;
+    case 8: spmm_b<TV, 8>(A, val, X, Y, s); break;
+    default: throw Error(SVDS_ERR_ARG, "spmm: block width must be 1..8");
+  }
+}
+
+void spmm(const Csr32& A, int b, const double* X, double* Y, hipStream_t s) {
+  spmm_dispatch<double>(A, b, A.val, X, Y, s);
+}
+
+void spmm_f32(const Csr32& A, int b, const float* X, float* Y, hipStream_t s) {
+  if (!A.val32) throw Error(SVDS_ERR_ARG, "spmm_f32: no FP32 values");
+  spmm_dispatch<float>(A, b, A.val32, X, Y, s);
+}
+
+}  // namespace svds

@@ -1,0 +1,91 @@
+// Small replicated objects of the eigensolver (Section 3.3: the projected
+// matrix, its eigenvectors, the refined R factor, restart coefficients) and
+// the decisions taken from them.  They live in device memory and are worked
+// on by single-workgroup kernels, so the iteration never needs the host to do
+// arithmetic; the host only reads the decision record back.
+#pragma once
+
+#include "common.h"
+
+namespace svds {
+
+constexpr int kLd = 48;          // leading dimension of the small matrices
+constexpr int kGmax = 48;        // largest basis the small kernels accept
+constexpr int kKmax = 48;        // largest number of wanted triplets
+
+enum Action : int {
+  kExpand = 0,      // correct the block and append it
+  kExitConverged = 1,
+  kExitFloor = 2,   // stage 1 stopped at its attainable accuracy
+  kExitBudget = 3,
+  kReset = 4,       // recompute W = Op V from a re-orthonormalised V
+  kLock = 5,        // stage 2: lock the converged prefix, then restart
+};
+
+struct Ctl {
+  int action;
+  int nblock;       // block columns to append
+  int restart;      // 1: restart coefficients are in Yr (gc x nr)
+  int nr;           // basis size after the restart
+  int nlockable;    // stage 2: converged prefix length
+  int nconv, npc;   // converged / practically converged among candidates
+  int floor_reset;  // the reset confirms the attainable floor
+  double normop;    // ||Op|| used by the tests
+  double maxres;    // largest residual of the wanted pairs
+  double minres;
+  double res[kKmax + 8];  // candidate residual norms (trace)
+  double val[kKmax + 8];  // candidate Ritz values (trace)
+};
+
+struct Small {
+  double H[kLd * kLd];     // V^T Op V
+  double Y[kLd * kLd];     // extraction vectors (eigen- or right singular vectors)
+  double theta[kLd];       // Ritz values (refined: y^T H y)
+  double sv[kLd];          // refined: singular values of Rr
+  double Rr[kLd * kLd];    // refined: R of (W - tau V) = Q Rr
+  double Yr[kLd * kLd];    // restart coefficients
+  double Qt[kLd * kLd];    // refined restart: R Yr = Qt Rt
+  double yprev[kLd * kMaxBlock];  // +k coefficient vectors
+  double Hn[(256 + kMaxBlock) * kMaxBlock];  // new columns of the projected matrix
+  double C0[(256 + kMaxBlock) * kMaxBlock];  // orthogonalisation coefficients, pass 1
+  double C1[256 * kMaxBlock];                // pass 2
+  double G[kMaxBlock * kMaxBlock];           // Gram of the block
+  double R1[kMaxBlock * kMaxBlock], R1inv[kMaxBlock * kMaxBlock];
+  double R2[kMaxBlock * kMaxBlock], R2inv[kMaxBlock * kMaxBlock];
+  double sums[6 * (kKmax + 8)];              // residual sums
+  double best[kKmax + 8];
+  int stall[kKmax + 8];
+  int blk[kMaxBlock];
+  int bad;                // orthogonalisation breakdown bitmask
+  int nprev, gprev;       // +k vectors: count and rows
+  double normop;          // running ||Op||
+  double lockval[kKmax];  // stage 2: locked Ritz values
+  Ctl ctl;
+};
+
+// parameters of a control step (by value)
+struct CtlParams {
+  int stage;        // 1 or 2
+  int gc, g, r, p, b, k;
+  int nc;           // candidates whose residuals were computed
+  int nlock;        // stage 2: vectors locked so far
+  int since_reset, floor_resets, budget_hit;
+  int refined;
+  double tol, normA, eps;
+};
+
+void small_eig(int g, const double* H, int ldh, int descending, double* theta, double* Y, int ldy,
+               hipStream_t s);
+void small_svd(int g, const double* R, int ldr, double* s, double* Y, int ldy, double* AV,
+               int ldav, hipStream_t st);
+void small_h_append(Small* d, int gc, int nb, hipStream_t s);
+void small_extract(Small* d, int gc, int descending, int refined, hipStream_t s);
+void small_chol(Small* d, int nb, int which, int ncheck, hipStream_t s);
+void small_rr_append(Small* d, int gc, int nb, int total, hipStream_t s);
+void small_control(Small* d, const CtlParams& p, hipStream_t s);
+void small_rtr_accumulate(const double* C0, int ldc0, const double* C1, int total, int nb,
+                          double* Cout, hipStream_t s);
+void small_final_rr(int k, double* G, int ldg, int descending, double* lam, double* Z, int ldz,
+                    hipStream_t s);
+
+}  // namespace svds

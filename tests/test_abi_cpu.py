@@ -1,0 +1,71 @@
+"""CPU checks of the C-ABI library: it loads without a GPU, exports every
+function include/svds.h declares, and the host-only entry points work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "svds.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(svds_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1607_01404_amd as P
+    return P.load_library()
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for want in ("svds_opts_init", "svds_error_string", "svds_matrix_create", "svds_matrix_destroy",
+                 "svds_matrix_spmm", "svds_solve", "svds_solve_prepared", "svds_small_eig",
+                 "svds_small_svd"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_opts_defaults(lib):
+    import paper_1607_01404_amd as P
+    o = P.opts_init()
+    assert o.max_basis_size == 0 and o.min_restart_size == 0 and o.block_size == 0
+    assert o.max_prev_retain == -1 and o.two_sided_cleanup == 1 and o.precision == P.FP64
+    assert lib.svds_opts_init(None) == -1
+
+
+def test_error_strings():
+    import paper_1607_01404_amd as P
+    assert P.error_string(0) == "ok"
+    assert "CSR" in P.error_string(-2)
+    assert P.error_string(12345) == "unknown status"
+
+
+def test_struct_layouts_match_header(tmp_path):
+    import shutil
+    import subprocess
+    import paper_1607_01404_amd._lib as L
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include "svds.h"\nint main(){printf("%zu %zu %zu\\n",'
+                   'sizeof(svds_opts),sizeof(svds_stats),sizeof(svds_csr));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.check_call([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split()
+    assert [int(x) for x in out] == [ctypes.sizeof(L.Opts), ctypes.sizeof(L.Stats), ctypes.sizeof(L.Csr)]
+
+
+def test_null_arguments_rejected(lib):
+    assert lib.svds_matrix_create(None, None, None) == -1
+    assert lib.svds_solve_prepared(None, 1, 0, 1e-10, None, None, None, 1, None, 1, None, None, None) == -1

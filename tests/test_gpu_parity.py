@@ -1,0 +1,208 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Every test prints the case it runs before touching the GPU."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import oracle.phsvds as OP
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1607_01404_amd as P
+    P.load_library()
+    return P
+
+
+def _binned_matrix(seed=3):
+    """Rows of every length class: empty, 1..4, ... up to one 5000-long row."""
+    rng = np.random.default_rng(seed)
+    n = 6000
+    lengths = [0, 0, 1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 31, 33, 63, 65, 127, 129, 500, 1000, 4096,
+               4097, 5000]
+    lengths = lengths + list(rng.integers(0, 40, size=3000))
+    m = len(lengths)
+    return synth.random_uniform_rows(m, n, np.array(lengths), seed=seed)
+
+
+@pytest.mark.parametrize("b", [1, 2, 3, 4, 8])
+def test_spmm_matches_scipy(P, b):
+    import torch
+    A = _binned_matrix()
+    _say("spmm", A.shape, A.nnz, "b", b)
+    M = P.Matrix.from_scipy(A)
+    rng = np.random.default_rng(b)
+    for trans in (False, True):
+        X = rng.standard_normal((A.shape[0] if trans else A.shape[1], b))
+        Y = M.spmm(torch.from_numpy(X).cuda(), trans=trans).cpu().numpy()
+        ref = (A.T @ X) if trans else (A @ X)
+        scale = (abs(A).T @ abs(X)) if trans else (abs(A) @ abs(X))
+        assert np.all(np.abs(Y - ref) <= 1e-14 * scale + 1e-300), trans
+    M.close()
+
+
+def test_spmm_deterministic(P):
+    import torch
+    A = synth.config3(m=20000, n=10000)
+    _say("spmm determinism", A.shape)
+    M = P.Matrix.from_scipy(A)
+    X = torch.from_numpy(np.random.default_rng(0).standard_normal((A.shape[1], 4))).cuda()
+    Y1 = M.spmm(X)
+    Y2 = M.spmm(X)
+    assert torch.equal(Y1, Y2)
+    M.close()
+
+
+@pytest.mark.parametrize("g", [1, 2, 7, 15, 35, 48])
+def test_small_eig_matches_lapack(P, g):
+    import torch
+    _say("small_eig", g)
+    rng = np.random.default_rng(g)
+    Q, _ = np.linalg.qr(rng.standard_normal((g, g)))
+    lam = np.sort(np.concatenate([rng.uniform(-1, 1, g - g // 3), 0.3 + 1e-9 * np.arange(g // 3)]))
+    H = (Q * lam) @ Q.T
+    for desc in (False, True):
+        th, Y = P.small_eig(torch.from_numpy(H).cuda(), descending=desc)
+        th = th.cpu().numpy()
+        Y = Y.cpu().numpy()
+        ref = np.linalg.eigvalsh(H)
+        ref = ref[::-1] if desc else ref
+        assert np.max(np.abs(th - ref)) <= 1e-14 * max(1.0, np.abs(lam).max()) * g
+        assert np.abs(Y.T @ Y - np.eye(g)).max() <= 1e-13
+        assert np.abs(H @ Y - Y * th).max() <= 1e-13
+
+
+@pytest.mark.parametrize("g", [1, 3, 16, 35, 48])
+def test_small_svd_matches_lapack(P, g):
+    import torch
+    _say("small_svd", g)
+    rng = np.random.default_rng(100 + g)
+    R = np.triu(rng.standard_normal((g, g)))
+    R[:, 0] *= 1e-9  # a tiny singular value, as in the refined factor near convergence
+    s, Y = P.small_svd(torch.from_numpy(R).cuda())
+    s = s.cpu().numpy()
+    Y = Y.cpu().numpy()
+    ref = np.sort(np.linalg.svd(R, compute_uv=False))
+    assert np.all(np.abs(s - ref) <= 1e-13 * ref.max() + 1e-15 * ref)
+    assert np.abs(Y.T @ Y - np.eye(g)).max() <= 1e-13
+    # smallest right singular vector: ||R y|| = s_min
+    assert abs(np.linalg.norm(R @ Y[:, 0]) - s[0]) <= 1e-13 * ref.max()
+
+
+def _compare(A, sig, U, V, rn, st, ref_sig, tol, normA, rel=1e-10):
+    sig = sig.cpu().numpy()
+    U = U.cpu().numpy()
+    V = V.cpu().numpy()
+    rn = rn.cpu().numpy()
+    k = sig.size
+    assert np.max(np.abs(sig - ref_sig) / ref_sig) <= rel, (sig, ref_sig)
+    # eq. (res) recomputed on the CPU from the returned triplets
+    r = np.sqrt(np.linalg.norm(A @ V - U * sig, axis=0) ** 2 + np.linalg.norm(A.T @ U - V * sig, axis=0) ** 2)
+    assert np.all(r <= tol * normA * 1.0001), r / normA
+    assert np.allclose(r, rn, rtol=1e-3, atol=1e-3 * tol * normA)
+    assert np.abs(U.T @ U - np.eye(k)).max() <= 1e-12
+    assert np.abs(V.T @ V - np.eye(k)).max() <= 1e-12
+    return sig, U, V
+
+
+@pytest.mark.parametrize("target", ["largest", "smallest"])
+@pytest.mark.parametrize("force2", [0, 1])
+def test_config1_against_oracle(P, target, force2):
+    A = synth.config1()
+    normA = float(np.linalg.norm(A.toarray(), 2))
+    _say("solve config1", target, "force_stage2", force2)
+    sig, U, V, rn, st = P.svds(A, 5, target, 1e-10, max_basis_size=15, min_restart_size=6,
+                               block_size=1, norm_A=normA, seed=11, force_stage2=force2)
+    ref, Ur, Vr, rr, sr = oracle.svds(A, 5, target, 1e-10, max_basis=15, min_restart=6, block=1,
+                                      norm_A=normA, seed=11, force_stage2=bool(force2))
+    assert st["converged"], st
+    assert st["stage_exit"] == (2 if force2 else 1)
+    s, Ug, Vg = _compare(A, sig, U, V, rn, st, ref, 1e-10, normA)
+    # same singular vectors as the oracle (sign convention applied on both)
+    assert np.all(np.abs(np.sum(Vg * Vr, axis=0) - 1) < 1e-8)
+
+
+@pytest.mark.parametrize("target", ["largest", "smallest"])
+def test_stage2_from_loose_stage1(P, target):
+    A = synth.config1()
+    normA = float(np.linalg.norm(A.toarray(), 2))
+    _say("solve config1 stage2 from stage1_tol 1e-4", target)
+    sig, U, V, rn, st = P.svds(A, 5, target, 1e-10, max_basis_size=15, min_restart_size=6,
+                               norm_A=normA, seed=5, stage1_tol=1e-4)
+    ref, _, _, _, _ = oracle.svds(A, 5, target, 1e-10, max_basis=15, min_restart=6, norm_A=normA,
+                                  seed=5, stage1_tol=1e-4)
+    assert st["converged"] and st["stage_exit"] == 2 and st["iters"][1] > 0, st
+    _compare(A, sig, U, V, rn, st, ref, 1e-10, normA)
+
+
+def test_ill_conditioned_smallest_with_jacobi(P):
+    A = synth.banded_scaled(300, 150, seed=1, log_lo=-6)
+    normA = float(np.linalg.norm(A.toarray(), 2))
+    _say("solve banded_scaled 300x150 kappa~2e6 smallest jacobi")
+    sig, U, V, rn, st = P.svds(A, 3, "smallest", 1e-10, block_size=1, norm_A=normA, seed=7,
+                               precond=P.PC_JACOBI)
+    s = np.sort(np.linalg.svd(A.toarray(), compute_uv=False))[:3]
+    assert st["converged"], st
+    _compare(A, sig, U, V, rn, st, s, 1e-10, normA, rel=1e-9)
+
+
+def test_block_and_wide(P):
+    A = synth.random_uniform_rows(300, 600, 12, seed=21)
+    normA = float(np.linalg.norm(A.toarray(), 2))
+    _say("solve wide 300x600 largest b=2")
+    sig, U, V, rn, st = P.svds(A, 4, "largest", 1e-10, block_size=2, norm_A=normA, seed=3)
+    assert U.shape == (300, 4) and V.shape == (600, 4)
+    s = np.linalg.svd(A.toarray(), compute_uv=False)[:4]
+    _compare(A, sig, U, V, rn, st, s, 1e-10, normA)
+
+
+def test_norm_estimate(P):
+    A = synth.config1()
+    normA = float(np.linalg.norm(A.toarray(), 2))
+    _say("solve config1 with internal norm estimate")
+    sig, U, V, rn, st = P.svds(A, 2, "largest", 1e-10, seed=3)
+    assert abs(st["norm_A_used"] - normA) / normA < 1e-6
+    assert st["converged"]
+
+
+def test_malformed_csr_rejected(P):
+    import torch
+    _say("malformed csr")
+    A = synth.config1(m=50, n=20, nnz_per_row=3)
+    ip, ix, dv = P._lib.to_device(A)
+    ix_bad = ix.clone()
+    ix_bad[5] = 25  # out of range column
+    with pytest.raises(P.SvdsError) as e:
+        P.solve(ip, ix_bad, dv, 50, 20, 2)
+    assert e.value.code == -2
+    ip_bad = ip.clone()
+    ip_bad[-1] += 1
+    with pytest.raises(P.SvdsError) as e:
+        P.solve(ip_bad, ix, dv, 50, 20, 2)
+    assert e.value.code == -2
+    with pytest.raises(P.SvdsError) as e:
+        P.solve(ip, ix, dv, 50, 20, 0)
+    assert e.value.code == -1
+
+
+def test_deterministic_solve(P):
+    A = synth.config1()
+    _say("solve determinism")
+    a = P.svds(A, 3, "smallest", 1e-10, seed=9, norm_A=8.0)
+    b = P.svds(A, 3, "smallest", 1e-10, seed=9, norm_A=8.0)
+    import torch
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[2], b[2])
