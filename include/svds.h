@@ -98,6 +98,8 @@ typedef struct svds_opts {
   int two_sided_cleanup;  /* 1 (default): final two-sided Rayleigh-Ritz     */
                           /* (SVD of U^T A V) of the returned vectors       */
   int print_level;        /* 0 silent .. 5 per-iteration trace on stderr    */
+  int profile;            /* 1: time the sparse products with HIP events on */
+                          /* `stream` and report them in svds_stats         */
 } svds_opts;
 
 /* ---- statistics (host struct, filled by svds_solve) ---------------------- */
@@ -114,6 +116,11 @@ typedef struct svds_stats {
   double seconds[2];      /* wall time per stage                            */
   double setup_seconds;   /* CSR checks, transpose, binning, ||A||          */
   double norm_A_used;     /* ||A|| used by the convergence tests            */
+  /* filled when opts.profile = 1 (zero otherwise): */
+  int64_t spmm_calls;     /* sparse products timed (one call = all row bins) */
+  double spmm_seconds;    /* their summed duration (HIP events)             */
+  double spmm_bytes;      /* their algorithmic bytes: nnz*(8+4) + 4*(rows+1)*/
+                          /* + 8*b*(rows + cols) per call                   */
 } svds_stats;
 
 /* Fill *opts with the defaults above.  Returns SVDS_OK or SVDS_ERR_ARG. */

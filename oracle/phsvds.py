@@ -312,6 +312,19 @@ def _pad(Y, g):
     return P
 
 
+class _TimedBudget(int):
+    """A matrix-vector budget that also runs out after ``seconds`` of wall
+    time (used to take bounded timing samples of the reference)."""
+
+    def __new__(cls, mv, seconds):
+        obj = int.__new__(cls, mv)
+        obj.deadline = time.perf_counter() + seconds
+        return obj
+
+    def __le__(self, other):
+        return time.perf_counter() > self.deadline or int(self) <= other
+
+
 # ---------------------------------------------------------------------------
 # Parameters
 # ---------------------------------------------------------------------------
@@ -663,7 +676,7 @@ def _sign_normalise(U, V):
 # ---------------------------------------------------------------------------
 def svds(A, k, target="largest", tol=1e-10, *, max_basis=None, min_restart=None, block=None,
          prev_retain=None, max_matvecs=None, norm_A=None, seed=0, precond="none",
-         force_stage2=False, cleanup=True, stage1_tol=None, trace=None):
+         force_stage2=False, cleanup=True, stage1_tol=None, trace=None, time_limit=None):
     """k largest or smallest singular triplets of the sparse matrix A with
     eq. (res) residual below tol*||A||.  Returns (sigma, U, V, rnorm, stats);
     U is m x k, V is n x k, both in target order with the largest-magnitude
@@ -686,6 +699,8 @@ def svds(A, k, target="largest", tol=1e-10, *, max_basis=None, min_restart=None,
         raise ValueError("need max_basis >= min_restart + prev_retain + block, and k + block "
                          "within the basis and the smaller dimension")
     budget = max_matvecs if max_matvecs else 2_000_000
+    if time_limit is not None:
+        budget = _TimedBudget(budget, time_limit)
     stats = {"iters": [0, 0], "restarts": [0, 0], "resets": 0, "matvecs": [0, 0],
              "stage_exit": 1, "stage1_status": None, "norm_A_used": None, "nconv": 0,
              "seconds": [0.0, 0.0]}

@@ -31,7 +31,7 @@ class Opts(C.Structure):
                 ("max_matvecs", C.c_int64), ("norm_A", C.c_double), ("stage1_tol", C.c_double),
                 ("seed", C.c_uint64), ("precision", C.c_int), ("precond", C.c_int),
                 ("force_stage2", C.c_int), ("two_sided_cleanup", C.c_int),
-                ("print_level", C.c_int)]
+                ("print_level", C.c_int), ("profile", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -39,7 +39,8 @@ class Stats(C.Structure):
                 ("pad_", C.c_int), ("matvecs", C.c_int64 * 2), ("iters", C.c_int64 * 2),
                 ("restarts", C.c_int64 * 2), ("resets", C.c_int64), ("breakdowns", C.c_int64),
                 ("seconds", C.c_double * 2), ("setup_seconds", C.c_double),
-                ("norm_A_used", C.c_double)]
+                ("norm_A_used", C.c_double), ("spmm_calls", C.c_int64),
+                ("spmm_seconds", C.c_double), ("spmm_bytes", C.c_double)]
 
     def to_dict(self):
         return {"nconv": self.nconv, "stage_exit": self.stage_exit,
@@ -47,7 +48,9 @@ class Stats(C.Structure):
                 "matvecs": list(self.matvecs), "iters": list(self.iters),
                 "restarts": list(self.restarts), "resets": self.resets,
                 "breakdowns": self.breakdowns, "seconds": list(self.seconds),
-                "setup_seconds": self.setup_seconds, "norm_A_used": self.norm_A_used}
+                "setup_seconds": self.setup_seconds, "norm_A_used": self.norm_A_used,
+                "spmm_calls": self.spmm_calls, "spmm_seconds": self.spmm_seconds,
+                "spmm_bytes": self.spmm_bytes}
 
 
 _lib = None

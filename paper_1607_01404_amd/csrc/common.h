@@ -97,6 +97,8 @@ struct Csr32 {
   float* val32 = nullptr;  // nnz, FP32 copy for the mixed-precision stage 1
   int32_t* binrows = nullptr;       // rows, grouped by bin, row order kept
   int64_t bin_off[kNumBins + 1] = {0};
+  int merged_bin = -1;  // >= 0: narrow row-length spread, one launch in this bin's
+                        // lane shape over all rows in natural order
 };
 
 }  // namespace svds

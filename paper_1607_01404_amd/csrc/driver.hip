@@ -137,20 +137,62 @@ class Solver {
   const Csr32& A() const { return M_->A; }
   const Csr32& At() const { return M_->At; }
 
+  // sparse product with optional event timing
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_;
+  double spmm_bytes_ = 0.0;
+  void timed_spmm(const Csr32& Mx, int nb, const double* X, double* Y) {
+    if (!o_.profile) {
+      spmm(Mx, nb, X, Y, s_);
+      return;
+    }
+    hipEvent_t a, b;
+    SVDS_HIP(hipEventCreate(&a));
+    SVDS_HIP(hipEventCreate(&b));
+    SVDS_HIP(hipEventRecord(a, s_));
+    spmm(Mx, nb, X, Y, s_);
+    SVDS_HIP(hipEventRecord(b, s_));
+    ev_.emplace_back(a, b);
+    spmm_bytes_ += (double)Mx.nnz * 12.0 + 4.0 * (double)(Mx.rows + 1) +
+                   8.0 * nb * (double)(Mx.rows + Mx.cols);
+  }
+  void collect_profile(svds_stats* st) {
+    double total = 0.0;
+    for (auto& e : ev_) {
+      float ms = 0.f;
+      SVDS_HIP(hipEventSynchronize(e.second));
+      SVDS_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+      total += ms * 1e-3;
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    st->spmm_calls = (int64_t)ev_.size();
+    st->spmm_seconds = total;
+    st->spmm_bytes = spmm_bytes_;
+    ev_.clear();
+  }
+
   // W block (compact, N x nb) = Op T block (compact)
   void apply_op(const double* Tc, double* Wc, int nb) {
     if (stage_ == 1) {
-      spmm(A(), nb, Tc, Yc_, s_);   // m x nb
-      spmm(At(), nb, Yc_, Wc, s_);  // n x nb
+      timed_spmm(A(), nb, Tc, Yc_);   // m x nb
+      timed_spmm(At(), nb, Yc_, Wc);  // n x nb
     } else {
-      spmm(At(), nb, Tc + n_ * nb, Wc, s_);  // v-half: A^T x_u
-      spmm(A(), nb, Tc, Wc + n_ * nb, s_);   // u-half: A x_v
+      timed_spmm(At(), nb, Tc + n_ * nb, Wc);  // v-half: A^T x_u
+      timed_spmm(A(), nb, Tc, Wc + n_ * nb);   // u-half: A x_v
     }
     mv_ += 2 * nb;
   }
 
   // ---- orthogonalisation: CGS twice against segs, Cholesky QR twice ----------
   int ortho_once(double* T, int64_t ldt, int nb, const Seg* segs, int nseg, double* compact) {
+    ortho_enqueue(T, ldt, nb, segs, nseg, compact);
+    SVDS_HIP(hipMemcpyAsync(hbad_, &d_->bad, sizeof(int), hipMemcpyDeviceToHost, s_));
+    SVDS_HIP(hipStreamSynchronize(s_));
+    return *hbad_;
+  }
+
+  // CGS twice + CholQR twice, enqueued only; d_->bad records dependent columns
+  void ortho_enqueue(double* T, int64_t ldt, int nb, const Seg* segs, int nseg, double* compact) {
     int total = 0;
     for (int i = 0; i < nseg; ++i) total += segs[i].ncols;
     SVDS_HIP(hipMemsetAsync(&d_->bad, 0, sizeof(int), s_));
@@ -175,9 +217,25 @@ class Solver {
     tsgemm_tn(&st, 1, N_, T, ldt, nb, partial_, d_->G, s_);
     small_chol(d_, nb, 2, total, s_);
     ts_scale(T, ldt, N_, nb, d_->R2inv, compact, s_);
-    SVDS_HIP(hipMemcpyAsync(hbad_, &d_->bad, sizeof(int), hipMemcpyDeviceToHost, s_));
-    SVDS_HIP(hipStreamSynchronize(s_));
-    return *hbad_;
+  }
+
+  // repair after the control step reported a breakdown of the last block:
+  // roll the block back, give its dependent columns fresh random numbers and
+  // redo it synchronously
+  void repair_block(int nb, int bad, const Seg* segs, int nseg) {
+    gc_ -= nb;
+    ++breakdowns_;
+    double* T = V_ + gc_ * ld_;
+    const uint64_t stream = kStreamBreak + (uint64_t)rand_count_++;
+    int i = 0;
+    for (int j = 0; j < nb; ++j)
+      if (bad & (1 << j)) fill_random(T + j * ld_, ld_, N_, 1, o_.seed, stream, i++, s_);
+    Seg sg[3];
+    for (int q = 0; q < nseg; ++q) sg[q] = segs[q];
+    sg[nseg - 1].ncols = gc_;  // the basis segment, rolled back
+    ortho(T, ld_, nb, sg, nseg, Tc_);
+    append(nb);
+    extract_stage();
   }
 
   // with breakdown repair: dependent columns get fresh counter-based vectors
@@ -290,9 +348,9 @@ class Solver {
 
   void trace(const char* what, int it, const Ctl& c, int nc) {
     if (o_.print_level < 3) return;
-    std::fprintf(stderr, "[svds] stage %d %s it %d g %d act %d nb %d rs %d nr %d res0 %.3e maxres %.3e val0 %.12e mv %lld\n",
-                 stage_, what, it, gc_, c.action, c.nblock, c.restart, c.nr, nc > 0 ? c.res[0] : 0.0,
-                 c.maxres, nc > 0 ? c.val[0] : 0.0, (long long)mv_);
+    std::fprintf(stderr, "[svds] stage %d %s it %d g %d act %d nb %d rs %d nr %d sweeps %d res0 %.3e maxres %.3e val0 %.12e mv %lld\n",
+                 stage_, what, it, gc_, c.action, c.nblock, c.restart, c.nr, c.eig_sweeps,
+                 nc > 0 ? c.res[0] : 0.0, c.maxres, nc > 0 ? c.val[0] : 0.0, (long long)mv_);
   }
 
   // preconditioner for the stage-2 block: [K A^T r_u; A K r_v] (pseudo-inverse
@@ -418,6 +476,7 @@ int Solver::stage1(double* V1, double* U1, double* sig, double* rn, double* taus
   int64_t iters = 0, restarts = 0, resets = 0;
   int since_reset = 0, floor_resets = 0;
   int status = 2;
+  int last_nb = 0;
   for (;;) {
     const int nc = std::min(gc_, k_ + b_);
     residual(nc, N_);
@@ -438,6 +497,11 @@ int Solver::stage1(double* V1, double* U1, double* sig, double* rn, double* taus
     P.eps = kEps;
     Ctl c = control(P);
     trace("s1", (int)iters, c, nc);
+    if (c.action == kBreakdown) {
+      Seg sv{V_, gc_, ld_};
+      repair_block(last_nb, c.bad, &sv, 1);
+      continue;
+    }
     if (c.action == kExitConverged || c.action == kExitFloor || c.action == kExitBudget) {
       status = c.action == kExitConverged ? 0 : (c.action == kExitFloor ? 1 : 2);
       normA_ = std::max(normA_, std::sqrt(c.normop));
@@ -466,8 +530,9 @@ int Solver::stage1(double* V1, double* U1, double* sig, double* rn, double* taus
                      ld_, s_);
     }
     Seg sv{V_, gc_, ld_};
-    ortho(T, ld_, nb, &sv, 1, Tc_);
+    ortho_enqueue(T, ld_, nb, &sv, 1, Tc_);
     append(nb);
+    last_nb = nb;
     extract_stage();
     ++iters;
   }
@@ -539,6 +604,7 @@ int Solver::stage2(const double* taus_h, double* V1, double* U1, double* sig, in
   int64_t iters = 0, restarts = 0, resets = 0;
   int since_reset = 0;
   int exit_action = kExitBudget;
+  int last_nb = 0;
   for (;;) {
     const int nc = std::min(gc_, b_);
     residual(nc, n_);
@@ -560,6 +626,11 @@ int Solver::stage2(const double* taus_h, double* V1, double* U1, double* sig, in
     P.eps = kEps;
     Ctl c = control(P);
     trace("s2", (int)iters, c, nc);
+    if (c.action == kBreakdown) {
+      Seg segs[2] = {Seg{X_, nlock_, ld_}, Seg{V_, gc_, ld_}};
+      repair_block(last_nb, c.bad, segs, 2);
+      continue;
+    }
     if (c.nlockable > 0) {
       // x = V y for the converged prefix -> locked vectors
       ts_gemm_nn(V_, ld_, gc_, N_, d_->Y, kLd, c.nlockable, X_ + nlock_ * ld_, ld_, s_);
@@ -596,8 +667,13 @@ int Solver::stage2(const double* taus_h, double* V1, double* U1, double* sig, in
     double* T = V_ + gc_ * ld_;
     precond_stage2(T, nb);
     Seg segs[2] = {Seg{X_, nlock_, ld_}, Seg{V_, gc_, ld_}};
-    ortho(T, ld_, nb, segs, 2, Tc_);
+    if (refined_) {
+      ortho(T, ld_, nb, segs, 2, Tc_);  // the refined factor update needs a valid block
+    } else {
+      ortho_enqueue(T, ld_, nb, segs, 2, Tc_);
+    }
     append(nb);
+    last_nb = nb;
     extract_stage();
     ++iters;
   }
@@ -708,7 +784,7 @@ int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, d
   Yc_ = buf_.get<double>((size_t)ld_ * kMaxBlock);
   Wc_ = buf_.get<double>((size_t)ld_ * kMaxBlock);
   Zc_ = buf_.get<double>((size_t)ld_ * kMaxBlock);
-  partial_ = buf_.get<double>((size_t)1024 * 264 * kMaxBlock + 1024);
+  partial_ = buf_.get<double>((size_t)2048 * 264 * kMaxBlock + 4096);
   d_ = buf_.get<Small>(1);
   vec_ = buf_.get<double>(16 * kLd * kLd);
   double* V1 = buf_.get<double>((size_t)ld_ * kKmax);
@@ -772,6 +848,7 @@ int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, d
   }
   st->nconv = good;
   st->norm_A_used = normA_;
+  collect_profile(st);
   st->breakdowns = breakdowns_;
   if (!finite && good == 0) return SVDS_ERR_BREAKDOWN;
   return good >= k_ ? SVDS_OK : SVDS_NOT_CONVERGED;

@@ -11,9 +11,11 @@ namespace svds {
 constexpr int kThreads = 256;
 constexpr int kMaxSegCols = 256;  // columns of [X_lock V T] in one projection
 
+// workgroups of the streaming kernels: about one 256-row chunk per workgroup,
+// at most 2048 (8 per CU on 256 CUs), whole rounds of the 8 XCDs
 int reduce_blocks(int64_t N) {
-  int64_t nb = (N + 8 * kThreads - 1) / (8 * kThreads);
-  nb = std::max<int64_t>(1, std::min<int64_t>(nb, 1024));
+  int64_t nb = (N + kThreads - 1) / kThreads;
+  nb = std::max<int64_t>(1, std::min<int64_t>(nb, 2048));
   if (nb >= 64) nb = (nb / 8) * 8;
   return (int)nb;
 }
@@ -54,72 +56,87 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NA], double* sh
 
 // ---------------------------------------------------------------------------
 // C = [segs]^T T  (partials per workgroup)
+// A workgroup walks 256-row chunks; the chunk of T (256 x B) is staged in LDS
+// once and each of the 4 wavefronts accumulates its own set of basis columns
+// (w, w+4, ...), each lane covering 4 rows.  T is read once per chunk and the
+// basis columns once; the per-wave accumulators are reduced at the end.
 // ---------------------------------------------------------------------------
-constexpr int kJC = 8;
+constexpr int kCPW = 8;  // basis columns per wavefront (32 per workgroup column)
 
 template <int B>
 __global__ __launch_bounds__(kThreads) void k_tsgemm_tn(Segs3 segs, int total, int64_t N,
                                                         const double* __restrict__ T,
                                                         int64_t ldt,
                                                         double* __restrict__ partial) {
-  __shared__ double sh[4 * kJC * B];
-  const int c0 = blockIdx.y * kJC;
-  const int ncol = min(kJC, total - c0);
-  const double* qp[kJC];
+  __shared__ double ts[kThreads * B];
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int c0 = blockIdx.y * (4 * kCPW);
+  const double* qp[kCPW];
+  bool ok[kCPW];
 #pragma unroll
-  for (int jj = 0; jj < kJC; ++jj) qp[jj] = seg_col(segs, min(c0 + jj, total - 1));
-  double acc[kJC * B];
+  for (int jj = 0; jj < kCPW; ++jj) {
+    const int col = c0 + w + 4 * jj;
+    ok[jj] = col < total;
+    qp[jj] = seg_col(segs, min(col, total - 1));
+  }
+  double acc[kCPW * B];
 #pragma unroll
-  for (int a = 0; a < kJC * B; ++a) acc[a] = 0.0;
+  for (int a = 0; a < kCPW * B; ++a) acc[a] = 0.0;
   const int bid = xcd_block(blockIdx.x, gridDim.x);
-  for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < N;
-       i += (int64_t)gridDim.x * kThreads) {
-    double t[B];
+  for (int64_t base = (int64_t)bid * kThreads; base < N; base += (int64_t)gridDim.x * kThreads) {
+    __syncthreads();
+    {
+      const int64_t row = base + threadIdx.x;
 #pragma unroll
-    for (int c = 0; c < B; ++c) t[c] = T[i + c * ldt];
+      for (int c = 0; c < B; ++c) ts[threadIdx.x * B + c] = (row < N) ? T[row + c * ldt] : 0.0;
+    }
+    __syncthreads();
 #pragma unroll
-    for (int jj = 0; jj < kJC; ++jj) {
-      if (jj < ncol) {
-        const double q = qp[jj][i];
+    for (int i = 0; i < kThreads / kWave; ++i) {
+      const int r = lane + kWave * i;
+      const int64_t row = base + r;
+      if (row < N) {
+        double tv[B];
 #pragma unroll
-        for (int c = 0; c < B; ++c) acc[jj * B + c] = fma(q, t[c], acc[jj * B + c]);
+        for (int c = 0; c < B; ++c) tv[c] = ts[r * B + c];
+#pragma unroll
+        for (int jj = 0; jj < kCPW; ++jj) {
+          if (ok[jj]) {
+            const double q = qp[jj][row];
+#pragma unroll
+            for (int c = 0; c < B; ++c) acc[jj * B + c] = fma(q, tv[c], acc[jj * B + c]);
+          }
+        }
       }
     }
   }
-  // partial layout: [block][c * total + col]
-  double* out = partial + (int64_t)blockIdx.x * total * B;
-  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  // partial layout: [c * total + col][block]
+  const int nblk = gridDim.x;
 #pragma unroll
-  for (int a = 0; a < kJC * B; ++a) {
-    double v = wave_sum(acc[a]);
-    if (lane == 0) sh[w * kJC * B + a] = v;
-  }
-  __syncthreads();
-  for (int a = threadIdx.x; a < kJC * B; a += kThreads) {
-    int jj = a / B, c = a % B;
-    if (jj < ncol) {
-      double v = ((sh[a] + sh[kJC * B + a]) + sh[2 * kJC * B + a]) + sh[3 * kJC * B + a];
-      out[(int64_t)c * total + c0 + jj] = v;
+  for (int jj = 0; jj < kCPW; ++jj) {
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      const double v = wave_sum(acc[jj * B + c]);
+      if (lane == 0 && ok[jj])
+        partial[((int64_t)c * total + c0 + w + 4 * jj) * nblk + blockIdx.x] = v;
     }
   }
 }
 
-__global__ void k_reduce_partials(const double* __restrict__ P, int nblk, int nout,
-                                  double* __restrict__ out) {
-  __shared__ double sh[4][64];
-  const int o = blockIdx.x * 64 + (threadIdx.x % 64);
-  const int part = threadIdx.x / 64;
+// one wavefront per output: out[o] = sum over blocks of P[o * nblk + block]
+__global__ __launch_bounds__(64) void k_reduce_partials(const double* __restrict__ P, int nblk,
+                                                        double* __restrict__ out) {
+  const int o = blockIdx.x;
+  const double* p = P + (int64_t)o * nblk;
   double s = 0.0;
-  if (o < nout)
-    for (int b = part; b < nblk; b += 4) s += P[(int64_t)b * nout + o];
-  sh[part][threadIdx.x % 64] = s;
-  __syncthreads();
-  if (part == 0 && o < nout)
-    out[o] = ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) + sh[3][threadIdx.x];
+  for (int b = threadIdx.x; b < nblk; b += 64) s += p[b];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) out[o] = s;
 }
 
 static void reduce_partials(const double* P, int nblk, int nout, double* out, hipStream_t s) {
-  k_reduce_partials<<<(nout + 63) / 64, 256, 0, s>>>(P, nblk, nout, out);
+  if (nout <= 0) return;
+  k_reduce_partials<<<nout, 64, 0, s>>>(P, nblk, out);
   SVDS_LAUNCH_CHECK();
 }
 
@@ -143,8 +160,9 @@ static Segs3 make_segs(const Seg* segs, int nseg, int& total) {
 template <int B>
 static void tsgemm_b(const Segs3& sg, int total, int64_t N, const double* T, int64_t ldt,
                      double* partial, double* C, hipStream_t s) {
-  int nb = reduce_blocks(N);
-  dim3 grid(nb, (total + kJC - 1) / kJC);
+  // several 256-row chunks per workgroup amortise the final wave reductions
+  int nb = std::min(reduce_blocks(N), 512);
+  dim3 grid(nb, (total + 4 * kCPW - 1) / (4 * kCPW));
   k_tsgemm_tn<B><<<grid, kThreads, 0, s>>>(sg, total, N, T, ldt, partial);
   SVDS_LAUNCH_CHECK();
   reduce_partials(partial, nb, total * B, C, s);
@@ -204,7 +222,7 @@ void ts_update(const Seg* segs, int nseg, int64_t N, const double* C, int ldc, d
   Segs3 sg = make_segs(segs, nseg, total);
   if (total == 0) return;
   if (total > kMaxSegCols) throw Error(SVDS_ERR_ARG, "update too wide");
-  int nb = reduce_blocks(N) * 2;
+  int nb = reduce_blocks(N);
   switch (b) {
 #define CASE(BB) \
   case BB: k_ts_update<BB><<<nb, kThreads, 0, s>>>(sg, total, N, C, ldc, T, ldt); break;
@@ -218,7 +236,7 @@ void ts_update(const Seg* segs, int nseg, int64_t N, const double* C, int ldc, d
 // ---------------------------------------------------------------------------
 // Out = Q Y   (restart V <- V Y, W <- W Y, Q <- Q Q~, locking x = V y)
 // ---------------------------------------------------------------------------
-constexpr int kOC = 16;
+constexpr int kOC = 24;
 
 __global__ __launch_bounds__(kThreads) void k_gemm_nn(const double* __restrict__ Q, int64_t ldq,
                                                       int nq, int64_t N,
@@ -254,7 +272,7 @@ void ts_gemm_nn(const double* Q, int64_t ldq, int nq, int64_t N, const double* Y
                 int nout, double* Out, int64_t ldo, hipStream_t s) {
   if (nout <= 0 || N == 0) return;
   if (nq > kMaxBasis) throw Error(SVDS_ERR_ARG, "gemm: inner dimension too large");
-  dim3 grid(reduce_blocks(N) * 2, (nout + kOC - 1) / kOC);
+  dim3 grid(reduce_blocks(N), (nout + kOC - 1) / kOC);
   k_gemm_nn<<<grid, kThreads, 0, s>>>(Q, ldq, nq, N, Y, ldy, nout, Out, ldo);
   SVDS_LAUNCH_CHECK();
 }
@@ -293,7 +311,7 @@ __global__ __launch_bounds__(kThreads) void k_ts_scale(double* __restrict__ T, i
 
 void ts_scale(double* T, int64_t ldt, int64_t N, int b, const double* Rinv, double* compact,
               hipStream_t s) {
-  int nb = reduce_blocks(N) * 2;
+  int nb = reduce_blocks(N);
   switch (b) {
 #define CASE(BB) \
   case BB: k_ts_scale<BB><<<nb, kThreads, 0, s>>>(T, ldt, N, Rinv, compact); break;
@@ -310,84 +328,98 @@ void ts_scale(double* T, int64_t ldt, int64_t N, int b, const double* Rinv, doub
 // with lo = rows < nsplit (the v-half on B), hi = the rest (the u-half).
 // One pass over V and W (the "special kernels" of Section 3.3).
 // ---------------------------------------------------------------------------
-constexpr int kNCC = 8;  // candidates per workgroup column
-
+template <int NCC, int NS>
 __global__ __launch_bounds__(kThreads) void k_residual(
     const double* __restrict__ V, const double* __restrict__ W, int64_t ld, int64_t N,
     int64_t nsplit, int g, const double* __restrict__ Y, int64_t ldy,
     const double* __restrict__ theta, int nc, double* __restrict__ R, int64_t ldr,
     double* __restrict__ partial) {
-  __shared__ double ys[kMaxBasis * kNCC];
-  __shared__ double th[kNCC];
-  __shared__ double sh[4 * 6 * kNCC];
-  const int c0 = blockIdx.y * kNCC;
-  const int ncc = min(kNCC, nc - c0);
-  for (int a = threadIdx.x; a < g * kNCC; a += kThreads) {
-    int j = a / kNCC, c = a % kNCC;
+  __shared__ double ys[kMaxBasis * NCC];
+  __shared__ double th[NCC];
+  __shared__ double sh[4 * NS * NCC];
+  const int c0 = blockIdx.y * NCC;
+  const int ncc = min(NCC, nc - c0);
+  for (int a = threadIdx.x; a < g * NCC; a += kThreads) {
+    int j = a / NCC, c = a % NCC;
     ys[a] = (c < ncc) ? Y[(int64_t)(c0 + c) * ldy + j] : 0.0;
   }
-  if (threadIdx.x < kNCC) th[threadIdx.x] = (threadIdx.x < ncc) ? theta[c0 + threadIdx.x] : 0.0;
+  if (threadIdx.x < NCC) th[threadIdx.x] = (threadIdx.x < ncc) ? theta[c0 + threadIdx.x] : 0.0;
   __syncthreads();
-  double acc[6 * kNCC];
+  double acc[NS * NCC];
 #pragma unroll
-  for (int a = 0; a < 6 * kNCC; ++a) acc[a] = 0.0;
+  for (int a = 0; a < NS * NCC; ++a) acc[a] = 0.0;
   const int bid = xcd_block(blockIdx.x, gridDim.x);
   for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * kThreads) {
-    double x[kNCC], w[kNCC];
+    double x[NCC], w[NCC];
 #pragma unroll
-    for (int c = 0; c < kNCC; ++c) x[c] = w[c] = 0.0;
+    for (int c = 0; c < NCC; ++c) x[c] = w[c] = 0.0;
     for (int j = 0; j < g; ++j) {
       const double v = V[i + (int64_t)j * ld];
       const double ww = W[i + (int64_t)j * ld];
 #pragma unroll
-      for (int c = 0; c < kNCC; ++c) {
-        x[c] = fma(v, ys[j * kNCC + c], x[c]);
-        w[c] = fma(ww, ys[j * kNCC + c], w[c]);
+      for (int c = 0; c < NCC; ++c) {
+        x[c] = fma(v, ys[j * NCC + c], x[c]);
+        w[c] = fma(ww, ys[j * NCC + c], w[c]);
       }
     }
-    const int off = (i < nsplit) ? 0 : 3;
+    const bool lo = i < nsplit;
 #pragma unroll
-    for (int c = 0; c < kNCC; ++c) {
+    for (int c = 0; c < NCC; ++c) {
       const double r = fma(-th[c], x[c], w[c]);
       if (c < ncc) R[i + (int64_t)(c0 + c) * ldr] = r;
-      // branch-free selection of the half
-      double* a6 = acc + 6 * c;
-      const double rr = r * r, xr = x[c] * r, xx = x[c] * x[c];
-      if (off == 0) {
-        a6[0] += rr; a6[1] += xr; a6[2] += xx;
+      if constexpr (NS == 1) {
+        acc[c] = fma(r, r, acc[c]);
       } else {
-        a6[3] += rr; a6[4] += xr; a6[5] += xx;
+        double* a6 = acc + 6 * c;
+        const double rr = r * r, xr = x[c] * r, xx = x[c] * x[c];
+        if (lo) {
+          a6[0] += rr; a6[1] += xr; a6[2] += xx;
+        } else {
+          a6[3] += rr; a6[4] += xr; a6[5] += xx;
+        }
       }
     }
   }
-  // partial layout: [block][q * nc + cand]
+  // partial layout: [q * nc + cand][block]
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
 #pragma unroll
-  for (int a = 0; a < 6 * kNCC; ++a) {
+  for (int a = 0; a < NS * NCC; ++a) {
     double v = wave_sum(acc[a]);
-    if (lane == 0) sh[w * 6 * kNCC + a] = v;
+    if (lane == 0) sh[w * NS * NCC + a] = v;
   }
   __syncthreads();
-  for (int a = threadIdx.x; a < 6 * kNCC; a += kThreads) {
-    const int c = a / 6, q = a % 6;
+  for (int a = threadIdx.x; a < NS * NCC; a += kThreads) {
+    const int c = a / NS, q = a % NS;
     if (c < ncc) {
-      double v = ((sh[a] + sh[6 * kNCC + a]) + sh[12 * kNCC + a]) + sh[18 * kNCC + a];
-      partial[(int64_t)blockIdx.x * 6 * nc + q * nc + c0 + c] = v;
+      double v = ((sh[a] + sh[NS * NCC + a]) + sh[2 * NS * NCC + a]) + sh[3 * NS * NCC + a];
+      partial[((int64_t)q * nc + c0 + c) * gridDim.x + blockIdx.x] = v;
     }
   }
 }
 
+// nsplit >= N: one sum per candidate (||r||^2 in sums[c]); otherwise the six
+// sums of the two halves in sums[q*nc + c]
 void ts_residual(const double* V, const double* W, int64_t ld, int64_t N, int64_t nsplit, int g,
                  const double* Y, int64_t ldy, const double* theta, int nc, double* R,
                  int64_t ldr, double* partial, double* sums, hipStream_t s) {
   if (g > kMaxBasis) throw Error(SVDS_ERR_ARG, "residual: basis too large");
   int nb = reduce_blocks(N);
-  dim3 grid(nb, (nc + kNCC - 1) / kNCC);
-  k_residual<<<grid, kThreads, 0, s>>>(V, W, ld, N, nsplit, g, Y, ldy, theta, nc, R, ldr,
-                                        partial);
-  SVDS_LAUNCH_CHECK();
-  reduce_partials(partial, nb, 6 * nc, sums, s);
+  if (nsplit >= N) {
+    constexpr int NCC = 16;
+    dim3 grid(nb, (nc + NCC - 1) / NCC);
+    k_residual<NCC, 1><<<grid, kThreads, 0, s>>>(V, W, ld, N, nsplit, g, Y, ldy, theta, nc, R,
+                                                  ldr, partial);
+    SVDS_LAUNCH_CHECK();
+    reduce_partials(partial, nb, nc, sums, s);
+  } else {
+    constexpr int NCC = 8;
+    dim3 grid(nb, (nc + NCC - 1) / NCC);
+    k_residual<NCC, 6><<<grid, kThreads, 0, s>>>(V, W, ld, N, nsplit, g, Y, ldy, theta, nc, R,
+                                                  ldr, partial);
+    SVDS_LAUNCH_CHECK();
+    reduce_partials(partial, nb, 6 * nc, sums, s);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -505,7 +537,7 @@ __global__ __launch_bounds__(kThreads) void k_colres(const double* __restrict__ 
   acc = wave_sum(acc);
   if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * k + c] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+  if (threadIdx.x == 0) partial[(int64_t)c * gridDim.x + blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }
 
 void col_residual2(const double* A, int64_t lda, const double* B, int64_t ldb, const double* sc,

@@ -279,6 +279,21 @@ void build_bins(Csr32& A, hipStream_t s) {
   SVDS_HIP(hipStreamSynchronize(s));
   for (int bn = 0; bn < kNumBins; ++bn) A.bin_off[bn] = h[bn];
   A.bin_off[kNumBins] = rows;
+  // narrow spread (at most three adjacent lane shapes, no workgroup rows):
+  // one launch over all rows in natural order, in the lane shape of the mean
+  int lo = -1, hi = -1;
+  for (int bn = 0; bn < kNumBins; ++bn)
+    if (A.bin_off[bn + 1] > A.bin_off[bn]) {
+      if (lo < 0) lo = bn;
+      hi = bn;
+    }
+  A.merged_bin = -1;
+  if (lo >= 0 && hi - lo <= 2 && hi < kNumBins - 1 && rows > 0) {
+    const double mean = (double)A.nnz / (double)rows;
+    int mb = 0;
+    while (mb < kNumBins - 2 && mean > 4.0 * (double)(1 << mb)) ++mb;
+    A.merged_bin = std::max(lo, std::min(mb, hi));
+  }
   SVDS_HIP(hipFreeAsync(counts, s));
   SVDS_HIP(hipFreeAsync(offs, s));
 }

@@ -24,80 +24,131 @@ __device__ __forceinline__ void rr_pair(int np, int r, int k, int& p, int& q) {
 }
 
 // ---------------------------------------------------------------------------
-// symmetric eigenproblem by cyclic Jacobi; A (n x n, ld kLs) in LDS is
-// destroyed, Z receives the eigenvectors (unsorted), d the eigenvalues.
+// symmetric eigenproblem by cyclic Jacobi with a round-robin parallel order.
+// A (n x n, ld kLs) in LDS is destroyed; Z must hold an orthonormal matrix W
+// on entry (identity, or the previous eigenvectors when H was expressed in a
+// basis close to its eigenbasis) and receives W J, the eigenvectors; d the
+// eigenvalues (unsorted).  Each round applies the disjoint rotations of all
+// pairs as independent 2 x 2 block updates of A (one barrier) and the column
+// rotations of Z.
 // ---------------------------------------------------------------------------
-__device__ void jacobi_eig_lds(int n, double* A, double* Z, double* d, double* cs, double* sn,
-                               int* flag) {
+__device__ void make_pairs(int np, unsigned char* pp, unsigned char* pq) {
+  for (int a = threadIdx.x; a < (np - 1) * (np / 2); a += kT) {
+    const int r = a / (np / 2), k = a % (np / 2);
+    int p, q;
+    rr_pair(np, r, k, p, q);
+    pp[a] = (unsigned char)p;
+    pq[a] = (unsigned char)q;
+  }
+}
+
+__device__ int jacobi_eig_lds(int n, double* A, double* Z, double* d, double* cs, double* sn,
+                              int* flag, double thr_floor = 0.0) {
+  __shared__ double tt_[kLd / 2 + 1], apq_[kLd / 2 + 1];
+  __shared__ int zero_[kLd / 2 + 1];
+  __shared__ double red_[kT / kWave];
+  __shared__ unsigned char pp[(kLd - 1) * (kLd / 2)], pq[(kLd - 1) * (kLd / 2)];
   const int t = threadIdx.x;
   const int np = n + (n & 1);
-  for (int a = t; a < np * kLs; a += kT) Z[a] = 0.0;
-  __syncthreads();
-  if (n & 1) {  // padding index with a zero row and column
+  const int npair = np / 2;
+  if (n & 1) {  // padding index: zero row and column of A, unit vector in Z
     for (int j = t; j < np; j += kT) {
       A[n * kLs + j] = 0.0;
       A[j * kLs + n] = 0.0;
+      Z[n * kLs + j] = (j == n) ? 1.0 : 0.0;
+      Z[j * kLs + n] = (j == n) ? 1.0 : 0.0;
     }
   }
-  for (int j = t; j < np; j += kT) Z[j * kLs + j] = 1.0;
-  __shared__ double frob2;
-  if (t == 0) {
-    double f = 0.0;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) f += A[i * kLs + j] * A[i * kLs + j];
-    frob2 = f;
+  make_pairs(np, pp, pq);
+  double f = 0.0;
+  for (int a = t; a < n * n; a += kT) {
+    const double v = A[(a / n) * kLs + (a % n)];
+    f += v * v;
   }
+  f = wave_sum(f);
+  if (t % kWave == 0) red_[t / kWave] = f;
   __syncthreads();
-  const double thr = 0.1 * kEps * sqrt(frob2) / (double)max(n, 1);
-  for (int sweep = 0; sweep < 50 && np > 1; ++sweep) {
+  const double frob = sqrt(((red_[0] + red_[1]) + red_[2]) + red_[3]);
+  // off-diagonal entries below eps*||A||/4 are dropped: they move eigenvalues
+  // and residuals of the Ritz pairs by less than the rounding level of the
+  // projected matrix itself
+  const double thr = fmax(0.25 * kEps * frob, thr_floor);
+  __shared__ int round_rot;
+  int sweep = 0;
+  for (; sweep < 60 && np > 1; ++sweep) {
     if (t == 0) *flag = 0;
     __syncthreads();
     for (int r = 0; r < np - 1; ++r) {
-      if (t < np / 2) {
-        int p, q;
-        rr_pair(np, r, t, p, q);
+      const unsigned char* P = pp + r * npair;
+      const unsigned char* Q = pq + r * npair;
+      if (t == 0) round_rot = 0;
+      __syncthreads();
+      if (t < npair) {
+        const int p = P[t], q = Q[t];
         const double apq = A[p * kLs + q];
-        double c = 1.0, s = 0.0;
+        double c = 1.0, s = 0.0, tt = 0.0;
+        const double app = A[p * kLs + p], aqq = A[q * kLs + q];
         if (fabs(apq) > thr) {
-          const double app = A[p * kLs + p], aqq = A[q * kLs + q];
           const double th = (aqq - app) / (2.0 * apq);
-          const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
           c = 1.0 / sqrt(tt * tt + 1.0);
           s = tt * c;
           *flag = 1;
+          round_rot = 1;
         }
         cs[t] = c;
         sn[t] = s;
+        tt_[t] = tt;
+        apq_[t] = apq;
+        zero_[t] = (s == 0.0 && apq != 0.0) ? 1 : 0;
       }
       __syncthreads();
-      // rows p, q <- J^T rows
-      for (int a = t; a < (np / 2) * np; a += kT) {
-        const int k = a / np, j = a % np;
-        int p, q;
-        rr_pair(np, r, k, p, q);
-        const double c = cs[k], s = sn[k];
-        if (s != 0.0) {
-          const double x = A[p * kLs + j], y = A[q * kLs + j];
-          A[p * kLs + j] = c * x - s * y;
-          A[q * kLs + j] = s * x + c * y;
+      if (!round_rot) {  // only negligible entries: zero them and move on
+        if (t < npair && zero_[t]) {
+          A[P[t] * kLs + Q[t]] = 0.0;
+          A[Q[t] * kLs + P[t]] = 0.0;
         }
+        continue;
       }
-      __syncthreads();
-      // columns p, q <- columns J; eigenvectors likewise
-      for (int a = t; a < (np / 2) * np; a += kT) {
-        const int k = a / np, j = a % np;
-        int p, q;
-        rr_pair(np, r, k, p, q);
-        const double c = cs[k], s = sn[k];
-        if (s != 0.0) {
-          double x = A[j * kLs + p], y = A[j * kLs + q];
-          A[j * kLs + p] = c * x - s * y;
-          A[j * kLs + q] = s * x + c * y;
-          x = Z[j * kLs + p];
-          y = Z[j * kLs + q];
-          Z[j * kLs + p] = c * x - s * y;
-          Z[j * kLs + q] = s * x + c * y;
+      // A <- J^T A J as independent 2 x 2 block updates
+      for (int K = t >> 5; K < npair; K += kT / 32) {
+        const int L = t & 31;
+        if (L >= npair) continue;
+        const int pK = P[K], qK = Q[K];
+        if (K == L) {
+          if (sn[K] != 0.0) {
+            A[pK * kLs + pK] -= tt_[K] * apq_[K];
+            A[qK * kLs + qK] += tt_[K] * apq_[K];
+            A[pK * kLs + qK] = 0.0;
+            A[qK * kLs + pK] = 0.0;
+          } else if (zero_[K]) {
+            A[pK * kLs + qK] = 0.0;
+            A[qK * kLs + pK] = 0.0;
+          }
+          continue;
         }
+        const double cK = cs[K], sK = sn[K], cL = cs[L], sL = sn[L];
+        if (sK == 0.0 && sL == 0.0) continue;
+        const int pL = P[L], qL = Q[L];
+        const double a11 = A[pK * kLs + pL], a12 = A[pK * kLs + qL];
+        const double a21 = A[qK * kLs + pL], a22 = A[qK * kLs + qL];
+        const double b11 = cK * a11 - sK * a21, b12 = cK * a12 - sK * a22;
+        const double b21 = sK * a11 + cK * a21, b22 = sK * a12 + cK * a22;
+        A[pK * kLs + pL] = cL * b11 - sL * b12;
+        A[pK * kLs + qL] = sL * b11 + cL * b12;
+        A[qK * kLs + pL] = cL * b21 - sL * b22;
+        A[qK * kLs + qL] = sL * b21 + cL * b22;
+      }
+      // Z <- Z J
+      for (int L = t >> 6; L < npair; L += kT / kWave) {
+        const int i = t & 63;
+        const double sL = sn[L];
+        if (i >= np || sL == 0.0) continue;
+        const double cL = cs[L];
+        const int pL = P[L], qL = Q[L];
+        const double x = Z[i * kLs + pL], y = Z[i * kLs + qL];
+        Z[i * kLs + pL] = cL * x - sL * y;
+        Z[i * kLs + qL] = sL * x + cL * y;
       }
       __syncthreads();
     }
@@ -106,6 +157,7 @@ __device__ void jacobi_eig_lds(int n, double* A, double* Z, double* d, double* c
   }
   for (int i = t; i < n; i += kT) d[i] = A[i * kLs + i];
   __syncthreads();
+  return sweep + 1;
 }
 
 // sort eigenpairs: theta[rank] = d[i], Y[:, rank] = Z[0:n, i]
@@ -135,6 +187,7 @@ __global__ __launch_bounds__(kT) void k_eig(int g, const double* H, int ldh, int
   for (int a = threadIdx.x; a < g * g; a += kT) {
     const int i = a % g, j = a / g;
     A[i * kLs + j] = 0.5 * (H[(int64_t)j * ldh + i] + H[(int64_t)i * ldh + j]);
+    Z[i * kLs + j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
   jacobi_eig_lds(g, A, Z, d, cs, sn, &flag);
@@ -163,6 +216,9 @@ __device__ void jacobi_svd_lds(int n, double* A, double* Vm, double* cs, double*
   __syncthreads();
   const int npair = np / 2;
   constexpr int G = 8;  // lanes per pair
+  __shared__ unsigned char pp[(kLd - 1) * (kLd / 2)], pq[(kLd - 1) * (kLd / 2)];
+  make_pairs(np, pp, pq);
+  __syncthreads();
   for (int sweep = 0; sweep < 80 && np > 1; ++sweep) {
     if (t == 0) *flag = 0;
     __syncthreads();
@@ -171,7 +227,8 @@ __device__ void jacobi_svd_lds(int n, double* A, double* Vm, double* cs, double*
       double al = 0.0, be = 0.0, ga = 0.0;
       int p = 0, q = 0;
       if (k < npair) {
-        rr_pair(np, r, k, p, q);
+        p = pp[r * npair + k];
+        q = pq[r * npair + k];
         for (int i = l; i < n; i += G) {
           const double x = A[i * kLs + p], y = A[i * kLs + q];
           al += x * x;
@@ -187,7 +244,7 @@ __device__ void jacobi_svd_lds(int n, double* A, double* Vm, double* cs, double*
       }
       if (k < npair && l == 0) {
         double c = 1.0, s = 0.0;
-        if (fabs(ga) > kEps * sqrt(al * be) && ga != 0.0) {
+        if (fabs(ga) > kEps * (double)n * sqrt(al * be) && ga != 0.0) {
           const double zeta = (be - al) / (2.0 * ga);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           c = 1.0 / sqrt(1.0 + tt * tt);
@@ -198,20 +255,18 @@ __device__ void jacobi_svd_lds(int n, double* A, double* Vm, double* cs, double*
         sn[k] = s;
       }
       __syncthreads();
-      for (int a = t; a < npair * np; a += kT) {
-        const int kk = a / np, i = a % np;
-        int pp, qq;
-        rr_pair(np, r, kk, pp, qq);
+      for (int kk = t >> 6; kk < npair; kk += kT / kWave) {
+        const int i = t & 63;
         const double c = cs[kk], s = sn[kk];
-        if (s != 0.0) {
-          double x = A[i * kLs + pp], y = A[i * kLs + qq];
-          A[i * kLs + pp] = c * x - s * y;
-          A[i * kLs + qq] = s * x + c * y;
-          x = Vm[i * kLs + pp];
-          y = Vm[i * kLs + qq];
-          Vm[i * kLs + pp] = c * x - s * y;
-          Vm[i * kLs + qq] = s * x + c * y;
-        }
+        if (i >= np || s == 0.0) continue;
+        const int p2 = pp[r * npair + kk], q2 = pq[r * npair + kk];
+        double x = A[i * kLs + p2], y = A[i * kLs + q2];
+        A[i * kLs + p2] = c * x - s * y;
+        A[i * kLs + q2] = s * x + c * y;
+        x = Vm[i * kLs + p2];
+        y = Vm[i * kLs + q2];
+        Vm[i * kLs + p2] = c * x - s * y;
+        Vm[i * kLs + q2] = s * x + c * y;
       }
       __syncthreads();
     }
@@ -269,6 +324,15 @@ void small_svd(int g, const double* R, int ldr, double* s, double* Y, int ldy, d
 // ---------------------------------------------------------------------------
 __global__ void k_h_append(Small* d, int gc, int nb) {
   const int tot = gc + nb;
+  // previous eigenvectors stay a good start: W <- diag(W, I)
+  const bool warm = d->warm_g == gc;
+  for (int a = threadIdx.x; a < tot * tot; a += blockDim.x) {
+    const int i = a % tot, j = a / tot;
+    if (i < gc && j < gc) continue;
+    d->Yw[j * kLd + i] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) d->warm_g = warm ? tot : -1;
   for (int a = threadIdx.x; a < tot * nb; a += blockDim.x) {
     const int i = a % tot, c = a / tot;
     const int j = gc + c;
@@ -295,17 +359,51 @@ void small_h_append(Small* d, int gc, int nb, hipStream_t s) {
 __global__ __launch_bounds__(kT) void k_extract(Small* d, int gc, int descending, int refined) {
   __shared__ double A[kLd * kLs];
   __shared__ double Z[kLd * kLs];
+  __shared__ double Mx[kLd * kLs];
   __shared__ double dd[kLd], cs[kLd], sn[kLd];
   __shared__ int flag;
   const int t = threadIdx.x;
   if (!refined) {
+    const bool warm = d->warm_g == gc;
     for (int a = t; a < gc * gc; a += kT) {
       const int i = a % gc, j = a / gc;
       A[i * kLs + j] = 0.5 * (d->H[j * kLd + i] + d->H[i * kLd + j]);
+      Z[i * kLs + j] = warm ? d->Yw[j * kLd + i] : (i == j ? 1.0 : 0.0);
     }
     __syncthreads();
-    jacobi_eig_lds(gc, A, Z, dd, cs, sn, &flag);
+    if (warm) {  // A <- W^T A W with W the previous eigenvectors (padded)
+      for (int a = t; a < gc * gc; a += kT) {
+        const int i = a % gc, j = a / gc;
+        double acc = 0.0;
+        for (int c = 0; c < gc; ++c) acc += A[i * kLs + c] * Z[c * kLs + j];
+        Mx[i * kLs + j] = acc;
+      }
+      __syncthreads();
+      for (int a = t; a < gc * gc; a += kT) {
+        const int i = a % gc, j = a / gc;
+        double acc = 0.0;
+        for (int c = 0; c < gc; ++c) acc += Z[c * kLs + i] * Mx[c * kLs + j];
+        A[i * kLs + j] = acc;
+      }
+      __syncthreads();
+      for (int a = t; a < gc * gc; a += kT) {  // symmetrise
+        const int i = a % gc, j = a / gc;
+        if (i < j) {
+          const double v = 0.5 * (A[i * kLs + j] + A[j * kLs + i]);
+          A[i * kLs + j] = v;
+          A[j * kLs + i] = v;
+        }
+      }
+      __syncthreads();
+    }
+    const int nsw = jacobi_eig_lds(gc, A, Z, dd, cs, sn, &flag);
+    if (t == 0) d->eig_sweeps = nsw;
     sort_pairs(gc, dd, Z, descending, d->theta, d->Y, kLd);
+    for (int a = t; a < gc * gc; a += kT) {
+      const int i = a % gc, j = a / gc;
+      d->Yw[j * kLd + i] = d->Y[j * kLd + i];
+    }
+    if (t == 0) d->warm_g = gc;
   } else {
     for (int a = t; a < gc * gc; a += kT) {
       const int i = a % gc, j = a / gc;
@@ -314,14 +412,23 @@ __global__ __launch_bounds__(kT) void k_extract(Small* d, int gc, int descending
     __syncthreads();
     jacobi_svd_lds(gc, A, Z, cs, sn, &flag);
     svd_finish(gc, A, Z, dd, d->sv, d->Y, kLd, nullptr, 0);
-    // theta_j = y_j^T H y_j
+    // theta_j = y_j^T H y_j with H and the sorted Y staged in LDS
+    for (int a = t; a < gc * gc; a += kT) {
+      const int i = a % gc, j = a / gc;
+      A[i * kLs + j] = d->H[j * kLd + i];
+      Z[i * kLs + j] = d->Y[j * kLd + i];
+    }
+    __syncthreads();
+    for (int a = t; a < gc * gc; a += kT) {  // M = H Y
+      const int i = a % gc, j = a / gc;
+      double acc = 0.0;
+      for (int c = 0; c < gc; ++c) acc += A[i * kLs + c] * Z[c * kLs + j];
+      Mx[i * kLs + j] = acc;
+    }
+    __syncthreads();
     for (int j = t; j < gc; j += kT) {
       double acc = 0.0;
-      for (int r = 0; r < gc; ++r) {
-        double hy = 0.0;
-        for (int c = 0; c < gc; ++c) hy += d->H[c * kLd + r] * d->Y[j * kLd + c];
-        acc += d->Y[j * kLd + r] * hy;
-      }
+      for (int r = 0; r < gc; ++r) acc += Z[r * kLs + j] * Mx[r * kLs + j];
       d->theta[j] = acc;
     }
   }
@@ -340,51 +447,58 @@ void small_extract(Small* d, int gc, int descending, int refined, hipStream_t s)
 // last nb rows of C0), which = 2 writes R2/R2inv.
 // ---------------------------------------------------------------------------
 __global__ void k_chol(Small* d, int nb, int which, int total) {
-  if (threadIdx.x != 0) return;
-  double R[kMaxBlock * kMaxBlock], Ri[kMaxBlock * kMaxBlock];
-  const double* G = d->G;
-  int bad = 0;
-  for (int a = 0; a < nb * nb; ++a) R[a] = Ri[a] = 0.0;
-  for (int j = 0; j < nb; ++j) {
-    const double gjj = G[j * nb + j];
-    const double dj = sqrt(fmax(gjj, 0.0));
-    double s = gjj;
-    for (int i = 0; i < j; ++i) s -= R[j * nb + i] * R[j * nb + i];
-    bool ok = (s > (kBreakRatio * dj) * (kBreakRatio * dj)) && dj > 0.0;
-    if (which == 1 && ok) {
-      const int ld0 = total + nb;
-      const double g0 = d->C0[(int64_t)j * ld0 + total + j];  // ||t_j||^2 before projection
-      ok = (gjj > (kCollapse * kCollapse) * g0) && g0 > 0.0;
-    }
-    if (!ok) {
-      bad |= 1 << j;
-      R[j * nb + j] = 1.0;  // keep the factor finite; the block is redone
-      continue;
-    }
-    const double rjj = sqrt(s);
-    R[j * nb + j] = rjj;
-    for (int c = j + 1; c < nb; ++c) {
-      double v = 0.5 * (G[c * nb + j] + G[j * nb + c]);
-      for (int i = 0; i < j; ++i) v -= R[j * nb + i] * R[c * nb + i];
-      R[c * nb + j] = v / rjj;  // column-major: R(j, c) at c*nb + j
-    }
+  __shared__ double G[kMaxBlock * kMaxBlock], g0[kMaxBlock];
+  __shared__ double R[kMaxBlock * kMaxBlock], Ri[kMaxBlock * kMaxBlock];
+  __shared__ int sbad;
+  const int t = threadIdx.x;
+  const int ld0 = total + nb;
+  if (t < nb * nb) {
+    G[t] = d->G[t];
+    R[t] = 0.0;
+    Ri[t] = 0.0;
   }
-  // inverse of the upper triangular R (column-major)
-  for (int c = 0; c < nb; ++c) {
-    Ri[c * nb + c] = 1.0 / R[c * nb + c];
-    for (int i = c - 1; i >= 0; --i) {
-      double v = 0.0;
-      for (int j = i + 1; j <= c; ++j) v += R[j * nb + i] * Ri[c * nb + j];
-      Ri[c * nb + i] = -v / R[i * nb + i];
+  if (t < nb) g0[t] = (which == 1) ? d->C0[(int64_t)t * ld0 + total + t] : 0.0;
+  __syncthreads();
+  if (t == 0) {
+    int bad = 0;
+    for (int j = 0; j < nb; ++j) {
+      const double gjj = G[j * nb + j];
+      const double dj = sqrt(fmax(gjj, 0.0));
+      double s = gjj;
+      for (int i = 0; i < j; ++i) s -= R[j * nb + i] * R[j * nb + i];
+      bool ok = (s > (kBreakRatio * dj) * (kBreakRatio * dj)) && dj > 0.0;
+      if (which == 1 && ok) ok = (gjj > (kCollapse * kCollapse) * g0[j]) && g0[j] > 0.0;
+      if (!ok) {
+        bad |= 1 << j;
+        R[j * nb + j] = 1.0;  // keep the factor finite; the block is redone
+        continue;
+      }
+      const double rjj = sqrt(s);
+      R[j * nb + j] = rjj;
+      for (int c = j + 1; c < nb; ++c) {
+        double v = 0.5 * (G[c * nb + j] + G[j * nb + c]);
+        for (int i = 0; i < j; ++i) v -= R[j * nb + i] * R[c * nb + i];
+        R[c * nb + j] = v / rjj;  // column-major: R(j, c) at c*nb + j
+      }
     }
+    for (int c = 0; c < nb; ++c) {  // inverse of the upper triangular factor
+      Ri[c * nb + c] = 1.0 / R[c * nb + c];
+      for (int i = c - 1; i >= 0; --i) {
+        double v = 0.0;
+        for (int j = i + 1; j <= c; ++j) v += R[j * nb + i] * Ri[c * nb + j];
+        Ri[c * nb + i] = -v / R[i * nb + i];
+      }
+    }
+    sbad = bad;
   }
+  __syncthreads();
   double* Ro = which == 1 ? d->R1 : d->R2;
   double* Rio = which == 1 ? d->R1inv : d->R2inv;
-  for (int a = 0; a < nb * nb; ++a) {
-    Ro[a] = R[a];
-    Rio[a] = Ri[a];
+  if (t < nb * nb) {
+    Ro[t] = R[t];
+    Rio[t] = Ri[t];
   }
-  d->bad |= bad;
+  if (t == 0 && sbad) d->bad |= sbad;
 }
 
 void small_chol(Small* d, int nb, int which, int total, hipStream_t s) {
@@ -444,29 +558,58 @@ __global__ __launch_bounds__(kT) void k_control(Small* d, CtlParams P) {
   __shared__ double M[kLd * kLs];
   const int t = threadIdx.x;
   const int gc = P.gc, nc = P.nc;
+  __shared__ double th_s[kLd], sums_s[6 * (kKmax + 8)], best_s[kKmax + 8];
+  __shared__ int stall_s[kKmax + 8];
+  __shared__ bool conv[kKmax + 8], done[kKmax + 8];
+  __shared__ double rn[kKmax + 8];
+  __shared__ double mx_s;
+  for (int j = t; j < gc; j += kT) th_s[j] = d->theta[j];
+  for (int j = t; j < (P.stage == 1 ? nc : 6 * nc); j += kT) sums_s[j] = d->sums[j];
+  for (int j = t; j < nc; j += kT) {
+    best_s[j] = d->best[j];
+    stall_s[j] = d->stall[j];
+  }
+  if (t < kWave) {
+    double mx = 0.0;
+    for (int j = t; j < gc; j += kWave) mx = fmax(mx, fabs(d->theta[j]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, kWave));
+    if (t == 0) mx_s = mx;
+  }
+  __syncthreads();
+  __shared__ int s_bad;
+  if (t == 0) s_bad = d->bad;
+  __syncthreads();
+  if (s_bad) {  // leave every state untouched: the host rolls the block back
+    if (t == 0) {
+      d->ctl.action = kBreakdown;
+      d->ctl.bad = s_bad;
+      d->ctl.restart = 0;
+      d->ctl.nlockable = 0;
+      d->ctl.nblock = 0;
+    }
+    return;
+  }
   if (t == 0) {
     Ctl& C = d->ctl;
-    double mx = 0.0;
-    for (int j = 0; j < gc; ++j) mx = fmax(mx, fabs(d->theta[j]));
-    d->normop = fmax(d->normop, mx);
+    C.bad = 0;
+    d->normop = fmax(d->normop, mx_s);
     const double nop = d->normop;
-    bool conv[kKmax + 8], done[kKmax + 8];
-    double rn[kKmax + 8];
     int ncv = 0, npc = 0;
     for (int c = 0; c < nc; ++c) {
-      rn[c] = sqrt(fmax(d->sums[0 * nc + c] + d->sums[3 * nc + c], 0.0));
+      rn[c] = sqrt(fmax(P.stage == 1 ? sums_s[c] : sums_s[0 * nc + c] + sums_s[3 * nc + c], 0.0));
       C.res[c] = rn[c];
-      C.val[c] = d->theta[c];
+      C.val[c] = th_s[c];
       if (P.stage == 1) {
-        const double thr = fmax(sqrt(fabs(d->theta[c]) * nop) * P.tol, P.eps * nop);
+        const double thr = fmax(sqrt(fabs(th_s[c]) * nop) * P.tol, P.eps * nop);
         conv[c] = rn[c] <= thr;
-        const bool pc = !conv[c] && d->stall[c] >= kStallRestarts && rn[c] <= kFloorGate * P.eps * nop;
+        const bool pc = !conv[c] && stall_s[c] >= kStallRestarts && rn[c] <= kFloorGate * P.eps * nop;
         done[c] = conv[c] || pc;
         npc += pc;
       } else {
         conv[c] = false;
         if (rn[c] <= 1.4142135623730951 * nop * P.tol)
-          conv[c] = halves_res(d->sums, nc, c, d->theta[c]) < P.normA * P.tol;
+          conv[c] = halves_res(sums_s, nc, c, th_s[c]) < P.normA * P.tol;
         done[c] = conv[c];
       }
       ncv += conv[c];
@@ -507,11 +650,11 @@ __global__ __launch_bounds__(kT) void k_control(Small* d, CtlParams P) {
           if (gc + nb_next > P.g) {
             restart = 1;
             for (int c = 0; c < nc; ++c) {
-              if (rn[c] < 0.5 * d->best[c]) {
+              if (rn[c] < 0.5 * best_s[c]) {
                 d->best[c] = rn[c];
                 d->stall[c] = 0;
               } else {
-                d->stall[c] += 1;
+                d->stall[c] = stall_s[c] + 1;
               }
             }
             int nd = 0;
@@ -525,7 +668,7 @@ __global__ __launch_bounds__(kT) void k_control(Small* d, CtlParams P) {
       int L = 0;
       while (L < nc && conv[L]) ++L;
       if (L > 0) {
-        for (int i = 0; i < L; ++i) d->lockval[P.nlock + i] = d->theta[i];
+        for (int i = 0; i < L; ++i) d->lockval[P.nlock + i] = th_s[i];
         lock = L;
         if (P.nlock + L >= P.k) {
           action = kExitConverged;
@@ -554,6 +697,11 @@ __global__ __launch_bounds__(kT) void k_control(Small* d, CtlParams P) {
       peff = (P.p > 0) ? min(min(P.p, d->nprev), room) : 0;
     }
     if (action == kReset) d->nprev = 0;
+    {
+      double rmin = INFINITY;
+      for (int c = 0; c < nc; ++c) rmin = fmin(rmin, rn[c]);
+      d->res_min = (action == kExpand && isfinite(rmin)) ? rmin : 0.0;
+    }
     s_action = action;
     s_nblock = nblock;
     s_restart = restart;
@@ -568,6 +716,7 @@ __global__ __launch_bounds__(kT) void k_control(Small* d, CtlParams P) {
     C.npc = npc;
     C.floor_reset = floor_reset;
     C.normop = nop;
+    C.eig_sweeps = d->eig_sweeps;
     C.maxres = maxres;
     C.minres = minres;
   }
@@ -705,6 +854,7 @@ __global__ __launch_bounds__(kT) void k_control(Small* d, CtlParams P) {
       d->Yr[j * kLd + i] = Yr[i * kLs + j];
     }
     if (t == 0) {
+      d->warm_g = -1;
       d->ctl.restart = 1;
       d->ctl.nr = nr;
       if (action == kExpand) {

@@ -24,7 +24,7 @@ __global__ __launch_bounds__(256) void k_spmm_group(const int32_t* __restrict__ 
   const int lane = threadIdx.x % L;
   const int bid = xcd_block(blockIdx.x, gridDim.x);
   for (int64_t slot = (int64_t)bid * RPB + grp; slot < nrows; slot += (int64_t)gridDim.x * RPB) {
-    const int32_t row = rows[slot];
+    const int32_t row = rows ? rows[slot] : (int32_t)slot;
     const int32_t a = rp[row], e = rp[row + 1];
     TV acc[B];
 #pragma unroll
@@ -92,11 +92,13 @@ __global__ __launch_bounds__(256) void k_spmm_wg(const int32_t* __restrict__ rp,
 
 template <typename TV, int B>
 static void spmm_b(const Csr32& A, const TV* val, const TV* X, TV* Y, hipStream_t s) {
+  const bool merged = A.merged_bin >= 0;
   for (int bn = 0; bn < kNumBins; ++bn) {
-    int64_t r0 = A.bin_off[bn], r1 = A.bin_off[bn + 1];
+    if (merged && bn != A.merged_bin) continue;
+    int64_t r0 = merged ? 0 : A.bin_off[bn], r1 = merged ? A.rows : A.bin_off[bn + 1];
     int64_t nr = r1 - r0;
     if (nr <= 0) continue;
-    const int32_t* rows = A.binrows + r0;
+    const int32_t* rows = merged ? nullptr : A.binrows + r0;
     if (bn == kNumBins - 1) {
       int blocks = (int)std::min<int64_t>(nr, 8192);
       k_spmm_wg<TV, B><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, rows, nr, X, Y);

@@ -20,6 +20,7 @@ enum Action : int {
   kExitBudget = 3,
   kReset = 4,       // recompute W = Op V from a re-orthonormalised V
   kLock = 5,        // stage 2: lock the converged prefix, then restart
+  kBreakdown = 6,   // the last block orthogonalisation broke down: roll it back
 };
 
 struct Ctl {
@@ -30,6 +31,8 @@ struct Ctl {
   int nlockable;    // stage 2: converged prefix length
   int nconv, npc;   // converged / practically converged among candidates
   int floor_reset;  // the reset confirms the attainable floor
+  int eig_sweeps;   // Jacobi sweeps of the last extraction (trace)
+  int bad;          // breakdown bitmask of the last block orthogonalisation
   double normop;    // ||Op|| used by the tests
   double maxres;    // largest residual of the wanted pairs
   double minres;
@@ -40,6 +43,8 @@ struct Ctl {
 struct Small {
   double H[kLd * kLd];     // V^T Op V
   double Y[kLd * kLd];     // extraction vectors (eigen- or right singular vectors)
+  double Yw[kLd * kLd];    // warm start for the eigensolver: H is nearly diagonal in it
+  int warm_g;              // its size (-1: none)
   double theta[kLd];       // Ritz values (refined: y^T H y)
   double sv[kLd];          // refined: singular values of Rr
   double Rr[kLd * kLd];    // refined: R of (W - tau V) = Q Rr
@@ -59,6 +64,8 @@ struct Small {
   int bad;                // orthogonalisation breakdown bitmask
   int nprev, gprev;       // +k vectors: count and rows
   double normop;          // running ||Op||
+  int eig_sweeps;
+  double res_min;         // smallest candidate residual of the last control step
   double lockval[kKmax];  // stage 2: locked Ritz values
   Ctl ctl;
 };

@@ -206,3 +206,19 @@ def test_deterministic_solve(P):
     b = P.svds(A, 3, "smallest", 1e-10, seed=9, norm_A=8.0)
     import torch
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[2], b[2])
+
+
+def test_rank_deficient_breakdown_repair(P):
+    """A rank-3 matrix: the Krylov fill and the corrections run out of new
+    directions, so orthogonalisation breakdowns are repaired with counter-based
+    random vectors; the three nonzero singular values still match."""
+    rng = np.random.default_rng(4)
+    Ud, _ = np.linalg.qr(rng.standard_normal((300, 3)))
+    Vd, _ = np.linalg.qr(rng.standard_normal((200, 3)))
+    A = sp.csr_matrix((Ud * np.array([3.0, 2.0, 1.0])) @ Vd.T)
+    A = synth.to_csr(A)
+    _say("rank-3 300x200 largest k=3 b=2")
+    sig, U, V, rn, st = P.svds(A, 3, "largest", 1e-10, block_size=2, norm_A=3.0, seed=1)
+    assert st["breakdowns"] > 0, st
+    assert np.max(np.abs(sig.cpu().numpy() - [3.0, 2.0, 1.0])) < 1e-12
+    assert float(rn.max()) <= 3e-10
