@@ -133,28 +133,47 @@ void fill_random(double* X, int64_t ld, int64_t N, int ncols, uint64_t seed, uin
 void spmm(const Csr32& A, int b, const double* X, double* Y, hipStream_t s);
 void spmm_f32(const Csr32& A, int b, const float* X, float* Y, hipStream_t s);
 
-// dense tall-skinny (column-major, FP64 unless noted)
-struct Seg {
-  const double* p;
+// dense tall-skinny (column-major).  Basis segments may be stored in FP64 or
+// FP32 (mixed-precision stage 1); the arithmetic is FP64 throughout.
+template <typename TB>
+struct SegT {
+  const TB* p;
   int ncols;
   int64_t ld;
 };
+using Seg = SegT<double>;
+using Seg32 = SegT<float>;
 int reduce_blocks(int64_t N);
+// out[o] = sum over blocks of P[o * nblk + block]  (fixed order)
+void reduce_partials(const double* P, int nblk, int nout, double* out, hipStream_t s);
 // C ((sum of seg cols) x b, col-major, ld = total) = [segs]^T T
-void tsgemm_tn(const Seg* segs, int nseg, int64_t N, const double* T, int64_t ldt, int b,
+template <typename TB>
+void tsgemm_tn(const SegT<TB>* segs, int nseg, int64_t N, const double* T, int64_t ldt, int b,
                double* partial, double* C, hipStream_t s);
 // T -= [segs] C   (C: total x b, column-major with leading dimension ldc)
-void ts_update(const Seg* segs, int nseg, int64_t N, const double* C, int ldc, double* T,
+template <typename TB>
+void ts_update(const SegT<TB>* segs, int nseg, int64_t N, const double* C, int ldc, double* T,
                int64_t ldt, int b, hipStream_t s);
 // Out (N x nout) = Q (N x nq) Y (nq x nout, ld ldy); Out may not alias Q
-void ts_gemm_nn(const double* Q, int64_t ldq, int nq, int64_t N, const double* Y, int64_t ldy,
-                int nout, double* Out, int64_t ldo, hipStream_t s);
+template <typename TI, typename TO>
+void ts_gemm_nn(const TI* Q, int64_t ldq, int nq, int64_t N, const double* Y, int64_t ldy,
+                int nout, TO* Out, int64_t ldo, hipStream_t s);
+template <typename TI, typename TO>
+void copy_cols_cvt(const TI* A, int64_t lda, int64_t N, int b, TO* B, int64_t ldb, TO* compact,
+                   hipStream_t s);
+void unpack_rows_f32(const float* compact, int64_t N, int b, float* A, int64_t lda,
+                     hipStream_t s);
+// H columns of the mixed-precision stage 1: [V]^T W (FP32 storage) with BF16
+// MFMA products (hi/lo split) accumulated in FP32, partials summed in FP64
+void proj_bf16x3(const float* V, int64_t ldv, int nv, const float* W, int64_t ldw, int nb,
+                 int64_t N, double* partial, double* C, hipStream_t s);
 // T <- T Rinv (b x b upper), optionally also writes a row-major copy
 void ts_scale(double* T, int64_t ldt, int64_t N, int b, const double* Rinv, double* compact,
               hipStream_t s);
 // fused residual for nc candidates: R = W Y - V Y diag(theta); per-candidate
 // sums (rows < nsplit | rows >= nsplit): ||r||^2, x.r, ||x||^2 each
-void ts_residual(const double* V, const double* W, int64_t ld, int64_t N, int64_t nsplit, int g,
+template <typename TB>
+void ts_residual(const TB* V, const TB* W, int64_t ld, int64_t N, int64_t nsplit, int g,
                  const double* Y, int64_t ldy, const double* theta, int nc, double* R,
                  int64_t ldr, double* partial, double* sums, hipStream_t s);
 void pack_rows(const double* A, int64_t lda, const double* B, double beta, int64_t N, int b,

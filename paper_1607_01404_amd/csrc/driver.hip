@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "small.h"
@@ -132,6 +133,11 @@ class Solver {
   Ctl* hctl_ = nullptr;     // pinned
   int* hbad_ = nullptr;     // pinned
   double* vec_ = nullptr;   // small device vectors (k-sized)
+  // mixed-precision stage 1: FP32 basis, FP64 work block, FP32 compact blocks
+  float *V32_ = nullptr, *W32_ = nullptr, *Vt32_ = nullptr, *Wt32_ = nullptr;
+  float *Tc32_ = nullptr, *Yc32_ = nullptr, *Wc32_ = nullptr;
+  double* Tb_ = nullptr;
+  bool mixed_ = false;
 
   // ---- operators -----------------------------------------------------------
   const Csr32& A() const { return M_->A; }
@@ -140,20 +146,26 @@ class Solver {
   // sparse product with optional event timing
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_;
   double spmm_bytes_ = 0.0;
-  void timed_spmm(const Csr32& Mx, int nb, const double* X, double* Y) {
+  template <typename TV>
+  void timed_spmm(const Csr32& Mx, int nb, const TV* X, TV* Y) {
+    auto run = [&] {
+      if constexpr (std::is_same<TV, double>::value) spmm(Mx, nb, X, Y, s_);
+      else spmm_f32(Mx, nb, X, Y, s_);
+    };
     if (!o_.profile) {
-      spmm(Mx, nb, X, Y, s_);
+      run();
       return;
     }
     hipEvent_t a, b;
     SVDS_HIP(hipEventCreate(&a));
     SVDS_HIP(hipEventCreate(&b));
     SVDS_HIP(hipEventRecord(a, s_));
-    spmm(Mx, nb, X, Y, s_);
+    run();
     SVDS_HIP(hipEventRecord(b, s_));
     ev_.emplace_back(a, b);
-    spmm_bytes_ += (double)Mx.nnz * 12.0 + 4.0 * (double)(Mx.rows + 1) +
-                   8.0 * nb * (double)(Mx.rows + Mx.cols);
+    const double sv = (double)sizeof(TV);
+    spmm_bytes_ += (double)Mx.nnz * (sv + 4.0) + 4.0 * (double)(Mx.rows + 1) +
+                   sv * nb * (double)(Mx.rows + Mx.cols);
   }
   void collect_profile(svds_stats* st) {
     double total = 0.0;
@@ -184,7 +196,9 @@ class Solver {
   }
 
   // ---- orthogonalisation: CGS twice against segs, Cholesky QR twice ----------
-  int ortho_once(double* T, int64_t ldt, int nb, const Seg* segs, int nseg, double* compact) {
+  template <typename TB>
+  int ortho_once(double* T, int64_t ldt, int nb, const SegT<TB>* segs, int nseg,
+                 double* compact) {
     ortho_enqueue(T, ldt, nb, segs, nseg, compact);
     SVDS_HIP(hipMemcpyAsync(hbad_, &d_->bad, sizeof(int), hipMemcpyDeviceToHost, s_));
     SVDS_HIP(hipStreamSynchronize(s_));
@@ -192,30 +206,45 @@ class Solver {
   }
 
   // CGS twice + CholQR twice, enqueued only; d_->bad records dependent columns
-  void ortho_enqueue(double* T, int64_t ldt, int nb, const Seg* segs, int nseg, double* compact) {
+  template <typename TB>
+  void ortho_enqueue(double* T, int64_t ldt, int nb, const SegT<TB>* segs, int nseg,
+                     double* compact) {
     int total = 0;
     for (int i = 0; i < nseg; ++i) total += segs[i].ncols;
     SVDS_HIP(hipMemsetAsync(&d_->bad, 0, sizeof(int), s_));
-    Seg s1[3];
+    SegT<TB> sb[3];
     int n1 = 0;
     for (int i = 0; i < nseg; ++i)
-      if (segs[i].ncols > 0) s1[n1++] = segs[i];
-    Seg sb[3];
-    for (int i = 0; i < n1; ++i) sb[i] = s1[i];
-    s1[n1] = Seg{T, nb, ldt};
-    // pass 1 with the block's own Gram (pre-projection norms) appended
-    tsgemm_tn(s1, n1 + 1, N_, T, ldt, nb, partial_, d_->C0, s_);
+      if (segs[i].ncols > 0) sb[n1++] = segs[i];
+    Seg st{T, nb, ldt};
+    const double* G0;
+    int ldg0, ldc0;
+    if constexpr (std::is_same<TB, double>::value) {
+      // pass 1 with the block's own Gram (pre-projection norms) appended
+      Seg s1[3];
+      for (int i = 0; i < n1; ++i) s1[i] = sb[i];
+      s1[n1] = st;
+      tsgemm_tn(s1, n1 + 1, N_, T, ldt, nb, partial_, d_->C0, s_);
+      G0 = d_->C0 + total;
+      ldg0 = total + nb;
+      ldc0 = total + nb;
+    } else {
+      tsgemm_tn(&st, 1, N_, T, ldt, nb, partial_, d_->G0, s_);
+      if (total > 0) tsgemm_tn(sb, n1, N_, T, ldt, nb, partial_, d_->C0, s_);
+      G0 = d_->G0;
+      ldg0 = nb;
+      ldc0 = total;
+    }
     if (total > 0) {
-      ts_update(sb, n1, N_, d_->C0, total + nb, T, ldt, nb, s_);
+      ts_update(sb, n1, N_, d_->C0, ldc0, T, ldt, nb, s_);
       tsgemm_tn(sb, n1, N_, T, ldt, nb, partial_, d_->C1, s_);
       ts_update(sb, n1, N_, d_->C1, total, T, ldt, nb, s_);
     }
-    Seg st{T, nb, ldt};
     tsgemm_tn(&st, 1, N_, T, ldt, nb, partial_, d_->G, s_);
-    small_chol(d_, nb, 1, total, s_);
+    small_chol(d_, nb, 1, G0, ldg0, s_);
     ts_scale(T, ldt, N_, nb, d_->R1inv, nullptr, s_);
     tsgemm_tn(&st, 1, N_, T, ldt, nb, partial_, d_->G, s_);
-    small_chol(d_, nb, 2, total, s_);
+    small_chol(d_, nb, 2, nullptr, 0, s_);
     ts_scale(T, ldt, N_, nb, d_->R2inv, compact, s_);
   }
 
@@ -239,7 +268,8 @@ class Solver {
   }
 
   // with breakdown repair: dependent columns get fresh counter-based vectors
-  void ortho(double* T, int64_t ldt, int nb, const Seg* segs, int nseg, double* compact) {
+  template <typename TB>
+  void ortho(double* T, int64_t ldt, int nb, const SegT<TB>* segs, int nseg, double* compact) {
     for (int attempt = 0; attempt < 4; ++attempt) {
       int bad = ortho_once(T, ldt, nb, segs, nseg, compact);
       if (!bad) return;
@@ -369,9 +399,62 @@ class Solver {
     mv_ += 2 * nb;
   }
 
+  // ---- mixed-precision stage 1 (FP32 basis, FP64 reorthogonalisation) --------
+  // the orthonormal FP64 block Tb_ becomes V32[:, gc:gc+nb] and the FP32
+  // row-major block for the sparse products
+  void commit32(int nb) {
+    copy_cols_cvt<double, float>(Tb_, ld_, N_, nb, V32_ + gc_ * ld_, ld_, Tc32_, s_);
+  }
+  void append32(int nb) {
+    timed_spmm(A(), nb, (const float*)Tc32_, Yc32_);
+    timed_spmm(At(), nb, (const float*)Yc32_, Wc32_);
+    mv_ += 2 * nb;
+    float* Wcol = W32_ + gc_ * ld_;
+    unpack_rows_f32(Wc32_, N_, nb, Wcol, ld_, s_);
+    proj_bf16x3(V32_, ld_, gc_ + nb, Wcol, ld_, nb, N_, partial_, d_->Hn, s_);
+    small_h_append(d_, gc_, nb, s_);
+    gc_ += nb;
+  }
+  void restart32(int nr) {
+    ts_gemm_nn(V32_, ld_, gc_, N_, d_->Yr, kLd, nr, Vt32_, ld_, s_);
+    ts_gemm_nn(W32_, ld_, gc_, N_, d_->Yr, kLd, nr, Wt32_, ld_, s_);
+    std::swap(V32_, Vt32_);
+    std::swap(W32_, Wt32_);
+    gc_ = nr;
+  }
+  void reset32() {
+    const int gold = gc_;
+    std::swap(V32_, Vt32_);
+    gc_ = 0;
+    for (int c0 = 0; c0 < gold; c0 += kMaxBlock) {
+      const int nb = std::min(kMaxBlock, gold - c0);
+      copy_cols_cvt<float, double>(Vt32_ + c0 * ld_, ld_, N_, nb, Tb_, ld_, nullptr, s_);
+      Seg32 sv{V32_, gc_, ld_};
+      ortho(Tb_, ld_, nb, &sv, 1, (double*)nullptr);
+      commit32(nb);
+      append32(nb);
+    }
+  }
+  void repair32(int nb, int bad) {
+    gc_ -= nb;
+    ++breakdowns_;
+    const uint64_t stream = kStreamBreak + (uint64_t)rand_count_++;
+    int i = 0;
+    for (int j = 0; j < nb; ++j)
+      if (bad & (1 << j)) fill_random(Tb_ + j * ld_, ld_, N_, 1, o_.seed, stream, i++, s_);
+    Seg32 sv{V32_, gc_, ld_};
+    ortho(Tb_, ld_, nb, &sv, 1, (double*)nullptr);
+    commit32(nb);
+    append32(nb);
+    extract_stage();
+  }
+
   // ---- stages ------------------------------------------------------------------
   int stage1(double* Vout /*n x k*/, double* Uout /*m x k*/, double* sig, double* rn, double* taus,
              int* ok, int* status1, svds_stats* st);
+  int stage1_mixed(double* V1, double* U1, double* sig, double* rn, double* taus, int* ok,
+                   int* status1, svds_stats* st);
+  void final_rr(double* Xk, double* V1, double* U1, double* sig, double* rn, double* taus, int* ok);
   int stage2(const double* taus_h, double* Vout, double* Uout, double* sig, int* nconv,
              svds_stats* st);
   void cleanup_and_output(double* Vw /*n x k*/, double* Uw /*m x k*/, double* sig, double* sigma,
@@ -420,7 +503,7 @@ void Solver::estimate_norm() {
   refined_ = false;
   const int steps = (int)std::min<int64_t>(std::min(30, kGmax), n_);
   fill_random(V_, ld_, N_, 1, o_.seed, kStreamNorm, 0, s_);
-  ortho(V_, ld_, 1, nullptr, 0, Tc_);
+  ortho<double>(V_, ld_, 1, nullptr, 0, Tc_);
   append(1);
   while (gc_ < steps) {
     double* T = V_ + gc_ * ld_;
@@ -463,7 +546,7 @@ int Solver::stage1(double* V1, double* U1, double* sig, double* rn, double* taus
   const int r = std::min(r_, std::max(1, g - b_ - p_));
   const int fill = std::min(std::max(r, k_ + b_), g - b_);
   fill_random(V_, ld_, N_, b_, o_.seed, kStreamInit, 0, s_);
-  ortho(V_, ld_, b_, nullptr, 0, Tc_);
+  ortho<double>(V_, ld_, b_, nullptr, 0, Tc_);
   append(b_);
   while (gc_ < fill && gc_ + b_ <= g) {
     double* T = V_ + gc_ * ld_;
@@ -495,6 +578,7 @@ int Solver::stage1(double* V1, double* U1, double* sig, double* rn, double* taus
     P.tol = tol1_;
     P.normA = normA_;
     P.eps = kEps;
+    P.gate = kFloorGate * kEps;
     Ctl c = control(P);
     trace("s1", (int)iters, c, nc);
     if (c.action == kBreakdown) {
@@ -539,26 +623,7 @@ int Solver::stage1(double* V1, double* U1, double* sig, double* rn, double* taus
   // final Rayleigh-Ritz on A X (steps 4-5)
   double* Xk = X_;  // n x k (ld ld_)
   ts_gemm_nn(V_, ld_, gc_, N_, d_->Y, kLd, k_, Xk, ld_, s_);
-  double* AX = R_;  // m x k, ld ld_
-  spmm_cols(A(), Xk, ld_, n_, k_, AX, ld_, m_);
-  double* G = vec_;                 // k x k
-  double* lam = vec_ + kKmax * kKmax;
-  double* Z = lam + kKmax;          // k x k (ld kLd)
-  double* inv = Z + kLd * kLd;
-  double* rl2 = inv + kKmax;
-  double* rr2 = rl2 + kKmax;
-  gram(AX, ld_, AX, ld_, m_, k_, G);
-  small_eig(k_, G, k_, largest_ ? 1 : 0, lam, Z, kLd, s_);
-  ts_gemm_nn(Xk, ld_, k_, n_, Z, kLd, k_, V1, ld_, s_);      // v = X z
-  ts_gemm_nn(AX, ld_, k_, m_, Z, kLd, k_, Wt_, ld_, s_);     // A v
-  sigma_from_lambda(k_, lam, sig, inv, s_);
-  copy_cols(Wt_, ld_, m_, k_, U1, ld_, s_);
-  col_scale(U1, ld_, m_, k_, inv, s_);                      // u = A v / sigma
-  double* AtU = Vt_;
-  spmm_cols(At(), U1, ld_, m_, k_, AtU, ld_, n_);
-  col_residual2(Wt_, ld_, U1, ld_, sig, m_, k_, partial_, rl2, s_);   // ||A v - s u||^2
-  col_residual2(AtU, ld_, V1, ld_, sig, n_, k_, partial_, rr2, s_);   // ||A^T u - s v||^2
-  stage1_check(k_, rl2, rr2, sig, normA_, tol_, rn, taus, ok, s_);
+  final_rr(Xk, V1, U1, sig, rn, taus, ok);
   SVDS_HIP(hipStreamSynchronize(s_));
   st->iters[0] = iters;
   st->restarts[0] = restarts;
@@ -624,6 +689,7 @@ int Solver::stage2(const double* taus_h, double* V1, double* U1, double* sig, in
     P.tol = tol_;
     P.normA = normA_;
     P.eps = kEps;
+    P.gate = kFloorGate * kEps;
     Ctl c = control(P);
     trace("s2", (int)iters, c, nc);
     if (c.action == kBreakdown) {
@@ -762,6 +828,153 @@ void Solver::cleanup_and_output(double* Vw, double* Uw, double* sig, double* sig
   SVDS_HIP(hipMemcpyAsync(sigma, sig, sizeof(double) * k_, hipMemcpyDeviceToDevice, s_));
 }
 
+// Rayleigh-Ritz on the returned basis through A X (Algorithm 1, steps 4-5):
+// G = (A X)^T (A X), sigma = |lambda|^(1/2), v = X z, u = A v / sigma, then
+// eq. (res) and the stage-2 shifts
+void Solver::final_rr(double* Xk, double* V1, double* U1, double* sig, double* rn, double* taus,
+                      int* ok) {
+  double* AX = R_;  // m x k, ld ld_
+  spmm_cols(A(), Xk, ld_, n_, k_, AX, ld_, m_);
+  double* G = vec_;                 // k x k
+  double* lam = vec_ + kKmax * kKmax;
+  double* Z = lam + kKmax;          // k x k (ld kLd)
+  double* inv = Z + kLd * kLd;
+  double* rl2 = inv + kKmax;
+  double* rr2 = rl2 + kKmax;
+  gram(AX, ld_, AX, ld_, m_, k_, G);
+  small_eig(k_, G, k_, largest_ ? 1 : 0, lam, Z, kLd, s_);
+  ts_gemm_nn(Xk, ld_, k_, n_, Z, kLd, k_, V1, ld_, s_);      // v = X z
+  ts_gemm_nn(AX, ld_, k_, m_, Z, kLd, k_, Wt_, ld_, s_);     // A v
+  sigma_from_lambda(k_, lam, sig, inv, s_);
+  copy_cols(Wt_, ld_, m_, k_, U1, ld_, s_);
+  col_scale(U1, ld_, m_, k_, inv, s_);                      // u = A v / sigma
+  double* AtU = Vt_;
+  spmm_cols(At(), U1, ld_, m_, k_, AtU, ld_, n_);
+  col_residual2(Wt_, ld_, U1, ld_, sig, m_, k_, partial_, rl2, s_);   // ||A v - s u||^2
+  col_residual2(AtU, ld_, V1, ld_, sig, n_, k_, partial_, rr2, s_);   // ||A^T u - s v||^2
+  stage1_check(k_, rl2, rr2, sig, normA_, tol_, rn, taus, ok, s_);
+}
+
+// ---------------------------------------------------------------------------
+// Stage 1 in mixed precision: the basis V, W = C V and the sparse products in
+// FP32, the new columns of H = V^T W with BF16 matrix-core products (FP32
+// accumulation); reorthogonalisation, Cholesky QR Gram matrices, the
+// projected eigenproblem and the residual norms in FP64.  The stage-1 floor
+// uses the unit roundoff of the projections (2^-16 for the split BF16
+// product); stage 2 and the final Rayleigh-Ritz are FP64.
+// ---------------------------------------------------------------------------
+constexpr double kEpsMixed = 1.52587890625e-05;  // 2^-16
+
+int Solver::stage1_mixed(double* V1, double* U1, double* sig, double* rn, double* taus, int* ok,
+                         int* status1, svds_stats* st) {
+  stage_ = 1;
+  N_ = n_;
+  gc_ = 0;
+  nlock_ = 0;
+  refined_ = false;
+  const double t0 = now();
+  const int64_t mv0 = mv_;
+  SVDS_HIP(hipMemsetAsync(d_, 0, sizeof(Small), s_));
+  {
+    std::vector<double> best(kKmax + 8, INFINITY);
+    SVDS_HIP(hipMemcpyAsync(d_->best, best.data(), sizeof(double) * best.size(),
+                            hipMemcpyHostToDevice, s_));
+    double nc = normA_ * normA_;
+    SVDS_HIP(hipMemcpyAsync(&d_->normop, &nc, sizeof(double), hipMemcpyHostToDevice, s_));
+    SVDS_HIP(hipStreamSynchronize(s_));
+  }
+  const int g = (int)std::min<int64_t>(g_, n_);
+  const int r = std::min(r_, std::max(1, g - b_ - p_));
+  const int fill = std::min(std::max(r, k_ + b_), g - b_);
+  fill_random(Tb_, ld_, N_, b_, o_.seed, kStreamInit, 0, s_);
+  ortho<double>(Tb_, ld_, b_, nullptr, 0, nullptr);
+  commit32(b_);
+  append32(b_);
+  while (gc_ < fill && gc_ + b_ <= g) {
+    copy_cols_cvt<float, double>(W32_ + (gc_ - b_) * ld_, ld_, N_, b_, Tb_, ld_, nullptr, s_);
+    Seg32 sv{V32_, gc_, ld_};
+    ortho(Tb_, ld_, b_, &sv, 1, (double*)nullptr);
+    commit32(b_);
+    append32(b_);
+  }
+  extract_stage();
+  int64_t iters = 0, restarts = 0, resets = 0;
+  int since_reset = 0, floor_resets = 0;
+  int status = 2;
+  int last_nb = 0;
+  for (;;) {
+    const int nc = std::min(gc_, k_ + b_);
+    ts_residual(V32_, W32_, ld_, N_, N_, gc_, d_->Y, kLd, d_->theta, nc, R_, ld_, partial_,
+                d_->sums, s_);
+    CtlParams P{};
+    P.stage = 1;
+    P.gc = gc_;
+    P.g = g;
+    P.r = r;
+    P.p = p_;
+    P.b = b_;
+    P.k = k_;
+    P.nc = nc;
+    P.since_reset = since_reset;
+    P.floor_resets = floor_resets;
+    P.budget_hit = mv_ >= budget_;
+    P.tol = tol1_;
+    P.normA = normA_;
+    P.eps = kEpsMixed;
+    P.gate = std::min(kFloorGate * kEpsMixed, 1e-2);
+    Ctl c = control(P);
+    trace("s1m", (int)iters, c, nc);
+    if (c.action == kBreakdown) {
+      repair32(last_nb, c.bad);
+      continue;
+    }
+    if (c.action == kExitConverged || c.action == kExitFloor || c.action == kExitBudget) {
+      status = c.action == kExitConverged ? 0 : (c.action == kExitFloor ? 1 : 2);
+      normA_ = std::max(normA_, std::sqrt(c.normop));
+      break;
+    }
+    if (c.action == kReset) {
+      reset32();
+      ++resets;
+      since_reset = 0;
+      floor_resets += c.floor_reset;
+      extract_stage();
+      continue;
+    }
+    if (c.restart) {
+      restart32(c.nr);
+      ++restarts;
+      ++since_reset;
+    }
+    int nb = c.nblock;
+    if (nb == 0) {
+      nb = b_;
+      fill_random(Tb_, ld_, N_, nb, o_.seed, kStreamBreak + (uint64_t)rand_count_++, 0, s_);
+    } else {
+      gather_precond(R_, ld_, d_->blk, nb, o_.precond == SVDS_PC_JACOBI ? dinv_ : nullptr, N_,
+                     Tb_, ld_, s_);
+    }
+    Seg32 sv{V32_, gc_, ld_};
+    ortho_enqueue(Tb_, ld_, nb, &sv, 1, (double*)nullptr);
+    commit32(nb);
+    append32(nb);
+    last_nb = nb;
+    extract_stage();
+    ++iters;
+  }
+  double* Xk = X_;
+  ts_gemm_nn(V32_, ld_, gc_, N_, d_->Y, kLd, k_, Xk, ld_, s_);
+  final_rr(Xk, V1, U1, sig, rn, taus, ok);
+  SVDS_HIP(hipStreamSynchronize(s_));
+  st->iters[0] = iters;
+  st->restarts[0] = restarts;
+  st->resets += resets;
+  st->matvecs[0] = mv_ - mv0;
+  st->seconds[0] = now() - t0;
+  *status1 = status;
+  return 0;
+}
+
 int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, double* rnorm,
                 svds_stats* st) {
   std::memset(st, 0, sizeof(*st));
@@ -793,6 +1006,17 @@ int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, d
   double* rn1 = buf_.get<double>(kKmax);
   double* taus = buf_.get<double>(kKmax);
   int* ok = buf_.get<int>(1);
+  mixed_ = o_.precision == SVDS_MIXED;
+  if (mixed_) {
+    V32_ = buf_.get<float>(basis);
+    W32_ = buf_.get<float>(basis);
+    Vt32_ = buf_.get<float>(basis);
+    Wt32_ = buf_.get<float>(basis);
+    Tc32_ = buf_.get<float>((size_t)ld_ * kMaxBlock);
+    Yc32_ = buf_.get<float>((size_t)ld_ * kMaxBlock);
+    Wc32_ = buf_.get<float>((size_t)ld_ * kMaxBlock);
+    Tb_ = buf_.get<double>((size_t)ld_ * kMaxBlock);
+  }
   SVDS_HIP(hipHostMalloc((void**)&hctl_, sizeof(Ctl), hipHostMallocDefault));
   SVDS_HIP(hipHostMalloc((void**)&hbad_, sizeof(int), hipHostMallocDefault));
   struct PinnedFree {
@@ -823,7 +1047,11 @@ int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, d
   st->setup_seconds = now() - t0;
   // ---- stage 1
   int okh = 0, status1 = 2;
-  stage1(V1, U1, sig, rn1, taus, ok, &status1, st);
+  if (mixed_) {
+    stage1_mixed(V1, U1, sig, rn1, taus, ok, &status1, st);
+  } else {
+    stage1(V1, U1, sig, rn1, taus, ok, &status1, st);
+  }
   SVDS_HIP(hipMemcpyAsync(&okh, ok, sizeof(int), hipMemcpyDeviceToHost, s_));
   SVDS_HIP(hipStreamSynchronize(s_));
   st->stage1_status = status1;
@@ -933,6 +1161,11 @@ int create_matrix(const svds_csr* A, svds_matrix** out, hipStream_t s) {
     SVDS_HIP(hipFreeAsync(cursor, s));
     svds::build_bins(a, s);
     svds::build_bins(at, s);
+    // FP32 copies of the values for the mixed-precision stage 1
+    SVDS_HIP(hipMalloc((void**)&a.val32, sizeof(float) * std::max<int64_t>(A->nnz, 1)));
+    SVDS_HIP(hipMalloc((void**)&at.val32, sizeof(float) * std::max<int64_t>(A->nnz, 1)));
+    svds::to_fp32(a.val, a.val32, A->nnz, s);
+    svds::to_fp32(at.val, at.val32, A->nnz, s);
     if (h->transposed) {
       h->A = at;
       h->At = a;
@@ -972,7 +1205,7 @@ int solve_prepared(const svds_matrix* h, int k, int target, double tol, const sv
   if (k < 1 || k > mn || k > svds::kKmax) throw Error(SVDS_ERR_ARG, "k out of range");
   if (ldu < h->m || ldv < h->n) throw Error(SVDS_ERR_ARG, "leading dimension too small");
   svds_opts o = opts ? *opts : default_opts();
-  if (o.precision != SVDS_FP64) throw Error(SVDS_ERR_ARG, "precision not available");
+  if (o.precision != SVDS_FP64 && o.precision != SVDS_MIXED) throw Error(SVDS_ERR_ARG, "precision");
   if (o.precond != SVDS_PC_NONE && o.precond != SVDS_PC_JACOBI) throw Error(SVDS_ERR_ARG, "precond");
   svds_stats local;
   svds_stats* st = stats ? stats : &local;

@@ -20,13 +20,16 @@ int reduce_blocks(int64_t N) {
   return (int)nb;
 }
 
-struct Segs3 {
-  const double* p[3];
+template <typename TB>
+struct Segs3T {
+  const TB* p[3];
   int64_t ld[3];
   int n0, n1, n2;  // columns per segment
 };
+using Segs3 = Segs3T<double>;
 
-__device__ __forceinline__ const double* seg_col(const Segs3& s, int v) {
+template <typename TB>
+__device__ __forceinline__ const TB* seg_col(const Segs3T<TB>& s, int v) {
   if (v < s.n0) return s.p[0] + (int64_t)v * s.ld[0];
   v -= s.n0;
   if (v < s.n1) return s.p[1] + (int64_t)v * s.ld[1];
@@ -63,15 +66,15 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NA], double* sh
 // ---------------------------------------------------------------------------
 constexpr int kCPW = 8;  // basis columns per wavefront (32 per workgroup column)
 
-template <int B>
-__global__ __launch_bounds__(kThreads) void k_tsgemm_tn(Segs3 segs, int total, int64_t N,
+template <int B, typename TB>
+__global__ __launch_bounds__(kThreads) void k_tsgemm_tn(Segs3T<TB> segs, int total, int64_t N,
                                                         const double* __restrict__ T,
                                                         int64_t ldt,
                                                         double* __restrict__ partial) {
   __shared__ double ts[kThreads * B];
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int c0 = blockIdx.y * (4 * kCPW);
-  const double* qp[kCPW];
+  const TB* qp[kCPW];
   bool ok[kCPW];
 #pragma unroll
   for (int jj = 0; jj < kCPW; ++jj) {
@@ -102,7 +105,7 @@ __global__ __launch_bounds__(kThreads) void k_tsgemm_tn(Segs3 segs, int total, i
 #pragma unroll
         for (int jj = 0; jj < kCPW; ++jj) {
           if (ok[jj]) {
-            const double q = qp[jj][row];
+            const double q = (double)qp[jj][row];
 #pragma unroll
             for (int c = 0; c < B; ++c) acc[jj * B + c] = fma(q, tv[c], acc[jj * B + c]);
           }
@@ -134,15 +137,16 @@ __global__ __launch_bounds__(64) void k_reduce_partials(const double* __restrict
   if (threadIdx.x == 0) out[o] = s;
 }
 
-static void reduce_partials(const double* P, int nblk, int nout, double* out, hipStream_t s) {
+void reduce_partials(const double* P, int nblk, int nout, double* out, hipStream_t s) {
   if (nout <= 0) return;
   k_reduce_partials<<<nout, 64, 0, s>>>(P, nblk, out);
   SVDS_LAUNCH_CHECK();
 }
 
-static Segs3 make_segs(const Seg* segs, int nseg, int& total) {
+template <typename TB>
+static Segs3T<TB> make_segs(const SegT<TB>* segs, int nseg, int& total) {
   if (nseg > 3) throw Error(SVDS_ERR_ARG, "at most 3 segments");
-  Segs3 s{};
+  Segs3T<TB> s{};
   int n[3] = {0, 0, 0};
   for (int i = 0; i < 3; ++i) {
     s.p[i] = i < nseg ? segs[i].p : nullptr;
@@ -157,21 +161,22 @@ static Segs3 make_segs(const Seg* segs, int nseg, int& total) {
   return s;
 }
 
-template <int B>
-static void tsgemm_b(const Segs3& sg, int total, int64_t N, const double* T, int64_t ldt,
+template <int B, typename TB>
+static void tsgemm_b(const Segs3T<TB>& sg, int total, int64_t N, const double* T, int64_t ldt,
                      double* partial, double* C, hipStream_t s) {
   // several 256-row chunks per workgroup amortise the final wave reductions
   int nb = std::min(reduce_blocks(N), 512);
   dim3 grid(nb, (total + 4 * kCPW - 1) / (4 * kCPW));
-  k_tsgemm_tn<B><<<grid, kThreads, 0, s>>>(sg, total, N, T, ldt, partial);
+  k_tsgemm_tn<B, TB><<<grid, kThreads, 0, s>>>(sg, total, N, T, ldt, partial);
   SVDS_LAUNCH_CHECK();
   reduce_partials(partial, nb, total * B, C, s);
 }
 
-void tsgemm_tn(const Seg* segs, int nseg, int64_t N, const double* T, int64_t ldt, int b,
+template <typename TB>
+void tsgemm_tn(const SegT<TB>* segs, int nseg, int64_t N, const double* T, int64_t ldt, int b,
                double* partial, double* C, hipStream_t s) {
   int total = 0;
-  Segs3 sg = make_segs(segs, nseg, total);
+  Segs3T<TB> sg = make_segs(segs, nseg, total);
   if (total == 0) return;
   if (total > kMaxSegCols) throw Error(SVDS_ERR_ARG, "projection too wide");
   switch (b) {
@@ -186,12 +191,16 @@ void tsgemm_tn(const Seg* segs, int nseg, int64_t N, const double* T, int64_t ld
     default: throw Error(SVDS_ERR_ARG, "tsgemm: b must be 1..8");
   }
 }
+template void tsgemm_tn<double>(const SegT<double>*, int, int64_t, const double*, int64_t, int,
+                                double*, double*, hipStream_t);
+template void tsgemm_tn<float>(const SegT<float>*, int, int64_t, const double*, int64_t, int,
+                               double*, double*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // T -= [segs] C      (C: total x b, column-major)
 // ---------------------------------------------------------------------------
-template <int B>
-__global__ __launch_bounds__(kThreads) void k_ts_update(Segs3 segs, int total, int64_t N,
+template <int B, typename TB>
+__global__ __launch_bounds__(kThreads) void k_ts_update(Segs3T<TB> segs, int total, int64_t N,
                                                         const double* __restrict__ C, int ldc,
                                                         double* __restrict__ T, int64_t ldt) {
   __shared__ double cs[kMaxSegCols * B];
@@ -207,7 +216,7 @@ __global__ __launch_bounds__(kThreads) void k_ts_update(Segs3 segs, int total, i
 #pragma unroll
     for (int c = 0; c < B; ++c) t[c] = T[i + c * ldt];
     for (int j = 0; j < total; ++j) {
-      const double q = seg_col(segs, j)[i];
+      const double q = (double)seg_col(segs, j)[i];
 #pragma unroll
       for (int c = 0; c < B; ++c) t[c] = fma(-q, cs[j * B + c], t[c]);
     }
@@ -216,32 +225,38 @@ __global__ __launch_bounds__(kThreads) void k_ts_update(Segs3 segs, int total, i
   }
 }
 
-void ts_update(const Seg* segs, int nseg, int64_t N, const double* C, int ldc, double* T,
+template <typename TB>
+void ts_update(const SegT<TB>* segs, int nseg, int64_t N, const double* C, int ldc, double* T,
                int64_t ldt, int b, hipStream_t s) {
   int total = 0;
-  Segs3 sg = make_segs(segs, nseg, total);
+  Segs3T<TB> sg = make_segs(segs, nseg, total);
   if (total == 0) return;
   if (total > kMaxSegCols) throw Error(SVDS_ERR_ARG, "update too wide");
   int nb = reduce_blocks(N);
   switch (b) {
 #define CASE(BB) \
-  case BB: k_ts_update<BB><<<nb, kThreads, 0, s>>>(sg, total, N, C, ldc, T, ldt); break;
+  case BB: k_ts_update<BB, TB><<<nb, kThreads, 0, s>>>(sg, total, N, C, ldc, T, ldt); break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
     default: throw Error(SVDS_ERR_ARG, "ts_update: b must be 1..8");
   }
   SVDS_LAUNCH_CHECK();
 }
+template void ts_update<double>(const SegT<double>*, int, int64_t, const double*, int, double*,
+                                int64_t, int, hipStream_t);
+template void ts_update<float>(const SegT<float>*, int, int64_t, const double*, int, double*,
+                               int64_t, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Out = Q Y   (restart V <- V Y, W <- W Y, Q <- Q Q~, locking x = V y)
 // ---------------------------------------------------------------------------
 constexpr int kOC = 24;
 
-__global__ __launch_bounds__(kThreads) void k_gemm_nn(const double* __restrict__ Q, int64_t ldq,
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kThreads) void k_gemm_nn(const TI* __restrict__ Q, int64_t ldq,
                                                       int nq, int64_t N,
                                                       const double* __restrict__ Y, int64_t ldy,
-                                                      int nout, double* __restrict__ Out,
+                                                      int nout, TO* __restrict__ Out,
                                                       int64_t ldo) {
   __shared__ double ys[kMaxBasis * kOC];
   const int o0 = blockIdx.y * kOC;
@@ -258,24 +273,31 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nn(const double* __restrict__
 #pragma unroll
     for (int o = 0; o < kOC; ++o) acc[o] = 0.0;
     for (int j = 0; j < nq; ++j) {
-      const double q = Q[i + (int64_t)j * ldq];
+      const double q = (double)Q[i + (int64_t)j * ldq];
 #pragma unroll
       for (int o = 0; o < kOC; ++o) acc[o] = fma(q, ys[j * kOC + o], acc[o]);
     }
 #pragma unroll
     for (int o = 0; o < kOC; ++o)
-      if (o < no) Out[i + (int64_t)(o0 + o) * ldo] = acc[o];
+      if (o < no) Out[i + (int64_t)(o0 + o) * ldo] = (TO)acc[o];
   }
 }
 
-void ts_gemm_nn(const double* Q, int64_t ldq, int nq, int64_t N, const double* Y, int64_t ldy,
-                int nout, double* Out, int64_t ldo, hipStream_t s) {
+template <typename TI, typename TO>
+void ts_gemm_nn(const TI* Q, int64_t ldq, int nq, int64_t N, const double* Y, int64_t ldy,
+                int nout, TO* Out, int64_t ldo, hipStream_t s) {
   if (nout <= 0 || N == 0) return;
   if (nq > kMaxBasis) throw Error(SVDS_ERR_ARG, "gemm: inner dimension too large");
   dim3 grid(reduce_blocks(N), (nout + kOC - 1) / kOC);
-  k_gemm_nn<<<grid, kThreads, 0, s>>>(Q, ldq, nq, N, Y, ldy, nout, Out, ldo);
+  k_gemm_nn<TI, TO><<<grid, kThreads, 0, s>>>(Q, ldq, nq, N, Y, ldy, nout, Out, ldo);
   SVDS_LAUNCH_CHECK();
 }
+template void ts_gemm_nn<double, double>(const double*, int64_t, int, int64_t, const double*,
+                                         int64_t, int, double*, int64_t, hipStream_t);
+template void ts_gemm_nn<float, float>(const float*, int64_t, int, int64_t, const double*,
+                                       int64_t, int, float*, int64_t, hipStream_t);
+template void ts_gemm_nn<float, double>(const float*, int64_t, int, int64_t, const double*,
+                                        int64_t, int, double*, int64_t, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // T <- T Rinv (upper triangular b x b, column-major), optional row-major copy
@@ -328,9 +350,9 @@ void ts_scale(double* T, int64_t ldt, int64_t N, int b, const double* Rinv, doub
 // with lo = rows < nsplit (the v-half on B), hi = the rest (the u-half).
 // One pass over V and W (the "special kernels" of Section 3.3).
 // ---------------------------------------------------------------------------
-template <int NCC, int NS>
+template <int NCC, int NS, typename TB>
 __global__ __launch_bounds__(kThreads) void k_residual(
-    const double* __restrict__ V, const double* __restrict__ W, int64_t ld, int64_t N,
+    const TB* __restrict__ V, const TB* __restrict__ W, int64_t ld, int64_t N,
     int64_t nsplit, int g, const double* __restrict__ Y, int64_t ldy,
     const double* __restrict__ theta, int nc, double* __restrict__ R, int64_t ldr,
     double* __restrict__ partial) {
@@ -355,8 +377,8 @@ __global__ __launch_bounds__(kThreads) void k_residual(
 #pragma unroll
     for (int c = 0; c < NCC; ++c) x[c] = w[c] = 0.0;
     for (int j = 0; j < g; ++j) {
-      const double v = V[i + (int64_t)j * ld];
-      const double ww = W[i + (int64_t)j * ld];
+      const double v = (double)V[i + (int64_t)j * ld];
+      const double ww = (double)W[i + (int64_t)j * ld];
 #pragma unroll
       for (int c = 0; c < NCC; ++c) {
         x[c] = fma(v, ys[j * NCC + c], x[c]);
@@ -400,7 +422,8 @@ __global__ __launch_bounds__(kThreads) void k_residual(
 
 // nsplit >= N: one sum per candidate (||r||^2 in sums[c]); otherwise the six
 // sums of the two halves in sums[q*nc + c]
-void ts_residual(const double* V, const double* W, int64_t ld, int64_t N, int64_t nsplit, int g,
+template <typename TB>
+void ts_residual(const TB* V, const TB* W, int64_t ld, int64_t N, int64_t nsplit, int g,
                  const double* Y, int64_t ldy, const double* theta, int nc, double* R,
                  int64_t ldr, double* partial, double* sums, hipStream_t s) {
   if (g > kMaxBasis) throw Error(SVDS_ERR_ARG, "residual: basis too large");
@@ -408,19 +431,25 @@ void ts_residual(const double* V, const double* W, int64_t ld, int64_t N, int64_
   if (nsplit >= N) {
     constexpr int NCC = 16;
     dim3 grid(nb, (nc + NCC - 1) / NCC);
-    k_residual<NCC, 1><<<grid, kThreads, 0, s>>>(V, W, ld, N, nsplit, g, Y, ldy, theta, nc, R,
-                                                  ldr, partial);
+    k_residual<NCC, 1, TB><<<grid, kThreads, 0, s>>>(V, W, ld, N, nsplit, g, Y, ldy, theta, nc,
+                                                      R, ldr, partial);
     SVDS_LAUNCH_CHECK();
     reduce_partials(partial, nb, nc, sums, s);
   } else {
     constexpr int NCC = 8;
     dim3 grid(nb, (nc + NCC - 1) / NCC);
-    k_residual<NCC, 6><<<grid, kThreads, 0, s>>>(V, W, ld, N, nsplit, g, Y, ldy, theta, nc, R,
-                                                  ldr, partial);
+    k_residual<NCC, 6, TB><<<grid, kThreads, 0, s>>>(V, W, ld, N, nsplit, g, Y, ldy, theta, nc,
+                                                      R, ldr, partial);
     SVDS_LAUNCH_CHECK();
     reduce_partials(partial, nb, 6 * nc, sums, s);
   }
 }
+template void ts_residual<double>(const double*, const double*, int64_t, int64_t, int64_t, int,
+                                  const double*, int64_t, const double*, int, double*, int64_t,
+                                  double*, double*, hipStream_t);
+template void ts_residual<float>(const float*, const float*, int64_t, int64_t, int64_t, int,
+                                 const double*, int64_t, const double*, int, double*, int64_t,
+                                 double*, double*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // small helpers: pack / unpack between column-major and row-major blocks,
@@ -503,6 +532,50 @@ __global__ void k_copy_cols(const double* __restrict__ A, int64_t lda, int64_t N
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; i < N; i += stride)
     for (int c = 0; c < b; ++c) Bm[i + c * ldb] = A[i + c * lda];
+}
+
+template <typename TI, typename TO>
+__global__ void k_copy_cols_cvt(const TI* __restrict__ A, int64_t lda, int64_t N, int b,
+                                TO* __restrict__ Bm, int64_t ldb, TO* __restrict__ compact) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < N; i += stride)
+    for (int c = 0; c < b; ++c) {
+      const TO v = (TO)A[i + c * lda];
+      if (Bm) Bm[i + c * ldb] = v;
+      if (compact) compact[i * b + c] = v;
+    }
+}
+
+template <typename TI, typename TO>
+void copy_cols_cvt(const TI* A, int64_t lda, int64_t N, int b, TO* B, int64_t ldb, TO* compact,
+                   hipStream_t s) {
+  int blocks = (int)std::min<int64_t>(8192, (N + 255) / 256);
+  if (blocks < 1 || b < 1) return;
+  k_copy_cols_cvt<TI, TO><<<blocks, 256, 0, s>>>(A, lda, N, b, B, ldb, compact);
+  SVDS_LAUNCH_CHECK();
+}
+template void copy_cols_cvt<double, float>(const double*, int64_t, int64_t, int, float*, int64_t,
+                                           float*, hipStream_t);
+template void copy_cols_cvt<float, double>(const float*, int64_t, int64_t, int, double*, int64_t,
+                                           double*, hipStream_t);
+template void copy_cols_cvt<float, float>(const float*, int64_t, int64_t, int, float*, int64_t,
+                                          float*, hipStream_t);
+
+__global__ void k_unpack_f32(const float* __restrict__ in, int64_t N, int b, float* __restrict__ A,
+                             int64_t lda) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < N; i += stride)
+    for (int c = 0; c < b; ++c) A[i + c * lda] = in[i * b + c];
+}
+
+void unpack_rows_f32(const float* compact, int64_t N, int b, float* A, int64_t lda,
+                     hipStream_t s) {
+  int blocks = (int)std::min<int64_t>(8192, (N + 255) / 256);
+  if (blocks < 1) return;
+  k_unpack_f32<<<blocks, 256, 0, s>>>(compact, N, b, A, lda);
+  SVDS_LAUNCH_CHECK();
 }
 
 void copy_cols(const double* A, int64_t lda, int64_t N, int b, double* B, int64_t ldb,

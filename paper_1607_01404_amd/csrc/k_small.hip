@@ -446,18 +446,17 @@ void small_extract(Small* d, int gc, int descending, int refined, hipStream_t s)
 // collapsed during projection against the pre-projection norms stored as the
 // last nb rows of C0), which = 2 writes R2/R2inv.
 // ---------------------------------------------------------------------------
-__global__ void k_chol(Small* d, int nb, int which, int total) {
+__global__ void k_chol(Small* d, int nb, int which, const double* G0, int ldg0) {
   __shared__ double G[kMaxBlock * kMaxBlock], g0[kMaxBlock];
   __shared__ double R[kMaxBlock * kMaxBlock], Ri[kMaxBlock * kMaxBlock];
   __shared__ int sbad;
   const int t = threadIdx.x;
-  const int ld0 = total + nb;
   if (t < nb * nb) {
     G[t] = d->G[t];
     R[t] = 0.0;
     Ri[t] = 0.0;
   }
-  if (t < nb) g0[t] = (which == 1) ? d->C0[(int64_t)t * ld0 + total + t] : 0.0;
+  if (t < nb) g0[t] = (which == 1) ? G0[(int64_t)t * ldg0 + t] : 0.0;
   __syncthreads();
   if (t == 0) {
     int bad = 0;
@@ -501,8 +500,8 @@ __global__ void k_chol(Small* d, int nb, int which, int total) {
   if (t == 0 && sbad) d->bad |= sbad;
 }
 
-void small_chol(Small* d, int nb, int which, int total, hipStream_t s) {
-  k_chol<<<1, 64, 0, s>>>(d, nb, which, total);
+void small_chol(Small* d, int nb, int which, const double* G0, int ldg0, hipStream_t s) {
+  k_chol<<<1, 64, 0, s>>>(d, nb, which, G0, ldg0);
   SVDS_LAUNCH_CHECK();
 }
 
@@ -603,7 +602,7 @@ __global__ __launch_bounds__(kT) void k_control(Small* d, CtlParams P) {
       if (P.stage == 1) {
         const double thr = fmax(sqrt(fabs(th_s[c]) * nop) * P.tol, P.eps * nop);
         conv[c] = rn[c] <= thr;
-        const bool pc = !conv[c] && stall_s[c] >= kStallRestarts && rn[c] <= kFloorGate * P.eps * nop;
+        const bool pc = !conv[c] && stall_s[c] >= kStallRestarts && rn[c] <= P.gate * nop;
         done[c] = conv[c] || pc;
         npc += pc;
       } else {

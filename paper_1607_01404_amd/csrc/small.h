@@ -55,6 +55,7 @@ struct Small {
   double C0[(256 + kMaxBlock) * kMaxBlock];  // orthogonalisation coefficients, pass 1
   double C1[256 * kMaxBlock];                // pass 2
   double G[kMaxBlock * kMaxBlock];           // Gram of the block
+  double G0[kMaxBlock * kMaxBlock];          // Gram before projection (FP32 bases)
   double R1[kMaxBlock * kMaxBlock], R1inv[kMaxBlock * kMaxBlock];
   double R2[kMaxBlock * kMaxBlock], R2inv[kMaxBlock * kMaxBlock];
   double sums[6 * (kKmax + 8)];              // residual sums
@@ -79,6 +80,7 @@ struct CtlParams {
   int since_reset, floor_resets, budget_hit;
   int refined;
   double tol, normA, eps;
+  double gate;      // stalled pairs count as at the floor below gate * ||Op||
 };
 
 void small_eig(int g, const double* H, int ldh, int descending, double* theta, double* Y, int ldy,
@@ -87,7 +89,9 @@ void small_svd(int g, const double* R, int ldr, double* s, double* Y, int ldy, d
                int ldav, hipStream_t st);
 void small_h_append(Small* d, int gc, int nb, hipStream_t s);
 void small_extract(Small* d, int gc, int descending, int refined, hipStream_t s);
-void small_chol(Small* d, int nb, int which, int ncheck, hipStream_t s);
+// which = 1: also test columns that collapsed during projection against the
+// pre-projection Gram diagonal G0[j*ldg0 + j]
+void small_chol(Small* d, int nb, int which, const double* G0, int ldg0, hipStream_t s);
 void small_rr_append(Small* d, int gc, int nb, int total, hipStream_t s);
 void small_control(Small* d, const CtlParams& p, hipStream_t s);
 void small_rtr_accumulate(const double* C0, int ldc0, const double* C1, int total, int nb,

@@ -222,3 +222,34 @@ def test_rank_deficient_breakdown_repair(P):
     assert st["breakdowns"] > 0, st
     assert np.max(np.abs(sig.cpu().numpy() - [3.0, 2.0, 1.0])) < 1e-12
     assert float(rn.max()) <= 3e-10
+
+
+@pytest.mark.parametrize("target", ["largest", "smallest"])
+def test_mixed_precision_config1(P, target):
+    """Mixed stage 1 (FP32 basis and SpMM, BF16 MFMA projections), FP64
+    stage 2: same triplets as the FP64 oracle."""
+    A = synth.config1()
+    normA = float(np.linalg.norm(A.toarray(), 2))
+    _say("mixed config1", target)
+    sig, U, V, rn, st = P.svds(A, 5, target, 1e-10, max_basis_size=15, min_restart_size=6,
+                               norm_A=normA, seed=11, precision=P.MIXED)
+    ref, _, _, _, _ = oracle.svds(A, 5, target, 1e-10, max_basis=15, min_restart=6, norm_A=normA,
+                                  seed=11)
+    assert st["converged"], st
+    _compare(A, sig, U, V, rn, st, ref, 1e-10, normA)
+
+
+def test_mixed_precision_powerlaw_largest(P):
+    """Power-law rows (mean 20, max 2000, exponent 2.1) at 20000 x 10000, k = 20
+    largest, block 8: mixed and FP64 GPU results against the FP64 oracle."""
+    A = synth.config3(m=20000, n=10000)
+    normA = float(np.linalg.norm(A.toarray(), 2)) if A.shape[1] <= 4000 else None
+    ref, _, _, _, sref = oracle.svds(A, 20, "largest", 1e-10, block=8, max_basis=35,
+                                     min_restart=14, seed=3)
+    normA = sref["norm_A_used"]
+    for prec in (P.FP64, P.MIXED):
+        _say("powerlaw 20000x10000 k=20 largest b=8 precision", prec)
+        sig, U, V, rn, st = P.svds(A, 20, "largest", 1e-10, block_size=8, max_basis_size=35,
+                                   min_restart_size=14, seed=3, norm_A=normA, precision=prec)
+        assert st["converged"], st
+        _compare(A, sig, U, V, rn, st, ref, 1e-10, normA)
