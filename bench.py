@@ -31,6 +31,12 @@ WORKLOADS = {
              "k=10 smallest, block 4, basis 35, restart 14, tol 1e-10, Jacobi preconditioner",
         k=10, target="smallest", opts=dict(block_size=4, max_basis_size=35, min_restart_size=14,
                                            precond=1, seed=2002)),
+    "powerlaw_2e6x1e6_k20_largest": dict(
+        gen=lambda: __import__("synth").config3(),
+        desc="2,000,000 x 1,000,000, power-law rows (mean 20, max 2000, exponent 2.1), N(0,1); "
+             "k=20 largest, block 8, basis 35, restart 14, tol 1e-10",
+        k=20, target="largest", opts=dict(block_size=8, max_basis_size=35, min_restart_size=14,
+                                          seed=2003)),
     "random_2000x1000_k5_largest": dict(
         gen=lambda: __import__("synth").config1(),
         desc="2000 x 1000, 10 nnz/row uniform, N(0,1); k=5 largest, block 1, basis 15, tol 1e-10",
@@ -66,6 +72,37 @@ def cpu_baseline(A, w, gpu_matvecs, seconds):
     return {"value": value, "unit": "s", "cores": cores, "kind": "oracle", "sample": sample}
 
 
+def mixed_comparison(P, torch):
+    """FP64 and mixed-precision solves of the power-law workload (k = 20
+    largest): wall time of each and the difference of their results."""
+    import numpy as np
+    w = WORKLOADS["powerlaw_2e6x1e6_k20_largest"]
+    log("generating power-law workload")
+    A = w["gen"]()
+    ip, ix, dv = P._lib.to_device(A)
+    m, n = A.shape
+    out = {"workload": w["desc"], "nnz": int(A.nnz)}
+    sigs = {}
+    for name, prec in (("fp64", P.FP64), ("mixed", P.MIXED)):
+        opts = dict(w["opts"], precision=prec, profile=1)
+        P.solve(ip, ix, dv, m, n, w["k"], w["target"], 1e-10, **opts)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sig, U, V, rn, st = P.solve(ip, ix, dv, m, n, w["k"], w["target"], 1e-10, **opts)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        sigs[name] = sig.cpu().numpy()
+        out[name] = {"seconds": el, "converged": bool(st["converged"]),
+                     "max_rnorm_over_normA": float(rn.max()) / st["norm_A_used"],
+                     "matvecs": st["matvecs"], "iters": st["iters"], "stage_exit": st["stage_exit"],
+                     "stage_seconds": st["seconds"],
+                     "spmm_GBps": st["spmm_bytes"] / max(st["spmm_seconds"], 1e-12) / 1e9}
+        log(f"{name}: {el:.3f} s {st['iters']} {st['matvecs']}")
+    out["max_rel_sigma_diff"] = float(np.max(np.abs(sigs["mixed"] - sigs["fp64"]) / sigs["fp64"]))
+    out["speedup_mixed_over_fp64"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +111,8 @@ def main():
     ap.add_argument("--workload", default="banded_1e6x5e5_k10_smallest", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the mixed-precision comparison on the power-law workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -156,6 +195,8 @@ def main():
             "spmm_share_of_solve": ssec / el,
         },
     }
+    if not args.no_extras:
+        res["mixed_precision"] = mixed_comparison(P, torch)
     if not args.no_cpu:
         gpu_mv = int(sum(st["matvecs"]))
         log("cpu baseline (oracle) ...")
