@@ -100,6 +100,11 @@ typedef struct svds_opts {
   int print_level;        /* 0 silent .. 5 per-iteration trace on stderr    */
   int profile;            /* 1: time the sparse products with HIP events on */
                           /* `stream` and report them in svds_stats         */
+  int autotune;           /* 1 (default): on the first solve of a prepared  */
+                          /* matrix, time the SpMM launch shapes (row bins  */
+                          /* or one launch with 1..64 lanes per row) for    */
+                          /* the block width and keep the fastest; 0: use   */
+                          /* the row-length rule of thumb                   */
 } svds_opts;
 
 /* ---- statistics (host struct, filled by svds_solve) ---------------------- */
@@ -166,6 +171,21 @@ int svds_solve(const svds_csr* A, int k, int target, double tol, const svds_opts
 int svds_solve_prepared(const svds_matrix* h, int k, int target, double tol,
                         const svds_opts* opts, double* sigma, double* U, int64_t ldu,
                         double* V, int64_t ldv, double* rnorm, svds_stats* stats, void* stream);
+
+/* ---- batched solve --------------------------------------------------------- */
+/* nprob independent problems A[i] with the same k, target, tol and options;
+ * outputs per problem as for svds_solve (sigma[i], U[i] with ldu[i], V[i] with
+ * ldv[i], rnorm[i]; stats may be NULL or an array of nprob).  The problems are
+ * distributed over `nworkers` (0 -> min(nprob, 16)) host workers, each driving
+ * its own HIP stream at default priority, so that the small per-problem
+ * kernels of different problems overlap on the GPU; the caller's stream is
+ * made to wait for all of them before the call returns.  Returns the worst
+ * status over the problems (an error code if any failed, else
+ * SVDS_NOT_CONVERGED if any ran out of budget, else SVDS_OK). */
+int svds_solve_batched(int nprob, const svds_csr* A, int k, int target, double tol,
+                       const svds_opts* opts, double* const* sigma, double* const* U,
+                       const int64_t* ldu, double* const* V, const int64_t* ldv,
+                       double* const* rnorm, svds_stats* stats, int nworkers, void* stream);
 
 /* ---- single steps of the iteration (used by parity tests) ----------------- */
 /* Symmetric eigenproblem of the g x g projected matrix (Section 3.3: the

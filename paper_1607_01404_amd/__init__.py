@@ -21,6 +21,7 @@ from ._lib import (  # noqa: F401
     error_string,
     Matrix,
     solve,
+    solve_batched,
     svds,
     small_eig,
     small_svd,

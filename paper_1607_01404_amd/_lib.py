@@ -31,7 +31,7 @@ class Opts(C.Structure):
                 ("max_matvecs", C.c_int64), ("norm_A", C.c_double), ("stage1_tol", C.c_double),
                 ("seed", C.c_uint64), ("precision", C.c_int), ("precond", C.c_int),
                 ("force_stage2", C.c_int), ("two_sided_cleanup", C.c_int),
-                ("print_level", C.c_int), ("profile", C.c_int)]
+                ("print_level", C.c_int), ("profile", C.c_int), ("autotune", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -80,6 +80,8 @@ def load_library():
                                i64, vp, C.POINTER(Stats), vp]
     lib.svds_solve_prepared.argtypes = [vp, i32, i32, dbl, C.POINTER(Opts), vp, vp, i64, vp,
                                         i64, vp, C.POINTER(Stats), vp]
+    lib.svds_solve_batched.argtypes = [i32, vp, i32, i32, dbl, C.POINTER(Opts), vp, vp, vp, vp,
+                                       vp, vp, vp, i32, vp]
     lib.svds_small_eig.argtypes = [i32, vp, i64, i32, vp, vp, i64, vp]
     lib.svds_small_svd.argtypes = [i32, vp, i64, vp, vp, i64, vp]
     _lib = lib
@@ -211,6 +213,46 @@ def svds(A, k, target="largest", tol=1e-10, device="cuda", **opts):
     """Convenience: upload a scipy CSR matrix and solve."""
     ip, ix, dv = to_device(A, device)
     return solve(ip, ix, dv, A.shape[0], A.shape[1], k, target, tol, **opts)
+
+
+def solve_batched(problems, k, target="largest", tol=1e-10, nworkers=0, stream=None, **opts):
+    """svds_solve_batched over a list of device CSR tuples (indptr, indices,
+    data, m, n).  Returns (status, list of (sigma, U, V, rnorm, stats))."""
+    import torch
+    n = len(problems)
+    tgt = {"largest": LARGEST, "smallest": SMALLEST}[target] if isinstance(target, str) else target
+    o = opts_init(**opts)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    csrs = (Csr * n)()
+    outs = []
+    for i, (ip, ix, dv, m, nn) in enumerate(problems):
+        csrs[i] = _csr(ip, ix, dv, int(m), int(nn))
+        outs.append((torch.empty(k, dtype=torch.float64, device=dev),
+                     torch.empty((k, int(m)), dtype=torch.float64, device=dev),
+                     torch.empty((k, int(nn)), dtype=torch.float64, device=dev),
+                     torch.empty(k, dtype=torch.float64, device=dev)))
+    P = C.c_void_p * n
+    sig = P(*[o_[0].data_ptr() for o_ in outs])
+    Up = P(*[o_[1].data_ptr() for o_ in outs])
+    Vp = P(*[o_[2].data_ptr() for o_ in outs])
+    rp = P(*[o_[3].data_ptr() for o_ in outs])
+    ldu = (C.c_int64 * n)(*[int(p[3]) for p in problems])
+    ldv = (C.c_int64 * n)(*[int(p[4]) for p in problems])
+    st = (Stats * n)()
+    rc = load_library().svds_solve_batched(n, C.cast(csrs, C.c_void_p), k, tgt, float(tol),
+                                           C.byref(o), C.cast(sig, C.c_void_p),
+                                           C.cast(Up, C.c_void_p), C.cast(ldu, C.c_void_p),
+                                           C.cast(Vp, C.c_void_p), C.cast(ldv, C.c_void_p),
+                                           C.cast(rp, C.c_void_p), C.cast(st, C.c_void_p),
+                                           int(nworkers), _stream(stream))
+    _check(rc, "solve_batched")
+    torch.cuda.synchronize()
+    res = []
+    for i, o_ in enumerate(outs):
+        d = st[i].to_dict()
+        d["converged"] = d["nconv"] >= k
+        res.append((o_[0], o_[1].t(), o_[2].t(), o_[3], d))
+    return rc, res
 
 
 def small_eig(H, descending=False, stream=None):

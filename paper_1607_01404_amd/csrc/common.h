@@ -97,8 +97,10 @@ struct Csr32 {
   float* val32 = nullptr;  // nnz, FP32 copy for the mixed-precision stage 1
   int32_t* binrows = nullptr;       // rows, grouped by bin, row order kept
   int64_t bin_off[kNumBins + 1] = {0};
-  int merged_bin = -1;  // >= 0: narrow row-length spread, one launch in this bin's
-                        // lane shape over all rows in natural order
+  int merged_bin = -1;  // >= 0: one launch over all rows in natural order with the
+                        // lane shape of that bin; -1: one launch per row-length bin
+  int heuristic_bin = -1;  // the rule-of-thumb choice made when the bins were built
+  int tuned_b = 0;         // block width the launch shape was last tuned for
 };
 
 }  // namespace svds
@@ -110,6 +112,11 @@ struct svds_matrix {
   svds::Csr32 At;                  // its transpose
   double* diagC = nullptr;         // diag(A_w^T A_w) (length A.cols)
   int device = 0;
+  // set when the arrays were allocated stream-ordered on `owner` (the
+  // internal create/solve/destroy sequence of one svds_solve call); they are
+  // then released with stream-ordered frees on the same stream
+  hipStream_t owner = nullptr;
+  bool stream_ordered = false;
 };
 
 namespace svds {
@@ -128,6 +135,10 @@ void to_fp32(const double* in, float* out, int64_t n, hipStream_t s);
 void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t s);
 void fill_random(double* X, int64_t ld, int64_t N, int ncols, uint64_t seed, uint64_t stream,
                  int col0, hipStream_t s);
+
+// SpMM launch-shape autotuner: times the candidate shapes for block width b
+// and keeps the fastest (cached per matrix signature for the process)
+void autotune_spmm(Csr32& A, int b, bool fp32, hipStream_t s);
 
 // SpMM: Y (rows x b, row-major) = A X (cols x b, row-major)
 void spmm(const Csr32& A, int b, const double* X, double* Y, hipStream_t s);

@@ -4,7 +4,9 @@
 // enqueues them on the caller's stream and reads back one small decision
 // record per iteration (the Ctl struct written by the control kernel), plus a
 // breakdown flag after each block orthogonalisation.
+#include <atomic>
 #include <chrono>
+#include <thread>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -1105,26 +1107,56 @@ int guarded(F&& f) {
   }
 }
 
-void free_csr(svds::Csr32& c) {
-  (void)hipFree(c.rp);
-  (void)hipFree(c.ci);
-  (void)hipFree(c.val);
-  (void)hipFree(c.val32);
-  (void)hipFree(c.binrows);
+// Device arrays of a prepared matrix: plain allocations for handles made by
+// svds_matrix_create, stream-ordered ones (on the call's stream) for the
+// transient handle inside svds_solve, so that concurrent solves on different
+// streams do not synchronise the device on every allocation and release.
+struct MemMode {
+  bool async;
+  hipStream_t s;
+  template <class T>
+  void alloc(T** p, size_t count) const {
+    const size_t bytes = sizeof(T) * std::max<size_t>(count, 1);
+    if (async) SVDS_HIP(hipMallocAsync((void**)p, bytes, s));
+    else SVDS_HIP(hipMalloc((void**)p, bytes));
+  }
+  void release(void* p) const {
+    if (!p) return;
+    if (async) (void)hipFreeAsync(p, s);
+    else (void)hipFree(p);
+  }
+};
+
+void free_csr(svds::Csr32& c, const MemMode& mm) {
+  mm.release(c.rp);
+  mm.release(c.ci);
+  mm.release(c.val);
+  mm.release(c.val32);
+  mm.release(c.binrows);
   c = svds::Csr32{};
 }
 
-void alloc_csr(svds::Csr32& c, int64_t rows, int64_t cols, int64_t nnz) {
+void alloc_csr(svds::Csr32& c, int64_t rows, int64_t cols, int64_t nnz, const MemMode& mm) {
   c.rows = rows;
   c.cols = cols;
   c.nnz = nnz;
-  SVDS_HIP(hipMalloc((void**)&c.rp, sizeof(int32_t) * (rows + 1)));
-  SVDS_HIP(hipMalloc((void**)&c.ci, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
-  SVDS_HIP(hipMalloc((void**)&c.val, sizeof(double) * std::max<int64_t>(nnz, 1)));
-  SVDS_HIP(hipMalloc((void**)&c.binrows, sizeof(int32_t) * std::max<int64_t>(rows, 1)));
+  mm.alloc(&c.rp, rows + 1);
+  mm.alloc(&c.ci, nnz);
+  mm.alloc(&c.val, nnz);
+  mm.alloc(&c.binrows, rows);
+  mm.alloc(&c.val32, nnz);
 }
 
-int create_matrix(const svds_csr* A, svds_matrix** out, hipStream_t s) {
+void destroy_matrix(svds_matrix* h) {
+  if (!h) return;
+  const MemMode mm{h->stream_ordered, h->owner};
+  free_csr(h->A, mm);
+  free_csr(h->At, mm);
+  mm.release(h->diagC);
+  delete h;
+}
+
+int create_matrix(const svds_csr* A, svds_matrix** out, hipStream_t s, bool stream_ordered) {
   if (!A || !out) throw Error(SVDS_ERR_ARG, "null argument");
   if (A->m <= 0 || A->n <= 0 || A->nnz < 0 || !A->rowptr || (A->nnz > 0 && (!A->colind || !A->values)))
     throw Error(SVDS_ERR_ARG, "bad sizes or pointers");
@@ -1145,6 +1177,9 @@ int create_matrix(const svds_csr* A, svds_matrix** out, hipStream_t s) {
   if (ends[0] != 0 || ends[1] != A->nnz || flag) throw Error(SVDS_ERR_CSR, "malformed CSR");
 
   auto* h = new svds_matrix();
+  const MemMode mm{stream_ordered, s};
+  h->owner = s;
+  h->stream_ordered = stream_ordered;
   try {
     SVDS_HIP(hipGetDevice(&h->device));
     h->m = A->m;
@@ -1152,8 +1187,8 @@ int create_matrix(const svds_csr* A, svds_matrix** out, hipStream_t s) {
     h->nnz = A->nnz;
     h->transposed = A->m < A->n;
     svds::Csr32 a, at;
-    alloc_csr(a, A->m, A->n, A->nnz);
-    alloc_csr(at, A->n, A->m, A->nnz);
+    alloc_csr(a, A->m, A->n, A->nnz, mm);
+    alloc_csr(at, A->n, A->m, A->nnz, mm);
     svds::copy_csr_arrays(*A, a, s);
     int32_t* cursor = nullptr;
     SVDS_HIP(hipMallocAsync((void**)&cursor, sizeof(int32_t) * (A->n + 1), s));
@@ -1162,8 +1197,6 @@ int create_matrix(const svds_csr* A, svds_matrix** out, hipStream_t s) {
     svds::build_bins(a, s);
     svds::build_bins(at, s);
     // FP32 copies of the values for the mixed-precision stage 1
-    SVDS_HIP(hipMalloc((void**)&a.val32, sizeof(float) * std::max<int64_t>(A->nnz, 1)));
-    SVDS_HIP(hipMalloc((void**)&at.val32, sizeof(float) * std::max<int64_t>(A->nnz, 1)));
     svds::to_fp32(a.val, a.val32, A->nnz, s);
     svds::to_fp32(at.val, at.val32, A->nnz, s);
     if (h->transposed) {
@@ -1173,14 +1206,11 @@ int create_matrix(const svds_csr* A, svds_matrix** out, hipStream_t s) {
       h->A = a;
       h->At = at;
     }
-    SVDS_HIP(hipMalloc((void**)&h->diagC, sizeof(double) * h->A.cols));
+    mm.alloc(&h->diagC, h->A.cols);
     svds::row_sqnorms(h->At, h->diagC, s);  // rows of A_w^T = columns of A_w
     SVDS_HIP(hipStreamSynchronize(s));
   } catch (...) {
-    free_csr(h->A);
-    free_csr(h->At);
-    (void)hipFree(h->diagC);
-    delete h;
+    destroy_matrix(h);
     throw;
   }
   *out = h;
@@ -1192,6 +1222,7 @@ svds_opts default_opts() {
   std::memset(&o, 0, sizeof(o));
   o.max_prev_retain = -1;
   o.two_sided_cleanup = 1;
+  o.autotune = 1;
   return o;
 }
 
@@ -1209,6 +1240,21 @@ int solve_prepared(const svds_matrix* h, int k, int target, double tol, const sv
   if (o.precond != SVDS_PC_NONE && o.precond != SVDS_PC_JACOBI) throw Error(SVDS_ERR_ARG, "precond");
   svds_stats local;
   svds_stats* st = stats ? stats : &local;
+  {
+    // launch shapes of the two sparse products for this block width
+    auto* mh = const_cast<svds_matrix*>(h);
+    const int b = o.block_size > 0 ? o.block_size : 1;
+    const bool fp32 = o.precision == SVDS_MIXED;
+    if (o.autotune) {
+      svds::autotune_spmm(mh->A, b, false, s);
+      svds::autotune_spmm(mh->At, b, false, s);
+      (void)fp32;
+    } else {
+      mh->A.merged_bin = mh->A.heuristic_bin;
+      mh->At.merged_bin = mh->At.heuristic_bin;
+      mh->A.tuned_b = mh->At.tuned_b = 0;
+    }
+  }
   svds::Solver solver(h, k, target, tol, o, s);
   return solver.run(sigma, U, ldu, V, ldv, rnorm, st);
 }
@@ -1237,15 +1283,11 @@ const char* svds_error_string(int code) {
 }
 
 int svds_matrix_create(const svds_csr* A, svds_matrix** out, void* stream) {
-  return guarded([&] { return create_matrix(A, out, (hipStream_t)stream); });
+  return guarded([&] { return create_matrix(A, out, (hipStream_t)stream, false); });
 }
 
 int svds_matrix_destroy(svds_matrix* h) {
-  if (!h) return SVDS_OK;
-  free_csr(h->A);
-  free_csr(h->At);
-  (void)hipFree(h->diagC);
-  delete h;
+  destroy_matrix(h);
   return SVDS_OK;
 }
 
@@ -1275,10 +1317,10 @@ int svds_solve(const svds_csr* A, int k, int target, double tol, const svds_opts
   return guarded([&] {
     const double t0 = svds::now();
     svds_matrix* h = nullptr;
-    create_matrix(A, &h, (hipStream_t)stream);
+    create_matrix(A, &h, (hipStream_t)stream, true);
     struct Guard {
       svds_matrix* h;
-      ~Guard() { svds_matrix_destroy(h); }
+      ~Guard() { destroy_matrix(h); }
     } g{h};
     const double t1 = svds::now();
     int rc = solve_prepared(h, k, target, tol, opts, sigma, U, ldu, V, ldv, rnorm, stats,
@@ -1286,6 +1328,66 @@ int svds_solve(const svds_csr* A, int k, int target, double tol, const svds_opts
     if (stats) stats->setup_seconds += t1 - t0;
     return rc;
   });
+}
+
+int svds_solve_batched(int nprob, const svds_csr* A, int k, int target, double tol,
+                       const svds_opts* opts, double* const* sigma, double* const* U,
+                       const int64_t* ldu, double* const* V, const int64_t* ldv,
+                       double* const* rnorm, svds_stats* stats, int nworkers, void* stream) {
+  if (nprob < 0 || (nprob > 0 && (!A || !sigma || !U || !ldu || !V || !ldv || !rnorm)))
+    return SVDS_ERR_ARG;
+  if (nprob == 0) return SVDS_OK;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return SVDS_ERR_HIP;
+  const int nw = std::max(1, std::min(nprob, nworkers > 0 ? nworkers : 16));
+  std::vector<int> rc(nprob, SVDS_OK);
+  std::atomic<int> next{0};
+  std::vector<hipStream_t> streams(nw, nullptr);
+  for (int w = 0; w < nw; ++w)
+    if (hipStreamCreateWithFlags(&streams[w], hipStreamNonBlocking) != hipSuccess) {
+      for (int q = 0; q < w; ++q) (void)hipStreamDestroy(streams[q]);
+      return SVDS_ERR_HIP;
+    }
+  // the problems' inputs were produced on the caller's stream
+  if (stream) {
+    hipEvent_t ready;
+    if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) == hipSuccess) {
+      (void)hipEventRecord(ready, (hipStream_t)stream);
+      for (int w = 0; w < nw; ++w) (void)hipStreamWaitEvent(streams[w], ready, 0);
+      (void)hipEventDestroy(ready);
+    }
+  }
+  auto work = [&](int w) {
+    (void)hipSetDevice(dev);
+    for (;;) {
+      const int i = next.fetch_add(1);
+      if (i >= nprob) break;
+      rc[i] = svds_solve(&A[i], k, target, tol, opts, sigma[i], U[i], ldu[i], V[i], ldv[i],
+                         rnorm[i], stats ? &stats[i] : nullptr, streams[w]);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int w = 1; w < nw; ++w) pool.emplace_back(work, w);
+  work(0);
+  for (auto& t : pool) t.join();
+  // make the caller's stream wait for every worker stream
+  for (int w = 0; w < nw; ++w) {
+    hipEvent_t done;
+    if (hipEventCreateWithFlags(&done, hipEventDisableTiming) == hipSuccess) {
+      (void)hipEventRecord(done, streams[w]);
+      if (stream) (void)hipStreamWaitEvent((hipStream_t)stream, done, 0);
+      else (void)hipEventSynchronize(done);
+      (void)hipEventDestroy(done);
+    }
+    (void)hipStreamSynchronize(streams[w]);
+    (void)hipStreamDestroy(streams[w]);
+  }
+  int worst = SVDS_OK;
+  for (int x : rc) {
+    if (x < 0 && (worst >= 0 || x < worst)) worst = x;
+    else if (worst >= 0 && x > worst) worst = x;
+  }
+  return worst;
 }
 
 int svds_small_eig(int g, const double* H, int64_t ldh, int descending, double* theta, double* Y,

@@ -294,6 +294,7 @@ void build_bins(Csr32& A, hipStream_t s) {
     while (mb < kNumBins - 2 && mean > 4.0 * (double)(1 << mb)) ++mb;
     A.merged_bin = std::max(lo, std::min(mb, hi));
   }
+  A.heuristic_bin = A.merged_bin;
   SVDS_HIP(hipFreeAsync(counts, s));
   SVDS_HIP(hipFreeAsync(offs, s));
 }

@@ -1,0 +1,100 @@
+// Autotuner for the launch shape of the sparse products.
+//
+// Candidates: one launch per row-length bin (row lists), or a single launch
+// over all rows in natural order with L = 1, 2, ..., 64 lanes per row.  Each
+// candidate is timed with HIP events on the caller's stream for the block
+// width the solve will use; the fastest is kept in the prepared matrix and in
+// a process-wide cache keyed by a matrix signature (rows, columns, mean and
+// maximum row-length bucket, block width, precision), so that matrices of the
+// same shape class skip the search.
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "common.h"
+
+namespace svds {
+
+namespace {
+using Key = std::tuple<int, int, int, int, int, int>;
+std::mutex g_mu;
+std::map<Key, int> g_cache;
+
+int log2i(int64_t x) {
+  int l = 0;
+  while ((int64_t(1) << (l + 1)) <= x) ++l;
+  return l;
+}
+
+Key signature(const Csr32& A, int b, bool fp32) {
+  int hi = 0;
+  for (int bn = 0; bn < kNumBins; ++bn)
+    if (A.bin_off[bn + 1] > A.bin_off[bn]) hi = bn;
+  const int mean_bucket = (int)std::lround(4.0 * std::log2(1.0 + (double)A.nnz / std::max<int64_t>(A.rows, 1)));
+  return Key(log2i(A.rows), log2i(A.cols), mean_bucket, hi, b, fp32 ? 1 : 0);
+}
+}  // namespace
+
+void autotune_spmm(Csr32& A, int b, bool fp32, hipStream_t s) {
+  if (A.tuned_b == b || A.rows == 0 || A.nnz == 0) return;
+  const Key key = signature(A, b, fp32);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+      A.merged_bin = it->second;
+      A.tuned_b = b;
+      return;
+    }
+  }
+  // candidate shapes: -1 (binned) and single launches with 1..64 lanes per row
+  // (only when no row needs the workgroup-per-row kernel)
+  const bool has_wg_rows = A.bin_off[kNumBins] > A.bin_off[kNumBins - 1];
+  std::vector<int> cand = {-1};
+  if (!has_wg_rows)
+    for (int bn = 0; bn < kNumBins - 1; ++bn) cand.push_back(bn);
+  const size_t es = fp32 ? sizeof(float) : sizeof(double);
+  void *X = nullptr, *Y = nullptr;
+  SVDS_HIP(hipMallocAsync(&X, es * (size_t)A.cols * b, s));
+  SVDS_HIP(hipMallocAsync(&Y, es * (size_t)A.rows * b, s));
+  SVDS_HIP(hipMemsetAsync(X, 0, es * (size_t)A.cols * b, s));
+  hipEvent_t e0, e1;
+  SVDS_HIP(hipEventCreate(&e0));
+  SVDS_HIP(hipEventCreate(&e1));
+  const int keep = A.merged_bin;
+  int best = keep;
+  float best_ms = 1e30f;
+  for (int c : cand) {
+    A.merged_bin = c;
+    auto run = [&] {
+      if (fp32) spmm_f32(A, b, (const float*)X, (float*)Y, s);
+      else spmm(A, b, (const double*)X, (double*)Y, s);
+    };
+    run();  // warm-up
+    float tmin = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      SVDS_HIP(hipEventRecord(e0, s));
+      run();
+      SVDS_HIP(hipEventRecord(e1, s));
+      SVDS_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      SVDS_HIP(hipEventElapsedTime(&ms, e0, e1));
+      tmin = std::min(tmin, ms);
+    }
+    if (tmin < best_ms) {
+      best_ms = tmin;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  SVDS_HIP(hipFreeAsync(X, s));
+  SVDS_HIP(hipFreeAsync(Y, s));
+  A.merged_bin = best;
+  A.tuned_b = b;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_cache[key] = best;
+}
+
+}  // namespace svds

@@ -253,3 +253,56 @@ def test_mixed_precision_powerlaw_largest(P):
                                    min_restart_size=14, seed=3, norm_A=normA, precision=prec)
         assert st["converged"], st
         _compare(A, sig, U, V, rn, st, ref, 1e-10, normA)
+
+
+def _batch(count, mmin=2000, mmax=6000):
+    return [synth.batched_problem(i, mmin=mmin, mmax=mmax) for i in range(count)]
+
+
+def test_batched_matches_single_solves(P):
+    """svds_solve_batched on problems of uneven sizes: every problem's result is
+    bit-identical to its own svds_solve (the kernels are deterministic and the
+    workers share nothing but the launch-shape cache, switched off here), and
+    the singular values match the oracle."""
+    import torch
+    As = _batch(6)
+    dev = [P._lib.to_device(A) + A.shape for A in As]
+    opts = dict(block_size=8, max_basis_size=35, min_restart_size=14, seed=17, autotune=0)
+    _say("batched", [A.shape for A in As], "k=4 smallest b=8 workers 3")
+    rc, res = P.solve_batched(dev, 4, "smallest", 1e-10, nworkers=3, **opts)
+    assert rc == 0, [r[4] for r in res]
+    for i, (A, d) in enumerate(zip(As, dev)):
+        _say("single", i, A.shape)
+        sig, U, V, rn, st = P.solve(*d, 4, "smallest", 1e-10, **opts)
+        assert torch.equal(sig, res[i][0]) and torch.equal(U, res[i][1]) and torch.equal(V, res[i][2])
+        assert res[i][4]["converged"] and res[i][4]["matvecs"] == st["matvecs"]
+    for i in range(2):
+        A = As[i]
+        ref = np.sort(np.linalg.svd(A.toarray(), compute_uv=False))[:4]
+        normA = res[i][4]["norm_A_used"]
+        _compare(A, *res[i][:4], res[i][4], ref, 1e-10, normA, rel=1e-9)
+
+
+def test_batched_empty_and_arguments(P):
+    _say("batched empty")
+    rc, res = P.solve_batched([], 4)
+    assert rc == 0 and res == []
+    lib = P.load_library()
+    assert lib.svds_solve_batched(-1, None, 4, 0, 1e-10, None, None, None, None, None, None,
+                                  None, None, 0, None) == -1
+
+
+def test_autotuned_launch_shapes_agree(P):
+    """The autotuner only changes launch shapes (lanes per row and binning),
+    hence the summation order of the sparse products: results with and without
+    it agree to the solve tolerance and both converge."""
+    A = synth.config3(m=20000, n=10000)
+    out = {}
+    for tune in (0, 1):
+        _say("powerlaw 20000x10000 k=10 largest b=8 autotune", tune)
+        out[tune] = P.svds(A, 10, "largest", 1e-10, block_size=8, max_basis_size=35,
+                           min_restart_size=14, seed=3, autotune=tune)
+        assert out[tune][4]["converged"]
+    normA = out[0][4]["norm_A_used"]
+    ref = out[0][0].cpu().numpy()
+    _compare(A, *out[1][:4], out[1][4], ref, 1e-10, normA)
