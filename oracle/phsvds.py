@@ -345,12 +345,14 @@ def default_params(k, target, max_basis=None, min_restart=None, block=None, prev
 # Stage 1: GD+k on C with soft locking (Algorithm 1, steps 1-8)
 # ---------------------------------------------------------------------------
 def _stage1(ops, k, target, tol, normA, g, r, b, p, seed, precond, budget, stats, rand_state,
-            trace=None):
+            trace=None, capture=None):
     n = ops.n
     g = min(g, n)
     r = min(r, max(1, g - b - p))
     normC = normA * normA
-    if precond is not None:
+    if callable(precond):
+        K = precond
+    elif precond is not None:
         d = precond.copy()
         d[d <= 0] = 1.0
         K = lambda R: R / d[:, None]
@@ -443,6 +445,13 @@ def _stage1(ops, k, target, tol, normA, g, r, b, p, seed, precond, budget, stats
             Yb = Yr.T @ Yb
             restarts += 1
             since_reset += 1
+        if (capture is not None and block and iters % capture["every"] == 0
+                and len(capture["idx"]) < capture["max"]):
+            # training pair for a learned preconditioner: residual and Ritz
+            # vector of the block's first target
+            capture["R"].append(R[:, block[0]].copy())
+            capture["X"].append(X[:, block[0]].copy())
+            capture["idx"].append(block[0])
         T = K(R[:, block]) if block else rand_next(b)
         T, _, _ = ortho_block(T, [S.V], rand_next)
         y_prev = Yb
@@ -510,11 +519,15 @@ def _stage2(ops, k, target, tol, normA, g, r, b, p, seed, precond, budget, stats
     refined = target == "smallest"
 
     if precond is not None:
-        d = precond.copy()
-        d[d <= 0] = 1.0
+        if callable(precond):
+            Kc = precond
+        else:
+            d = precond.copy()
+            d[d <= 0] = 1.0
+            Kc = lambda R: R / d[:, None]
 
         def K(R):  # pseudo-inverse composition [K A^T y_u; A K y_v] of B
-            return np.vstack([ops.At_mul(R[n:]) / d[:, None], ops.A_mul(R[:n] / d[:, None])])
+            return np.vstack([Kc(ops.At_mul(R[n:])), ops.A_mul(Kc(R[:n]))])
     else:
         K = lambda R: R
 
@@ -676,13 +689,21 @@ def _sign_normalise(U, V):
 # ---------------------------------------------------------------------------
 def svds(A, k, target="largest", tol=1e-10, *, max_basis=None, min_restart=None, block=None,
          prev_retain=None, max_matvecs=None, norm_A=None, seed=0, precond="none",
-         force_stage2=False, cleanup=True, stage1_tol=None, trace=None, time_limit=None):
+         force_stage2=False, cleanup=True, stage1_tol=None, trace=None, time_limit=None,
+         capture=None):
     """k largest or smallest singular triplets of the sparse matrix A with
     eq. (res) residual below tol*||A||.  Returns (sigma, U, V, rnorm, stats);
     U is m x k, V is n x k, both in target order with the largest-magnitude
     entry of each v positive.  ``stage1_tol`` sets the user tolerance of the
     stage-1 test separately (each stage's eigensolver parameters can be set
-    apart, Section 3.4); stage 2 and acceptance always use ``tol``."""
+    apart, Section 3.4); stage 2 and acceptance always use ``tol``.
+
+    ``precond`` is "none", "jacobi" or a callable applying a linear operator to
+    an N x c block of vectors in the space of the smaller Gram matrix (N =
+    min(m, n)).  ``capture`` = {"every": e, "max": P} collects, at every e-th
+    stage-1 iteration (at most P times), the residual, the Ritz vector and
+    the target index of the block's first target into its "R", "X" and "idx"
+    lists (training pairs for a learned preconditioner)."""
     t0 = time.perf_counter()
     if target not in ("largest", "smallest"):
         raise ValueError("target must be 'largest' or 'smallest'")
@@ -705,7 +726,10 @@ def svds(A, k, target="largest", tol=1e-10, *, max_basis=None, min_restart=None,
              "stage_exit": 1, "stage1_status": None, "norm_A_used": None, "nconv": 0,
              "seconds": [0.0, 0.0]}
     rand_state = {"count": 0}
-    pc = jacobi_diag(Aw) if precond == "jacobi" else None
+    if callable(precond):
+        pc = precond  # a linear operator on vectors of length min(m, n) (the space of C)
+    else:
+        pc = jacobi_diag(Aw) if precond == "jacobi" else None
     if norm_A is None or norm_A <= 0:
         normA = estimate_norm(ops, seed)
         ops.mv = 0
@@ -714,8 +738,12 @@ def svds(A, k, target="largest", tol=1e-10, *, max_basis=None, min_restart=None,
 
     # ---- stage 1 on C
     tol1 = tol if stage1_tol is None else float(stage1_tol)
+    if capture is not None:
+        capture.setdefault("R", [])
+        capture.setdefault("X", [])
+        capture.setdefault("idx", [])
     Xk, normC, status = _stage1(ops, k, target, tol1, normA, g, r, b, p, seed, pc, budget,
-                                stats, rand_state, trace)
+                                stats, rand_state, trace, capture)
     normA = max(normA, math.sqrt(normC))
     sig, U, V, rn = _final_rr(ops, Xk, target)
     stats["matvecs"][0] = ops.mv
