@@ -65,6 +65,9 @@ extern "C" {
                                 /* m < n); on B the composition              */
                                 /* [K A^T y_u; A K y_v] (applyPreconditioner */
                                 /* modes AtA / augmented, Section 3.4)       */
+#define SVDS_PC_LEARNED 2       /* K = the learned polynomial preconditioner */
+                                /* of opts.pc_model (svds_lpc_* below), with */
+                                /* the same composition on B                 */
 
 /* ---- CSR matrix (device arrays, caller-owned, read-only) ----------------- */
 typedef struct svds_csr {
@@ -105,6 +108,10 @@ typedef struct svds_opts {
                           /* or one launch with 1..64 lanes per row) for    */
                           /* the block width and keep the fastest; 0: use   */
                           /* the row-length rule of thumb                   */
+  int pc_degree;          /* SVDS_PC_LEARNED: polynomial degree d, 1..15;   */
+                          /* 0 -> 8                                         */
+  const float* pc_model;  /* SVDS_PC_LEARNED: device array of               */
+                          /* SVDS_LPC_NPARAMS FP32 parameters               */
 } svds_opts;
 
 /* ---- statistics (host struct, filled by svds_solve) ---------------------- */
@@ -186,6 +193,84 @@ int svds_solve_batched(int nprob, const svds_csr* A, int k, int target, double t
                        const svds_opts* opts, double* const* sigma, double* const* U,
                        const int64_t* ldu, double* const* V, const int64_t* ldv,
                        double* const* rnorm, svds_stats* stats, int nworkers, void* stream);
+
+/* ---- learned preconditioner ----------------------------------------------- */
+/* A preconditioner for the correction equation (the applyPreconditioner hook
+ * of Section 3.4) whose per-row coefficients come from a small network over
+ * local features of the operator.  For the work matrix A_w (the tall one of A
+ * and A^T, N = its column count = min(m, n)) and C = A_w^T A_w:
+ *
+ *   K(r) = D^-1/2 sum_{l=0..d} c_l (.) T_l(2M - I) D^-1/2 r,
+ *   M = D^-1/2 C D^-1/2 / rho,   D = diag(C) (zeros -> 1),
+ *   rho = max_i (D^-1/2 |A_w|^T |A_w| D^-1/2 1)_i,
+ *
+ * T_l the Chebyshev polynomials, c_l (length N) the coefficients, (.) the
+ * row-wise product.  Row i's polynomial is sum_m exp(o_{m,i}) times the
+ * Jackson-damped Chebyshev series of 1/(x + delta_m), delta_m =
+ * 10^(-5 + 5m/7), m = 0..7, hence positive on [0, 1] for any output o.  The
+ * network (parameters: W1 16x32, b1 32, W2 64x32, b2 32, W3 32x8, b3 8,
+ * row-major [in][out], in this order) reads 8 features per row:
+ *   f = [1, log d_i - mean log d, (M 1)_i, (D^-1/2|A_w|^T|A_w|D^-1/2 1)_i/rho,
+ *        column count / mean, (M^2 1)_i, 0, 0]
+ * and computes x1 = [f, agg f], h1 = gelu(x1 W1 + b1), x2 = [h1, agg h1],
+ * h2 = gelu(x2 W2 + b2), o = clip(h2 W3 + b3, -30, 30), with
+ * agg(h) = S^-1 |A_w|^T |A_w| h, S = diag(|A_w|^T |A_w| 1) (zeros -> 1),
+ * gelu(x) = x Phi(x).  The dense layers use BF16 matrix-core products with
+ * FP32 accumulation; the polynomial is applied in FP64.
+ * Training pairs come from the solver: residuals r of its stage-1 iterations
+ * (svds_collect_residuals); with e = r/|r| the pair is (C e, e) and its loss
+ * 1 - (t.e)^2/(|t|^2 |e|^2), t = K(C e).  Arrays of length N, N x 8, N x 16
+ * are row-major FP32 unless stated. */
+#define SVDS_LPC_NPARAMS 2888
+#define SVDS_LPC_MAX_DEGREE 15
+#define SVDS_LPC_CACHE_PER_ROW 192  /* floats of forward cache per row      */
+
+/* Deterministic parameters: hidden weights uniform with variance 1/fan_in
+ * from the counter generator at `seed`, biases and W3 zero, b3 = out_bias
+ * (host, 8 values; NULL -> zeros).  params: device, SVDS_LPC_NPARAMS. */
+int svds_lpc_init(float* params, uint64_t seed, const float* out_bias, void* stream);
+/* The 8 features of every row (feat: N x 8). */
+int svds_lpc_features(const svds_matrix* A, float* feat, void* stream);
+/* Forward pass: coef (N x 16; entries beyond `degree` are zero) and, if
+ * cache is not NULL, the activations the backward pass needs
+ * (SVDS_LPC_CACHE_PER_ROW * N floats). */
+int svds_lpc_forward(const svds_matrix* A, const float* params, const float* feat, int degree,
+                     float* coef, float* cache, void* stream);
+/* Backward pass: grad (SVDS_LPC_NPARAMS, overwritten) = d loss / d params for
+ * dcoef = d loss / d coef (N x 16) and the cache of the forward pass. */
+int svds_lpc_backward(const svds_matrix* A, const float* params, const float* cache, int degree,
+                      const float* dcoef, float* grad, void* stream);
+/* Mean pair loss of np pairs built from residuals R (N x np, column-major
+ * FP64, ld ldr) for the coefficients coef, and dcoef = d loss / d coef
+ * (N x 16).  loss: host. */
+int svds_lpc_loss(const svds_matrix* A, int np, const double* R, int64_t ldr, const float* coef,
+                  int degree, float* dcoef, double* loss, void* stream);
+/* T = K(R) for nb <= 8 columns (N rows, column-major FP64; T may equal R). */
+int svds_lpc_apply(const svds_matrix* A, const float* coef, int degree, int nb, const double* R,
+                   int64_t ldr, double* T, int64_t ldt, void* stream);
+/* One Adam step (Kingma and Ba 2015) on n FP32 parameters; step counts from 1. */
+int svds_lpc_adam(int n, float* params, const float* grad, float* m, float* v, int step, float lr,
+                  float beta1, float beta2, float eps, void* stream);
+
+typedef struct svds_lpc_set {
+  const svds_matrix* A;   /* training operator                              */
+  int npairs;             /* residuals captured from its solve              */
+  const double* R;        /* N x npairs, column-major FP64                  */
+  int64_t ldr;
+} svds_lpc_set;
+/* Full-batch Adam (beta 0.9/0.999, eps 1e-8, learning rate lr) on the mean
+ * over sets of each set's mean pair loss, `steps` steps, updating params in
+ * place; loss_history (host, may be NULL) receives the loss of every step. */
+int svds_lpc_train(int nsets, const svds_lpc_set* sets, int degree, int steps, float lr,
+                   float* params, double* loss_history, void* stream);
+
+/* Solve with A (as svds_solve_prepared, FP64 precision) and keep the stage-1
+ * residual of the block's first target at every `every`-th iteration, at most
+ * max_pairs of them, in R (N x max_pairs, column-major, ld ldr >= N);
+ * *npairs (host) receives the count.  The triplets are not returned. */
+int svds_collect_residuals(const svds_matrix* A, int k, int target, double tol,
+                           const svds_opts* opts, int every, int max_pairs, double* R,
+                           int64_t ldr, int* npairs, svds_stats* stats, void* stream);
 
 /* ---- single steps of the iteration (used by parity tests) ----------------- */
 /* Symmetric eigenproblem of the g x g projected matrix (Section 3.3: the

@@ -12,6 +12,8 @@ from ._lib import (  # noqa: F401
     MIXED,
     PC_NONE,
     PC_JACOBI,
+    PC_LEARNED,
+    LPC_NPARAMS,
     SvdsError,
     Opts,
     Stats,
@@ -25,4 +27,13 @@ from ._lib import (  # noqa: F401
     svds,
     small_eig,
     small_svd,
+    lpc_init,
+    lpc_features,
+    lpc_forward,
+    lpc_backward,
+    lpc_loss,
+    lpc_apply,
+    lpc_adam,
+    lpc_train,
+    collect_residuals,
 )

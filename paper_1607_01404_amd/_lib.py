@@ -8,7 +8,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 LARGEST, SMALLEST = 0, 1
 FP64, MIXED = 0, 1
-PC_NONE, PC_JACOBI = 0, 1
+PC_NONE, PC_JACOBI, PC_LEARNED = 0, 1, 2
+LPC_NPARAMS = 2888
+LPC_CACHE_PER_ROW = 192
 
 _STATUS = {0: "ok", 1: "not converged", -1: "invalid argument", -2: "malformed CSR",
            -3: "device out of memory", -4: "HIP runtime error", -5: "numerical breakdown"}
@@ -31,7 +33,8 @@ class Opts(C.Structure):
                 ("max_matvecs", C.c_int64), ("norm_A", C.c_double), ("stage1_tol", C.c_double),
                 ("seed", C.c_uint64), ("precision", C.c_int), ("precond", C.c_int),
                 ("force_stage2", C.c_int), ("two_sided_cleanup", C.c_int),
-                ("print_level", C.c_int), ("profile", C.c_int), ("autotune", C.c_int)]
+                ("print_level", C.c_int), ("profile", C.c_int), ("autotune", C.c_int),
+                ("pc_degree", C.c_int), ("pc_model", C.c_void_p)]
 
 
 class Stats(C.Structure):
@@ -82,6 +85,17 @@ def load_library():
                                         i64, vp, C.POINTER(Stats), vp]
     lib.svds_solve_batched.argtypes = [i32, vp, i32, i32, dbl, C.POINTER(Opts), vp, vp, vp, vp,
                                        vp, vp, vp, i32, vp]
+    f32 = C.c_float
+    lib.svds_lpc_init.argtypes = [vp, C.c_uint64, vp, vp]
+    lib.svds_lpc_features.argtypes = [vp, vp, vp]
+    lib.svds_lpc_forward.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+    lib.svds_lpc_backward.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+    lib.svds_lpc_loss.argtypes = [vp, i32, vp, i64, vp, i32, vp, C.POINTER(dbl), vp]
+    lib.svds_lpc_apply.argtypes = [vp, vp, i32, i32, vp, i64, vp, i64, vp]
+    lib.svds_lpc_adam.argtypes = [i32, vp, vp, vp, vp, i32, f32, f32, f32, f32, vp]
+    lib.svds_lpc_train.argtypes = [i32, vp, i32, i32, f32, vp, vp, vp]
+    lib.svds_collect_residuals.argtypes = [vp, i32, i32, dbl, C.POINTER(Opts), i32, i32, vp, i64,
+                                           C.POINTER(i32), C.POINTER(Stats), vp]
     lib.svds_small_eig.argtypes = [i32, vp, i64, i32, vp, vp, i64, vp]
     lib.svds_small_svd.argtypes = [i32, vp, i64, vp, vp, i64, vp]
     _lib = lib
@@ -104,6 +118,9 @@ def opts_init(**kw):
     for key, val in kw.items():
         if not hasattr(o, key):
             raise TypeError(f"unknown option {key}")
+        if key == "pc_model" and hasattr(val, "data_ptr"):
+            assert val.is_cuda and val.numel() == LPC_NPARAMS and str(val.dtype) == "torch.float32"
+            val = val.data_ptr()
         setattr(o, key, val)
     return o
 
@@ -283,3 +300,128 @@ def small_svd(R, stream=None):
     torch.cuda.synchronize()
     del Rcm
     return s, Yt.t()
+
+
+# ---------------------------------------------------------------------------
+# learned preconditioner
+# ---------------------------------------------------------------------------
+class LpcSet(C.Structure):
+    _fields_ = [("A", C.c_void_p), ("npairs", C.c_int), ("R", C.c_void_p), ("ldr", C.c_int64)]
+
+
+def _dev():
+    import torch
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+def lpc_init(seed=0, out_bias=None, stream=None):
+    """Initial parameters (device FP32 tensor of LPC_NPARAMS)."""
+    import torch
+    p = torch.empty(LPC_NPARAMS, dtype=torch.float32, device=_dev())
+    ob = None
+    if out_bias is not None:
+        ob = (C.c_float * 8)(*[float(x) for x in out_bias])
+    _check(load_library().svds_lpc_init(_ptr(p), int(seed), ob, _stream(stream)), "lpc_init")
+    return p
+
+
+def _n_c(M):
+    return min(M.m, M.n)
+
+
+def lpc_features(M, stream=None):
+    import torch
+    f = torch.empty((_n_c(M), 8), dtype=torch.float32, device=_dev())
+    _check(load_library().svds_lpc_features(M.handle, _ptr(f), _stream(stream)), "lpc_features")
+    return f
+
+
+def lpc_forward(M, params, feat, degree, stream=None):
+    """Returns (coef N x 16, cache)."""
+    import torch
+    N = _n_c(M)
+    coef = torch.empty((N, 16), dtype=torch.float32, device=_dev())
+    cache = torch.empty(N * LPC_CACHE_PER_ROW, dtype=torch.float32, device=_dev())
+    _check(load_library().svds_lpc_forward(M.handle, _ptr(params), _ptr(feat), int(degree),
+                                           _ptr(coef), _ptr(cache), _stream(stream)), "lpc_forward")
+    return coef, cache
+
+
+def lpc_backward(M, params, cache, degree, dcoef, stream=None):
+    import torch
+    g = torch.empty(LPC_NPARAMS, dtype=torch.float32, device=_dev())
+    _check(load_library().svds_lpc_backward(M.handle, _ptr(params), _ptr(cache), int(degree),
+                                            _ptr(dcoef), _ptr(g), _stream(stream)), "lpc_backward")
+    return g
+
+
+def _colmajor(R):
+    """(N, P) tensor -> contiguous (P, N) storage = column-major N x P."""
+    return R.t().contiguous()
+
+
+def lpc_loss(M, R, coef, degree, stream=None):
+    """Mean pair loss of the pairs built from residuals R (N x P) and
+    dloss/dcoef (N x 16)."""
+    import torch
+    Rc = _colmajor(R)
+    N, P = R.shape
+    dc = torch.empty((N, 16), dtype=torch.float32, device=_dev())
+    loss = C.c_double()
+    _check(load_library().svds_lpc_loss(M.handle, P, _ptr(Rc), N, _ptr(coef), int(degree),
+                                        _ptr(dc), C.byref(loss), _stream(stream)), "lpc_loss")
+    return loss.value, dc
+
+
+def lpc_apply(M, coef, degree, R, stream=None):
+    """T = K(R) for R (N x nb), nb <= 8."""
+    Rc = _colmajor(R)
+    N, nb = R.shape
+    T = Rc.clone()
+    _check(load_library().svds_lpc_apply(M.handle, _ptr(coef), int(degree), nb, _ptr(Rc), N,
+                                         _ptr(T), N, _stream(stream)), "lpc_apply")
+    return T.t()
+
+
+def lpc_adam(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(load_library().svds_lpc_adam(params.numel(), _ptr(params), _ptr(grad), _ptr(m), _ptr(v),
+                                        int(step), lr, beta1, beta2, eps, _stream(stream)),
+           "lpc_adam")
+
+
+def lpc_train(sets, degree, steps, lr, params, stream=None):
+    """sets: list of (Matrix, R (N x P device FP64)).  Trains params in place;
+    returns the loss of every step (numpy)."""
+    import numpy as np
+    keep = []
+    arr = (LpcSet * len(sets))()
+    for i, (M, R) in enumerate(sets):
+        Rc = _colmajor(R) if R.shape[1] > 0 else None
+        keep.append(Rc)
+        arr[i] = LpcSet(M.handle.value if hasattr(M.handle, "value") else M.handle, int(R.shape[1]),
+                        Rc.data_ptr() if Rc is not None else None, int(R.shape[0]))
+    hist = np.zeros(max(int(steps), 1), dtype=np.float64)
+    _check(load_library().svds_lpc_train(len(sets), C.cast(arr, C.c_void_p), int(degree), int(steps),
+                                         lr, _ptr(params), hist.ctypes.data_as(C.c_void_p),
+                                         _stream(stream)), "lpc_train")
+    return hist[: int(steps)]
+
+
+def collect_residuals(M, k, target="smallest", tol=1e-10, every=1, max_pairs=64, stream=None,
+                      **opts):
+    """Solve with M, keeping stage-1 residuals; returns (R (N x count), stats)."""
+    import torch
+    N = _n_c(M)
+    tgt = {"largest": LARGEST, "smallest": SMALLEST}[target] if isinstance(target, str) else target
+    o = opts_init(**opts)
+    Rc = torch.zeros((max(int(max_pairs), 1), N), dtype=torch.float64, device=_dev())
+    cnt = C.c_int()
+    st = Stats()
+    rc = load_library().svds_collect_residuals(M.handle, int(k), tgt, float(tol), C.byref(o),
+                                               int(every), int(max_pairs), _ptr(Rc), N,
+                                               C.byref(cnt), C.byref(st), _stream(stream))
+    _check(rc, "collect_residuals")
+    d = st.to_dict()
+    d["status"] = rc
+    d["converged"] = rc == 0
+    return Rc[: cnt.value].t(), d

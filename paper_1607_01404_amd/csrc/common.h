@@ -4,8 +4,12 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <new>
 #include <stdexcept>
 #include <string>
+#include <vector>
 
 #include "svds.h"
 
@@ -28,6 +32,47 @@ struct Error : public std::runtime_error {
   } while (0)
 
 #define SVDS_LAUNCH_CHECK() SVDS_HIP(hipGetLastError())
+
+// runs f and turns exceptions into status codes (no exception crosses the ABI)
+template <typename F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    if (std::getenv("SVDS_DEBUG")) std::fprintf(stderr, "[svds] error %d: %s\n", e.code, e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    return SVDS_ERR_OOM;
+  } catch (...) {
+    return SVDS_ERR_HIP;
+  }
+}
+
+// stream-ordered device allocations released together at the end of a call
+template <typename T>
+T* dalloc(size_t n, hipStream_t s) {
+  T* p = nullptr;
+  if (n == 0) n = 1;
+  SVDS_HIP(hipMallocAsync((void**)&p, sizeof(T) * n, s));
+  return p;
+}
+
+struct DeviceBuffers {
+  std::vector<void*> ptrs;
+  hipStream_t s;
+  explicit DeviceBuffers(hipStream_t st) : s(st) {}
+  template <typename T>
+  T* get(size_t n) {
+    T* p = dalloc<T>(n, s);
+    ptrs.push_back(p);
+    return p;
+  }
+  ~DeviceBuffers() {
+    for (void* p : ptrs) (void)hipFreeAsync(p, s);
+  }
+};
+
+
 
 constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kMaxBasis = 64;      // g <= 64 (small problems fit one workgroup)

@@ -5,6 +5,7 @@
 // record per iteration (the Ctl struct written by the control kernel), plus a
 // breakdown flag after each block orthogonalisation.
 #include <atomic>
+#include <memory>
 #include <chrono>
 #include <thread>
 #include <cmath>
@@ -14,6 +15,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "lpc.h"
 #include "small.h"
 
 namespace svds {
@@ -40,29 +42,6 @@ double now() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
       .count();
 }
-
-template <typename T>
-T* dalloc(size_t n, hipStream_t s) {
-  T* p = nullptr;
-  if (n == 0) n = 1;
-  SVDS_HIP(hipMallocAsync((void**)&p, sizeof(T) * n, s));
-  return p;
-}
-
-struct DeviceBuffers {
-  std::vector<void*> ptrs;
-  hipStream_t s;
-  explicit DeviceBuffers(hipStream_t st) : s(st) {}
-  template <typename T>
-  T* get(size_t n) {
-    T* p = dalloc<T>(n, s);
-    ptrs.push_back(p);
-    return p;
-  }
-  ~DeviceBuffers() {
-    for (void* p : ptrs) (void)hipFreeAsync(p, s);
-  }
-};
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
@@ -99,7 +78,31 @@ class Solver {
   int run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, double* rnorm,
           svds_stats* st);
 
+  // stage-1 residuals of the block's first target at every `every`-th
+  // iteration (training pairs of the learned preconditioner)
+  struct Capture {
+    int every = 1, max = 0, count = 0;
+    double* R = nullptr;
+    int64_t ldr = 0;
+  };
+  void set_capture(Capture* c) { cap_ = c; }
+
  private:
+  Capture* cap_ = nullptr;
+  // learned preconditioner
+  bool learned_ = false;
+  int ldeg_ = 0;
+  LpcOp lop_;
+  float* lcoef_ = nullptr;
+  LpcScratch lsc_;
+  void setup_learned();
+  // T (N_ x nb, column-major, stage 1) <- K T
+  void learned_apply(double* T, int nb) {
+    lpc_apply(lop_, lcoef_, ldeg_, nb, T, ld_, T, ld_, lsc_, s_);
+    mv_ += 2 * (int64_t)ldeg_ * nb;
+  }
+  void capture_residual(int64_t iters, const Ctl& c);
+
   // ---- configuration
   const svds_matrix* M_;
   int k_, target_;
@@ -389,6 +392,18 @@ class Solver {
   // of B with (A^T A)^-1 ~ K), or the identity
   void precond_stage2(double* T, int nb) {
     gather_precond(R_, ld_, d_->blk, nb, nullptr, N_, T, ld_, s_);
+    if (learned_) {
+      lpc_apply(lop_, lcoef_, ldeg_, nb, T, ld_, T, ld_, lsc_, s_);  // T_v <- K r_v
+      pack_rows(T, ld_, nullptr, 0.0, n_, nb, Tc_, s_);               // K r_v (n x nb)
+      pack_rows(T + n_, ld_, nullptr, 0.0, m_, nb, Yc_, s_);          // r_u (m x nb)
+      spmm(At(), nb, Yc_, Wc_, s_);                                   // A^T r_u
+      spmm(A(), nb, Tc_, Yc_, s_);                                    // A K r_v
+      unpack_rows(Wc_, n_, nb, T, ld_, s_);
+      lpc_apply(lop_, lcoef_, ldeg_, nb, T, ld_, T, ld_, lsc_, s_);  // K A^T r_u
+      unpack_rows(Yc_, m_, nb, T + n_, ld_, s_);
+      mv_ += 2 * nb + 4 * (int64_t)ldeg_ * nb;
+      return;
+    }
     if (o_.precond != SVDS_PC_JACOBI) return;
     scale_rows(T, ld_, n_, nb, dinv_, s_);                  // T_v <- K r_v
     pack_rows(T, ld_, nullptr, 0.0, n_, nb, Tc_, s_);       // K r_v (n x nb)
@@ -583,6 +598,7 @@ int Solver::stage1(double* V1, double* U1, double* sig, double* rn, double* taus
     P.gate = kFloorGate * kEps;
     Ctl c = control(P);
     trace("s1", (int)iters, c, nc);
+    if (cap_) capture_residual(iters, c);
     if (c.action == kBreakdown) {
       Seg sv{V_, gc_, ld_};
       repair_block(last_nb, c.bad, &sv, 1);
@@ -614,6 +630,7 @@ int Solver::stage1(double* V1, double* U1, double* sig, double* rn, double* taus
     } else {
       gather_precond(R_, ld_, d_->blk, nb, o_.precond == SVDS_PC_JACOBI ? dinv_ : nullptr, N_, T,
                      ld_, s_);
+      if (learned_) learned_apply(T, nb);
     }
     Seg sv{V_, gc_, ld_};
     ortho_enqueue(T, ld_, nb, &sv, 1, Tc_);
@@ -955,6 +972,7 @@ int Solver::stage1_mixed(double* V1, double* U1, double* sig, double* rn, double
     } else {
       gather_precond(R_, ld_, d_->blk, nb, o_.precond == SVDS_PC_JACOBI ? dinv_ : nullptr, N_,
                      Tb_, ld_, s_);
+      if (learned_) learned_apply(Tb_, nb);
     }
     Seg32 sv{V32_, gc_, ld_};
     ortho_enqueue(Tb_, ld_, nb, &sv, 1, (double*)nullptr);
@@ -975,6 +993,34 @@ int Solver::stage1_mixed(double* V1, double* U1, double* sig, double* rn, double
   st->seconds[0] = now() - t0;
   *status1 = status;
   return 0;
+}
+
+// coefficients of the learned preconditioner for this matrix (one forward
+// pass of the network; its activations are freed right after)
+void Solver::setup_learned() {
+  if (!o_.pc_model) throw Error(SVDS_ERR_ARG, "learned preconditioner without pc_model");
+  ldeg_ = o_.pc_degree > 0 ? o_.pc_degree : kLpcDefaultDegree;
+  if (ldeg_ > kLpcMaxDegree) throw Error(SVDS_ERR_ARG, "pc_degree out of range");
+  lpc_prepare(M_, lop_, buf_, s_);
+  lcoef_ = buf_.get<float>((size_t)n_ * kLpcCoef);
+  lpc_scratch(lop_, kMaxBlock, lsc_, buf_);
+  DeviceBuffers tmp(s_);
+  float* feat = tmp.get<float>((size_t)n_ * kLpcNF);
+  float* cache = tmp.get<float>((size_t)n_ * kLpcCacheRow);
+  float* gbuf = tmp.get<float>((size_t)m_ * kLpcHid);
+  lpc_features(lop_, feat, s_);
+  lpc_forward(lop_, o_.pc_model, feat, ldeg_, lcoef_, cache, gbuf, s_);
+  learned_ = true;
+}
+
+// enqueue a copy of R_[:, blk[0]] (blk on the device) into the capture array
+void Solver::capture_residual(int64_t iters, const Ctl& c) {
+  const bool expand = c.action != kBreakdown && c.action != kExitConverged &&
+                      c.action != kExitFloor && c.action != kExitBudget && c.action != kReset;
+  if (!expand || c.nblock <= 0 || cap_->count >= cap_->max || iters % cap_->every != 0) return;
+  gather_precond(R_, ld_, d_->blk, 1, nullptr, N_, cap_->R + (int64_t)cap_->count * cap_->ldr,
+                 cap_->ldr, s_);
+  ++cap_->count;
 }
 
 int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, double* rnorm,
@@ -1038,6 +1084,7 @@ int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, d
     for (auto& x : hd) x = x > 0 ? 1.0 / x : 1.0;
     SVDS_HIP(hipMemcpyAsync(dinv_, hd.data(), sizeof(double) * n_, hipMemcpyHostToDevice, s_));
   }
+  if (o_.precond == SVDS_PC_LEARNED) setup_learned();
   SVDS_HIP(hipMemsetAsync(d_, 0, sizeof(Small), s_));
   // ---- ||A||
   if (o_.norm_A > 0) {
@@ -1090,22 +1137,9 @@ int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, d
 // C ABI
 // ===========================================================================
 using svds::Error;
+using svds::guarded;
 
 namespace {
-
-template <typename F>
-int guarded(F&& f) {
-  try {
-    return f();
-  } catch (const Error& e) {
-    if (std::getenv("SVDS_DEBUG")) std::fprintf(stderr, "[svds] error %d: %s\n", e.code, e.what());
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    return SVDS_ERR_OOM;
-  } catch (...) {
-    return SVDS_ERR_HIP;
-  }
-}
 
 // Device arrays of a prepared matrix: plain allocations for handles made by
 // svds_matrix_create, stream-ordered ones (on the call's stream) for the
@@ -1228,7 +1262,7 @@ svds_opts default_opts() {
 
 int solve_prepared(const svds_matrix* h, int k, int target, double tol, const svds_opts* opts,
                    double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, double* rnorm,
-                   svds_stats* stats, hipStream_t s) {
+                   svds_stats* stats, hipStream_t s, svds::Solver::Capture* cap = nullptr) {
   if (!h || !sigma || !U || !V || !rnorm) throw Error(SVDS_ERR_ARG, "null argument");
   if (target != SVDS_LARGEST && target != SVDS_SMALLEST) throw Error(SVDS_ERR_ARG, "target");
   if (!(tol > 0.0 && tol < 1.0)) throw Error(SVDS_ERR_ARG, "tol must be in (0, 1)");
@@ -1237,7 +1271,10 @@ int solve_prepared(const svds_matrix* h, int k, int target, double tol, const sv
   if (ldu < h->m || ldv < h->n) throw Error(SVDS_ERR_ARG, "leading dimension too small");
   svds_opts o = opts ? *opts : default_opts();
   if (o.precision != SVDS_FP64 && o.precision != SVDS_MIXED) throw Error(SVDS_ERR_ARG, "precision");
-  if (o.precond != SVDS_PC_NONE && o.precond != SVDS_PC_JACOBI) throw Error(SVDS_ERR_ARG, "precond");
+  if (o.precond != SVDS_PC_NONE && o.precond != SVDS_PC_JACOBI && o.precond != SVDS_PC_LEARNED)
+    throw Error(SVDS_ERR_ARG, "precond");
+  if (o.precond == SVDS_PC_LEARNED && (!o.pc_model || o.pc_degree < 0 || o.pc_degree > 15))
+    throw Error(SVDS_ERR_ARG, "learned preconditioner: pc_model / pc_degree");
   svds_stats local;
   svds_stats* st = stats ? stats : &local;
   {
@@ -1256,6 +1293,10 @@ int solve_prepared(const svds_matrix* h, int k, int target, double tol, const sv
     }
   }
   svds::Solver solver(h, k, target, tol, o, s);
+  if (cap) {
+    if (o.precision != SVDS_FP64) throw Error(SVDS_ERR_ARG, "residual capture needs FP64");
+    solver.set_capture(cap);
+  }
   return solver.run(sigma, U, ldu, V, ldv, rnorm, st);
 }
 
@@ -1388,6 +1429,182 @@ int svds_solve_batched(int nprob, const svds_csr* A, int k, int target, double t
     else if (worst >= 0 && x > worst) worst = x;
   }
   return worst;
+}
+
+
+// ---- learned preconditioner ------------------------------------------------
+namespace {
+void check_degree(int degree) {
+  if (degree < 0 || degree > svds::kLpcMaxDegree) throw Error(SVDS_ERR_ARG, "degree out of range");
+}
+}  // namespace
+
+int svds_lpc_init(float* params, uint64_t seed, const float* out_bias, void* stream) {
+  return guarded([&] {
+    if (!params) throw Error(SVDS_ERR_ARG, "null params");
+    using namespace svds;
+    std::vector<float> h(kLpcNParams, 0.0f);
+    auto fill = [&](int off, int fan_in, int count, uint64_t strm) {
+      // uniform on [-sqrt(3/fan_in), sqrt(3/fan_in)): variance 1/fan_in
+      const double a = 2.0 * std::sqrt(3.0 / fan_in);
+      for (int i = 0; i < count; ++i) h[off + i] = (float)(a * counter_uniform(seed, strm, 0, i));
+    };
+    fill(kW1, 2 * kLpcNF, 2 * kLpcNF * kLpcHid, 101);
+    fill(kW2, 2 * kLpcHid, 2 * kLpcHid * kLpcHid, 102);
+    if (out_bias)
+      for (int m = 0; m < kLpcOut; ++m) h[kB3 + m] = out_bias[m];
+    hipStream_t s = (hipStream_t)stream;
+    SVDS_HIP(hipMemcpyAsync(params, h.data(), sizeof(float) * kLpcNParams, hipMemcpyHostToDevice, s));
+    SVDS_HIP(hipStreamSynchronize(s));
+    return SVDS_OK;
+  });
+}
+
+int svds_lpc_features(const svds_matrix* A, float* feat, void* stream) {
+  return guarded([&] {
+    if (!A || !feat) throw Error(SVDS_ERR_ARG, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    svds::DeviceBuffers buf(s);
+    svds::LpcOp op;
+    svds::lpc_prepare(A, op, buf, s);
+    svds::lpc_features(op, feat, s);
+    SVDS_HIP(hipStreamSynchronize(s));
+    return SVDS_OK;
+  });
+}
+
+int svds_lpc_forward(const svds_matrix* A, const float* params, const float* feat, int degree,
+                     float* coef, float* cache, void* stream) {
+  return guarded([&] {
+    if (!A || !params || !feat || !coef) throw Error(SVDS_ERR_ARG, "null argument");
+    check_degree(degree);
+    hipStream_t s = (hipStream_t)stream;
+    svds::DeviceBuffers buf(s);
+    svds::LpcOp op;
+    svds::lpc_prepare(A, op, buf, s);
+    float* c = cache ? cache : buf.get<float>((size_t)op.N * svds::kLpcCacheRow);
+    float* gbuf = buf.get<float>((size_t)op.mw * svds::kLpcHid);
+    svds::lpc_forward(op, params, feat, degree, coef, c, gbuf, s);
+    SVDS_HIP(hipStreamSynchronize(s));
+    return SVDS_OK;
+  });
+}
+
+int svds_lpc_backward(const svds_matrix* A, const float* params, const float* cache, int degree,
+                      const float* dcoef, float* grad, void* stream) {
+  return guarded([&] {
+    if (!A || !params || !cache || !dcoef || !grad) throw Error(SVDS_ERR_ARG, "null argument");
+    check_degree(degree);
+    hipStream_t s = (hipStream_t)stream;
+    svds::DeviceBuffers buf(s);
+    svds::LpcOp op;
+    svds::lpc_prepare(A, op, buf, s);
+    float* work = buf.get<float>((size_t)op.N * (svds::kLpcOut + 3 * svds::kLpcHid));
+    float* gbuf = buf.get<float>((size_t)op.mw * svds::kLpcHid);
+    float* part = buf.get<float>((size_t)svds::lpc_partial_floats(op.N));
+    svds::lpc_backward(op, params, cache, degree, dcoef, grad, false, work, gbuf, part, s);
+    SVDS_HIP(hipStreamSynchronize(s));
+    return SVDS_OK;
+  });
+}
+
+int svds_lpc_loss(const svds_matrix* A, int np, const double* R, int64_t ldr, const float* coef,
+                  int degree, float* dcoef, double* loss, void* stream) {
+  return guarded([&] {
+    if (!A || !R || !coef || !dcoef || !loss || np < 1) throw Error(SVDS_ERR_ARG, "bad argument");
+    check_degree(degree);
+    const int64_t N = A->A.cols;
+    if (ldr < N) throw Error(SVDS_ERR_ARG, "leading dimension too small");
+    hipStream_t s = (hipStream_t)stream;
+    svds::LpcSet st(A, np, R, ldr, degree, s);
+    SVDS_HIP(hipMemcpyAsync(st.coef, coef, sizeof(float) * N * svds::kLpcCoef,
+                            hipMemcpyDeviceToDevice, s));
+    svds::DeviceBuffers buf(s);
+    double* dl = buf.get<double>(1);
+    SVDS_HIP(hipMemsetAsync(dl, 0, sizeof(double), s));
+    svds::lpc_loss(st, degree, 1.0, dl, s);
+    SVDS_HIP(hipMemcpyAsync(dcoef, st.dcoef, sizeof(float) * N * svds::kLpcCoef,
+                            hipMemcpyDeviceToDevice, s));
+    SVDS_HIP(hipMemcpyAsync(loss, dl, sizeof(double), hipMemcpyDeviceToHost, s));
+    SVDS_HIP(hipStreamSynchronize(s));
+    return SVDS_OK;
+  });
+}
+
+int svds_lpc_apply(const svds_matrix* A, const float* coef, int degree, int nb, const double* R,
+                   int64_t ldr, double* T, int64_t ldt, void* stream) {
+  return guarded([&] {
+    if (!A || !coef || !R || !T || nb < 1 || nb > svds::kMaxBlock)
+      throw Error(SVDS_ERR_ARG, "bad argument");
+    check_degree(degree);
+    if (ldr < A->A.cols || ldt < A->A.cols) throw Error(SVDS_ERR_ARG, "leading dimension");
+    hipStream_t s = (hipStream_t)stream;
+    svds::DeviceBuffers buf(s);
+    svds::LpcOp op;
+    svds::lpc_prepare(A, op, buf, s);
+    svds::LpcScratch sc;
+    svds::lpc_scratch(op, nb, sc, buf);
+    svds::lpc_apply(op, coef, degree, nb, R, ldr, T, ldt, sc, s);
+    SVDS_HIP(hipStreamSynchronize(s));
+    return SVDS_OK;
+  });
+}
+
+int svds_lpc_adam(int n, float* params, const float* grad, float* m, float* v, int step, float lr,
+                  float beta1, float beta2, float eps, void* stream) {
+  return guarded([&] {
+    if (n < 0 || (n > 0 && (!params || !grad || !m || !v)) || step < 1)
+      throw Error(SVDS_ERR_ARG, "bad argument");
+    if (n == 0) return SVDS_OK;
+    svds::lpc_adam(n, params, grad, m, v, step, lr, beta1, beta2, eps, (hipStream_t)stream);
+    SVDS_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return SVDS_OK;
+  });
+}
+
+int svds_lpc_train(int nsets, const svds_lpc_set* sets, int degree, int steps, float lr,
+                   float* params, double* loss_history, void* stream) {
+  return guarded([&] {
+    if (nsets < 1 || !sets || !params || steps < 0) throw Error(SVDS_ERR_ARG, "bad argument");
+    check_degree(degree);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<std::unique_ptr<svds::LpcSet>> own;
+    std::vector<svds::LpcSet*> ptrs;
+    for (int i = 0; i < nsets; ++i) {
+      const svds_lpc_set& q = sets[i];
+      if (!q.A || q.npairs < 0 || (q.npairs > 0 && (!q.R || q.ldr < q.A->A.cols)))
+        throw Error(SVDS_ERR_ARG, "bad training set");
+      own.emplace_back(new svds::LpcSet(q.A, q.npairs, q.R, q.ldr, degree, s));
+      ptrs.push_back(own.back().get());
+    }
+    svds::lpc_train(ptrs, degree, steps, lr, params, loss_history, s);
+    return SVDS_OK;
+  });
+}
+
+int svds_collect_residuals(const svds_matrix* A, int k, int target, double tol,
+                           const svds_opts* opts, int every, int max_pairs, double* R,
+                           int64_t ldr, int* npairs, svds_stats* stats, void* stream) {
+  return guarded([&] {
+    if (!A || !R || !npairs || every < 1 || max_pairs < 0 || ldr < A->A.cols)
+      throw Error(SVDS_ERR_ARG, "bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    svds::DeviceBuffers buf(s);
+    const int kk = std::max(k, 1);
+    double* sig = buf.get<double>(kk);
+    double* rn = buf.get<double>(kk);
+    double* U = buf.get<double>((size_t)A->m * kk);
+    double* V = buf.get<double>((size_t)A->n * kk);
+    svds::Solver::Capture cap;
+    cap.every = every;
+    cap.max = max_pairs;
+    cap.R = R;
+    cap.ldr = ldr;
+    const int rc = solve_prepared(A, k, target, tol, opts, sig, U, A->m, V, A->n, rn, stats, s, &cap);
+    SVDS_HIP(hipStreamSynchronize(s));
+    *npairs = cap.count;
+    return rc;
+  });
 }
 
 int svds_small_eig(int g, const double* H, int64_t ldh, int descending, double* theta, double* Y,

@@ -58,12 +58,16 @@ def test_struct_layouts_match_header(tmp_path):
     if cc is None:
         pytest.skip("no host C compiler")
     src = tmp_path / "sz.c"
-    src.write_text('#include <stdio.h>\n#include "svds.h"\nint main(){printf("%zu %zu %zu\\n",'
-                   'sizeof(svds_opts),sizeof(svds_stats),sizeof(svds_csr));return 0;}\n')
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "svds.h"\n'
+                   'int main(){printf("%zu %zu %zu %zu %zu %d\\n",sizeof(svds_opts),'
+                   'sizeof(svds_stats),sizeof(svds_csr),sizeof(svds_lpc_set),'
+                   'offsetof(svds_opts,pc_model),SVDS_LPC_NPARAMS);return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     out = subprocess.check_output([str(exe)]).decode().split()
-    assert [int(x) for x in out] == [ctypes.sizeof(L.Opts), ctypes.sizeof(L.Stats), ctypes.sizeof(L.Csr)]
+    assert [int(x) for x in out] == [ctypes.sizeof(L.Opts), ctypes.sizeof(L.Stats),
+                                     ctypes.sizeof(L.Csr), ctypes.sizeof(L.LpcSet),
+                                     L.Opts.pc_model.offset, L.LPC_NPARAMS]
 
 
 def test_null_arguments_rejected(lib):
