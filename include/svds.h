@@ -117,7 +117,7 @@ typedef struct svds_opts {
 /* ---- statistics (host struct, filled by svds_solve) ---------------------- */
 typedef struct svds_stats {
   int nconv;              /* triplets meeting eq. (res)                     */
-  int stage_exit;         /* 1: returned after stage 1 (Algorithm 1 step 7) */
+  int stage_exit;         /* 1: returned after stage 1 (Algorithm 1)        */
   int stage1_status;      /* 0 converged, 1 attainable floor, 2 budget      */
   int pad_;
   int64_t matvecs[2];     /* columns multiplied by A or A^T per stage       */

@@ -104,7 +104,7 @@ class Operators:
         return np.asarray(self.At @ X)
 
     def C(self, X):
-        """C X = A^T (A X) on dimension n (Algorithm 1, stage 1, step 1)."""
+        """C X = A^T (A X) on dimension n (Algorithm 1, stage 1)."""
         return self.At_mul(self.A_mul(X))
 
     def B(self, X):
@@ -342,7 +342,7 @@ def default_params(k, target, max_basis=None, min_restart=None, block=None, prev
 
 
 # ---------------------------------------------------------------------------
-# Stage 1: GD+k on C with soft locking (Algorithm 1, steps 1-8)
+# Stage 1: GD+k on C with soft locking (Algorithm 1, first stage)
 # ---------------------------------------------------------------------------
 def _stage1(ops, k, target, tol, normA, g, r, b, p, seed, precond, budget, stats, rand_state,
             trace=None, capture=None):
@@ -493,11 +493,11 @@ def _final_rr(ops, Xk, target):
 
 
 # ---------------------------------------------------------------------------
-# Stage 2: GD+k on B with hard locking (Algorithm 1, steps 9-18)
+# Stage 2: GD+k on B with hard locking (Algorithm 1, second stage)
 # ---------------------------------------------------------------------------
 def _halves_residual(x, w, theta, n):
     """eq. (res) for the normalised halves of an eigenvector approximation x of
-    B with W-part w = B x and sigma = |theta| (Algorithm 1, step 16)."""
+    B with W-part w = B x and sigma = |theta| (Algorithm 1, second stage)."""
     xv, xu = x[:n], x[n:]
     a, c = np.linalg.norm(xv), np.linalg.norm(xu)
     if a == 0.0 or c == 0.0:

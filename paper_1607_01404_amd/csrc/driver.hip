@@ -538,7 +538,7 @@ void Solver::estimate_norm() {
 }
 
 // ---------------------------------------------------------------------------
-// Stage 1: GD+k on C with soft locking (Algorithm 1, steps 1-8)
+// Stage 1: GD+k on C with soft locking (Algorithm 1, first stage)
 // ---------------------------------------------------------------------------
 int Solver::stage1(double* V1, double* U1, double* sig, double* rn, double* taus, int* ok,
                    int* status1, svds_stats* st) {
@@ -639,7 +639,7 @@ int Solver::stage1(double* V1, double* U1, double* sig, double* rn, double* taus
     extract_stage();
     ++iters;
   }
-  // final Rayleigh-Ritz on A X (steps 4-5)
+  // final Rayleigh-Ritz on A X (Algorithm 1, end of the first stage)
   double* Xk = X_;  // n x k (ld ld_)
   ts_gemm_nn(V_, ld_, gc_, N_, d_->Y, kLd, k_, Xk, ld_, s_);
   final_rr(Xk, V1, U1, sig, rn, taus, ok);
@@ -655,7 +655,7 @@ int Solver::stage1(double* V1, double* U1, double* sig, double* rn, double* taus
 
 // ---------------------------------------------------------------------------
 // Stage 2: GD+k on B with hard locking and, for the smallest values, the
-// simplified refined projection (Algorithm 1, steps 9-18)
+// simplified refined projection (Algorithm 1, second stage)
 // ---------------------------------------------------------------------------
 int Solver::stage2(const double* taus_h, double* V1, double* U1, double* sig, int* nconv,
                    svds_stats* st) {
@@ -771,7 +771,7 @@ int Solver::stage2(const double* taus_h, double* V1, double* U1, double* sig, in
                             hipMemcpyDeviceToDevice, s_));
     have += extra;
   }
-  // halves: v = x(1:n)/||.||, u = x(n+1:)/||.||, sigma = |lambda| (step 17)
+  // halves: v = x(1:n)/||.||, u = x(n+1:)/||.||, sigma = |lambda| (Algorithm 1)
   double* nv = vec_;
   double* nu = nv + kKmax;
   double* fv = nu + kKmax;
@@ -847,7 +847,7 @@ void Solver::cleanup_and_output(double* Vw, double* Uw, double* sig, double* sig
   SVDS_HIP(hipMemcpyAsync(sigma, sig, sizeof(double) * k_, hipMemcpyDeviceToDevice, s_));
 }
 
-// Rayleigh-Ritz on the returned basis through A X (Algorithm 1, steps 4-5):
+// Rayleigh-Ritz on the returned basis through A X (Algorithm 1, first stage):
 // G = (A X)^T (A X), sigma = |lambda|^(1/2), v = X z, u = A v / sigma, then
 // eq. (res) and the stage-2 shifts
 void Solver::final_rr(double* Xk, double* V1, double* U1, double* sig, double* rn, double* taus,

@@ -1,5 +1,5 @@
-// Small kernels of the stage-1 finalisation (Algorithm 1, steps 4-7), the
-// stage-2 hand-over (steps 9-15) and the final two-sided clean-up.
+// Small kernels of the stage-1 finalisation and the stage-2 hand-over
+// (Algorithm 1) and of the final two-sided clean-up.
 #include "small.h"
 
 namespace svds {

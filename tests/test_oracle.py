@@ -192,7 +192,7 @@ def test_stage2_refines_loose_stage1(target):
 
 def test_stage2_needed_for_ill_conditioned_smallest():
     """kappa ~ 2e6: the stage-1 criterion holds but eq. (res) does not, so
-    Algorithm 1 moves to stage 2 (steps 6-9)."""
+    Algorithm 1 moves to stage 2."""
     A = synth.banded_scaled(300, 150, seed=1, log_lo=-6)
     _, s, _ = _lapack(A)
     out, U, V, rn, st = oracle.svds(A, 3, "smallest", 1e-10, block=1, seed=7, precond="jacobi")
