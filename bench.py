@@ -103,6 +103,108 @@ def mixed_comparison(P, torch):
     return out
 
 
+def _gen_batched(i):
+    import synth
+    return synth.batched_problem(i)
+
+
+def batched_extra(P, torch, nprob):
+    """Config 4: nprob independent problems (rows U{5000..200000}, cols rows/2,
+    8-12 nnz/row), k = 4 smallest each, block 8, solved by svds_solve_batched
+    with 16 workers; the first 16 also one after another for comparison."""
+    import multiprocessing as mp
+    import numpy as np
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    t = time.perf_counter()
+    with mp.get_context("spawn").Pool(workers) as pool:
+        mats = pool.map(_gen_batched, range(nprob), chunksize=4)
+    gen = time.perf_counter() - t
+    log(f"batched: generated {nprob} problems in {gen:.1f} s")
+    dev = [P._lib.to_device(A) + A.shape for A in mats]
+    opts = dict(block_size=8, max_basis_size=35, min_restart_size=14, seed=2004)
+    k = 4
+    sub = dev[:16]
+    P.solve_batched(sub, k, "smallest", 1e-10, nworkers=16, **opts)  # warm-up and autotune
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for d in sub:
+        P.solve(*d, k, "smallest", 1e-10, **opts)
+    torch.cuda.synchronize()
+    serial16 = time.perf_counter() - t
+    t = time.perf_counter()
+    P.solve_batched(sub, k, "smallest", 1e-10, nworkers=16, **opts)
+    torch.cuda.synchronize()
+    batched16 = time.perf_counter() - t
+    t = time.perf_counter()
+    rc, res = P.solve_batched(dev, k, "smallest", 1e-10, nworkers=16, **opts)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    conv = sum(1 for r in res if r[4]["converged"])
+    rmax = max(float(r[3].max()) / r[4]["norm_A_used"] for r in res)
+    nnz = int(sum(A.nnz for A in mats))
+    return {"workload": f"{nprob} problems, rows U{{5000..200000}}, cols rows/2, 8-12 nnz/row, "
+                        "N(0,1); k=4 smallest, block 8, basis 35, restart 14, tol 1e-10",
+            "nnz_total": nnz, "seconds": el, "problems_per_second": nprob / el,
+            "converged": conv, "status": rc, "max_rnorm_over_normA": rmax,
+            "matvecs_total": int(sum(sum(r[4]["matvecs"]) for r in res)),
+            "stage2_problems": int(sum(1 for r in res if r[4]["stage_exit"] == 2)),
+            "first16_serial_seconds": serial16, "first16_batched_seconds": batched16,
+            "workers": 16, "generation_seconds": gen}
+
+
+def learned_extra(P, torch, full_seconds):
+    """Config 5: learned preconditioner trained on the GPU from residuals of
+    Jacobi solves on eight 32x32 coefficient fields (seeds 5001-5008),
+    evaluated against Jacobi and no preconditioning on a held-out field
+    (seed 5000) at 128x128 and at the full 1024x1024 size (budget-capped)."""
+    import numpy as np
+    import synth
+    degree = 15
+    t = time.perf_counter()
+    sets = []
+    for sd in range(5001, 5009):
+        M = P.Matrix.from_scipy(synth.config5(ng=32, seed=sd))
+        R, st = P.collect_residuals(M, 10, "smallest", 1e-10, every=4, max_pairs=64, block_size=1,
+                                    seed=1, precond=P.PC_JACOBI)
+        sets.append((M, R))
+    collect = time.perf_counter() - t
+    bias = np.full(8, -8.0)
+    bias[7] = 0.0
+    params = P.lpc_init(seed=0, out_bias=bias)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    hist = P.lpc_train(sets, degree, 200, 1e-2, params)
+    torch.cuda.synchronize()
+    train = time.perf_counter() - t
+    out = {"training": {"sets": "eight 32x32 fields (seeds 5001-5008), Jacobi solves, k=10 smallest,"
+                                " a residual every 4th stage-1 iteration, 64 per field",
+                        "collect_seconds": collect, "train_seconds": train, "steps": 200,
+                        "degree": degree, "loss_first": float(hist[0]), "loss_last": float(hist[-1])}}
+    runs = [("none", dict(precond=P.PC_NONE)), ("jacobi", dict(precond=P.PC_JACOBI)),
+            ("learned", dict(precond=P.PC_LEARNED, pc_model=params, pc_degree=degree))]
+    for label, ng, cap in (("replica_128x128", 128, 60.0), ("full_1024x1024", 1024, full_seconds)):
+        B = synth.config5(ng=ng, seed=5000)
+        MB = P.Matrix.from_scipy(B)
+        res = {"shape": list(B.shape), "nnz": int(B.nnz), "max_seconds": cap}
+        for name, kw in runs:
+            log(f"learned extra: {label} {name}")
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            sig, U, V, rn, st = MB.solve(10, "smallest", 1e-10, block_size=1, seed=1,
+                                         max_seconds=cap, **kw)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            res[name] = {"seconds": el, "converged": bool(st["converged"]), "nconv": st["nconv"],
+                         "iters": st["iters"], "matvecs": st["matvecs"],
+                         "max_rnorm_over_normA": float(rn.max()) / st["norm_A_used"],
+                         "sigma_min": float(sig[0])}
+        out[label] = res
+        MB.close()
+    for M, _ in sets:
+        M.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,7 +214,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the mixed-precision comparison on the power-law workload")
+                    help="skip the mixed-precision, batched and learned-preconditioner extras")
+    ap.add_argument("--batched", type=int, default=256, help="problems in the batched extra (0: skip)")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--full-seconds", type=float, default=20.0,
+                    help="time budget of each full-size convection-diffusion solve")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -197,6 +303,10 @@ def main():
     }
     if not args.no_extras:
         res["mixed_precision"] = mixed_comparison(P, torch)
+        if args.batched > 0:
+            res["batched"] = batched_extra(P, torch, args.batched)
+        if not args.no_learned:
+            res["learned_preconditioner"] = learned_extra(P, torch, args.full_seconds)
     if not args.no_cpu:
         gpu_mv = int(sum(st["matvecs"]))
         log("cpu baseline (oracle) ...")

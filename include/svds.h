@@ -108,6 +108,8 @@ typedef struct svds_opts {
                           /* or one launch with 1..64 lanes per row) for    */
                           /* the block width and keep the fastest; 0: use   */
                           /* the row-length rule of thumb                   */
+  double max_seconds;     /* wall-clock budget of the solve (> 0), checked  */
+                          /* once per iteration like max_matvecs; 0: none  */
   int pc_degree;          /* SVDS_PC_LEARNED: polynomial degree d, 1..15;   */
                           /* 0 -> 8                                         */
   const float* pc_model;  /* SVDS_PC_LEARNED: device array of               */

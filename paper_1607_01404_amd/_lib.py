@@ -34,7 +34,7 @@ class Opts(C.Structure):
                 ("seed", C.c_uint64), ("precision", C.c_int), ("precond", C.c_int),
                 ("force_stage2", C.c_int), ("two_sided_cleanup", C.c_int),
                 ("print_level", C.c_int), ("profile", C.c_int), ("autotune", C.c_int),
-                ("pc_degree", C.c_int), ("pc_model", C.c_void_p)]
+                ("max_seconds", C.c_double), ("pc_degree", C.c_int), ("pc_model", C.c_void_p)]
 
 
 class Stats(C.Structure):

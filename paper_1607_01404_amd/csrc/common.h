@@ -146,6 +146,8 @@ struct Csr32 {
                         // lane shape of that bin; -1: one launch per row-length bin
   int heuristic_bin = -1;  // the rule-of-thumb choice made when the bins were built
   int tuned_b = 0;         // block width the launch shape was last tuned for
+  int unroll = 1;          // nonzeros per lane per step (1, 2 or 4)
+  int heuristic_unroll = 1;
 };
 
 }  // namespace svds

@@ -114,6 +114,10 @@ class Solver {
   bool largest_;
   int g_, r_, b_, p_;
   int64_t budget_;
+  double run_t0_ = 0.0;  // start of run(), for the wall-clock budget
+  bool over_budget() const {
+    return mv_ >= budget_ || (o_.max_seconds > 0.0 && now() - run_t0_ > o_.max_seconds);
+  }
   double normA_ = 0.0;
 
   // ---- per-stage state
@@ -591,7 +595,7 @@ int Solver::stage1(double* V1, double* U1, double* sig, double* rn, double* taus
     P.nc = nc;
     P.since_reset = since_reset;
     P.floor_resets = floor_resets;
-    P.budget_hit = mv_ >= budget_;
+    P.budget_hit = over_budget() ? 1 : 0;
     P.tol = tol1_;
     P.normA = normA_;
     P.eps = kEps;
@@ -703,7 +707,7 @@ int Solver::stage2(const double* taus_h, double* V1, double* U1, double* sig, in
     P.nc = nc;
     P.nlock = nlock_;
     P.since_reset = since_reset;
-    P.budget_hit = mv_ >= budget_;
+    P.budget_hit = over_budget() ? 1 : 0;
     P.refined = refined_ ? 1 : 0;
     P.tol = tol_;
     P.normA = normA_;
@@ -936,7 +940,7 @@ int Solver::stage1_mixed(double* V1, double* U1, double* sig, double* rn, double
     P.nc = nc;
     P.since_reset = since_reset;
     P.floor_resets = floor_resets;
-    P.budget_hit = mv_ >= budget_;
+    P.budget_hit = over_budget() ? 1 : 0;
     P.tol = tol1_;
     P.normA = normA_;
     P.eps = kEpsMixed;
@@ -1027,6 +1031,7 @@ int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, d
                 svds_stats* st) {
   std::memset(st, 0, sizeof(*st));
   const double t0 = now();
+  run_t0_ = t0;
   // ---- buffers
   const int64_t Nmax = m_ + n_;
   ld_ = round_up(Nmax, 64);
@@ -1289,6 +1294,8 @@ int solve_prepared(const svds_matrix* h, int k, int target, double tol, const sv
     } else {
       mh->A.merged_bin = mh->A.heuristic_bin;
       mh->At.merged_bin = mh->At.heuristic_bin;
+      mh->A.unroll = mh->A.heuristic_unroll;
+      mh->At.unroll = mh->At.heuristic_unroll;
       mh->A.tuned_b = mh->At.tuned_b = 0;
     }
   }

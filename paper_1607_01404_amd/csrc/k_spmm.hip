@@ -3,16 +3,24 @@
 //
 // Rows are grouped into bins by length; each bin runs a kernel in which a
 // group of L lanes (L = 1 ... 64, or a whole workgroup for very long rows)
-// shares one row, each lane striding over the row's nonzeros and
-// accumulating all b columns of the row-major block X (one contiguous b-wide
-// gather per nonzero), followed by a shuffle reduction inside the group.
+// shares one row, each lane striding over the row's nonzeros (U at a time)
+// and accumulating all b columns of the row-major block X (one contiguous
+// b-wide gather per nonzero), followed by a shuffle reduction inside the
+// group.  Alternatively one launch covers all rows in natural order with one
+// lane shape (chosen by the autotuner or by the row-length rule).
 // Every row is summed by one group in a fixed order: no atomics, results are
 // bitwise reproducible.
 #include "common.h"
 
 namespace svds {
 
-template <typename TV, int B, int L>
+// L lanes per row; each lane takes U of the row's nonzeros per step (lane
+// offsets l, l+L, ..., l+(U-1)L), issuing all their index, value and
+// gathered-row loads before the multiply-adds so that U loads per lane are in
+// flight.  The summation order inside a lane is the same for every U, so the
+// result depends on L only.  After the shuffle reduction lanes 0..B-1 of the
+// group store the row's B outputs side by side (one coalesced store).
+template <typename TV, int B, int L, int U>
 __global__ __launch_bounds__(256) void k_spmm_group(const int32_t* __restrict__ rp,
                                                     const int32_t* __restrict__ ci,
                                                     const TV* __restrict__ val,
@@ -29,12 +37,30 @@ __global__ __launch_bounds__(256) void k_spmm_group(const int32_t* __restrict__ 
     TV acc[B];
 #pragma unroll
     for (int j = 0; j < B; ++j) acc[j] = TV(0);
-    for (int32_t k = a + lane; k < e; k += L) {
-      const int32_t c = ci[k];
-      const TV v = val[k];
-      const TV* __restrict__ x = X + (int64_t)c * B;
+    for (int32_t k0 = a + lane; k0 < e; k0 += L * U) {
+      int32_t c[U];
+      TV v[U];
 #pragma unroll
-      for (int j = 0; j < B; ++j) acc[j] = fma(v, x[j], acc[j]);
+      for (int u = 0; u < U; ++u) {
+        const int32_t k = k0 + u * L;
+        const bool ok = (u == 0) || k < e;
+        c[u] = ok ? ci[k] : 0;
+        v[u] = ok ? val[k] : TV(0);
+      }
+      TV x[U][B];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const TV* __restrict__ xr = X + (int64_t)c[u] * B;
+#pragma unroll
+        for (int j = 0; j < B; ++j) x[u][j] = xr[j];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (u == 0 || k0 + u * L < e) {
+#pragma unroll
+          for (int j = 0; j < B; ++j) acc[j] = fma(v[u], x[u][j], acc[j]);
+        }
+      }
     }
     if constexpr (L > 1) {
 #pragma unroll
@@ -43,10 +69,18 @@ __global__ __launch_bounds__(256) void k_spmm_group(const int32_t* __restrict__ 
         for (int off = L / 2; off > 0; off >>= 1) acc[j] += __shfl_xor(acc[j], off, kWave);
       }
     }
-    if (lane == 0) {
-      TV* __restrict__ y = Y + (int64_t)row * B;
+    TV* __restrict__ y = Y + (int64_t)row * B;
+    if constexpr (L >= B) {
+      TV out = acc[0];
 #pragma unroll
-      for (int j = 0; j < B; ++j) y[j] = acc[j];
+      for (int j = 1; j < B; ++j)
+        if (lane == j) out = acc[j];
+      if (lane < B) y[lane] = out;
+    } else {
+      if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < B; ++j) y[j] = acc[j];
+      }
     }
   }
 }
@@ -90,9 +124,20 @@ __global__ __launch_bounds__(256) void k_spmm_wg(const int32_t* __restrict__ rp,
   }
 }
 
+template <typename TV, int B, int L>
+static void launch_group(int U, int blocks, const Csr32& A, const TV* val, const int32_t* rows,
+                         int64_t nr, const TV* X, TV* Y, hipStream_t s) {
+  switch (U) {
+    case 4: k_spmm_group<TV, B, L, 4><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, rows, nr, X, Y); break;
+    case 2: k_spmm_group<TV, B, L, 2><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, rows, nr, X, Y); break;
+    default: k_spmm_group<TV, B, L, 1><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, rows, nr, X, Y); break;
+  }
+}
+
 template <typename TV, int B>
 static void spmm_b(const Csr32& A, const TV* val, const TV* X, TV* Y, hipStream_t s) {
   const bool merged = A.merged_bin >= 0;
+  const int U = A.unroll;
   for (int bn = 0; bn < kNumBins; ++bn) {
     if (merged && bn != A.merged_bin) continue;
     int64_t r0 = merged ? 0 : A.bin_off[bn], r1 = merged ? A.rows : A.bin_off[bn + 1];
@@ -109,13 +154,13 @@ static void spmm_b(const Csr32& A, const TV* val, const TV* X, TV* Y, hipStream_
       int blocks = (int)std::min<int64_t>(need, 16384);
       if (blocks >= 64) blocks = (blocks / 8) * 8;  // whole XCD rounds for the remap
       switch (bn) {
-        case 0: k_spmm_group<TV, B, 1><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, rows, nr, X, Y); break;
-        case 1: k_spmm_group<TV, B, 2><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, rows, nr, X, Y); break;
-        case 2: k_spmm_group<TV, B, 4><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, rows, nr, X, Y); break;
-        case 3: k_spmm_group<TV, B, 8><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, rows, nr, X, Y); break;
-        case 4: k_spmm_group<TV, B, 16><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, rows, nr, X, Y); break;
-        case 5: k_spmm_group<TV, B, 32><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, rows, nr, X, Y); break;
-        default: k_spmm_group<TV, B, 64><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, rows, nr, X, Y); break;
+        case 0: launch_group<TV, B, 1>(U, blocks, A, val, rows, nr, X, Y, s); break;
+        case 1: launch_group<TV, B, 2>(U, blocks, A, val, rows, nr, X, Y, s); break;
+        case 2: launch_group<TV, B, 4>(U, blocks, A, val, rows, nr, X, Y, s); break;
+        case 3: launch_group<TV, B, 8>(U, blocks, A, val, rows, nr, X, Y, s); break;
+        case 4: launch_group<TV, B, 16>(U, blocks, A, val, rows, nr, X, Y, s); break;
+        case 5: launch_group<TV, B, 32>(U, blocks, A, val, rows, nr, X, Y, s); break;
+        default: launch_group<TV, B, 64>(U, blocks, A, val, rows, nr, X, Y, s); break;
       }
     }
     SVDS_LAUNCH_CHECK();

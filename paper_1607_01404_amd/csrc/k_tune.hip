@@ -1,13 +1,16 @@
 // Autotuner for the launch shape of the sparse products.
 //
 // Candidates: one launch per row-length bin (row lists), or a single launch
-// over all rows in natural order with L = 1, 2, ..., 64 lanes per row.  Each
+// over all rows in natural order with L = 1, 2, ..., 64 lanes per row; each
+// with 1, 2 or 4 nonzeros per lane per step.  Each
 // candidate is timed with HIP events on the caller's stream for the block
 // width the solve will use; the fastest is kept in the prepared matrix and in
 // a process-wide cache keyed by a matrix signature (rows, columns, mean and
 // maximum row-length bucket, block width, precision), so that matrices of the
 // same shape class skip the search.
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -19,7 +22,7 @@ namespace svds {
 namespace {
 using Key = std::tuple<int, int, int, int, int, int>;
 std::mutex g_mu;
-std::map<Key, int> g_cache;
+std::map<Key, std::pair<int, int>> g_cache;  // (merged bin or -1, unroll)
 
 int log2i(int64_t x) {
   int l = 0;
@@ -43,7 +46,8 @@ void autotune_spmm(Csr32& A, int b, bool fp32, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_cache.find(key);
     if (it != g_cache.end()) {
-      A.merged_bin = it->second;
+      A.merged_bin = it->second.first;
+      A.unroll = it->second.second;
       A.tuned_b = b;
       return;
     }
@@ -51,9 +55,12 @@ void autotune_spmm(Csr32& A, int b, bool fp32, hipStream_t s) {
   // candidate shapes: -1 (binned) and single launches with 1..64 lanes per row
   // (only when no row needs the workgroup-per-row kernel)
   const bool has_wg_rows = A.bin_off[kNumBins] > A.bin_off[kNumBins - 1];
-  std::vector<int> cand = {-1};
-  if (!has_wg_rows)
-    for (int bn = 0; bn < kNumBins - 1; ++bn) cand.push_back(bn);
+  std::vector<std::pair<int, int>> cand;
+  for (int u : {1, 2, 4}) {
+    cand.push_back({-1, u});
+    if (!has_wg_rows)
+      for (int bn = 0; bn < kNumBins - 1; ++bn) cand.push_back({bn, u});
+  }
   const size_t es = fp32 ? sizeof(float) : sizeof(double);
   void *X = nullptr, *Y = nullptr;
   SVDS_HIP(hipMallocAsync(&X, es * (size_t)A.cols * b, s));
@@ -62,11 +69,12 @@ void autotune_spmm(Csr32& A, int b, bool fp32, hipStream_t s) {
   hipEvent_t e0, e1;
   SVDS_HIP(hipEventCreate(&e0));
   SVDS_HIP(hipEventCreate(&e1));
-  const int keep = A.merged_bin;
-  int best = keep;
+  std::pair<int, int> best{A.merged_bin, A.unroll};
   float best_ms = 1e30f;
-  for (int c : cand) {
-    A.merged_bin = c;
+  const bool verbose = std::getenv("SVDS_DEBUG") != nullptr;
+  for (const auto& c : cand) {
+    A.merged_bin = c.first;
+    A.unroll = c.second;
     auto run = [&] {
       if (fp32) spmm_f32(A, b, (const float*)X, (float*)Y, s);
       else spmm(A, b, (const double*)X, (double*)Y, s);
@@ -82,6 +90,9 @@ void autotune_spmm(Csr32& A, int b, bool fp32, hipStream_t s) {
       SVDS_HIP(hipEventElapsedTime(&ms, e0, e1));
       tmin = std::min(tmin, ms);
     }
+    if (verbose)
+      std::fprintf(stderr, "[svds] autotune rows %lld b %d fp32 %d shape %d unroll %d: %.1f us\n",
+                   (long long)A.rows, b, fp32 ? 1 : 0, c.first, c.second, tmin * 1e3);
     if (tmin < best_ms) {
       best_ms = tmin;
       best = c;
@@ -91,7 +102,8 @@ void autotune_spmm(Csr32& A, int b, bool fp32, hipStream_t s) {
   (void)hipEventDestroy(e1);
   SVDS_HIP(hipFreeAsync(X, s));
   SVDS_HIP(hipFreeAsync(Y, s));
-  A.merged_bin = best;
+  A.merged_bin = best.first;
+  A.unroll = best.second;
   A.tuned_b = b;
   std::lock_guard<std::mutex> lk(g_mu);
   g_cache[key] = best;
