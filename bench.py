@@ -24,6 +24,22 @@ METRIC = ("time to k triplets at ‖r‖≤1e-10‖A‖ (plain vs mixed/learned)
           "SpMM HBM GB/s")
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
+# HBM bytes per SpMM launch of the default workload from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes scaled by a copy kernel (profiles/spmm_banded_1e6x5e5_b4_fp64_hbm_traffic.md),
+# valid while the kernel source is the one those counters were taken on
+SPMM_TRAFFIC = {"workload": "banded_1e6x5e5_k10_smallest", "bytes_per_launch": 244.2e6,
+                "source": "paper_1607_01404_amd/csrc/k_spmm.hip", "sha256_prefix": "cf44994ea69fed23"}
+
+
+def spmm_traffic(workload):
+    import hashlib
+    t = SPMM_TRAFFIC
+    if workload != t["workload"]:
+        return None
+    with open(os.path.join(ROOT, t["source"]), "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()[:16]
+    return t["bytes_per_launch"] if h == t["sha256_prefix"] else None
+
 WORKLOADS = {
     "banded_1e6x5e5_k10_smallest": dict(
         gen=lambda: __import__("synth").config2(),
@@ -219,7 +235,20 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--full-seconds", type=float, default=20.0,
                     help="time budget of each full-size convection-diffusion solve")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (scales the HBM byte "
+                         "counters of a profiler run) and exit")
     args = ap.parse_args()
+    if args.copy_calibration > 0:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "copies": 5}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -295,7 +324,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": spmm_traffic(args.workload),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-scaled)",
             "avg_call_us": ssec / max(calls, 1) * 1e6,
             "bytes_per_call": sbytes / max(calls, 1),
             "spmm_share_of_solve": ssec / el,
