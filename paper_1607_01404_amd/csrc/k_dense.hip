@@ -64,21 +64,22 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NA], double* sh
 // (w, w+4, ...), each lane covering 4 rows.  T is read once per chunk and the
 // basis columns once; the per-wave accumulators are reduced at the end.
 // ---------------------------------------------------------------------------
-constexpr int kCPW = 8;  // basis columns per wavefront (32 per workgroup column)
+constexpr int kCPW = 4;   // basis columns per wavefront (16 per workgroup column)
+constexpr int kTU = 8;    // 64-row groups per step: all their loads are issued first
 
 template <int B, typename TB>
 __global__ __launch_bounds__(kThreads) void k_tsgemm_tn(Segs3T<TB> segs, int total, int64_t N,
                                                         const double* __restrict__ T,
-                                                        int64_t ldt,
+                                                        int64_t ldt, int64_t chunk,
                                                         double* __restrict__ partial) {
-  __shared__ double ts[kThreads * B];
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  const int c0 = blockIdx.y * (4 * kCPW);
+  const int c0 = blockIdx.y * (4 * kCPW) + w * kCPW;
+  if (c0 >= total) return;  // the whole wavefront has no column
   const TB* qp[kCPW];
   bool ok[kCPW];
 #pragma unroll
   for (int jj = 0; jj < kCPW; ++jj) {
-    const int col = c0 + w + 4 * jj;
+    const int col = c0 + jj;
     ok[jj] = col < total;
     qp[jj] = seg_col(segs, min(col, total - 1));
   }
@@ -86,32 +87,25 @@ __global__ __launch_bounds__(kThreads) void k_tsgemm_tn(Segs3T<TB> segs, int tot
 #pragma unroll
   for (int a = 0; a < kCPW * B; ++a) acc[a] = 0.0;
   const int bid = xcd_block(blockIdx.x, gridDim.x);
-  for (int64_t base = (int64_t)bid * kThreads; base < N; base += (int64_t)gridDim.x * kThreads) {
-    __syncthreads();
-    {
-      const int64_t row = base + threadIdx.x;
+  const int64_t r0 = (int64_t)bid * chunk;
+  const int64_t r1 = (r0 + chunk < N) ? r0 + chunk : N;
+  for (int64_t base = r0; base < r1; base += kWave * kTU) {
+    double tv[kTU][B], q[kTU][kCPW];
 #pragma unroll
-      for (int c = 0; c < B; ++c) ts[threadIdx.x * B + c] = (row < N) ? T[row + c * ldt] : 0.0;
+    for (int u = 0; u < kTU; ++u) {
+      const int64_t row = base + u * kWave + lane;
+      const bool in = row < r1;
+#pragma unroll
+      for (int c = 0; c < B; ++c) tv[u][c] = in ? T[row + c * ldt] : 0.0;
+#pragma unroll
+      for (int jj = 0; jj < kCPW; ++jj) q[u][jj] = (in && ok[jj]) ? (double)qp[jj][row] : 0.0;
     }
-    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kThreads / kWave; ++i) {
-      const int r = lane + kWave * i;
-      const int64_t row = base + r;
-      if (row < N) {
-        double tv[B];
+    for (int u = 0; u < kTU; ++u)
 #pragma unroll
-        for (int c = 0; c < B; ++c) tv[c] = ts[r * B + c];
+      for (int jj = 0; jj < kCPW; ++jj)
 #pragma unroll
-        for (int jj = 0; jj < kCPW; ++jj) {
-          if (ok[jj]) {
-            const double q = (double)qp[jj][row];
-#pragma unroll
-            for (int c = 0; c < B; ++c) acc[jj * B + c] = fma(q, tv[c], acc[jj * B + c]);
-          }
-        }
-      }
-    }
+        for (int c = 0; c < B; ++c) acc[jj * B + c] = fma(q[u][jj], tv[u][c], acc[jj * B + c]);
   }
   // partial layout: [c * total + col][block]
   const int nblk = gridDim.x;
@@ -120,8 +114,7 @@ __global__ __launch_bounds__(kThreads) void k_tsgemm_tn(Segs3T<TB> segs, int tot
 #pragma unroll
     for (int c = 0; c < B; ++c) {
       const double v = wave_sum(acc[jj * B + c]);
-      if (lane == 0 && ok[jj])
-        partial[((int64_t)c * total + c0 + w + 4 * jj) * nblk + blockIdx.x] = v;
+      if (lane == 0 && ok[jj]) partial[((int64_t)c * total + c0 + jj) * nblk + blockIdx.x] = v;
     }
   }
 }
@@ -164,10 +157,17 @@ static Segs3T<TB> make_segs(const SegT<TB>* segs, int nseg, int& total) {
 template <int B, typename TB>
 static void tsgemm_b(const Segs3T<TB>& sg, int total, int64_t N, const double* T, int64_t ldt,
                      double* partial, double* C, hipStream_t s) {
-  // several 256-row chunks per workgroup amortise the final wave reductions
-  int nb = std::min(reduce_blocks(N), 512);
+  // one contiguous row range per workgroup column (several 256-row steps
+  // amortise the final wave reductions)
+  int nb = std::min(reduce_blocks(N), 256);
+  int64_t chunk = (N + nb - 1) / nb;
+  chunk = (chunk + kWave * kTU - 1) / (kWave * kTU) * (kWave * kTU);
+  nb = (int)((N + chunk - 1) / chunk);
+  if (nb >= 64 && nb % 8) {  // whole XCD rounds for the remap
+    nb = (nb + 7) / 8 * 8;
+  }
   dim3 grid(nb, (total + 4 * kCPW - 1) / (4 * kCPW));
-  k_tsgemm_tn<B, TB><<<grid, kThreads, 0, s>>>(sg, total, N, T, ldt, partial);
+  k_tsgemm_tn<B, TB><<<grid, kThreads, 0, s>>>(sg, total, N, T, ldt, chunk, partial);
   SVDS_LAUNCH_CHECK();
   reduce_partials(partial, nb, total * B, C, s);
 }
@@ -272,7 +272,17 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nn(const TI* __restrict__ Q, 
     double acc[kOC];
 #pragma unroll
     for (int o = 0; o < kOC; ++o) acc[o] = 0.0;
-    for (int j = 0; j < nq; ++j) {
+    int j = 0;
+    for (; j + 4 <= nq; j += 4) {  // four loads in flight, same summation order
+      double q[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) q[u] = (double)Q[i + (int64_t)(j + u) * ldq];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int o = 0; o < kOC; ++o) acc[o] = fma(q[u], ys[(j + u) * kOC + o], acc[o]);
+    }
+    for (; j < nq; ++j) {
       const double q = (double)Q[i + (int64_t)j * ldq];
 #pragma unroll
       for (int o = 0; o < kOC; ++o) acc[o] = fma(q, ys[j * kOC + o], acc[o]);
@@ -376,7 +386,26 @@ __global__ __launch_bounds__(kThreads) void k_residual(
     double x[NCC], w[NCC];
 #pragma unroll
     for (int c = 0; c < NCC; ++c) x[c] = w[c] = 0.0;
-    for (int j = 0; j < g; ++j) {
+    // four basis columns per step, their loads issued together (the same
+    // summation order as one column at a time)
+    int j = 0;
+    for (; j + 4 <= g; j += 4) {
+      double v[4], ww[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        v[u] = (double)V[i + (int64_t)(j + u) * ld];
+        ww[u] = (double)W[i + (int64_t)(j + u) * ld];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int c = 0; c < NCC; ++c) {
+          x[c] = fma(v[u], ys[(j + u) * NCC + c], x[c]);
+          w[c] = fma(ww[u], ys[(j + u) * NCC + c], w[c]);
+        }
+      }
+    }
+    for (; j < g; ++j) {
       const double v = (double)V[i + (int64_t)j * ld];
       const double ww = (double)W[i + (int64_t)j * ld];
 #pragma unroll

@@ -11,6 +11,7 @@ namespace svds {
 
 constexpr int kT = kSmallThreads;
 constexpr int kLs = kLd + 1;  // padded leading dimension in LDS
+constexpr int kEigT = 1024;   // threads of the eigensolver kernels
 
 // round-robin pairing for np (even) indices, round r in [0, np-1)
 __device__ __forceinline__ void rr_pair(int np, int r, int k, int& p, int& q) {
@@ -42,120 +43,133 @@ __device__ void make_pairs(int np, unsigned char* pp, unsigned char* pq) {
   }
 }
 
+template <int NT>
 __device__ int jacobi_eig_lds(int n, double* A, double* Z, double* d, double* cs, double* sn,
                               int* flag, double thr_floor = 0.0) {
   __shared__ double tt_[kLd / 2 + 1], apq_[kLd / 2 + 1];
   __shared__ int zero_[kLd / 2 + 1];
-  __shared__ double red_[kT / kWave];
+  __shared__ double red_[NT / kWave];
   __shared__ unsigned char pp[(kLd - 1) * (kLd / 2)], pq[(kLd - 1) * (kLd / 2)];
+  __shared__ unsigned char active[kLd];
+  __shared__ int nactive;
   const int t = threadIdx.x;
   const int np = n + (n & 1);
   const int npair = np / 2;
   if (n & 1) {  // padding index: zero row and column of A, unit vector in Z
-    for (int j = t; j < np; j += kT) {
+    for (int j = t; j < np; j += NT) {
       A[n * kLs + j] = 0.0;
       A[j * kLs + n] = 0.0;
       Z[n * kLs + j] = (j == n) ? 1.0 : 0.0;
       Z[j * kLs + n] = (j == n) ? 1.0 : 0.0;
     }
   }
-  make_pairs(np, pp, pq);
+  for (int a = t; a < (np - 1) * npair; a += NT) {
+    const int r = a / npair, k = a % npair;
+    int p, q;
+    rr_pair(np, r, k, p, q);
+    pp[a] = (unsigned char)p;
+    pq[a] = (unsigned char)q;
+  }
   double f = 0.0;
-  for (int a = t; a < n * n; a += kT) {
+  for (int a = t; a < n * n; a += NT) {
     const double v = A[(a / n) * kLs + (a % n)];
     f += v * v;
   }
   f = wave_sum(f);
   if (t % kWave == 0) red_[t / kWave] = f;
   __syncthreads();
-  const double frob = sqrt(((red_[0] + red_[1]) + red_[2]) + red_[3]);
+  double fr = 0.0;
+  for (int w = 0; w < NT / kWave; ++w) fr += red_[w];
+  const double frob = sqrt(fr);
   // off-diagonal entries below eps*||A||/4 are dropped: they move eigenvalues
   // and residuals of the Ritz pairs by less than the rounding level of the
   // projected matrix itself
   const double thr = fmax(0.25 * kEps * frob, thr_floor);
-  __shared__ int round_rot;
+  // Threshold cyclic Jacobi on active rounds only: each sweep first scans all
+  // off-diagonal entries and marks the rounds of the parallel ordering that
+  // hold an entry above the threshold; only those rounds are processed.
+  // Rotations create fill-in in other rounds, which the next sweep's scan
+  // picks up; the iteration ends when a scan finds nothing.  A round's 2 x 2
+  // block updates of A and its rotations of Z are one flat work list over
+  // the workgroup.
   int sweep = 0;
   for (; sweep < 60 && np > 1; ++sweep) {
-    if (t == 0) *flag = 0;
+    if (t < np - 1) active[t] = 0;
+    if (t == 0) nactive = 0;
     __syncthreads();
+    for (int e = t; e < (np - 1) * npair; e += NT)
+      if (fabs(A[pp[e] * kLs + pq[e]]) > thr) active[e / npair] = 1;
+    __syncthreads();
+    if (t < np - 1 && active[t]) atomicAdd(&nactive, 1);
+    __syncthreads();
+    if (nactive == 0) break;
     for (int r = 0; r < np - 1; ++r) {
+      if (!active[r]) continue;  // uniform: read after a barrier
       const unsigned char* P = pp + r * npair;
       const unsigned char* Q = pq + r * npair;
-      if (t == 0) round_rot = 0;
-      __syncthreads();
       if (t < npair) {
         const int p = P[t], q = Q[t];
         const double apq = A[p * kLs + q];
-        double c = 1.0, s = 0.0, tt = 0.0;
+        double c = 1.0, sv = 0.0, tt = 0.0;
         const double app = A[p * kLs + p], aqq = A[q * kLs + q];
         if (fabs(apq) > thr) {
           const double th = (aqq - app) / (2.0 * apq);
           tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
           c = 1.0 / sqrt(tt * tt + 1.0);
-          s = tt * c;
-          *flag = 1;
-          round_rot = 1;
+          sv = tt * c;
         }
         cs[t] = c;
-        sn[t] = s;
+        sn[t] = sv;
         tt_[t] = tt;
         apq_[t] = apq;
-        zero_[t] = (s == 0.0 && apq != 0.0) ? 1 : 0;
+        zero_[t] = (sv == 0.0 && apq != 0.0) ? 1 : 0;
       }
       __syncthreads();
-      if (!round_rot) {  // only negligible entries: zero them and move on
-        if (t < npair && zero_[t]) {
-          A[P[t] * kLs + Q[t]] = 0.0;
-          A[Q[t] * kLs + P[t]] = 0.0;
-        }
-        continue;
-      }
-      // A <- J^T A J as independent 2 x 2 block updates
-      for (int K = t >> 5; K < npair; K += kT / 32) {
-        const int L = t & 31;
-        if (L >= npair) continue;
-        const int pK = P[K], qK = Q[K];
-        if (K == L) {
-          if (sn[K] != 0.0) {
-            A[pK * kLs + pK] -= tt_[K] * apq_[K];
-            A[qK * kLs + qK] += tt_[K] * apq_[K];
-            A[pK * kLs + qK] = 0.0;
-            A[qK * kLs + pK] = 0.0;
-          } else if (zero_[K]) {
-            A[pK * kLs + qK] = 0.0;
-            A[qK * kLs + pK] = 0.0;
+      const int nA = npair * npair;
+      for (int idx = t; idx < nA + npair * np; idx += NT) {
+        if (idx < nA) {  // A <- J^T A J, block (K, L)
+          const int K = idx / npair, L = idx % npair;
+          const int pK = P[K], qK = Q[K];
+          if (K == L) {
+            if (sn[K] != 0.0) {
+              A[pK * kLs + pK] -= tt_[K] * apq_[K];
+              A[qK * kLs + qK] += tt_[K] * apq_[K];
+              A[pK * kLs + qK] = 0.0;
+              A[qK * kLs + pK] = 0.0;
+            } else if (zero_[K]) {
+              A[pK * kLs + qK] = 0.0;
+              A[qK * kLs + pK] = 0.0;
+            }
+            continue;
           }
-          continue;
+          const double cK = cs[K], sK = sn[K], cL = cs[L], sL = sn[L];
+          if (sK == 0.0 && sL == 0.0) continue;
+          const int pL = P[L], qL = Q[L];
+          const double a11 = A[pK * kLs + pL], a12 = A[pK * kLs + qL];
+          const double a21 = A[qK * kLs + pL], a22 = A[qK * kLs + qL];
+          const double b11 = cK * a11 - sK * a21, b12 = cK * a12 - sK * a22;
+          const double b21 = sK * a11 + cK * a21, b22 = sK * a12 + cK * a22;
+          A[pK * kLs + pL] = cL * b11 - sL * b12;
+          A[pK * kLs + qL] = sL * b11 + cL * b12;
+          A[qK * kLs + pL] = cL * b21 - sL * b22;
+          A[qK * kLs + qL] = sL * b21 + cL * b22;
+        } else {  // Z <- Z J, row i of rotation L
+          const int e2 = idx - nA;
+          const int L = e2 / np, i = e2 % np;
+          const double sL = sn[L];
+          if (sL == 0.0) continue;
+          const double cL = cs[L];
+          const int pL = P[L], qL = Q[L];
+          const double x = Z[i * kLs + pL], y = Z[i * kLs + qL];
+          Z[i * kLs + pL] = cL * x - sL * y;
+          Z[i * kLs + qL] = sL * x + cL * y;
         }
-        const double cK = cs[K], sK = sn[K], cL = cs[L], sL = sn[L];
-        if (sK == 0.0 && sL == 0.0) continue;
-        const int pL = P[L], qL = Q[L];
-        const double a11 = A[pK * kLs + pL], a12 = A[pK * kLs + qL];
-        const double a21 = A[qK * kLs + pL], a22 = A[qK * kLs + qL];
-        const double b11 = cK * a11 - sK * a21, b12 = cK * a12 - sK * a22;
-        const double b21 = sK * a11 + cK * a21, b22 = sK * a12 + cK * a22;
-        A[pK * kLs + pL] = cL * b11 - sL * b12;
-        A[pK * kLs + qL] = sL * b11 + cL * b12;
-        A[qK * kLs + pL] = cL * b21 - sL * b22;
-        A[qK * kLs + qL] = sL * b21 + cL * b22;
-      }
-      // Z <- Z J
-      for (int L = t >> 6; L < npair; L += kT / kWave) {
-        const int i = t & 63;
-        const double sL = sn[L];
-        if (i >= np || sL == 0.0) continue;
-        const double cL = cs[L];
-        const int pL = P[L], qL = Q[L];
-        const double x = Z[i * kLs + pL], y = Z[i * kLs + qL];
-        Z[i * kLs + pL] = cL * x - sL * y;
-        Z[i * kLs + qL] = sL * x + cL * y;
       }
       __syncthreads();
     }
-    if (*flag == 0) break;
-    __syncthreads();
   }
-  for (int i = t; i < n; i += kT) d[i] = A[i * kLs + i];
+  if (t == 0) *flag = 0;
+  for (int i = t; i < n; i += NT) d[i] = A[i * kLs + i];
   __syncthreads();
   return sweep + 1;
 }
@@ -178,26 +192,26 @@ __device__ void sort_pairs(int n, const double* d, const double* Z, int descendi
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kT) void k_eig(int g, const double* H, int ldh, int descending,
+__global__ __launch_bounds__(kEigT) void k_eig(int g, const double* H, int ldh, int descending,
                                             double* theta, double* Y, int ldy) {
   __shared__ double A[kLd * kLs];
   __shared__ double Z[kLd * kLs];
   __shared__ double d[kLd], cs[kLd], sn[kLd];
   __shared__ int flag;
-  for (int a = threadIdx.x; a < g * g; a += kT) {
+  for (int a = threadIdx.x; a < g * g; a += kEigT) {
     const int i = a % g, j = a / g;
     A[i * kLs + j] = 0.5 * (H[(int64_t)j * ldh + i] + H[(int64_t)i * ldh + j]);
     Z[i * kLs + j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  jacobi_eig_lds(g, A, Z, d, cs, sn, &flag);
+  jacobi_eig_lds<kEigT>(g, A, Z, d, cs, sn, &flag);
   sort_pairs(g, d, Z, descending, theta, Y, ldy);
 }
 
 void small_eig(int g, const double* H, int ldh, int descending, double* theta, double* Y, int ldy,
                hipStream_t s) {
   if (g < 1 || g > kGmax) throw Error(SVDS_ERR_ARG, "small_eig: 1 <= g <= 48");
-  k_eig<<<1, kT, 0, s>>>(g, H, ldh, descending, theta, Y, ldy);
+  k_eig<<<1, kEigT, 0, s>>>(g, H, ldh, descending, theta, Y, ldy);
   SVDS_LAUNCH_CHECK();
 }
 
@@ -356,87 +370,95 @@ void small_h_append(Small* d, int gc, int nb, hipStream_t s) {
 // refined projection, right singular vectors of Rr in ascending order with
 // theta_j = y_j^T H y_j (Section 3.2)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kT) void k_extract(Small* d, int gc, int descending, int refined) {
+__global__ __launch_bounds__(kEigT) void k_extract_rr(Small* d, int gc, int descending) {
   __shared__ double A[kLd * kLs];
   __shared__ double Z[kLd * kLs];
   __shared__ double Mx[kLd * kLs];
   __shared__ double dd[kLd], cs[kLd], sn[kLd];
   __shared__ int flag;
   const int t = threadIdx.x;
-  if (!refined) {
-    const bool warm = d->warm_g == gc;
-    for (int a = t; a < gc * gc; a += kT) {
-      const int i = a % gc, j = a / gc;
-      A[i * kLs + j] = 0.5 * (d->H[j * kLd + i] + d->H[i * kLd + j]);
-      Z[i * kLs + j] = warm ? d->Yw[j * kLd + i] : (i == j ? 1.0 : 0.0);
-    }
-    __syncthreads();
-    if (warm) {  // A <- W^T A W with W the previous eigenvectors (padded)
-      for (int a = t; a < gc * gc; a += kT) {
-        const int i = a % gc, j = a / gc;
-        double acc = 0.0;
-        for (int c = 0; c < gc; ++c) acc += A[i * kLs + c] * Z[c * kLs + j];
-        Mx[i * kLs + j] = acc;
-      }
-      __syncthreads();
-      for (int a = t; a < gc * gc; a += kT) {
-        const int i = a % gc, j = a / gc;
-        double acc = 0.0;
-        for (int c = 0; c < gc; ++c) acc += Z[c * kLs + i] * Mx[c * kLs + j];
-        A[i * kLs + j] = acc;
-      }
-      __syncthreads();
-      for (int a = t; a < gc * gc; a += kT) {  // symmetrise
-        const int i = a % gc, j = a / gc;
-        if (i < j) {
-          const double v = 0.5 * (A[i * kLs + j] + A[j * kLs + i]);
-          A[i * kLs + j] = v;
-          A[j * kLs + i] = v;
-        }
-      }
-      __syncthreads();
-    }
-    const int nsw = jacobi_eig_lds(gc, A, Z, dd, cs, sn, &flag);
-    if (t == 0) d->eig_sweeps = nsw;
-    sort_pairs(gc, dd, Z, descending, d->theta, d->Y, kLd);
-    for (int a = t; a < gc * gc; a += kT) {
-      const int i = a % gc, j = a / gc;
-      d->Yw[j * kLd + i] = d->Y[j * kLd + i];
-    }
-    if (t == 0) d->warm_g = gc;
-  } else {
-    for (int a = t; a < gc * gc; a += kT) {
-      const int i = a % gc, j = a / gc;
-      A[i * kLs + j] = (i <= j) ? d->Rr[j * kLd + i] : 0.0;
-    }
-    __syncthreads();
-    jacobi_svd_lds(gc, A, Z, cs, sn, &flag);
-    svd_finish(gc, A, Z, dd, d->sv, d->Y, kLd, nullptr, 0);
-    // theta_j = y_j^T H y_j with H and the sorted Y staged in LDS
-    for (int a = t; a < gc * gc; a += kT) {
-      const int i = a % gc, j = a / gc;
-      A[i * kLs + j] = d->H[j * kLd + i];
-      Z[i * kLs + j] = d->Y[j * kLd + i];
-    }
-    __syncthreads();
-    for (int a = t; a < gc * gc; a += kT) {  // M = H Y
+  const bool warm = d->warm_g == gc;
+  for (int a = t; a < gc * gc; a += kEigT) {
+    const int i = a % gc, j = a / gc;
+    A[i * kLs + j] = 0.5 * (d->H[j * kLd + i] + d->H[i * kLd + j]);
+    Z[i * kLs + j] = warm ? d->Yw[j * kLd + i] : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (warm) {  // A <- W^T A W with W the previous eigenvectors (padded)
+    for (int a = t; a < gc * gc; a += kEigT) {
       const int i = a % gc, j = a / gc;
       double acc = 0.0;
       for (int c = 0; c < gc; ++c) acc += A[i * kLs + c] * Z[c * kLs + j];
       Mx[i * kLs + j] = acc;
     }
     __syncthreads();
-    for (int j = t; j < gc; j += kT) {
+    for (int a = t; a < gc * gc; a += kEigT) {
+      const int i = a % gc, j = a / gc;
       double acc = 0.0;
-      for (int r = 0; r < gc; ++r) acc += Z[r * kLs + j] * Mx[r * kLs + j];
-      d->theta[j] = acc;
+      for (int c = 0; c < gc; ++c) acc += Z[c * kLs + i] * Mx[c * kLs + j];
+      A[i * kLs + j] = acc;
     }
+    __syncthreads();
+    for (int a = t; a < gc * gc; a += kEigT) {  // symmetrise
+      const int i = a % gc, j = a / gc;
+      if (i < j) {
+        const double v = 0.5 * (A[i * kLs + j] + A[j * kLs + i]);
+        A[i * kLs + j] = v;
+        A[j * kLs + i] = v;
+      }
+    }
+    __syncthreads();
+  }
+  const int nsw = jacobi_eig_lds<kEigT>(gc, A, Z, dd, cs, sn, &flag);
+  if (t == 0) d->eig_sweeps = nsw;
+  sort_pairs(gc, dd, Z, descending, d->theta, d->Y, kLd);
+  for (int a = t; a < gc * gc; a += kEigT) {
+    const int i = a % gc, j = a / gc;
+    d->Yw[j * kLd + i] = d->Y[j * kLd + i];
+  }
+  if (t == 0) d->warm_g = gc;
+}
+
+__global__ __launch_bounds__(kT) void k_extract_refined(Small* d, int gc) {
+  __shared__ double A[kLd * kLs];
+  __shared__ double Z[kLd * kLs];
+  __shared__ double Mx[kLd * kLs];
+  __shared__ double dd[kLd];
+  __shared__ double cs[kLd], sn[kLd];
+  __shared__ int flag;
+  const int t = threadIdx.x;
+  for (int a = t; a < gc * gc; a += kT) {
+    const int i = a % gc, j = a / gc;
+    A[i * kLs + j] = (i <= j) ? d->Rr[j * kLd + i] : 0.0;
+  }
+  __syncthreads();
+  jacobi_svd_lds(gc, A, Z, cs, sn, &flag);
+  svd_finish(gc, A, Z, dd, d->sv, d->Y, kLd, nullptr, 0);
+  // theta_j = y_j^T H y_j with H and the sorted Y staged in LDS
+  for (int a = t; a < gc * gc; a += kT) {
+    const int i = a % gc, j = a / gc;
+    A[i * kLs + j] = d->H[j * kLd + i];
+    Z[i * kLs + j] = d->Y[j * kLd + i];
+  }
+  __syncthreads();
+  for (int a = t; a < gc * gc; a += kT) {  // M = H Y
+    const int i = a % gc, j = a / gc;
+    double acc = 0.0;
+    for (int c = 0; c < gc; ++c) acc += A[i * kLs + c] * Z[c * kLs + j];
+    Mx[i * kLs + j] = acc;
+  }
+  __syncthreads();
+  for (int j = t; j < gc; j += kT) {
+    double acc = 0.0;
+    for (int r = 0; r < gc; ++r) acc += Z[r * kLs + j] * Mx[r * kLs + j];
+    d->theta[j] = acc;
   }
 }
 
 void small_extract(Small* d, int gc, int descending, int refined, hipStream_t s) {
   if (gc < 1 || gc > kGmax) throw Error(SVDS_ERR_ARG, "extract: basis size");
-  k_extract<<<1, kT, 0, s>>>(d, gc, descending, refined);
+  if (refined) k_extract_refined<<<1, kT, 0, s>>>(d, gc);
+  else k_extract_rr<<<1, kEigT, 0, s>>>(d, gc, descending);
   SVDS_LAUNCH_CHECK();
 }
 
