@@ -14,12 +14,24 @@
 
 namespace svds {
 
+// sum over the L lanes of a group (L <= 64, a power of two); every lane of
+// the group ends with the total
+template <typename TV, int L>
+__device__ __forceinline__ TV group_total(TV v) {
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
 // L lanes per row; each lane takes U of the row's nonzeros per step (lane
-// offsets l, l+L, ..., l+(U-1)L), issuing all their index, value and
-// gathered-row loads before the multiply-adds so that U loads per lane are in
-// flight.  The summation order inside a lane is the same for every U, so the
-// result depends on L only.  After the shuffle reduction lanes 0..B-1 of the
-// group store the row's B outputs side by side (one coalesced store).
+// offsets l, l+L, ..., l+(U-1)L).  The index and value loads of a step are
+// issued together and without branches (positions past the row end read the
+// row's last entry and are masked), then the U gathered rows of X, then the
+// multiply-adds, so that U loads per lane are in flight.  The row bounds of
+// the group's next row are loaded before the current row is processed.
+// The summation order inside a lane is the same for every U, so the result
+// depends on L only.  After the shuffle reduction lanes 0..B-1 of the group
+// store the row's B outputs side by side (one coalesced store).
 template <typename TV, int B, int L, int U>
 __global__ __launch_bounds__(256) void k_spmm_group(const int32_t* __restrict__ rp,
                                                     const int32_t* __restrict__ ci,
@@ -31,9 +43,23 @@ __global__ __launch_bounds__(256) void k_spmm_group(const int32_t* __restrict__ 
   const int grp = threadIdx.x / L;
   const int lane = threadIdx.x % L;
   const int bid = xcd_block(blockIdx.x, gridDim.x);
-  for (int64_t slot = (int64_t)bid * RPB + grp; slot < nrows; slot += (int64_t)gridDim.x * RPB) {
-    const int32_t row = rows ? rows[slot] : (int32_t)slot;
-    const int32_t a = rp[row], e = rp[row + 1];
+  const int64_t stride = (int64_t)gridDim.x * RPB;
+  int64_t slot = (int64_t)bid * RPB + grp;
+  int32_t row = 0, a = 0, e = 0;
+  if (slot < nrows) {
+    row = rows ? rows[slot] : (int32_t)slot;
+    a = rp[row];
+    e = rp[row + 1];
+  }
+  while (slot < nrows) {
+    // bounds of the next row first
+    const int64_t nslot = slot + stride;
+    int32_t nrow = 0, na = 0, ne = 0;
+    if (nslot < nrows) {
+      nrow = rows ? rows[nslot] : (int32_t)nslot;
+      na = rp[nrow];
+      ne = rp[nrow + 1];
+    }
     TV acc[B];
 #pragma unroll
     for (int j = 0; j < B; ++j) acc[j] = TV(0);
@@ -43,9 +69,9 @@ __global__ __launch_bounds__(256) void k_spmm_group(const int32_t* __restrict__ 
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int32_t k = k0 + u * L;
-        const bool ok = (u == 0) || k < e;
-        c[u] = ok ? ci[k] : 0;
-        v[u] = ok ? val[k] : TV(0);
+        const int32_t kk = k < e ? k : e - 1;
+        c[u] = ci[kk];
+        v[u] = val[kk];
       }
       TV x[U][B];
 #pragma unroll
@@ -56,20 +82,100 @@ __global__ __launch_bounds__(256) void k_spmm_group(const int32_t* __restrict__ 
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (u == 0 || k0 + u * L < e) {
+        const bool in = k0 + u * L < e;
 #pragma unroll
-          for (int j = 0; j < B; ++j) acc[j] = fma(v[u], x[u][j], acc[j]);
+        for (int j = 0; j < B; ++j) {
+          const TV t = fma(v[u], x[u][j], acc[j]);
+          acc[j] = in ? t : acc[j];
         }
       }
     }
     if constexpr (L > 1) {
 #pragma unroll
-      for (int j = 0; j < B; ++j) {
-#pragma unroll
-        for (int off = L / 2; off > 0; off >>= 1) acc[j] += __shfl_xor(acc[j], off, kWave);
-      }
+      for (int j = 0; j < B; ++j) acc[j] = group_total<TV, L>(acc[j]);
     }
     TV* __restrict__ y = Y + (int64_t)row * B;
+    if constexpr (L >= B) {
+      TV out = acc[0];
+#pragma unroll
+      for (int j = 1; j < B; ++j)
+        if (lane == j) out = acc[j];
+      if (lane < B) y[lane] = out;
+    } else {
+      if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < B; ++j) y[j] = acc[j];
+      }
+    }
+    slot = nslot;
+    row = nrow;
+    a = na;
+    e = ne;
+  }
+}
+
+// Natural row order (one launch over all rows): the workgroup's RPB
+// consecutive rows have consecutive row pointers, which it stages in LDS with
+// one coalesced load per step; each group then starts on its row's nonzeros
+// at once instead of waiting for its own row-pointer loads.  Same lane
+// arithmetic and summation order as k_spmm_group.
+template <typename TV, int B, int L, int U>
+__global__ __launch_bounds__(256) void k_spmm_nat(const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ ci,
+                                                  const TV* __restrict__ val, int64_t nrows,
+                                                  const TV* __restrict__ X,
+                                                  TV* __restrict__ Y) {
+  constexpr int RPB = 256 / L;
+  __shared__ int32_t rps[RPB + 1];
+  const int grp = threadIdx.x / L;
+  const int lane = threadIdx.x % L;
+  const int bid = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t stride = (int64_t)gridDim.x * RPB;
+  for (int64_t s0 = (int64_t)bid * RPB; s0 < nrows; s0 += stride) {
+    __syncthreads();
+    for (int t = threadIdx.x; t <= RPB; t += 256) {
+      const int64_t r = s0 + t;
+      rps[t] = rp[r < nrows ? r : nrows];
+    }
+    __syncthreads();
+    const int64_t row = s0 + grp;
+    if (row >= nrows) continue;
+    const int32_t a = rps[grp], e = rps[grp + 1];
+    TV acc[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) acc[j] = TV(0);
+    for (int32_t k0 = a + lane; k0 < e; k0 += L * U) {
+      int32_t c[U];
+      TV v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t k = k0 + u * L;
+        const int32_t kk = k < e ? k : e - 1;
+        c[u] = ci[kk];
+        v[u] = val[kk];
+      }
+      TV x[U][B];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const TV* __restrict__ xr = X + (int64_t)c[u] * B;
+#pragma unroll
+        for (int j = 0; j < B; ++j) x[u][j] = xr[j];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool in = k0 + u * L < e;
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+          const TV t = fma(v[u], x[u][j], acc[j]);
+          acc[j] = in ? t : acc[j];
+        }
+      }
+    }
+    if constexpr (L > 1) {
+#pragma unroll
+      for (int j = 0; j < B; ++j) acc[j] = group_total<TV, L>(acc[j]);
+    }
+    TV* __restrict__ y = Y + row * B;
     if constexpr (L >= B) {
       TV out = acc[0];
 #pragma unroll
@@ -127,6 +233,14 @@ __global__ __launch_bounds__(256) void k_spmm_wg(const int32_t* __restrict__ rp,
 template <typename TV, int B, int L>
 static void launch_group(int U, int blocks, const Csr32& A, const TV* val, const int32_t* rows,
                          int64_t nr, const TV* X, TV* Y, hipStream_t s) {
+  if (!rows) {
+    switch (U) {
+      case 4: k_spmm_nat<TV, B, L, 4><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, nr, X, Y); break;
+      case 2: k_spmm_nat<TV, B, L, 2><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, nr, X, Y); break;
+      default: k_spmm_nat<TV, B, L, 1><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, nr, X, Y); break;
+    }
+    return;
+  }
   switch (U) {
     case 4: k_spmm_group<TV, B, L, 4><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, rows, nr, X, Y); break;
     case 2: k_spmm_group<TV, B, L, 2><<<blocks, 256, 0, s>>>(A.rp, A.ci, val, rows, nr, X, Y); break;
