@@ -20,4 +20,5 @@ from .phsvds import (  # noqa: F401
     jacobi_diag,
     svds,
     svd_residuals,
+    condest,
 )

@@ -345,7 +345,7 @@ def default_params(k, target, max_basis=None, min_restart=None, block=None, prev
 # Stage 1: GD+k on C with soft locking (Algorithm 1, first stage)
 # ---------------------------------------------------------------------------
 def _stage1(ops, k, target, tol, normA, g, r, b, p, seed, precond, budget, stats, rand_state,
-            trace=None, capture=None):
+            trace=None, capture=None, relative=False):
     n = ops.n
     g = min(g, n)
     r = min(r, max(1, g - b - p))
@@ -396,7 +396,13 @@ def _stage1(ops, k, target, tol, normA, g, r, b, p, seed, precond, budget, stats
         R = S.W @ Y[:, :nc] - X * lam[:nc]
         rn = np.linalg.norm(R, axis=0)
         # Algorithm 1 stage-1 test: ||r^C|| <= max(sqrt(|lam| ||C||) delta, eps ||C||)
-        thr = np.maximum(np.sqrt(np.abs(lam[:nc]) * normC) * tol, EPS * normC)
+        if relative:
+            # residual below tol times the eigenvalue (the low-accuracy stopping
+            # rule of Section 4.4): ||r^C|| <= tol |lambda|, i.e. the SVD
+            # residual below tol sigma
+            thr = np.maximum(tol * np.abs(lam[:nc]), EPS * normC)
+        else:
+            thr = np.maximum(np.sqrt(np.abs(lam[:nc]) * normC) * tol, EPS * normC)
         conv = rn <= thr
         # practically converged: stuck near the attainable floor
         pc = (~conv) & (stall[:nc] >= STALL_RESTARTS) & (rn <= FLOOR_GATE * EPS * normC)
@@ -690,7 +696,7 @@ def _sign_normalise(U, V):
 def svds(A, k, target="largest", tol=1e-10, *, max_basis=None, min_restart=None, block=None,
          prev_retain=None, max_matvecs=None, norm_A=None, seed=0, precond="none",
          force_stage2=False, cleanup=True, stage1_tol=None, trace=None, time_limit=None,
-         capture=None):
+         capture=None, method="hybrid", relative=False):
     """k largest or smallest singular triplets of the sparse matrix A with
     eq. (res) residual below tol*||A||.  Returns (sigma, U, V, rnorm, stats);
     U is m x k, V is n x k, both in target order with the largest-magnitude
@@ -703,7 +709,16 @@ def svds(A, k, target="largest", tol=1e-10, *, max_basis=None, min_restart=None,
     min(m, n)).  ``capture`` = {"every": e, "max": P} collects, at every e-th
     stage-1 iteration (at most P times), the residual, the Ritz vector and
     the target index of the block's first target into its "R", "X" and "idx"
-    lists (training pairs for a learned preconditioner)."""
+    lists (training pairs for a learned preconditioner).
+
+    ``method``: "hybrid" (the two-stage method), "normal" (stage 1 on the
+    normal equations alone, accepted as it ends) or "augmented" (stage 2 on
+    B alone from counter-based random vectors, largest values only: for the
+    smallest, B's spectrum is symmetric about the target region and its
+    shifts need the stage-1 bounds) -- the single-stage methods of
+    Section 3.4.  ``relative``: the stopping rule
+    ||r|| <= tol * sigma of the low-accuracy condition estimate (Section 4.4);
+    only with method "normal"."""
     t0 = time.perf_counter()
     if target not in ("largest", "smallest"):
         raise ValueError("target must be 'largest' or 'smallest'")
@@ -715,6 +730,15 @@ def svds(A, k, target="largest", tol=1e-10, *, max_basis=None, min_restart=None,
     m, n = ops.m, ops.n
     if not (1 <= k <= n):
         raise ValueError("k out of range")
+    if method not in ("hybrid", "normal", "augmented"):
+        raise ValueError("method must be 'hybrid', 'normal' or 'augmented'")
+    if relative and method != "normal":
+        raise ValueError("the relative stopping rule needs method 'normal'")
+    if method == "augmented" and target == "smallest":
+        # on B alone the smallest values are interior, with -sigma as close to a
+        # shift near zero as +sigma (and m - n zero eigenvalues when m != n):
+        # the shifts need the stage-1 bounds, which is the hybrid method
+        raise ValueError("the augmented method alone seeks the largest values only")
     g, r, b, p = default_params(k, target, max_basis, min_restart, block, prev_retain)
     if not (b >= 1 and g >= r + p + b and r >= 1 and min(g, n) >= k + b):
         raise ValueError("need max_basis >= min_restart + prev_retain + block, and k + block "
@@ -742,16 +766,27 @@ def svds(A, k, target="largest", tol=1e-10, *, max_basis=None, min_restart=None,
         capture.setdefault("R", [])
         capture.setdefault("X", [])
         capture.setdefault("idx", [])
-    Xk, normC, status = _stage1(ops, k, target, tol1, normA, g, r, b, p, seed, pc, budget,
-                                stats, rand_state, trace, capture)
-    normA = max(normA, math.sqrt(normC))
-    sig, U, V, rn = _final_rr(ops, Xk, target)
-    stats["matvecs"][0] = ops.mv
     t1 = time.perf_counter()
-    stats["seconds"][0] = t1 - t0
-    ok = np.all(rn < normA * tol)
-    nconv = k if ok else 0
-    if status != "budget" and (force_stage2 or not ok):
+    if method == "augmented":
+        # random start on B: [v; u] from one counter-based block of length n + m
+        X0 = counter_uniform(seed, STREAM_INIT, n + m, k)
+        V, U = X0[:n], X0[n:]
+        sig = np.zeros(k)
+        rn = np.full(k, np.inf)
+        status = "augmented"
+    else:
+        Xk, normC, status = _stage1(ops, k, target, tol1, normA, g, r, b, p, seed, pc, budget,
+                                    stats, rand_state, trace, capture, relative)
+        normA = max(normA, math.sqrt(normC))
+        sig, U, V, rn = _final_rr(ops, Xk, target)
+        stats["matvecs"][0] = ops.mv
+        t1 = time.perf_counter()
+        stats["seconds"][0] = t1 - t0
+    lim = tol * sig if relative else normA * tol
+    ok = np.all(rn < lim)
+    nconv = k if ok else int(np.sum(rn < lim))
+    if method == "augmented" or (method == "hybrid" and status != "budget"
+                                 and (force_stage2 or not ok)):
         # ---- stage 2 on B
         mv0 = ops.mv
         sig, U, V, nconv, status2 = _stage2(ops, k, target, tol, normA, g, r, b, p, seed, pc,
@@ -759,8 +794,6 @@ def svds(A, k, target="largest", tol=1e-10, *, max_basis=None, min_restart=None,
         stats["matvecs"][1] = ops.mv - mv0
         stats["stage_exit"] = 2
         stats["seconds"][1] = time.perf_counter() - t1
-    elif status == "budget":
-        nconv = int(np.sum(rn < normA * tol))
     if cleanup:
         sig, U, V = _cleanup(ops, sig, U, V, target)
     rnorm = svd_residuals(Aw, sig, U, V)
@@ -768,6 +801,20 @@ def svds(A, k, target="largest", tol=1e-10, *, max_basis=None, min_restart=None,
         U, V = V, U
     U, V = _sign_normalise(U, V)
     stats["norm_A_used"] = normA
-    stats["nconv"] = int(nconv)
-    stats["converged"] = bool(nconv >= k and np.all(rnorm < normA * tol))
+    lim = tol * sig if relative else normA * tol
+    stats["nconv"] = int(np.sum(rnorm < lim)) if method != "hybrid" else int(nconv)
+    stats["converged"] = bool(np.all(rnorm < lim) and stats["nconv"] >= k)
     return sig, U, V, rnorm, stats
+
+
+def condest(A, tol=0.1, *, seed=0, precond="none", max_basis=None, min_restart=None,
+            max_matvecs=None, norm_A=None):
+    """Condition-number estimate of Section 4.4: one largest and one smallest
+    singular triplet, block size 1, stage 1 stopped when the residual is
+    below tol times the singular value (tol = 0.1 gives about 10 %).
+    Returns (kappa, sigma_max, sigma_min, (stats_largest, stats_smallest))."""
+    kw = dict(block=1, seed=seed, precond=precond, max_basis=max_basis, min_restart=min_restart,
+              max_matvecs=max_matvecs, norm_A=norm_A, method="normal", relative=True)
+    s1, _, _, _, st1 = svds(A, 1, "largest", tol, **kw)
+    s0, _, _, _, st0 = svds(A, 1, "smallest", tol, **kw)
+    return float(s1[0] / s0[0]), float(s1[0]), float(s0[0]), (st1, st0)

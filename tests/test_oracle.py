@@ -263,3 +263,45 @@ def test_rejects_bad_arguments():
         oracle.svds(A, 3, "middle")
     with pytest.raises(ValueError):
         oracle.svds(A, 3, "largest", max_basis=8, min_restart=6, block=2)
+
+
+# ---- single-stage methods and the condition-number estimate (Sections 3.4, 4.4)
+def test_normal_equations_alone_cannot_reach_small_residual_for_ill_conditioned():
+    """The normal equations limit the accuracy of the smallest triplets
+    (Section 2.1): with kappa ~ 1e6, stage 1 alone stops at its floor above
+    1e-10 ||A||, while the two-stage method reaches it."""
+    A = synth.banded_scaled(300, 150, seed=1, log_lo=-6)
+    normA = float(np.linalg.norm(A.toarray(), 2))
+    s_ref = np.sort(np.linalg.svd(A.toarray(), compute_uv=False))[:2]
+    sn, _, _, rn_n, st_n = oracle.svds(A, 2, "smallest", 1e-10, block=1, seed=7, norm_A=normA,
+                                       precond="jacobi", method="normal")
+    sh, _, _, rn_h, st_h = oracle.svds(A, 2, "smallest", 1e-10, block=1, seed=7, norm_A=normA,
+                                       precond="jacobi")
+    assert st_n["stage_exit"] == 1 and not st_n["converged"]
+    assert rn_n.max() > 1e-10 * normA
+    assert st_h["converged"] and st_h["stage_exit"] == 2
+    assert np.max(np.abs(sh - s_ref) / s_ref) < 1e-9
+
+
+def test_augmented_alone_largest():
+    A = synth.config1(m=200, n=100, nnz_per_row=8)
+    s_ref = np.linalg.svd(A.toarray(), compute_uv=False)
+    s, U, V, rn, st = oracle.svds(A, 3, "largest", 1e-10, block=1, seed=2, method="augmented")
+    assert st["converged"] and st["stage_exit"] == 2 and st["matvecs"][0] == 0
+    assert np.max(np.abs(s - s_ref[:3]) / s_ref[:3]) < 1e-10
+    with pytest.raises(ValueError):
+        oracle.svds(A, 2, "smallest", 1e-10, method="augmented")
+    with pytest.raises(ValueError):
+        oracle.svds(A, 2, "smallest", 1e-10, relative=True)
+
+
+def test_condition_estimate_within_ten_percent():
+    """kappa = 1e4 prescribed (Section 4.4: block 1, stop at residual below
+    0.1 sigma gives about 10 % relative error of the extreme values)."""
+    sigma = np.geomspace(1e-4, 1.0, 60)
+    A, srt, _, _ = synth.prescribed_dense(90, 60, sigma, seed=5)
+    kappa, smax, smin, (st1, st0) = oracle.condest(A, 0.1, seed=1)
+    assert abs(smax - 1.0) < 0.1 and abs(smin - 1e-4) / 1e-4 < 0.1
+    assert abs(kappa - 1e4) / 1e4 < 0.2
+    assert st1["converged"] and st0["converged"]
+    assert st1["stage_exit"] == 1 and st0["stage_exit"] == 1
