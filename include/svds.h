@@ -69,6 +69,13 @@ extern "C" {
                                 /* of opts.pc_model (svds_lpc_* below), with */
                                 /* the same composition on B                 */
 
+#define SVDS_METHOD_HYBRID 0     /* the two-stage method (default)          */
+#define SVDS_METHOD_NORMAL 1     /* stage 1 on A^T A alone, accepted as it  */
+                                 /* ends (primme_svds_normalequations)      */
+#define SVDS_METHOD_AUGMENTED 2  /* stage 2 on B alone from random vectors, */
+                                 /* largest values only                     */
+                                 /* (primme_svds_augmented; Section 3.4)    */
+
 /* ---- CSR matrix (device arrays, caller-owned, read-only) ----------------- */
 typedef struct svds_csr {
   int64_t m, n, nnz;
@@ -108,6 +115,10 @@ typedef struct svds_opts {
                           /* or one launch with 1..64 lanes per row) for    */
                           /* the block width and keep the fastest; 0: use   */
                           /* the row-length rule of thumb                   */
+  int method;             /* SVDS_METHOD_*                                  */
+  int relative_tol;       /* 1: converged when ||r|| < tol * sigma (the     */
+                          /* stopping rule of the condition estimate,       */
+                          /* Section 4.4); needs SVDS_METHOD_NORMAL         */
   double max_seconds;     /* wall-clock budget of the solve (> 0), checked  */
                           /* once per iteration like max_matvecs; 0: none  */
   int pc_degree;          /* SVDS_PC_LEARNED: polynomial degree d, 1..15;   */
@@ -195,6 +206,16 @@ int svds_solve_batched(int nprob, const svds_csr* A, int k, int target, double t
                        const svds_opts* opts, double* const* sigma, double* const* U,
                        const int64_t* ldu, double* const* V, const int64_t* ldv,
                        double* const* rnorm, svds_stats* stats, int nworkers, void* stream);
+
+/* ---- condition-number estimate (Section 4.4) ------------------------------- */
+/* One largest and one smallest singular value with block size 1 and stage 1
+ * on A^T A stopped when the residual is below rtol * sigma (rtol <= 0 or
+ * >= 1 -> 0.1, which the paper found to give about 10 % relative error);
+ * opts supplies the rest (basis sizes, preconditioner, budget, seed).
+ * sigma_max, sigma_min, kappa: host; stats: NULL or an array of 2 (largest,
+ * smallest).  Returns the worse of the two solves' status codes. */
+int svds_condest(const svds_matrix* A, double rtol, const svds_opts* opts, double* sigma_max,
+                 double* sigma_min, double* kappa, svds_stats* stats, void* stream);
 
 /* ---- learned preconditioner ----------------------------------------------- */
 /* A preconditioner for the correction equation (the applyPreconditioner hook

@@ -13,6 +13,10 @@ from ._lib import (  # noqa: F401
     PC_NONE,
     PC_JACOBI,
     PC_LEARNED,
+    METHOD_HYBRID,
+    METHOD_NORMAL,
+    METHOD_AUGMENTED,
+    condest,
     LPC_NPARAMS,
     SvdsError,
     Opts,

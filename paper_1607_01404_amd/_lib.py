@@ -9,6 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LARGEST, SMALLEST = 0, 1
 FP64, MIXED = 0, 1
 PC_NONE, PC_JACOBI, PC_LEARNED = 0, 1, 2
+METHOD_HYBRID, METHOD_NORMAL, METHOD_AUGMENTED = 0, 1, 2
 LPC_NPARAMS = 2888
 LPC_CACHE_PER_ROW = 192
 
@@ -34,6 +35,7 @@ class Opts(C.Structure):
                 ("seed", C.c_uint64), ("precision", C.c_int), ("precond", C.c_int),
                 ("force_stage2", C.c_int), ("two_sided_cleanup", C.c_int),
                 ("print_level", C.c_int), ("profile", C.c_int), ("autotune", C.c_int),
+                ("method", C.c_int), ("relative_tol", C.c_int),
                 ("max_seconds", C.c_double), ("pc_degree", C.c_int), ("pc_model", C.c_void_p)]
 
 
@@ -96,6 +98,8 @@ def load_library():
     lib.svds_lpc_train.argtypes = [i32, vp, i32, i32, f32, vp, vp, vp]
     lib.svds_collect_residuals.argtypes = [vp, i32, i32, dbl, C.POINTER(Opts), i32, i32, vp, i64,
                                            C.POINTER(i32), C.POINTER(Stats), vp]
+    lib.svds_condest.argtypes = [vp, dbl, C.POINTER(Opts), C.POINTER(dbl), C.POINTER(dbl),
+                                 C.POINTER(dbl), vp, vp]
     lib.svds_small_eig.argtypes = [i32, vp, i64, i32, vp, vp, i64, vp]
     lib.svds_small_svd.argtypes = [i32, vp, i64, vp, vp, i64, vp]
     _lib = lib
@@ -425,3 +429,21 @@ def collect_residuals(M, k, target="smallest", tol=1e-10, every=1, max_pairs=64,
     d["status"] = rc
     d["converged"] = rc == 0
     return Rc[: cnt.value].t(), d
+
+
+def condest(M, rtol=0.1, stream=None, **opts):
+    """svds_condest on a prepared Matrix: (kappa, sigma_max, sigma_min,
+    (stats_largest, stats_smallest))."""
+    o = opts_init(**opts)
+    smax, smin, kap = C.c_double(), C.c_double(), C.c_double()
+    st = (Stats * 2)()
+    rc = load_library().svds_condest(M.handle, float(rtol), C.byref(o), C.byref(smax),
+                                     C.byref(smin), C.byref(kap), C.cast(st, C.c_void_p),
+                                     _stream(stream))
+    _check(rc, "condest")
+    out = []
+    for i in range(2):
+        d = st[i].to_dict()
+        d["status"] = rc
+        out.append(d)
+    return kap.value, smax.value, smin.value, tuple(out)

@@ -28,7 +28,7 @@ void sign_factors(const double* V, int64_t ldv, int64_t N, int k, double* partia
                   hipStream_t s);
 void sigma_from_lambda(int k, const double* lam, double* sig, double* inv, hipStream_t s);
 void stage1_check(int k, const double* rl2, const double* rr2, const double* sig, double normA,
-                  double tol, double* rn, double* taus, int* ok, hipStream_t s);
+                  double tol, int rel, double* rn, double* taus, int* ok, hipStream_t s);
 void sqrt_sum(int k, const double* a, const double* b, double* out, hipStream_t s);
 void inv_sqrt(int k, const double* x, double* f, hipStream_t s);
 void abs_vec(int k, const double* x, double* y, hipStream_t s);
@@ -597,6 +597,7 @@ int Solver::stage1(double* V1, double* U1, double* sig, double* rn, double* taus
     P.floor_resets = floor_resets;
     P.budget_hit = over_budget() ? 1 : 0;
     P.tol = tol1_;
+    P.rel = o_.relative_tol ? 1 : 0;
     P.normA = normA_;
     P.eps = kEps;
     P.gate = kFloorGate * kEps;
@@ -875,7 +876,7 @@ void Solver::final_rr(double* Xk, double* V1, double* U1, double* sig, double* r
   spmm_cols(At(), U1, ld_, m_, k_, AtU, ld_, n_);
   col_residual2(Wt_, ld_, U1, ld_, sig, m_, k_, partial_, rl2, s_);   // ||A v - s u||^2
   col_residual2(AtU, ld_, V1, ld_, sig, n_, k_, partial_, rr2, s_);   // ||A^T u - s v||^2
-  stage1_check(k_, rl2, rr2, sig, normA_, tol_, rn, taus, ok, s_);
+  stage1_check(k_, rl2, rr2, sig, normA_, tol_, o_.relative_tol ? 1 : 0, rn, taus, ok, s_);
 }
 
 // ---------------------------------------------------------------------------
@@ -942,6 +943,7 @@ int Solver::stage1_mixed(double* V1, double* U1, double* sig, double* rn, double
     P.floor_resets = floor_resets;
     P.budget_hit = over_budget() ? 1 : 0;
     P.tol = tol1_;
+    P.rel = o_.relative_tol ? 1 : 0;
     P.normA = normA_;
     P.eps = kEpsMixed;
     P.gate = std::min(kFloorGate * kEpsMixed, 1e-2);
@@ -1099,34 +1101,49 @@ int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, d
     mv_ = 0;
   }
   st->setup_seconds = now() - t0;
-  // ---- stage 1
-  int okh = 0, status1 = 2;
-  if (mixed_) {
-    stage1_mixed(V1, U1, sig, rn1, taus, ok, &status1, st);
-  } else {
-    stage1(V1, U1, sig, rn1, taus, ok, &status1, st);
-  }
-  SVDS_HIP(hipMemcpyAsync(&okh, ok, sizeof(int), hipMemcpyDeviceToHost, s_));
-  SVDS_HIP(hipStreamSynchronize(s_));
-  st->stage1_status = status1;
-  st->stage_exit = 1;
   int nconv = 0;
-  if (status1 != 2 && (o_.force_stage2 || !okh)) {
-    std::vector<double> th(k_);
-    SVDS_HIP(hipMemcpyAsync(th.data(), taus, sizeof(double) * k_, hipMemcpyDeviceToHost, s_));
-    SVDS_HIP(hipStreamSynchronize(s_));
+  if (o_.method == SVDS_METHOD_AUGMENTED) {
+    // stage 2 alone (largest values) from one counter-based block [v; u]
+    // of length n + m; no stage-1 bounds
+    fill_random(X_, ld_, n_ + m_, k_, o_.seed, kStreamInit, 0, s_);
+    copy_cols(X_, ld_, n_, k_, V1, ld_, s_);
+    copy_cols(X_ + n_, ld_, m_, k_, U1, ld_, s_);
+    std::vector<double> th(k_, normA_ * kEps);
+    st->stage1_status = 0;
     stage2(th.data(), V1, U1, sig, &nconv, st);
     st->stage_exit = 2;
+  } else {
+    // ---- stage 1
+    int okh = 0, status1 = 2;
+    if (mixed_) {
+      stage1_mixed(V1, U1, sig, rn1, taus, ok, &status1, st);
+    } else {
+      stage1(V1, U1, sig, rn1, taus, ok, &status1, st);
+    }
+    SVDS_HIP(hipMemcpyAsync(&okh, ok, sizeof(int), hipMemcpyDeviceToHost, s_));
+    SVDS_HIP(hipStreamSynchronize(s_));
+    st->stage1_status = status1;
+    st->stage_exit = 1;
+    if (o_.method == SVDS_METHOD_HYBRID && status1 != 2 && (o_.force_stage2 || !okh)) {
+      std::vector<double> th(k_);
+      SVDS_HIP(hipMemcpyAsync(th.data(), taus, sizeof(double) * k_, hipMemcpyDeviceToHost, s_));
+      SVDS_HIP(hipStreamSynchronize(s_));
+      stage2(th.data(), V1, U1, sig, &nconv, st);
+      st->stage_exit = 2;
+    }
   }
   cleanup_and_output(V1, U1, sig, sigma, U, ldu, V, ldv, rnorm);
-  std::vector<double> hr(k_);
+  std::vector<double> hr(k_), hs(k_);
   SVDS_HIP(hipMemcpyAsync(hr.data(), rnorm, sizeof(double) * k_, hipMemcpyDeviceToHost, s_));
+  SVDS_HIP(hipMemcpyAsync(hs.data(), sigma, sizeof(double) * k_, hipMemcpyDeviceToHost, s_));
   SVDS_HIP(hipStreamSynchronize(s_));
   int good = 0;
   bool finite = true;
-  for (double x : hr) {
-    good += x < normA_ * tol_;
-    finite = finite && std::isfinite(x);
+  for (int i = 0; i < k_; ++i) {
+    // eq. (res), or the relative rule of the condition estimate
+    const double lim = (o_.relative_tol ? hs[i] : normA_) * tol_;
+    good += hr[i] < lim;
+    finite = finite && std::isfinite(hr[i]);
   }
   st->nconv = good;
   st->norm_A_used = normA_;
@@ -1280,6 +1297,13 @@ int solve_prepared(const svds_matrix* h, int k, int target, double tol, const sv
     throw Error(SVDS_ERR_ARG, "precond");
   if (o.precond == SVDS_PC_LEARNED && (!o.pc_model || o.pc_degree < 0 || o.pc_degree > 15))
     throw Error(SVDS_ERR_ARG, "learned preconditioner: pc_model / pc_degree");
+  if (o.method != SVDS_METHOD_HYBRID && o.method != SVDS_METHOD_NORMAL &&
+      o.method != SVDS_METHOD_AUGMENTED)
+    throw Error(SVDS_ERR_ARG, "method");
+  if (o.method == SVDS_METHOD_AUGMENTED && target != SVDS_LARGEST)
+    throw Error(SVDS_ERR_ARG, "the augmented method alone seeks the largest values only");
+  if (o.relative_tol && o.method != SVDS_METHOD_NORMAL)
+    throw Error(SVDS_ERR_ARG, "the relative stopping rule needs the normal-equations method");
   svds_stats local;
   svds_stats* st = stats ? stats : &local;
   {
@@ -1611,6 +1635,38 @@ int svds_collect_residuals(const svds_matrix* A, int k, int target, double tol,
     SVDS_HIP(hipStreamSynchronize(s));
     *npairs = cap.count;
     return rc;
+  });
+}
+
+int svds_condest(const svds_matrix* A, double rtol, const svds_opts* opts, double* sigma_max,
+                 double* sigma_min, double* kappa, svds_stats* stats, void* stream) {
+  return guarded([&] {
+    if (!A || !sigma_max || !sigma_min || !kappa) throw Error(SVDS_ERR_ARG, "null argument");
+    if (!(rtol > 0.0 && rtol < 1.0)) rtol = 0.1;
+    svds_opts o = opts ? *opts : default_opts();
+    o.method = SVDS_METHOD_NORMAL;
+    o.relative_tol = 1;
+    o.block_size = 1;
+    hipStream_t s = (hipStream_t)stream;
+    svds::DeviceBuffers buf(s);
+    double* sig = buf.get<double>(1);
+    double* rn = buf.get<double>(1);
+    double* U = buf.get<double>((size_t)A->m);
+    double* V = buf.get<double>((size_t)A->n);
+    double h[2] = {0.0, 0.0};
+    int worst = SVDS_OK;
+    for (int t = 0; t < 2; ++t) {
+      const int rc = solve_prepared(A, 1, t == 0 ? SVDS_LARGEST : SVDS_SMALLEST, rtol, &o, sig, U,
+                                    A->m, V, A->n, rn, stats ? &stats[t] : nullptr, s);
+      if (rc < 0) return rc;
+      worst = std::max(worst, rc);
+      SVDS_HIP(hipMemcpyAsync(&h[t], sig, sizeof(double), hipMemcpyDeviceToHost, s));
+      SVDS_HIP(hipStreamSynchronize(s));
+    }
+    *sigma_max = h[0];
+    *sigma_min = h[1];
+    *kappa = h[1] > 0.0 ? h[0] / h[1] : INFINITY;
+    return worst;
   });
 }
 

@@ -21,14 +21,15 @@ void sigma_from_lambda(int k, const double* lam, double* sig, double* inv, hipSt
 // eq. (res) from the two squared halves; all-below-tolerance flag; stage-2
 // shifts max(sigma - sqrt(2)||r||, ||A|| eps) (||r^C|| = sigma ||r||)
 __global__ void k_stage1_check(int k, const double* rl2, const double* rr2, const double* sig,
-                               double normA, double tol, double* rn, double* taus, int* ok) {
+                               double normA, double tol, int rel, double* rn, double* taus,
+                               int* ok) {
   if (threadIdx.x != 0) return;
   int good = 1;
   for (int i = 0; i < k; ++i) {
     double r = sqrt(fmax(rl2[i], 0.0) + fmax(rr2[i], 0.0));
     if (!(sig[i] > 0.0)) r = INFINITY;
     rn[i] = r;
-    good = good && (r < normA * tol);
+    good = good && (r < (rel ? sig[i] : normA) * tol);
     const double rr = isfinite(r) ? r : sig[i];
     taus[i] = fmax(sig[i] - 1.4142135623730951 * rr, normA * kEps);
   }
@@ -36,8 +37,8 @@ __global__ void k_stage1_check(int k, const double* rl2, const double* rr2, cons
 }
 
 void stage1_check(int k, const double* rl2, const double* rr2, const double* sig, double normA,
-                  double tol, double* rn, double* taus, int* ok, hipStream_t s) {
-  k_stage1_check<<<1, 64, 0, s>>>(k, rl2, rr2, sig, normA, tol, rn, taus, ok);
+                  double tol, int rel, double* rn, double* taus, int* ok, hipStream_t s) {
+  k_stage1_check<<<1, 64, 0, s>>>(k, rl2, rr2, sig, normA, tol, rel, rn, taus, ok);
   SVDS_LAUNCH_CHECK();
 }
 

@@ -622,7 +622,8 @@ __global__ __launch_bounds__(kT) void k_control(Small* d, CtlParams P) {
       C.res[c] = rn[c];
       C.val[c] = th_s[c];
       if (P.stage == 1) {
-        const double thr = fmax(sqrt(fabs(th_s[c]) * nop) * P.tol, P.eps * nop);
+        const double thr = P.rel ? fmax(P.tol * fabs(th_s[c]), P.eps * nop)
+                                 : fmax(sqrt(fabs(th_s[c]) * nop) * P.tol, P.eps * nop);
         conv[c] = rn[c] <= thr;
         const bool pc = !conv[c] && stall_s[c] >= kStallRestarts && rn[c] <= P.gate * nop;
         done[c] = conv[c] || pc;

@@ -79,6 +79,7 @@ struct CtlParams {
   int nlock;        // stage 2: vectors locked so far
   int since_reset, floor_resets, budget_hit;
   int refined;
+  int rel;          // stage 1: converged when ||r^C|| <= tol |lambda| (relative rule)
   double tol, normA, eps;
   double gate;      // stalled pairs count as at the floor below gate * ||Op||
 };

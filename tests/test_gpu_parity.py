@@ -306,3 +306,53 @@ def test_autotuned_launch_shapes_agree(P):
     normA = out[0][4]["norm_A_used"]
     ref = out[0][0].cpu().numpy()
     _compare(A, *out[1][:4], out[1][4], ref, 1e-10, normA)
+
+
+def test_normal_method_stops_at_the_stage1_floor(P):
+    """Stage 1 alone on a kappa ~ 1e6 smallest problem ends above 1e-10 ||A||
+    on both sides; its values agree with the oracle's to the stage-1 level."""
+    A = synth.banded_scaled(300, 150, seed=1, log_lo=-6)
+    normA = float(np.linalg.norm(A.toarray(), 2))
+    _say("normal method banded_scaled 300x150 smallest")
+    sig, U, V, rn, st = P.svds(A, 2, "smallest", 1e-10, block_size=1, norm_A=normA, seed=7,
+                               precond=P.PC_JACOBI, method=P.METHOD_NORMAL)
+    ref, _, _, rr, sr = oracle.svds(A, 2, "smallest", 1e-10, block=1, seed=7, norm_A=normA,
+                                    precond="jacobi", method="normal")
+    assert st["stage_exit"] == 1 and not st["converged"] and not sr["converged"]
+    assert float(rn.max()) > 1e-10 * normA
+    assert np.max(np.abs(sig.cpu().numpy() - ref) / ref) < 1e-3
+
+
+def test_augmented_method_largest(P):
+    A = synth.config1()
+    normA = float(np.linalg.norm(A.toarray(), 2))
+    _say("augmented method config1 largest")
+    sig, U, V, rn, st = P.svds(A, 5, "largest", 1e-10, max_basis_size=15, min_restart_size=6,
+                               norm_A=normA, seed=11, method=P.METHOD_AUGMENTED)
+    ref, _, _, _, sr = oracle.svds(A, 5, "largest", 1e-10, max_basis=15, min_restart=6,
+                                   norm_A=normA, seed=11, method="augmented")
+    assert st["converged"] and st["stage_exit"] == 2 and st["matvecs"][0] == 0
+    _compare(A, sig, U, V, rn, st, ref, 1e-10, normA)
+
+
+def test_condition_estimate(P):
+    sigma = np.geomspace(1e-4, 1.0, 60)
+    A, _, _, _ = synth.prescribed_dense(90, 60, sigma, seed=5)
+    _say("condest prescribed 90x60 kappa 1e4")
+    M = P.Matrix.from_scipy(A)
+    kappa, smax, smin, (s1, s0) = P.condest(M, 0.1, seed=1)
+    k_ref, smax_ref, smin_ref, _ = oracle.condest(A, 0.1, seed=1)
+    assert abs(smax - 1.0) < 0.1 and abs(smin - 1e-4) / 1e-4 < 0.1
+    assert abs(kappa - 1e4) / 1e4 < 0.2
+    assert abs(smax - smax_ref) / smax_ref < 0.05 and abs(smin - smin_ref) / smin_ref < 0.05
+    assert s1["stage_exit"] == 1 and s0["stage_exit"] == 1
+    M.close()
+
+
+def test_method_argument_errors(P):
+    A = synth.config1(m=60, n=30, nnz_per_row=4)
+    _say("method argument errors")
+    for kw in (dict(method=P.METHOD_AUGMENTED), dict(relative_tol=1), dict(method=7)):
+        with pytest.raises(P.SvdsError) as e:
+            P.svds(A, 2, "smallest", 1e-10, **kw)
+        assert e.value.code == -1
