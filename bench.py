@@ -218,6 +218,73 @@ def learned_extra(P, torch, full_seconds):
         MB.close()
     for M, _ in sets:
         M.close()
+    return out, params
+
+
+def methods_extra(P, torch, cap):
+    """Single-stage methods against the two-stage method (Section 3.4):
+    smallest triplets of an ill-conditioned banded matrix (normal equations
+    alone vs hybrid) and largest triplets of a power-law matrix (normal,
+    augmented, hybrid)."""
+    import synth
+    out = {}
+    cases = [
+        ("smallest_banded_2e5x1e5_kappa1e6",
+         lambda: synth.banded_scaled(200000, 100000, seed=2005, log_lo=-6.0), 5, "smallest",
+         dict(block_size=4, max_basis_size=35, min_restart_size=14, precond=P.PC_JACOBI, seed=2005),
+         (("hybrid", P.METHOD_HYBRID), ("normal", P.METHOD_NORMAL))),
+        ("largest_powerlaw_2e5x1e5",
+         lambda: synth.powerlaw_rows(200000, 100000, seed=2006), 10, "largest",
+         dict(block_size=4, max_basis_size=35, min_restart_size=14, seed=2006),
+         (("hybrid", P.METHOD_HYBRID), ("normal", P.METHOD_NORMAL),
+          ("augmented", P.METHOD_AUGMENTED))),
+    ]
+    for label, gen, k, target, opts, methods in cases:
+        A = gen()
+        M = P.Matrix.from_scipy(A)
+        res = {"shape": list(A.shape), "nnz": int(A.nnz), "k": k, "target": target,
+               "max_seconds": cap}
+        for name, meth in methods:
+            log(f"methods extra: {label} {name}")
+            M.solve(k, target, 1e-10, method=meth, max_seconds=cap, **opts)  # warm-up
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            sig, U, V, rn, st = M.solve(k, target, 1e-10, method=meth, max_seconds=cap, **opts)
+            torch.cuda.synchronize()
+            res[name] = {"seconds": time.perf_counter() - t, "converged": bool(st["converged"]),
+                         "max_rnorm_over_normA": float(rn.max()) / st["norm_A_used"],
+                         "matvecs": st["matvecs"], "iters": st["iters"],
+                         "stage_exit": st["stage_exit"]}
+        out[label] = res
+        M.close()
+    return out
+
+
+def condest_extra(P, torch, main_matrix, learned_params):
+    """Condition-number estimate of Section 4.4 (block 1, stage 1 stopped at
+    ||r|| < 0.1 sigma): the banded 1e6 x 5e5 matrix with Jacobi, and the
+    128 x 128 convection-diffusion field with Jacobi and with the learned
+    preconditioner."""
+    import synth
+    out = {}
+    runs = [("banded_1e6x5e5_jacobi", main_matrix, dict(precond=P.PC_JACOBI, seed=7))]
+    B = synth.config5(ng=128, seed=5000)
+    MB = P.Matrix.from_scipy(B)
+    runs.append(("convdiff_128x128_jacobi", MB, dict(precond=P.PC_JACOBI, seed=7)))
+    if learned_params is not None:
+        runs.append(("convdiff_128x128_learned", MB,
+                     dict(precond=P.PC_LEARNED, pc_model=learned_params, pc_degree=15, seed=7)))
+    for label, M, kw in runs:
+        log(f"condest extra: {label}")
+        P.condest(M, 0.1, **kw)  # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        kappa, smax, smin, (s1, s0) = P.condest(M, 0.1, **kw)
+        torch.cuda.synchronize()
+        out[label] = {"seconds": time.perf_counter() - t, "kappa": kappa, "sigma_max": smax,
+                      "sigma_min": smin,
+                      "matvecs": int(sum(s1["matvecs"]) + sum(s0["matvecs"]))}
+    MB.close()
     return out
 
 
@@ -335,8 +402,13 @@ def main():
         res["mixed_precision"] = mixed_comparison(P, torch)
         if args.batched > 0:
             res["batched"] = batched_extra(P, torch, args.batched)
+        params = None
         if not args.no_learned:
-            res["learned_preconditioner"] = learned_extra(P, torch, args.full_seconds)
+            res["learned_preconditioner"], params = learned_extra(P, torch, args.full_seconds)
+        res["methods"] = methods_extra(P, torch, 30.0)
+        Mmain = P.Matrix(ip, ix, dv, m, n)
+        res["condition_estimate"] = condest_extra(P, torch, Mmain, params)
+        Mmain.close()
     if not args.no_cpu:
         gpu_mv = int(sum(st["matvecs"]))
         log("cpu baseline (oracle) ...")

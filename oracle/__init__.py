@@ -18,6 +18,7 @@ from .phsvds import (  # noqa: F401
     estimate_norm,
     ortho_block,
     jacobi_diag,
+    block_jacobi,
     svds,
     svd_residuals,
     condest,

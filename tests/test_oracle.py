@@ -305,3 +305,35 @@ def test_condition_estimate_within_ten_percent():
     assert abs(kappa - 1e4) / 1e4 < 0.2
     assert st1["converged"] and st0["converged"]
     assert st1["stage_exit"] == 1 and st0["stage_exit"] == 1
+
+
+def test_block_jacobi_pins():
+    """Block size 1 is point Jacobi; blocks that cover whole independent
+    column groups give the exact inverse of C; a block covering all columns
+    is C^-1."""
+    A = synth.config1(m=120, n=50, nnz_per_row=6)
+    R = np.random.default_rng(1).standard_normal((50, 3))
+    d = oracle.jacobi_diag(A)
+    assert np.allclose(oracle.block_jacobi(A, 1)(R), R / d[:, None], rtol=1e-13)
+    C = (A.T @ A).toarray()
+    assert np.allclose(oracle.block_jacobi(A, 64)(C @ R), R, rtol=1e-9, atol=1e-9)
+    Bd, blocks = synth.block_diagonal(4, 30, 10, seed=2)  # 120 x 40, four 10-column groups
+    Cb = (Bd.T @ Bd).toarray()
+    Rb = np.random.default_rng(2).standard_normal((40, 2))
+    assert np.allclose(oracle.block_jacobi(Bd, 10)(Cb @ Rb), Rb, rtol=1e-9, atol=1e-9)
+    # an empty column keeps a unit scale
+    E = synth.to_csr(sp.hstack([A[:, :10], sp.csr_matrix((120, 1)), A[:, 10:20]]))
+    K = oracle.block_jacobi(E, 8)
+    e = np.zeros((21, 1)); e[10] = 1.0
+    assert np.allclose(K(e)[:, 0], e[:, 0])
+
+
+def test_block_jacobi_solve_beats_point_jacobi():
+    A = synth.config5(ng=16, seed=5001)
+    s_ref = np.sort(np.linalg.svd(A.toarray(), compute_uv=False))[:4]
+    s1, _, _, _, st1 = oracle.svds(A, 4, "smallest", 1e-10, block=1, seed=1, precond="jacobi")
+    s2, _, _, _, st2 = oracle.svds(A, 4, "smallest", 1e-10, block=1, seed=1,
+                                   precond="blockjacobi", pc_block=32)
+    assert st1["converged"] and st2["converged"]
+    assert np.max(np.abs(s2 - s_ref) / s_ref) < 1e-9
+    assert st2["iters"][0] < st1["iters"][0]
