@@ -197,6 +197,7 @@ def learned_extra(P, torch, full_seconds):
                         "collect_seconds": collect, "train_seconds": train, "steps": 200,
                         "degree": degree, "loss_first": float(hist[0]), "loss_last": float(hist[-1])}}
     runs = [("none", dict(precond=P.PC_NONE)), ("jacobi", dict(precond=P.PC_JACOBI)),
+            ("block_jacobi_128", dict(precond=P.PC_BLOCKJACOBI, pc_block=128)),
             ("learned", dict(precond=P.PC_LEARNED, pc_model=params, pc_degree=degree))]
     for label, ng, cap in (("replica_128x128", 128, 60.0), ("full_1024x1024", 1024, full_seconds)):
         B = synth.config5(ng=ng, seed=5000)
@@ -271,6 +272,8 @@ def condest_extra(P, torch, main_matrix, learned_params):
     B = synth.config5(ng=128, seed=5000)
     MB = P.Matrix.from_scipy(B)
     runs.append(("convdiff_128x128_jacobi", MB, dict(precond=P.PC_JACOBI, seed=7)))
+    runs.append(("convdiff_128x128_block_jacobi_128", MB,
+                 dict(precond=P.PC_BLOCKJACOBI, pc_block=128, seed=7)))
     if learned_params is not None:
         runs.append(("convdiff_128x128_learned", MB,
                      dict(precond=P.PC_LEARNED, pc_model=learned_params, pc_degree=15, seed=7)))

@@ -65,6 +65,11 @@ extern "C" {
                                 /* m < n); on B the composition              */
                                 /* [K A^T y_u; A K y_v] (applyPreconditioner */
                                 /* modes AtA / augmented, Section 3.4)       */
+#define SVDS_PC_BLOCKJACOBI 3   /* K = inverses of the diagonal blocks of    */
+                                /* A^T A over contiguous ranges of           */
+                                /* opts.pc_block columns (Section 4's        */
+                                /* generic preconditioner), same composition */
+                                /* on B                                      */
 #define SVDS_PC_LEARNED 2       /* K = the learned polynomial preconditioner */
                                 /* of opts.pc_model (svds_lpc_* below), with */
                                 /* the same composition on B                 */
@@ -121,6 +126,8 @@ typedef struct svds_opts {
                           /* Section 4.4); needs SVDS_METHOD_NORMAL         */
   double max_seconds;     /* wall-clock budget of the solve (> 0), checked  */
                           /* once per iteration like max_matvecs; 0: none  */
+  int pc_block;           /* SVDS_PC_BLOCKJACOBI: columns per block, 1..128;*/
+                          /* 0 -> 64                                        */
   int pc_degree;          /* SVDS_PC_LEARNED: polynomial degree d, 1..15;   */
                           /* 0 -> 8                                         */
   const float* pc_model;  /* SVDS_PC_LEARNED: device array of               */
@@ -296,6 +303,12 @@ int svds_collect_residuals(const svds_matrix* A, int k, int target, double tol,
                            int64_t ldr, int* npairs, svds_stats* stats, void* stream);
 
 /* ---- single steps of the iteration (used by parity tests) ----------------- */
+/* T = K R with the block-Jacobi preconditioner of blocks of nb (1..128)
+ * columns (SVDS_PC_BLOCKJACOBI), for b <= 8 vectors of length N = min(m, n)
+ * (column-major FP64; T may equal R).  Builds the block inverses each call. */
+int svds_blockjacobi_apply(const svds_matrix* A, int nb, int b, const double* R, int64_t ldr,
+                           double* T, int64_t ldt, void* stream);
+
 /* Symmetric eigenproblem of the g x g projected matrix (Section 3.3: the
  * small replicated problem), 1 <= g <= 64, on the device: H (ld ldh >= g),
  * theta (g) and Y (g x g, ld ldy >= g) in ascending (descending != 0:

@@ -13,10 +13,12 @@ from ._lib import (  # noqa: F401
     PC_NONE,
     PC_JACOBI,
     PC_LEARNED,
+    PC_BLOCKJACOBI,
     METHOD_HYBRID,
     METHOD_NORMAL,
     METHOD_AUGMENTED,
     condest,
+    blockjacobi_apply,
     LPC_NPARAMS,
     SvdsError,
     Opts,

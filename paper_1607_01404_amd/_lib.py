@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 LARGEST, SMALLEST = 0, 1
 FP64, MIXED = 0, 1
-PC_NONE, PC_JACOBI, PC_LEARNED = 0, 1, 2
+PC_NONE, PC_JACOBI, PC_LEARNED, PC_BLOCKJACOBI = 0, 1, 2, 3
 METHOD_HYBRID, METHOD_NORMAL, METHOD_AUGMENTED = 0, 1, 2
 LPC_NPARAMS = 2888
 LPC_CACHE_PER_ROW = 192
@@ -36,7 +36,8 @@ class Opts(C.Structure):
                 ("force_stage2", C.c_int), ("two_sided_cleanup", C.c_int),
                 ("print_level", C.c_int), ("profile", C.c_int), ("autotune", C.c_int),
                 ("method", C.c_int), ("relative_tol", C.c_int),
-                ("max_seconds", C.c_double), ("pc_degree", C.c_int), ("pc_model", C.c_void_p)]
+                ("max_seconds", C.c_double), ("pc_block", C.c_int), ("pc_degree", C.c_int),
+                ("pc_model", C.c_void_p)]
 
 
 class Stats(C.Structure):
@@ -100,6 +101,7 @@ def load_library():
                                            C.POINTER(i32), C.POINTER(Stats), vp]
     lib.svds_condest.argtypes = [vp, dbl, C.POINTER(Opts), C.POINTER(dbl), C.POINTER(dbl),
                                  C.POINTER(dbl), vp, vp]
+    lib.svds_blockjacobi_apply.argtypes = [vp, i32, i32, vp, i64, vp, i64, vp]
     lib.svds_small_eig.argtypes = [i32, vp, i64, i32, vp, vp, i64, vp]
     lib.svds_small_svd.argtypes = [i32, vp, i64, vp, vp, i64, vp]
     _lib = lib
@@ -447,3 +449,13 @@ def condest(M, rtol=0.1, stream=None, **opts):
         d["status"] = rc
         out.append(d)
     return kap.value, smax.value, smin.value, tuple(out)
+
+
+def blockjacobi_apply(M, nb, R, stream=None):
+    """T = K R with the block-Jacobi preconditioner (blocks of nb columns)."""
+    Rc = _colmajor(R)
+    N, b = R.shape
+    T = Rc.clone()
+    _check(load_library().svds_blockjacobi_apply(M.handle, int(nb), b, _ptr(Rc), N, _ptr(T), N,
+                                                 _stream(stream)), "blockjacobi_apply")
+    return T.t()

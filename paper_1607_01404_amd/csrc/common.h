@@ -244,6 +244,11 @@ void scale_rows(double* T, int64_t ldt, int64_t N, int b, const double* dinv, hi
 void copy_cols(const double* A, int64_t lda, int64_t N, int b, double* B, int64_t ldb,
                hipStream_t s);
 
+// block-Jacobi preconditioner of C: K holds ceil(N/nb) blocks of nb x nb
+void bj_setup(const svds_matrix* M, int nb, double* K, hipStream_t s);
+void bj_apply(const double* K, int nb, int64_t N, int b, const double* R, int64_t ldr, double* T,
+              int64_t ldt, hipStream_t s);
+
 // small single-workgroup kernels (all on device, FP64)
 struct SmallState;  // defined in small.h
 }  // namespace svds

@@ -89,6 +89,9 @@ class Solver {
 
  private:
   Capture* cap_ = nullptr;
+  // block-Jacobi preconditioner: inverses of the diagonal blocks of C
+  double* bjK_ = nullptr;
+  int bjnb_ = 0;
   // learned preconditioner
   bool learned_ = false;
   int ldeg_ = 0;
@@ -392,30 +395,29 @@ class Solver {
                  nc > 0 ? c.res[0] : 0.0, c.maxres, nc > 0 ? c.val[0] : 0.0, (long long)mv_);
   }
 
+  // T (the first n_ rows of nb columns, leading dimension ld_) <- K T with
+  // the preconditioner of C (point Jacobi, learned polynomial, block Jacobi)
+  void apply_pc(double* T, int nb) {
+    switch (o_.precond) {
+      case SVDS_PC_JACOBI: scale_rows(T, ld_, n_, nb, dinv_, s_); break;
+      case SVDS_PC_LEARNED: learned_apply(T, nb); break;
+      case SVDS_PC_BLOCKJACOBI: bj_apply(bjK_, bjnb_, n_, nb, T, ld_, T, ld_, s_); break;
+      default: break;
+    }
+  }
+
   // preconditioner for the stage-2 block: [K A^T r_u; A K r_v] (pseudo-inverse
   // of B with (A^T A)^-1 ~ K), or the identity
   void precond_stage2(double* T, int nb) {
     gather_precond(R_, ld_, d_->blk, nb, nullptr, N_, T, ld_, s_);
-    if (learned_) {
-      lpc_apply(lop_, lcoef_, ldeg_, nb, T, ld_, T, ld_, lsc_, s_);  // T_v <- K r_v
-      pack_rows(T, ld_, nullptr, 0.0, n_, nb, Tc_, s_);               // K r_v (n x nb)
-      pack_rows(T + n_, ld_, nullptr, 0.0, m_, nb, Yc_, s_);          // r_u (m x nb)
-      spmm(At(), nb, Yc_, Wc_, s_);                                   // A^T r_u
-      spmm(A(), nb, Tc_, Yc_, s_);                                    // A K r_v
-      unpack_rows(Wc_, n_, nb, T, ld_, s_);
-      lpc_apply(lop_, lcoef_, ldeg_, nb, T, ld_, T, ld_, lsc_, s_);  // K A^T r_u
-      unpack_rows(Yc_, m_, nb, T + n_, ld_, s_);
-      mv_ += 2 * nb + 4 * (int64_t)ldeg_ * nb;
-      return;
-    }
-    if (o_.precond != SVDS_PC_JACOBI) return;
-    scale_rows(T, ld_, n_, nb, dinv_, s_);                  // T_v <- K r_v
+    if (o_.precond == SVDS_PC_NONE) return;
+    apply_pc(T, nb);                                        // T_v <- K r_v
     pack_rows(T, ld_, nullptr, 0.0, n_, nb, Tc_, s_);       // K r_v (n x nb)
     pack_rows(T + n_, ld_, nullptr, 0.0, m_, nb, Yc_, s_);  // r_u (m x nb)
     spmm(At(), nb, Yc_, Wc_, s_);                           // A^T r_u (n x nb)
     spmm(A(), nb, Tc_, Yc_, s_);                            // A K r_v (m x nb)
     unpack_rows(Wc_, n_, nb, T, ld_, s_);
-    scale_rows(T, ld_, n_, nb, dinv_, s_);                  // K A^T r_u
+    apply_pc(T, nb);                                        // K A^T r_u
     unpack_rows(Yc_, m_, nb, T + n_, ld_, s_);
     mv_ += 2 * nb;
   }
@@ -635,7 +637,7 @@ int Solver::stage1(double* V1, double* U1, double* sig, double* rn, double* taus
     } else {
       gather_precond(R_, ld_, d_->blk, nb, o_.precond == SVDS_PC_JACOBI ? dinv_ : nullptr, N_, T,
                      ld_, s_);
-      if (learned_) learned_apply(T, nb);
+      if (o_.precond != SVDS_PC_JACOBI) apply_pc(T, nb);
     }
     Seg sv{V_, gc_, ld_};
     ortho_enqueue(T, ld_, nb, &sv, 1, Tc_);
@@ -978,7 +980,7 @@ int Solver::stage1_mixed(double* V1, double* U1, double* sig, double* rn, double
     } else {
       gather_precond(R_, ld_, d_->blk, nb, o_.precond == SVDS_PC_JACOBI ? dinv_ : nullptr, N_,
                      Tb_, ld_, s_);
-      if (learned_) learned_apply(Tb_, nb);
+      if (o_.precond != SVDS_PC_JACOBI) apply_pc(Tb_, nb);
     }
     Seg32 sv{V32_, gc_, ld_};
     ortho_enqueue(Tb_, ld_, nb, &sv, 1, (double*)nullptr);
@@ -1092,6 +1094,11 @@ int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, d
     SVDS_HIP(hipMemcpyAsync(dinv_, hd.data(), sizeof(double) * n_, hipMemcpyHostToDevice, s_));
   }
   if (o_.precond == SVDS_PC_LEARNED) setup_learned();
+  if (o_.precond == SVDS_PC_BLOCKJACOBI) {
+    bjnb_ = o_.pc_block > 0 ? o_.pc_block : 64;
+    bjK_ = buf_.get<double>((size_t)((n_ + bjnb_ - 1) / bjnb_) * bjnb_ * bjnb_);
+    bj_setup(M_, bjnb_, bjK_, s_);
+  }
   SVDS_HIP(hipMemsetAsync(d_, 0, sizeof(Small), s_));
   // ---- ||A||
   if (o_.norm_A > 0) {
@@ -1293,8 +1300,11 @@ int solve_prepared(const svds_matrix* h, int k, int target, double tol, const sv
   if (ldu < h->m || ldv < h->n) throw Error(SVDS_ERR_ARG, "leading dimension too small");
   svds_opts o = opts ? *opts : default_opts();
   if (o.precision != SVDS_FP64 && o.precision != SVDS_MIXED) throw Error(SVDS_ERR_ARG, "precision");
-  if (o.precond != SVDS_PC_NONE && o.precond != SVDS_PC_JACOBI && o.precond != SVDS_PC_LEARNED)
+  if (o.precond != SVDS_PC_NONE && o.precond != SVDS_PC_JACOBI && o.precond != SVDS_PC_LEARNED &&
+      o.precond != SVDS_PC_BLOCKJACOBI)
     throw Error(SVDS_ERR_ARG, "precond");
+  if (o.precond == SVDS_PC_BLOCKJACOBI && (o.pc_block < 0 || o.pc_block > 128))
+    throw Error(SVDS_ERR_ARG, "block-Jacobi block size 1..128");
   if (o.precond == SVDS_PC_LEARNED && (!o.pc_model || o.pc_degree < 0 || o.pc_degree > 15))
     throw Error(SVDS_ERR_ARG, "learned preconditioner: pc_model / pc_degree");
   if (o.method != SVDS_METHOD_HYBRID && o.method != SVDS_METHOD_NORMAL &&
@@ -1667,6 +1677,23 @@ int svds_condest(const svds_matrix* A, double rtol, const svds_opts* opts, doubl
     *sigma_min = h[1];
     *kappa = h[1] > 0.0 ? h[0] / h[1] : INFINITY;
     return worst;
+  });
+}
+
+int svds_blockjacobi_apply(const svds_matrix* A, int nb, int b, const double* R, int64_t ldr,
+                           double* T, int64_t ldt, void* stream) {
+  return guarded([&] {
+    if (!A || !R || !T || b < 1 || b > svds::kMaxBlock || nb < 1 || nb > 128)
+      throw Error(SVDS_ERR_ARG, "bad argument");
+    const int64_t N = A->A.cols;
+    if (ldr < N || ldt < N) throw Error(SVDS_ERR_ARG, "leading dimension");
+    hipStream_t s = (hipStream_t)stream;
+    svds::DeviceBuffers buf(s);
+    double* K = buf.get<double>((size_t)((N + nb - 1) / nb) * nb * nb);
+    svds::bj_setup(A, nb, K, s);
+    svds::bj_apply(K, nb, N, b, R, ldr, T, ldt, s);
+    SVDS_HIP(hipStreamSynchronize(s));
+    return SVDS_OK;
   });
 }
 
