@@ -22,4 +22,5 @@ from .phsvds import (  # noqa: F401
     svds,
     svd_residuals,
     condest,
+    minres,
 )

@@ -560,8 +560,55 @@ def _halves_residual(x, w, theta, n):
     return math.sqrt(np.linalg.norm(Av - s * u) ** 2 + np.linalg.norm(Atu - s * v) ** 2)
 
 
+def minres(Mop, rhs, tol, maxit):
+    """MINRES (Paige and Saunders, 1975) for a symmetric, possibly indefinite
+    operator, from x0 = 0: Lanczos vectors q_k, the QR factorisation of the
+    tridiagonal projection by Givens rotations, and the update
+    x_k = x_{k-1} + tau_k d_k.  Stops after maxit steps or when the residual
+    norm |phi| falls to tol * ||rhs||."""
+    rhs = np.asarray(rhs, dtype=np.float64)
+    x = np.zeros_like(rhs)
+    beta1 = float(np.linalg.norm(rhs))
+    if beta1 == 0.0:
+        return x, 0
+    q_prev = np.zeros_like(rhs)
+    q = rhs / beta1
+    d1 = np.zeros_like(rhs)
+    d2 = np.zeros_like(rhs)
+    c1, s1, c2, s2 = 1.0, 0.0, 1.0, 0.0   # rotations k-1 and k-2
+    beta = 0.0                           # coupling of q_k to q_{k-1}
+    phi = beta1
+    its = 0
+    for _ in range(maxit):
+        z = Mop(q)
+        alpha = float(q @ z)
+        z = z - alpha * q - beta * q_prev
+        beta_next = float(np.linalg.norm(z))
+        eps = s2 * beta                  # entry two rows above the diagonal
+        dlt = c2 * beta
+        delta = c1 * dlt + s1 * alpha    # entry one row above the diagonal
+        gbar = -s1 * dlt + c1 * alpha
+        gamma = math.hypot(gbar, beta_next)
+        its += 1
+        if gamma == 0.0:
+            break
+        c, sn = gbar / gamma, beta_next / gamma
+        tk = c * phi
+        phi = -sn * phi
+        dn = (q - delta * d1 - eps * d2) / gamma
+        x = x + tk * dn
+        d2, d1 = d1, dn
+        c2, s2, c1, s1 = c1, s1, c, sn
+        q_prev = q
+        q = z / beta_next if beta_next > 0.0 else np.zeros_like(z)
+        beta = beta_next
+        if abs(phi) <= tol * beta1 or beta_next == 0.0:
+            break
+    return x, its
+
+
 def _stage2(ops, k, target, tol, normA, g, r, b, p, seed, precond, budget, stats, rand_state,
-            sig1, U1, V1, rn1, trace=None):
+            sig1, U1, V1, rn1, trace=None, solver="gdk", jd_maxit=20, jd_tol=0.1):
     n, m = ops.n, ops.m
     N = n + m
     g = min(g, N)
@@ -670,7 +717,28 @@ def _stage2(ops, k, target, tol, normA, g, r, b, p, seed, precond, budget, stats
             Yb = Yr.T @ Yb
             restarts += 1
             since_reset += 1
-        T = K(R[:, block])
+        if solver == "jd":
+            # Jacobi-Davidson correction (the second stage's default solver of
+            # the paper): (I - QQ^T)(B - s I)(I - QQ^T) t = r with Q the locked
+            # vectors and the block's Ritz vectors, s the active shift (refined)
+            # or the Ritz value, solved approximately by MINRES; the sign of t
+            # does not matter for the expansion
+            Q = np.hstack([S.X, X[:, block]])
+            T = np.empty((N, len(block)))
+            for jj, j in enumerate(block):
+                shift = tau if refined else lam[j]
+
+                def Mop(y, shift=shift):
+                    y = y - Q @ (Q.T @ y)
+                    z = ops.B(y[:, None])[:, 0] - shift * y
+                    return z - Q @ (Q.T @ z)
+
+                rj = R[:, j] - Q @ (Q.T @ R[:, j])
+                T[:, jj], its = minres(Mop, rj, jd_tol, jd_maxit)
+                stats.setdefault("inner_iters", 0)
+                stats["inner_iters"] += its
+        else:
+            T = K(R[:, block])
         T, _, _ = ortho_block(T, [S.X, S.V], rand_next)
         y_prev = Yb
         S.append(T)
@@ -741,7 +809,8 @@ def _sign_normalise(U, V):
 def svds(A, k, target="largest", tol=1e-10, *, max_basis=None, min_restart=None, block=None,
          prev_retain=None, max_matvecs=None, norm_A=None, seed=0, precond="none",
          force_stage2=False, cleanup=True, stage1_tol=None, trace=None, time_limit=None,
-         capture=None, method="hybrid", relative=False, pc_block=64):
+         capture=None, method="hybrid", relative=False, pc_block=64, stage2_solver="gdk",
+         jd_maxit=20, jd_tol=0.1):
     """k largest or smallest singular triplets of the sparse matrix A with
     eq. (res) residual below tol*||A||.  Returns (sigma, U, V, rnorm, stats);
     U is m x k, V is n x k, both in target order with the largest-magnitude
@@ -764,7 +833,10 @@ def svds(A, k, target="largest", tol=1e-10, *, max_basis=None, min_restart=None,
     shifts need the stage-1 bounds) -- the single-stage methods of
     Section 3.4.  ``relative``: the stopping rule
     ||r|| <= tol * sigma of the low-accuracy condition estimate (Section 4.4);
-    only with method "normal"."""
+    only with method "normal".  ``stage2_solver``: "gdk" (GD+k, the default
+    here) or "jd" (Jacobi-Davidson with at most ``jd_maxit`` MINRES steps to
+    a residual reduction of ``jd_tol``, unpreconditioned; the paper's second
+    stage defaults to JDQMR, Section 3.4)."""
     t0 = time.perf_counter()
     if target not in ("largest", "smallest"):
         raise ValueError("target must be 'largest' or 'smallest'")
@@ -838,7 +910,8 @@ def svds(A, k, target="largest", tol=1e-10, *, max_basis=None, min_restart=None,
         # ---- stage 2 on B
         mv0 = ops.mv
         sig, U, V, nconv, status2 = _stage2(ops, k, target, tol, normA, g, r, b, p, seed, pc,
-                                            budget, stats, rand_state, sig, U, V, rn, trace)
+                                            budget, stats, rand_state, sig, U, V, rn, trace,
+                                            stage2_solver, jd_maxit, jd_tol)
         stats["matvecs"][1] = ops.mv - mv0
         stats["stage_exit"] = 2
         stats["seconds"][1] = time.perf_counter() - t1

@@ -337,3 +337,40 @@ def test_block_jacobi_solve_beats_point_jacobi():
     assert st1["converged"] and st2["converged"]
     assert np.max(np.abs(s2 - s_ref) / s_ref) < 1e-9
     assert st2["iters"][0] < st1["iters"][0]
+
+
+def test_minres_is_the_minimal_residual_krylov_iterate():
+    """After k steps MINRES returns argmin ||b - M x|| over the Krylov space
+    K_k(M, b) (its definition), computed here by least squares on an explicit
+    orthonormal Krylov basis; with n steps it solves the system."""
+    rng = np.random.default_rng(3)
+    n = 30
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    ev = np.concatenate([-np.linspace(1, 3, 10), np.linspace(0.5, 4, 20)])  # indefinite
+    M = (Q * ev) @ Q.T
+    b = rng.standard_normal(n)
+    for k in (1, 3, 6):
+        x, its = oracle.minres(lambda y: M @ y, b, 0.0, k)
+        Kb = np.column_stack([np.linalg.matrix_power(M, j) @ b for j in range(k)])
+        Bq, _ = np.linalg.qr(Kb)
+        c, *_ = np.linalg.lstsq(M @ Bq, b, rcond=None)
+        assert its == k
+        assert np.allclose(x, Bq @ c, rtol=1e-8, atol=1e-10)
+    x, _ = oracle.minres(lambda y: M @ y, b, 1e-14, 200)
+    assert np.allclose(M @ x, b, atol=1e-10)
+
+
+@pytest.mark.parametrize("target", ["largest", "smallest"])
+def test_jacobi_davidson_stage2(target):
+    A = synth.config1()
+    normA = float(np.linalg.norm(A.toarray(), 2))
+    s_all = np.linalg.svd(A.toarray(), compute_uv=False)
+    ref = s_all[:5] if target == "largest" else np.sort(s_all)[:5]
+    s, U, V, rn, st = oracle.svds(A, 5, target, 1e-10, max_basis=15, min_restart=6, norm_A=normA,
+                                  seed=11, force_stage2=True, stage2_solver="jd")
+    assert st["converged"] and st["stage_exit"] == 2
+    assert np.max(np.abs(s - ref) / ref) < 1e-10
+    s2, _, _, _, st2 = oracle.svds(A, 5, target, 1e-10, max_basis=15, min_restart=6, norm_A=normA,
+                                   seed=5, stage1_tol=1e-4, stage2_solver="jd")
+    assert st2["converged"] and st2["stage_exit"] == 2 and st2["inner_iters"] > 0
+    assert np.max(np.abs(s2 - ref) / ref) < 1e-10
