@@ -81,6 +81,16 @@ extern "C" {
                                  /* largest values only                     */
                                  /* (primme_svds_augmented; Section 3.4)    */
 
+#define SVDS_STAGE2_GDK 0        /* second stage: GD+k (default)            */
+#define SVDS_STAGE2_JD 1         /* second stage: Jacobi-Davidson, the       */
+                                 /* correction equation (I - QQ^T)(B - s I)  */
+                                 /* (I - QQ^T) t = r (Q: locked and block    */
+                                 /* Ritz vectors; s: the stage-1 bound for   */
+                                 /* the smallest values, the Ritz value for  */
+                                 /* the largest) solved by MINRES, the       */
+                                 /* paper's default second stage (JDQMR,     */
+                                 /* Section 3.4) without preconditioner      */
+
 /* ---- CSR matrix (device arrays, caller-owned, read-only) ----------------- */
 typedef struct svds_csr {
   int64_t m, n, nnz;
@@ -121,6 +131,9 @@ typedef struct svds_opts {
                           /* the block width and keep the fastest; 0: use   */
                           /* the row-length rule of thumb                   */
   int method;             /* SVDS_METHOD_*                                  */
+  int stage2_solver;      /* SVDS_STAGE2_GDK or SVDS_STAGE2_JD              */
+  int jd_max_inner;       /* JD: MINRES steps per correction; 0 -> 20       */
+  double jd_inner_tol;    /* JD: stop at this residual reduction; 0 -> 0.1  */
   int relative_tol;       /* 1: converged when ||r|| < tol * sigma (the     */
                           /* stopping rule of the condition estimate,       */
                           /* Section 4.4); needs SVDS_METHOD_NORMAL         */
@@ -153,6 +166,7 @@ typedef struct svds_stats {
   double spmm_seconds;    /* their summed duration (HIP events)             */
   double spmm_bytes;      /* their algorithmic bytes: nnz*(8+4) + 4*(rows+1)*/
                           /* + 8*b*(rows + cols) per call                   */
+  int64_t inner_iters;    /* JD second stage: MINRES steps (block steps)    */
 } svds_stats;
 
 /* Fill *opts with the defaults above.  Returns SVDS_OK or SVDS_ERR_ARG. */

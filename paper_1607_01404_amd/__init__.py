@@ -17,6 +17,8 @@ from ._lib import (  # noqa: F401
     METHOD_HYBRID,
     METHOD_NORMAL,
     METHOD_AUGMENTED,
+    STAGE2_GDK,
+    STAGE2_JD,
     condest,
     blockjacobi_apply,
     LPC_NPARAMS,

@@ -10,6 +10,7 @@ LARGEST, SMALLEST = 0, 1
 FP64, MIXED = 0, 1
 PC_NONE, PC_JACOBI, PC_LEARNED, PC_BLOCKJACOBI = 0, 1, 2, 3
 METHOD_HYBRID, METHOD_NORMAL, METHOD_AUGMENTED = 0, 1, 2
+STAGE2_GDK, STAGE2_JD = 0, 1
 LPC_NPARAMS = 2888
 LPC_CACHE_PER_ROW = 192
 
@@ -35,7 +36,8 @@ class Opts(C.Structure):
                 ("seed", C.c_uint64), ("precision", C.c_int), ("precond", C.c_int),
                 ("force_stage2", C.c_int), ("two_sided_cleanup", C.c_int),
                 ("print_level", C.c_int), ("profile", C.c_int), ("autotune", C.c_int),
-                ("method", C.c_int), ("relative_tol", C.c_int),
+                ("method", C.c_int), ("stage2_solver", C.c_int), ("jd_max_inner", C.c_int),
+                ("jd_inner_tol", C.c_double), ("relative_tol", C.c_int),
                 ("max_seconds", C.c_double), ("pc_block", C.c_int), ("pc_degree", C.c_int),
                 ("pc_model", C.c_void_p)]
 
@@ -46,7 +48,8 @@ class Stats(C.Structure):
                 ("restarts", C.c_int64 * 2), ("resets", C.c_int64), ("breakdowns", C.c_int64),
                 ("seconds", C.c_double * 2), ("setup_seconds", C.c_double),
                 ("norm_A_used", C.c_double), ("spmm_calls", C.c_int64),
-                ("spmm_seconds", C.c_double), ("spmm_bytes", C.c_double)]
+                ("spmm_seconds", C.c_double), ("spmm_bytes", C.c_double),
+                ("inner_iters", C.c_int64)]
 
     def to_dict(self):
         return {"nconv": self.nconv, "stage_exit": self.stage_exit,
@@ -56,7 +59,7 @@ class Stats(C.Structure):
                 "breakdowns": self.breakdowns, "seconds": list(self.seconds),
                 "setup_seconds": self.setup_seconds, "norm_A_used": self.norm_A_used,
                 "spmm_calls": self.spmm_calls, "spmm_seconds": self.spmm_seconds,
-                "spmm_bytes": self.spmm_bytes}
+                "spmm_bytes": self.spmm_bytes, "inner_iters": self.inner_iters}
 
 
 _lib = None

@@ -89,6 +89,46 @@ class Solver {
 
  private:
   Capture* cap_ = nullptr;
+  // Jacobi-Davidson second stage
+  bool jd_ = false;
+  double *jdXb_ = nullptr, *jdB_ = nullptr, *jdQ_ = nullptr, *jdQp_ = nullptr, *jdZ_ = nullptr;
+  double *jdD1_ = nullptr, *jdD2_ = nullptr, *jdC_ = nullptr, *jdShift_ = nullptr;
+  double *jdN2_ = nullptr, *jdAlpha_ = nullptr, *jdBn2_ = nullptr;
+  JdCol* jdSt_ = nullptr;
+  JdCol* hjd_ = nullptr;  // pinned
+  void jd_project(double* Z, int nb) {
+    Seg q[2] = {Seg{X_, nlock_, ld_}, Seg{jdXb_, nb, ld_}};
+    tsgemm_tn(q, 2, N_, Z, ld_, nb, partial_, jdC_, s_);
+    ts_update(q, 2, N_, jdC_, nlock_ + nb, Z, ld_, nb, s_);
+  }
+  // T (N_ x nb) <- approximate solutions of the correction equations of the
+  // block (MINRES from zero); the Ritz vectors jdXb_ and shifts jdShift_ are set
+  void jd_correct(double* T, int nb) {
+    gather_precond(R_, ld_, d_->blk, nb, nullptr, N_, jdB_, ld_, s_);
+    jd_project(jdB_, nb);
+    jd_col_dots(jdB_, nullptr, ld_, N_, nb, partial_, jdN2_, s_);
+    jd_start(N_, nb, ld_, jdB_, jdN2_, jdSt_, jdQ_, jdQp_, jdD1_, jdD2_, T, s_);
+    const int maxit = o_.jd_max_inner > 0 ? o_.jd_max_inner : 20;
+    const double tol = o_.jd_inner_tol > 0.0 ? o_.jd_inner_tol : 0.1;
+    for (int it = 0; it < maxit; ++it) {
+      pack_rows(jdQ_, ld_, nullptr, 0.0, N_, nb, Tc_, s_);
+      apply_op(Tc_, Wc_, nb);
+      jd_shift(N_, nb, Wc_, jdQ_, ld_, jdShift_, jdZ_, s_);
+      jd_project(jdZ_, nb);
+      jd_col_dots(jdQ_, jdZ_, ld_, N_, nb, partial_, jdAlpha_, s_);
+      jd_step(N_, nb, ld_, jdZ_, jdQ_, jdQp_, jdD1_, jdD2_, T, jdAlpha_, jdBn2_, tol, jdSt_,
+              partial_, s_);
+      ++jd_inner_;
+      if ((it + 1) % 4 == 0 && it + 1 < maxit) {
+        SVDS_HIP(hipMemcpyAsync(hjd_, jdSt_, sizeof(JdCol) * nb, hipMemcpyDeviceToHost, s_));
+        SVDS_HIP(hipStreamSynchronize(s_));
+        bool all = true;
+        for (int j = 0; j < nb; ++j) all = all && hjd_[j].done;
+        if (all) break;
+      }
+    }
+  }
+  int64_t jd_inner_ = 0;
   // block-Jacobi preconditioner: inverses of the diagonal blocks of C
   double* bjK_ = nullptr;
   int bjnb_ = 0;
@@ -667,6 +707,23 @@ int Solver::stage1(double* V1, double* U1, double* sig, double* rn, double* taus
 int Solver::stage2(const double* taus_h, double* V1, double* U1, double* sig, int* nconv,
                    svds_stats* st) {
   stage_ = 2;
+  jd_ = o_.stage2_solver == SVDS_STAGE2_JD;
+  if (jd_ && !jdXb_) {
+    const size_t blk = (size_t)ld_ * kMaxBlock;
+    jdXb_ = buf_.get<double>(blk);
+    jdB_ = buf_.get<double>(blk);
+    jdQ_ = buf_.get<double>(blk);
+    jdQp_ = buf_.get<double>(blk);
+    jdZ_ = buf_.get<double>(blk);
+    jdD1_ = buf_.get<double>(blk);
+    jdD2_ = buf_.get<double>(blk);
+    jdC_ = buf_.get<double>((size_t)(kKmax + kMaxBlock) * kMaxBlock);
+    jdShift_ = buf_.get<double>(kMaxBlock);
+    jdN2_ = buf_.get<double>(kMaxBlock);
+    jdAlpha_ = buf_.get<double>(kMaxBlock);
+    jdBn2_ = buf_.get<double>(kMaxBlock);
+    jdSt_ = buf_.get<JdCol>(kMaxBlock);
+  }
   N_ = n_ + m_;
   gc_ = 0;
   nlock_ = 0;
@@ -750,14 +807,27 @@ int Solver::stage2(const double* taus_h, double* V1, double* U1, double* sig, in
       extract_stage();
       continue;
     }
+    const int nb = c.nblock;
+    if (jd_) {
+      // Ritz vectors of the block and the shifts, before a restart changes V
+      ts_gemm_nn(V_, ld_, gc_, N_, d_->Y, kLd, nb, jdXb_, ld_, s_);
+      if (refined_) {
+        double sh[kMaxBlock];
+        for (int j = 0; j < nb; ++j) sh[j] = tau_;
+        SVDS_HIP(hipMemcpyAsync(jdShift_, sh, sizeof(double) * nb, hipMemcpyHostToDevice, s_));
+      } else {
+        SVDS_HIP(hipMemcpyAsync(jdShift_, d_->theta, sizeof(double) * nb, hipMemcpyDeviceToDevice,
+                                s_));
+      }
+    }
     if (c.restart) {
       restart_basis(c.nr);
       ++restarts;
       ++since_reset;
     }
-    const int nb = c.nblock;
     double* T = V_ + gc_ * ld_;
-    precond_stage2(T, nb);
+    if (jd_) jd_correct(T, nb);
+    else precond_stage2(T, nb);
     Seg segs[2] = {Seg{X_, nlock_, ld_}, Seg{V_, gc_, ld_}};
     if (refined_) {
       ortho(T, ld_, nb, segs, 2, Tc_);  // the refined factor update needs a valid block
@@ -1076,14 +1146,17 @@ int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, d
   }
   SVDS_HIP(hipHostMalloc((void**)&hctl_, sizeof(Ctl), hipHostMallocDefault));
   SVDS_HIP(hipHostMalloc((void**)&hbad_, sizeof(int), hipHostMallocDefault));
+  SVDS_HIP(hipHostMalloc((void**)&hjd_, sizeof(JdCol) * kMaxBlock, hipHostMallocDefault));
   struct PinnedFree {
     Ctl* c;
     int* b;
+    JdCol* j;
     ~PinnedFree() {
       (void)hipHostFree(c);
       (void)hipHostFree(b);
+      (void)hipHostFree(j);
     }
-  } pf{hctl_, hbad_};
+  } pf{hctl_, hbad_, hjd_};
   if (o_.precond == SVDS_PC_JACOBI) {
     dinv_ = buf_.get<double>(n_);
     // 1/diag(C), with 1 where the column is empty
@@ -1153,6 +1226,7 @@ int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, d
     finite = finite && std::isfinite(hr[i]);
   }
   st->nconv = good;
+  st->inner_iters = jd_inner_;
   st->norm_A_used = normA_;
   collect_profile(st);
   st->breakdowns = breakdowns_;
@@ -1312,6 +1386,8 @@ int solve_prepared(const svds_matrix* h, int k, int target, double tol, const sv
     throw Error(SVDS_ERR_ARG, "method");
   if (o.method == SVDS_METHOD_AUGMENTED && target != SVDS_LARGEST)
     throw Error(SVDS_ERR_ARG, "the augmented method alone seeks the largest values only");
+  if (o.stage2_solver != SVDS_STAGE2_GDK && o.stage2_solver != SVDS_STAGE2_JD)
+    throw Error(SVDS_ERR_ARG, "stage2_solver");
   if (o.relative_tol && o.method != SVDS_METHOD_NORMAL)
     throw Error(SVDS_ERR_ARG, "the relative stopping rule needs the normal-equations method");
   svds_stats local;

@@ -73,3 +73,29 @@ def test_struct_layouts_match_header(tmp_path):
 def test_null_arguments_rejected(lib):
     assert lib.svds_matrix_create(None, None, None) == -1
     assert lib.svds_solve_prepared(None, 1, 0, 1e-10, None, None, None, 1, None, 1, None, None, None) == -1
+
+
+def test_every_field_offset_matches_header(tmp_path):
+    """Each ctypes field of the option, statistics and CSR structs sits at the
+    offset the C compiler gives it."""
+    import shutil
+    import subprocess
+    import paper_1607_01404_amd._lib as L
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = [("svds_opts", L.Opts), ("svds_stats", L.Stats), ("svds_csr", L.Csr),
+               ("svds_lpc_set", L.LpcSet)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "svds.h"', 'int main(){']
+    expect = []
+    for cname, cls in structs:
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {fname}));')
+            expect.append(getattr(cls, fname).offset)
+    lines.append("return 0;}")
+    src = tmp_path / "off.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "off"
+    subprocess.check_call([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).decode().split()]
+    assert got == expect

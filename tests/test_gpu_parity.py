@@ -394,3 +394,46 @@ def test_blockjacobi_solve(P):
         out[name] = st
     assert out["block"]["iters"][0] < out["jacobi"]["iters"][0]
     assert out["block_stage2"]["stage_exit"] == 2
+
+
+@pytest.mark.parametrize("target", ["largest", "smallest"])
+def test_jacobi_davidson_stage2(P, target):
+    """The JD second stage (MINRES inner solver) reaches the dense-LAPACK
+    values from a loose stage 1 in fewer outer iterations than GD+k, as the
+    oracle's JD stage does."""
+    A = synth.config1()
+    normA = float(np.linalg.norm(A.toarray(), 2))
+    s_all = np.linalg.svd(A.toarray(), compute_uv=False)
+    ref = s_all[:5] if target == "largest" else np.sort(s_all)[:5]
+    out = {}
+    for name, solver in (("gdk", P.STAGE2_GDK), ("jd", P.STAGE2_JD)):
+        _say("config1 stage 2", name, target)
+        sig, U, V, rn, st = P.svds(A, 5, target, 1e-10, max_basis_size=15, min_restart_size=6,
+                                   norm_A=normA, seed=5, stage1_tol=1e-4, stage2_solver=solver)
+        assert st["converged"] and st["stage_exit"] == 2, (name, st)
+        _compare(A, sig, U, V, rn, st, ref, 1e-10, normA)
+        out[name] = st
+    o_s, _, _, _, o_st = oracle.svds(A, 5, target, 1e-10, max_basis=15, min_restart=6,
+                                     norm_A=normA, seed=5, stage1_tol=1e-4, stage2_solver="jd")
+    assert out["jd"]["inner_iters"] > 0 and out["gdk"]["inner_iters"] == 0
+    assert out["jd"]["iters"][1] < out["gdk"]["iters"][1]
+    assert np.max(np.abs(o_s - ref) / ref) < 1e-10
+
+
+def test_jacobi_davidson_ill_conditioned_and_wide(P):
+    A = synth.banded_scaled(300, 150, seed=1, log_lo=-6)
+    normA = float(np.linalg.norm(A.toarray(), 2))
+    _say("JD stage 2 banded_scaled 300x150 smallest")
+    sig, U, V, rn, st = P.svds(A, 3, "smallest", 1e-10, block_size=1, norm_A=normA, seed=7,
+                               precond=P.PC_JACOBI, stage2_solver=P.STAGE2_JD)
+    s = np.sort(np.linalg.svd(A.toarray(), compute_uv=False))[:3]
+    assert st["converged"] and st["stage_exit"] == 2
+    _compare(A, sig, U, V, rn, st, s, 1e-10, normA, rel=1e-9)
+    W = synth.random_uniform_rows(300, 600, 12, seed=21)
+    nW = float(np.linalg.norm(W.toarray(), 2))
+    _say("JD stage 2 wide 300x600 b=2 forced")
+    sig, U, V, rn, st = P.svds(W, 4, "smallest", 1e-10, block_size=2, norm_A=nW, seed=3,
+                               stage1_tol=1e-3, stage2_solver=P.STAGE2_JD)
+    s = np.sort(np.linalg.svd(W.toarray(), compute_uv=False))[:4]
+    assert st["converged"] and st["stage_exit"] == 2
+    _compare(A=W, sig=sig, U=U, V=V, rn=rn, st=st, ref_sig=s, tol=1e-10, normA=nW)
