@@ -99,8 +99,9 @@ def mixed_comparison(P, torch):
     m, n = A.shape
     out = {"workload": w["desc"], "nnz": int(A.nnz)}
     sigs = {}
-    for name, prec in (("fp64", P.FP64), ("mixed", P.MIXED)):
-        opts = dict(w["opts"], precision=prec, profile=1)
+    for name, prec, s2 in (("fp64", P.FP64, P.STAGE2_GDK), ("mixed", P.MIXED, P.STAGE2_GDK),
+                           ("mixed_jd", P.MIXED, P.STAGE2_JD)):
+        opts = dict(w["opts"], precision=prec, profile=1, stage2_solver=s2)
         P.solve(ip, ix, dv, m, n, w["k"], w["target"], 1e-10, **opts)  # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -111,11 +112,13 @@ def mixed_comparison(P, torch):
         out[name] = {"seconds": el, "converged": bool(st["converged"]),
                      "max_rnorm_over_normA": float(rn.max()) / st["norm_A_used"],
                      "matvecs": st["matvecs"], "iters": st["iters"], "stage_exit": st["stage_exit"],
-                     "stage_seconds": st["seconds"],
+                     "stage_seconds": st["seconds"], "inner_iters": st["inner_iters"],
                      "spmm_GBps": st["spmm_bytes"] / max(st["spmm_seconds"], 1e-12) / 1e9}
         log(f"{name}: {el:.3f} s {st['iters']} {st['matvecs']}")
     out["max_rel_sigma_diff"] = float(np.max(np.abs(sigs["mixed"] - sigs["fp64"]) / sigs["fp64"]))
+    out["max_rel_sigma_diff_jd"] = float(np.max(np.abs(sigs["mixed_jd"] - sigs["fp64"]) / sigs["fp64"]))
     out["speedup_mixed_over_fp64"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+    out["speedup_mixed_jd_over_fp64"] = out["fp64"]["seconds"] / out["mixed_jd"]["seconds"]
     return out
 
 
@@ -196,7 +199,9 @@ def learned_extra(P, torch, full_seconds):
                                 " a residual every 4th stage-1 iteration, 64 per field",
                         "collect_seconds": collect, "train_seconds": train, "steps": 200,
                         "degree": degree, "loss_first": float(hist[0]), "loss_last": float(hist[-1])}}
-    runs = [("none", dict(precond=P.PC_NONE)), ("jacobi", dict(precond=P.PC_JACOBI)),
+    runs = [("none", dict(precond=P.PC_NONE)),
+            ("none_jd", dict(precond=P.PC_NONE, stage2_solver=P.STAGE2_JD)),
+            ("jacobi", dict(precond=P.PC_JACOBI)),
             ("block_jacobi_128", dict(precond=P.PC_BLOCKJACOBI, pc_block=128)),
             ("learned", dict(precond=P.PC_LEARNED, pc_model=params, pc_degree=degree))]
     for label, ng, cap in (("replica_128x128", 128, 60.0), ("full_1024x1024", 1024, full_seconds)):
@@ -213,6 +218,7 @@ def learned_extra(P, torch, full_seconds):
             el = time.perf_counter() - t
             res[name] = {"seconds": el, "converged": bool(st["converged"]), "nconv": st["nconv"],
                          "iters": st["iters"], "matvecs": st["matvecs"],
+                         "inner_iters": st["inner_iters"],
                          "max_rnorm_over_normA": float(rn.max()) / st["norm_A_used"],
                          "sigma_min": float(sig[0])}
         out[label] = res
