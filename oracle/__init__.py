@@ -23,4 +23,5 @@ from .phsvds import (  # noqa: F401
     svd_residuals,
     condest,
     minres,
+    sqmr,
 )

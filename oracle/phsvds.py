@@ -607,6 +607,56 @@ def minres(Mop, rhs, tol, maxit):
     return x, its
 
 
+def sqmr(Mop, rhs, tol, maxit, Pop=None):
+    """Symmetric QMR (Freund and Nachtigal, 1994) for a symmetric, possibly
+    indefinite operator with a symmetric, possibly indefinite preconditioner
+    ``Pop`` (None: the identity), from x0 = 0.  The conjugate-gradient-like
+    recurrence gives the Lanczos residuals r_k; the quasi-residual norm tau_k
+    comes from a running Givens-type smoothing with c_k = 1/sqrt(1 + theta_k^2),
+    theta_k = ||r_k|| / tau_{k-1}, and the iterate is advanced by
+    d_k = c_k^2 theta_{k-1}^2 d_{k-1} + c_k^2 alpha_k q_k.  Without a
+    preconditioner the Lanczos residuals are orthogonal and the iterates are
+    those of MINRES.  Stops after maxit steps, when tau_k falls to tol * ||rhs||
+    or on a breakdown (q^T M q = 0 or r^T P r = 0)."""
+    rhs = np.asarray(rhs, dtype=np.float64)
+    x = np.zeros_like(rhs)
+    tau0 = float(np.linalg.norm(rhs))
+    if tau0 == 0.0:
+        return x, 0
+    P = Pop if Pop is not None else (lambda y: y)
+    r = rhs.copy()
+    t = P(r)
+    q = t.copy()
+    rho = float(r @ t)
+    tau = tau0
+    theta = 0.0
+    d = np.zeros_like(rhs)
+    its = 0
+    for _ in range(maxit):
+        if rho == 0.0:
+            break
+        w = Mop(q)
+        sigma = float(q @ w)
+        if sigma == 0.0:
+            break
+        alpha = rho / sigma
+        r = r - alpha * w
+        theta_prev = theta
+        theta = float(np.linalg.norm(r)) / tau
+        c2 = 1.0 / (1.0 + theta * theta)
+        tau = tau * theta * math.sqrt(c2)
+        d = (c2 * theta_prev * theta_prev) * d + (c2 * alpha) * q
+        x = x + d
+        its += 1
+        if tau <= tol * tau0:
+            break
+        t = P(r)
+        rho_next = float(r @ t)
+        q = t + (rho_next / rho) * q
+        rho = rho_next
+    return x, its
+
+
 def _stage2(ops, k, target, tol, normA, g, r, b, p, seed, precond, budget, stats, rand_state,
             sig1, U1, V1, rn1, trace=None, solver="gdk", jd_maxit=20, jd_tol=0.1):
     n, m = ops.n, ops.m
@@ -718,23 +768,25 @@ def _stage2(ops, k, target, tol, normA, g, r, b, p, seed, precond, budget, stats
             restarts += 1
             since_reset += 1
         if solver == "jd":
-            # Jacobi-Davidson correction (the second stage's default solver of
-            # the paper): (I - QQ^T)(B - s I)(I - QQ^T) t = r with Q the locked
-            # vectors and the block's Ritz vectors, s the active shift (refined)
-            # or the Ritz value, solved approximately by MINRES; the sign of t
-            # does not matter for the expansion
+            # Jacobi-Davidson correction (the paper's second stage, JDQMR):
+            # (I - QQ^T)(B - s I)(I - QQ^T) t = r with Q the locked vectors and
+            # the block's Ritz vectors, s the active shift (refined) or the
+            # Ritz value, solved approximately by symmetric QMR with the
+            # preconditioner (I - QQ^T) K (I - QQ^T); the sign of t does not
+            # matter for the expansion
             Q = np.hstack([S.X, X[:, block]])
             T = np.empty((N, len(block)))
+            proj = lambda y: y - Q @ (Q.T @ y)
+            Pop = None if precond is None else (lambda y: proj(K(proj(y)[:, None])[:, 0]))
             for jj, j in enumerate(block):
                 shift = tau if refined else lam[j]
 
                 def Mop(y, shift=shift):
-                    y = y - Q @ (Q.T @ y)
-                    z = ops.B(y[:, None])[:, 0] - shift * y
-                    return z - Q @ (Q.T @ z)
+                    y = proj(y)
+                    return proj(ops.B(y[:, None])[:, 0] - shift * y)
 
-                rj = R[:, j] - Q @ (Q.T @ R[:, j])
-                T[:, jj], its = minres(Mop, rj, jd_tol, jd_maxit)
+                rj = proj(R[:, j])
+                T[:, jj], its = sqmr(Mop, rj, jd_tol, jd_maxit, Pop)
                 stats.setdefault("inner_iters", 0)
                 stats["inner_iters"] += its
         else:
@@ -809,7 +861,7 @@ def _sign_normalise(U, V):
 def svds(A, k, target="largest", tol=1e-10, *, max_basis=None, min_restart=None, block=None,
          prev_retain=None, max_matvecs=None, norm_A=None, seed=0, precond="none",
          force_stage2=False, cleanup=True, stage1_tol=None, trace=None, time_limit=None,
-         capture=None, method="hybrid", relative=False, pc_block=64, stage2_solver="gdk",
+         capture=None, method="hybrid", relative=False, pc_block=64, stage2_solver="jd",
          jd_maxit=20, jd_tol=0.1):
     """k largest or smallest singular triplets of the sparse matrix A with
     eq. (res) residual below tol*||A||.  Returns (sigma, U, V, rnorm, stats);
@@ -833,10 +885,11 @@ def svds(A, k, target="largest", tol=1e-10, *, max_basis=None, min_restart=None,
     shifts need the stage-1 bounds) -- the single-stage methods of
     Section 3.4.  ``relative``: the stopping rule
     ||r|| <= tol * sigma of the low-accuracy condition estimate (Section 4.4);
-    only with method "normal".  ``stage2_solver``: "gdk" (GD+k, the default
-    here) or "jd" (Jacobi-Davidson with at most ``jd_maxit`` MINRES steps to
-    a residual reduction of ``jd_tol``, unpreconditioned; the paper's second
-    stage defaults to JDQMR, Section 3.4)."""
+    only with method "normal".  ``stage2_solver``: "jd" (the default:
+    Jacobi-Davidson with at most ``jd_maxit`` symmetric-QMR steps to a
+    quasi-residual reduction of ``jd_tol``, preconditioned by the stage-2
+    composition; the paper's second stage is JDQMR, Section 3.4) or "gdk"
+    (GD+k with the same preconditioner on the residuals)."""
     t0 = time.perf_counter()
     if target not in ("largest", "smallest"):
         raise ValueError("target must be 'largest' or 'smallest'")
@@ -852,6 +905,8 @@ def svds(A, k, target="largest", tol=1e-10, *, max_basis=None, min_restart=None,
         raise ValueError("method must be 'hybrid', 'normal' or 'augmented'")
     if relative and method != "normal":
         raise ValueError("the relative stopping rule needs method 'normal'")
+    if stage2_solver not in ("gdk", "jd"):
+        raise ValueError("stage2_solver must be 'jd' or 'gdk'")
     if method == "augmented" and target == "smallest":
         # on B alone the smallest values are interior, with -sigma as close to a
         # shift near zero as +sigma (and m - n zero eigenvalues when m != n):

@@ -111,7 +111,7 @@ def test_config1_against_lapack(target, force2):
     _, s, _ = _lapack(A)
     ref = s[:5] if target == "largest" else np.sort(s)[:5]
     sig, U, V, rn, st = oracle.svds(A, 5, target, 1e-10, max_basis=15, min_restart=6, block=1,
-                                    seed=11, force_stage2=force2)
+                                    seed=11, force_stage2=force2, stage2_solver="gdk")
     assert st["converged"]
     assert st["stage_exit"] == (2 if force2 else 1)
     _check_triplets(A, sig, U, V, rn, ref, 1e-10)
@@ -184,7 +184,7 @@ def test_stage2_refines_loose_stage1(target):
     _, s, _ = _lapack(A)
     ref = s[:5] if target == "largest" else np.sort(s)[:5]
     out, U, V, rn, st = oracle.svds(A, 5, target, 1e-10, max_basis=15, min_restart=6, seed=5,
-                                    stage1_tol=1e-4)
+                                    stage1_tol=1e-4, stage2_solver="gdk")
     assert st["stage_exit"] == 2 and st["converged"]
     assert st["iters"][1] > 0
     _check_triplets(A, out, U, V, rn, ref, 1e-10)
@@ -198,6 +198,23 @@ def test_stage2_needed_for_ill_conditioned_smallest():
     out, U, V, rn, st = oracle.svds(A, 3, "smallest", 1e-10, block=1, seed=7, precond="jacobi")
     assert st["stage_exit"] == 2 and st["converged"]
     _check_triplets(A, out, U, V, rn, np.sort(s)[:3], 1e-10, rel=1e-9)
+
+
+def test_default_stage2_solver():
+    """The second stage defaults to Jacobi-Davidson with the preconditioned
+    symmetric-QMR correction (the paper's JDQMR, Section 3.4).  The five
+    smallest values of a kappa ~ 1e6 banded matrix with m - n = 600 zero
+    eigenvalues of B next to them need stage 2; the default meets eq. (res)
+    within a few outer iterations."""
+    A = synth.banded_scaled(1200, 600, seed=2005, log_lo=-6)
+    _, s, _ = _lapack(A)
+    out, U, V, rn, st = oracle.svds(A, 5, "smallest", 1e-10, block=4, max_basis=35,
+                                    min_restart=14, precond="jacobi", seed=2005)
+    assert st["stage_exit"] == 2 and st["converged"] and st["inner_iters"] > 0
+    assert st["iters"][1] <= 20
+    _check_triplets(A, out, U, V, rn, np.sort(s)[:5], 1e-10, rel=1e-9)
+    with pytest.raises(ValueError):
+        oracle.svds(A, 3, "smallest", 1e-10, stage2_solver="qmr")
 
 
 def test_stage1_bracket():
@@ -358,6 +375,55 @@ def test_minres_is_the_minimal_residual_krylov_iterate():
         assert np.allclose(x, Bq @ c, rtol=1e-8, atol=1e-10)
     x, _ = oracle.minres(lambda y: M @ y, b, 1e-14, 200)
     assert np.allclose(M @ x, b, atol=1e-10)
+
+
+def _sym_indefinite(rng, n):
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    ev = np.concatenate([-np.linspace(1, 3, n // 3), np.linspace(0.5, 4, n - n // 3)])
+    return (Q * ev) @ Q.T
+
+
+def test_sqmr_without_preconditioner_is_minimal_residual():
+    """Symmetric QMR with P = I: after k steps the minimiser of ||b - M x||
+    over K_k(M, b), by least squares on an explicit Krylov basis."""
+    rng = np.random.default_rng(4)
+    M = _sym_indefinite(rng, 30)
+    b = rng.standard_normal(30)
+    for k in (1, 2, 5, 9):
+        x, its = oracle.sqmr(lambda y: M @ y, b, 0.0, k)
+        Kb = np.column_stack([np.linalg.matrix_power(M, j) @ b for j in range(k)])
+        Bq, _ = np.linalg.qr(Kb)
+        c, *_ = np.linalg.lstsq(M @ Bq, b, rcond=None)
+        assert its == k
+        assert np.allclose(x, Bq @ c, rtol=1e-8, atol=1e-10)
+
+
+def test_sqmr_with_preconditioner():
+    """Symmetric QMR with a symmetric indefinite preconditioner P: the k-th
+    iterate lies in the preconditioned Krylov space K_k(PM, Pb); the exact
+    inverse gives the solution in one step; an approximate inverse reaches
+    the solution."""
+    rng = np.random.default_rng(5)
+    n = 40
+    M = _sym_indefinite(rng, n)
+    b = rng.standard_normal(n)
+    E = 0.05 * rng.standard_normal((n, n))
+    Pm = np.linalg.inv(M + E + E.T)
+    for k in (2, 4, 7):
+        x, its = oracle.sqmr(lambda y: M @ y, b, 0.0, k, lambda y: Pm @ y)
+        assert its == k
+        Kb = np.column_stack([np.linalg.matrix_power(Pm @ M, j) @ (Pm @ b) for j in range(k)])
+        Bq, _ = np.linalg.qr(Kb)
+        assert np.linalg.norm(x - Bq @ (Bq.T @ x)) < 1e-10 * np.linalg.norm(x)
+        xk1, _ = oracle.sqmr(lambda y: M @ y, b, 0.0, k + 1, lambda y: Pm @ y)
+        assert np.linalg.norm(xk1 - Bq @ (Bq.T @ xk1)) > 1e-6 * np.linalg.norm(xk1)
+    Minv = np.linalg.inv(M)
+    x, its = oracle.sqmr(lambda y: M @ y, b, 1e-12, 5, lambda y: Minv @ y)
+    assert its == 1 and np.allclose(x, Minv @ b, rtol=1e-12, atol=1e-12)
+    x, its = oracle.sqmr(lambda y: M @ y, b, 1e-13, 200, lambda y: Pm @ y)
+    assert np.linalg.norm(M @ x - b) < 1e-11 * np.linalg.norm(b)
+    x, its = oracle.sqmr(lambda y: M @ y, np.zeros(n), 0.1, 5)
+    assert its == 0 and not x.any()
 
 
 @pytest.mark.parametrize("target", ["largest", "smallest"])
