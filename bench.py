@@ -99,8 +99,8 @@ def mixed_comparison(P, torch):
     m, n = A.shape
     out = {"workload": w["desc"], "nnz": int(A.nnz)}
     sigs = {}
-    for name, prec, s2 in (("fp64", P.FP64, P.STAGE2_GDK), ("mixed", P.MIXED, P.STAGE2_GDK),
-                           ("mixed_jd", P.MIXED, P.STAGE2_JD)):
+    for name, prec, s2 in (("fp64", P.FP64, P.STAGE2_JD), ("mixed", P.MIXED, P.STAGE2_JD),
+                           ("fp64_gdk", P.FP64, P.STAGE2_GDK), ("mixed_gdk", P.MIXED, P.STAGE2_GDK)):
         opts = dict(w["opts"], precision=prec, profile=1, stage2_solver=s2)
         P.solve(ip, ix, dv, m, n, w["k"], w["target"], 1e-10, **opts)  # warm-up
         torch.cuda.synchronize()
@@ -116,9 +116,10 @@ def mixed_comparison(P, torch):
                      "spmm_GBps": st["spmm_bytes"] / max(st["spmm_seconds"], 1e-12) / 1e9}
         log(f"{name}: {el:.3f} s {st['iters']} {st['matvecs']}")
     out["max_rel_sigma_diff"] = float(np.max(np.abs(sigs["mixed"] - sigs["fp64"]) / sigs["fp64"]))
-    out["max_rel_sigma_diff_jd"] = float(np.max(np.abs(sigs["mixed_jd"] - sigs["fp64"]) / sigs["fp64"]))
+    out["max_rel_sigma_diff_gdk"] = float(np.max(np.abs(sigs["mixed_gdk"] - sigs["fp64_gdk"])
+                                                 / sigs["fp64_gdk"]))
     out["speedup_mixed_over_fp64"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
-    out["speedup_mixed_jd_over_fp64"] = out["fp64"]["seconds"] / out["mixed_jd"]["seconds"]
+    out["speedup_mixed_over_fp64_gdk"] = out["fp64_gdk"]["seconds"] / out["mixed_gdk"]["seconds"]
     return out
 
 
@@ -200,8 +201,9 @@ def learned_extra(P, torch, full_seconds):
                         "collect_seconds": collect, "train_seconds": train, "steps": 200,
                         "degree": degree, "loss_first": float(hist[0]), "loss_last": float(hist[-1])}}
     runs = [("none", dict(precond=P.PC_NONE)),
-            ("none_jd", dict(precond=P.PC_NONE, stage2_solver=P.STAGE2_JD)),
+            ("none_gdk", dict(precond=P.PC_NONE, stage2_solver=P.STAGE2_GDK)),
             ("jacobi", dict(precond=P.PC_JACOBI)),
+            ("jacobi_gdk", dict(precond=P.PC_JACOBI, stage2_solver=P.STAGE2_GDK)),
             ("block_jacobi_128", dict(precond=P.PC_BLOCKJACOBI, pc_block=128)),
             ("learned", dict(precond=P.PC_LEARNED, pc_model=params, pc_degree=degree))]
     for label, ng, cap in (("replica_128x128", 128, 60.0), ("full_1024x1024", 1024, full_seconds)):

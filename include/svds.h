@@ -81,15 +81,18 @@ extern "C" {
                                  /* largest values only                     */
                                  /* (primme_svds_augmented; Section 3.4)    */
 
-#define SVDS_STAGE2_GDK 0        /* second stage: GD+k (default)            */
-#define SVDS_STAGE2_JD 1         /* second stage: Jacobi-Davidson, the       */
-                                 /* correction equation (I - QQ^T)(B - s I)  */
-                                 /* (I - QQ^T) t = r (Q: locked and block    */
-                                 /* Ritz vectors; s: the stage-1 bound for   */
-                                 /* the smallest values, the Ritz value for  */
-                                 /* the largest) solved by MINRES, the       */
-                                 /* paper's default second stage (JDQMR,     */
-                                 /* Section 3.4) without preconditioner      */
+#define SVDS_STAGE2_GDK 0        /* second stage: GD+k with the stage-2      */
+                                 /* preconditioner on the residuals         */
+#define SVDS_STAGE2_JD 1         /* second stage (default): Jacobi-Davidson, */
+                                 /* the correction equation                 */
+                                 /* (I - QQ^T)(B - s I)(I - QQ^T) t = r     */
+                                 /* (Q: locked and block Ritz vectors; s:   */
+                                 /* the stage-1 bound for the smallest      */
+                                 /* values, the Ritz value for the largest) */
+                                 /* solved by symmetric QMR with the        */
+                                 /* projected stage-2 preconditioner: the   */
+                                 /* paper's default second stage (JDQMR,    */
+                                 /* Section 3.4)                            */
 
 /* ---- CSR matrix (device arrays, caller-owned, read-only) ----------------- */
 typedef struct svds_csr {
@@ -131,8 +134,8 @@ typedef struct svds_opts {
                           /* the block width and keep the fastest; 0: use   */
                           /* the row-length rule of thumb                   */
   int method;             /* SVDS_METHOD_*                                  */
-  int stage2_solver;      /* SVDS_STAGE2_GDK or SVDS_STAGE2_JD              */
-  int jd_max_inner;       /* JD: MINRES steps per correction; 0 -> 20       */
+  int stage2_solver;      /* SVDS_STAGE2_JD (default) or SVDS_STAGE2_GDK    */
+  int jd_max_inner;       /* JD: QMR steps per correction; 0 -> 20          */
   double jd_inner_tol;    /* JD: stop at this residual reduction; 0 -> 0.1  */
   int relative_tol;       /* 1: converged when ||r|| < tol * sigma (the     */
                           /* stopping rule of the condition estimate,       */

@@ -244,22 +244,28 @@ void scale_rows(double* T, int64_t ldt, int64_t N, int b, const double* dinv, hi
 void copy_cols(const double* A, int64_t lda, int64_t N, int b, double* B, int64_t ldb,
                hipStream_t s);
 
-// Jacobi-Davidson correction of the second stage: per-column MINRES state
+// Jacobi-Davidson correction of the second stage: per-column symmetric-QMR state
 struct JdCol {
-  double beta1, phi, beta, c1, s1, c2, s2;  // |rhs|, residual estimate, coupling, rotations
-  double tk, delta, eps, invg;              // coefficients of the current update
+  double tau0, tau, theta, rho;  // |rhs|, quasi-residual norm, smoothing, r.Pr
+  double dcoef, acoef, beta;     // coefficients of the current update
   int done, apply;
 };
 // out[j] = X_j . Y_j (Y null: X_j . X_j) for nb column pairs
 void jd_col_dots(const double* X, const double* Y, int64_t ld, int64_t N, int nb, double* partial,
                  double* out, hipStream_t s);
-void jd_start(int64_t N, int nb, int64_t ld, const double* b, const double* n2, JdCol* st,
-              double* q, double* qp, double* d1, double* d2, double* x, hipStream_t s);
+// state from ||r_0||^2 (n2) and r_0 . t_0 (rho0; null: n2); q = t_0, d = x = 0
+void jd_start(int64_t N, int nb, int64_t ld, const double* t, const double* n2,
+              const double* rho0, JdCol* st, double* q, double* d, double* x, hipStream_t s);
+// w = (B q)_compact - s_j q
 void jd_shift(int64_t N, int nb, const double* Wc, const double* q, int64_t ld,
-              const double* shift, double* z, hipStream_t s);
-void jd_step(int64_t N, int nb, int64_t ld, double* z, double* q, double* qp, double* d1,
-             double* d2, double* x, const double* alpha, double* bnext2, double tol, JdCol* st,
+              const double* shift, double* w, hipStream_t s);
+// r -= alpha w, the scalar step, d and x; then q = r + beta q (t null) or t = r
+void jd_step(int64_t N, int nb, int64_t ld, double* r, const double* w, double* q, double* d,
+             double* x, double* t, const double* sigma, double* rn2, double tol, JdCol* st,
              double* partial, hipStream_t s);
+// preconditioned continuation: beta = rho'/rho, q = t + beta q
+void jd_precond_step(int64_t N, int nb, int64_t ld, const double* rho_next, const double* t,
+                     double* q, JdCol* st, hipStream_t s);
 
 // block-Jacobi preconditioner of C: K holds ceil(N/nb) blocks of nb x nb
 void bj_setup(const svds_matrix* M, int nb, double* K, hipStream_t s);

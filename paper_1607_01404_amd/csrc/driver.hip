@@ -91,9 +91,9 @@ class Solver {
   Capture* cap_ = nullptr;
   // Jacobi-Davidson second stage
   bool jd_ = false;
-  double *jdXb_ = nullptr, *jdB_ = nullptr, *jdQ_ = nullptr, *jdQp_ = nullptr, *jdZ_ = nullptr;
-  double *jdD1_ = nullptr, *jdD2_ = nullptr, *jdC_ = nullptr, *jdShift_ = nullptr;
-  double *jdN2_ = nullptr, *jdAlpha_ = nullptr, *jdBn2_ = nullptr;
+  double *jdXb_ = nullptr, *jdR_ = nullptr, *jdQ_ = nullptr, *jdW_ = nullptr, *jdD_ = nullptr;
+  double *jdT_ = nullptr, *jdC_ = nullptr, *jdShift_ = nullptr;
+  double *jdN2_ = nullptr, *jdSig_ = nullptr, *jdRn2_ = nullptr, *jdRho_ = nullptr;
   JdCol* jdSt_ = nullptr;
   JdCol* hjd_ = nullptr;  // pinned
   void jd_project(double* Z, int nb) {
@@ -102,23 +102,38 @@ class Solver {
     ts_update(q, 2, N_, jdC_, nlock_ + nb, Z, ld_, nb, s_);
   }
   // T (N_ x nb) <- approximate solutions of the correction equations of the
-  // block (MINRES from zero); the Ritz vectors jdXb_ and shifts jdShift_ are set
+  // block (symmetric QMR from zero with the projected stage-2
+  // preconditioner); the Ritz vectors jdXb_ and shifts jdShift_ are set
   void jd_correct(double* T, int nb) {
-    gather_precond(R_, ld_, d_->blk, nb, nullptr, N_, jdB_, ld_, s_);
-    jd_project(jdB_, nb);
-    jd_col_dots(jdB_, nullptr, ld_, N_, nb, partial_, jdN2_, s_);
-    jd_start(N_, nb, ld_, jdB_, jdN2_, jdSt_, jdQ_, jdQp_, jdD1_, jdD2_, T, s_);
+    const bool pc = o_.precond != SVDS_PC_NONE;
+    gather_precond(R_, ld_, d_->blk, nb, nullptr, N_, jdR_, ld_, s_);
+    jd_project(jdR_, nb);
+    jd_col_dots(jdR_, nullptr, ld_, N_, nb, partial_, jdN2_, s_);
+    if (pc) {
+      copy_cols(jdR_, ld_, N_, nb, jdT_, ld_, s_);
+      apply_pcB(jdT_, nb);
+      jd_project(jdT_, nb);
+      jd_col_dots(jdR_, jdT_, ld_, N_, nb, partial_, jdRho_, s_);
+    }
+    jd_start(N_, nb, ld_, pc ? jdT_ : jdR_, jdN2_, pc ? jdRho_ : nullptr, jdSt_, jdQ_, jdD_, T,
+             s_);
     const int maxit = o_.jd_max_inner > 0 ? o_.jd_max_inner : 20;
     const double tol = o_.jd_inner_tol > 0.0 ? o_.jd_inner_tol : 0.1;
     for (int it = 0; it < maxit; ++it) {
       pack_rows(jdQ_, ld_, nullptr, 0.0, N_, nb, Tc_, s_);
       apply_op(Tc_, Wc_, nb);
-      jd_shift(N_, nb, Wc_, jdQ_, ld_, jdShift_, jdZ_, s_);
-      jd_project(jdZ_, nb);
-      jd_col_dots(jdQ_, jdZ_, ld_, N_, nb, partial_, jdAlpha_, s_);
-      jd_step(N_, nb, ld_, jdZ_, jdQ_, jdQp_, jdD1_, jdD2_, T, jdAlpha_, jdBn2_, tol, jdSt_,
-              partial_, s_);
+      jd_shift(N_, nb, Wc_, jdQ_, ld_, jdShift_, jdW_, s_);
+      jd_project(jdW_, nb);
+      jd_col_dots(jdQ_, jdW_, ld_, N_, nb, partial_, jdSig_, s_);
+      jd_step(N_, nb, ld_, jdR_, jdW_, jdQ_, jdD_, T, pc ? jdT_ : nullptr, jdSig_, jdRn2_, tol,
+              jdSt_, partial_, s_);
       ++jd_inner_;
+      if (pc && it + 1 < maxit) {
+        apply_pcB(jdT_, nb);
+        jd_project(jdT_, nb);
+        jd_col_dots(jdR_, jdT_, ld_, N_, nb, partial_, jdRho_, s_);
+        jd_precond_step(N_, nb, ld_, jdRho_, jdT_, jdQ_, jdSt_, s_);
+      }
       if ((it + 1) % 4 == 0 && it + 1 < maxit) {
         SVDS_HIP(hipMemcpyAsync(hjd_, jdSt_, sizeof(JdCol) * nb, hipMemcpyDeviceToHost, s_));
         SVDS_HIP(hipStreamSynchronize(s_));
@@ -450,6 +465,11 @@ class Solver {
   // of B with (A^T A)^-1 ~ K), or the identity
   void precond_stage2(double* T, int nb) {
     gather_precond(R_, ld_, d_->blk, nb, nullptr, N_, T, ld_, s_);
+    apply_pcB(T, nb);
+  }
+  // T (N_ x nb, the v half first) <- K_B T with the pseudo-inverse composition
+  // K_B [y_v; y_u] = [K A^T y_u; A K y_v] of the preconditioner K of C
+  void apply_pcB(double* T, int nb) {
     if (o_.precond == SVDS_PC_NONE) return;
     apply_pc(T, nb);                                        // T_v <- K r_v
     pack_rows(T, ld_, nullptr, 0.0, n_, nb, Tc_, s_);       // K r_v (n x nb)
@@ -711,17 +731,17 @@ int Solver::stage2(const double* taus_h, double* V1, double* U1, double* sig, in
   if (jd_ && !jdXb_) {
     const size_t blk = (size_t)ld_ * kMaxBlock;
     jdXb_ = buf_.get<double>(blk);
-    jdB_ = buf_.get<double>(blk);
+    jdR_ = buf_.get<double>(blk);
     jdQ_ = buf_.get<double>(blk);
-    jdQp_ = buf_.get<double>(blk);
-    jdZ_ = buf_.get<double>(blk);
-    jdD1_ = buf_.get<double>(blk);
-    jdD2_ = buf_.get<double>(blk);
+    jdW_ = buf_.get<double>(blk);
+    jdD_ = buf_.get<double>(blk);
+    jdT_ = buf_.get<double>(blk);
     jdC_ = buf_.get<double>((size_t)(kKmax + kMaxBlock) * kMaxBlock);
     jdShift_ = buf_.get<double>(kMaxBlock);
     jdN2_ = buf_.get<double>(kMaxBlock);
-    jdAlpha_ = buf_.get<double>(kMaxBlock);
-    jdBn2_ = buf_.get<double>(kMaxBlock);
+    jdSig_ = buf_.get<double>(kMaxBlock);
+    jdRn2_ = buf_.get<double>(kMaxBlock);
+    jdRho_ = buf_.get<double>(kMaxBlock);
     jdSt_ = buf_.get<JdCol>(kMaxBlock);
   }
   N_ = n_ + m_;
@@ -1360,6 +1380,7 @@ svds_opts default_opts() {
   o.max_prev_retain = -1;
   o.two_sided_cleanup = 1;
   o.autotune = 1;
+  o.stage2_solver = SVDS_STAGE2_JD;
   return o;
 }
 

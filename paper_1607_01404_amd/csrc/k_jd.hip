@@ -1,13 +1,20 @@
 // Jacobi-Davidson correction for the second stage (the paper's default
-// second-stage solver, Section 3.4): for each of the nb block columns,
+// second-stage solver, JDQMR, Section 3.4): for each of the nb block columns,
 //   (I - QQ^T)(B - s_j I)(I - QQ^T) t_j = r_j
-// solved approximately by MINRES (Paige and Saunders) from t_j = 0.  The nb
-// columns run side by side: the Lanczos vectors are column-major N x nb
-// blocks, the products with B are the library's block SpMMs, and the scalar
-// recurrences (Givens rotations of the tridiagonal projection) run in a
-// one-wavefront kernel on per-column state in device memory, so the inner
-// loop needs no host synchronisation.  A column that has met its residual
-// reduction (or lost its Lanczos vector) stops updating its solution.
+// solved approximately from t_j = 0 by symmetric QMR (Freund and Nachtigal)
+// with the stage-2 preconditioner projected the same way.  The nb columns run
+// side by side: the vectors are column-major N x nb blocks, the products with
+// B and the preconditioner are the library's block kernels, and the scalar
+// recurrences run in a one-wavefront kernel on per-column state in device
+// memory, so the inner loop needs no host synchronisation.  A column that has
+// met its residual reduction (or broken down) stops updating its solution.
+//
+// One inner step of column j, from the residual r, direction q, increment d:
+//   w = M q,  sigma = q.w,  alpha = rho / sigma,  r -= alpha w,
+//   theta' = ||r|| / tau,  c2 = 1 / (1 + theta'^2),  tau = tau theta' sqrt(c2),
+//   d = c2 theta^2 d + c2 alpha q,  x += d,  theta = theta',
+//   t = P r,  rho' = r.t,  q = t + (rho' / rho) q,  rho = rho'
+// (P = I: t = r and rho' = ||r||^2, and the iterates are those of MINRES).
 #include "common.h"
 
 namespace svds {
@@ -19,6 +26,8 @@ constexpr int kJT = 256;
 inline int blocks_for(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>((n + kJT - 1) / kJT, 2048));
 }
+
+inline unsigned elem_blocks(int64_t tot) { return (unsigned)((tot + 255) / 256); }
 
 // per-block partial sums of x_j . y_j (y null: x_j . x_j), partial[j * nblk + block]
 __global__ __launch_bounds__(kJT) void k_jd_dots(const double* __restrict__ X,
@@ -51,62 +60,63 @@ __global__ __launch_bounds__(kJT) void k_jd_dots(const double* __restrict__ X,
   }
 }
 
-// start: beta1 = ||b_j||, q = b / beta1, the other vectors zero
-__global__ void k_jd_start(int nb, const double* __restrict__ n2, JdCol* __restrict__ st) {
+// start: tau = tau0 = ||r_0||, rho = r_0 . t_0 (no preconditioner: ||r_0||^2)
+__global__ void k_jd_start(int nb, const double* __restrict__ n2, const double* __restrict__ rho0,
+                           JdCol* __restrict__ st) {
   const int j = threadIdx.x;
   if (j >= nb) return;
   JdCol c{};
-  c.beta1 = sqrt(fmax(n2[j], 0.0));
-  c.phi = c.beta1;
-  c.c1 = c.c2 = 1.0;
-  c.s1 = c.s2 = 0.0;
-  c.beta = 0.0;
-  c.done = c.beta1 > 0.0 ? 0 : 1;
+  c.tau0 = sqrt(fmax(n2[j], 0.0));
+  c.tau = c.tau0;
+  c.theta = 0.0;
+  c.rho = rho0 ? rho0[j] : n2[j];
+  c.done = (c.tau0 > 0.0 && c.rho != 0.0) ? 0 : 1;
+  c.apply = 0;
   st[j] = c;
 }
 
-__global__ void k_jd_init_vecs(int64_t N, int nb, int64_t ld, const double* __restrict__ b,
-                               const JdCol* __restrict__ st, double* __restrict__ q,
-                               double* __restrict__ qp, double* __restrict__ d1,
-                               double* __restrict__ d2, double* __restrict__ x) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t i = t % N;
-  const int j = (int)(t / N);
+// q = t_0, d = 0, x = 0
+__global__ void k_jd_init_vecs(int64_t N, int nb, int64_t ld, const double* __restrict__ t,
+                               double* __restrict__ q, double* __restrict__ d,
+                               double* __restrict__ x) {
+  const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = e0 % N;
+  const int j = (int)(e0 / N);
   if (j >= nb) return;
   const int64_t e = i + j * ld;
-  const double b1 = st[j].beta1;
-  q[e] = b1 > 0.0 ? b[e] / b1 : 0.0;
-  qp[e] = 0.0;
-  d1[e] = 0.0;
-  d2[e] = 0.0;
+  q[e] = t[e];
+  d[e] = 0.0;
   x[e] = 0.0;
 }
 
-// z = (B q)_compact - s_j q   (the product arrives as a row-major N x nb block)
+// w = (B q)_compact - s_j q   (the product arrives as a row-major N x nb block)
 __global__ void k_jd_shift(int64_t N, int nb, const double* __restrict__ Wc,
                            const double* __restrict__ q, int64_t ld,
-                           const double* __restrict__ shift, double* __restrict__ z) {
+                           const double* __restrict__ shift, double* __restrict__ w) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t i = t / nb;
   const int j = (int)(t % nb);
   if (i >= N) return;
-  z[i + j * ld] = Wc[t] - shift[j] * q[i + j * ld];
+  w[i + j * ld] = Wc[t] - shift[j] * q[i + j * ld];
 }
 
-// z -= alpha_j q + beta_j q_prev, and partial sums of ||z_j||^2
-__global__ __launch_bounds__(kJT) void k_jd_lanczos(int64_t N, int nb, int64_t ld,
-                                                    double* __restrict__ z,
-                                                    const double* __restrict__ q,
-                                                    const double* __restrict__ qp,
-                                                    const double* __restrict__ alpha,
-                                                    const JdCol* __restrict__ st,
-                                                    double* __restrict__ partial) {
+__device__ inline double step_alpha(const JdCol& c, double sigma) {
+  return (!c.done && sigma != 0.0) ? c.rho / sigma : 0.0;
+}
+
+// r -= alpha_j w (alpha_j = rho_j / sigma_j of an active column, else 0) and
+// partial sums of ||r_j||^2
+__global__ __launch_bounds__(kJT) void k_jd_resid(int64_t N, int nb, int64_t ld,
+                                                  double* __restrict__ r,
+                                                  const double* __restrict__ w,
+                                                  const double* __restrict__ sigma,
+                                                  const JdCol* __restrict__ st,
+                                                  double* __restrict__ partial) {
   __shared__ double sh[kJT / kWave][kMaxBlock];
-  double a[kMaxBlock], bt[kMaxBlock], acc[kMaxBlock];
+  double a[kMaxBlock], acc[kMaxBlock];
 #pragma unroll
   for (int j = 0; j < kMaxBlock; ++j) {
-    a[j] = j < nb ? alpha[j] : 0.0;
-    bt[j] = j < nb ? st[j].beta : 0.0;
+    a[j] = j < nb ? step_alpha(st[j], sigma[j]) : 0.0;
     acc[j] = 0.0;
   }
   for (int64_t i = (int64_t)blockIdx.x * kJT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kJT) {
@@ -114,17 +124,17 @@ __global__ __launch_bounds__(kJT) void k_jd_lanczos(int64_t N, int nb, int64_t l
     for (int j = 0; j < kMaxBlock; ++j) {
       if (j < nb) {
         const int64_t e = i + j * ld;
-        const double v = z[e] - a[j] * q[e] - bt[j] * qp[e];
-        z[e] = v;
+        const double v = fma(-a[j], w[e], r[e]);
+        r[e] = v;
         acc[j] = fma(v, v, acc[j]);
       }
     }
   }
-  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
 #pragma unroll
   for (int j = 0; j < kMaxBlock; ++j) {
     const double v = wave_sum(acc[j]);
-    if (lane == 0) sh[w][j] = v;
+    if (lane == 0) sh[wv][j] = v;
   }
   __syncthreads();
   if (threadIdx.x < nb) {
@@ -134,67 +144,89 @@ __global__ __launch_bounds__(kJT) void k_jd_lanczos(int64_t N, int nb, int64_t l
   }
 }
 
-// the scalar step of MINRES for every column: the new column
-// [beta_k, alpha_k, beta_{k+1}] of the tridiagonal matrix through the two
-// previous rotations, the new rotation, the solution coefficient tau_k and
-// the residual norm |phi|
-__global__ void k_jd_scalar(int nb, const double* __restrict__ alpha,
-                            const double* __restrict__ bnext2, double tol,
+// the scalar QMR step of every column: the smoothing parameters, the new
+// quasi-residual norm tau, the increment coefficients, the stopping test;
+// without a preconditioner also rho' = ||r||^2 and beta
+__global__ void k_jd_scalar(int nb, const double* __restrict__ sigma,
+                            const double* __restrict__ rn2, double tol, int precond,
                             JdCol* __restrict__ st) {
   const int j = threadIdx.x;
   if (j >= nb) return;
   JdCol c = st[j];
   c.apply = 0;
   if (!c.done) {
-    const double al = alpha[j];
-    const double bn = sqrt(fmax(bnext2[j], 0.0));
-    const double eps = c.s2 * c.beta;
-    const double dlt = c.c2 * c.beta;
-    const double delta = c.c1 * dlt + c.s1 * al;
-    const double gbar = -c.s1 * dlt + c.c1 * al;
-    const double gamma = hypot(gbar, bn);
-    if (gamma > 0.0) {
-      const double cn = gbar / gamma, sn = bn / gamma;
-      c.tk = cn * c.phi;
-      c.phi = -sn * c.phi;
-      c.delta = delta;
-      c.eps = eps;
-      c.invg = 1.0 / gamma;
-      c.c2 = c.c1;
-      c.s2 = c.s1;
-      c.c1 = cn;
-      c.s1 = sn;
-      c.beta = bn;
-      c.apply = 1;
-      if (fabs(c.phi) <= tol * c.beta1 || bn == 0.0) c.done = 1;
+    const double sg = sigma[j];
+    if (sg == 0.0) {
+      c.done = 1;  // breakdown: keep the current solution
     } else {
-      c.done = 1;
+      const double alpha = c.rho / sg;
+      const double th = sqrt(fmax(rn2[j], 0.0)) / c.tau;
+      const double c2 = 1.0 / (1.0 + th * th);
+      c.tau = c.tau * th * sqrt(c2);
+      c.dcoef = c2 * c.theta * c.theta;
+      c.acoef = c2 * alpha;
+      c.theta = th;
+      c.apply = 1;
+      if (c.tau <= tol * c.tau0) c.done = 1;
+      if (!precond && !c.done) {
+        const double rho_next = rn2[j];
+        c.beta = rho_next / c.rho;
+        c.rho = rho_next;
+        if (rho_next == 0.0) c.done = 1;
+      }
     }
   }
   st[j] = c;
 }
 
-// d_new = (q - delta d1 - eps d2) / gamma;  x += tau d_new;  d2 <- d1, d1 <- d_new;
-// q_prev <- q;  q <- z / beta_{k+1}
+// d = dcoef d + acoef q;  x += d;  then, without a preconditioner, q = r + beta q,
+// with one, t = r (the input of the preconditioner)
 __global__ void k_jd_vec(int64_t N, int nb, int64_t ld, double* __restrict__ q,
-                         double* __restrict__ qp, const double* __restrict__ z,
-                         double* __restrict__ d1, double* __restrict__ d2,
-                         double* __restrict__ x, const JdCol* __restrict__ st) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t i = t % N;
-  const int j = (int)(t / N);
+                         double* __restrict__ d, double* __restrict__ x,
+                         const double* __restrict__ r, double* __restrict__ t,
+                         const JdCol* __restrict__ st) {
+  const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = e0 % N;
+  const int j = (int)(e0 / N);
   if (j >= nb) return;
   const JdCol& c = st[j];
   if (!c.apply) return;
   const int64_t e = i + j * ld;
   const double qv = q[e];
-  const double d1v = d1[e];
-  const double dn = (qv - c.delta * d1v - c.eps * d2[e]) * c.invg;
-  x[e] += c.tk * dn;
-  d2[e] = d1v;
-  d1[e] = dn;
-  qp[e] = qv;
-  q[e] = c.beta > 0.0 ? z[e] / c.beta : 0.0;
+  const double dn = c.dcoef * d[e] + c.acoef * qv;
+  d[e] = dn;
+  x[e] += dn;
+  if (t) {
+    t[e] = r[e];
+  } else if (!c.done) {
+    q[e] = r[e] + c.beta * qv;
+  }
+}
+
+// preconditioned: rho' = r . t, beta = rho' / rho, rho = rho'
+__global__ void k_jd_beta(int nb, const double* __restrict__ rho_next, JdCol* __restrict__ st) {
+  const int j = threadIdx.x;
+  if (j >= nb) return;
+  JdCol c = st[j];
+  if (c.apply && !c.done) {
+    c.beta = rho_next[j] / c.rho;
+    c.rho = rho_next[j];
+    if (c.rho == 0.0) c.done = 1;
+  }
+  st[j] = c;
+}
+
+// q = t + beta q for the columns that go on
+__global__ void k_jd_qupd(int64_t N, int nb, int64_t ld, const double* __restrict__ t,
+                          double* __restrict__ q, const JdCol* __restrict__ st) {
+  const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = e0 % N;
+  const int j = (int)(e0 / N);
+  if (j >= nb) return;
+  const JdCol& c = st[j];
+  if (!c.apply || c.done) return;
+  const int64_t e = i + j * ld;
+  q[e] = t[e] + c.beta * q[e];
 }
 
 }  // namespace
@@ -207,31 +239,35 @@ void jd_col_dots(const double* X, const double* Y, int64_t ld, int64_t N, int nb
   reduce_partials(partial, nblk, nb, out, s);
 }
 
-void jd_start(int64_t N, int nb, int64_t ld, const double* b, const double* n2, JdCol* st,
-              double* q, double* qp, double* d1, double* d2, double* x, hipStream_t s) {
-  k_jd_start<<<1, 64, 0, s>>>(nb, n2, st);
-  const int64_t tot = N * nb;
-  k_jd_init_vecs<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(N, nb, ld, b, st, q, qp, d1, d2, x);
+void jd_start(int64_t N, int nb, int64_t ld, const double* t, const double* n2,
+              const double* rho0, JdCol* st, double* q, double* d, double* x, hipStream_t s) {
+  k_jd_start<<<1, 64, 0, s>>>(nb, n2, rho0, st);
+  k_jd_init_vecs<<<elem_blocks(N * nb), 256, 0, s>>>(N, nb, ld, t, q, d, x);
   SVDS_LAUNCH_CHECK();
 }
 
 void jd_shift(int64_t N, int nb, const double* Wc, const double* q, int64_t ld,
-              const double* shift, double* z, hipStream_t s) {
-  const int64_t tot = N * nb;
-  k_jd_shift<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(N, nb, Wc, q, ld, shift, z);
+              const double* shift, double* w, hipStream_t s) {
+  k_jd_shift<<<elem_blocks(N * nb), 256, 0, s>>>(N, nb, Wc, q, ld, shift, w);
   SVDS_LAUNCH_CHECK();
 }
 
-void jd_step(int64_t N, int nb, int64_t ld, double* z, double* q, double* qp, double* d1,
-             double* d2, double* x, const double* alpha, double* bnext2, double tol, JdCol* st,
+void jd_step(int64_t N, int nb, int64_t ld, double* r, const double* w, double* q, double* d,
+             double* x, double* t, const double* sigma, double* rn2, double tol, JdCol* st,
              double* partial, hipStream_t s) {
   const int nblk = blocks_for(N);
-  k_jd_lanczos<<<nblk, kJT, 0, s>>>(N, nb, ld, z, q, qp, alpha, st, partial);
+  k_jd_resid<<<nblk, kJT, 0, s>>>(N, nb, ld, r, w, sigma, st, partial);
   SVDS_LAUNCH_CHECK();
-  reduce_partials(partial, nblk, nb, bnext2, s);
-  k_jd_scalar<<<1, 64, 0, s>>>(nb, alpha, bnext2, tol, st);
-  const int64_t tot = N * nb;
-  k_jd_vec<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(N, nb, ld, q, qp, z, d1, d2, x, st);
+  reduce_partials(partial, nblk, nb, rn2, s);
+  k_jd_scalar<<<1, 64, 0, s>>>(nb, sigma, rn2, tol, t != nullptr, st);
+  k_jd_vec<<<elem_blocks(N * nb), 256, 0, s>>>(N, nb, ld, q, d, x, r, t, st);
+  SVDS_LAUNCH_CHECK();
+}
+
+void jd_precond_step(int64_t N, int nb, int64_t ld, const double* rho_next, const double* t,
+                     double* q, JdCol* st, hipStream_t s) {
+  k_jd_beta<<<1, 64, 0, s>>>(nb, rho_next, st);
+  k_jd_qupd<<<elem_blocks(N * nb), 256, 0, s>>>(N, nb, ld, t, q, st);
   SVDS_LAUNCH_CHECK();
 }
 

@@ -246,13 +246,16 @@ def test_trained_network_beats_jacobi_and_none(P):
     MB.close()
 
 
-def test_learned_stage2_composition(P):
-    """Stage 2 on B with the learned K in the composition [K A^T r_u; A K r_v]."""
+@pytest.mark.parametrize("solver", ["jd", "gdk"])
+def test_learned_stage2_composition(P, solver):
+    """Stage 2 on B with the learned K in the composition [K A^T r_u; A K r_v],
+    inside the JD correction's symmetric QMR or on the GD+k residuals."""
     A = synth.config5(ng=12, seed=5013)
-    _say("learned stage 2 12x12 k=3 smallest")
+    _say("learned stage 2 12x12 k=3 smallest", solver)
     params = P.lpc_init(seed=5)
     sig, U, V, rn, st = P.svds(A, 3, "smallest", 1e-10, block_size=1, seed=2, force_stage2=1,
-                               precond=P.PC_LEARNED, pc_model=params, pc_degree=6)
+                               precond=P.PC_LEARNED, pc_model=params, pc_degree=6,
+                               stage2_solver=P.STAGE2_JD if solver == "jd" else P.STAGE2_GDK)
     assert st["converged"] and st["stage_exit"] == 2 and st["iters"][1] >= 0
     ref = _grid_dense_sigma(A, 3)
     assert np.max(np.abs(sig.cpu().numpy() - ref) / ref) <= 1e-9

@@ -398,7 +398,7 @@ def test_blockjacobi_solve(P):
 
 @pytest.mark.parametrize("target", ["largest", "smallest"])
 def test_jacobi_davidson_stage2(P, target):
-    """The JD second stage (MINRES inner solver) reaches the dense-LAPACK
+    """The JD second stage (symmetric-QMR inner solver) reaches the dense-LAPACK
     values from a loose stage 1 in fewer outer iterations than GD+k, as the
     oracle's JD stage does."""
     A = synth.config1()
@@ -418,6 +418,30 @@ def test_jacobi_davidson_stage2(P, target):
     assert out["jd"]["inner_iters"] > 0 and out["gdk"]["inner_iters"] == 0
     assert out["jd"]["iters"][1] < out["gdk"]["iters"][1]
     assert np.max(np.abs(o_s - ref) / ref) < 1e-10
+
+
+@pytest.mark.parametrize("pc", ["jacobi", "blockjacobi"])
+def test_preconditioned_jd_near_the_null_space_of_B(P, pc):
+    """Five smallest values of a kappa ~ 1e6 banded 1200 x 600 matrix, next to
+    the 600 zero eigenvalues of B: the default second stage (JD with the
+    preconditioned symmetric-QMR correction) converges in a few outer
+    iterations, as the oracle's does, to the dense-LAPACK values."""
+    A = synth.banded_scaled(1200, 600, seed=2005, log_lo=-6)
+    normA = float(np.linalg.norm(A.toarray(), 2))
+    ref = np.sort(np.linalg.svd(A.toarray(), compute_uv=False))[:5]
+    kw = dict(precond=P.PC_JACOBI) if pc == "jacobi" else dict(precond=P.PC_BLOCKJACOBI,
+                                                                pc_block=64)
+    _say("preconditioned JD banded_scaled 1200x600 smallest", pc)
+    sig, U, V, rn, st = P.svds(A, 5, "smallest", 1e-10, block_size=4, max_basis_size=35,
+                               min_restart_size=14, norm_A=normA, seed=2005, **kw)
+    assert st["converged"] and st["stage_exit"] == 2, st
+    assert st["inner_iters"] > 0 and st["iters"][1] <= 20, st
+    _compare(A, sig, U, V, rn, st, ref, 1e-10, normA, rel=1e-9)
+    o_s, _, _, _, o_st = oracle.svds(A, 5, "smallest", 1e-10, block=4, max_basis=35,
+                                     min_restart=14, norm_A=normA, seed=2005, precond=pc,
+                                     pc_block=64)
+    assert o_st["converged"] and o_st["iters"][1] <= 20
+    assert np.max(np.abs(o_s - sig.cpu().numpy()) / ref) < 1e-9
 
 
 def test_jacobi_davidson_ill_conditioned_and_wide(P):
