@@ -27,8 +27,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # HBM bytes per SpMM launch of the default workload from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by a copy kernel (profiles/spmm_banded_1e6x5e5_b4_fp64_hbm_traffic.md),
 # valid while the kernel source is the one those counters were taken on
-SPMM_TRAFFIC = {"workload": "banded_1e6x5e5_k10_smallest", "bytes_per_launch": 244.2e6,
-                "source": "paper_1607_01404_amd/csrc/k_spmm.hip", "sha256_prefix": "cf44994ea69fed23"}
+SPMM_TRAFFIC = {"workload": "banded_1e6x5e5_k10_smallest", "bytes_per_launch": 245.1e6,
+                "source": "paper_1607_01404_amd/csrc/k_spmm.hip", "sha256_prefix": "8d27654782fae0d0"}
 
 
 def spmm_traffic(workload):
