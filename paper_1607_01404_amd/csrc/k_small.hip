@@ -174,6 +174,328 @@ __device__ int jacobi_eig_lds(int n, double* A, double* Z, double* d, double* cs
   return sweep + 1;
 }
 
+// ---------------------------------------------------------------------------
+// symmetric eigenproblem of a bordered diagonal matrix.  A (g x g, ld kLs):
+// its leading g0 x g0 block is diagonal to rounding (the projected matrix in
+// the previous eigenbasis, or after a restart in the retained Ritz vectors),
+// the last g - g0 <= kBordMax columns are dense.  The border columns are
+// added one at a time; each step is the arrowhead eigenproblem
+// [[diag(lam), z], [z^T, alpha]] in the current eigenbasis, whose eigenvalues
+// are the roots of  alpha - mu - sum_j z_j^2 / (lam_j - mu) = 0,  one in each
+// gap between consecutive poles and one beyond each end.  Couplings below
+// 8 eps ||.|| deflate their pole; two poles closer than that (after a
+// rotation that moves the coupling onto the upper one) deflate the lower.
+// Each root is found by 16 lanes (the sums split over them) with a
+// safeguarded iteration that keeps its nearest pole exact and linearises
+// the rest, in coordinates relative to that pole.  The eigenvectors come
+// from Loewner's formula for the coupling vector that the computed roots
+// solve exactly (Gu and Eisenstat), which keeps them orthogonal.
+// Z holds an orthonormal W on entry and W U on return; d receives the
+// eigenvalues (ascending).  A is destroyed; U0, V (kLd x kLs) and Bc
+// (kLd x kBordMax) are scratch.
+// ---------------------------------------------------------------------------
+constexpr int kBordMax = 16;
+constexpr int kRootLanes = 16;
+
+__device__ __forceinline__ double group16_sum(double v) {
+#pragma unroll
+  for (int off = kRootLanes / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return __shfl(v, (int)(threadIdx.x % kWave) & ~(kRootLanes - 1), kWave);  // lane 0 of the group
+}
+
+template <int NT>
+__device__ void bordered_eig_lds(int g, int g0, double* A, double* Z, double* d, double* U0,
+                                 double* V, double* Bc) {
+  __shared__ double lam[kLd + 1], zv[kLd], dk[kLd], zk[kLd], zh[kLd], tau[kLd + 1];
+  __shared__ double nrm[kLd + 1], vals[kLd + 1];
+  __shared__ int kidx[kLd], defl[kLd], Kk[kLd + 1], pos[kLd + 1];
+  __shared__ int rot_p[kLd], rot_j[kLd];
+  __shared__ double rot_c[kLd], rot_s[kLd];
+  __shared__ int s_m, s_nrot;
+  __shared__ double s_lo, s_hi;
+  const int t = threadIdx.x;
+  const int nbd = g - g0;
+  for (int a = t; a < g * nbd; a += NT) {
+    const int r = a % g, c = a / g;
+    Bc[c * kLd + r] = A[r * kLs + g0 + c];
+  }
+  for (int i = t; i < g0; i += NT) vals[i] = A[i * kLs + i];
+  for (int a = t; a < g0 * g0; a += NT) U0[(a / g0) * kLs + (a % g0)] = 0.0;
+  __syncthreads();
+  for (int i = t; i < g0; i += NT) {  // ascending order: U = a permutation
+    const double v = vals[i];
+    int rank = 0;
+    for (int j = 0; j < g0; ++j) rank += (vals[j] < v || (vals[j] == v && j < i));
+    lam[rank] = v;
+    U0[i * kLs + rank] = 1.0;
+  }
+  __syncthreads();
+  double* U = U0;
+  double* Un = A;
+  for (int c = 0; c < nbd; ++c) {
+    const int n = g0 + c;  // size before this step
+    const double alpha = Bc[c * kLd + n];
+    for (int i = t; i < n; i += NT) {  // z = U^T x
+      double acc = 0.0;
+      for (int r = 0; r < n; ++r) acc = fma(U[r * kLs + i], Bc[c * kLd + r], acc);
+      zv[i] = acc;
+    }
+    __syncthreads();
+    if (t < kWave) {
+      // deflation in wave 0 (lane i: pole i); nearly equal poles are rare and
+      // take the serial path below
+      const int i = t;
+      const double zi = (i < n) ? zv[i] : 0.0;
+      const double li = (i < n) ? lam[i] : 0.0;
+      const double zn = wave_sum(zi * zi);
+      double lm = fabs(li);
+#pragma unroll
+      for (int off = kWave / 2; off > 0; off >>= 1) lm = fmax(lm, __shfl_xor(lm, off, kWave));
+      const double tol = 8.0 * kEps * fmax(fmax(lm, fabs(alpha)), sqrt(zn));
+      const bool keep = i < n && fabs(zi) > tol;
+      const unsigned long long kmask = __ballot(keep);
+      const unsigned long long below = (i == 0) ? 0ull : (kmask & ((1ull << i) - 1ull));
+      bool close = false;
+      if (keep && below) {
+        const int p = 63 - __clzll((long long)below);
+        const double zp = zv[p];
+        const double r = hypot(zp, zi);
+        close = fabs((zi / r) * (zp / r) * (li - lam[p])) <= tol;
+      }
+      const unsigned long long cmask = __ballot(close);
+      if (cmask == 0ull) {
+        const unsigned long long lower = (i == 0) ? 0ull : ((1ull << i) - 1ull);
+        const int m = __popcll(kmask);
+        if (keep) {
+          const int q = __popcll(kmask & lower);
+          kidx[q] = i;
+          dk[q] = li;
+          zk[q] = zi;
+        } else if (i < n) {
+          defl[__popcll(~kmask & lower)] = i;
+        }
+        const double zk2 = wave_sum(keep ? zi * zi : 0.0);
+        if (i == 0) {
+          const double znk = sqrt(zk2);
+          const double lo0 = m ? lam[__ffsll((long long)kmask) - 1] : alpha;
+          const double hi0 = m ? lam[63 - __clzll((long long)kmask)] : alpha;
+          s_lo = fmin(lo0, alpha) - znk - tol;
+          s_hi = fmax(hi0, alpha) + znk + tol;
+          s_m = m;
+          s_nrot = 0;
+        }
+      } else if (i == 0) {
+        int m = 0, nrot = 0;
+        for (int j = 0; j < n; ++j) {
+          if (!(fabs(zv[j]) > tol)) continue;
+          if (m > 0) {
+            const int p = kidx[m - 1];
+            const double r = hypot(zv[p], zv[j]);
+            const double cc = zv[j] / r, ss = zv[p] / r;
+            if (fabs(cc * ss * (lam[j] - lam[p])) <= tol) {
+              const double lp = cc * cc * lam[p] + ss * ss * lam[j];
+              const double lj = ss * ss * lam[p] + cc * cc * lam[j];
+              lam[p] = lp;
+              lam[j] = lj;
+              zv[p] = 0.0;
+              zv[j] = r;
+              rot_p[nrot] = p;
+              rot_j[nrot] = j;
+              rot_c[nrot] = cc;
+              rot_s[nrot] = ss;
+              ++nrot;
+              --m;
+            }
+          }
+          kidx[m++] = j;
+        }
+        double zk2 = 0.0;
+        for (int j = 0; j < m; ++j) {
+          dk[j] = lam[kidx[j]];
+          zk[j] = zv[kidx[j]];
+          zk2 = fma(zk[j], zk[j], zk2);
+        }
+        int q = 0, nd = 0;
+        for (int j = 0; j < n; ++j) {
+          if (q < m && kidx[q] == j) ++q;
+          else defl[nd++] = j;
+        }
+        const double znk = sqrt(zk2);
+        s_lo = (m ? fmin(dk[0], alpha) : alpha) - znk - tol;
+        s_hi = (m ? fmax(dk[m - 1], alpha) : alpha) + znk + tol;
+        s_m = m;
+        s_nrot = nrot;
+      }
+    }
+    __syncthreads();
+    const int m = s_m;
+    const int nrot = s_nrot;
+    for (int r = t; r < n && nrot > 0; r += NT) {  // deflation rotations on U's columns
+      for (int q = 0; q < nrot; ++q) {
+        const int p = rot_p[q], j = rot_j[q];
+        const double up = U[r * kLs + p], uj = U[r * kLs + j];
+        U[r * kLs + p] = rot_c[q] * up - rot_s[q] * uj;
+        U[r * kLs + j] = rot_s[q] * up + rot_c[q] * uj;
+      }
+    }
+    if (m == 0) {
+      if (t == 0) {
+        Kk[0] = -1;
+        tau[0] = alpha;
+      }
+    } else if (t < (m + 1) * kRootLanes) {  // whole 16-lane groups
+      const int k = t / kRootLanes, l = t % kRootLanes;
+      int K;
+      double a, b;
+      if (k == 0) {
+        K = 0;
+        a = s_lo - dk[0];
+        b = 0.0;
+      } else if (k == m) {
+        K = m - 1;
+        a = 0.0;
+        b = s_hi - dk[m - 1];
+      } else {
+        const double base = dk[k - 1];
+        const double mid = 0.5 * (dk[k] - base);
+        double s = 0.0;
+        for (int j = l; j < m; j += kRootLanes) s += zk[j] * zk[j] / ((dk[j] - base) - mid);
+        s = group16_sum(s);
+        if ((alpha - base) - mid - s < 0.0) {  // root left of the middle: origin dk[k-1]
+          K = k - 1;
+          a = 0.0;
+          b = mid;
+        } else {
+          K = k;
+          a = -mid;
+          b = 0.0;
+        }
+      }
+      const double dK = dk[K], zK2 = zk[K] * zk[K], aK = alpha - dK;
+      double tt = 0.5 * (a + b);
+      for (int it = 0; it < 200; ++it) {
+        double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        for (int j = l; j < m; j += kRootLanes) {
+          if (j == K) continue;
+          const double qj = zk[j] / ((dk[j] - dK) - tt);
+          s1 = fma(zk[j], qj, s1);
+          s2 = fma(qj, qj, s2);
+          s3 += fabs(zk[j] * qj);
+        }
+        s1 = group16_sum(s1);
+        s2 = group16_sum(s2);
+        s3 = group16_sum(s3);
+        const double R = aK - tt - s1;  // the secular function without the origin pole
+        const double Rp = -1.0 - s2;
+        const double f = R + zK2 / tt;
+        if (fabs(f) <= 8.0 * kEps * (fabs(aK) + fabs(tt) + s3 + zK2 / fabs(tt))) break;
+        if (f > 0.0) a = tt;
+        else b = tt;
+        // R + Rp (x - tt) + zK2 / x = 0, i.e. Rp x^2 + B x + zK2 = 0 (Rp < 0: real roots)
+        const double B = R - Rp * tt;
+        const double sq = sqrt(B * B - 4.0 * Rp * zK2);
+        double r1, r2;
+        if (B >= 0.0) {
+          const double w = -B - sq;
+          r1 = w / (2.0 * Rp);
+          r2 = 2.0 * zK2 / w;
+        } else {
+          const double w = -B + sq;
+          r1 = 2.0 * zK2 / w;
+          r2 = w / (2.0 * Rp);
+        }
+        double tn = 0.5 * (a + b);
+        if (a < r1 && r1 < b) tn = r1;
+        else if (a < r2 && r2 < b) tn = r2;
+        const bool stop = fabs(tn - tt) <= 4.0 * kEps * fabs(tn) ||
+                          (b - a) <= 4.0 * kEps * fmax(fabs(a), fabs(b));
+        tt = tn;
+        if (stop) break;
+      }
+      if (l == 0) {
+        Kk[k] = K;
+        tau[k] = tt;
+      }
+    }
+    __syncthreads();
+    // roots mu_k = dk[Kk[k]] + tau[k]; Loewner's coupling vector
+    if (t < m * kRootLanes) {  // 16 lanes per pole j, whole groups
+      const int j = t / kRootLanes, l = t % kRootLanes;
+      const double dj = dk[j];
+      double p = (l == 0) ? (dk[Kk[m]] - dj) + tau[m] : 1.0;
+      for (int k = l; k < m; k += kRootLanes) {
+        const double num = (dk[Kk[k]] - dj) + tau[k];
+        p *= (k == j) ? num : num / (dk[k] - dj);
+      }
+#pragma unroll
+      for (int off = kRootLanes / 2; off > 0; off >>= 1) p *= __shfl_xor(p, off, kWave);
+      if (l == 0) zh[j] = copysign(sqrt(fabs(p)), zk[j]);
+    }
+    // the new eigenvalues in ascending order: roots first, then deflated poles
+    for (int q = t; q <= n; q += NT) {
+      const double v = (q <= m) ? ((m == 0) ? alpha : dk[Kk[q]] + tau[q]) : lam[defl[q - m - 1]];
+      vals[q] = v;
+    }
+    __syncthreads();
+    for (int a = t; a < (m + 1) * (m + 1); a += NT) {  // arrowhead eigenvectors (unnormalised)
+      const int j = a % (m + 1), k = a / (m + 1);
+      V[j * kLs + k] = (j < m) ? zh[j] / ((dk[j] - dk[Kk[k]]) - tau[k]) : -1.0;
+    }
+    for (int q = t; q <= n; q += NT) {
+      const double v = vals[q];
+      int rank = 0;
+      for (int j = 0; j <= n; ++j) rank += (vals[j] < v || (vals[j] == v && j < q));
+      pos[q] = rank;
+    }
+    __syncthreads();
+    if (t < (m + 1) * kRootLanes) {  // 16 lanes per column k
+      const int k = t / kRootLanes, l = t % kRootLanes;
+      double s = 0.0;
+      for (int j = l; j <= m; j += kRootLanes) s = fma(V[j * kLs + k], V[j * kLs + k], s);
+      s = group16_sum(s);
+      if (l == 0) nrm[k] = 1.0 / sqrt(s);
+    }
+    __syncthreads();
+    // Un = [U 0; 0 1] [arrowhead eigenvectors | deflated unit vectors], columns in order
+    for (int a = t; a < (n + 1) * (n + 1); a += NT) {
+      const int r = a / (n + 1), q = a % (n + 1);
+      double v;
+      if (q <= m) {
+        if (r == n) {
+          v = -nrm[q];
+        } else {
+          double acc = 0.0;
+          for (int j = 0; j < m; ++j) acc = fma(U[r * kLs + kidx[j]], V[j * kLs + q], acc);
+          v = acc * nrm[q];
+        }
+      } else {
+        v = (r < n) ? U[r * kLs + defl[q - m - 1]] : 0.0;
+      }
+      Un[r * kLs + pos[q]] = v;
+    }
+    __syncthreads();
+    for (int q = t; q <= n; q += NT) lam[pos[q]] = vals[q];
+    double* tmp = U;
+    U = Un;
+    Un = tmp;
+    __syncthreads();
+  }
+  for (int i = t; i < g; i += NT) d[i] = lam[i];
+  // Z <- W U
+  for (int a = t; a < g * g; a += NT) {
+    const int r = a / g, c = a % g;
+    double acc = 0.0;
+    for (int i = 0; i < g; ++i) acc = fma(Z[r * kLs + i], U[i * kLs + c], acc);
+    Un[r * kLs + c] = acc;
+  }
+  __syncthreads();
+  for (int a = t; a < g * g; a += NT) {
+    const int r = a / g, c = a % g;
+    Z[r * kLs + c] = Un[r * kLs + c];
+  }
+  __syncthreads();
+}
+
 // sort eigenpairs: theta[rank] = d[i], Y[:, rank] = Z[0:n, i]
 __device__ void sort_pairs(int n, const double* d, const double* Z, int descending,
                            double* theta, double* Y, int ldy) {
@@ -338,15 +660,19 @@ void small_svd(int g, const double* R, int ldr, double* s, double* Y, int ldy, d
 // ---------------------------------------------------------------------------
 __global__ void k_h_append(Small* d, int gc, int nb) {
   const int tot = gc + nb;
-  // previous eigenvectors stay a good start: W <- diag(W, I)
-  const bool warm = d->warm_g == gc;
+  // previous eigenvectors stay a good start: W <- diag(W, I); a projected
+  // matrix built from nothing starts from W = I with no diagonal block
+  const bool warm = d->warm_g == gc || gc == 0;
   for (int a = threadIdx.x; a < tot * tot; a += blockDim.x) {
     const int i = a % tot, j = a / tot;
     if (i < gc && j < gc) continue;
     d->Yw[j * kLd + i] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  if (threadIdx.x == 0) d->warm_g = warm ? tot : -1;
+  if (threadIdx.x == 0) {
+    d->warm_g = warm ? tot : -1;
+    if (gc == 0) d->warm_diag = 0;
+  }
   for (int a = threadIdx.x; a < tot * nb; a += blockDim.x) {
     const int i = a % tot, c = a / tot;
     const int j = gc + c;
@@ -370,44 +696,71 @@ void small_h_append(Small* d, int gc, int nb, hipStream_t s) {
 // refined projection, right singular vectors of Rr in ascending order with
 // theta_j = y_j^T H y_j (Section 3.2)
 // ---------------------------------------------------------------------------
+// A (g x g) <- Z^T A Z, symmetrised; Mx scratch
+__device__ void project_lds(int g, double* A, const double* Z, double* Mx) {
+  const int t = threadIdx.x;
+  for (int a = t; a < g * g; a += kEigT) {
+    const int i = a % g, j = a / g;
+    double acc = 0.0;
+    for (int c = 0; c < g; ++c) acc += A[i * kLs + c] * Z[c * kLs + j];
+    Mx[i * kLs + j] = acc;
+  }
+  __syncthreads();
+  for (int a = t; a < g * g; a += kEigT) {
+    const int i = a % g, j = a / g;
+    double acc = 0.0;
+    for (int c = 0; c < g; ++c) acc += Z[c * kLs + i] * Mx[c * kLs + j];
+    A[i * kLs + j] = acc;
+  }
+  __syncthreads();
+  for (int a = t; a < g * g; a += kEigT) {
+    const int i = a % g, j = a / g;
+    if (i < j) {
+      const double v = 0.5 * (A[i * kLs + j] + A[j * kLs + i]);
+      A[i * kLs + j] = v;
+      A[j * kLs + i] = v;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ void load_sym_h(const Small* d, int g, double* A) {
+  for (int a = threadIdx.x; a < g * g; a += kEigT) {
+    const int i = a % g, j = a / g;
+    A[i * kLs + j] = 0.5 * (d->H[j * kLd + i] + d->H[i * kLd + j]);
+  }
+}
+
+// Rayleigh-Ritz extraction.  H is expressed in the warm basis W (the
+// previous eigenvectors, padded with the identity for new columns), where its
+// leading block is diagonal to rounding.  When the dense border is narrow the
+// bordered solver gives eigenvectors W U of that form; H is then projected on
+// them again and the threshold Jacobi finishes on the exact projection (one
+// active sweep in practice), so the rounding of the warm basis never
+// accumulates from one extraction to the next.  Otherwise Jacobi runs from W.
 __global__ __launch_bounds__(kEigT) void k_extract_rr(Small* d, int gc, int descending) {
   __shared__ double A[kLd * kLs];
   __shared__ double Z[kLd * kLs];
   __shared__ double Mx[kLd * kLs];
+  __shared__ double Vb[kLd * kLs];
+  __shared__ double Bc[kLd * kBordMax];
   __shared__ double dd[kLd], cs[kLd], sn[kLd];
   __shared__ int flag;
   const int t = threadIdx.x;
   const bool warm = d->warm_g == gc;
+  load_sym_h(d, gc, A);
   for (int a = t; a < gc * gc; a += kEigT) {
     const int i = a % gc, j = a / gc;
-    A[i * kLs + j] = 0.5 * (d->H[j * kLd + i] + d->H[i * kLd + j]);
     Z[i * kLs + j] = warm ? d->Yw[j * kLd + i] : (i == j ? 1.0 : 0.0);
   }
   __syncthreads();
-  if (warm) {  // A <- W^T A W with W the previous eigenvectors (padded)
-    for (int a = t; a < gc * gc; a += kEigT) {
-      const int i = a % gc, j = a / gc;
-      double acc = 0.0;
-      for (int c = 0; c < gc; ++c) acc += A[i * kLs + c] * Z[c * kLs + j];
-      Mx[i * kLs + j] = acc;
-    }
+  if (warm) project_lds(gc, A, Z, Mx);
+  const int g0 = warm ? d->warm_diag : -1;
+  if (warm && g0 >= 0 && g0 <= gc && gc - g0 <= kBordMax) {
+    bordered_eig_lds<kEigT>(gc, g0, A, Z, dd, Mx, Vb, Bc);
+    load_sym_h(d, gc, A);
     __syncthreads();
-    for (int a = t; a < gc * gc; a += kEigT) {
-      const int i = a % gc, j = a / gc;
-      double acc = 0.0;
-      for (int c = 0; c < gc; ++c) acc += Z[c * kLs + i] * Mx[c * kLs + j];
-      A[i * kLs + j] = acc;
-    }
-    __syncthreads();
-    for (int a = t; a < gc * gc; a += kEigT) {  // symmetrise
-      const int i = a % gc, j = a / gc;
-      if (i < j) {
-        const double v = 0.5 * (A[i * kLs + j] + A[j * kLs + i]);
-        A[i * kLs + j] = v;
-        A[j * kLs + i] = v;
-      }
-    }
-    __syncthreads();
+    project_lds(gc, A, Z, Mx);
   }
   const int nsw = jacobi_eig_lds<kEigT>(gc, A, Z, dd, cs, sn, &flag);
   if (t == 0) d->eig_sweeps = nsw;
@@ -416,7 +769,10 @@ __global__ __launch_bounds__(kEigT) void k_extract_rr(Small* d, int gc, int desc
     const int i = a % gc, j = a / gc;
     d->Yw[j * kLd + i] = d->Y[j * kLd + i];
   }
-  if (t == 0) d->warm_g = gc;
+  if (t == 0) {
+    d->warm_g = gc;
+    d->warm_diag = gc;
+  }
 }
 
 __global__ __launch_bounds__(kT) void k_extract_refined(Small* d, int gc) {
@@ -875,8 +1231,16 @@ __global__ __launch_bounds__(kT) void k_control(Small* d, CtlParams P) {
       const int i = a % gc, j = a / gc;
       d->Yr[j * kLd + i] = Yr[i * kLs + j];
     }
+    // the retained extraction vectors are eigenvectors of H (Rayleigh-Ritz), so
+    // the leading reff x reff block of the restarted H is diagonal: warm start
+    // from the identity with that block known diagonal
+    for (int a = t; a < nr * nr; a += kT) {
+      const int i = a % nr, j = a / nr;
+      d->Yw[j * kLd + i] = (i == j) ? 1.0 : 0.0;
+    }
     if (t == 0) {
-      d->warm_g = -1;
+      d->warm_g = P.refined ? -1 : nr;
+      d->warm_diag = reff;
       d->ctl.restart = 1;
       d->ctl.nr = nr;
       if (action == kExpand) {

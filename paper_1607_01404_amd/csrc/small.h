@@ -45,6 +45,7 @@ struct Small {
   double Y[kLd * kLd];     // extraction vectors (eigen- or right singular vectors)
   double Yw[kLd * kLd];    // warm start for the eigensolver: H is nearly diagonal in it
   int warm_g;              // its size (-1: none)
+  int warm_diag;           // leading block of Yw^T H Yw that is diagonal to rounding
   double theta[kLd];       // Ritz values (refined: y^T H y)
   double sv[kLd];          // refined: singular values of Rr
   double Rr[kLd * kLd];    // refined: R of (W - tau V) = Q Rr
