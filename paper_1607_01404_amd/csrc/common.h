@@ -202,16 +202,20 @@ struct SegT {
 using Seg = SegT<double>;
 using Seg32 = SegT<float>;
 int reduce_blocks(int64_t N);
-// out[o] = sum over blocks of P[o * nblk + block]  (fixed order)
-void reduce_partials(const double* P, int nblk, int nout, double* out, hipStream_t s);
-// C ((sum of seg cols) x b, col-major, ld = total) = [segs]^T T
+// out[o] = sum over blocks of P[o * nblk + block]  (fixed order); with a
+// device flag *skip != 0 the outputs are zero (the producing pass was skipped)
+void reduce_partials(const double* P, int nblk, int nout, double* out, hipStream_t s,
+                     const int* skip = nullptr);
+// C ((sum of seg cols) x b, col-major, ld = total) = [segs]^T T; a non-null
+// skip points to a device flag that, when set, turns the pass into C = 0
 template <typename TB>
 void tsgemm_tn(const SegT<TB>* segs, int nseg, int64_t N, const double* T, int64_t ldt, int b,
-               double* partial, double* C, hipStream_t s);
-// T -= [segs] C   (C: total x b, column-major with leading dimension ldc)
+               double* partial, double* C, hipStream_t s, const int* skip = nullptr);
+// T -= [segs] C   (C: total x b, column-major with leading dimension ldc);
+// nothing when the device flag *skip is set
 template <typename TB>
 void ts_update(const SegT<TB>* segs, int nseg, int64_t N, const double* C, int ldc, double* T,
-               int64_t ldt, int b, hipStream_t s);
+               int64_t ldt, int b, hipStream_t s, const int* skip = nullptr);
 // Out (N x nout) = Q (N x nq) Y (nq x nout, ld ldy); Out may not alias Q
 template <typename TI, typename TO>
 void ts_gemm_nn(const TI* Q, int64_t ldq, int nq, int64_t N, const double* Y, int64_t ldy,

@@ -295,6 +295,7 @@ class Solver {
       G0 = d_->C0 + total;
       ldg0 = total + nb;
       ldc0 = total + nb;
+      if (total > 0) small_dgks(d_, total, nb, d_->C0, ldc0, s_);
     } else {
       tsgemm_tn(&st, 1, N_, T, ldt, nb, partial_, d_->G0, s_);
       if (total > 0) tsgemm_tn(sb, n1, N_, T, ldt, nb, partial_, d_->C0, s_);
@@ -303,9 +304,12 @@ class Solver {
       ldc0 = total;
     }
     if (total > 0) {
+      // second pass only where the device-side test asks for it (FP64 basis);
+      // the FP32 basis of the mixed stage always takes both passes
+      const int* sk = std::is_same<TB, double>::value ? &d_->skip2 : nullptr;
       ts_update(sb, n1, N_, d_->C0, ldc0, T, ldt, nb, s_);
-      tsgemm_tn(sb, n1, N_, T, ldt, nb, partial_, d_->C1, s_);
-      ts_update(sb, n1, N_, d_->C1, total, T, ldt, nb, s_);
+      tsgemm_tn(sb, n1, N_, T, ldt, nb, partial_, d_->C1, s_, sk);
+      ts_update(sb, n1, N_, d_->C1, total, T, ldt, nb, s_, sk);
     }
     tsgemm_tn(&st, 1, N_, T, ldt, nb, partial_, d_->G, s_);
     small_chol(d_, nb, 1, G0, ldg0, s_);

@@ -71,7 +71,9 @@ template <int B, typename TB>
 __global__ __launch_bounds__(kThreads) void k_tsgemm_tn(Segs3T<TB> segs, int total, int64_t N,
                                                         const double* __restrict__ T,
                                                         int64_t ldt, int64_t chunk,
-                                                        double* __restrict__ partial) {
+                                                        double* __restrict__ partial,
+                                                        const int* __restrict__ skip) {
+  if (skip && *skip) return;  // device-side decision: this pass is not needed
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int c0 = blockIdx.y * (4 * kCPW) + w * kCPW;
   if (c0 >= total) return;  // the whole wavefront has no column
@@ -121,8 +123,13 @@ __global__ __launch_bounds__(kThreads) void k_tsgemm_tn(Segs3T<TB> segs, int tot
 
 // one wavefront per output: out[o] = sum over blocks of P[o * nblk + block]
 __global__ __launch_bounds__(64) void k_reduce_partials(const double* __restrict__ P, int nblk,
-                                                        double* __restrict__ out) {
+                                                        double* __restrict__ out,
+                                                        const int* __restrict__ skip) {
   const int o = blockIdx.x;
+  if (skip && *skip) {  // the producing pass was skipped: its result is zero
+    if (threadIdx.x == 0) out[o] = 0.0;
+    return;
+  }
   const double* p = P + (int64_t)o * nblk;
   double s = 0.0;
   for (int b = threadIdx.x; b < nblk; b += 64) s += p[b];
@@ -130,9 +137,10 @@ __global__ __launch_bounds__(64) void k_reduce_partials(const double* __restrict
   if (threadIdx.x == 0) out[o] = s;
 }
 
-void reduce_partials(const double* P, int nblk, int nout, double* out, hipStream_t s) {
+void reduce_partials(const double* P, int nblk, int nout, double* out, hipStream_t s,
+                     const int* skip) {
   if (nout <= 0) return;
-  k_reduce_partials<<<nout, 64, 0, s>>>(P, nblk, out);
+  k_reduce_partials<<<nout, 64, 0, s>>>(P, nblk, out, skip);
   SVDS_LAUNCH_CHECK();
 }
 
@@ -156,7 +164,7 @@ static Segs3T<TB> make_segs(const SegT<TB>* segs, int nseg, int& total) {
 
 template <int B, typename TB>
 static void tsgemm_b(const Segs3T<TB>& sg, int total, int64_t N, const double* T, int64_t ldt,
-                     double* partial, double* C, hipStream_t s) {
+                     double* partial, double* C, hipStream_t s, const int* skip) {
   // one contiguous row range per workgroup column (several 256-row steps
   // amortise the final wave reductions)
   int nb = std::min(reduce_blocks(N), 256);
@@ -167,34 +175,34 @@ static void tsgemm_b(const Segs3T<TB>& sg, int total, int64_t N, const double* T
     nb = (nb + 7) / 8 * 8;
   }
   dim3 grid(nb, (total + 4 * kCPW - 1) / (4 * kCPW));
-  k_tsgemm_tn<B, TB><<<grid, kThreads, 0, s>>>(sg, total, N, T, ldt, chunk, partial);
+  k_tsgemm_tn<B, TB><<<grid, kThreads, 0, s>>>(sg, total, N, T, ldt, chunk, partial, skip);
   SVDS_LAUNCH_CHECK();
-  reduce_partials(partial, nb, total * B, C, s);
+  reduce_partials(partial, nb, total * B, C, s, skip);
 }
 
 template <typename TB>
 void tsgemm_tn(const SegT<TB>* segs, int nseg, int64_t N, const double* T, int64_t ldt, int b,
-               double* partial, double* C, hipStream_t s) {
+               double* partial, double* C, hipStream_t s, const int* skip) {
   int total = 0;
   Segs3T<TB> sg = make_segs(segs, nseg, total);
   if (total == 0) return;
   if (total > kMaxSegCols) throw Error(SVDS_ERR_ARG, "projection too wide");
   switch (b) {
-    case 1: tsgemm_b<1>(sg, total, N, T, ldt, partial, C, s); break;
-    case 2: tsgemm_b<2>(sg, total, N, T, ldt, partial, C, s); break;
-    case 3: tsgemm_b<3>(sg, total, N, T, ldt, partial, C, s); break;
-    case 4: tsgemm_b<4>(sg, total, N, T, ldt, partial, C, s); break;
-    case 5: tsgemm_b<5>(sg, total, N, T, ldt, partial, C, s); break;
-    case 6: tsgemm_b<6>(sg, total, N, T, ldt, partial, C, s); break;
-    case 7: tsgemm_b<7>(sg, total, N, T, ldt, partial, C, s); break;
-    case 8: tsgemm_b<8>(sg, total, N, T, ldt, partial, C, s); break;
+    case 1: tsgemm_b<1>(sg, total, N, T, ldt, partial, C, s, skip); break;
+    case 2: tsgemm_b<2>(sg, total, N, T, ldt, partial, C, s, skip); break;
+    case 3: tsgemm_b<3>(sg, total, N, T, ldt, partial, C, s, skip); break;
+    case 4: tsgemm_b<4>(sg, total, N, T, ldt, partial, C, s, skip); break;
+    case 5: tsgemm_b<5>(sg, total, N, T, ldt, partial, C, s, skip); break;
+    case 6: tsgemm_b<6>(sg, total, N, T, ldt, partial, C, s, skip); break;
+    case 7: tsgemm_b<7>(sg, total, N, T, ldt, partial, C, s, skip); break;
+    case 8: tsgemm_b<8>(sg, total, N, T, ldt, partial, C, s, skip); break;
     default: throw Error(SVDS_ERR_ARG, "tsgemm: b must be 1..8");
   }
 }
 template void tsgemm_tn<double>(const SegT<double>*, int, int64_t, const double*, int64_t, int,
-                                double*, double*, hipStream_t);
+                                double*, double*, hipStream_t, const int*);
 template void tsgemm_tn<float>(const SegT<float>*, int, int64_t, const double*, int64_t, int,
-                               double*, double*, hipStream_t);
+                               double*, double*, hipStream_t, const int*);
 
 // ---------------------------------------------------------------------------
 // T -= [segs] C      (C: total x b, column-major)
@@ -202,7 +210,9 @@ template void tsgemm_tn<float>(const SegT<float>*, int, int64_t, const double*, 
 template <int B, typename TB>
 __global__ __launch_bounds__(kThreads) void k_ts_update(Segs3T<TB> segs, int total, int64_t N,
                                                         const double* __restrict__ C, int ldc,
-                                                        double* __restrict__ T, int64_t ldt) {
+                                                        double* __restrict__ T, int64_t ldt,
+                                                        const int* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ double cs[kMaxSegCols * B];
   for (int a = threadIdx.x; a < total * B; a += kThreads) {
     int j = a / B, c = a % B;
@@ -227,7 +237,7 @@ __global__ __launch_bounds__(kThreads) void k_ts_update(Segs3T<TB> segs, int tot
 
 template <typename TB>
 void ts_update(const SegT<TB>* segs, int nseg, int64_t N, const double* C, int ldc, double* T,
-               int64_t ldt, int b, hipStream_t s) {
+               int64_t ldt, int b, hipStream_t s, const int* skip) {
   int total = 0;
   Segs3T<TB> sg = make_segs(segs, nseg, total);
   if (total == 0) return;
@@ -235,7 +245,7 @@ void ts_update(const SegT<TB>* segs, int nseg, int64_t N, const double* C, int l
   int nb = reduce_blocks(N);
   switch (b) {
 #define CASE(BB) \
-  case BB: k_ts_update<BB, TB><<<nb, kThreads, 0, s>>>(sg, total, N, C, ldc, T, ldt); break;
+  case BB: k_ts_update<BB, TB><<<nb, kThreads, 0, s>>>(sg, total, N, C, ldc, T, ldt, skip); break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
     default: throw Error(SVDS_ERR_ARG, "ts_update: b must be 1..8");
@@ -243,9 +253,9 @@ void ts_update(const SegT<TB>* segs, int nseg, int64_t N, const double* C, int l
   SVDS_LAUNCH_CHECK();
 }
 template void ts_update<double>(const SegT<double>*, int, int64_t, const double*, int, double*,
-                                int64_t, int, hipStream_t);
+                                int64_t, int, hipStream_t, const int*);
 template void ts_update<float>(const SegT<float>*, int, int64_t, const double*, int, double*,
-                               int64_t, int, hipStream_t);
+                               int64_t, int, hipStream_t, const int*);
 
 // ---------------------------------------------------------------------------
 // Out = Q Y   (restart V <- V Y, W <- W Y, Q <- Q Q~, locking x = V y)

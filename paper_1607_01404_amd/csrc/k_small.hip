@@ -686,6 +686,28 @@ __global__ void k_h_append(Small* d, int gc, int nb) {
   }
 }
 
+// second-pass test of classical Gram-Schmidt (Daniel, Gragg, Kaufman and
+// Stewart): after one pass against an orthonormal basis a column whose norm
+// fell by less than a factor sqrt(2) is orthogonal to working accuracy, so
+// the second pass is needed only when some column lost more
+__global__ void k_dgks(Small* d, int total, int nb, const double* __restrict__ C0, int ldc0) {
+  const int lane = threadIdx.x;
+  int need = 0;
+  for (int c = 0; c < nb; ++c) {
+    double s = 0.0;
+    for (int j = lane; j < total; j += kWave) s = fma(C0[(int64_t)c * ldc0 + j], C0[(int64_t)c * ldc0 + j], s);
+    s = wave_sum(s);
+    const double g0 = C0[(int64_t)c * ldc0 + total + c];
+    if (!(s <= 0.5 * g0)) need = 1;
+  }
+  if (lane == 0) d->skip2 = need ? 0 : 1;
+}
+
+void small_dgks(Small* d, int total, int nb, const double* C0, int ldc0, hipStream_t s) {
+  k_dgks<<<1, kWave, 0, s>>>(d, total, nb, C0, ldc0);
+  SVDS_LAUNCH_CHECK();
+}
+
 void small_h_append(Small* d, int gc, int nb, hipStream_t s) {
   k_h_append<<<1, kT, 0, s>>>(d, gc, nb);
   SVDS_LAUNCH_CHECK();

@@ -64,6 +64,7 @@ struct Small {
   int stall[kKmax + 8];
   int blk[kMaxBlock];
   int bad;                // orthogonalisation breakdown bitmask
+  int skip2;              // 1: the second Gram-Schmidt pass is not needed
   int nprev, gprev;       // +k vectors: count and rows
   double normop;          // running ||Op||
   int eig_sweeps;
@@ -90,6 +91,10 @@ void small_eig(int g, const double* H, int ldh, int descending, double* theta, d
 void small_svd(int g, const double* R, int ldr, double* s, double* Y, int ldy, double* AV,
                int ldav, hipStream_t st);
 void small_h_append(Small* d, int gc, int nb, hipStream_t s);
+// d->skip2 = every column kept at least 1/sqrt(2) of its norm in the first
+// Gram-Schmidt pass: ||c_j||^2 <= G0_jj / 2 with C0 (total x nb, ld ldc0) the
+// coefficients of the pass and G0 = C0 + total the block's own Gram matrix
+void small_dgks(Small* d, int total, int nb, const double* C0, int ldc0, hipStream_t s);
 void small_extract(Small* d, int gc, int descending, int refined, hipStream_t s);
 // which = 1: also test columns that collapsed during projection against the
 // pre-projection Gram diagonal G0[j*ldg0 + j]
