@@ -278,7 +278,6 @@ class Solver {
                      double* compact) {
     int total = 0;
     for (int i = 0; i < nseg; ++i) total += segs[i].ncols;
-    SVDS_HIP(hipMemsetAsync(&d_->bad, 0, sizeof(int), s_));
     SegT<TB> sb[3];
     int n1 = 0;
     for (int i = 0; i < nseg; ++i)

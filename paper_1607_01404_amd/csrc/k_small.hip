@@ -897,7 +897,11 @@ __global__ void k_chol(Small* d, int nb, int which, const double* G0, int ldg0) 
     Ro[t] = R[t];
     Rio[t] = Ri[t];
   }
-  if (t == 0 && sbad) d->bad |= sbad;
+  // the first factor of a block starts the breakdown record, the second adds to it
+  if (t == 0) {
+    if (which == 1) d->bad = sbad;
+    else if (sbad) d->bad |= sbad;
+  }
 }
 
 void small_chol(Small* d, int nb, int which, const double* G0, int ldg0, hipStream_t s) {
