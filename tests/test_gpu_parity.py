@@ -461,3 +461,24 @@ def test_jacobi_davidson_ill_conditioned_and_wide(P):
     s = np.sort(np.linalg.svd(W.toarray(), compute_uv=False))[:4]
     assert st["converged"] and st["stage_exit"] == 2
     _compare(A=W, sig=sig, U=U, V=V, rn=rn, st=st, ref_sig=s, tol=1e-10, normA=nW)
+
+
+@pytest.mark.parametrize("target", ["largest", "smallest"])
+def test_repeated_singular_values(P, target):
+    """Singular values of multiplicity 3 and 2 (a scrambled sparse diagonal
+    matrix): the projected matrices carry equal Ritz values, which the
+    extraction deflates as equal poles; the values match the prescribed
+    ones and the vectors stay orthonormal with eq. (res) residuals."""
+    rng = np.random.default_rng(41)
+    m, n = 900, 600
+    s = np.concatenate([[5.0, 5.0, 5.0, 4.0, 4.0], np.linspace(3.5, 0.5, n - 10), [0.2, 0.2, 0.2, 0.1, 0.1]])
+    rows = rng.permutation(m)[:n]
+    cols = rng.permutation(n)
+    A = sp.csr_matrix((s, (rows, cols)), shape=(m, n))
+    normA = 5.0
+    ref = np.sort(s)[::-1][:5] if target == "largest" else np.sort(s)[:5]
+    _say("repeated singular values 900x600", target)
+    sig, U, V, rn, st = P.svds(A, 5, target, 1e-10, block_size=4, max_basis_size=30,
+                               min_restart_size=12, norm_A=normA, seed=41)
+    assert st["converged"], st
+    _compare(A, sig, U, V, rn, st, ref, 1e-10, normA, rel=1e-9)
