@@ -197,10 +197,32 @@ __device__ int jacobi_eig_lds(int n, double* A, double* Z, double* d, double* cs
 constexpr int kBordMax = 16;
 constexpr int kRootLanes = 16;
 
+// a double moved between lanes of one 16-lane row with a DPP pattern
+template <int CTRL>
+__device__ __forceinline__ double dpp_row(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
+// sum over the 16 lanes of a row (a root's group): swaps within quads, then
+// the mirrors of the half row and of the row; every lane adds the same pairs
+// (in swapped order), so all lanes hold the same bits
 __device__ __forceinline__ double group16_sum(double v) {
-#pragma unroll
-  for (int off = kRootLanes / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return __shfl(v, (int)(threadIdx.x % kWave) & ~(kRootLanes - 1), kWave);  // lane 0 of the group
+  v += dpp_row<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_row<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_row<0x141>(v);  // row_half_mirror
+  v += dpp_row<0x140>(v);  // row_mirror
+  return v;
+}
+
+__device__ __forceinline__ double group16_prod(double v) {
+  v *= dpp_row<0xB1>(v);
+  v *= dpp_row<0x4E>(v);
+  v *= dpp_row<0x141>(v);
+  v *= dpp_row<0x140>(v);
+  return v;
 }
 
 template <int NT>
@@ -427,8 +449,7 @@ __device__ void bordered_eig_lds(int g, int g0, double* A, double* Z, double* d,
         const double num = (dk[Kk[k]] - dj) + tau[k];
         p *= (k == j) ? num : num / (dk[k] - dj);
       }
-#pragma unroll
-      for (int off = kRootLanes / 2; off > 0; off >>= 1) p *= __shfl_xor(p, off, kWave);
+      p = group16_prod(p);
       if (l == 0) zh[j] = copysign(sqrt(fabs(p)), zk[j]);
     }
     // the new eigenvalues in ascending order: roots first, then deflated poles
