@@ -100,10 +100,33 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <int L>
-__device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-  for (int off = L / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+// a value moved between the lanes of a 16-lane row by a DPP pattern
+template <int CTRL>
+__device__ __forceinline__ float dpp_row(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_row(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
+// sum over aligned groups of L lanes (L a power of two, at most 64); every
+// lane of a group ends with the same bits.  Inside a 16-lane row the levels
+// are DPP moves (the two quad swaps, then the half-row and row mirrors, which
+// pair the same partial sums as an exchange with lane i^4 and i^8); only the
+// levels across rows go through lane permutes.  A group never reads lanes
+// outside itself, so groups that have left a loop may sit beside it.
+template <typename TV, int L>
+__device__ __forceinline__ TV lane_sum(TV v) {
+  if constexpr (L >= 2) v += dpp_row<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  if constexpr (L >= 4) v += dpp_row<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  if constexpr (L >= 8) v += dpp_row<0x141>(v);  // row_half_mirror
+  if constexpr (L >= 16) v += dpp_row<0x140>(v);  // row_mirror
+  if constexpr (L >= 32) v += __shfl_xor(v, 16, kWave);
+  if constexpr (L >= 64) v += __shfl_xor(v, 32, kWave);
   return v;
 }
 

@@ -197,25 +197,8 @@ __device__ int jacobi_eig_lds(int n, double* A, double* Z, double* d, double* cs
 constexpr int kBordMax = 16;
 constexpr int kRootLanes = 16;
 
-// a double moved between lanes of one 16-lane row with a DPP pattern
-template <int CTRL>
-__device__ __forceinline__ double dpp_row(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
-}
-
-// sum over the 16 lanes of a row (a root's group): swaps within quads, then
-// the mirrors of the half row and of the row; every lane adds the same pairs
-// (in swapped order), so all lanes hold the same bits
-__device__ __forceinline__ double group16_sum(double v) {
-  v += dpp_row<0xB1>(v);   // quad_perm [1, 0, 3, 2]
-  v += dpp_row<0x4E>(v);   // quad_perm [2, 3, 0, 1]
-  v += dpp_row<0x141>(v);  // row_half_mirror
-  v += dpp_row<0x140>(v);  // row_mirror
-  return v;
-}
+// sum over the 16 lanes of a row (a root's group); all lanes hold the same bits
+__device__ __forceinline__ double group16_sum(double v) { return lane_sum<double, 16>(v); }
 
 __device__ __forceinline__ double group16_prod(double v) {
   v *= dpp_row<0xB1>(v);
