@@ -74,6 +74,11 @@ class Solver {
     if (std::min<int64_t>(g_, n_) < k + b_)
       throw Error(SVDS_ERR_ARG, "k + block size exceeds the smaller dimension or the basis");
   }
+  ~Solver() {
+    for (hipEvent_t e : evpool_) (void)hipEventDestroy(e);
+  }
+  Solver(const Solver&) = delete;
+  Solver& operator=(const Solver&) = delete;
 
   int run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, double* rnorm,
           svds_stats* st);
@@ -210,9 +215,37 @@ class Solver {
   const Csr32& A() const { return M_->A; }
   const Csr32& At() const { return M_->At; }
 
-  // sparse product with optional event timing
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_;
+  // sparse product with optional event timing.  The events only time the
+  // products: they are created without the system-scope fence (a default
+  // record writes back and invalidates the caches, which both costs time and
+  // hands the next kernel a cold L2), kept in a pool, and read back at the
+  // solver's synchronisation points, after which they are reused.
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_;  // recorded since the last harvest
+  std::vector<hipEvent_t> evpool_;                     // every event created by this solve
+  size_t evnext_ = 0;                                  // first unused event of the pool
+  double spmm_seconds_ = 0.0;
+  int64_t spmm_calls_ = 0;
   double spmm_bytes_ = 0.0;
+  hipEvent_t pool_event() {
+    if (evnext_ == evpool_.size()) {
+      hipEvent_t e;
+      SVDS_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+      evpool_.push_back(e);
+    }
+    return evpool_[evnext_++];
+  }
+  // after a stream synchronisation: every recorded pair has completed
+  void harvest_events() {
+    for (auto& e : ev_) {
+      float ms = 0.f;
+      SVDS_HIP(hipEventSynchronize(e.second));
+      SVDS_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+      spmm_seconds_ += ms * 1e-3;
+    }
+    spmm_calls_ += (int64_t)ev_.size();
+    ev_.clear();
+    evnext_ = 0;
+  }
   template <typename TV>
   void timed_spmm(const Csr32& Mx, int nb, const TV* X, TV* Y) {
     auto run = [&] {
@@ -223,9 +256,7 @@ class Solver {
       run();
       return;
     }
-    hipEvent_t a, b;
-    SVDS_HIP(hipEventCreate(&a));
-    SVDS_HIP(hipEventCreate(&b));
+    hipEvent_t a = pool_event(), b = pool_event();
     SVDS_HIP(hipEventRecord(a, s_));
     run();
     SVDS_HIP(hipEventRecord(b, s_));
@@ -235,19 +266,10 @@ class Solver {
                    sv * nb * (double)(Mx.rows + Mx.cols);
   }
   void collect_profile(svds_stats* st) {
-    double total = 0.0;
-    for (auto& e : ev_) {
-      float ms = 0.f;
-      SVDS_HIP(hipEventSynchronize(e.second));
-      SVDS_HIP(hipEventElapsedTime(&ms, e.first, e.second));
-      total += ms * 1e-3;
-      (void)hipEventDestroy(e.first);
-      (void)hipEventDestroy(e.second);
-    }
-    st->spmm_calls = (int64_t)ev_.size();
-    st->spmm_seconds = total;
+    harvest_events();
+    st->spmm_calls = spmm_calls_;
+    st->spmm_seconds = spmm_seconds_;
     st->spmm_bytes = spmm_bytes_;
-    ev_.clear();
   }
 
   // W block (compact, N x nb) = Op T block (compact)
@@ -443,6 +465,7 @@ class Solver {
     small_control(d_, p, s_);
     SVDS_HIP(hipMemcpyAsync(hctl_, &d_->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s_));
     SVDS_HIP(hipStreamSynchronize(s_));
+    if (!ev_.empty()) harvest_events();
     return *hctl_;
   }
 
