@@ -202,7 +202,8 @@ class Solver {
   double* partial_ = nullptr;
   double* dinv_ = nullptr;  // 1 / diag(A^T A) (ones where zero)
   Small* d_ = nullptr;
-  Ctl* hctl_ = nullptr;     // pinned
+  Ctl* hctl_ = nullptr;     // pinned, coherent
+  Ctl* dctl_ = nullptr;     // its device address
   int* hbad_ = nullptr;     // pinned
   double* vec_ = nullptr;   // small device vectors (k-sized)
   // mixed-precision stage 1: FP32 basis, FP64 work block, FP32 compact blocks
@@ -462,8 +463,7 @@ class Solver {
   }
 
   Ctl control(const CtlParams& p) {
-    small_control(d_, p, s_);
-    SVDS_HIP(hipMemcpyAsync(hctl_, &d_->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s_));
+    small_control(d_, p, s_, dctl_);  // the kernel writes the record to hctl_ itself
     SVDS_HIP(hipStreamSynchronize(s_));
     if (!ev_.empty()) harvest_events();
     return *hctl_;
@@ -1190,7 +1190,8 @@ int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, d
     Wc32_ = buf_.get<float>((size_t)ld_ * kMaxBlock);
     Tb_ = buf_.get<double>((size_t)ld_ * kMaxBlock);
   }
-  SVDS_HIP(hipHostMalloc((void**)&hctl_, sizeof(Ctl), hipHostMallocDefault));
+  SVDS_HIP(hipHostMalloc((void**)&hctl_, sizeof(Ctl), hipHostMallocMapped | hipHostMallocCoherent));
+  SVDS_HIP(hipHostGetDevicePointer((void**)&dctl_, hctl_, 0));
   SVDS_HIP(hipHostMalloc((void**)&hbad_, sizeof(int), hipHostMallocDefault));
   SVDS_HIP(hipHostMalloc((void**)&hjd_, sizeof(JdCol) * kMaxBlock, hipHostMallocDefault));
   struct PinnedFree {

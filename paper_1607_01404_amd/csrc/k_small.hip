@@ -958,7 +958,7 @@ __device__ __forceinline__ double halves_res(const double* sums, int nc, int c, 
   return sqrt(fmax(t1, 0.0) + fmax(t2, 0.0));
 }
 
-__global__ __launch_bounds__(kT) void k_control(Small* d, CtlParams P) {
+__device__ void control_body(Small* d, const CtlParams& P) {
   __shared__ int s_action, s_nblock, s_restart, s_reff, s_off, s_peff, s_nr, s_lock;
   __shared__ int s_blk[kMaxBlock];
   __shared__ double Yr[kLd * kLs];
@@ -1299,9 +1299,24 @@ __global__ __launch_bounds__(kT) void k_control(Small* d, CtlParams P) {
   if (t < kMaxBlock) d->blk[t] = (t < nblock) ? s_blk[t] : 0;
 }
 
-void small_control(Small* d, const CtlParams& p, hipStream_t s) {
+// the control step; with a non-null host record (pinned, coherent host memory
+// mapped for the device) the decision record is also written there with
+// ordinary vector stores, so the host reads it after the stream
+// synchronisation without a separate copy
+__global__ __launch_bounds__(kT) void k_control(Small* d, CtlParams P, Ctl* host) {
+  control_body(d, P);
+  if (host) {
+    __syncthreads();
+    const unsigned int* src = reinterpret_cast<const unsigned int*>(&d->ctl);
+    unsigned int* dst = reinterpret_cast<unsigned int*>(host);
+    for (int a = threadIdx.x; a < (int)(sizeof(Ctl) / sizeof(unsigned int)); a += kT)
+      dst[a] = src[a];
+  }
+}
+
+void small_control(Small* d, const CtlParams& p, hipStream_t s, Ctl* host) {
   if (p.nc > kKmax + 8 || p.gc > kGmax) throw Error(SVDS_ERR_ARG, "control: sizes");
-  k_control<<<1, kT, 0, s>>>(d, p);
+  k_control<<<1, kT, 0, s>>>(d, p, host);
   SVDS_LAUNCH_CHECK();
 }
 

@@ -100,7 +100,9 @@ void small_extract(Small* d, int gc, int descending, int refined, hipStream_t s)
 // pre-projection Gram diagonal G0[j*ldg0 + j]
 void small_chol(Small* d, int nb, int which, const double* G0, int ldg0, hipStream_t s);
 void small_rr_append(Small* d, int gc, int nb, int total, hipStream_t s);
-void small_control(Small* d, const CtlParams& p, hipStream_t s);
+// the control step; host (may be null) is the device address of a pinned,
+// coherent host copy of d->ctl that the kernel fills at its end
+void small_control(Small* d, const CtlParams& p, hipStream_t s, Ctl* host = nullptr);
 void small_rtr_accumulate(const double* C0, int ldc0, const double* C1, int total, int nb,
                           double* Cout, hipStream_t s);
 void small_final_rr(int k, double* G, int ldg, int descending, double* lam, double* Z, int ldz,
