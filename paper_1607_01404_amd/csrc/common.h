@@ -48,12 +48,17 @@ int guarded(F&& f) {
   }
 }
 
+// the library's stream-ordered memory pool on the current device: created on
+// first use with no release threshold, so memory freed at the end of a call
+// stays in the pool for the next call instead of going back to the driver
+hipMemPool_t device_pool();
+
 // stream-ordered device allocations released together at the end of a call
 template <typename T>
 T* dalloc(size_t n, hipStream_t s) {
   T* p = nullptr;
   if (n == 0) n = 1;
-  SVDS_HIP(hipMallocAsync((void**)&p, sizeof(T) * n, s));
+  SVDS_HIP(hipMallocFromPoolAsync((void**)&p, sizeof(T) * n, device_pool(), s));
   return p;
 }
 
@@ -234,6 +239,10 @@ void reduce_partials(const double* P, int nblk, int nout, double* out, hipStream
 template <typename TB>
 void tsgemm_tn(const SegT<TB>* segs, int nseg, int64_t N, const double* T, int64_t ldt, int b,
                double* partial, double* C, hipStream_t s, const int* skip = nullptr);
+// the same product left as per-workgroup partial sums, partial[o * nblk + block]
+// with o = c * total + col; returns nblk (the consumer reduces them)
+int tsgemm_tn_partial(const Seg* segs, int nseg, int64_t N, const double* T, int64_t ldt, int b,
+                      double* partial, hipStream_t s);
 // T -= [segs] C   (C: total x b, column-major with leading dimension ldc);
 // nothing when the device flag *skip is set
 template <typename TB>
@@ -267,6 +276,8 @@ void unpack_rows(const double* compact, int64_t N, int b, double* A, int64_t lda
 // T[:, j] = R[:, blk[j]] * dinv  (dinv may be null); blk on device
 void gather_precond(const double* R, int64_t ldr, const int* d_blk, int nb, const double* dinv,
                     int64_t N, double* T, int64_t ldt, hipStream_t s);
+// out = 1 / d elementwise (1 where d <= 0)
+void invert_diag(const double* d, int64_t n, double* out, hipStream_t s);
 void scale_rows(double* T, int64_t ldt, int64_t N, int b, const double* dinv, hipStream_t s);
 void copy_cols(const double* A, int64_t lda, int64_t N, int b, double* B, int64_t ldb,
                hipStream_t s);

@@ -5,7 +5,9 @@
 // record per iteration (the Ctl struct written by the control kernel), plus a
 // breakdown flag after each block orthogonalisation.
 #include <atomic>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <chrono>
 #include <thread>
 #include <cmath>
@@ -46,6 +48,27 @@ double now() {
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 }  // namespace
+
+hipMemPool_t device_pool() {
+  static std::mutex mu;
+  static std::map<int, hipMemPool_t> pools;
+  int dev = 0;
+  SVDS_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = pools.find(dev);
+  if (it != pools.end()) return it->second;
+  hipMemPoolProps props{};
+  props.allocType = hipMemAllocationTypePinned;
+  props.handleTypes = hipMemHandleTypeNone;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = dev;
+  hipMemPool_t pool = nullptr;
+  SVDS_HIP(hipMemPoolCreate(&pool, &props));
+  uint64_t keep = UINT64_MAX;
+  SVDS_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+  pools[dev] = pool;
+  return pool;
+}
 
 // ---------------------------------------------------------------------------
 // The solver state of one svds call
@@ -333,11 +356,12 @@ class Solver {
       tsgemm_tn(sb, n1, N_, T, ldt, nb, partial_, d_->C1, s_, sk);
       ts_update(sb, n1, N_, d_->C1, total, T, ldt, nb, s_, sk);
     }
-    tsgemm_tn(&st, 1, N_, T, ldt, nb, partial_, d_->G, s_);
-    small_chol(d_, nb, 1, G0, ldg0, s_);
+    // Cholesky QR twice; the Cholesky kernels sum the Gram partial sums themselves
+    int nbk = tsgemm_tn_partial(&st, 1, N_, T, ldt, nb, partial_, s_);
+    small_chol(d_, nb, 1, G0, ldg0, s_, partial_, nbk);
     ts_scale(T, ldt, N_, nb, d_->R1inv, nullptr, s_);
-    tsgemm_tn(&st, 1, N_, T, ldt, nb, partial_, d_->G, s_);
-    small_chol(d_, nb, 2, nullptr, 0, s_);
+    nbk = tsgemm_tn_partial(&st, 1, N_, T, ldt, nb, partial_, s_);
+    small_chol(d_, nb, 2, nullptr, 0, s_, partial_, nbk);
     ts_scale(T, ldt, N_, nb, d_->R2inv, compact, s_);
   }
 
@@ -1206,12 +1230,7 @@ int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, d
   } pf{hctl_, hbad_, hjd_};
   if (o_.precond == SVDS_PC_JACOBI) {
     dinv_ = buf_.get<double>(n_);
-    // 1/diag(C), with 1 where the column is empty
-    std::vector<double> hd(n_);
-    SVDS_HIP(hipMemcpyAsync(hd.data(), M_->diagC, sizeof(double) * n_, hipMemcpyDeviceToHost, s_));
-    SVDS_HIP(hipStreamSynchronize(s_));
-    for (auto& x : hd) x = x > 0 ? 1.0 / x : 1.0;
-    SVDS_HIP(hipMemcpyAsync(dinv_, hd.data(), sizeof(double) * n_, hipMemcpyHostToDevice, s_));
+    invert_diag(M_->diagC, n_, dinv_, s_);  // 1/diag(C), with 1 where the column is empty
   }
   if (o_.precond == SVDS_PC_LEARNED) setup_learned();
   if (o_.precond == SVDS_PC_BLOCKJACOBI) {
@@ -1301,7 +1320,7 @@ struct MemMode {
   template <class T>
   void alloc(T** p, size_t count) const {
     const size_t bytes = sizeof(T) * std::max<size_t>(count, 1);
-    if (async) SVDS_HIP(hipMallocAsync((void**)p, bytes, s));
+    if (async) SVDS_HIP(hipMallocFromPoolAsync((void**)p, bytes, svds::device_pool(), s));
     else SVDS_HIP(hipMalloc((void**)p, bytes));
   }
   void release(void* p) const {
@@ -1351,7 +1370,7 @@ int create_matrix(const svds_csr* A, svds_matrix** out, hipStream_t s, bool stre
   SVDS_HIP(hipMemcpyAsync(&ends[0], A->rowptr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   SVDS_HIP(hipMemcpyAsync(&ends[1], A->rowptr + A->m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   int* dflag = nullptr;
-  SVDS_HIP(hipMallocAsync((void**)&dflag, sizeof(int), s));
+  SVDS_HIP(hipMallocFromPoolAsync((void**)&dflag, sizeof(int), svds::device_pool(), s));
   SVDS_HIP(hipMemsetAsync(dflag, 0, sizeof(int), s));
   svds::check_csr(*A, dflag, s);
   int flag = 0;
@@ -1375,7 +1394,8 @@ int create_matrix(const svds_csr* A, svds_matrix** out, hipStream_t s, bool stre
     alloc_csr(at, A->n, A->m, A->nnz, mm);
     svds::copy_csr_arrays(*A, a, s);
     int32_t* cursor = nullptr;
-    SVDS_HIP(hipMallocAsync((void**)&cursor, sizeof(int32_t) * (A->n + 1), s));
+    SVDS_HIP(hipMallocFromPoolAsync((void**)&cursor, sizeof(int32_t) * (A->n + 1),
+                                    svds::device_pool(), s));
     svds::transpose_csr(a, at, cursor, s);
     SVDS_HIP(hipFreeAsync(cursor, s));
     svds::build_bins(a, s);

@@ -163,8 +163,8 @@ static Segs3T<TB> make_segs(const SegT<TB>* segs, int nseg, int& total) {
 }
 
 template <int B, typename TB>
-static void tsgemm_b(const Segs3T<TB>& sg, int total, int64_t N, const double* T, int64_t ldt,
-                     double* partial, double* C, hipStream_t s, const int* skip) {
+static int tsgemm_b(const Segs3T<TB>& sg, int total, int64_t N, const double* T, int64_t ldt,
+                    double* partial, double* C, hipStream_t s, const int* skip) {
   // one contiguous row range per workgroup column (several 256-row steps
   // amortise the final wave reductions)
   int nb = std::min(reduce_blocks(N), 256);
@@ -177,28 +177,41 @@ static void tsgemm_b(const Segs3T<TB>& sg, int total, int64_t N, const double* T
   dim3 grid(nb, (total + 4 * kCPW - 1) / (4 * kCPW));
   k_tsgemm_tn<B, TB><<<grid, kThreads, 0, s>>>(sg, total, N, T, ldt, chunk, partial, skip);
   SVDS_LAUNCH_CHECK();
-  reduce_partials(partial, nb, total * B, C, s, skip);
+  if (C) reduce_partials(partial, nb, total * B, C, s, skip);
+  return nb;
+}
+
+template <typename TB>
+static int tsgemm_any(const SegT<TB>* segs, int nseg, int64_t N, const double* T, int64_t ldt,
+                      int b, double* partial, double* C, hipStream_t s, const int* skip) {
+  int total = 0;
+  Segs3T<TB> sg = make_segs(segs, nseg, total);
+  if (total == 0) return 0;
+  if (total > kMaxSegCols) throw Error(SVDS_ERR_ARG, "projection too wide");
+  switch (b) {
+    case 1: return tsgemm_b<1>(sg, total, N, T, ldt, partial, C, s, skip);
+    case 2: return tsgemm_b<2>(sg, total, N, T, ldt, partial, C, s, skip);
+    case 3: return tsgemm_b<3>(sg, total, N, T, ldt, partial, C, s, skip);
+    case 4: return tsgemm_b<4>(sg, total, N, T, ldt, partial, C, s, skip);
+    case 5: return tsgemm_b<5>(sg, total, N, T, ldt, partial, C, s, skip);
+    case 6: return tsgemm_b<6>(sg, total, N, T, ldt, partial, C, s, skip);
+    case 7: return tsgemm_b<7>(sg, total, N, T, ldt, partial, C, s, skip);
+    case 8: return tsgemm_b<8>(sg, total, N, T, ldt, partial, C, s, skip);
+    default: throw Error(SVDS_ERR_ARG, "tsgemm: b must be 1..8");
+  }
 }
 
 template <typename TB>
 void tsgemm_tn(const SegT<TB>* segs, int nseg, int64_t N, const double* T, int64_t ldt, int b,
                double* partial, double* C, hipStream_t s, const int* skip) {
-  int total = 0;
-  Segs3T<TB> sg = make_segs(segs, nseg, total);
-  if (total == 0) return;
-  if (total > kMaxSegCols) throw Error(SVDS_ERR_ARG, "projection too wide");
-  switch (b) {
-    case 1: tsgemm_b<1>(sg, total, N, T, ldt, partial, C, s, skip); break;
-    case 2: tsgemm_b<2>(sg, total, N, T, ldt, partial, C, s, skip); break;
-    case 3: tsgemm_b<3>(sg, total, N, T, ldt, partial, C, s, skip); break;
-    case 4: tsgemm_b<4>(sg, total, N, T, ldt, partial, C, s, skip); break;
-    case 5: tsgemm_b<5>(sg, total, N, T, ldt, partial, C, s, skip); break;
-    case 6: tsgemm_b<6>(sg, total, N, T, ldt, partial, C, s, skip); break;
-    case 7: tsgemm_b<7>(sg, total, N, T, ldt, partial, C, s, skip); break;
-    case 8: tsgemm_b<8>(sg, total, N, T, ldt, partial, C, s, skip); break;
-    default: throw Error(SVDS_ERR_ARG, "tsgemm: b must be 1..8");
-  }
+  tsgemm_any(segs, nseg, N, T, ldt, b, partial, C, s, skip);
 }
+
+int tsgemm_tn_partial(const Seg* segs, int nseg, int64_t N, const double* T, int64_t ldt, int b,
+                      double* partial, hipStream_t s) {
+  return tsgemm_any(segs, nseg, N, T, ldt, b, partial, nullptr, s, nullptr);
+}
+
 template void tsgemm_tn<double>(const SegT<double>*, int, int64_t, const double*, int64_t, int,
                                 double*, double*, hipStream_t, const int*);
 template void tsgemm_tn<float>(const SegT<float>*, int, int64_t, const double*, int64_t, int,
@@ -558,6 +571,22 @@ __global__ void k_scale_rows(double* __restrict__ T, int64_t ldt, int64_t N, int
   }
 }
 
+// out[i] = 1 / d[i], or 1 where d[i] is not positive (an empty column)
+__global__ void k_invert_diag(const double* __restrict__ d, int64_t n, double* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double x = d[i];
+    out[i] = x > 0.0 ? 1.0 / x : 1.0;
+  }
+}
+
+void invert_diag(const double* d, int64_t n, double* out, hipStream_t s) {
+  const int blocks = (int)std::min<int64_t>(8192, (n + 255) / 256);
+  if (blocks < 1) return;
+  k_invert_diag<<<blocks, 256, 0, s>>>(d, n, out);
+  SVDS_LAUNCH_CHECK();
+}
+
 void scale_rows(double* T, int64_t ldt, int64_t N, int b, const double* dinv, hipStream_t s) {
   int blocks = (int)std::min<int64_t>(8192, (N + 255) / 256);
   if (blocks < 1) return;
@@ -715,15 +744,19 @@ __global__ __launch_bounds__(kThreads) void k_colargmax(const double* __restrict
   }
 }
 
-// flip (u_c, v_c) when the first largest-magnitude entry of v_c is negative
-__global__ void k_sign_flip(const double* __restrict__ pval, const int64_t* __restrict__ pidx,
-                            int nblk, int k, const double* __restrict__ Vv, int64_t ldv,
-                            double* __restrict__ f) {
-  const int c = threadIdx.x;
-  if (c >= k) return;
+// flip (u_c, v_c) when the first largest-magnitude entry of v_c is negative;
+// one wavefront per column c: lanes stride over the blocks' candidates, then
+// the (largest value, smallest index) candidate wins across the lanes (a
+// total order, so the winner does not depend on the reduction order)
+__global__ __launch_bounds__(kWave) void k_sign_flip(const double* __restrict__ pval,
+                                                     const int64_t* __restrict__ pidx, int nblk,
+                                                     int k, const double* __restrict__ Vv,
+                                                     int64_t ldv, double* __restrict__ f) {
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x;
   double best = -1.0;
   int64_t bi = INT64_MAX;
-  for (int b = 0; b < nblk; ++b) {
+  for (int b = lane; b < nblk; b += kWave) {
     const double v = pval[(int64_t)b * k + c];
     const int64_t i = pidx[(int64_t)b * k + c];
     if (v > best || (v == best && i < bi)) {
@@ -731,7 +764,16 @@ __global__ void k_sign_flip(const double* __restrict__ pval, const int64_t* __re
       bi = i;
     }
   }
-  f[c] = (bi != INT64_MAX && Vv[bi + c * ldv] < 0.0) ? -1.0 : 1.0;
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    const double v = __shfl_xor(best, off, kWave);
+    const int64_t i = __shfl_xor(bi, off, kWave);
+    if (v > best || (v == best && i < bi)) {
+      best = v;
+      bi = i;
+    }
+  }
+  if (lane == 0) f[c] = (bi != INT64_MAX && Vv[bi + c * ldv] < 0.0) ? -1.0 : 1.0;
 }
 
 void sign_factors(const double* V, int64_t ldv, int64_t N, int k, double* partial, double* f,
@@ -742,7 +784,7 @@ void sign_factors(const double* V, int64_t ldv, int64_t N, int k, double* partia
   dim3 grid(nb, k);
   k_colargmax<<<grid, kThreads, 0, s>>>(V, ldv, N, k, pval, pidx);
   SVDS_LAUNCH_CHECK();
-  k_sign_flip<<<1, 64, 0, s>>>(pval, pidx, nb, k, V, ldv, f);
+  k_sign_flip<<<k, kWave, 0, s>>>(pval, pidx, nb, k, V, ldv, f);
   SVDS_LAUNCH_CHECK();
 }
 

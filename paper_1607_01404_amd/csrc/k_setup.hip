@@ -97,8 +97,8 @@ void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t 
   int64_t nb = (n + kScanBlock - 1) / kScanBlock;
   int32_t* bs = nullptr;
   int32_t* bso = nullptr;
-  SVDS_HIP(hipMallocAsync((void**)&bs, sizeof(int32_t) * nb, s));
-  SVDS_HIP(hipMallocAsync((void**)&bso, sizeof(int32_t) * nb, s));
+  SVDS_HIP(hipMallocFromPoolAsync((void**)&bs, sizeof(int32_t) * nb, device_pool(), s));
+  SVDS_HIP(hipMallocFromPoolAsync((void**)&bso, sizeof(int32_t) * nb, device_pool(), s));
   k_scan_local<<<(unsigned)nb, kScanBlock, 0, s>>>(in, out, bs, n);
   SVDS_LAUNCH_CHECK();
   if (nb > 1) {
@@ -263,8 +263,10 @@ void build_bins(Csr32& A, hipStream_t s) {
   int64_t nblk = std::max<int64_t>(1, (rows + kBinBlock - 1) / kBinBlock);
   int32_t* counts = nullptr;
   int32_t* offs = nullptr;
-  SVDS_HIP(hipMallocAsync((void**)&counts, sizeof(int32_t) * (kNumBins * nblk + 1), s));
-  SVDS_HIP(hipMallocAsync((void**)&offs, sizeof(int32_t) * (kNumBins * nblk + 1), s));
+  SVDS_HIP(hipMallocFromPoolAsync((void**)&counts, sizeof(int32_t) * (kNumBins * nblk + 1),
+                                  device_pool(), s));
+  SVDS_HIP(hipMallocFromPoolAsync((void**)&offs, sizeof(int32_t) * (kNumBins * nblk + 1),
+                                  device_pool(), s));
   SVDS_HIP(hipMemsetAsync(counts, 0, sizeof(int32_t) * (kNumBins * nblk + 1), s));
   k_bin_hist<<<(unsigned)nblk, kBinBlock, 0, s>>>(A.rp, rows, counts, nblk);
   SVDS_LAUNCH_CHECK();

@@ -12,6 +12,7 @@ namespace svds {
 constexpr int kT = kSmallThreads;
 constexpr int kLs = kLd + 1;  // padded leading dimension in LDS
 constexpr int kEigT = 1024;   // threads of the eigensolver kernels
+constexpr int kCholT = 1024;  // threads of the block Cholesky (one wavefront per Gram entry)
 
 // round-robin pairing for np (even) indices, round r in [0, np-1)
 __device__ __forceinline__ void rr_pair(int np, int r, int k, int& p, int& q) {
@@ -850,13 +851,27 @@ void small_extract(Small* d, int gc, int descending, int refined, hipStream_t s)
 // collapsed during projection against the pre-projection norms stored as the
 // last nb rows of C0), which = 2 writes R2/R2inv.
 // ---------------------------------------------------------------------------
-__global__ void k_chol(Small* d, int nb, int which, const double* G0, int ldg0) {
+__global__ __launch_bounds__(kCholT) void k_chol(Small* d, int nb, int which, const double* G0,
+                                                int ldg0, const double* __restrict__ P,
+                                                int nblk) {
   __shared__ double G[kMaxBlock * kMaxBlock], g0[kMaxBlock];
   __shared__ double R[kMaxBlock * kMaxBlock], Ri[kMaxBlock * kMaxBlock];
   __shared__ int sbad;
   const int t = threadIdx.x;
-  if (t < nb * nb) {
+  if (P) {
+    // the Gram matrix from the projection's partial sums: one wavefront per
+    // entry, the summation of the separate reduction kernel
+    const int lane = t % kWave, w = t / kWave;
+    for (int o = w; o < nb * nb; o += kCholT / kWave) {
+      double s = 0.0;
+      for (int b = lane; b < nblk; b += kWave) s += P[(int64_t)o * nblk + b];
+      s = wave_sum(s);
+      if (lane == 0) G[o] = s;
+    }
+  } else if (t < nb * nb) {
     G[t] = d->G[t];
+  }
+  if (t < nb * nb) {
     R[t] = 0.0;
     Ri[t] = 0.0;
   }
@@ -908,8 +923,9 @@ __global__ void k_chol(Small* d, int nb, int which, const double* G0, int ldg0) 
   }
 }
 
-void small_chol(Small* d, int nb, int which, const double* G0, int ldg0, hipStream_t s) {
-  k_chol<<<1, 64, 0, s>>>(d, nb, which, G0, ldg0);
+void small_chol(Small* d, int nb, int which, const double* G0, int ldg0, hipStream_t s,
+                const double* partial, int nblk) {
+  k_chol<<<1, kCholT, 0, s>>>(d, nb, which, G0, ldg0, partial, nblk);
   SVDS_LAUNCH_CHECK();
 }
 

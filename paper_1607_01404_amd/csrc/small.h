@@ -97,8 +97,11 @@ void small_h_append(Small* d, int gc, int nb, hipStream_t s);
 void small_dgks(Small* d, int total, int nb, const double* C0, int ldc0, hipStream_t s);
 void small_extract(Small* d, int gc, int descending, int refined, hipStream_t s);
 // which = 1: also test columns that collapsed during projection against the
-// pre-projection Gram diagonal G0[j*ldg0 + j]
-void small_chol(Small* d, int nb, int which, const double* G0, int ldg0, hipStream_t s);
+// pre-projection Gram diagonal G0[j*ldg0 + j].  The Gram matrix is d->G, or,
+// with partial non-null, the sums of the projection's nblk per-workgroup
+// partial sums (partial[o * nblk + block], o = c * nb + j)
+void small_chol(Small* d, int nb, int which, const double* G0, int ldg0, hipStream_t s,
+                const double* partial = nullptr, int nblk = 0);
 void small_rr_append(Small* d, int gc, int nb, int total, hipStream_t s);
 // the control step; host (may be null) is the device address of a pinned,
 // coherent host copy of d->ctl that the kernel fills at its end
