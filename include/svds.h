@@ -205,8 +205,10 @@ int svds_matrix_spmm(const svds_matrix* h, int trans, int b, const double* X, do
  * signed so that the largest-magnitude entry of v is positive.
  * opts may be NULL (defaults); stats may be NULL.  Returns SVDS_OK,
  * SVDS_NOT_CONVERGED (partial results as described above) or an error;
- * on error the outputs are unspecified.  Device workspace is allocated and
- * freed inside the call. */
+ * on error the outputs are unspecified.  Device workspace is stream-ordered
+ * on `stream`; blocks released at the end of a call are kept by the library
+ * (at most 16 GiB per process, never returned) and reused by later calls on
+ * the same stream that ask for the same sizes. */
 int svds_solve(const svds_csr* A, int k, int target, double tol, const svds_opts* opts,
                double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, double* rnorm,
                svds_stats* stats, void* stream);

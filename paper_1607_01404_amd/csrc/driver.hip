@@ -70,6 +70,56 @@ hipMemPool_t device_pool() {
   return pool;
 }
 
+namespace {
+constexpr size_t kCacheCap = (size_t)16 << 30;  // bytes kept for reuse, all streams together
+struct BlockCache {
+  std::mutex mu;
+  std::map<std::pair<hipStream_t, size_t>, std::vector<void*>> free;  // (stream, bytes) -> blocks
+  std::map<void*, size_t> size;                                        // every live block
+  size_t cached = 0;
+};
+BlockCache& block_cache() {
+  static BlockCache* c = new BlockCache();  // kept to the end of the process
+  return *c;
+}
+}  // namespace
+
+void* stream_alloc(size_t bytes, hipStream_t s) {
+  BlockCache& c = block_cache();
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.free.find({s, bytes});
+    if (it != c.free.end() && !it->second.empty()) {
+      void* p = it->second.back();
+      it->second.pop_back();
+      c.cached -= bytes;
+      return p;
+    }
+  }
+  void* p = nullptr;
+  SVDS_HIP(hipMallocFromPoolAsync(&p, bytes, device_pool(), s));
+  std::lock_guard<std::mutex> lk(c.mu);
+  c.size[p] = bytes;
+  return p;
+}
+
+void stream_free(void* p, hipStream_t s) {
+  if (!p) return;
+  BlockCache& c = block_cache();
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.size.find(p);
+    const size_t bytes = it != c.size.end() ? it->second : 0;
+    if (bytes && c.cached + bytes <= kCacheCap) {
+      c.free[{s, bytes}].push_back(p);
+      c.cached += bytes;
+      return;
+    }
+    if (it != c.size.end()) c.size.erase(it);
+  }
+  (void)hipFreeAsync(p, s);
+}
+
 // ---------------------------------------------------------------------------
 // The solver state of one svds call
 // ---------------------------------------------------------------------------
@@ -1320,12 +1370,12 @@ struct MemMode {
   template <class T>
   void alloc(T** p, size_t count) const {
     const size_t bytes = sizeof(T) * std::max<size_t>(count, 1);
-    if (async) SVDS_HIP(hipMallocFromPoolAsync((void**)p, bytes, svds::device_pool(), s));
+    if (async) *p = static_cast<T*>(svds::stream_alloc(bytes, s));
     else SVDS_HIP(hipMalloc((void**)p, bytes));
   }
   void release(void* p) const {
     if (!p) return;
-    if (async) (void)hipFreeAsync(p, s);
+    if (async) svds::stream_free(p, s);
     else (void)hipFree(p);
   }
 };
@@ -1370,12 +1420,12 @@ int create_matrix(const svds_csr* A, svds_matrix** out, hipStream_t s, bool stre
   SVDS_HIP(hipMemcpyAsync(&ends[0], A->rowptr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   SVDS_HIP(hipMemcpyAsync(&ends[1], A->rowptr + A->m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   int* dflag = nullptr;
-  SVDS_HIP(hipMallocFromPoolAsync((void**)&dflag, sizeof(int), svds::device_pool(), s));
+  dflag = static_cast<int*>(svds::stream_alloc(sizeof(int), s));
   SVDS_HIP(hipMemsetAsync(dflag, 0, sizeof(int), s));
   svds::check_csr(*A, dflag, s);
   int flag = 0;
   SVDS_HIP(hipMemcpyAsync(&flag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
-  SVDS_HIP(hipFreeAsync(dflag, s));
+  svds::stream_free(dflag, s);
   SVDS_HIP(hipStreamSynchronize(s));
   if (ends[0] != 0 || ends[1] != A->nnz || flag) throw Error(SVDS_ERR_CSR, "malformed CSR");
 
@@ -1394,10 +1444,9 @@ int create_matrix(const svds_csr* A, svds_matrix** out, hipStream_t s, bool stre
     alloc_csr(at, A->n, A->m, A->nnz, mm);
     svds::copy_csr_arrays(*A, a, s);
     int32_t* cursor = nullptr;
-    SVDS_HIP(hipMallocFromPoolAsync((void**)&cursor, sizeof(int32_t) * (A->n + 1),
-                                    svds::device_pool(), s));
+    cursor = static_cast<int32_t*>(svds::stream_alloc(sizeof(int32_t) * (A->n + 1), s));
     svds::transpose_csr(a, at, cursor, s);
-    SVDS_HIP(hipFreeAsync(cursor, s));
+    svds::stream_free(cursor, s);
     svds::build_bins(a, s);
     svds::build_bins(at, s);
     // FP32 copies of the values for the mixed-precision stage 1

@@ -97,8 +97,8 @@ void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t 
   int64_t nb = (n + kScanBlock - 1) / kScanBlock;
   int32_t* bs = nullptr;
   int32_t* bso = nullptr;
-  SVDS_HIP(hipMallocFromPoolAsync((void**)&bs, sizeof(int32_t) * nb, device_pool(), s));
-  SVDS_HIP(hipMallocFromPoolAsync((void**)&bso, sizeof(int32_t) * nb, device_pool(), s));
+  bs = static_cast<int32_t*>(stream_alloc(sizeof(int32_t) * nb, s));
+  bso = static_cast<int32_t*>(stream_alloc(sizeof(int32_t) * nb, s));
   k_scan_local<<<(unsigned)nb, kScanBlock, 0, s>>>(in, out, bs, n);
   SVDS_LAUNCH_CHECK();
   if (nb > 1) {
@@ -106,8 +106,8 @@ void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t 
     k_scan_add<<<(unsigned)nb, kScanBlock, 0, s>>>(out, bso, n);
     SVDS_LAUNCH_CHECK();
   }
-  SVDS_HIP(hipFreeAsync(bs, s));
-  SVDS_HIP(hipFreeAsync(bso, s));
+  stream_free(bs, s);
+  stream_free(bso, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -263,10 +263,8 @@ void build_bins(Csr32& A, hipStream_t s) {
   int64_t nblk = std::max<int64_t>(1, (rows + kBinBlock - 1) / kBinBlock);
   int32_t* counts = nullptr;
   int32_t* offs = nullptr;
-  SVDS_HIP(hipMallocFromPoolAsync((void**)&counts, sizeof(int32_t) * (kNumBins * nblk + 1),
-                                  device_pool(), s));
-  SVDS_HIP(hipMallocFromPoolAsync((void**)&offs, sizeof(int32_t) * (kNumBins * nblk + 1),
-                                  device_pool(), s));
+  counts = static_cast<int32_t*>(stream_alloc(sizeof(int32_t) * (kNumBins * nblk + 1), s));
+  offs = static_cast<int32_t*>(stream_alloc(sizeof(int32_t) * (kNumBins * nblk + 1), s));
   SVDS_HIP(hipMemsetAsync(counts, 0, sizeof(int32_t) * (kNumBins * nblk + 1), s));
   k_bin_hist<<<(unsigned)nblk, kBinBlock, 0, s>>>(A.rp, rows, counts, nblk);
   SVDS_LAUNCH_CHECK();
@@ -297,8 +295,8 @@ void build_bins(Csr32& A, hipStream_t s) {
     A.merged_bin = std::max(lo, std::min(mb, hi));
   }
   A.heuristic_bin = A.merged_bin;
-  SVDS_HIP(hipFreeAsync(counts, s));
-  SVDS_HIP(hipFreeAsync(offs, s));
+  stream_free(counts, s);
+  stream_free(offs, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -63,8 +63,8 @@ void autotune_spmm(Csr32& A, int b, bool fp32, hipStream_t s) {
   }
   const size_t es = fp32 ? sizeof(float) : sizeof(double);
   void *X = nullptr, *Y = nullptr;
-  SVDS_HIP(hipMallocFromPoolAsync(&X, es * (size_t)A.cols * b, device_pool(), s));
-  SVDS_HIP(hipMallocFromPoolAsync(&Y, es * (size_t)A.rows * b, device_pool(), s));
+  X = stream_alloc(es * (size_t)A.cols * b, s);
+  Y = stream_alloc(es * (size_t)A.rows * b, s);
   SVDS_HIP(hipMemsetAsync(X, 0, es * (size_t)A.cols * b, s));
   hipEvent_t e0, e1;
   SVDS_HIP(hipEventCreate(&e0));
@@ -100,8 +100,8 @@ void autotune_spmm(Csr32& A, int b, bool fp32, hipStream_t s) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  SVDS_HIP(hipFreeAsync(X, s));
-  SVDS_HIP(hipFreeAsync(Y, s));
+  stream_free(X, s);
+  stream_free(Y, s);
   A.merged_bin = best.first;
   A.unroll = best.second;
   A.tuned_b = b;
