@@ -688,13 +688,28 @@ void Solver::estimate_norm() {
   fill_random(V_, ld_, N_, 1, o_.seed, kStreamNorm, 0, s_);
   ortho<double>(V_, ld_, 1, nullptr, 0, Tc_);
   append(1);
+  // all steps are enqueued without host synchronisation; each records its
+  // breakdown flag, and the space ends before the first step that broke down
+  // (an invariant subspace).  Later steps only add rows and columns to H
+  // beyond the valid leading block.
+  const int first = gc_;
   while (gc_ < steps) {
     double* T = V_ + gc_ * ld_;
     copy_cols(W_ + (gc_ - 1) * ld_, ld_, N_, 1, T, ld_, s_);
     Seg sv{V_, gc_, ld_};
-    int bad = ortho_once(T, ld_, 1, &sv, 1, Tc_);
-    if (bad) break;  // invariant subspace
+    ortho_enqueue(T, ld_, 1, &sv, 1, Tc_);
+    small_record_bad(d_, gc_, s_);
     append(1);
+  }
+  if (gc_ > first) {
+    int hb[kGmax];
+    SVDS_HIP(hipMemcpyAsync(hb, d_->stepbad, sizeof(int) * gc_, hipMemcpyDeviceToHost, s_));
+    SVDS_HIP(hipStreamSynchronize(s_));
+    for (int st = first; st < gc_; ++st)
+      if (hb[st]) {
+        gc_ = st;
+        break;
+      }
   }
   small_extract(d_, gc_, 1, 0, s_);
   double lam = 0.0;

@@ -708,6 +708,16 @@ __global__ void k_dgks(Small* d, int total, int nb, const double* __restrict__ C
   if (lane == 0) d->skip2 = need ? 0 : 1;
 }
 
+__global__ void k_record_bad(Small* d, int step) {
+  if (threadIdx.x == 0) d->stepbad[step] = d->bad;
+}
+
+void small_record_bad(Small* d, int step, hipStream_t s) {
+  if (step < 0 || step >= kGmax) throw Error(SVDS_ERR_ARG, "record_bad: step");
+  k_record_bad<<<1, kWave, 0, s>>>(d, step);
+  SVDS_LAUNCH_CHECK();
+}
+
 void small_dgks(Small* d, int total, int nb, const double* C0, int ldc0, hipStream_t s) {
   k_dgks<<<1, kWave, 0, s>>>(d, total, nb, C0, ldc0);
   SVDS_LAUNCH_CHECK();

@@ -65,6 +65,7 @@ struct Small {
   int blk[kMaxBlock];
   int bad;                // orthogonalisation breakdown bitmask
   int skip2;              // 1: the second Gram-Schmidt pass is not needed
+  int stepbad[kGmax];     // breakdown record of each step of the norm estimate
   int nprev, gprev;       // +k vectors: count and rows
   double normop;          // running ||Op||
   int eig_sweeps;
@@ -95,6 +96,8 @@ void small_h_append(Small* d, int gc, int nb, hipStream_t s);
 // Gram-Schmidt pass: ||c_j||^2 <= G0_jj / 2 with C0 (total x nb, ld ldc0) the
 // coefficients of the pass and G0 = C0 + total the block's own Gram matrix
 void small_dgks(Small* d, int total, int nb, const double* C0, int ldc0, hipStream_t s);
+// d->stepbad[step] = d->bad (the breakdown record of the last orthogonalisation)
+void small_record_bad(Small* d, int step, hipStream_t s);
 void small_extract(Small* d, int gc, int descending, int refined, hipStream_t s);
 // which = 1: also test columns that collapsed during projection against the
 // pre-projection Gram diagonal G0[j*ldg0 + j].  The Gram matrix is d->G, or,
