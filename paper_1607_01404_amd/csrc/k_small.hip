@@ -25,6 +25,35 @@ __device__ __forceinline__ void rr_pair(int np, int r, int k, int& p, int& q) {
   }
 }
 
+// C (M x N) = op(A) B with op(A) (M x K) and B (K x N), all in LDS with
+// leading dimension kLs; op(A) = A^T when TA.  Each thread forms a 2 x 2 tile
+// (half the LDS reads of one output per thread); every output is summed over
+// the inner index in order.
+template <bool TA>
+__device__ void lds_gemm(int M, int N, int K, const double* A, const double* B, double* C) {
+  const int mt = (M + 1) >> 1, nt = (N + 1) >> 1;
+  for (int a = threadIdx.x; a < mt * nt; a += kEigT) {
+    const int i0 = 2 * (a % mt), j0 = 2 * (a / mt);
+    const int i1 = min(i0 + 1, M - 1), j1 = min(j0 + 1, N - 1);
+    double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
+    for (int c = 0; c < K; ++c) {
+      const double a0 = TA ? A[c * kLs + i0] : A[i0 * kLs + c];
+      const double a1 = TA ? A[c * kLs + i1] : A[i1 * kLs + c];
+      const double b0 = B[c * kLs + j0], b1 = B[c * kLs + j1];
+      c00 = fma(a0, b0, c00);
+      c01 = fma(a0, b1, c01);
+      c10 = fma(a1, b0, c10);
+      c11 = fma(a1, b1, c11);
+    }
+    C[i0 * kLs + j0] = c00;
+    if (j0 + 1 < N) C[i0 * kLs + j0 + 1] = c01;
+    if (i0 + 1 < M) {
+      C[(i0 + 1) * kLs + j0] = c10;
+      if (j0 + 1 < N) C[(i0 + 1) * kLs + j0 + 1] = c11;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // symmetric eigenproblem by cyclic Jacobi with a round-robin parallel order.
 // A (n x n, ld kLs) in LDS is destroyed; Z must hold an orthonormal matrix W
@@ -198,6 +227,17 @@ __device__ int jacobi_eig_lds(int n, double* A, double* Z, double* d, double* cs
 constexpr int kBordMax = 16;
 constexpr int kRootLanes = 16;
 
+// 1/x to about one ulp for normal x: the hardware estimate refined by two
+// Newton steps (each at least doubles the correct bits).  The secular sums
+// use it; their error bound already allows a few ulps per term.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // sum over the 16 lanes of a row (a root's group); all lanes hold the same bits
 __device__ __forceinline__ double group16_sum(double v) { return lane_sum<double, 16>(v); }
 
@@ -241,10 +281,12 @@ __device__ void bordered_eig_lds(int g, int g0, double* A, double* Z, double* d,
   for (int c = 0; c < nbd; ++c) {
     const int n = g0 + c;  // size before this step
     const double alpha = Bc[c * kLd + n];
-    for (int i = t; i < n; i += NT) {  // z = U^T x
+    for (int a = t; a < n * kRootLanes; a += NT) {  // z = U^T x, 16 lanes per entry
+      const int i = a / kRootLanes, l = a % kRootLanes;
       double acc = 0.0;
-      for (int r = 0; r < n; ++r) acc = fma(U[r * kLs + i], Bc[c * kLd + r], acc);
-      zv[i] = acc;
+      for (int r = l; r < n; r += kRootLanes) acc = fma(U[r * kLs + i], Bc[c * kLd + r], acc);
+      acc = group16_sum(acc);
+      if (l == 0) zv[i] = acc;
     }
     __syncthreads();
     if (t < kWave) {
@@ -383,7 +425,7 @@ __device__ void bordered_eig_lds(int g, int g0, double* A, double* Z, double* d,
         double s1 = 0.0, s2 = 0.0, s3 = 0.0;
         for (int j = l; j < m; j += kRootLanes) {
           if (j == K) continue;
-          const double qj = zk[j] / ((dk[j] - dK) - tt);
+          const double qj = zk[j] * rcp_nr((dk[j] - dK) - tt);
           s1 = fma(zk[j], qj, s1);
           s2 = fma(qj, qj, s2);
           s3 += fabs(zk[j] * qj);
@@ -393,26 +435,28 @@ __device__ void bordered_eig_lds(int g, int g0, double* A, double* Z, double* d,
         s3 = group16_sum(s3);
         const double R = aK - tt - s1;  // the secular function without the origin pole
         const double Rp = -1.0 - s2;
-        const double f = R + zK2 / tt;
-        if (fabs(f) <= 8.0 * kEps * (fabs(aK) + fabs(tt) + s3 + zK2 / fabs(tt))) break;
+        const double zt = zK2 / tt;
+        const double f = R + zt;
+        if (fabs(f) <= 8.0 * kEps * (fabs(aK) + fabs(tt) + s3 + fabs(zt))) break;
         if (f > 0.0) a = tt;
         else b = tt;
-        // R + Rp (x - tt) + zK2 / x = 0, i.e. Rp x^2 + B x + zK2 = 0 (Rp < 0: real roots)
+        // R + Rp (x - tt) + zK2 / x = 0, i.e. Rp x^2 + B x + zK2 = 0.  With
+        // Rp < 0 < zK2 it has one positive and one negative root; the bracket
+        // lies on one side of the origin pole, so only that side's root is
+        // formed, each in its cancellation-free form
         const double B = R - Rp * tt;
         const double sq = sqrt(B * B - 4.0 * Rp * zK2);
-        double r1, r2;
+        const bool right = a >= 0.0;
+        double rq;
         if (B >= 0.0) {
           const double w = -B - sq;
-          r1 = w / (2.0 * Rp);
-          r2 = 2.0 * zK2 / w;
+          rq = right ? w / (2.0 * Rp) : 2.0 * zK2 / w;
         } else {
           const double w = -B + sq;
-          r1 = 2.0 * zK2 / w;
-          r2 = w / (2.0 * Rp);
+          rq = right ? 2.0 * zK2 / w : w / (2.0 * Rp);
         }
         double tn = 0.5 * (a + b);
-        if (a < r1 && r1 < b) tn = r1;
-        else if (a < r2 && r2 < b) tn = r2;
+        if (a < rq && rq < b) tn = rq;
         const bool stop = fabs(tn - tt) <= 4.0 * kEps * fabs(tn) ||
                           (b - a) <= 4.0 * kEps * fmax(fabs(a), fabs(b));
         tt = tn;
@@ -442,41 +486,65 @@ __device__ void bordered_eig_lds(int g, int g0, double* A, double* Z, double* d,
       vals[q] = v;
     }
     __syncthreads();
-    for (int a = t; a < (m + 1) * (m + 1); a += NT) {  // arrowhead eigenvectors (unnormalised)
-      const int j = a % (m + 1), k = a / (m + 1);
-      V[j * kLs + k] = (j < m) ? zh[j] / ((dk[j] - dk[Kk[k]]) - tau[k]) : -1.0;
+    // arrowhead eigenvectors (unnormalised) without their last entry, -1: row
+    // i of V belongs to pole i of U, zero for the deflated poles, so that the
+    // product with U needs no index gather
+    for (int a = t; a < n * (m + 1); a += NT) {
+      const int k = a / n, e = a % n;
+      if (e < m) V[kidx[e] * kLs + k] = zh[e] / ((dk[e] - dk[Kk[k]]) - tau[k]);
+      else V[defl[e - m] * kLs + k] = 0.0;
     }
-    for (int q = t; q <= n; q += NT) {
+    for (int a = t; a < (n + 1) * kRootLanes; a += NT) {  // ranks, 16 lanes per entry
+      const int q = a / kRootLanes, l = a % kRootLanes;
       const double v = vals[q];
-      int rank = 0;
-      for (int j = 0; j <= n; ++j) rank += (vals[j] < v || (vals[j] == v && j < q));
-      pos[q] = rank;
+      double rank = 0.0;
+      for (int j = l; j <= n; j += kRootLanes)
+        rank += (vals[j] < v || (vals[j] == v && j < q)) ? 1.0 : 0.0;
+      rank = group16_sum(rank);
+      if (l == 0) pos[q] = (int)rank;
     }
     __syncthreads();
     if (t < (m + 1) * kRootLanes) {  // 16 lanes per column k
       const int k = t / kRootLanes, l = t % kRootLanes;
-      double s = 0.0;
-      for (int j = l; j <= m; j += kRootLanes) s = fma(V[j * kLs + k], V[j * kLs + k], s);
+      double s = (l == 0) ? 1.0 : 0.0;  // the last entry, -1
+      for (int i = l; i < n; i += kRootLanes) s = fma(V[i * kLs + k], V[i * kLs + k], s);
       s = group16_sum(s);
       if (l == 0) nrm[k] = 1.0 / sqrt(s);
     }
     __syncthreads();
     // Un = [U 0; 0 1] [arrowhead eigenvectors | deflated unit vectors], columns in order
-    for (int a = t; a < (n + 1) * (n + 1); a += NT) {
-      const int r = a / (n + 1), q = a % (n + 1);
-      double v;
-      if (q <= m) {
-        if (r == n) {
-          v = -nrm[q];
-        } else {
-          double acc = 0.0;
-          for (int j = 0; j < m; ++j) acc = fma(U[r * kLs + kidx[j]], V[j * kLs + q], acc);
-          v = acc * nrm[q];
+    {
+      const int mt = (n + 1) >> 1, qt = (m + 2) >> 1;  // 2 x 2 tiles of rows < n, columns <= m
+      const int ntile = mt * qt;
+      const int nd = n - m;  // deflated columns
+      for (int a = t; a < ntile + (m + 1) + (n + 1) * nd; a += NT) {
+        if (a < ntile) {
+          const int r0 = 2 * (a % mt), q0 = 2 * (a / mt);
+          const int r1 = min(r0 + 1, n - 1), q1 = min(q0 + 1, m);
+          double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
+          for (int j = 0; j < n; ++j) {
+            const double u0 = U[r0 * kLs + j], u1 = U[r1 * kLs + j];
+            const double v0 = V[j * kLs + q0], v1 = V[j * kLs + q1];
+            c00 = fma(u0, v0, c00);
+            c01 = fma(u0, v1, c01);
+            c10 = fma(u1, v0, c10);
+            c11 = fma(u1, v1, c11);
+          }
+          Un[r0 * kLs + pos[q0]] = c00 * nrm[q0];
+          if (q0 + 1 <= m) Un[r0 * kLs + pos[q0 + 1]] = c01 * nrm[q0 + 1];
+          if (r0 + 1 < n) {
+            Un[(r0 + 1) * kLs + pos[q0]] = c10 * nrm[q0];
+            if (q0 + 1 <= m) Un[(r0 + 1) * kLs + pos[q0 + 1]] = c11 * nrm[q0 + 1];
+          }
+        } else if (a < ntile + m + 1) {  // the new last row of the root columns
+          const int q = a - ntile;
+          Un[n * kLs + pos[q]] = -nrm[q];
+        } else {  // deflated unit vectors: columns of U, zero in the new row
+          const int e = a - ntile - (m + 1);
+          const int r = e / nd, q = m + 1 + e % nd;
+          Un[r * kLs + pos[q]] = (r < n) ? U[r * kLs + defl[q - m - 1]] : 0.0;
         }
-      } else {
-        v = (r < n) ? U[r * kLs + defl[q - m - 1]] : 0.0;
       }
-      Un[r * kLs + pos[q]] = v;
     }
     __syncthreads();
     for (int q = t; q <= n; q += NT) lam[pos[q]] = vals[q];
@@ -487,12 +555,7 @@ __device__ void bordered_eig_lds(int g, int g0, double* A, double* Z, double* d,
   }
   for (int i = t; i < g; i += NT) d[i] = lam[i];
   // Z <- W U
-  for (int a = t; a < g * g; a += NT) {
-    const int r = a / g, c = a % g;
-    double acc = 0.0;
-    for (int i = 0; i < g; ++i) acc = fma(Z[r * kLs + i], U[i * kLs + c], acc);
-    Un[r * kLs + c] = acc;
-  }
+  lds_gemm<false>(g, g, g, Z, U, Un);
   __syncthreads();
   for (int a = t; a < g * g; a += NT) {
     const int r = a / g, c = a % g;
@@ -736,19 +799,9 @@ void small_h_append(Small* d, int gc, int nb, hipStream_t s) {
 // A (g x g) <- Z^T A Z, symmetrised; Mx scratch
 __device__ void project_lds(int g, double* A, const double* Z, double* Mx) {
   const int t = threadIdx.x;
-  for (int a = t; a < g * g; a += kEigT) {
-    const int i = a % g, j = a / g;
-    double acc = 0.0;
-    for (int c = 0; c < g; ++c) acc += A[i * kLs + c] * Z[c * kLs + j];
-    Mx[i * kLs + j] = acc;
-  }
+  lds_gemm<false>(g, g, g, A, Z, Mx);
   __syncthreads();
-  for (int a = t; a < g * g; a += kEigT) {
-    const int i = a % g, j = a / g;
-    double acc = 0.0;
-    for (int c = 0; c < g; ++c) acc += Z[c * kLs + i] * Mx[c * kLs + j];
-    A[i * kLs + j] = acc;
-  }
+  lds_gemm<true>(g, g, g, Z, Mx, A);
   __syncthreads();
   for (int a = t; a < g * g; a += kEigT) {
     const int i = a % g, j = a / g;
