@@ -148,6 +148,11 @@ typedef struct svds_opts {
                           /* 0 -> 8                                         */
   const float* pc_model;  /* SVDS_PC_LEARNED: device array of               */
                           /* SVDS_LPC_NPARAMS FP32 parameters               */
+  int fused_gram;         /* 1 (default): FP64 stage-1 products with C =    */
+                          /* A^T A in one pass over A when the prepared     */
+                          /* matrix has a plan for it (see                  */
+                          /* svds_matrix_normal) and it moves fewer bytes   */
+                          /* than the two products; 0: always A, then A^T   */
 } svds_opts;
 
 /* ---- statistics (host struct, filled by svds_solve) ---------------------- */
@@ -169,7 +174,16 @@ typedef struct svds_stats {
   double spmm_seconds;    /* their summed duration (HIP events)             */
   double spmm_bytes;      /* their algorithmic bytes: nnz*(8+4) + 4*(rows+1)*/
                           /* + 8*b*(rows + cols) per call                   */
-  int64_t inner_iters;    /* JD second stage: MINRES steps (block steps)    */
+  int64_t inner_iters;    /* JD second stage: symmetric-QMR steps (block    */
+                          /* steps)                                         */
+  /* filled when opts.profile = 1 (zero otherwise): */
+  int64_t gram_calls;     /* one-pass A^T A products timed (their first,    */
+                          /* partial-sum kernel)                            */
+  double gram_seconds;    /* its summed duration (HIP events)               */
+  double gram_bytes;      /* its algorithmic bytes: nnz*(8+4+1) +           */
+                          /* 4*(rows+1) + 8*b*cols + (4 + 8*b)*wsum +       */
+                          /* 20*nblk per call (wsum: the windows' summed    */
+                          /* widths, nblk: row blocks)                      */
 } svds_stats;
 
 /* Fill *opts with the defaults above.  Returns SVDS_OK or SVDS_ERR_ARG. */
@@ -182,7 +196,9 @@ const char* svds_error_string(int code);
 /* A prepared matrix holds the device-side copies the solver works from: the
  * validated CSR with 32-bit row offsets, the explicit transpose A^T (so that
  * both products of Section 3.3 are atomic-free row-parallel SpMMs), the
- * row-length bins of both, and diag(A^T A) / diag(A A^T).  Preparing reads the
+ * row-length bins of both, and diag(A^T A) / diag(A A^T).  When the work
+ * matrix A_w (A if m >= n, else A^T) qualifies, it also holds the plan of a
+ * one-pass product with A_w^T A_w (svds_matrix_normal).  Preparing reads the
  * caller's CSR arrays on `stream`; afterwards they are no longer needed. */
 typedef struct svds_matrix svds_matrix;
 
@@ -196,6 +212,24 @@ int svds_matrix_destroy(svds_matrix* h);
  * matrixMatvec callback of Section 3.4 with blockSize = b, run on the device. */
 int svds_matrix_spmm(const svds_matrix* h, int trans, int b, const double* X, double* Y,
                      void* stream);
+
+/* Product with the first stage's operator C = A_w^T A_w (Section 3.3; A_w is
+ * the work matrix above, p = min(m, n) its column count):
+ *   Z (p x b) = C X (p x b), row-major blocks as for svds_matrix_spmm.
+ * The prepared matrix has a one-pass plan when, for some R in 16..128, every
+ * block of R consecutive rows of A_w holds at most 2048 nonzeros and touches
+ * a window of at most 1024 columns, the windows' first columns never
+ * decrease, and the windows' summed widths stay within 4 p (banded matrices
+ * and other locally coupled ones).  With fused != 0, a plan, and fewer
+ * algorithmic bytes than two SpMMs for this b, C X is formed in one read of
+ * A_w: each workgroup multiplies its row block by X and then by the block's
+ * transpose from LDS, and a second kernel adds the windows' partial sums per
+ * column in block order.  Otherwise it is A_w^T (A_w X) by two SpMMs.  Both
+ * ways are deterministic.  *used (may be NULL) receives 1 for the one-pass
+ * product, 0 otherwise.  Workspace (p x b, or the windows' partial sums) is
+ * stream-ordered on `stream`. */
+int svds_matrix_normal(const svds_matrix* h, int b, const double* X, double* Z, int fused,
+                       int* used, void* stream);
 
 /* ---- solve ---------------------------------------------------------------- */
 /* k triplets of A (1 <= k <= min(m, n)), target SVDS_LARGEST/SVDS_SMALLEST,

@@ -39,7 +39,7 @@ class Opts(C.Structure):
                 ("method", C.c_int), ("stage2_solver", C.c_int), ("jd_max_inner", C.c_int),
                 ("jd_inner_tol", C.c_double), ("relative_tol", C.c_int),
                 ("max_seconds", C.c_double), ("pc_block", C.c_int), ("pc_degree", C.c_int),
-                ("pc_model", C.c_void_p)]
+                ("pc_model", C.c_void_p), ("fused_gram", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -49,7 +49,8 @@ class Stats(C.Structure):
                 ("seconds", C.c_double * 2), ("setup_seconds", C.c_double),
                 ("norm_A_used", C.c_double), ("spmm_calls", C.c_int64),
                 ("spmm_seconds", C.c_double), ("spmm_bytes", C.c_double),
-                ("inner_iters", C.c_int64)]
+                ("inner_iters", C.c_int64), ("gram_calls", C.c_int64),
+                ("gram_seconds", C.c_double), ("gram_bytes", C.c_double)]
 
     def to_dict(self):
         return {"nconv": self.nconv, "stage_exit": self.stage_exit,
@@ -59,7 +60,9 @@ class Stats(C.Structure):
                 "breakdowns": self.breakdowns, "seconds": list(self.seconds),
                 "setup_seconds": self.setup_seconds, "norm_A_used": self.norm_A_used,
                 "spmm_calls": self.spmm_calls, "spmm_seconds": self.spmm_seconds,
-                "spmm_bytes": self.spmm_bytes, "inner_iters": self.inner_iters}
+                "spmm_bytes": self.spmm_bytes, "inner_iters": self.inner_iters,
+                "gram_calls": self.gram_calls, "gram_seconds": self.gram_seconds,
+                "gram_bytes": self.gram_bytes}
 
 
 _lib = None
@@ -85,6 +88,7 @@ def load_library():
     lib.svds_matrix_create.argtypes = [C.POINTER(Csr), C.POINTER(vp), vp]
     lib.svds_matrix_destroy.argtypes = [vp]
     lib.svds_matrix_spmm.argtypes = [vp, i32, i32, vp, vp, vp]
+    lib.svds_matrix_normal.argtypes = [vp, i32, vp, vp, i32, C.POINTER(i32), vp]
     lib.svds_solve.argtypes = [C.POINTER(Csr), i32, i32, dbl, C.POINTER(Opts), vp, vp, i64, vp,
                                i64, vp, C.POINTER(Stats), vp]
     lib.svds_solve_prepared.argtypes = [vp, i32, i32, dbl, C.POINTER(Opts), vp, vp, i64, vp,
@@ -200,6 +204,19 @@ class Matrix:
         _check(load_library().svds_matrix_spmm(self.handle, int(trans), b, _ptr(X), _ptr(Y),
                                                _stream(stream)), "spmm")
         return Y
+
+    def normal(self, X, fused=True, stream=None):
+        """Z = A_w^T A_w X (svds_matrix_normal); A_w = A if m >= n else A^T.
+        Returns (Z, used) with used = 1 when the one-pass product ran."""
+        import torch
+        p = min(self.m, self.n)
+        assert X.shape[0] == p and X.is_contiguous() and X.dtype == torch.float64
+        Z = torch.empty_like(X)
+        used = C.c_int(-1)
+        _check(load_library().svds_matrix_normal(self.handle, X.shape[1], _ptr(X), _ptr(Z),
+                                                 int(bool(fused)), C.byref(used),
+                                                 _stream(stream)), "normal")
+        return Z, used.value
 
     def solve(self, k, target="largest", tol=1e-10, stream=None, **opts):
         return _solve(lambda *a: load_library().svds_solve_prepared(self.handle, *a),

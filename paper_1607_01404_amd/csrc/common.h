@@ -184,6 +184,29 @@ struct Csr32 {
   int heuristic_unroll = 1;
 };
 
+// Plan of the one-pass normal-equations product Z = A^T (A X) (k_gram.hip)
+// for matrices whose blocks of R consecutive rows touch narrow column windows.
+// Block b covers rows [b R, min((b+1) R, rows)) and columns [lo[b], hi[b]].
+struct GramPlan {
+  int R = 0;                  // rows per block (16..128); 0: no plan
+  int64_t nblk = 0;           // blocks
+  int64_t wsum = 0;           // total window width (rows of the partial sums)
+  int32_t* lo = nullptr;      // nblk: first window column, nondecreasing
+  int32_t* hi = nullptr;      // nblk: last window column (lo - 1: empty block)
+  int64_t* poff = nullptr;    // nblk + 1: window offsets, the prefix of the widths
+  int32_t* colptr = nullptr;  // wsum + nblk: block-local column pointers; block
+                              //   b's w_b + 1 entries start at poff[b] + b
+  uint8_t* rank = nullptr;    // nnz, CSR order: rank of the nonzero among its
+                              //   block's nonzeros in the same column (rows
+                              //   ascending)
+  int32_t* cover = nullptr;   // cols: first block whose window holds the column
+                              //   (nblk: none)
+};
+constexpr int kGramMaxNnz = 2048;    // nonzeros per block (staged in LDS)
+constexpr int kGramMaxWidth = 1024;  // columns per window
+constexpr int kGramMinRows = 16;     // finest block the windows are measured at
+constexpr int kGramMaxRows = 128;    // tallest block
+
 }  // namespace svds
 
 struct svds_matrix {
@@ -192,6 +215,7 @@ struct svds_matrix {
   svds::Csr32 A;                   // work matrix (tall): rows >= cols
   svds::Csr32 At;                  // its transpose
   double* diagC = nullptr;         // diag(A_w^T A_w) (length A.cols)
+  svds::GramPlan G;                // one-pass A_w^T A_w product (G.R = 0: none)
   int device = 0;
   // set when the arrays were allocated stream-ordered on `owner` (the
   // internal create/solve/destroy sequence of one svds_solve call); they are
@@ -223,6 +247,15 @@ void autotune_spmm(Csr32& A, int b, bool fp32, hipStream_t s);
 
 // SpMM: Y (rows x b, row-major) = A X (cols x b, row-major)
 void spmm(const Csr32& A, int b, const double* X, double* Y, hipStream_t s);
+// one-pass normal-equations product (k_gram.hip)
+void gram_windows(const Csr32& A, int64_t nblk, int32_t* lo, int32_t* hi, int32_t* nnzb,
+                  hipStream_t s);
+void gram_build(const Csr32& A, const GramPlan& G, hipStream_t s);
+// P: workspace of G.wsum * b doubles (the windows' partial sums)
+void gram_partial(const Csr32& A, const GramPlan& G, int b, const double* X, double* P,
+                  hipStream_t s);
+void gram_combine(const GramPlan& G, int64_t cols, int b, const double* P, double* Z,
+                  hipStream_t s);
 void spmm_f32(const Csr32& A, int b, const float* X, float* Y, hipStream_t s);
 
 // dense tall-skinny (column-major).  Basis segments may be stored in FP64 or

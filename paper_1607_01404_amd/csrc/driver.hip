@@ -47,6 +47,26 @@ double now() {
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
+// algorithmic bytes of the one-pass product's partial-sum kernel: CSR rows
+// (row pointers, indices, values) with the one-byte ranks, the gathered X,
+// the column pointers and written partial sums of the windows, the block
+// descriptors
+double gram_partial_bytes(const Csr32& A, const GramPlan& G, int b) {
+  return 13.0 * (double)A.nnz + 4.0 * (double)(A.rows + 1) + 8.0 * b * (double)A.cols +
+         (4.0 + 8.0 * b) * (double)G.wsum + 20.0 * (double)G.nblk;
+}
+
+// the one-pass product (partial sums, then their per-column sums) against A
+// then A^T by two SpMMs, in algorithmic bytes; taken when it moves at most
+// 90 % of the two products' bytes
+bool gram_cheaper(const Csr32& A, const GramPlan& G, int b) {
+  const double fused = gram_partial_bytes(A, G, b) + 8.0 * b * (double)G.wsum +
+                       (4.0 + 8.0 * b) * (double)A.cols;
+  const double two = 24.0 * (double)A.nnz + 4.0 * (double)(A.rows + A.cols + 2) +
+                     16.0 * b * (double)(A.rows + A.cols);
+  return fused <= 0.9 * two;
+}
+
 }  // namespace
 
 hipMemPool_t device_pool() {
@@ -294,12 +314,20 @@ class Solver {
   // record writes back and invalidates the caches, which both costs time and
   // hands the next kernel a cold L2), kept in a pool, and read back at the
   // solver's synchronisation points, after which they are reused.
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_;  // recorded since the last harvest
+  struct TimedCall {
+    hipEvent_t a, b;
+    bool gram;  // the one-pass A^T A product (else an SpMM)
+  };
+  std::vector<TimedCall> ev_;                          // recorded since the last harvest
   std::vector<hipEvent_t> evpool_;                     // every event created by this solve
   size_t evnext_ = 0;                                  // first unused event of the pool
   double spmm_seconds_ = 0.0;
   int64_t spmm_calls_ = 0;
   double spmm_bytes_ = 0.0;
+  double gram_seconds_ = 0.0;
+  int64_t gram_calls_ = 0;
+  double gram_bytes_ = 0.0;
+  double* gramP_ = nullptr;  // partial sums of the one-pass product (wsum x kMaxBlock)
   hipEvent_t pool_event() {
     if (evnext_ == evpool_.size()) {
       hipEvent_t e;
@@ -312,11 +340,16 @@ class Solver {
   void harvest_events() {
     for (auto& e : ev_) {
       float ms = 0.f;
-      SVDS_HIP(hipEventSynchronize(e.second));
-      SVDS_HIP(hipEventElapsedTime(&ms, e.first, e.second));
-      spmm_seconds_ += ms * 1e-3;
+      SVDS_HIP(hipEventSynchronize(e.b));
+      SVDS_HIP(hipEventElapsedTime(&ms, e.a, e.b));
+      if (e.gram) {
+        gram_seconds_ += ms * 1e-3;
+        ++gram_calls_;
+      } else {
+        spmm_seconds_ += ms * 1e-3;
+        ++spmm_calls_;
+      }
     }
-    spmm_calls_ += (int64_t)ev_.size();
     ev_.clear();
     evnext_ = 0;
   }
@@ -334,7 +367,7 @@ class Solver {
     SVDS_HIP(hipEventRecord(a, s_));
     run();
     SVDS_HIP(hipEventRecord(b, s_));
-    ev_.emplace_back(a, b);
+    ev_.push_back(TimedCall{a, b, false});
     const double sv = (double)sizeof(TV);
     spmm_bytes_ += (double)Mx.nnz * (sv + 4.0) + 4.0 * (double)(Mx.rows + 1) +
                    sv * nb * (double)(Mx.rows + Mx.cols);
@@ -344,11 +377,36 @@ class Solver {
     st->spmm_calls = spmm_calls_;
     st->spmm_seconds = spmm_seconds_;
     st->spmm_bytes = spmm_bytes_;
+    st->gram_calls = gram_calls_;
+    st->gram_seconds = gram_seconds_;
+    st->gram_bytes = gram_bytes_;
+  }
+  // Z (n x nb) = A^T (A X) by the one-pass product; only its first kernel is
+  // timed (the partial sums, which read A)
+  void timed_gram(int nb, const double* X, double* Z) {
+    const GramPlan& G = M_->G;
+    if (!gramP_) gramP_ = buf_.get<double>((size_t)G.wsum * kMaxBlock);
+    if (!o_.profile) {
+      gram_partial(A(), G, nb, X, gramP_, s_);
+    } else {
+      hipEvent_t a = pool_event(), b = pool_event();
+      SVDS_HIP(hipEventRecord(a, s_));
+      gram_partial(A(), G, nb, X, gramP_, s_);
+      SVDS_HIP(hipEventRecord(b, s_));
+      ev_.push_back(TimedCall{a, b, true});
+      gram_bytes_ += gram_partial_bytes(A(), G, nb);
+    }
+    gram_combine(G, A().cols, nb, gramP_, Z, s_);
+  }
+  bool use_gram(int nb) const {
+    return o_.fused_gram && M_->G.R > 0 && gram_cheaper(A(), M_->G, nb);
   }
 
   // W block (compact, N x nb) = Op T block (compact)
   void apply_op(const double* Tc, double* Wc, int nb) {
-    if (stage_ == 1) {
+    if (stage_ == 1 && use_gram(nb)) {
+      timed_gram(nb, Tc, Wc);  // n x nb in one pass over A
+    } else if (stage_ == 1) {
       timed_spmm(A(), nb, Tc, Yc_);   // m x nb
       timed_spmm(At(), nb, Yc_, Wc);  // n x nb
     } else {
@@ -1415,11 +1473,88 @@ void alloc_csr(svds::Csr32& c, int64_t rows, int64_t cols, int64_t nnz, const Me
   mm.alloc(&c.val32, nnz);
 }
 
+void free_gram(svds::GramPlan& g, const MemMode& mm) {
+  mm.release(g.lo);
+  mm.release(g.hi);
+  mm.release(g.poff);
+  mm.release(g.colptr);
+  mm.release(g.rank);
+  mm.release(g.cover);
+  g = svds::GramPlan{};
+}
+
+// Plan of the one-pass A^T A product (k_gram.hip).  The windows are measured
+// on blocks of kGramMinRows rows and merged on the host for the candidate
+// block heights; the tallest block height whose blocks stay within the LDS
+// limits is kept.  No plan when the windows' first columns decrease, or when
+// the windows together would exceed four times the column count (their
+// partial sums would cost more traffic than the second product saves).
+void build_gram_plan(svds_matrix* h, const MemMode& mm, hipStream_t s) {
+  const svds::Csr32& A = h->A;
+  constexpr int F = svds::kGramMinRows;
+  const int64_t nf = (A.rows + F - 1) / F;
+  if (A.nnz <= 0 || nf <= 0) return;
+  std::vector<int32_t> flo(nf), fhi(nf), fnz(nf);
+  int32_t* d = static_cast<int32_t*>(svds::stream_alloc(sizeof(int32_t) * 3 * nf, s));
+  svds::gram_windows(A, nf, d, d + nf, d + 2 * nf, s);
+  SVDS_HIP(hipMemcpyAsync(flo.data(), d, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s));
+  SVDS_HIP(hipMemcpyAsync(fhi.data(), d + nf, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s));
+  SVDS_HIP(hipMemcpyAsync(fnz.data(), d + 2 * nf, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s));
+  svds::stream_free(d, s);
+  SVDS_HIP(hipStreamSynchronize(s));
+  for (int R = svds::kGramMaxRows; R >= F; R /= 2) {
+    const int64_t k = R / F;
+    const int64_t nb = (nf + k - 1) / k;
+    std::vector<int32_t> lo(nb), hi(nb);
+    std::vector<int64_t> poff(nb + 1, 0);
+    bool ok = true;
+    int32_t prev = 0;
+    for (int64_t b = 0; b < nb && ok; ++b) {
+      int32_t mn = INT32_MAX, mx = -1;
+      int64_t nz = 0;
+      for (int64_t f = b * k; f < std::min(nf, (b + 1) * k); ++f) {
+        mn = std::min(mn, flo[f]);
+        mx = std::max(mx, fhi[f]);
+        nz += fnz[f];
+      }
+      if (mx < 0) {  // empty block: an empty window at the previous start
+        mn = prev;
+        mx = prev - 1;
+      }
+      ok = nz <= svds::kGramMaxNnz && mx - mn + 1 <= svds::kGramMaxWidth && mn >= prev;
+      lo[b] = mn;
+      hi[b] = mx;
+      prev = mn;
+      poff[b + 1] = poff[b] + (mx - mn + 1);
+    }
+    if (!ok) continue;
+    if (poff[nb] > 4 * A.cols) return;  // shorter blocks only add overlap
+    svds::GramPlan& g = h->G;
+    g.R = R;
+    g.nblk = nb;
+    g.wsum = poff[nb];
+    mm.alloc(&g.lo, nb);
+    mm.alloc(&g.hi, nb);
+    mm.alloc(&g.poff, nb + 1);
+    mm.alloc(&g.colptr, g.wsum + nb);
+    mm.alloc(&g.rank, A.nnz);
+    mm.alloc(&g.cover, A.cols);
+    SVDS_HIP(hipMemcpyAsync(g.lo, lo.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s));
+    SVDS_HIP(hipMemcpyAsync(g.hi, hi.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s));
+    SVDS_HIP(hipMemcpyAsync(g.poff, poff.data(), sizeof(int64_t) * (nb + 1),
+                            hipMemcpyHostToDevice, s));
+    svds::gram_build(A, g, s);
+    SVDS_HIP(hipStreamSynchronize(s));  // the host vectors above end here
+    return;
+  }
+}
+
 void destroy_matrix(svds_matrix* h) {
   if (!h) return;
   const MemMode mm{h->stream_ordered, h->owner};
   free_csr(h->A, mm);
   free_csr(h->At, mm);
+  free_gram(h->G, mm);
   mm.release(h->diagC);
   delete h;
 }
@@ -1476,6 +1611,7 @@ int create_matrix(const svds_csr* A, svds_matrix** out, hipStream_t s, bool stre
     }
     mm.alloc(&h->diagC, h->A.cols);
     svds::row_sqnorms(h->At, h->diagC, s);  // rows of A_w^T = columns of A_w
+    build_gram_plan(h, mm, s);
     SVDS_HIP(hipStreamSynchronize(s));
   } catch (...) {
     destroy_matrix(h);
@@ -1491,6 +1627,7 @@ svds_opts default_opts() {
   o.max_prev_retain = -1;
   o.two_sided_cleanup = 1;
   o.autotune = 1;
+  o.fused_gram = 1;
   o.stage2_solver = SVDS_STAGE2_JD;
   return o;
 }
@@ -1579,6 +1716,29 @@ int svds_matrix_create(const svds_csr* A, svds_matrix** out, void* stream) {
 int svds_matrix_destroy(svds_matrix* h) {
   destroy_matrix(h);
   return SVDS_OK;
+}
+
+int svds_matrix_normal(const svds_matrix* h, int b, const double* X, double* Z, int fused,
+                       int* used, void* stream) {
+  return guarded([&] {
+    if (!h || !X || !Z || b < 1 || b > svds::kMaxBlock) throw Error(SVDS_ERR_ARG, "normal args");
+    const hipStream_t s = (hipStream_t)stream;
+    const svds::Csr32& A = h->A;
+    const bool one = fused && h->G.R > 0 && svds::gram_cheaper(A, h->G, b);
+    if (used) *used = one ? 1 : 0;
+    if (one) {
+      double* P = static_cast<double*>(svds::stream_alloc(sizeof(double) * h->G.wsum * b, s));
+      svds::gram_partial(A, h->G, b, X, P, s);
+      svds::gram_combine(h->G, A.cols, b, P, Z, s);
+      svds::stream_free(P, s);
+    } else {
+      double* Y = static_cast<double*>(svds::stream_alloc(sizeof(double) * A.rows * b, s));
+      svds::spmm(A, b, X, Y, s);
+      svds::spmm(h->At, b, Y, Z, s);
+      svds::stream_free(Y, s);
+    }
+    return SVDS_OK;
+  });
 }
 
 int svds_matrix_spmm(const svds_matrix* h, int trans, int b, const double* X, double* Y,
