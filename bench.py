@@ -21,7 +21,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = ("time to k triplets at ‖r‖≤1e-10‖A‖ (plain vs mixed/learned); "
-          "SpMM HBM GB/s")
+          "sparse-operator HBM GB/s")
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 # HBM bytes per SpMM launch of the default workload from rocprofv3 FETCH_SIZE and
@@ -31,10 +31,15 @@ SPMM_TRAFFIC = {"workload": "banded_1e6x5e5_k10_smallest", "bytes_per_launch": 2
                 "source": "paper_1607_01404_amd/csrc/k_spmm.hip", "sha256_prefix": "8d27654782fae0d0"}
 
 
-def spmm_traffic(workload):
+# the same for the partial-sum kernel of the one-pass A^T A product
+# (profiles/gram_banded_1e6x5e5_b4_fp64_hbm_traffic.md)
+GRAM_TRAFFIC = {"workload": "banded_1e6x5e5_k10_smallest", "bytes_per_launch": None,
+                "source": "paper_1607_01404_amd/csrc/k_gram.hip", "sha256_prefix": ""}
+
+
+def counted_traffic(t, workload):
     import hashlib
-    t = SPMM_TRAFFIC
-    if workload != t["workload"]:
+    if workload != t["workload"] or t["bytes_per_launch"] is None:
         return None
     with open(os.path.join(ROOT, t["source"]), "rb") as f:
         h = hashlib.sha256(f.read()).hexdigest()[:16]
@@ -299,6 +304,24 @@ def condest_extra(P, torch, main_matrix, learned_params):
     return out
 
 
+def two_product_run(P, torch, ip, ix, dv, m, n, k, w, args):
+    """One solve of the same workload with the one-pass product switched off
+    (every product with C as A, then A^T by two SpMMs), for comparison."""
+    opts = dict(w["opts"], profile=1, fused_gram=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sig, U, V, rn, st = P.solve(ip, ix, dv, m, n, k, w["target"], 1e-10, **opts)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ach = st["spmm_bytes"] / max(st["spmm_seconds"], 1e-12) / 1e9
+    return {"seconds": el, "converged": bool(st["converged"]), "iters": st["iters"],
+            "matvecs": st["matvecs"],
+            "spmm": {"achieved_GBps": ach, "frac": ach / HBM_PEAK_GBS,
+                     "avg_call_us": st["spmm_seconds"] / max(st["spmm_calls"], 1) * 1e6,
+                     "bytes_per_call": st["spmm_bytes"] / max(st["spmm_calls"], 1),
+                     "traffic": counted_traffic(SPMM_TRAFFIC, args.workload)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -368,10 +391,18 @@ def main():
     sig, U, V, rn, _ = out
     normA = st["norm_A_used"]
     ok = bool(st["converged"]) and float(rn.max()) <= 1e-10 * normA
-    calls = sum(s["spmm_calls"] for s in stats)
-    ssec = sum(s["spmm_seconds"] for s in stats)
-    sbytes = sum(s["spmm_bytes"] for s in stats)
+    # the dominant sparse kernel: the one-pass A^T A product when the solve
+    # took it, else the SpMM
+    gram = sum(s["gram_calls"] for s in stats) > 0
+    key = "gram" if gram else "spmm"
+    calls = sum(s[key + "_calls"] for s in stats)
+    ssec = sum(s[key + "_seconds"] for s in stats)
+    sbytes = sum(s[key + "_bytes"] for s in stats)
     achieved = sbytes / ssec / 1e9 if ssec > 0 else 0.0
+    kernel = ("one-pass A^T A product, partial-sum kernel k_gram_partial (every stage-1 "
+              "product with C; the window combine runs after it)" if gram else
+              "binned CSR SpMM (A and A^T products of every iteration)")
+    traffic = counted_traffic(GRAM_TRAFFIC if gram else SPMM_TRAFFIC, args.workload)
     res = {
         "metric": METRIC,
         "value": sec,
@@ -397,18 +428,20 @@ def main():
         "stage_seconds": st["seconds"],
         "roofline": {
             "bound": "hbm",
-            "kernel": "binned CSR SpMM (A and A^T products of every iteration)",
+            "kernel": kernel,
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": spmm_traffic(args.workload),
+            "traffic": traffic,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-scaled)",
             "avg_call_us": ssec / max(calls, 1) * 1e6,
             "bytes_per_call": sbytes / max(calls, 1),
-            "spmm_share_of_solve": ssec / el,
+            "share_of_solve": ssec / el,
         },
     }
+    if gram:
+        res["two_product_comparison"] = two_product_run(P, torch, ip, ix, dv, m, n, k, w, args)
     if not args.no_extras:
         res["mixed_precision"] = mixed_comparison(P, torch)
         if args.batched > 0:

@@ -52,9 +52,10 @@ void gram_windows(const Csr32& A, int64_t nblk, int32_t* lo, int32_t* hi, int32_
 
 // block-local column ordering: per block, the column pointers of its window
 // and, for each nonzero in CSR order, its rank among the block's nonzeros of
-// the same column (rows ascending), so that column order position = column
-// pointer + rank.  Column c of the window belongs to thread c % kGramT, so
-// the counts and ranks need no atomics and are fixed.
+// the same column (rows ascending), so that column-order position = column
+// pointer + rank.  Each column of the window gets a bit mask of the block's
+// rows that hold it (set with atomic ORs, whose result does not depend on
+// their order); counts and ranks are population counts of these masks.
 __global__ __launch_bounds__(kGramT) void k_gram_csc(const int32_t* __restrict__ rp,
                                                      const int32_t* __restrict__ ci, int64_t rows,
                                                      int R, const int32_t* __restrict__ lo,
@@ -62,32 +63,29 @@ __global__ __launch_bounds__(kGramT) void k_gram_csc(const int32_t* __restrict__
                                                      const int64_t* __restrict__ poff,
                                                      int32_t* __restrict__ colptr,
                                                      uint8_t* __restrict__ rank) {
-  __shared__ uint32_t key[kGramMaxNnz];  // local column << 8 | local row, CSR order
-  __shared__ int32_t cnt[kGramMaxWidth];
+  constexpr int MW = kGramMaxRows / 64;  // mask words per column
+  __shared__ unsigned long long mask[kGramMaxWidth * MW];
   __shared__ int32_t part[kGramT];
   const int t = threadIdx.x;
   const int64_t b = blockIdx.x;
   const int64_t r0 = b * R, r1 = min(r0 + (int64_t)R, rows);
-  const int32_t base = rp[r0];
-  const int nz = rp[r1] - base;
+  const int nr = (int)(r1 - r0);
   const int32_t c0 = lo[b];
   const int w = hi[b] - c0 + 1;
   int32_t* cp = colptr + poff[b] + b;
-  for (int r = t; r < (int)(r1 - r0); r += kGramT)
-    for (int32_t k = rp[r0 + r]; k < rp[r0 + r + 1]; ++k)
-      key[k - base] = ((uint32_t)(ci[k] - c0) << 8) | (uint32_t)r;
-  for (int c = t; c < w; c += kGramT) cnt[c] = 0;
+  for (int i = t; i < w * MW; i += kGramT) mask[i] = 0ull;
   __syncthreads();
-  for (int e = 0; e < nz; ++e) {
-    const int c = (int)(key[e] >> 8);
-    if (c % kGramT == t) ++cnt[c];
-  }
+  // one row per group of 4 lanes, its nonzeros strided over the lanes
+  for (int r = t / 4; r < nr; r += kGramT / 4)
+    for (int32_t k = rp[r0 + r] + (t % 4); k < rp[r0 + r + 1]; k += 4)
+      atomicOr(&mask[(ci[k] - c0) * MW + r / 64], 1ull << (r % 64));
   __syncthreads();
-  // exclusive scan of the counts: one contiguous chunk of columns per thread
+  // exclusive scan of the column counts: one contiguous chunk per thread
   const int chunk = (w + kGramT - 1) / kGramT;
   const int ca = min(t * chunk, w), cb = min(ca + chunk, w);
   int sum = 0;
-  for (int c = ca; c < cb; ++c) sum += cnt[c];
+  for (int c = ca; c < cb; ++c)
+    for (int q = 0; q < MW; ++q) sum += __popcll(mask[c * MW + q]);
   part[t] = sum;
   __syncthreads();
   if (t == 0) {
@@ -101,18 +99,19 @@ __global__ __launch_bounds__(kGramT) void k_gram_csc(const int32_t* __restrict__
   __syncthreads();
   int run = part[t];
   for (int c = ca; c < cb; ++c) {
-    const int v = cnt[c];
-    cnt[c] = run;
     cp[c] = run;
-    run += v;
+    for (int q = 0; q < MW; ++q) run += __popcll(mask[c * MW + q]);
   }
-  if (t == 0) cp[w] = nz;
-  for (int c = ca; c < cb; ++c) cnt[c] = 0;
-  __syncthreads();
-  for (int e = 0; e < nz; ++e) {
-    const int c = (int)(key[e] >> 8);
-    if (c % kGramT == t) rank[base + e] = (uint8_t)(cnt[c]++);
-  }
+  if (t == 0) cp[w] = rp[r1] - rp[r0];
+  // rank of (r, c): the rows above r holding column c
+  for (int r = t / 4; r < nr; r += kGramT / 4)
+    for (int32_t k = rp[r0 + r] + (t % 4); k < rp[r0 + r + 1]; k += 4) {
+      const unsigned long long* m = mask + (ci[k] - c0) * MW;
+      int below = 0;
+      for (int q = 0; q < r / 64; ++q) below += __popcll(m[q]);
+      below += __popcll(m[r / 64] & ((1ull << (r % 64)) - 1ull));
+      rank[k] = (uint8_t)below;
+    }
 }
 
 __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
