@@ -33,8 +33,8 @@ SPMM_TRAFFIC = {"workload": "banded_1e6x5e5_k10_smallest", "bytes_per_launch": 2
 
 # the same for the partial-sum kernel of the one-pass A^T A product
 # (profiles/gram_banded_1e6x5e5_b4_fp64_hbm_traffic.md)
-GRAM_TRAFFIC = {"workload": "banded_1e6x5e5_k10_smallest", "bytes_per_launch": None,
-                "source": "paper_1607_01404_amd/csrc/k_gram.hip", "sha256_prefix": ""}
+GRAM_TRAFFIC = {"workload": "banded_1e6x5e5_k10_smallest", "bytes_per_launch": 283.5e6,
+                "source": "paper_1607_01404_amd/csrc/k_gram.hip", "sha256_prefix": "f25b2ccf6ecc65ca"}
 
 
 def counted_traffic(t, workload):
