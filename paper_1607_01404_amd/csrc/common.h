@@ -251,11 +251,12 @@ void spmm(const Csr32& A, int b, const double* X, double* Y, hipStream_t s);
 void gram_windows(const Csr32& A, int64_t nblk, int32_t* lo, int32_t* hi, int32_t* nnzb,
                   hipStream_t s);
 void gram_build(const Csr32& A, const GramPlan& G, hipStream_t s);
-// P: workspace of G.wsum * b doubles (the windows' partial sums)
+// P: workspace of G.wsum * b doubles (the windows' partial sums); Z of the
+// combine: row-major (ldz = 0) or column-major with leading dimension ldz
 void gram_partial(const Csr32& A, const GramPlan& G, int b, const double* X, double* P,
                   hipStream_t s);
 void gram_combine(const GramPlan& G, int64_t cols, int b, const double* P, double* Z,
-                  hipStream_t s);
+                  int64_t ldz, hipStream_t s);
 void spmm_f32(const Csr32& A, int b, const float* X, float* Y, hipStream_t s);
 
 // dense tall-skinny (column-major).  Basis segments may be stored in FP64 or

@@ -381,9 +381,10 @@ class Solver {
     st->gram_seconds = gram_seconds_;
     st->gram_bytes = gram_bytes_;
   }
-  // Z (n x nb) = A^T (A X) by the one-pass product; only its first kernel is
-  // timed (the partial sums, which read A)
-  void timed_gram(int nb, const double* X, double* Z) {
+  // Z (n x nb) = A^T (A X) by the one-pass product, Z row-major (ldz = 0) or
+  // column-major with leading dimension ldz; only the first kernel is timed
+  // (the partial sums, which read A)
+  void timed_gram(int nb, const double* X, double* Z, int64_t ldz) {
     const GramPlan& G = M_->G;
     if (!gramP_) gramP_ = buf_.get<double>((size_t)G.wsum * kMaxBlock);
     if (!o_.profile) {
@@ -396,7 +397,7 @@ class Solver {
       ev_.push_back(TimedCall{a, b, true});
       gram_bytes_ += gram_partial_bytes(A(), G, nb);
     }
-    gram_combine(G, A().cols, nb, gramP_, Z, s_);
+    gram_combine(G, A().cols, nb, gramP_, Z, ldz, s_);
   }
   bool use_gram(int nb) const {
     return o_.fused_gram && M_->G.R > 0 && gram_cheaper(A(), M_->G, nb);
@@ -405,7 +406,7 @@ class Solver {
   // W block (compact, N x nb) = Op T block (compact)
   void apply_op(const double* Tc, double* Wc, int nb) {
     if (stage_ == 1 && use_gram(nb)) {
-      timed_gram(nb, Tc, Wc);  // n x nb in one pass over A
+      timed_gram(nb, Tc, Wc, 0);  // n x nb in one pass over A
     } else if (stage_ == 1) {
       timed_spmm(A(), nb, Tc, Yc_);   // m x nb
       timed_spmm(At(), nb, Yc_, Wc);  // n x nb
@@ -511,9 +512,14 @@ class Solver {
   // V[:, gc:gc+nb] is orthonormal and Tc_ holds it row-major
   void append(int nb) {
     double* Tcol = V_ + gc_ * ld_;
-    apply_op(Tc_, Wc_, nb);
     double* Wcol = W_ + gc_ * ld_;
-    unpack_rows(Wc_, N_, nb, Wcol, ld_, s_);
+    if (stage_ == 1 && use_gram(nb)) {  // the combine writes W's columns directly
+      timed_gram(nb, Tc_, Wcol, ld_);
+      mv_ += 2 * nb;
+    } else {
+      apply_op(Tc_, Wc_, nb);
+      unpack_rows(Wc_, N_, nb, Wcol, ld_, s_);
+    }
     Seg sv{V_, gc_ + nb, ld_};
     tsgemm_tn(&sv, 1, N_, Wcol, ld_, nb, partial_, d_->Hn, s_);
     small_h_append(d_, gc_, nb, s_);
@@ -1729,7 +1735,7 @@ int svds_matrix_normal(const svds_matrix* h, int b, const double* X, double* Z, 
     if (one) {
       double* P = static_cast<double*>(svds::stream_alloc(sizeof(double) * h->G.wsum * b, s));
       svds::gram_partial(A, h->G, b, X, P, s);
-      svds::gram_combine(h->G, A.cols, b, P, Z, s);
+      svds::gram_combine(h->G, A.cols, b, P, Z, 0, s);
       svds::stream_free(P, s);
     } else {
       double* Y = static_cast<double*>(svds::stream_alloc(sizeof(double) * A.rows * b, s));

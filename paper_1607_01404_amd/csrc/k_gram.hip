@@ -241,12 +241,14 @@ __global__ __launch_bounds__(kGramT) void k_gram_partial(
 
 // Z[j] = the sum of column j's partial sums over the blocks whose windows
 // hold it, in block order (the windows' first columns are nondecreasing, so
-// these blocks lie between cover[j] and the first block starting past j)
+// these blocks lie between cover[j] and the first block starting past j).
+// Z is row-major (ldz = 0: entry (j, q) at j*B + q) or column-major with
+// leading dimension ldz (entry (j, q) at j + q*ldz).
 template <int B>
 __global__ void k_gram_combine(const int32_t* __restrict__ cover, const int32_t* __restrict__ lo,
                                const int32_t* __restrict__ hi, const int64_t* __restrict__ poff,
                                int64_t nblk, const double* __restrict__ P, int64_t cols,
-                               double* __restrict__ Z) {
+                               double* __restrict__ Z, int64_t ldz) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= cols) return;
   double acc[B];
@@ -258,8 +260,13 @@ __global__ void k_gram_combine(const int32_t* __restrict__ cover, const int32_t*
 #pragma unroll
     for (int q = 0; q < B; ++q) acc[q] += p[q];
   }
+  if (ldz > 0) {
 #pragma unroll
-  for (int q = 0; q < B; ++q) Z[j * B + q] = acc[q];
+    for (int q = 0; q < B; ++q) Z[j + q * ldz] = acc[q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < B; ++q) Z[j * B + q] = acc[q];
+  }
 }
 
 template <int B>
@@ -270,10 +277,10 @@ static void partial_b(const Csr32& A, const GramPlan& G, const double* X, double
 }
 
 template <int B>
-static void combine_b(const GramPlan& G, int64_t cols, const double* P, double* Z,
+static void combine_b(const GramPlan& G, int64_t cols, const double* P, double* Z, int64_t ldz,
                       hipStream_t s) {
   k_gram_combine<B><<<(unsigned)((cols + 255) / 256), 256, 0, s>>>(G.cover, G.lo, G.hi, G.poff,
-                                                                  G.nblk, P, cols, Z);
+                                                                  G.nblk, P, cols, Z, ldz);
 }
 
 void gram_partial(const Csr32& A, const GramPlan& G, int b, const double* X, double* P,
@@ -294,18 +301,18 @@ void gram_partial(const Csr32& A, const GramPlan& G, int b, const double* X, dou
 }
 
 void gram_combine(const GramPlan& G, int64_t cols, int b, const double* P, double* Z,
-                  hipStream_t s) {
+                  int64_t ldz, hipStream_t s) {
   if (cols <= 0) return;
   if (G.R <= 0 || G.nblk <= 0) throw Error(SVDS_ERR_ARG, "gram: no plan");
   switch (b) {
-    case 1: combine_b<1>(G, cols, P, Z, s); break;
-    case 2: combine_b<2>(G, cols, P, Z, s); break;
-    case 3: combine_b<3>(G, cols, P, Z, s); break;
-    case 4: combine_b<4>(G, cols, P, Z, s); break;
-    case 5: combine_b<5>(G, cols, P, Z, s); break;
-    case 6: combine_b<6>(G, cols, P, Z, s); break;
-    case 7: combine_b<7>(G, cols, P, Z, s); break;
-    case 8: combine_b<8>(G, cols, P, Z, s); break;
+    case 1: combine_b<1>(G, cols, P, Z, ldz, s); break;
+    case 2: combine_b<2>(G, cols, P, Z, ldz, s); break;
+    case 3: combine_b<3>(G, cols, P, Z, ldz, s); break;
+    case 4: combine_b<4>(G, cols, P, Z, ldz, s); break;
+    case 5: combine_b<5>(G, cols, P, Z, ldz, s); break;
+    case 6: combine_b<6>(G, cols, P, Z, ldz, s); break;
+    case 7: combine_b<7>(G, cols, P, Z, ldz, s); break;
+    case 8: combine_b<8>(G, cols, P, Z, ldz, s); break;
     default: throw Error(SVDS_ERR_ARG, "gram: block width must be 1..8");
   }
   SVDS_LAUNCH_CHECK();

@@ -394,7 +394,8 @@ __device__ void bordered_eig_lds(int g, int g0, double* A, double* Z, double* d,
     } else if (t < (m + 1) * kRootLanes) {  // whole 16-lane groups
       const int k = t / kRootLanes, l = t % kRootLanes;
       int K;
-      double a, b;
+      double a, b, t0 = 0.0;
+      bool guess = false;
       if (k == 0) {
         K = 0;
         a = s_lo - dk[0];
@@ -405,11 +406,13 @@ __device__ void bordered_eig_lds(int g, int g0, double* A, double* Z, double* d,
         b = s_hi - dk[m - 1];
       } else {
         const double base = dk[k - 1];
-        const double mid = 0.5 * (dk[k] - base);
+        const double del = dk[k] - base;
+        const double mid = 0.5 * del;
         double s = 0.0;
         for (int j = l; j < m; j += kRootLanes) s += zk[j] * zk[j] / ((dk[j] - base) - mid);
         s = group16_sum(s);
-        if ((alpha - base) - mid - s < 0.0) {  // root left of the middle: origin dk[k-1]
+        const double fm = (alpha - base) - mid - s;
+        if (fm < 0.0) {  // root left of the middle: origin dk[k-1]
           K = k - 1;
           a = 0.0;
           b = mid;
@@ -418,9 +421,23 @@ __device__ void bordered_eig_lds(int g, int g0, double* A, double* Z, double* d,
           a = -mid;
           b = 0.0;
         }
+        // first guess: the gap's two poles exact, every other term (and the
+        // linear one) frozen at the middle, tau offset from dk[k-1]:
+        //   c + zl^2 / tau - zh^2 / (del - tau) = 0,
+        //   i.e. -c tau^2 + (c del - zl^2 - zh^2) tau + zl^2 del = 0,
+        // whose one root in (0, del) is formed without cancellation
+        const double zl2 = zk[k - 1] * zk[k - 1], zh2 = zk[k] * zk[k];
+        const double c = fm - zl2 / mid + zh2 / mid;
+        const double Bq = c * del - zl2 - zh2;
+        const double sq = sqrt(fmax(Bq * Bq + 4.0 * c * zl2 * del, 0.0));
+        const double r1 = (Bq >= 0.0) ? (Bq + sq) / (2.0 * c) : (Bq - sq) / (2.0 * c);
+        const double r2 = (Bq >= 0.0) ? -2.0 * zl2 * del / (Bq + sq) : 2.0 * zl2 * del / (sq - Bq);
+        const double tau0 = (r1 > 0.0 && r1 < del) ? r1 : r2;
+        t0 = (K == k - 1) ? tau0 : tau0 - del;
+        guess = true;
       }
       const double dK = dk[K], zK2 = zk[K] * zk[K], aK = alpha - dK;
-      double tt = 0.5 * (a + b);
+      double tt = (guess && a < t0 && t0 < b) ? t0 : 0.5 * (a + b);
       for (int it = 0; it < 200; ++it) {
         double s1 = 0.0, s2 = 0.0, s3 = 0.0;
         for (int j = l; j < m; j += kRootLanes) {
