@@ -34,7 +34,7 @@ SPMM_TRAFFIC = {"workload": "banded_1e6x5e5_k10_smallest", "bytes_per_launch": 2
 # the same for the partial-sum kernel of the one-pass A^T A product
 # (profiles/gram_banded_1e6x5e5_b4_fp64_hbm_traffic.md)
 GRAM_TRAFFIC = {"workload": "banded_1e6x5e5_k10_smallest", "bytes_per_launch": 283.5e6,
-                "source": "paper_1607_01404_amd/csrc/k_gram.hip", "sha256_prefix": "f25b2ccf6ecc65ca"}
+                "source": "paper_1607_01404_amd/csrc/k_gram.hip", "sha256_prefix": "f501ebefc0458d4d"}
 
 
 def counted_traffic(t, workload):
@@ -331,7 +331,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the mixed-precision, batched and learned-preconditioner extras")
+                    help="skip the mixed-precision, batched and learned-preconditioner extras "
+                         "and the two-product comparison")
     ap.add_argument("--batched", type=int, default=256, help="problems in the batched extra (0: skip)")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--full-seconds", type=float, default=20.0,
@@ -440,7 +441,7 @@ def main():
             "share_of_solve": ssec / el,
         },
     }
-    if gram:
+    if gram and not args.no_extras:
         res["two_product_comparison"] = two_product_run(P, torch, ip, ix, dv, m, n, k, w, args)
     if not args.no_extras:
         res["mixed_precision"] = mixed_comparison(P, torch)
