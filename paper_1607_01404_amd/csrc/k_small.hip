@@ -29,10 +29,10 @@ __device__ __forceinline__ void rr_pair(int np, int r, int k, int& p, int& q) {
 // leading dimension kLs; op(A) = A^T when TA.  Each thread forms a 2 x 2 tile
 // (half the LDS reads of one output per thread); every output is summed over
 // the inner index in order.
-template <bool TA>
+template <bool TA, int NT = kEigT>
 __device__ void lds_gemm(int M, int N, int K, const double* A, const double* B, double* C) {
   const int mt = (M + 1) >> 1, nt = (N + 1) >> 1;
-  for (int a = threadIdx.x; a < mt * nt; a += kEigT) {
+  for (int a = threadIdx.x; a < mt * nt; a += NT) {
     const int i0 = 2 * (a % mt), j0 = 2 * (a / mt);
     const int i1 = min(i0 + 1, M - 1), j1 = min(j0 + 1, N - 1);
     double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
@@ -1055,7 +1055,7 @@ __device__ __forceinline__ double halves_res(const double* sums, int nc, int c, 
 }
 
 __device__ void control_body(Small* d, const CtlParams& P) {
-  __shared__ int s_action, s_nblock, s_restart, s_reff, s_off, s_peff, s_nr, s_lock;
+  __shared__ int s_action, s_nblock, s_restart, s_reff, s_off, s_peff, s_lock;
   __shared__ int s_blk[kMaxBlock];
   __shared__ double Yr[kLd * kLs];
   __shared__ double M[kLd * kLs];
@@ -1235,62 +1235,76 @@ __device__ void control_body(Small* d, const CtlParams& P) {
       Yr[i * kLs + j] = d->Y[(off + j) * kLd + i];
     }
     __syncthreads();
-    // +k: previous block coefficient vectors (zero padded), Gram-Schmidt
-    // twice against Y[:, 0:off+reff] and the accepted ones, in wave 0
+    // +k: previous block coefficient vectors (zero padded), classical
+    // Gram-Schmidt twice against Y[:, 0:off], the retained vectors and the
+    // accepted ones: all projections of a pass at once, 16 lanes per product
+    __shared__ double yv[kLd], dots[2 * kLd], s_ny;
     int nr = reff;
-    if (t < kWave) {
-      const int lane = t;
-      for (int pv = 0; pv < peff; ++pv) {
-        double y = (lane < d->gprev) ? d->yprev[pv * kLd + lane] : 0.0;
-        if (lane >= gc) y = 0.0;
-        for (int rep = 0; rep < 2; ++rep) {
-          for (int q = 0; q < off; ++q) {
-            const double yq = (lane < gc) ? d->Y[q * kLd + lane] : 0.0;
-            const double dot = wave_sum(y * yq);
-            y -= dot * yq;
-          }
-          for (int q = 0; q < nr; ++q) {
-            const double yq = (lane < gc) ? Yr[lane * kLs + q] : 0.0;
-            const double dot = wave_sum(y * yq);
-            y -= dot * yq;
-          }
+    for (int pv = 0; pv < peff; ++pv) {
+      for (int i = t; i < kLd; i += kT)
+        yv[i] = (i < gc && i < d->gprev) ? d->yprev[pv * kLd + i] : 0.0;
+      __syncthreads();
+      const int nq = off + nr;
+      for (int rep = 0; rep < 2; ++rep) {
+        for (int a = t; a < nq * 16; a += kT) {
+          const int q = a / 16, l = a % 16;
+          double acc = 0.0;
+          for (int i = l; i < gc; i += 16)
+            acc = fma(yv[i], (q < off) ? d->Y[q * kLd + i] : Yr[i * kLs + (q - off)], acc);
+          acc = lane_sum<double, 16>(acc);
+          if (l == 0) dots[q] = acc;
         }
-        const double ny = sqrt(wave_sum(y * y));
-        if (ny > kPrevDrop) {
-          if (lane < gc) Yr[lane * kLs + nr] = y / ny;
-          ++nr;
+        __syncthreads();
+        for (int i = t; i < gc; i += kT) {
+          double y = yv[i];
+          for (int q = 0; q < nq; ++q)
+            y -= dots[q] * ((q < off) ? d->Y[q * kLd + i] : Yr[i * kLs + (q - off)]);
+          yv[i] = y;
         }
+        __syncthreads();
       }
-      if (lane == 0) s_nr = nr;
+      if (t < kWave) {
+        double v = (t < gc) ? yv[t] : 0.0;
+        v = wave_sum(v * v);
+        if (t == 0) s_ny = sqrt(v);
+      }
+      __syncthreads();
+      const double ny = s_ny;
+      if (ny > kPrevDrop) {  // uniform: read after a barrier
+        for (int i = t; i < gc; i += kT) Yr[i * kLs + nr] = yv[i] / ny;
+        ++nr;
+      }
+      __syncthreads();
+    }
+    // H <- Yr^T H Yr (M = H Yr first), from H staged in LDS
+    __shared__ double Hl[kLd * kLs];
+    for (int a = t; a < gc * gc; a += kT) {
+      const int i = a % gc, c = a / gc;
+      Hl[i * kLs + c] = d->H[c * kLd + i];
     }
     __syncthreads();
-    nr = s_nr;
-    // H <- Yr^T H Yr  (M = H Yr first)
-    for (int a = t; a < gc * nr; a += kT) {
-      const int i = a % gc, j = a / gc;
-      double acc = 0.0;
-      for (int c = 0; c < gc; ++c) acc += d->H[c * kLd + i] * Yr[c * kLs + j];
-      M[i * kLs + j] = acc;
-    }
+    lds_gemm<false, kT>(gc, nr, gc, Hl, Yr, M);
+    __syncthreads();
+    lds_gemm<true, kT>(nr, nr, gc, Yr, M, Hl);
     __syncthreads();
     for (int a = t; a < nr * nr; a += kT) {
       const int i = a % nr, j = a / nr;
-      double acc = 0.0;
-      for (int c = 0; c < gc; ++c) acc += Yr[c * kLs + i] * M[c * kLs + j];
-      d->Qt[j * kLd + i] = acc;  // staged; symmetrised below
+      d->H[j * kLd + i] = 0.5 * (Hl[i * kLs + j] + Hl[j * kLs + i]);
     }
     __syncthreads();
-    for (int a = t; a < nr * nr; a += kT) {
-      const int i = a % nr, j = a / nr;
-      d->H[j * kLd + i] = 0.5 * (d->Qt[j * kLd + i] + d->Qt[i * kLd + j]);
-    }
-    __syncthreads();
-    // next +k vectors: the block's coefficients in the new basis
+    // next +k vectors: the block's coefficients in the new basis (the
+    // block's extraction vectors staged in LDS first)
     if (action == kExpand) {
+      __shared__ double Yb[kMaxBlock * kLd];
+      for (int a = t; a < gc * nblock; a += kT) {
+        const int r = a % gc, c = a / gc;
+        Yb[c * kLd + r] = d->Y[s_blk[c] * kLd + r];
+      }
+      __syncthreads();
       for (int a = t; a < nr * nblock; a += kT) {
         const int i = a % nr, c = a / nr;
         double acc = 0.0;
-        for (int r = 0; r < gc; ++r) acc += Yr[r * kLs + i] * d->Y[s_blk[c] * kLd + r];
+        for (int r = 0; r < gc; ++r) acc += Yr[r * kLs + i] * Yb[c * kLd + r];
         d->yprev[c * kLd + i] = acc;
       }
     }
