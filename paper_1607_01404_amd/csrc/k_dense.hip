@@ -59,10 +59,12 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NA], double* sh
 
 // ---------------------------------------------------------------------------
 // C = [segs]^T T  (partials per workgroup)
-// A workgroup walks 256-row chunks; the chunk of T (256 x B) is staged in LDS
-// once and each of the 4 wavefronts accumulates its own set of basis columns
-// (w, w+4, ...), each lane covering 4 rows.  T is read once per chunk and the
-// basis columns once; the per-wave accumulators are reduced at the end.
+// Workgroup (x, y) takes a contiguous row range and the column groups
+// 4y .. 4y+3 of kCPW basis columns, one group per wavefront; each lane covers
+// rows lane, lane + 64, ... with kTU row groups' loads issued together.  When
+// fewer than four groups remain for the workgroup, its spare wavefronts split
+// the row range of a group, and the pieces are added in row order before the
+// partial is written, so every partial has the same layout.
 // ---------------------------------------------------------------------------
 constexpr int kCPW = 4;   // basis columns per wavefront (16 per workgroup column)
 constexpr int kTU = 8;    // 64-row groups per step: all their loads are issued first
@@ -73,10 +75,15 @@ __global__ __launch_bounds__(kThreads) void k_tsgemm_tn(Segs3T<TB> segs, int tot
                                                         int64_t ldt, int64_t chunk,
                                                         double* __restrict__ partial,
                                                         const int* __restrict__ skip) {
-  if (skip && *skip) return;  // device-side decision: this pass is not needed
+  if (skip && *skip) return;  // device-side decision: this pass is not needed (uniform)
+  __shared__ double red[4][kCPW * B];
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  const int c0 = blockIdx.y * (4 * kCPW) + w * kCPW;
-  if (c0 >= total) return;  // the whole wavefront has no column
+  const int g0 = blockIdx.y * 4;
+  const int ncg = min(4, (total + kCPW - 1) / kCPW - g0);  // column groups here, 1..4
+  const int spl = 4 / ncg;                                  // wavefronts per group
+  const int grp = w % ncg, sub = w / ncg;
+  const bool active = sub < spl;
+  const int c0 = (g0 + grp) * kCPW;
   const TB* qp[kCPW];
   bool ok[kCPW];
 #pragma unroll
@@ -89,9 +96,14 @@ __global__ __launch_bounds__(kThreads) void k_tsgemm_tn(Segs3T<TB> segs, int tot
 #pragma unroll
   for (int a = 0; a < kCPW * B; ++a) acc[a] = 0.0;
   const int bid = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t r0 = (int64_t)bid * chunk;
-  const int64_t r1 = (r0 + chunk < N) ? r0 + chunk : N;
-  for (int64_t base = r0; base < r1; base += kWave * kTU) {
+  const int64_t rb = (int64_t)bid * chunk;
+  const int64_t re = (rb + chunk < N) ? rb + chunk : N;
+  constexpr int64_t kStep = kWave * kTU;
+  const int64_t nsteps = (re > rb) ? (re - rb + kStep - 1) / kStep : 0;
+  const int64_t r0 = rb + (active ? nsteps * sub / spl : nsteps) * kStep;
+  const int64_t r1e = rb + (active ? nsteps * (sub + 1) / spl : nsteps) * kStep;
+  const int64_t r1 = (r1e < re) ? r1e : re;
+  for (int64_t base = r0; base < r1; base += kStep) {
     double tv[kTU][B], q[kTU][kCPW];
 #pragma unroll
     for (int u = 0; u < kTU; ++u) {
@@ -109,15 +121,19 @@ __global__ __launch_bounds__(kThreads) void k_tsgemm_tn(Segs3T<TB> segs, int tot
 #pragma unroll
         for (int c = 0; c < B; ++c) acc[jj * B + c] = fma(q[u][jj], tv[u][c], acc[jj * B + c]);
   }
+#pragma unroll
+  for (int a = 0; a < kCPW * B; ++a) {
+    const double v = wave_sum(acc[a]);
+    if (lane == 0) red[w][a] = v;
+  }
+  __syncthreads();
   // partial layout: [c * total + col][block]
-  const int nblk = gridDim.x;
-#pragma unroll
-  for (int jj = 0; jj < kCPW; ++jj) {
-#pragma unroll
-    for (int c = 0; c < B; ++c) {
-      const double v = wave_sum(acc[jj * B + c]);
-      if (lane == 0 && ok[jj]) partial[((int64_t)c * total + c0 + jj) * nblk + blockIdx.x] = v;
-    }
+  if (active && sub == 0 && lane < kCPW * B) {
+    const int jj = lane / B, c = lane % B;
+    double v = red[w][lane];
+    for (int q = 1; q < spl; ++q) v += red[grp + q * ncg][lane];
+    if (c0 + jj < total)
+      partial[((int64_t)c * total + c0 + jj) * gridDim.x + blockIdx.x] = v;
   }
 }
 
