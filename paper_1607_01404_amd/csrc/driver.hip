@@ -297,6 +297,9 @@ class Solver {
   Small* d_ = nullptr;
   Ctl* hctl_ = nullptr;     // pinned, coherent
   Ctl* dctl_ = nullptr;     // its device address
+  int* hseq_ = nullptr;     // sequence word beside the record (pinned, coherent)
+  int* dseq_ = nullptr;     // its device address
+  int seq_ = 0;             // last sequence number asked of the control kernel
   int* hbad_ = nullptr;     // pinned
   double* vec_ = nullptr;   // small device vectors (k-sized)
   // mixed-precision stage 1: FP32 basis, FP64 work block, FP32 compact blocks
@@ -600,11 +603,38 @@ class Solver {
                 d_->sums, s_);
   }
 
+  // The control kernel writes its record into pinned host memory, then
+  // publishes a sequence number.  The host polls that number instead of
+  // synchronising the stream and accepts the record once it carries the
+  // number and a matching checksum (the kernel may still be finishing); it
+  // checks the stream for errors every few thousand polls.
   Ctl control(const CtlParams& p) {
-    small_control(d_, p, s_, dctl_);  // the kernel writes the record to hctl_ itself
-    SVDS_HIP(hipStreamSynchronize(s_));
-    if (!ev_.empty()) harvest_events();
-    return *hctl_;
+    ++seq_;
+    small_control(d_, p, s_, dctl_, dseq_, seq_);
+    constexpr int nw = (int)(offsetof(Ctl, seq) / sizeof(unsigned int));
+    Ctl c;
+    for (uint32_t spins = 1;; ++spins) {
+      if (__atomic_load_n(hseq_, __ATOMIC_ACQUIRE) == seq_) {
+        std::memcpy(&c, hctl_, sizeof(Ctl));
+        if (c.seq == seq_) {
+          const unsigned int* w = reinterpret_cast<const unsigned int*>(&c);
+          unsigned int sum = ctl_mix((unsigned int)seq_, (unsigned int)nw);
+          for (int a = 0; a < nw; ++a) sum += ctl_mix(w[a], (unsigned int)a);
+          if (sum == c.sum) break;
+        }
+      }
+      if ((spins & 4095u) == 0) {
+        const hipError_t e = hipStreamQuery(s_);
+        if (e == hipSuccess) {  // the kernel has ended: the record is whole
+          std::memcpy(&c, hctl_, sizeof(Ctl));
+          if (c.seq == seq_) break;
+          throw Error(SVDS_ERR_HIP, "control record not written");
+        }
+        if (e != hipErrorNotReady) SVDS_HIP(e);
+      }
+    }
+    if (ev_.size() >= 64) harvest_events();  // the rest at collect_profile
+    return c;
   }
 
   void trace(const char* what, int it, const Ctl& c, int nc) {
@@ -1343,8 +1373,12 @@ int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, d
     Wc32_ = buf_.get<float>((size_t)ld_ * kMaxBlock);
     Tb_ = buf_.get<double>((size_t)ld_ * kMaxBlock);
   }
-  SVDS_HIP(hipHostMalloc((void**)&hctl_, sizeof(Ctl), hipHostMallocMapped | hipHostMallocCoherent));
+  constexpr size_t kSeqOff = (sizeof(Ctl) + 63) / 64 * 64;
+  SVDS_HIP(hipHostMalloc((void**)&hctl_, kSeqOff + 64, hipHostMallocMapped | hipHostMallocCoherent));
   SVDS_HIP(hipHostGetDevicePointer((void**)&dctl_, hctl_, 0));
+  hseq_ = reinterpret_cast<int*>(reinterpret_cast<char*>(hctl_) + kSeqOff);
+  dseq_ = reinterpret_cast<int*>(reinterpret_cast<char*>(dctl_) + kSeqOff);
+  __atomic_store_n(hseq_, 0, __ATOMIC_RELEASE);
   SVDS_HIP(hipHostMalloc((void**)&hbad_, sizeof(int), hipHostMallocDefault));
   SVDS_HIP(hipHostMalloc((void**)&hjd_, sizeof(JdCol) * kMaxBlock, hipHostMallocDefault));
   struct PinnedFree {

@@ -1413,20 +1413,39 @@ __device__ void control_body(Small* d, const CtlParams& P) {
 // mapped for the device) the decision record is also written there with
 // ordinary vector stores, so the host reads it after the stream
 // synchronisation without a separate copy
-__global__ __launch_bounds__(kT) void k_control(Small* d, CtlParams P, Ctl* host) {
+// Wavefront 0 copies the record to host memory with its sequence number and
+// a checksum of both; then, when seqp is given, lane 0 publishes seq with a
+// system-scope release store.  The host polls that word and accepts the
+// record once it carries seq and a matching checksum, before the kernel ends.
+__global__ __launch_bounds__(kT) void k_control(Small* d, CtlParams P, Ctl* host, int* seqp,
+                                               int seq) {
   control_body(d, P);
   if (host) {
     __syncthreads();
-    const unsigned int* src = reinterpret_cast<const unsigned int*>(&d->ctl);
-    unsigned int* dst = reinterpret_cast<unsigned int*>(host);
-    for (int a = threadIdx.x; a < (int)(sizeof(Ctl) / sizeof(unsigned int)); a += kT)
-      dst[a] = src[a];
+    if (threadIdx.x < kWave) {
+      constexpr int nw = (int)(offsetof(Ctl, seq) / sizeof(unsigned int));
+      const unsigned int* src = reinterpret_cast<const unsigned int*>(&d->ctl);
+      unsigned int* dst = reinterpret_cast<unsigned int*>(host);
+      unsigned int part = 0;
+      for (int a = threadIdx.x; a < nw; a += kWave) {
+        const unsigned int w = src[a];
+        dst[a] = w;
+        part += ctl_mix(w, (unsigned int)a);
+      }
+#pragma unroll
+      for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off, kWave);
+      if (threadIdx.x == 0) {
+        host->seq = seq;
+        host->sum = part + ctl_mix((unsigned int)seq, (unsigned int)nw);
+        if (seqp) __hip_atomic_store(seqp, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+    }
   }
 }
 
-void small_control(Small* d, const CtlParams& p, hipStream_t s, Ctl* host) {
+void small_control(Small* d, const CtlParams& p, hipStream_t s, Ctl* host, int* seqp, int seq) {
   if (p.nc > kKmax + 8 || p.gc > kGmax) throw Error(SVDS_ERR_ARG, "control: sizes");
-  k_control<<<1, kT, 0, s>>>(d, p, host);
+  k_control<<<1, kT, 0, s>>>(d, p, host, seqp, seq);
   SVDS_LAUNCH_CHECK();
 }
 

@@ -5,6 +5,8 @@
 // arithmetic; the host only reads the decision record back.
 #pragma once
 
+#include <cstddef>
+
 #include "common.h"
 
 namespace svds {
@@ -38,7 +40,15 @@ struct Ctl {
   double minres;
   double res[kKmax + 8];  // candidate residual norms (trace)
   double val[kKmax + 8];  // candidate Ritz values (trace)
+  int seq;                // host copy only: the control step's sequence number
+  unsigned int sum;       // host copy only: checksum of the words before seq
 };
+
+// checksum of a control record's words and its sequence number: a sum of
+// per-word mixes, so any order of summation gives it
+__host__ __device__ inline unsigned int ctl_mix(unsigned int w, unsigned int i) {
+  return (w ^ (i * 0x9E3779B9u)) * (2u * i + 1u);
+}
 
 struct Small {
   double H[kLd * kLd];     // V^T Op V
@@ -108,7 +118,10 @@ void small_chol(Small* d, int nb, int which, const double* G0, int ldg0, hipStre
 void small_rr_append(Small* d, int gc, int nb, int total, hipStream_t s);
 // the control step; host (may be null) is the device address of a pinned,
 // coherent host copy of d->ctl that the kernel fills at its end
-void small_control(Small* d, const CtlParams& p, hipStream_t s, Ctl* host = nullptr);
+// host: pinned host copy of the record; seqp (device address of a pinned
+// host word): receives seq after the record has been written
+void small_control(Small* d, const CtlParams& p, hipStream_t s, Ctl* host = nullptr,
+                   int* seqp = nullptr, int seq = 0);
 void small_rtr_accumulate(const double* C0, int ldc0, const double* C1, int total, int nb,
                           double* Cout, hipStream_t s);
 void small_final_rr(int k, double* G, int ldg, int descending, double* lam, double* Z, int ldz,
