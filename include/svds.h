@@ -127,7 +127,8 @@ typedef struct svds_opts {
                           /* (SVD of U^T A V) of the returned vectors       */
   int print_level;        /* 0 silent .. 5 per-iteration trace on stderr    */
   int profile;            /* 1: time the sparse products with HIP events on */
-                          /* `stream` and report them in svds_stats         */
+                          /* `stream` and report them in svds_stats (one    */
+                          /* product in four, to keep the events' cost low) */
   int autotune;           /* 1 (default): on the first solve of a prepared  */
                           /* matrix, time the SpMM launch shapes (row bins  */
                           /* or one launch with 1..64 lanes per row) for    */

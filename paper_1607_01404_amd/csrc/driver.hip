@@ -331,6 +331,10 @@ class Solver {
   int64_t gram_calls_ = 0;
   double gram_bytes_ = 0.0;
   double* gramP_ = nullptr;  // partial sums of the one-pass product (wsum x kMaxBlock)
+  // profile = 1: one call in kTimeEvery is bracketed by timing events (an
+  // event record between two kernels costs a few microseconds of idle time)
+  static constexpr uint64_t kTimeEvery = 4;
+  uint64_t spmm_seen_ = 0, gram_seen_ = 0;
   hipEvent_t pool_event() {
     if (evnext_ == evpool_.size()) {
       hipEvent_t e;
@@ -362,7 +366,9 @@ class Solver {
       if constexpr (std::is_same<TV, double>::value) spmm(Mx, nb, X, Y, s_);
       else spmm_f32(Mx, nb, X, Y, s_);
     };
-    if (!o_.profile) {
+    // both calls of every kTimeEvery-th pair (A then A^T, or the two halves
+    // of B) are timed
+    if (!o_.profile || ((spmm_seen_++ >> 1) % kTimeEvery) != 0) {
       run();
       return;
     }
@@ -390,7 +396,7 @@ class Solver {
   void timed_gram(int nb, const double* X, double* Z, int64_t ldz) {
     const GramPlan& G = M_->G;
     if (!gramP_) gramP_ = buf_.get<double>((size_t)G.wsum * kMaxBlock);
-    if (!o_.profile) {
+    if (!o_.profile || (gram_seen_++ % kTimeEvery) != 0) {
       gram_partial(A(), G, nb, X, gramP_, s_);
     } else {
       hipEvent_t a = pool_event(), b = pool_event();
