@@ -73,6 +73,8 @@ def test_struct_layouts_match_header(tmp_path):
 def test_null_arguments_rejected(lib):
     assert lib.svds_matrix_create(None, None, None) == -1
     assert lib.svds_solve_prepared(None, 1, 0, 1e-10, None, None, None, 1, None, 1, None, None, None) == -1
+    assert lib.svds_matrix_normal(None, 4, None, None, 1, None, None) == -1
+    assert lib.svds_matrix_spmm(None, 0, 4, None, None, None) == -1
 
 
 def test_every_field_offset_matches_header(tmp_path):

@@ -145,3 +145,18 @@ def test_solve_through_the_one_pass_product(P, target):
         assert np.all(r <= 1.01e-10 * normA), r
         out[fused] = sig
     assert np.all(np.abs(out[1] - out[0]) <= 1e-9 * normA)
+
+
+def test_normal_product_arguments(P):
+    import torch
+    A = synth.banded_scaled(400, 200, seed=14)
+    _say("normal product argument errors", A.shape)
+    M = P.Matrix.from_scipy(A)
+    lib = P.load_library()
+    X = torch.zeros((200, 9), dtype=torch.float64, device="cuda")
+    Z = torch.empty_like(X)
+    for b in (0, 9):
+        rc = lib.svds_matrix_normal(M.handle, b, X.data_ptr(), Z.data_ptr(), 1, None, None)
+        assert rc == -1, (b, rc)
+    assert lib.svds_matrix_normal(M.handle, 4, None, Z.data_ptr(), 1, None, None) == -1
+    M.close()
