@@ -1,8 +1,8 @@
 """FP64 CPU oracle for the two-stage hybrid partial SVD (PHSVDS).
 
-TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check of the graft
-entry point and the CPU-baseline leg of the benchmark may import or run
-anything in this package.  The library (the HIP path and its Python binding)
+TEST INFRASTRUCTURE ONLY.  Only the test suite, smoke() in __graft_entry__.py
+and the CPU-baseline leg of the benchmark may import or run anything in this
+package.  The library (the HIP path and its Python binding)
 never imports it, and it imports nothing from the library.
 
 Parity unpinned: iteration and matrix-vector counts (they depend on the
