@@ -441,6 +441,20 @@ def main():
             "share_of_solve": ssec / el,
         },
     }
+    # the two other HBM-bound kernels that lead the solve's time, by the same
+    # event timing (one call in four): the basis projections and the residual
+    others = {}
+    for key, name in (("proj", "k_tsgemm_tn (first Gram-Schmidt projection and new H columns)"),
+                      ("resid", "k_residual (fused residual and norms)")):
+        c = sum(s[key + "_calls"] for s in stats)
+        sec_k = sum(s[key + "_seconds"] for s in stats)
+        by = sum(s[key + "_bytes"] for s in stats)
+        if c > 0 and sec_k > 0:
+            ach = by / sec_k / 1e9
+            others[name] = {"achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": ach / HBM_PEAK_GBS, "avg_call_us": sec_k / c * 1e6,
+                            "bytes_per_call": by / c, "timed_calls": c}
+    res["roofline_others"] = others
     if gram and not args.no_extras:
         res["two_product_comparison"] = two_product_run(P, torch, ip, ix, dv, m, n, k, w, args)
     if not args.no_extras:

@@ -185,6 +185,16 @@ typedef struct svds_stats {
                           /* 4*(rows+1) + 8*b*cols + (4 + 8*b)*wsum +       */
                           /* 20*nblk per call (wsum: the windows' summed    */
                           /* widths, nblk: row blocks)                      */
+  /* filled when opts.profile = 1 (zero otherwise), FP64 iterations: */
+  int64_t proj_calls;     /* basis projections timed (the first Gram-      */
+                          /* Schmidt pass and the new H columns; the kernel */
+                          /* without its partial-sum reduction)             */
+  double proj_seconds;    /* their summed duration (HIP events)             */
+  double proj_bytes;      /* their algorithmic bytes: 8*N*(columns read)    */
+  int64_t resid_calls;    /* fused residual kernels timed (without their    */
+                          /* partial-sum reduction)                         */
+  double resid_seconds;   /* their summed duration (HIP events)             */
+  double resid_bytes;     /* their algorithmic bytes: 8*N*(2*g + nc)        */
 } svds_stats;
 
 /* Fill *opts with the defaults above.  Returns SVDS_OK or SVDS_ERR_ARG. */

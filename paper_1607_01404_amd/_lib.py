@@ -50,7 +50,10 @@ class Stats(C.Structure):
                 ("norm_A_used", C.c_double), ("spmm_calls", C.c_int64),
                 ("spmm_seconds", C.c_double), ("spmm_bytes", C.c_double),
                 ("inner_iters", C.c_int64), ("gram_calls", C.c_int64),
-                ("gram_seconds", C.c_double), ("gram_bytes", C.c_double)]
+                ("gram_seconds", C.c_double), ("gram_bytes", C.c_double),
+                ("proj_calls", C.c_int64), ("proj_seconds", C.c_double),
+                ("proj_bytes", C.c_double), ("resid_calls", C.c_int64),
+                ("resid_seconds", C.c_double), ("resid_bytes", C.c_double)]
 
     def to_dict(self):
         return {"nconv": self.nconv, "stage_exit": self.stage_exit,
@@ -62,7 +65,10 @@ class Stats(C.Structure):
                 "spmm_calls": self.spmm_calls, "spmm_seconds": self.spmm_seconds,
                 "spmm_bytes": self.spmm_bytes, "inner_iters": self.inner_iters,
                 "gram_calls": self.gram_calls, "gram_seconds": self.gram_seconds,
-                "gram_bytes": self.gram_bytes}
+                "gram_bytes": self.gram_bytes, "proj_calls": self.proj_calls,
+                "proj_seconds": self.proj_seconds, "proj_bytes": self.proj_bytes,
+                "resid_calls": self.resid_calls, "resid_seconds": self.resid_seconds,
+                "resid_bytes": self.resid_bytes}
 
 
 _lib = None

@@ -306,10 +306,12 @@ void ts_scale(double* T, int64_t ldt, int64_t N, int b, const double* Rinv, doub
               hipStream_t s);
 // fused residual for nc candidates: R = W Y - V Y diag(theta); per-candidate
 // sums (rows < nsplit | rows >= nsplit): ||r||^2, x.r, ||x||^2 each
+// (sums = nullptr: the partial sums stay in `partial` as [output][block] and
+// the caller reduces them).  Returns the number of blocks.
 template <typename TB>
-void ts_residual(const TB* V, const TB* W, int64_t ld, int64_t N, int64_t nsplit, int g,
-                 const double* Y, int64_t ldy, const double* theta, int nc, double* R,
-                 int64_t ldr, double* partial, double* sums, hipStream_t s);
+int ts_residual(const TB* V, const TB* W, int64_t ld, int64_t N, int64_t nsplit, int g,
+                const double* Y, int64_t ldy, const double* theta, int nc, double* R,
+                int64_t ldr, double* partial, double* sums, hipStream_t s);
 void pack_rows(const double* A, int64_t lda, const double* B, double beta, int64_t N, int b,
                double* compact, hipStream_t s);  // compact = A + beta*B (B may be null)
 void unpack_rows(const double* compact, int64_t N, int b, double* A, int64_t lda, hipStream_t s);

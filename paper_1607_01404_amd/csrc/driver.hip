@@ -317,24 +317,41 @@ class Solver {
   // record writes back and invalidates the caches, which both costs time and
   // hands the next kernel a cold L2), kept in a pool, and read back at the
   // solver's synchronisation points, after which they are reused.
+  // timed kernel classes: the SpMM, the one-pass product's partial sums, the
+  // basis projections of the FP64 stage-1 iteration and its residual
+  enum Timed { kTSpmm = 0, kTGram, kTProj, kTResid, kTKinds };
   struct TimedCall {
     hipEvent_t a, b;
-    bool gram;  // the one-pass A^T A product (else an SpMM)
+    int kind;
+  };
+  struct TimedAcc {
+    double seconds = 0.0, bytes = 0.0;
+    int64_t calls = 0;
+    uint64_t seen = 0;  // calls made, timed or not
   };
   std::vector<TimedCall> ev_;                          // recorded since the last harvest
   std::vector<hipEvent_t> evpool_;                     // every event created by this solve
   size_t evnext_ = 0;                                  // first unused event of the pool
-  double spmm_seconds_ = 0.0;
-  int64_t spmm_calls_ = 0;
-  double spmm_bytes_ = 0.0;
-  double gram_seconds_ = 0.0;
-  int64_t gram_calls_ = 0;
-  double gram_bytes_ = 0.0;
+  TimedAcc acc_[kTKinds];
   double* gramP_ = nullptr;  // partial sums of the one-pass product (wsum x kMaxBlock)
   // profile = 1: one call in kTimeEvery is bracketed by timing events (an
   // event record between two kernels costs a few microseconds of idle time)
   static constexpr uint64_t kTimeEvery = 4;
-  uint64_t spmm_seen_ = 0, gram_seen_ = 0;
+  // run(): the launches of one call of class `kind`; timed when its turn comes
+  template <class F>
+  void timed(int kind, double bytes, bool turn, F&& run) {
+    if (!o_.profile || !turn) {
+      run();
+      return;
+    }
+    hipEvent_t a = pool_event(), b = pool_event();
+    SVDS_HIP(hipEventRecord(a, s_));
+    run();
+    SVDS_HIP(hipEventRecord(b, s_));
+    ev_.push_back(TimedCall{a, b, kind});
+    acc_[kind].bytes += bytes;
+  }
+  bool turn(int kind) { return (acc_[kind].seen++ % kTimeEvery) == 0; }
   hipEvent_t pool_event() {
     if (evnext_ == evpool_.size()) {
       hipEvent_t e;
@@ -349,13 +366,8 @@ class Solver {
       float ms = 0.f;
       SVDS_HIP(hipEventSynchronize(e.b));
       SVDS_HIP(hipEventElapsedTime(&ms, e.a, e.b));
-      if (e.gram) {
-        gram_seconds_ += ms * 1e-3;
-        ++gram_calls_;
-      } else {
-        spmm_seconds_ += ms * 1e-3;
-        ++spmm_calls_;
-      }
+      acc_[e.kind].seconds += ms * 1e-3;
+      ++acc_[e.kind].calls;
     }
     ev_.clear();
     evnext_ = 0;
@@ -368,27 +380,27 @@ class Solver {
     };
     // both calls of every kTimeEvery-th pair (A then A^T, or the two halves
     // of B) are timed
-    if (!o_.profile || ((spmm_seen_++ >> 1) % kTimeEvery) != 0) {
-      run();
-      return;
-    }
-    hipEvent_t a = pool_event(), b = pool_event();
-    SVDS_HIP(hipEventRecord(a, s_));
-    run();
-    SVDS_HIP(hipEventRecord(b, s_));
-    ev_.push_back(TimedCall{a, b, false});
+    const bool t = ((acc_[kTSpmm].seen++ >> 1) % kTimeEvery) == 0;
     const double sv = (double)sizeof(TV);
-    spmm_bytes_ += (double)Mx.nnz * (sv + 4.0) + 4.0 * (double)(Mx.rows + 1) +
-                   sv * nb * (double)(Mx.rows + Mx.cols);
+    timed(kTSpmm,
+          (double)Mx.nnz * (sv + 4.0) + 4.0 * (double)(Mx.rows + 1) +
+              sv * nb * (double)(Mx.rows + Mx.cols),
+          t, run);
   }
   void collect_profile(svds_stats* st) {
     harvest_events();
-    st->spmm_calls = spmm_calls_;
-    st->spmm_seconds = spmm_seconds_;
-    st->spmm_bytes = spmm_bytes_;
-    st->gram_calls = gram_calls_;
-    st->gram_seconds = gram_seconds_;
-    st->gram_bytes = gram_bytes_;
+    st->spmm_calls = acc_[kTSpmm].calls;
+    st->spmm_seconds = acc_[kTSpmm].seconds;
+    st->spmm_bytes = acc_[kTSpmm].bytes;
+    st->gram_calls = acc_[kTGram].calls;
+    st->gram_seconds = acc_[kTGram].seconds;
+    st->gram_bytes = acc_[kTGram].bytes;
+    st->proj_calls = acc_[kTProj].calls;
+    st->proj_seconds = acc_[kTProj].seconds;
+    st->proj_bytes = acc_[kTProj].bytes;
+    st->resid_calls = acc_[kTResid].calls;
+    st->resid_seconds = acc_[kTResid].seconds;
+    st->resid_bytes = acc_[kTResid].bytes;
   }
   // Z (n x nb) = A^T (A X) by the one-pass product, Z row-major (ldz = 0) or
   // column-major with leading dimension ldz; only the first kernel is timed
@@ -396,16 +408,8 @@ class Solver {
   void timed_gram(int nb, const double* X, double* Z, int64_t ldz) {
     const GramPlan& G = M_->G;
     if (!gramP_) gramP_ = buf_.get<double>((size_t)G.wsum * kMaxBlock);
-    if (!o_.profile || (gram_seen_++ % kTimeEvery) != 0) {
-      gram_partial(A(), G, nb, X, gramP_, s_);
-    } else {
-      hipEvent_t a = pool_event(), b = pool_event();
-      SVDS_HIP(hipEventRecord(a, s_));
-      gram_partial(A(), G, nb, X, gramP_, s_);
-      SVDS_HIP(hipEventRecord(b, s_));
-      ev_.push_back(TimedCall{a, b, true});
-      gram_bytes_ += gram_partial_bytes(A(), G, nb);
-    }
+    timed(kTGram, gram_partial_bytes(A(), G, nb), turn(kTGram),
+          [&] { gram_partial(A(), G, nb, X, gramP_, s_); });
     gram_combine(G, A().cols, nb, gramP_, Z, ldz, s_);
   }
   bool use_gram(int nb) const {
@@ -454,7 +458,10 @@ class Solver {
       Seg s1[3];
       for (int i = 0; i < n1; ++i) s1[i] = sb[i];
       s1[n1] = st;
-      tsgemm_tn(s1, n1 + 1, N_, T, ldt, nb, partial_, d_->C0, s_);
+      int nbp = 0;
+      timed(kTProj, 8.0 * (double)N_ * (total + nb), turn(kTProj),
+            [&] { nbp = tsgemm_tn_partial(s1, n1 + 1, N_, T, ldt, nb, partial_, s_); });
+      reduce_partials(partial_, nbp, (total + nb) * nb, d_->C0, s_);
       G0 = d_->C0 + total;
       ldg0 = total + nb;
       ldc0 = total + nb;
@@ -530,7 +537,10 @@ class Solver {
       unpack_rows(Wc_, N_, nb, Wcol, ld_, s_);
     }
     Seg sv{V_, gc_ + nb, ld_};
-    tsgemm_tn(&sv, 1, N_, Wcol, ld_, nb, partial_, d_->Hn, s_);
+    int nbp = 0;
+    timed(kTProj, 8.0 * (double)N_ * (gc_ + 2 * nb), turn(kTProj),
+          [&] { nbp = tsgemm_tn_partial(&sv, 1, N_, Wcol, ld_, nb, partial_, s_); });
+    reduce_partials(partial_, nbp, (gc_ + nb) * nb, d_->Hn, s_);
     small_h_append(d_, gc_, nb, s_);
     if (refined_) {
       // Z = W_new - tau T, orthogonalised against Q: new columns of Rr
@@ -605,8 +615,12 @@ class Solver {
   }
 
   void residual(int nc, int64_t nsplit) {
-    ts_residual(V_, W_, ld_, N_, nsplit, gc_, d_->Y, kLd, d_->theta, nc, R_, ld_, partial_,
-                d_->sums, s_);
+    int nbr = 0;
+    timed(kTResid, 8.0 * (double)N_ * (2 * gc_ + nc), turn(kTResid), [&] {
+      nbr = ts_residual(V_, W_, ld_, N_, nsplit, gc_, d_->Y, kLd, d_->theta, nc, R_, ld_,
+                        partial_, nullptr, s_);
+    });
+    reduce_partials(partial_, nbr, (nsplit >= N_ ? 1 : 6) * nc, d_->sums, s_);
   }
 
   // The control kernel writes its record into pinned host memory, then

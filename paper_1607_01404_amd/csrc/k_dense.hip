@@ -491,7 +491,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(
 // nsplit >= N: one sum per candidate (||r||^2 in sums[c]); otherwise the six
 // sums of the two halves in sums[q*nc + c]
 template <typename TB>
-void ts_residual(const TB* V, const TB* W, int64_t ld, int64_t N, int64_t nsplit, int g,
+int ts_residual(const TB* V, const TB* W, int64_t ld, int64_t N, int64_t nsplit, int g,
                  const double* Y, int64_t ldy, const double* theta, int nc, double* R,
                  int64_t ldr, double* partial, double* sums, hipStream_t s) {
   if (g > kMaxBasis) throw Error(SVDS_ERR_ARG, "residual: basis too large");
@@ -502,20 +502,21 @@ void ts_residual(const TB* V, const TB* W, int64_t ld, int64_t N, int64_t nsplit
     k_residual<NCC, 1, TB><<<grid, kThreads, 0, s>>>(V, W, ld, N, nsplit, g, Y, ldy, theta, nc,
                                                       R, ldr, partial);
     SVDS_LAUNCH_CHECK();
-    reduce_partials(partial, nb, nc, sums, s);
+    if (sums) reduce_partials(partial, nb, nc, sums, s);
   } else {
     constexpr int NCC = 8;
     dim3 grid(nb, (nc + NCC - 1) / NCC);
     k_residual<NCC, 6, TB><<<grid, kThreads, 0, s>>>(V, W, ld, N, nsplit, g, Y, ldy, theta, nc,
                                                       R, ldr, partial);
     SVDS_LAUNCH_CHECK();
-    reduce_partials(partial, nb, 6 * nc, sums, s);
+    if (sums) reduce_partials(partial, nb, 6 * nc, sums, s);
   }
+  return nb;
 }
-template void ts_residual<double>(const double*, const double*, int64_t, int64_t, int64_t, int,
+template int ts_residual<double>(const double*, const double*, int64_t, int64_t, int64_t, int,
                                   const double*, int64_t, const double*, int, double*, int64_t,
                                   double*, double*, hipStream_t);
-template void ts_residual<float>(const float*, const float*, int64_t, int64_t, int64_t, int,
+template int ts_residual<float>(const float*, const float*, int64_t, int64_t, int64_t, int,
                                  const double*, int64_t, const double*, int, double*, int64_t,
                                  double*, double*, hipStream_t);
 
