@@ -1054,8 +1054,8 @@ __device__ __forceinline__ double halves_res(const double* sums, int nc, int c, 
   return sqrt(fmax(t1, 0.0) + fmax(t2, 0.0));
 }
 
-__device__ void control_body(Small* d, const CtlParams& P) {
-  __shared__ int s_action, s_nblock, s_restart, s_reff, s_off, s_peff, s_lock;
+__device__ void control_body(Small* d, const CtlParams& P, Ctl& C) {
+  __shared__ int s_action, s_nblock, s_restart, s_reff, s_off, s_peff, s_lock, s_bad;
   __shared__ int s_blk[kMaxBlock];
   __shared__ double Yr[kLd * kLs];
   __shared__ double M[kLd * kLs];
@@ -1066,6 +1066,11 @@ __device__ void control_body(Small* d, const CtlParams& P) {
   __shared__ bool conv[kKmax + 8], done[kKmax + 8];
   __shared__ double rn[kKmax + 8];
   __shared__ double mx_s;
+  {  // the record starts zeroed (C lives in LDS)
+    unsigned int* w = reinterpret_cast<unsigned int*>(&C);
+    for (int a = t; a < (int)(sizeof(Ctl) / sizeof(unsigned int)); a += kT) w[a] = 0u;
+  }
+  if (t == 0) s_bad = d->bad;
   for (int j = t; j < gc; j += kT) th_s[j] = d->theta[j];
   for (int j = t; j < (P.stage == 1 ? nc : 6 * nc); j += kT) sums_s[j] = d->sums[j];
   for (int j = t; j < nc; j += kT) {
@@ -1080,21 +1085,14 @@ __device__ void control_body(Small* d, const CtlParams& P) {
     if (t == 0) mx_s = mx;
   }
   __syncthreads();
-  __shared__ int s_bad;
-  if (t == 0) s_bad = d->bad;
-  __syncthreads();
   if (s_bad) {  // leave every state untouched: the host rolls the block back
     if (t == 0) {
-      d->ctl.action = kBreakdown;
-      d->ctl.bad = s_bad;
-      d->ctl.restart = 0;
-      d->ctl.nlockable = 0;
-      d->ctl.nblock = 0;
+      C.action = kBreakdown;
+      C.bad = s_bad;
     }
     return;
   }
   if (t == 0) {
-    Ctl& C = d->ctl;
     C.bad = 0;
     d->normop = fmax(d->normop, mx_s);
     const double nop = d->normop;
@@ -1381,8 +1379,8 @@ __device__ void control_body(Small* d, const CtlParams& P) {
     if (t == 0) {
       d->warm_g = P.refined ? -1 : nr;
       d->warm_diag = reff;
-      d->ctl.restart = 1;
-      d->ctl.nr = nr;
+      C.restart = 1;
+      C.nr = nr;
       if (action == kExpand) {
         d->nprev = nblock;
         d->gprev = nr;
@@ -1398,8 +1396,8 @@ __device__ void control_body(Small* d, const CtlParams& P) {
       }
     }
     if (t == 0) {
-      d->ctl.restart = 0;
-      d->ctl.nr = gc;
+      C.restart = 0;
+      C.nr = gc;
       if (action == kExpand) {
         d->nprev = nblock;
         d->gprev = gc;
@@ -1419,12 +1417,13 @@ __device__ void control_body(Small* d, const CtlParams& P) {
 // record once it carries seq and a matching checksum, before the kernel ends.
 __global__ __launch_bounds__(kT) void k_control(Small* d, CtlParams P, Ctl* host, int* seqp,
                                                int seq) {
-  control_body(d, P);
+  __shared__ Ctl rec;
+  control_body(d, P, rec);
   if (host) {
     __syncthreads();
     if (threadIdx.x < kWave) {
       constexpr int nw = (int)(offsetof(Ctl, seq) / sizeof(unsigned int));
-      const unsigned int* src = reinterpret_cast<const unsigned int*>(&d->ctl);
+      const unsigned int* src = reinterpret_cast<const unsigned int*>(&rec);
       unsigned int* dst = reinterpret_cast<unsigned int*>(host);
       unsigned int part = 0;
       for (int a = threadIdx.x; a < nw; a += kWave) {

@@ -81,7 +81,6 @@ struct Small {
   int eig_sweeps;
   double res_min;         // smallest candidate residual of the last control step
   double lockval[kKmax];  // stage 2: locked Ritz values
-  Ctl ctl;
 };
 
 // parameters of a control step (by value)
@@ -116,10 +115,10 @@ void small_extract(Small* d, int gc, int descending, int refined, hipStream_t s)
 void small_chol(Small* d, int nb, int which, const double* G0, int ldg0, hipStream_t s,
                 const double* partial = nullptr, int nblk = 0);
 void small_rr_append(Small* d, int gc, int nb, int total, hipStream_t s);
-// the control step; host (may be null) is the device address of a pinned,
-// coherent host copy of d->ctl that the kernel fills at its end
-// host: pinned host copy of the record; seqp (device address of a pinned
-// host word): receives seq after the record has been written
+// the control step: its decision record is built in LDS; host (may be null)
+// is the device address of a pinned, coherent host copy that the kernel
+// fills at its end; seqp (device address of a pinned host word) receives
+// seq after the record has been written
 void small_control(Small* d, const CtlParams& p, hipStream_t s, Ctl* host = nullptr,
                    int* seqp = nullptr, int seq = 0);
 void small_rtr_accumulate(const double* C0, int ldc0, const double* C1, int total, int nb,
