@@ -126,9 +126,10 @@ typedef struct svds_opts {
   int two_sided_cleanup;  /* 1 (default): final two-sided Rayleigh-Ritz     */
                           /* (SVD of U^T A V) of the returned vectors       */
   int print_level;        /* 0 silent .. 5 per-iteration trace on stderr    */
-  int profile;            /* 1: time the sparse products with HIP events on */
-                          /* `stream` and report them in svds_stats (one    */
-                          /* product in four, to keep the events' cost low) */
+  int profile;            /* 1: time the sparse products, the basis         */
+                          /* projections and the residual with HIP events  */
+                          /* on `stream` and report them in svds_stats (one */
+                          /* call in four, to keep the events' cost low)    */
   int autotune;           /* 1 (default): on the first solve of a prepared  */
                           /* matrix, time the SpMM launch shapes (row bins  */
                           /* or one launch with 1..64 lanes per row) for    */
