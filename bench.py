@@ -1,5 +1,7 @@
 """Benchmark: time to the k requested singular triplets at eq. (res) residual
-<= 1e-10 ||A|| on one MI355X, plus the SpMM roofline and a CPU-oracle baseline.
+<= 1e-10 ||A|| on one MI355X, plus the roofline of the dominant sparse kernel
+(the one-pass A^T A product's partial sums where the matrix has a plan, else
+the SpMM) and a CPU-oracle baseline.
 
 A step is one complete svds_solve call (CSR checks, transpose, binning, both
 stages when needed, clean-up) on a synthetic matrix already resident in HBM.
