@@ -1556,10 +1556,16 @@ void build_gram_plan(svds_matrix* h, const MemMode& mm, hipStream_t s) {
   if (A.nnz <= 0 || nf <= 0) return;
   std::vector<int32_t> flo(nf), fhi(nf), fnz(nf);
   int32_t* d = static_cast<int32_t*>(svds::stream_alloc(sizeof(int32_t) * 3 * nf, s));
-  svds::gram_windows(A, nf, d, d + nf, d + 2 * nf, s);
-  SVDS_HIP(hipMemcpyAsync(flo.data(), d, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s));
-  SVDS_HIP(hipMemcpyAsync(fhi.data(), d + nf, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s));
-  SVDS_HIP(hipMemcpyAsync(fnz.data(), d + 2 * nf, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s));
+  try {
+    svds::gram_windows(A, nf, d, d + nf, d + 2 * nf, s);
+    SVDS_HIP(hipMemcpyAsync(flo.data(), d, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s));
+    SVDS_HIP(hipMemcpyAsync(fhi.data(), d + nf, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s));
+    SVDS_HIP(hipMemcpyAsync(fnz.data(), d + 2 * nf, sizeof(int32_t) * nf, hipMemcpyDeviceToHost,
+                            s));
+  } catch (...) {
+    svds::stream_free(d, s);
+    throw;
+  }
   svds::stream_free(d, s);
   SVDS_HIP(hipStreamSynchronize(s));
   for (int R = svds::kGramMaxRows; R >= F; R /= 2) {
@@ -1629,12 +1635,16 @@ int create_matrix(const svds_csr* A, svds_matrix** out, hipStream_t s, bool stre
   int64_t ends[2] = {0, 0};
   SVDS_HIP(hipMemcpyAsync(&ends[0], A->rowptr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   SVDS_HIP(hipMemcpyAsync(&ends[1], A->rowptr + A->m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  int* dflag = nullptr;
-  dflag = static_cast<int*>(svds::stream_alloc(sizeof(int), s));
-  SVDS_HIP(hipMemsetAsync(dflag, 0, sizeof(int), s));
-  svds::check_csr(*A, dflag, s);
+  int* dflag = static_cast<int*>(svds::stream_alloc(sizeof(int), s));
   int flag = 0;
-  SVDS_HIP(hipMemcpyAsync(&flag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+  try {
+    SVDS_HIP(hipMemsetAsync(dflag, 0, sizeof(int), s));
+    svds::check_csr(*A, dflag, s);
+    SVDS_HIP(hipMemcpyAsync(&flag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+  } catch (...) {
+    svds::stream_free(dflag, s);
+    throw;
+  }
   svds::stream_free(dflag, s);
   SVDS_HIP(hipStreamSynchronize(s));
   if (ends[0] != 0 || ends[1] != A->nnz || flag) throw Error(SVDS_ERR_CSR, "malformed CSR");
