@@ -10,6 +10,7 @@
 #include <mutex>
 #include <chrono>
 #include <thread>
+#include <utility>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -1513,6 +1514,21 @@ struct MemMode {
   }
 };
 
+// Device scratch on a stream, returned to the stream-ordered cache when the
+// scope ends, also when an error unwinds it.
+struct StreamScratch {
+  void* p;
+  hipStream_t s;
+  StreamScratch(size_t bytes, hipStream_t st) : p(svds::stream_alloc(bytes, st)), s(st) {}
+  ~StreamScratch() { svds::stream_free(p, s); }
+  StreamScratch(const StreamScratch&) = delete;
+  StreamScratch& operator=(const StreamScratch&) = delete;
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
 void free_csr(svds::Csr32& c, const MemMode& mm) {
   mm.release(c.rp);
   mm.release(c.ci);
@@ -1555,18 +1571,15 @@ void build_gram_plan(svds_matrix* h, const MemMode& mm, hipStream_t s) {
   const int64_t nf = (A.rows + F - 1) / F;
   if (A.nnz <= 0 || nf <= 0) return;
   std::vector<int32_t> flo(nf), fhi(nf), fnz(nf);
-  int32_t* d = static_cast<int32_t*>(svds::stream_alloc(sizeof(int32_t) * 3 * nf, s));
-  try {
+  {
+    const StreamScratch w(sizeof(int32_t) * 3 * nf, s);
+    int32_t* d = w.as<int32_t>();
     svds::gram_windows(A, nf, d, d + nf, d + 2 * nf, s);
     SVDS_HIP(hipMemcpyAsync(flo.data(), d, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s));
     SVDS_HIP(hipMemcpyAsync(fhi.data(), d + nf, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s));
     SVDS_HIP(hipMemcpyAsync(fnz.data(), d + 2 * nf, sizeof(int32_t) * nf, hipMemcpyDeviceToHost,
                             s));
-  } catch (...) {
-    svds::stream_free(d, s);
-    throw;
   }
-  svds::stream_free(d, s);
   SVDS_HIP(hipStreamSynchronize(s));
   for (int R = svds::kGramMaxRows; R >= F; R /= 2) {
     const int64_t k = R / F;
@@ -1635,17 +1648,13 @@ int create_matrix(const svds_csr* A, svds_matrix** out, hipStream_t s, bool stre
   int64_t ends[2] = {0, 0};
   SVDS_HIP(hipMemcpyAsync(&ends[0], A->rowptr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   SVDS_HIP(hipMemcpyAsync(&ends[1], A->rowptr + A->m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  int* dflag = static_cast<int*>(svds::stream_alloc(sizeof(int), s));
   int flag = 0;
-  try {
-    SVDS_HIP(hipMemsetAsync(dflag, 0, sizeof(int), s));
-    svds::check_csr(*A, dflag, s);
-    SVDS_HIP(hipMemcpyAsync(&flag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
-  } catch (...) {
-    svds::stream_free(dflag, s);
-    throw;
+  {
+    const StreamScratch f(sizeof(int), s);
+    SVDS_HIP(hipMemsetAsync(f.p, 0, sizeof(int), s));
+    svds::check_csr(*A, f.as<int>(), s);
+    SVDS_HIP(hipMemcpyAsync(&flag, f.p, sizeof(int), hipMemcpyDeviceToHost, s));
   }
-  svds::stream_free(dflag, s);
   SVDS_HIP(hipStreamSynchronize(s));
   if (ends[0] != 0 || ends[1] != A->nnz || flag) throw Error(SVDS_ERR_CSR, "malformed CSR");
 
@@ -1659,26 +1668,24 @@ int create_matrix(const svds_csr* A, svds_matrix** out, hipStream_t s, bool stre
     h->n = A->n;
     h->nnz = A->nnz;
     h->transposed = A->m < A->n;
-    svds::Csr32 a, at;
+    // A and its transpose, owned by the handle from their allocation on (so
+    // that destroy_matrix releases them if a later step fails); swapped
+    // into A_w and A_w^T at the end
+    svds::Csr32& a = h->A;
+    svds::Csr32& at = h->At;
     alloc_csr(a, A->m, A->n, A->nnz, mm);
     alloc_csr(at, A->n, A->m, A->nnz, mm);
     svds::copy_csr_arrays(*A, a, s);
-    int32_t* cursor = nullptr;
-    cursor = static_cast<int32_t*>(svds::stream_alloc(sizeof(int32_t) * (A->n + 1), s));
-    svds::transpose_csr(a, at, cursor, s);
-    svds::stream_free(cursor, s);
+    {
+      const StreamScratch cursor(sizeof(int32_t) * (A->n + 1), s);
+      svds::transpose_csr(a, at, cursor.as<int32_t>(), s);
+    }
     svds::build_bins(a, s);
     svds::build_bins(at, s);
     // FP32 copies of the values for the mixed-precision stage 1
     svds::to_fp32(a.val, a.val32, A->nnz, s);
     svds::to_fp32(at.val, at.val32, A->nnz, s);
-    if (h->transposed) {
-      h->A = at;
-      h->At = a;
-    } else {
-      h->A = a;
-      h->At = at;
-    }
+    if (h->transposed) std::swap(h->A, h->At);
     mm.alloc(&h->diagC, h->A.cols);
     svds::row_sqnorms(h->At, h->diagC, s);  // rows of A_w^T = columns of A_w
     build_gram_plan(h, mm, s);
@@ -1797,15 +1804,13 @@ int svds_matrix_normal(const svds_matrix* h, int b, const double* X, double* Z, 
     const bool one = fused && h->G.R > 0 && svds::gram_cheaper(A, h->G, b);
     if (used) *used = one ? 1 : 0;
     if (one) {
-      double* P = static_cast<double*>(svds::stream_alloc(sizeof(double) * h->G.wsum * b, s));
-      svds::gram_partial(A, h->G, b, X, P, s);
-      svds::gram_combine(h->G, A.cols, b, P, Z, 0, s);
-      svds::stream_free(P, s);
+      const StreamScratch P(sizeof(double) * h->G.wsum * b, s);
+      svds::gram_partial(A, h->G, b, X, P.as<double>(), s);
+      svds::gram_combine(h->G, A.cols, b, P.as<double>(), Z, 0, s);
     } else {
-      double* Y = static_cast<double*>(svds::stream_alloc(sizeof(double) * A.rows * b, s));
-      svds::spmm(A, b, X, Y, s);
-      svds::spmm(h->At, b, Y, Z, s);
-      svds::stream_free(Y, s);
+      const StreamScratch Y(sizeof(double) * A.rows * b, s);
+      svds::spmm(A, b, X, Y.as<double>(), s);
+      svds::spmm(h->At, b, Y.as<double>(), Z, s);
     }
     return SVDS_OK;
   });
