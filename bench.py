@@ -49,19 +49,19 @@ def counted_traffic(t, workload):
 
 WORKLOADS = {
     "banded_1e6x5e5_k10_smallest": dict(
-        gen=lambda: __import__("synth").config2(),
+        gen=lambda: __import__("synth").banded_workload(),
         desc="1,000,000 x 500,000 banded (64-wide band, 16 nnz/row, N(0,1)) x diag(10^U(-4,0)); "
              "k=10 smallest, block 4, basis 35, restart 14, tol 1e-10, Jacobi preconditioner",
         k=10, target="smallest", opts=dict(block_size=4, max_basis_size=35, min_restart_size=14,
                                            precond=1, seed=2002)),
     "powerlaw_2e6x1e6_k20_largest": dict(
-        gen=lambda: __import__("synth").config3(),
+        gen=lambda: __import__("synth").powerlaw_workload(),
         desc="2,000,000 x 1,000,000, power-law rows (mean 20, max 2000, exponent 2.1), N(0,1); "
              "k=20 largest, block 8, basis 35, restart 14, tol 1e-10",
         k=20, target="largest", opts=dict(block_size=8, max_basis_size=35, min_restart_size=14,
                                           seed=2003)),
     "random_2000x1000_k5_largest": dict(
-        gen=lambda: __import__("synth").config1(),
+        gen=lambda: __import__("synth").uniform_workload(),
         desc="2000 x 1000, 10 nnz/row uniform, N(0,1); k=5 largest, block 1, basis 15, tol 1e-10",
         k=5, target="largest", opts=dict(block_size=1, max_basis_size=15, min_restart_size=6,
                                          seed=2001)),
@@ -136,7 +136,7 @@ def _gen_batched(i):
 
 
 def batched_extra(P, torch, nprob):
-    """Config 4: nprob independent problems (rows U{5000..200000}, cols rows/2,
+    """Batched workload: nprob independent problems (rows U{5000..200000}, cols rows/2,
     8-12 nnz/row), k = 4 smallest each, block 8, solved by svds_solve_batched
     with 16 workers; the first 16 also one after another for comparison."""
     import multiprocessing as mp
@@ -180,7 +180,7 @@ def batched_extra(P, torch, nprob):
 
 
 def learned_extra(P, torch, full_seconds):
-    """Config 5: learned preconditioner trained on the GPU from residuals of
+    """Learned-preconditioner workload: a preconditioner trained on the GPU from residuals of
     Jacobi solves on eight 32x32 coefficient fields (seeds 5001-5008),
     evaluated against Jacobi and no preconditioning on a held-out field
     (seed 5000) at 128x128 and at the full 1024x1024 size (budget-capped)."""
@@ -190,7 +190,7 @@ def learned_extra(P, torch, full_seconds):
     t = time.perf_counter()
     sets = []
     for sd in range(5001, 5009):
-        M = P.Matrix.from_scipy(synth.config5(ng=32, seed=sd))
+        M = P.Matrix.from_scipy(synth.convdiff_workload(ng=32, seed=sd))
         R, st = P.collect_residuals(M, 10, "smallest", 1e-10, every=4, max_pairs=64, block_size=1,
                                     seed=1, precond=P.PC_JACOBI)
         sets.append((M, R))
@@ -214,7 +214,7 @@ def learned_extra(P, torch, full_seconds):
             ("block_jacobi_128", dict(precond=P.PC_BLOCKJACOBI, pc_block=128)),
             ("learned", dict(precond=P.PC_LEARNED, pc_model=params, pc_degree=degree))]
     for label, ng, cap in (("replica_128x128", 128, 60.0), ("full_1024x1024", 1024, full_seconds)):
-        B = synth.config5(ng=ng, seed=5000)
+        B = synth.convdiff_workload(ng=ng, seed=5000)
         MB = P.Matrix.from_scipy(B)
         res = {"shape": list(B.shape), "nnz": int(B.nnz), "max_seconds": cap}
         for name, kw in runs:
@@ -284,7 +284,7 @@ def condest_extra(P, torch, main_matrix, learned_params):
     import synth
     out = {}
     runs = [("banded_1e6x5e5_jacobi", main_matrix, dict(precond=P.PC_JACOBI, seed=7))]
-    B = synth.config5(ng=128, seed=5000)
+    B = synth.convdiff_workload(ng=128, seed=5000)
     MB = P.Matrix.from_scipy(B)
     runs.append(("convdiff_128x128_jacobi", MB, dict(precond=P.PC_JACOBI, seed=7)))
     runs.append(("convdiff_128x128_block_jacobi_128", MB,

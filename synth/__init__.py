@@ -7,14 +7,14 @@ sharing any code of the method itself.
 from .matrices import (  # noqa: F401
     to_csr,
     random_uniform_rows,
-    config1,
+    uniform_workload,
     banded_scaled,
-    config2,
+    banded_workload,
     powerlaw_rows,
-    config3,
+    powerlaw_workload,
     batched_problem,
     convection_diffusion,
-    config5,
+    convdiff_workload,
     prescribed_dense,
     prescribed_givens,
     one_per_row,

@@ -70,7 +70,7 @@ def random_uniform_rows(m, n, lengths, seed) -> sp.csr_matrix:
     return _csr_from_rows(m, n, lengths, cols, vals)
 
 
-def config1(seed=1001, m=2000, n=1000, nnz_per_row=10) -> sp.csr_matrix:
+def uniform_workload(seed=1001, m=2000, n=1000, nnz_per_row=10) -> sp.csr_matrix:
     """2000 x 1000, 10 nonzeros per row at uniform random columns, N(0,1)."""
     return random_uniform_rows(m, n, nnz_per_row, seed)
 
@@ -104,7 +104,7 @@ def banded_scaled(m, n, seed, band=64, per_row=16, log_lo=-4.0, log_hi=0.0):
     return _csr_from_rows(m, n, np.full(m, per_row), cols, vals)
 
 
-def config2(m=1_000_000, n=500_000, seed=1002):
+def banded_workload(m=1_000_000, n=500_000, seed=1002):
     """Banded (64 wide, 16 per row) times log-uniform column scaling in
     [1e-4, 1]; least-squares-like with tiny smallest-gap ratios."""
     return banded_scaled(m, n, seed)
@@ -132,7 +132,7 @@ def powerlaw_rows(m, n, seed, exponent=2.1, lmin=3.924, lmax=2000):
     return _csr_from_rows(m, n, lengths, cols, vals)
 
 
-def config3(m=2_000_000, n=1_000_000, seed=1003):
+def powerlaw_workload(m=2_000_000, n=1_000_000, seed=1003):
     """Power-law row lengths (mean 20, max 2000, exponent 2.1), N(0,1)."""
     return powerlaw_rows(m, n, seed)
 
@@ -201,7 +201,7 @@ def convection_diffusion(ng, seed, peclet=10.0, drop_rows=None):
     return A
 
 
-def config5(ng=1024, seed=5000, drop_rows=None):
+def convdiff_workload(ng=1024, seed=5000, drop_rows=None):
     """1024^2 convection-diffusion, Pe = 10, last 4 grid lines (4096 rows)
     dropped: 1,044,480 x 1,048,576."""
     if drop_rows is None:

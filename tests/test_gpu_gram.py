@@ -95,7 +95,7 @@ def test_normal_product_wide_and_tiny(P):
 
 def test_normal_product_falls_back_for_scattered_rows(P):
     import torch
-    A = synth.config3(m=20000, n=10000)
+    A = synth.powerlaw_workload(m=20000, n=10000)
     _say("normal product power-law rows (no plan)", A.shape)
     M = P.Matrix.from_scipy(A)
     X = np.random.default_rng(2).standard_normal((A.shape[1], 4))

@@ -48,7 +48,7 @@ def _theta(seed):
 
 @pytest.mark.parametrize("shape", ["wide", "tall"])
 def test_features_match_reference(P, shape):
-    A = synth.config5(ng=12, seed=5007)
+    A = synth.convdiff_workload(ng=12, seed=5007)
     if shape == "tall":
         A = A.T.tocsr()
     _say("lpc features", shape, A.shape)
@@ -63,7 +63,7 @@ def test_features_match_reference(P, shape):
 @pytest.mark.parametrize("degree", [1, 8, 15])
 def test_forward_matches_reference(P, degree):
     import torch
-    A = synth.config5(ng=12, seed=5008)
+    A = synth.convdiff_workload(ng=12, seed=5008)
     _say("lpc forward degree", degree)
     M = P.Matrix.from_scipy(A)
     op = L.Operator(A)
@@ -84,7 +84,7 @@ def test_forward_matches_reference(P, degree):
 
 def test_backward_matches_reference(P):
     import torch
-    A = synth.config5(ng=12, seed=5009)
+    A = synth.convdiff_workload(ng=12, seed=5009)
     _say("lpc backward")
     M = P.Matrix.from_scipy(A)
     op = L.Operator(A)
@@ -112,7 +112,7 @@ def test_backward_matches_reference(P):
 
 def test_loss_and_dcoef_match_reference(P):
     import torch
-    A = synth.config5(ng=12, seed=5010)
+    A = synth.convdiff_workload(ng=12, seed=5010)
     _say("lpc loss")
     M = P.Matrix.from_scipy(A)
     op = L.Operator(A)
@@ -138,7 +138,7 @@ def test_loss_and_dcoef_match_reference(P):
 def test_apply_matches_reference(P, shape):
     """K(R) in FP64 with the same (FP32-representable) coefficients."""
     import torch
-    A = synth.config5(ng=12, seed=5011)
+    A = synth.convdiff_workload(ng=12, seed=5011)
     if shape == "tall":
         A = A.T.tocsr()
     _say("lpc apply", shape)
@@ -176,7 +176,7 @@ def test_collect_residuals_match_oracle(P):
     """The residuals the GPU solve captures are the oracle's at the same
     iterations (same method readings, same counter-based start), up to the
     sign of the Ritz vector, which the small eigensolvers fix differently."""
-    A = synth.config5(ng=12, seed=5012)
+    A = synth.convdiff_workload(ng=12, seed=5012)
     _say("collect residuals 12x12 k=3 smallest every 2")
     M = P.Matrix.from_scipy(A)
     R, st = P.collect_residuals(M, 3, "smallest", 1e-10, every=2, max_pairs=4, block_size=1,
@@ -208,7 +208,7 @@ def test_trained_network_beats_jacobi_and_none(P):
     import torch
     sets = []
     for sd in (5001, 5002, 5003):
-        A = synth.config5(ng=16, seed=sd)
+        A = synth.convdiff_workload(ng=16, seed=sd)
         _say("training residuals seed", sd)
         M = P.Matrix.from_scipy(A)
         R, st = P.collect_residuals(M, 4, "smallest", 1e-10, every=3, max_pairs=60, block_size=1,
@@ -221,7 +221,7 @@ def test_trained_network_beats_jacobi_and_none(P):
     _say("training 80 steps")
     hist = P.lpc_train(sets, 8, 80, 1e-2, params)
     assert np.all(np.isfinite(hist)) and hist[-1] < 0.7 * hist[0], hist[[0, -1]]
-    B = synth.config5(ng=16, seed=5000)
+    B = synth.convdiff_workload(ng=16, seed=5000)
     ref = _grid_dense_sigma(B, 4)
     MB = P.Matrix.from_scipy(B)
     res = {}
@@ -250,7 +250,7 @@ def test_trained_network_beats_jacobi_and_none(P):
 def test_learned_stage2_composition(P, solver):
     """Stage 2 on B with the learned K in the composition [K A^T r_u; A K r_v],
     inside the JD correction's symmetric QMR or on the GD+k residuals."""
-    A = synth.config5(ng=12, seed=5013)
+    A = synth.convdiff_workload(ng=12, seed=5013)
     _say("learned stage 2 12x12 k=3 smallest", solver)
     params = P.lpc_init(seed=5)
     sig, U, V, rn, st = P.svds(A, 3, "smallest", 1e-10, block_size=1, seed=2, force_stage2=1,
@@ -263,7 +263,7 @@ def test_learned_stage2_composition(P, solver):
 
 
 def test_learned_requires_model(P):
-    A = synth.config5(ng=8, seed=5014)
+    A = synth.convdiff_workload(ng=8, seed=5014)
     _say("learned without model")
     with pytest.raises(P.SvdsError) as e:
         P.svds(A, 2, "smallest", 1e-10, precond=P.PC_LEARNED)

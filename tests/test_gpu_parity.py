@@ -57,7 +57,7 @@ def test_spmm_matches_scipy(P, b):
 
 def test_spmm_deterministic(P):
     import torch
-    A = synth.config3(m=20000, n=10000)
+    A = synth.powerlaw_workload(m=20000, n=10000)
     _say("spmm determinism", A.shape)
     M = P.Matrix.from_scipy(A)
     X = torch.from_numpy(np.random.default_rng(0).standard_normal((A.shape[1], 4))).cuda()
@@ -121,10 +121,10 @@ def _compare(A, sig, U, V, rn, st, ref_sig, tol, normA, rel=1e-10):
 
 @pytest.mark.parametrize("target", ["largest", "smallest"])
 @pytest.mark.parametrize("force2", [0, 1])
-def test_config1_against_oracle(P, target, force2):
-    A = synth.config1()
+def test_uniform_workload_against_oracle(P, target, force2):
+    A = synth.uniform_workload()
     normA = float(np.linalg.norm(A.toarray(), 2))
-    _say("solve config1", target, "force_stage2", force2)
+    _say("solve uniform_workload", target, "force_stage2", force2)
     sig, U, V, rn, st = P.svds(A, 5, target, 1e-10, max_basis_size=15, min_restart_size=6,
                                block_size=1, norm_A=normA, seed=11, force_stage2=force2)
     ref, Ur, Vr, rr, sr = oracle.svds(A, 5, target, 1e-10, max_basis=15, min_restart=6, block=1,
@@ -138,9 +138,9 @@ def test_config1_against_oracle(P, target, force2):
 
 @pytest.mark.parametrize("target", ["largest", "smallest"])
 def test_stage2_from_loose_stage1(P, target):
-    A = synth.config1()
+    A = synth.uniform_workload()
     normA = float(np.linalg.norm(A.toarray(), 2))
-    _say("solve config1 stage2 from stage1_tol 1e-4", target)
+    _say("solve uniform_workload stage2 from stage1_tol 1e-4", target)
     sig, U, V, rn, st = P.svds(A, 5, target, 1e-10, max_basis_size=15, min_restart_size=6,
                                norm_A=normA, seed=5, stage1_tol=1e-4)
     ref, _, _, _, _ = oracle.svds(A, 5, target, 1e-10, max_basis=15, min_restart=6, norm_A=normA,
@@ -171,9 +171,9 @@ def test_block_and_wide(P):
 
 
 def test_norm_estimate(P):
-    A = synth.config1()
+    A = synth.uniform_workload()
     normA = float(np.linalg.norm(A.toarray(), 2))
-    _say("solve config1 with internal norm estimate")
+    _say("solve uniform_workload with internal norm estimate")
     sig, U, V, rn, st = P.svds(A, 2, "largest", 1e-10, seed=3)
     assert abs(st["norm_A_used"] - normA) / normA < 1e-6
     assert st["converged"]
@@ -182,7 +182,7 @@ def test_norm_estimate(P):
 def test_malformed_csr_rejected(P):
     import torch
     _say("malformed csr")
-    A = synth.config1(m=50, n=20, nnz_per_row=3)
+    A = synth.uniform_workload(m=50, n=20, nnz_per_row=3)
     ip, ix, dv = P._lib.to_device(A)
     ix_bad = ix.clone()
     ix_bad[5] = 25  # out of range column
@@ -200,7 +200,7 @@ def test_malformed_csr_rejected(P):
 
 
 def test_deterministic_solve(P):
-    A = synth.config1()
+    A = synth.uniform_workload()
     _say("solve determinism")
     a = P.svds(A, 3, "smallest", 1e-10, seed=9, norm_A=8.0)
     b = P.svds(A, 3, "smallest", 1e-10, seed=9, norm_A=8.0)
@@ -225,12 +225,12 @@ def test_rank_deficient_breakdown_repair(P):
 
 
 @pytest.mark.parametrize("target", ["largest", "smallest"])
-def test_mixed_precision_config1(P, target):
+def test_mixed_precision_uniform_workload(P, target):
     """Mixed stage 1 (FP32 basis and SpMM, BF16 MFMA projections), FP64
     stage 2: same triplets as the FP64 oracle."""
-    A = synth.config1()
+    A = synth.uniform_workload()
     normA = float(np.linalg.norm(A.toarray(), 2))
-    _say("mixed config1", target)
+    _say("mixed uniform_workload", target)
     sig, U, V, rn, st = P.svds(A, 5, target, 1e-10, max_basis_size=15, min_restart_size=6,
                                norm_A=normA, seed=11, precision=P.MIXED)
     ref, _, _, _, _ = oracle.svds(A, 5, target, 1e-10, max_basis=15, min_restart=6, norm_A=normA,
@@ -242,7 +242,7 @@ def test_mixed_precision_config1(P, target):
 def test_mixed_precision_powerlaw_largest(P):
     """Power-law rows (mean 20, max 2000, exponent 2.1) at 20000 x 10000, k = 20
     largest, block 8: mixed and FP64 GPU results against the FP64 oracle."""
-    A = synth.config3(m=20000, n=10000)
+    A = synth.powerlaw_workload(m=20000, n=10000)
     normA = float(np.linalg.norm(A.toarray(), 2)) if A.shape[1] <= 4000 else None
     ref, _, _, _, sref = oracle.svds(A, 20, "largest", 1e-10, block=8, max_basis=35,
                                      min_restart=14, seed=3)
@@ -296,7 +296,7 @@ def test_autotuned_launch_shapes_agree(P):
     """The autotuner only changes launch shapes (lanes per row and binning),
     hence the summation order of the sparse products: results with and without
     it agree to the solve tolerance and both converge."""
-    A = synth.config3(m=20000, n=10000)
+    A = synth.powerlaw_workload(m=20000, n=10000)
     out = {}
     for tune in (0, 1):
         _say("powerlaw 20000x10000 k=10 largest b=8 autotune", tune)
@@ -324,9 +324,9 @@ def test_normal_method_stops_at_the_stage1_floor(P):
 
 
 def test_augmented_method_largest(P):
-    A = synth.config1()
+    A = synth.uniform_workload()
     normA = float(np.linalg.norm(A.toarray(), 2))
-    _say("augmented method config1 largest")
+    _say("augmented method uniform_workload largest")
     sig, U, V, rn, st = P.svds(A, 5, "largest", 1e-10, max_basis_size=15, min_restart_size=6,
                                norm_A=normA, seed=11, method=P.METHOD_AUGMENTED)
     ref, _, _, _, sr = oracle.svds(A, 5, "largest", 1e-10, max_basis=15, min_restart=6,
@@ -350,7 +350,7 @@ def test_condition_estimate(P):
 
 
 def test_method_argument_errors(P):
-    A = synth.config1(m=60, n=30, nnz_per_row=4)
+    A = synth.uniform_workload(m=60, n=30, nnz_per_row=4)
     _say("method argument errors")
     for kw in (dict(method=P.METHOD_AUGMENTED), dict(relative_tol=1), dict(method=7)):
         with pytest.raises(P.SvdsError) as e:
@@ -361,7 +361,7 @@ def test_method_argument_errors(P):
 @pytest.mark.parametrize("shape", ["wide", "tall"])
 def test_blockjacobi_apply_matches_oracle(P, shape):
     import torch
-    A = synth.config5(ng=12, seed=5015)
+    A = synth.convdiff_workload(ng=12, seed=5015)
     if shape == "tall":
         A = A.T.tocsr()
     M = P.Matrix.from_scipy(A)
@@ -381,7 +381,7 @@ def test_blockjacobi_solve(P):
     """Block Jacobi (blocks of 64 columns) on a 16 x 16 convection-diffusion
     field: dense-LAPACK singular values, fewer iterations than point Jacobi,
     and through the stage-2 composition."""
-    A = synth.config5(ng=16, seed=5001)
+    A = synth.convdiff_workload(ng=16, seed=5001)
     ref = np.sort(np.linalg.svd(A.toarray(), compute_uv=False))[:4]
     out = {}
     for name, kw in (("jacobi", dict(precond=P.PC_JACOBI)),
@@ -401,13 +401,13 @@ def test_jacobi_davidson_stage2(P, target):
     """The JD second stage (symmetric-QMR inner solver) reaches the dense-LAPACK
     values from a loose stage 1 in fewer outer iterations than GD+k, as the
     oracle's JD stage does."""
-    A = synth.config1()
+    A = synth.uniform_workload()
     normA = float(np.linalg.norm(A.toarray(), 2))
     s_all = np.linalg.svd(A.toarray(), compute_uv=False)
     ref = s_all[:5] if target == "largest" else np.sort(s_all)[:5]
     out = {}
     for name, solver in (("gdk", P.STAGE2_GDK), ("jd", P.STAGE2_JD)):
-        _say("config1 stage 2", name, target)
+        _say("uniform_workload stage 2", name, target)
         sig, U, V, rn, st = P.svds(A, 5, target, 1e-10, max_basis_size=15, min_restart_size=6,
                                    norm_A=normA, seed=5, stage1_tol=1e-4, stage2_solver=solver)
         assert st["converged"] and st["stage_exit"] == 2, (name, st)

@@ -12,7 +12,7 @@ import synth
 
 
 def _small():
-    return synth.config5(ng=8, seed=5003)  # 32 dropped rows: 32 x 64 -> work matrix A^T
+    return synth.convdiff_workload(ng=8, seed=5003)  # 32 dropped rows: 32 x 64 -> work matrix A^T
 
 
 def _random_theta(seed=0, scale=0.5):
@@ -209,7 +209,7 @@ def test_oracle_capture_and_training_beat_jacobi():
     problem; Adam steps lower the mean pair loss, and the trained
     preconditioner reaches the same singular values in fewer iterations than
     point Jacobi on a problem with another coefficient field."""
-    A = synth.config5(ng=16, seed=5001)
+    A = synth.convdiff_workload(ng=16, seed=5001)
     cap = {"every": 3, "max": 60}
     sig, U, V, rn, st = oracle.svds(A, 4, "smallest", 1e-10, block=1, seed=1, precond="jacobi",
                                     capture=cap)
@@ -230,7 +230,7 @@ def test_oracle_capture_and_training_beat_jacobi():
         losses.append(loss)
         L.adam_step(theta, L.backward(op, theta, cache, dc), m, v, step, 1e-2)
     assert losses[-1] < 0.7 * losses[0], losses
-    B = synth.config5(ng=16, seed=5000)
+    B = synth.convdiff_workload(ng=16, seed=5000)
     opb = L.Operator(B)
     cb, _ = L.forward(opb, theta, L.features(opb), deg)
     K = lambda Rb: L.apply(opb, cb, Rb, deg)

@@ -69,7 +69,7 @@ def test_augmented_spectrum():
 
 
 def test_jacobi_diag_is_column_norms():
-    A = synth.config1()
+    A = synth.uniform_workload()
     assert np.allclose(oracle.jacobi_diag(A), np.sum(A.toarray() ** 2, axis=0), rtol=1e-14)
 
 
@@ -96,7 +96,7 @@ def test_ortho_block_identity_and_breakdown():
 
 
 def test_norm_estimate():
-    A = synth.config1()
+    A = synth.uniform_workload()
     ops = P.Operators(A)
     est = oracle.estimate_norm(ops, seed=3)
     true = np.linalg.norm(A.toarray(), 2)
@@ -106,8 +106,8 @@ def test_norm_estimate():
 
 @pytest.mark.parametrize("target", ["largest", "smallest"])
 @pytest.mark.parametrize("force2", [False, True])
-def test_config1_against_lapack(target, force2):
-    A = synth.config1()
+def test_uniform_workload_against_lapack(target, force2):
+    A = synth.uniform_workload()
     _, s, _ = _lapack(A)
     ref = s[:5] if target == "largest" else np.sort(s)[:5]
     sig, U, V, rn, st = oracle.svds(A, 5, target, 1e-10, max_basis=15, min_restart=6, block=1,
@@ -122,7 +122,7 @@ def test_config1_against_lapack(target, force2):
 
 
 def test_sign_convention():
-    A = synth.config1()
+    A = synth.uniform_workload()
     _, _, V, _, _ = oracle.svds(A, 3, "largest", 1e-10, seed=1)
     for j in range(3):
         i = np.argmax(np.abs(V[:, j]))
@@ -180,7 +180,7 @@ def test_wide_matrix_uses_smaller_gram():
 
 @pytest.mark.parametrize("target", ["largest", "smallest"])
 def test_stage2_refines_loose_stage1(target):
-    A = synth.config1()
+    A = synth.uniform_workload()
     _, s, _ = _lapack(A)
     ref = s[:5] if target == "largest" else np.sort(s)[:5]
     out, U, V, rn, st = oracle.svds(A, 5, target, 1e-10, max_basis=15, min_restart=6, seed=5,
@@ -220,7 +220,7 @@ def test_default_stage2_solver():
 def test_stage1_bracket():
     """sigma_i in [sigma~ - sqrt(2)||r^C||/sigma~, sigma~] after stage 1
     (Section 3.1), with ||r^C|| = sigma~ ||A^T u - sigma~ v||."""
-    A = synth.config1()
+    A = synth.uniform_workload()
     _, s, _ = _lapack(A)
     ops = P.Operators(A)
     st = {"iters": [0, 0], "restarts": [0, 0], "resets": 0}
@@ -249,7 +249,7 @@ def test_null_space_vector_rejected():
 
 
 def test_budget_exhaustion_reports_not_converged():
-    A = synth.config1()
+    A = synth.uniform_workload()
     out, U, V, rn, st = oracle.svds(A, 5, "smallest", 1e-10, max_matvecs=60, seed=1)
     assert not st["converged"]
     assert st["nconv"] < 5
@@ -266,14 +266,14 @@ def test_fig1_example_shape():
 
 
 def test_deterministic():
-    A = synth.config1()
+    A = synth.uniform_workload()
     a = oracle.svds(A, 3, "smallest", 1e-10, seed=9)
     b = oracle.svds(A, 3, "smallest", 1e-10, seed=9)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
 
 
 def test_rejects_bad_arguments():
-    A = synth.config1()
+    A = synth.uniform_workload()
     with pytest.raises(ValueError):
         oracle.svds(A, 0, "largest")
     with pytest.raises(ValueError):
@@ -301,7 +301,7 @@ def test_normal_equations_alone_cannot_reach_small_residual_for_ill_conditioned(
 
 
 def test_augmented_alone_largest():
-    A = synth.config1(m=200, n=100, nnz_per_row=8)
+    A = synth.uniform_workload(m=200, n=100, nnz_per_row=8)
     s_ref = np.linalg.svd(A.toarray(), compute_uv=False)
     s, U, V, rn, st = oracle.svds(A, 3, "largest", 1e-10, block=1, seed=2, method="augmented")
     assert st["converged"] and st["stage_exit"] == 2 and st["matvecs"][0] == 0
@@ -328,7 +328,7 @@ def test_block_jacobi_pins():
     """Block size 1 is point Jacobi; blocks that cover whole independent
     column groups give the exact inverse of C; a block covering all columns
     is C^-1."""
-    A = synth.config1(m=120, n=50, nnz_per_row=6)
+    A = synth.uniform_workload(m=120, n=50, nnz_per_row=6)
     R = np.random.default_rng(1).standard_normal((50, 3))
     d = oracle.jacobi_diag(A)
     assert np.allclose(oracle.block_jacobi(A, 1)(R), R / d[:, None], rtol=1e-13)
@@ -346,7 +346,7 @@ def test_block_jacobi_pins():
 
 
 def test_block_jacobi_solve_beats_point_jacobi():
-    A = synth.config5(ng=16, seed=5001)
+    A = synth.convdiff_workload(ng=16, seed=5001)
     s_ref = np.sort(np.linalg.svd(A.toarray(), compute_uv=False))[:4]
     s1, _, _, _, st1 = oracle.svds(A, 4, "smallest", 1e-10, block=1, seed=1, precond="jacobi")
     s2, _, _, _, st2 = oracle.svds(A, 4, "smallest", 1e-10, block=1, seed=1,
@@ -428,7 +428,7 @@ def test_sqmr_with_preconditioner():
 
 @pytest.mark.parametrize("target", ["largest", "smallest"])
 def test_jacobi_davidson_stage2(target):
-    A = synth.config1()
+    A = synth.uniform_workload()
     normA = float(np.linalg.norm(A.toarray(), 2))
     s_all = np.linalg.svd(A.toarray(), compute_uv=False)
     ref = s_all[:5] if target == "largest" else np.sort(s_all)[:5]
