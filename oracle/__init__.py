@@ -19,6 +19,7 @@ from .phsvds import (  # noqa: F401
     ortho_block,
     jacobi_diag,
     block_jacobi,
+    exact_inverse,
     svds,
     svd_residuals,
     condest,

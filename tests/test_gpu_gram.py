@@ -8,6 +8,7 @@ import pytest
 import scipy.sparse as sp
 
 import synth
+from parity import assert_sigma_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -138,13 +139,15 @@ def test_solve_through_the_one_pass_product(P, target):
         assert st["converged"], st
         assert (st["gram_calls"] > 0) == bool(fused), st
         sig = sig.cpu().numpy()
-        assert np.all(np.abs(sig - ref) <= 1e-9 * normA), (sig, ref)
+        rn = rn.cpu().numpy()
+        assert_sigma_parity(sig, ref, s_all, rn, np.zeros(4), normA, f"one-pass {fused} vs LAPACK")
         Uc, Vc = U.cpu().numpy(), V.cpu().numpy()
         r = np.sqrt(np.sum((A @ Vc - Uc * sig) ** 2, axis=0) +
                     np.sum((A.T @ Uc - Vc * sig) ** 2, axis=0))
         assert np.all(r <= 1.01e-10 * normA), r
-        out[fused] = sig
-    assert np.all(np.abs(out[1] - out[0]) <= 1e-9 * normA)
+        out[fused] = (sig, rn)
+    assert_sigma_parity(out[1][0], out[0][0], s_all, out[1][1], out[0][1], normA,
+                        "one-pass vs two products")
 
 
 def test_normal_product_arguments(P):

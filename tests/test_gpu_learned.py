@@ -9,6 +9,7 @@ import pytest
 import oracle
 import oracle.learned as L
 import synth
+from parity import assert_sigma_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -223,6 +224,7 @@ def test_trained_network_beats_jacobi_and_none(P):
     assert np.all(np.isfinite(hist)) and hist[-1] < 0.7 * hist[0], hist[[0, -1]]
     B = synth.convdiff_workload(ng=16, seed=5000)
     ref = _grid_dense_sigma(B, 4)
+    spec = np.linalg.svd(B.toarray(), compute_uv=False)
     MB = P.Matrix.from_scipy(B)
     res = {}
     for name, kw in (("none", dict(precond=P.PC_NONE)), ("jacobi", dict(precond=P.PC_JACOBI)),
@@ -235,7 +237,8 @@ def test_trained_network_beats_jacobi_and_none(P):
         torch.cuda.synchronize()
         res[name] = (time.perf_counter() - t0, sum(st["iters"]), st)
         assert st["converged"], (name, st)
-        assert np.max(np.abs(sig.cpu().numpy() - ref) / ref) <= 1e-9, name
+        assert_sigma_parity(sig.cpu().numpy(), ref, spec, rn.cpu().numpy(), np.zeros(4),
+                            st["norm_A_used"], f"learned-gain {name} vs LAPACK")
         assert float(rn.max()) <= 1e-10 * st["norm_A_used"]
     print("[result]", {k: (round(v[0], 4), v[1]) for k, v in res.items()}, flush=True)
     assert res["learned"][1] < 0.5 * res["jacobi"][1]
@@ -258,7 +261,9 @@ def test_learned_stage2_composition(P, solver):
                                stage2_solver=P.STAGE2_JD if solver == "jd" else P.STAGE2_GDK)
     assert st["converged"] and st["stage_exit"] == 2 and st["iters"][1] >= 0
     ref = _grid_dense_sigma(A, 3)
-    assert np.max(np.abs(sig.cpu().numpy() - ref) / ref) <= 1e-9
+    assert_sigma_parity(sig.cpu().numpy(), ref, np.linalg.svd(A.toarray(), compute_uv=False),
+                        rn.cpu().numpy(), np.zeros(3), st["norm_A_used"],
+                        f"learned stage 2 {solver} vs LAPACK")
     assert float(rn.max()) <= 1e-10 * st["norm_A_used"]
 
 
