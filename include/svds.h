@@ -24,8 +24,14 @@
  *    synchronise that stream before they return.
  *  - No C++ exception crosses the ABI; every entry point returns an int
  *    status code (below).  svds_error_string() names it.
- *  - The library keeps no global state between calls; distinct streams may
- *    run distinct solves concurrently.
+ *  - Library state that outlives a call, all of it behind locks: per device,
+ *    one stream-ordered memory pool; a cache of released device blocks keyed
+ *    by (stream, size), at most 16 GiB for the process, reused by later calls
+ *    on the same stream (svds_stream_release() frees the blocks of a stream
+ *    before the caller destroys it); a table of SpMM launch shapes keyed by a
+ *    matrix signature (autotuner); and in each prepared matrix the launch
+ *    shapes its solves use per block width.  Distinct streams may run
+ *    distinct solves concurrently, also on one prepared matrix.
  */
 #ifndef SVDS_H
 #define SVDS_H
@@ -120,7 +126,8 @@ typedef struct svds_opts {
   uint64_t seed;          /* counter-based random vectors (initial block,   */
                           /* breakdown replacements)                        */
   int precision;          /* SVDS_FP64 or SVDS_MIXED                        */
-  int precond;            /* SVDS_PC_NONE or SVDS_PC_JACOBI                 */
+  int precond;            /* SVDS_PC_NONE, SVDS_PC_JACOBI,                  */
+                          /* SVDS_PC_BLOCKJACOBI or SVDS_PC_LEARNED         */
   int force_stage2;       /* 1: run stage 2 even when stage 1 met the       */
                           /* tolerance (testing)                            */
   int two_sided_cleanup;  /* 1 (default): final two-sided Rayleigh-Ritz     */
@@ -251,18 +258,47 @@ int svds_matrix_normal(const svds_matrix* h, int b, const double* X, double* Z, 
  * signed so that the largest-magnitude entry of v is positive.
  * opts may be NULL (defaults); stats may be NULL.  Returns SVDS_OK,
  * SVDS_NOT_CONVERGED (partial results as described above) or an error;
- * on error the outputs are unspecified.  Device workspace is stream-ordered
- * on `stream`; blocks released at the end of a call are kept by the library
- * (at most 16 GiB per process, never returned) and reused by later calls on
- * the same stream that ask for the same sizes. */
+ * on error the outputs are unspecified.  Device workspace (the prepared
+ * matrix of the call and the solver's arrays) is stream-ordered on `stream`;
+ * blocks released at the end of a call are kept by the library (at most
+ * 16 GiB per process) and reused by later calls on the same stream that ask
+ * for the same sizes.  A caller that supplies the workspace itself prepares
+ * the matrix (svds_matrix_create) and calls svds_solve_prepared. */
 int svds_solve(const svds_csr* A, int k, int target, double tol, const svds_opts* opts,
                double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, double* rnorm,
                svds_stats* stats, void* stream);
 
-/* Same on a prepared matrix (setup excluded from the call). */
+/* Bytes of device workspace that svds_solve_prepared needs on h for these
+ * k, target and options (the workspace that Section 3.3 lets the library
+ * allocate or the user supply): the search space V, W = Op V and their
+ * restart copies, the refined factor's Q for the smallest values, the
+ * locked and stage-1 vectors, the compact blocks, partial sums, the small
+ * FP64 state, and what the chosen precision, preconditioner, second stage and
+ * one-pass product add.  *bytes: host.  Launches nothing.  SVDS_ERR_ARG for
+ * options out of range (as the solve would return). */
+int svds_workspace_size(const svds_matrix* h, int k, int target, const svds_opts* opts,
+                        size_t* bytes);
+
+/* Same as svds_solve on a prepared matrix (setup excluded from the call).
+ * workspace: NULL, or a device array of workspace_bytes >= the value of
+ * svds_workspace_size for the same h, k, target and options (any alignment);
+ * the solver's arrays are then carved from it and no device memory is
+ * allocated for them.  Still allocated by the library: the autotuner's probe
+ * blocks on the first solve of a block width (none with opts.autotune = 0),
+ * the learned preconditioner's set-up temporaries (SVDS_PC_LEARNED), and
+ * three small pinned host records of the control step.  The workspace must
+ * not be used by anything else until the stream has passed the call.
+ * SVDS_ERR_ARG if it is too small. */
 int svds_solve_prepared(const svds_matrix* h, int k, int target, double tol,
                         const svds_opts* opts, double* sigma, double* U, int64_t ldu,
-                        double* V, int64_t ldv, double* rnorm, svds_stats* stats, void* stream);
+                        double* V, int64_t ldv, double* rnorm, void* workspace,
+                        size_t workspace_bytes, svds_stats* stats, void* stream);
+
+/* Free the device blocks the library keeps for reuse on `stream` (released
+ * by earlier calls on it).  Call before destroying a stream that ran solves;
+ * blocks kept for a destroyed stream would otherwise stay reserved until the
+ * 16 GiB cap stops the caching.  Enqueues stream-ordered frees on `stream`. */
+int svds_stream_release(void* stream);
 
 /* ---- batched solve --------------------------------------------------------- */
 /* nprob independent problems A[i] with the same k, target, tol and options;

@@ -44,4 +44,5 @@ from ._lib import (  # noqa: F401
     lpc_adam,
     lpc_train,
     collect_residuals,
+    stream_release,
 )

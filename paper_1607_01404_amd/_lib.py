@@ -98,7 +98,9 @@ def load_library():
     lib.svds_solve.argtypes = [C.POINTER(Csr), i32, i32, dbl, C.POINTER(Opts), vp, vp, i64, vp,
                                i64, vp, C.POINTER(Stats), vp]
     lib.svds_solve_prepared.argtypes = [vp, i32, i32, dbl, C.POINTER(Opts), vp, vp, i64, vp,
-                                        i64, vp, C.POINTER(Stats), vp]
+                                        i64, vp, vp, C.c_size_t, C.POINTER(Stats), vp]
+    lib.svds_workspace_size.argtypes = [vp, i32, i32, C.POINTER(Opts), C.POINTER(C.c_size_t)]
+    lib.svds_stream_release.argtypes = [vp]
     lib.svds_solve_batched.argtypes = [i32, vp, i32, i32, dbl, C.POINTER(Opts), vp, vp, vp, vp,
                                        vp, vp, vp, i32, vp]
     f32 = C.c_float
@@ -224,9 +226,35 @@ class Matrix:
                                                  _stream(stream)), "normal")
         return Z, used.value
 
-    def solve(self, k, target="largest", tol=1e-10, stream=None, **opts):
-        return _solve(lambda *a: load_library().svds_solve_prepared(self.handle, *a),
-                      self.m, self.n, k, target, tol, stream, opts)
+    def workspace_size(self, k, target="largest", **opts):
+        """Bytes of caller workspace a solve with these arguments needs
+        (svds_workspace_size)."""
+        tgt = _target(target)
+        o = opts_init(**opts)
+        nb = C.c_size_t(0)
+        _check(load_library().svds_workspace_size(self.handle, k, tgt, C.byref(o), C.byref(nb)),
+               "workspace_size")
+        return nb.value
+
+    def solve(self, k, target="largest", tol=1e-10, stream=None, workspace=None, **opts):
+        """svds_solve_prepared; workspace: None or a device tensor whose bytes
+        the solver's arrays are carved from."""
+        wp = _ptr(workspace) if workspace is not None else None
+        wb = workspace.numel() * workspace.element_size() if workspace is not None else 0
+
+        def call(k_, tgt, tol_, o, sig, U, ldu, V, ldv, rn, st, strm):
+            return load_library().svds_solve_prepared(self.handle, k_, tgt, tol_, o, sig, U, ldu,
+                                                      V, ldv, rn, wp, wb, st, strm)
+        return _solve(call, self.m, self.n, k, target, tol, stream, opts)
+
+
+def _target(target):
+    return {"largest": LARGEST, "smallest": SMALLEST}[target] if isinstance(target, str) else target
+
+
+def stream_release(stream=None):
+    """Free the device blocks the library keeps for `stream` (svds_stream_release)."""
+    _check(load_library().svds_stream_release(_stream(stream)), "stream_release")
 
 
 def _solve(call, m, n, k, target, tol, stream, opts):

@@ -3,9 +3,12 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
+#include <map>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -60,6 +63,8 @@ hipMemPool_t device_pool();
 // free (a stream-ordered free costs the host about 0.1 ms).
 void* stream_alloc(size_t bytes, hipStream_t s);
 void stream_free(void* p, hipStream_t s);
+// release every block the cache keeps for stream s (before s is destroyed)
+void stream_cache_drop(hipStream_t s);
 
 // stream-ordered device allocations released together at the end of a call
 template <typename T>
@@ -68,12 +73,34 @@ T* dalloc(size_t n, hipStream_t s) {
   return static_cast<T*>(stream_alloc(sizeof(T) * n, s));
 }
 
+// Device arrays of one call.  By default each comes from the stream-ordered
+// block cache and is released when the object ends.  With use_workspace()
+// they are carved, 256-byte aligned and in request order, from a caller's
+// workspace instead (nothing is allocated or released); with count_only set
+// nothing is handed out and `used` only sums the aligned sizes (the size
+// query of the caller's workspace).
 struct DeviceBuffers {
   std::vector<void*> ptrs;
   hipStream_t s;
+  char* base = nullptr;  // caller workspace, or null
+  size_t cap = 0;        // its size in bytes
+  size_t used = 0;       // bytes handed out from it (or counted)
+  bool count_only = false;
   explicit DeviceBuffers(hipStream_t st) : s(st) {}
+  void use_workspace(void* p, size_t bytes) {
+    base = static_cast<char*>(p);
+    cap = bytes;
+    used = 0;
+  }
   template <typename T>
   T* get(size_t n) {
+    if (base || count_only) {
+      const size_t off = (used + 255) & ~static_cast<size_t>(255);
+      used = off + sizeof(T) * n;
+      if (count_only) return nullptr;
+      if (used > cap) throw Error(SVDS_ERR_ARG, "workspace smaller than the solve needs");
+      return reinterpret_cast<T*>(base + off);
+    }
     T* p = dalloc<T>(n, s);
     ptrs.push_back(p);
     return p;
@@ -82,8 +109,6 @@ struct DeviceBuffers {
     for (void* p : ptrs) stream_free(p, s);
   }
 };
-
-
 
 constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kMaxBasis = 64;      // g <= 64 (small problems fit one workgroup)
@@ -206,6 +231,9 @@ constexpr int kGramMaxNnz = 2048;    // nonzeros per block (staged in LDS)
 constexpr int kGramMaxWidth = 1024;  // columns per window
 constexpr int kGramMinRows = 16;     // finest block the windows are measured at
 constexpr int kGramMaxRows = 128;    // tallest block
+// whether the one-pass product moves at most 90 % of the algorithmic bytes of
+// the two SpMMs for block width b (the rule of svds_matrix_normal)
+bool gram_cheaper(const Csr32& A, const GramPlan& G, int b);
 
 }  // namespace svds
 
@@ -217,6 +245,12 @@ struct svds_matrix {
   double* diagC = nullptr;         // diag(A_w^T A_w) (length A.cols)
   svds::GramPlan G;                // one-pass A_w^T A_w product (G.R = 0: none)
   int device = 0;
+  // launch shapes of the two products per (block width, FP32): tuned by the
+  // first solve that needs them and fixed from then on, so that every solve
+  // on the handle uses the same shapes (the arrays above are never written
+  // after preparation; the solvers work on copies of A and At)
+  mutable std::mutex shape_mu;
+  mutable std::map<std::pair<int, int>, std::array<int, 4>> shapes;
   // set when the arrays were allocated stream-ordered on `owner` (the
   // internal create/solve/destroy sequence of one svds_solve call); they are
   // then released with stream-ordered frees on the same stream

@@ -39,6 +39,18 @@ void cleanup_finish(int k, const double* s, const double* Yq, int ldy, const dou
                     int ldav, int descending, double* sig, double* P, double* Q, int ldk,
                     hipStream_t st);
 
+// the one-pass product (partial sums, then their per-column sums) against A
+// then A^T by two SpMMs, in algorithmic bytes; taken when it moves at most
+// 90 % of the two products' bytes
+bool gram_cheaper(const Csr32& A, const GramPlan& G, int b) {
+  const double fused = 13.0 * (double)A.nnz + 4.0 * (double)(A.rows + 1) + 8.0 * b * (double)A.cols +
+                       (4.0 + 8.0 * b) * (double)G.wsum + 20.0 * (double)G.nblk +
+                       8.0 * b * (double)G.wsum + (4.0 + 8.0 * b) * (double)A.cols;
+  const double two = 24.0 * (double)A.nnz + 4.0 * (double)(A.rows + A.cols + 2) +
+                     16.0 * b * (double)(A.rows + A.cols);
+  return fused <= 0.9 * two;
+}
+
 namespace {
 
 double now() {
@@ -57,16 +69,6 @@ double gram_partial_bytes(const Csr32& A, const GramPlan& G, int b) {
          (4.0 + 8.0 * b) * (double)G.wsum + 20.0 * (double)G.nblk;
 }
 
-// the one-pass product (partial sums, then their per-column sums) against A
-// then A^T by two SpMMs, in algorithmic bytes; taken when it moves at most
-// 90 % of the two products' bytes
-bool gram_cheaper(const Csr32& A, const GramPlan& G, int b) {
-  const double fused = gram_partial_bytes(A, G, b) + 8.0 * b * (double)G.wsum +
-                       (4.0 + 8.0 * b) * (double)A.cols;
-  const double two = 24.0 * (double)A.nnz + 4.0 * (double)(A.rows + A.cols + 2) +
-                     16.0 * b * (double)(A.rows + A.cols);
-  return fused <= 0.9 * two;
-}
 
 }  // namespace
 
@@ -141,13 +143,38 @@ void stream_free(void* p, hipStream_t s) {
   (void)hipFreeAsync(p, s);
 }
 
+void stream_cache_drop(hipStream_t s) {
+  BlockCache& c = block_cache();
+  std::vector<void*> drop;
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    for (auto it = c.free.begin(); it != c.free.end();) {
+      if (it->first.first != s) {
+        ++it;
+        continue;
+      }
+      for (void* p : it->second) {
+        drop.push_back(p);
+        c.cached -= it->first.second;
+        c.size.erase(p);
+      }
+      it = c.free.erase(it);
+    }
+  }
+  for (void* p : drop) (void)hipFreeAsync(p, s);
+}
+
 // ---------------------------------------------------------------------------
 // The solver state of one svds call
 // ---------------------------------------------------------------------------
 class Solver {
  public:
-  Solver(const svds_matrix* M, int k, int target, double tol, const svds_opts& o, hipStream_t s)
-      : M_(M), k_(k), target_(target), tol_(tol), o_(o), s_(s), buf_(s) {
+  // a, at: the solve's copies of the work matrix and its transpose with the
+  // FP64 launch shapes; a32, at32: the same with the FP32 shapes
+  Solver(const svds_matrix* M, const Csr32& a, const Csr32& at, const Csr32& a32,
+         const Csr32& at32, int k, int target, double tol, const svds_opts& o, hipStream_t s)
+      : M_(M), A_(a), At_(at), A32_(a32), At32_(at32), k_(k), target_(target), tol_(tol), o_(o),
+        s_(s), buf_(s) {
     m_ = M->A.rows;
     n_ = M->A.cols;
     largest_ = target == SVDS_LARGEST;
@@ -176,6 +203,24 @@ class Solver {
 
   int run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, double* rnorm,
           svds_stats* st);
+
+  // every device array of the solve, from `a` (the block cache, a caller's
+  // workspace, or a count of the bytes); no launch
+  void allocate(DeviceBuffers& a);
+  // bytes of a caller workspace that holds them
+  size_t workspace_bytes() {
+    DeviceBuffers c(s_);
+    c.count_only = true;
+    allocate(c);
+    return c.used + 256;  // room to align the workspace's start
+  }
+  // carve the arrays from a caller's workspace instead of the block cache
+  void use_workspace(void* p, size_t bytes) {
+    const uintptr_t a = ((uintptr_t)p + 255) & ~(uintptr_t)255;
+    const size_t skip = a - (uintptr_t)p;
+    if (bytes < skip) throw Error(SVDS_ERR_ARG, "workspace smaller than the solve needs");
+    buf_.use_workspace((void*)a, bytes - skip);
+  }
 
   // stage-1 residuals of the block's first target at every `every`-th
   // iteration (training pairs of the learned preconditioner)
@@ -262,6 +307,7 @@ class Solver {
 
   // ---- configuration
   const svds_matrix* M_;
+  const Csr32 A_, At_, A32_, At32_;  // descriptors with this solve's launch shapes
   int k_, target_;
   double tol_, tol1_;
   svds_opts o_;
@@ -303,6 +349,9 @@ class Solver {
   int seq_ = 0;             // last sequence number asked of the control kernel
   int* hbad_ = nullptr;     // pinned
   double* vec_ = nullptr;   // small device vectors (k-sized)
+  // stage-1 results handed to stage 2 and the clean-up
+  double *V1_ = nullptr, *U1_ = nullptr, *sig_ = nullptr, *rn1_ = nullptr, *taus_ = nullptr;
+  int* ok_ = nullptr;
   // mixed-precision stage 1: FP32 basis, FP64 work block, FP32 compact blocks
   float *V32_ = nullptr, *W32_ = nullptr, *Vt32_ = nullptr, *Wt32_ = nullptr;
   float *Tc32_ = nullptr, *Yc32_ = nullptr, *Wc32_ = nullptr;
@@ -310,8 +359,8 @@ class Solver {
   bool mixed_ = false;
 
   // ---- operators -----------------------------------------------------------
-  const Csr32& A() const { return M_->A; }
-  const Csr32& At() const { return M_->At; }
+  const Csr32& A() const { return A_; }
+  const Csr32& At() const { return At_; }
 
   // sparse product with optional event timing.  The events only time the
   // products: they are created without the system-scope fence (a default
@@ -408,7 +457,6 @@ class Solver {
   // (the partial sums, which read A)
   void timed_gram(int nb, const double* X, double* Z, int64_t ldz) {
     const GramPlan& G = M_->G;
-    if (!gramP_) gramP_ = buf_.get<double>((size_t)G.wsum * kMaxBlock);
     timed(kTGram, gram_partial_bytes(A(), G, nb), turn(kTGram),
           [&] { gram_partial(A(), G, nb, X, gramP_, s_); });
     gram_combine(G, A().cols, nb, gramP_, Z, ldz, s_);
@@ -634,7 +682,14 @@ class Solver {
     small_control(d_, p, s_, dctl_, dseq_, seq_);
     constexpr int nw = (int)(offsetof(Ctl, seq) / sizeof(unsigned int));
     Ctl c;
+    // after a short busy spin the poll yields its core (the batched solve runs
+    // many of these loops at once); a record that does not appear while the
+    // stream is still busy ends the solve after kPollLimit seconds
+    constexpr double kPollLimit = 120.0;
+    double deadline = 0.0;
     for (uint32_t spins = 1;; ++spins) {
+      if (spins > 2048) std::this_thread::yield();
+      else __builtin_ia32_pause();
       if (__atomic_load_n(hseq_, __ATOMIC_ACQUIRE) == seq_) {
         std::memcpy(&c, hctl_, sizeof(Ctl));
         if (c.seq == seq_) {
@@ -652,6 +707,10 @@ class Solver {
           throw Error(SVDS_ERR_HIP, "control record not written");
         }
         if (e != hipErrorNotReady) SVDS_HIP(e);
+        const double t = now();
+        if (deadline == 0.0) deadline = t + kPollLimit;
+        else if (t > deadline)
+          throw Error(SVDS_ERR_HIP, "control record not published while the stream stays busy");
       }
     }
     if (ev_.size() >= 64) harvest_events();  // the rest at collect_profile
@@ -704,8 +763,8 @@ class Solver {
     copy_cols_cvt<double, float>(Tb_, ld_, N_, nb, V32_ + gc_ * ld_, ld_, Tc32_, s_);
   }
   void append32(int nb) {
-    timed_spmm(A(), nb, (const float*)Tc32_, Yc32_);
-    timed_spmm(At(), nb, (const float*)Yc32_, Wc32_);
+    timed_spmm(A32_, nb, (const float*)Tc32_, Yc32_);
+    timed_spmm(At32_, nb, (const float*)Yc32_, Wc32_);
     mv_ += 2 * nb;
     float* Wcol = W32_ + gc_ * ld_;
     unpack_rows_f32(Wc32_, N_, nb, Wcol, ld_, s_);
@@ -958,22 +1017,6 @@ int Solver::stage2(const double* taus_h, double* V1, double* U1, double* sig, in
                    svds_stats* st) {
   stage_ = 2;
   jd_ = o_.stage2_solver == SVDS_STAGE2_JD;
-  if (jd_ && !jdXb_) {
-    const size_t blk = (size_t)ld_ * kMaxBlock;
-    jdXb_ = buf_.get<double>(blk);
-    jdR_ = buf_.get<double>(blk);
-    jdQ_ = buf_.get<double>(blk);
-    jdW_ = buf_.get<double>(blk);
-    jdD_ = buf_.get<double>(blk);
-    jdT_ = buf_.get<double>(blk);
-    jdC_ = buf_.get<double>((size_t)(kKmax + kMaxBlock) * kMaxBlock);
-    jdShift_ = buf_.get<double>(kMaxBlock);
-    jdN2_ = buf_.get<double>(kMaxBlock);
-    jdSig_ = buf_.get<double>(kMaxBlock);
-    jdRn2_ = buf_.get<double>(kMaxBlock);
-    jdRho_ = buf_.get<double>(kMaxBlock);
-    jdSt_ = buf_.get<JdCol>(kMaxBlock);
-  }
   N_ = n_ + m_;
   gc_ = 0;
   nlock_ = 0;
@@ -1327,11 +1370,7 @@ int Solver::stage1_mixed(double* V1, double* U1, double* sig, double* rn, double
 // pass of the network; its activations are freed right after)
 void Solver::setup_learned() {
   if (!o_.pc_model) throw Error(SVDS_ERR_ARG, "learned preconditioner without pc_model");
-  ldeg_ = o_.pc_degree > 0 ? o_.pc_degree : kLpcDefaultDegree;
-  if (ldeg_ > kLpcMaxDegree) throw Error(SVDS_ERR_ARG, "pc_degree out of range");
-  lpc_prepare(M_, lop_, buf_, s_);
-  lcoef_ = buf_.get<float>((size_t)n_ * kLpcCoef);
-  lpc_scratch(lop_, kMaxBlock, lsc_, buf_);
+  lpc_compute(lop_, s_);
   DeviceBuffers tmp(s_);
   float* feat = tmp.get<float>((size_t)n_ * kLpcNF);
   float* cache = tmp.get<float>((size_t)n_ * kLpcCacheRow);
@@ -1351,49 +1390,83 @@ void Solver::capture_residual(int64_t iters, const Ctl& c) {
   ++cap_->count;
 }
 
+void Solver::allocate(DeviceBuffers& a) {
+  const int64_t Nmax = m_ + n_;
+  ld_ = round_up(Nmax, 64);
+  const size_t basis = (size_t)ld_ * kGmax;
+  const size_t blk = (size_t)ld_ * kMaxBlock;
+  V_ = a.get<double>(basis);
+  W_ = a.get<double>(basis);
+  Vt_ = a.get<double>(basis);
+  Wt_ = a.get<double>(basis);
+  if (!largest_) {
+    Q_ = a.get<double>(basis);
+    Qt_ = a.get<double>(basis);
+  }
+  X_ = a.get<double>((size_t)ld_ * std::max(kKmax, kLd));
+  R_ = a.get<double>((size_t)ld_ * std::max(kKmax + 8, kLd));
+  Tc_ = a.get<double>(blk);
+  Yc_ = a.get<double>(blk);
+  Wc_ = a.get<double>(blk);
+  Zc_ = a.get<double>(blk);
+  partial_ = a.get<double>((size_t)2048 * 264 * kMaxBlock + 4096);
+  d_ = a.get<Small>(1);
+  vec_ = a.get<double>(16 * kLd * kLd);
+  V1_ = a.get<double>((size_t)ld_ * kKmax);
+  U1_ = a.get<double>((size_t)ld_ * kKmax);
+  sig_ = a.get<double>(kKmax);
+  rn1_ = a.get<double>(kKmax);
+  taus_ = a.get<double>(kKmax);
+  ok_ = a.get<int>(1);
+  if (o_.precision == SVDS_MIXED) {
+    V32_ = a.get<float>(basis);
+    W32_ = a.get<float>(basis);
+    Vt32_ = a.get<float>(basis);
+    Wt32_ = a.get<float>(basis);
+    Tc32_ = a.get<float>(blk);
+    Yc32_ = a.get<float>(blk);
+    Wc32_ = a.get<float>(blk);
+    Tb_ = a.get<double>(blk);
+  }
+  if (o_.fused_gram && M_->G.R > 0) gramP_ = a.get<double>((size_t)M_->G.wsum * kMaxBlock);
+  if (o_.precond == SVDS_PC_JACOBI) dinv_ = a.get<double>(n_);
+  if (o_.precond == SVDS_PC_LEARNED) {
+    ldeg_ = o_.pc_degree > 0 ? o_.pc_degree : kLpcDefaultDegree;
+    if (ldeg_ > kLpcMaxDegree) throw Error(SVDS_ERR_ARG, "pc_degree out of range");
+    lpc_alloc(M_, lop_, a);
+    lcoef_ = a.get<float>((size_t)n_ * kLpcCoef);
+    lpc_scratch(lop_, kMaxBlock, lsc_, a);
+  }
+  if (o_.precond == SVDS_PC_BLOCKJACOBI) {
+    bjnb_ = o_.pc_block > 0 ? o_.pc_block : 64;
+    bjK_ = a.get<double>((size_t)((n_ + bjnb_ - 1) / bjnb_) * bjnb_ * bjnb_);
+  }
+  if (o_.stage2_solver == SVDS_STAGE2_JD && o_.method != SVDS_METHOD_NORMAL) {
+    jdXb_ = a.get<double>(blk);
+    jdR_ = a.get<double>(blk);
+    jdQ_ = a.get<double>(blk);
+    jdW_ = a.get<double>(blk);
+    jdD_ = a.get<double>(blk);
+    jdT_ = a.get<double>(blk);
+    jdC_ = a.get<double>((size_t)(kKmax + kMaxBlock) * kMaxBlock);
+    jdShift_ = a.get<double>(kMaxBlock);
+    jdN2_ = a.get<double>(kMaxBlock);
+    jdSig_ = a.get<double>(kMaxBlock);
+    jdRn2_ = a.get<double>(kMaxBlock);
+    jdRho_ = a.get<double>(kMaxBlock);
+    jdSt_ = a.get<JdCol>(kMaxBlock);
+  }
+}
+
 int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, double* rnorm,
                 svds_stats* st) {
   std::memset(st, 0, sizeof(*st));
   const double t0 = now();
   run_t0_ = t0;
-  // ---- buffers
-  const int64_t Nmax = m_ + n_;
-  ld_ = round_up(Nmax, 64);
-  const size_t basis = (size_t)ld_ * kGmax;
-  V_ = buf_.get<double>(basis);
-  W_ = buf_.get<double>(basis);
-  Vt_ = buf_.get<double>(basis);
-  Wt_ = buf_.get<double>(basis);
-  if (!largest_) {
-    Q_ = buf_.get<double>(basis);
-    Qt_ = buf_.get<double>(basis);
-  }
-  X_ = buf_.get<double>((size_t)ld_ * std::max(kKmax, kLd));
-  R_ = buf_.get<double>((size_t)ld_ * std::max(kKmax + 8, kLd));
-  Tc_ = buf_.get<double>((size_t)ld_ * kMaxBlock);
-  Yc_ = buf_.get<double>((size_t)ld_ * kMaxBlock);
-  Wc_ = buf_.get<double>((size_t)ld_ * kMaxBlock);
-  Zc_ = buf_.get<double>((size_t)ld_ * kMaxBlock);
-  partial_ = buf_.get<double>((size_t)2048 * 264 * kMaxBlock + 4096);
-  d_ = buf_.get<Small>(1);
-  vec_ = buf_.get<double>(16 * kLd * kLd);
-  double* V1 = buf_.get<double>((size_t)ld_ * kKmax);
-  double* U1 = buf_.get<double>((size_t)ld_ * kKmax);
-  double* sig = buf_.get<double>(kKmax);
-  double* rn1 = buf_.get<double>(kKmax);
-  double* taus = buf_.get<double>(kKmax);
-  int* ok = buf_.get<int>(1);
+  allocate(buf_);
+  double *V1 = V1_, *U1 = U1_, *sig = sig_, *rn1 = rn1_, *taus = taus_;
+  int* ok = ok_;
   mixed_ = o_.precision == SVDS_MIXED;
-  if (mixed_) {
-    V32_ = buf_.get<float>(basis);
-    W32_ = buf_.get<float>(basis);
-    Vt32_ = buf_.get<float>(basis);
-    Wt32_ = buf_.get<float>(basis);
-    Tc32_ = buf_.get<float>((size_t)ld_ * kMaxBlock);
-    Yc32_ = buf_.get<float>((size_t)ld_ * kMaxBlock);
-    Wc32_ = buf_.get<float>((size_t)ld_ * kMaxBlock);
-    Tb_ = buf_.get<double>((size_t)ld_ * kMaxBlock);
-  }
   constexpr size_t kSeqOff = (sizeof(Ctl) + 63) / 64 * 64;
   SVDS_HIP(hipHostMalloc((void**)&hctl_, kSeqOff + 64, hipHostMallocMapped | hipHostMallocCoherent));
   SVDS_HIP(hipHostGetDevicePointer((void**)&dctl_, hctl_, 0));
@@ -1412,16 +1485,10 @@ int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, d
       (void)hipHostFree(j);
     }
   } pf{hctl_, hbad_, hjd_};
-  if (o_.precond == SVDS_PC_JACOBI) {
-    dinv_ = buf_.get<double>(n_);
+  if (o_.precond == SVDS_PC_JACOBI)
     invert_diag(M_->diagC, n_, dinv_, s_);  // 1/diag(C), with 1 where the column is empty
-  }
   if (o_.precond == SVDS_PC_LEARNED) setup_learned();
-  if (o_.precond == SVDS_PC_BLOCKJACOBI) {
-    bjnb_ = o_.pc_block > 0 ? o_.pc_block : 64;
-    bjK_ = buf_.get<double>((size_t)((n_ + bjnb_ - 1) / bjnb_) * bjnb_ * bjnb_);
-    bj_setup(M_, bjnb_, bjK_, s_);
-  }
+  if (o_.precond == SVDS_PC_BLOCKJACOBI) bj_setup(M_, bjnb_, bjK_, s_);
   SVDS_HIP(hipMemsetAsync(d_, 0, sizeof(Small), s_));
   // ---- ||A||
   if (o_.norm_A > 0) {
@@ -1709,15 +1776,49 @@ svds_opts default_opts() {
   return o;
 }
 
-int solve_prepared(const svds_matrix* h, int k, int target, double tol, const svds_opts* opts,
-                   double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, double* rnorm,
-                   svds_stats* stats, hipStream_t s, svds::Solver::Capture* cap = nullptr) {
-  if (!h || !sigma || !U || !V || !rnorm) throw Error(SVDS_ERR_ARG, "null argument");
+// Launch shapes of the products with A_w and A_w^T for block width b (FP32
+// products when fp32): the handle's table entry if a solve already fixed one,
+// else tuned on the copies a, at (or the rule of thumb when tune is false,
+// which is not stored) and published; when two solves tune at once, the first
+// to publish wins and both use its shapes.
+void launch_shapes(const svds_matrix* h, int b, bool fp32, bool tune, svds::Csr32& a,
+                   svds::Csr32& at, hipStream_t s) {
+  if (!tune) {
+    a.merged_bin = a.heuristic_bin;
+    a.unroll = a.heuristic_unroll;
+    at.merged_bin = at.heuristic_bin;
+    at.unroll = at.heuristic_unroll;
+    return;
+  }
+  const std::pair<int, int> key(b, fp32 ? 1 : 0);
+  auto apply = [&](const std::array<int, 4>& v) {
+    a.merged_bin = v[0];
+    a.unroll = v[1];
+    at.merged_bin = v[2];
+    at.unroll = v[3];
+  };
+  {
+    std::lock_guard<std::mutex> lk(h->shape_mu);
+    auto it = h->shapes.find(key);
+    if (it != h->shapes.end()) {
+      apply(it->second);
+      return;
+    }
+  }
+  svds::autotune_spmm(a, b, fp32, s);
+  svds::autotune_spmm(at, b, fp32, s);
+  std::lock_guard<std::mutex> lk(h->shape_mu);
+  auto ins = h->shapes.emplace(key, std::array<int, 4>{a.merged_bin, a.unroll, at.merged_bin,
+                                                       at.unroll});
+  apply(ins.first->second);
+}
+
+// options with their defaults and range checks
+svds_opts checked_opts(const svds_matrix* h, int k, int target, const svds_opts* opts) {
+  if (!h) throw Error(SVDS_ERR_ARG, "null argument");
   if (target != SVDS_LARGEST && target != SVDS_SMALLEST) throw Error(SVDS_ERR_ARG, "target");
-  if (!(tol > 0.0 && tol < 1.0)) throw Error(SVDS_ERR_ARG, "tol must be in (0, 1)");
   const int64_t mn = std::min(h->m, h->n);
   if (k < 1 || k > mn || k > svds::kKmax) throw Error(SVDS_ERR_ARG, "k out of range");
-  if (ldu < h->m || ldv < h->n) throw Error(SVDS_ERR_ARG, "leading dimension too small");
   svds_opts o = opts ? *opts : default_opts();
   if (o.precision != SVDS_FP64 && o.precision != SVDS_MIXED) throw Error(SVDS_ERR_ARG, "precision");
   if (o.precond != SVDS_PC_NONE && o.precond != SVDS_PC_JACOBI && o.precond != SVDS_PC_LEARNED &&
@@ -1736,30 +1837,29 @@ int solve_prepared(const svds_matrix* h, int k, int target, double tol, const sv
     throw Error(SVDS_ERR_ARG, "stage2_solver");
   if (o.relative_tol && o.method != SVDS_METHOD_NORMAL)
     throw Error(SVDS_ERR_ARG, "the relative stopping rule needs the normal-equations method");
+  return o;
+}
+
+int solve_prepared(const svds_matrix* h, int k, int target, double tol, const svds_opts* opts,
+                   double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, double* rnorm,
+                   void* workspace, size_t workspace_bytes, svds_stats* stats, hipStream_t s,
+                   svds::Solver::Capture* cap = nullptr) {
+  const svds_opts o = checked_opts(h, k, target, opts);
+  if (!sigma || !U || !V || !rnorm) throw Error(SVDS_ERR_ARG, "null argument");
+  if (!(tol > 0.0 && tol < 1.0)) throw Error(SVDS_ERR_ARG, "tol must be in (0, 1)");
+  if (ldu < h->m || ldv < h->n) throw Error(SVDS_ERR_ARG, "leading dimension too small");
   svds_stats local;
   svds_stats* st = stats ? stats : &local;
-  {
-    // launch shapes of the two sparse products for this block width
-    auto* mh = const_cast<svds_matrix*>(h);
-    const int b = o.block_size > 0 ? o.block_size : 1;
-    const bool fp32 = o.precision == SVDS_MIXED;
-    if (o.autotune) {
-      svds::autotune_spmm(mh->A, b, false, s);
-      svds::autotune_spmm(mh->At, b, false, s);
-      (void)fp32;
-    } else {
-      mh->A.merged_bin = mh->A.heuristic_bin;
-      mh->At.merged_bin = mh->At.heuristic_bin;
-      mh->A.unroll = mh->A.heuristic_unroll;
-      mh->At.unroll = mh->At.heuristic_unroll;
-      mh->A.tuned_b = mh->At.tuned_b = 0;
-    }
-  }
-  svds::Solver solver(h, k, target, tol, o, s);
+  const int b = o.block_size > 0 ? o.block_size : 1;
+  svds::Csr32 a = h->A, at = h->At, a32 = h->A, at32 = h->At;
+  launch_shapes(h, b, false, o.autotune != 0, a, at, s);
+  if (o.precision == SVDS_MIXED) launch_shapes(h, b, true, o.autotune != 0, a32, at32, s);
+  svds::Solver solver(h, a, at, a32, at32, k, target, tol, o, s);
   if (cap) {
     if (o.precision != SVDS_FP64) throw Error(SVDS_ERR_ARG, "residual capture needs FP64");
     solver.set_capture(cap);
   }
+  if (workspace) solver.use_workspace(workspace, workspace_bytes);
   return solver.run(sigma, U, ldu, V, ldv, rnorm, st);
 }
 
@@ -1829,10 +1929,30 @@ int svds_matrix_spmm(const svds_matrix* h, int trans, int b, const double* X, do
 
 int svds_solve_prepared(const svds_matrix* h, int k, int target, double tol,
                         const svds_opts* opts, double* sigma, double* U, int64_t ldu, double* V,
-                        int64_t ldv, double* rnorm, svds_stats* stats, void* stream) {
+                        int64_t ldv, double* rnorm, void* workspace, size_t workspace_bytes,
+                        svds_stats* stats, void* stream) {
   return guarded([&] {
-    return solve_prepared(h, k, target, tol, opts, sigma, U, ldu, V, ldv, rnorm, stats,
-                          (hipStream_t)stream);
+    return solve_prepared(h, k, target, tol, opts, sigma, U, ldu, V, ldv, rnorm, workspace,
+                          workspace_bytes, stats, (hipStream_t)stream);
+  });
+}
+
+int svds_workspace_size(const svds_matrix* h, int k, int target, const svds_opts* opts,
+                        size_t* bytes) {
+  return guarded([&] {
+    if (!bytes) throw Error(SVDS_ERR_ARG, "null argument");
+    const svds_opts o = checked_opts(h, k, target, opts);
+    // the launch shapes do not change the arrays: the handle's descriptors serve
+    svds::Solver solver(h, h->A, h->At, h->A, h->At, k, target, 0.5, o, nullptr);
+    *bytes = solver.workspace_bytes();
+    return SVDS_OK;
+  });
+}
+
+int svds_stream_release(void* stream) {
+  return guarded([&] {
+    svds::stream_cache_drop((hipStream_t)stream);
+    return SVDS_OK;
   });
 }
 
@@ -1848,8 +1968,8 @@ int svds_solve(const svds_csr* A, int k, int target, double tol, const svds_opts
       ~Guard() { destroy_matrix(h); }
     } g{h};
     const double t1 = svds::now();
-    int rc = solve_prepared(h, k, target, tol, opts, sigma, U, ldu, V, ldv, rnorm, stats,
-                            (hipStream_t)stream);
+    int rc = solve_prepared(h, k, target, tol, opts, sigma, U, ldu, V, ldv, rnorm, nullptr, 0,
+                            stats, (hipStream_t)stream);
     if (stats) stats->setup_seconds += t1 - t0;
     return rc;
   });
@@ -1904,6 +2024,8 @@ int svds_solve_batched(int nprob, const svds_csr* A, int k, int target, double t
       else (void)hipEventSynchronize(done);
       (void)hipEventDestroy(done);
     }
+    (void)hipStreamSynchronize(streams[w]);
+    svds::stream_cache_drop(streams[w]);  // blocks kept for a stream that ends here
     (void)hipStreamSynchronize(streams[w]);
     (void)hipStreamDestroy(streams[w]);
   }
@@ -2084,7 +2206,8 @@ int svds_collect_residuals(const svds_matrix* A, int k, int target, double tol,
     cap.max = max_pairs;
     cap.R = R;
     cap.ldr = ldr;
-    const int rc = solve_prepared(A, k, target, tol, opts, sig, U, A->m, V, A->n, rn, stats, s, &cap);
+    const int rc = solve_prepared(A, k, target, tol, opts, sig, U, A->m, V, A->n, rn, nullptr, 0,
+                                  stats, s, &cap);
     SVDS_HIP(hipStreamSynchronize(s));
     *npairs = cap.count;
     return rc;
@@ -2110,7 +2233,7 @@ int svds_condest(const svds_matrix* A, double rtol, const svds_opts* opts, doubl
     int worst = SVDS_OK;
     for (int t = 0; t < 2; ++t) {
       const int rc = solve_prepared(A, 1, t == 0 ? SVDS_LARGEST : SVDS_SMALLEST, rtol, &o, sig, U,
-                                    A->m, V, A->n, rn, stats ? &stats[t] : nullptr, s);
+                                    A->m, V, A->n, rn, nullptr, 0, stats ? &stats[t] : nullptr, s);
       if (rc < 0) return rc;
       worst = std::max(worst, rc);
       SVDS_HIP(hipMemcpyAsync(&h[t], sig, sizeof(double), hipMemcpyDeviceToHost, s));

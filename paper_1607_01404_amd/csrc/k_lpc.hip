@@ -610,15 +610,23 @@ LpcPsi lpc_psi(int degree) {
   return p;
 }
 
-void lpc_prepare(const svds_matrix* M, LpcOp& op, DeviceBuffers& buf, hipStream_t s) {
+void lpc_alloc(const svds_matrix* M, LpcOp& op, DeviceBuffers& buf) {
   op.A = &M->A;
   op.At = &M->At;
   op.diag = M->diagC;
   op.N = M->A.cols;
   op.mw = M->A.rows;
+  op.dh = buf.get<double>(op.N);
+  op.sinv = buf.get<float>(op.N);
+}
+
+void lpc_prepare(const svds_matrix* M, LpcOp& op, DeviceBuffers& buf, hipStream_t s) {
+  lpc_alloc(M, op, buf);
+  lpc_compute(op, s);
+}
+
+void lpc_compute(LpcOp& op, hipStream_t s) {
   const int64_t N = op.N, mw = op.mw;
-  op.dh = buf.get<double>(N);
-  op.sinv = buf.get<float>(N);
   DeviceBuffers tmp(s);
   double* u = tmp.get<double>(mw);
   double* v = tmp.get<double>(N);

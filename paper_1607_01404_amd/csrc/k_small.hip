@@ -1409,23 +1409,29 @@ __device__ void control_body(Small* d, const CtlParams& P, Ctl& C) {
 
 // the control step; with a non-null host record (pinned, coherent host memory
 // mapped for the device) the decision record is also written there with
-// ordinary vector stores, so the host reads it after the stream
-// synchronisation without a separate copy
-// Wavefront 0 copies the record to host memory with its sequence number and
-// a checksum of both; then, when seqp is given, lane 0 publishes seq with a
-// system-scope release store.  The host polls that word and accepts the
-// record once it carries seq and a matching checksum, before the kernel ends.
+// ordinary vector stores, so the host reads it without a separate copy.
+// Publication order: the lanes of wavefront 0 write the record's words and a
+// checksum of them; each lane then executes a system-scope release fence, so
+// that its own words are visible to the host before the workgroup barrier
+// completes; after the barrier thread 0 writes the sequence number and the
+// checksum and publishes the sequence number with a system-scope release
+// store.  A host that reads the published number therefore reads every word
+// of the same record.  (A release store orders only the storing lane's own
+// earlier stores: without the fences of the other lanes, words written by
+// lanes 1..63 could reach host memory after the sequence word, and a host
+// polling that word could take the new number with words of the previous
+// record.)  The host also checks the checksum before it accepts the record.
 __global__ __launch_bounds__(kT) void k_control(Small* d, CtlParams P, Ctl* host, int* seqp,
                                                int seq) {
   __shared__ Ctl rec;
   control_body(d, P, rec);
   if (host) {
     __syncthreads();
+    constexpr int nw = (int)(offsetof(Ctl, seq) / sizeof(unsigned int));
+    unsigned int part = 0;
     if (threadIdx.x < kWave) {
-      constexpr int nw = (int)(offsetof(Ctl, seq) / sizeof(unsigned int));
       const unsigned int* src = reinterpret_cast<const unsigned int*>(&rec);
       unsigned int* dst = reinterpret_cast<unsigned int*>(host);
-      unsigned int part = 0;
       for (int a = threadIdx.x; a < nw; a += kWave) {
         const unsigned int w = src[a];
         dst[a] = w;
@@ -1433,11 +1439,13 @@ __global__ __launch_bounds__(kT) void k_control(Small* d, CtlParams P, Ctl* host
       }
 #pragma unroll
       for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off, kWave);
-      if (threadIdx.x == 0) {
-        host->seq = seq;
-        host->sum = part + ctl_mix((unsigned int)seq, (unsigned int)nw);
-        if (seqp) __hip_atomic_store(seqp, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");  // system scope: this lane's words
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      host->seq = seq;
+      host->sum = part + ctl_mix((unsigned int)seq, (unsigned int)nw);
+      if (seqp) __hip_atomic_store(seqp, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
 }

@@ -4,10 +4,10 @@
 // over all rows in natural order with L = 1, 2, ..., 64 lanes per row; each
 // with 1, 2 or 4 nonzeros per lane per step.  Each
 // candidate is timed with HIP events on the caller's stream for the block
-// width the solve will use; the fastest is kept in the prepared matrix and in
-// a process-wide cache keyed by a matrix signature (rows, columns, mean and
-// maximum row-length bucket, block width, precision), so that matrices of the
-// same shape class skip the search.
+// width the solve will use; the fastest is returned in the caller's copy of
+// the matrix descriptor and kept in a process-wide cache keyed by a matrix
+// signature (rows, columns, mean and maximum row-length bucket, block width,
+// precision), so that matrices of the same shape class skip the search.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -39,8 +39,10 @@ Key signature(const Csr32& A, int b, bool fp32) {
 }
 }  // namespace
 
+// A is the caller's own copy of a prepared matrix's descriptor: only its
+// launch-shape fields are written.
 void autotune_spmm(Csr32& A, int b, bool fp32, hipStream_t s) {
-  if (A.tuned_b == b || A.rows == 0 || A.nnz == 0) return;
+  if (A.rows == 0 || A.nnz == 0) return;
   const Key key = signature(A, b, fp32);
   {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -62,32 +64,41 @@ void autotune_spmm(Csr32& A, int b, bool fp32, hipStream_t s) {
       for (int bn = 0; bn < kNumBins - 1; ++bn) cand.push_back({bn, u});
   }
   const size_t es = fp32 ? sizeof(float) : sizeof(double);
-  void *X = nullptr, *Y = nullptr;
-  X = stream_alloc(es * (size_t)A.cols * b, s);
-  Y = stream_alloc(es * (size_t)A.rows * b, s);
-  SVDS_HIP(hipMemsetAsync(X, 0, es * (size_t)A.cols * b, s));
-  hipEvent_t e0, e1;
-  SVDS_HIP(hipEventCreate(&e0));
-  SVDS_HIP(hipEventCreate(&e1));
+  // probe blocks and events, released also when a launch throws
+  struct Scratch {
+    void* p;
+    hipStream_t s;
+    Scratch(size_t bytes, hipStream_t st) : p(stream_alloc(bytes, st)), s(st) {}
+    ~Scratch() { stream_free(p, s); }
+  };
+  struct Event {
+    hipEvent_t e = nullptr;
+    Event() { SVDS_HIP(hipEventCreate(&e)); }
+    ~Event() { (void)hipEventDestroy(e); }
+  };
+  const Scratch X(es * (size_t)A.cols * b, s), Y(es * (size_t)A.rows * b, s);
+  SVDS_HIP(hipMemsetAsync(X.p, 0, es * (size_t)A.cols * b, s));
+  const Event e0, e1;
   std::pair<int, int> best{A.merged_bin, A.unroll};
   float best_ms = 1e30f;
   const bool verbose = std::getenv("SVDS_DEBUG") != nullptr;
+  Csr32 T = A;  // the candidate shape under test
   for (const auto& c : cand) {
-    A.merged_bin = c.first;
-    A.unroll = c.second;
+    T.merged_bin = c.first;
+    T.unroll = c.second;
     auto run = [&] {
-      if (fp32) spmm_f32(A, b, (const float*)X, (float*)Y, s);
-      else spmm(A, b, (const double*)X, (double*)Y, s);
+      if (fp32) spmm_f32(T, b, (const float*)X.p, (float*)Y.p, s);
+      else spmm(T, b, (const double*)X.p, (double*)Y.p, s);
     };
     run();  // warm-up
     float tmin = 1e30f;
     for (int rep = 0; rep < 3; ++rep) {
-      SVDS_HIP(hipEventRecord(e0, s));
+      SVDS_HIP(hipEventRecord(e0.e, s));
       run();
-      SVDS_HIP(hipEventRecord(e1, s));
-      SVDS_HIP(hipEventSynchronize(e1));
+      SVDS_HIP(hipEventRecord(e1.e, s));
+      SVDS_HIP(hipEventSynchronize(e1.e));
       float ms = 0.f;
-      SVDS_HIP(hipEventElapsedTime(&ms, e0, e1));
+      SVDS_HIP(hipEventElapsedTime(&ms, e0.e, e1.e));
       tmin = std::min(tmin, ms);
     }
     if (verbose)
@@ -98,15 +109,11 @@ void autotune_spmm(Csr32& A, int b, bool fp32, hipStream_t s) {
       best = c;
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  stream_free(X, s);
-  stream_free(Y, s);
   A.merged_bin = best.first;
   A.unroll = best.second;
   A.tuned_b = b;
   std::lock_guard<std::mutex> lk(g_mu);
-  g_cache[key] = best;
+  g_cache.emplace(key, best);  // the first result for a signature is kept
 }
 
 }  // namespace svds

@@ -76,6 +76,9 @@ struct LpcOp {
   double rho = 1.0;
 };
 void lpc_prepare(const svds_matrix* M, LpcOp& op, DeviceBuffers& buf, hipStream_t s);
+// the same in two parts: the operator's arrays (no launch), then their values
+void lpc_alloc(const svds_matrix* M, LpcOp& op, DeviceBuffers& buf);
+void lpc_compute(LpcOp& op, hipStream_t s);
 // features (N x 8, row-major)
 void lpc_features(const LpcOp& op, float* feat, hipStream_t s);
 // coefficients (N x 16, row-major) and the cache of the backward pass

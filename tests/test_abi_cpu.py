@@ -72,7 +72,13 @@ def test_struct_layouts_match_header(tmp_path):
 
 def test_null_arguments_rejected(lib):
     assert lib.svds_matrix_create(None, None, None) == -1
-    assert lib.svds_solve_prepared(None, 1, 0, 1e-10, None, None, None, 1, None, 1, None, None, None) == -1
+    assert lib.svds_solve_prepared(None, 1, 0, 1e-10, None, None, None, 1, None, 1, None, None, 0,
+                                   None, None) == -1
+    import ctypes as C
+    nb = C.c_size_t(7)
+    assert lib.svds_workspace_size(None, 1, 0, None, C.byref(nb)) == -1 and nb.value == 7
+    assert lib.svds_workspace_size(None, 1, 0, None, None) == -1
+    assert lib.svds_stream_release(None) == 0  # nothing kept for the default stream yet
     assert lib.svds_matrix_normal(None, 4, None, None, 1, None, None) == -1
     assert lib.svds_matrix_spmm(None, 0, 4, None, None, None) == -1
 
