@@ -250,6 +250,18 @@ int svds_matrix_spmm(const svds_matrix* h, int trans, int b, const double* X, do
 int svds_matrix_normal(const svds_matrix* h, int b, const double* X, double* Z, int fused,
                        int* used, void* stream);
 
+/* The product of svds_matrix_normal without any allocation, for callers that
+ * cannot allocate device memory (code under stream capture, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments, result and
+ * choice between the one-pass product and the two SpMMs, bit for bit; the
+ * scratch (the windows' partial sums, wsum x b doubles, or A_w X, rows x b
+ * doubles) lives in one static device array of 64 MiB per GPU that the
+ * process holds until it ends.  SVDS_ERR_ARG when the scratch would exceed
+ * 64 MiB.  Every call on a GPU shares that array: calls that overlap on one
+ * GPU (different streams, or host threads without ordering) race. */
+int svds_matrix_normal_noalloc(const svds_matrix* h, int b, const double* X, double* Z, int fused,
+                               int* used, void* stream);
+
 /* ---- solve ---------------------------------------------------------------- */
 /* k triplets of A (1 <= k <= min(m, n)), target SVDS_LARGEST/SVDS_SMALLEST,
  * 0 < tol < 1.  Outputs (device): sigma (k), U (m x k, ld ldu >= m),

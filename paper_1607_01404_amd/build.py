@@ -18,7 +18,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsvds_hip.so")
 
 SOURCES = ["k_setup.hip", "k_spmm.hip", "k_dense.hip", "k_mfma.hip", "k_small.hip", "k_final.hip",
-           "k_tune.hip", "k_lpc.hip", "k_bjac.hip", "k_jd.hip", "k_gram.hip", "driver.hip"]
+           "k_tune.hip", "k_lpc.hip", "k_bjac.hip", "k_jd.hip", "k_gram.hip", "driver.hip",
+           "noalloc.hip"]
 
 ARCH = os.environ.get("SVDS_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
