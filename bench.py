@@ -1,7 +1,8 @@
 """Benchmark: time to the k requested singular triplets at eq. (res) residual
 <= 1e-10 ||A|| on one MI355X, plus the roofline of the dominant sparse kernel
-(the one-pass A^T A product's partial sums where the matrix has a plan, else
-the SpMM) and a CPU-oracle baseline.
+(the one-pass A^T A product, its two kernels together, where the matrix has a
+plan, else the SpMM), the roofline of the whole solve, and the CPU oracle run
+to completion on the same matrix.
 
 A step is one complete svds_solve call (CSR checks, transpose, binning, both
 stages when needed, clean-up) on a synthetic matrix already resident in HBM.
@@ -33,9 +34,10 @@ SPMM_TRAFFIC = {"workload": "banded_1e6x5e5_k10_smallest", "bytes_per_launch": 2
                 "source": "paper_1607_01404_amd/csrc/k_spmm.hip", "sha256_prefix": "8d27654782fae0d0"}
 
 
-# the same for the partial-sum kernel of the one-pass A^T A product
+# the same for one product with C by the one-pass A^T A product: its partial-sum
+# kernel (283.5 MB) and its window combine (50.9 MB)
 # (profiles/gram_banded_1e6x5e5_b4_fp64_hbm_traffic.md)
-GRAM_TRAFFIC = {"workload": "banded_1e6x5e5_k10_smallest", "bytes_per_launch": 283.5e6,
+GRAM_TRAFFIC = {"workload": "banded_1e6x5e5_k10_smallest", "bytes_per_launch": 334.4e6,
                 "source": "paper_1607_01404_amd/csrc/k_gram.hip", "sha256_prefix": "f501ebefc0458d4d"}
 
 
@@ -72,10 +74,13 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(A, w, gpu_matvecs, seconds):
-    """The oracle, as it stands, on the same matrix, stopped after `seconds` of
-    wall time; its seconds per matrix-vector product scaled to the GPU solve's
-    matrix-vector count."""
+def cpu_baseline(A, w, gpu_sigma, gpu_matvecs, cap):
+    """The oracle, as it stands, on the same matrix with the same settings, run
+    to completion (stopped after `cap` seconds if it has not converged by then:
+    then its seconds per matrix-vector product are scaled to the GPU solve's
+    count).  Returns the baseline record and the largest relative difference
+    between the GPU's and the oracle's singular values."""
+    import numpy as np
     import oracle
     cores = len(os.sched_getaffinity(0))
     opts = dict(w["opts"])
@@ -83,16 +88,42 @@ def cpu_baseline(A, w, gpu_matvecs, seconds):
               block=opts.get("block_size"), seed=opts.get("seed", 0),
               precond="jacobi" if opts.get("precond") == 1 else "none")
     t0 = time.perf_counter()
-    sig, U, V, rn, st = oracle.svds(A, w["k"], w["target"], 1e-10, time_limit=seconds, **kw)
+
+    def progress(stage, it, g, lam, rn_, conv):  # a line every 50 iterations
+        if it % 50 == 0:
+            log(f"oracle stage {stage} iteration {it} converged {int(conv.sum())} "
+                f"({time.perf_counter() - t0:.0f} s)")
+
+    sig, U, V, rn, st = oracle.svds(A, w["k"], w["target"], 1e-10, time_limit=cap,
+                                    trace=progress, **kw)
     el = time.perf_counter() - t0
     mv = sum(st["matvecs"])
     s_per_mv = el / max(mv, 1)
     done = bool(st["converged"])
     value = el if done else s_per_mv * gpu_matvecs
-    sample = (f"oracle on the full matrix: {'converged' if done else 'stopped'} after {el:.1f} s "
-              f"and {mv} matrix-vector products ({s_per_mv * 1e3:.2f} ms each)"
+    sample = (f"the whole solve on the full matrix, same settings: "
+              f"{'converged' if done else 'stopped at the cap'} after {el:.1f} s and {mv} "
+              f"matrix-vector products ({s_per_mv * 1e3:.2f} ms each)"
               + ("" if done else f"; scaled to the GPU solve's {gpu_matvecs} products"))
-    return {"value": value, "unit": "s", "cores": cores, "kind": "oracle", "sample": sample}
+    rel = float(np.max(np.abs(np.asarray(gpu_sigma) - sig) / sig)) if done else None
+    return ({"value": value, "unit": "s", "cores": cores, "kind": "oracle", "sample": sample,
+             "time_to_solution": done, "oracle_iters": st["iters"],
+             "oracle_max_rnorm_over_normA": float(rn.max()) / st["norm_A_used"]}, rel)
+
+
+def no_precond_budget_run(P, torch, ip, ix, dv, m, n, w, budget):
+    """The same workload without a preconditioner (K = I) under a budget of
+    `budget` matrix-vector products: the residual it reaches."""
+    opts = dict(w["opts"], precond=0, max_matvecs=budget)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sig, U, V, rn, st = P.solve(ip, ix, dv, m, n, w["k"], w["target"], 1e-10, **opts)
+    torch.cuda.synchronize()
+    return {"seconds": time.perf_counter() - t0, "max_matvecs": budget,
+            "converged": bool(st["converged"]), "nconv": st["nconv"],
+            "matvecs": st["matvecs"], "iters": st["iters"], "stage_exit": st["stage_exit"],
+            "max_rnorm_over_normA": float(rn.max()) / st["norm_A_used"],
+            "min_rnorm_over_normA": float(rn.min()) / st["norm_A_used"]}
 
 
 def mixed_comparison(P, torch):
@@ -143,8 +174,11 @@ def batched_extra(P, torch, nprob):
     import numpy as np
     workers = max(1, min(16, len(os.sched_getaffinity(0))))
     t = time.perf_counter()
-    with mp.get_context("spawn").Pool(workers) as pool:
-        mats = pool.map(_gen_batched, range(nprob), chunksize=4)
+    if nprob > 32:
+        with mp.get_context("spawn").Pool(workers) as pool:
+            mats = pool.map(_gen_batched, range(nprob), chunksize=4)
+    else:  # small batches (and profiled runs) without worker processes
+        mats = [_gen_batched(i) for i in range(nprob)]
     gen = time.perf_counter() - t
     log(f"batched: generated {nprob} problems in {gen:.1f} s")
     dev = [P._lib.to_device(A) + A.shape for A in mats]
@@ -179,7 +213,7 @@ def batched_extra(P, torch, nprob):
             "workers": 16, "generation_seconds": gen}
 
 
-def learned_extra(P, torch, full_seconds):
+def learned_extra(P, torch, full_seconds, replica=True):
     """Learned-preconditioner workload: a preconditioner trained on the GPU from residuals of
     Jacobi solves on eight 32x32 coefficient fields (seeds 5001-5008),
     evaluated against Jacobi and no preconditioning on a held-out field
@@ -208,12 +242,13 @@ def learned_extra(P, torch, full_seconds):
                         "collect_seconds": collect, "train_seconds": train, "steps": 200,
                         "degree": degree, "loss_first": float(hist[0]), "loss_last": float(hist[-1])}}
     runs = [("none", dict(precond=P.PC_NONE)),
-            ("none_gdk", dict(precond=P.PC_NONE, stage2_solver=P.STAGE2_GDK)),
             ("jacobi", dict(precond=P.PC_JACOBI)),
             ("jacobi_gdk", dict(precond=P.PC_JACOBI, stage2_solver=P.STAGE2_GDK)),
             ("block_jacobi_128", dict(precond=P.PC_BLOCKJACOBI, pc_block=128)),
             ("learned", dict(precond=P.PC_LEARNED, pc_model=params, pc_degree=degree))]
-    for label, ng, cap in (("replica_128x128", 128, 60.0), ("full_1024x1024", 1024, full_seconds)):
+    sizes = ((("replica_128x128", 128, 60.0),) if replica else ()) + (
+        ("full_1024x1024", 1024, full_seconds),)
+    for label, ng, cap in sizes:
         B = synth.convdiff_workload(ng=ng, seed=5000)
         MB = P.Matrix.from_scipy(B)
         res = {"shape": list(B.shape), "nnz": int(B.nnz), "max_seconds": cap}
@@ -330,7 +365,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="banded_1e6x5e5_k10_smallest", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-seconds", type=float, default=600.0,
+                    help="cap of the oracle's solve (it normally converges well before)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed-precision, batched and learned-preconditioner extras "
@@ -339,6 +375,11 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--full-seconds", type=float, default=20.0,
                     help="time budget of each full-size convection-diffusion solve")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
+                    help="precision of the timed solves (mixed: FP32/BF16 stage 1, FP64 stage 2)")
+    ap.add_argument("--only", default=None,
+                    choices=["mixed", "batched", "learned", "learned_full", "methods", "condest"],
+                    help="run only this extra (for profiling) and print its record")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (scales the HBM byte "
                          "counters of a profiler run) and exit")
@@ -362,6 +403,25 @@ def main():
 
     import paper_1607_01404_amd as P
 
+    if args.only:
+        torch.cuda.set_device(0)
+        if args.only == "mixed":
+            out = mixed_comparison(P, torch)
+        elif args.only == "batched":
+            out = batched_extra(P, torch, max(args.batched, 16))
+        elif args.only in ("learned", "learned_full"):
+            out, _ = learned_extra(P, torch, args.full_seconds, replica=args.only == "learned")
+        elif args.only == "methods":
+            out = methods_extra(P, torch, 30.0)
+        else:
+            import synth
+            Ab = synth.banded_workload()
+            Mb = P.Matrix.from_scipy(Ab)
+            out = condest_extra(P, torch, Mb, None)
+            Mb.close()
+        print(json.dumps({"only": args.only, "record": out}), flush=True)
+        return
+
     w = WORKLOADS[args.workload]
     log("generating", args.workload)
     t = time.perf_counter()
@@ -371,7 +431,7 @@ def main():
     ip, ix, dv = P._lib.to_device(A)
     m, n = A.shape
     k = w["k"]
-    opts = dict(w["opts"], profile=1)
+    opts = dict(w["opts"], profile=1, precision=P.MIXED if args.precision == "mixed" else P.FP64)
     torch.cuda.synchronize()
 
     def step():
@@ -402,8 +462,9 @@ def main():
     ssec = sum(s[key + "_seconds"] for s in stats)
     sbytes = sum(s[key + "_bytes"] for s in stats)
     achieved = sbytes / ssec / 1e9 if ssec > 0 else 0.0
-    kernel = ("one-pass A^T A product, partial-sum kernel k_gram_partial (every stage-1 "
-              "product with C; the window combine runs after it)" if gram else
+    kernel = ("one-pass A^T A product: k_gram_partial then k_gram_combine, timed together "
+              "(every stage-1 product with C); bytes: the method's, A read once, X read "
+              "and Z written once" if gram else
               "binned CSR SpMM (A and A^T products of every iteration)")
     traffic = counted_traffic(GRAM_TRAFFIC if gram else SPMM_TRAFFIC, args.workload)
     res = {
@@ -417,10 +478,10 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32+bf16 stage 1, f64 stage 2",
         "data": "synthetic",
         "config": {"workload": w["desc"], "m": m, "n": n, "nnz": int(A.nnz), "k": k,
-                   "target": w["target"], "tol": 1e-10, "precision": "fp64"},
+                   "target": w["target"], "tol": 1e-10, "precision": args.precision},
         "converged": ok,
         "sigma": [float(x) for x in sig.cpu().numpy()],
         "max_rnorm_over_normA": float(rn.max()) / normA,
@@ -437,7 +498,9 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-scaled)",
+            "traffic_unit": ("bytes per product with C, both kernels (rocprofv3 FETCH_SIZE/"
+                             "WRITE_SIZE, copy-scaled)" if gram else
+                             "bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-scaled)"),
             "avg_call_us": ssec / max(calls, 1) * 1e6,
             "bytes_per_call": sbytes / max(calls, 1),
             # the solver times one call in four with events: these two
@@ -460,6 +523,15 @@ def main():
                             "frac": ach / HBM_PEAK_GBS, "avg_call_us": sec_k / c * 1e6,
                             "bytes_per_call": by / c, "timed_calls": c}
     res["roofline_others"] = others
+    # the whole solve: every counted kernel's algorithmic bytes over the solve's
+    # wall time (set-up, norm estimate and clean-up are in the time, not in the
+    # bytes, so this is a lower bound)
+    ab = sum(s_["alg_bytes"] for s_ in stats) / len(stats)
+    res["whole_solve_roofline"] = {
+        "bound": "hbm", "achieved": ab / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": ab / sec / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_solve": ab,
+        "counted": "sparse products, projections, updates, Cholesky QR passes, residuals, "
+                   "restarts and corrections of every iteration; not set-up or clean-up"}
     if gram and not args.no_extras:
         res["two_product_comparison"] = two_product_run(P, torch, ip, ix, dv, m, n, k, w, args)
     if not args.no_extras:
@@ -473,10 +545,15 @@ def main():
         Mmain = P.Matrix(ip, ix, dv, m, n)
         res["condition_estimate"] = condest_extra(P, torch, Mmain, params)
         Mmain.close()
+    if not args.no_extras:
+        log("no preconditioner under a budget ...")
+        res["no_preconditioner_budget"] = no_precond_budget_run(P, torch, ip, ix, dv, m, n, w,
+                                                                200000)
     if not args.no_cpu:
         gpu_mv = int(sum(st["matvecs"]))
         log("cpu baseline (oracle) ...")
-        res["cpu_baseline"] = cpu_baseline(A, w, gpu_mv, args.cpu_seconds)
+        res["cpu_baseline"], res["max_rel_sigma_err_vs_oracle"] = cpu_baseline(
+            A, w, res["sigma"], gpu_mv, args.cpu_seconds)
     print(json.dumps(res), flush=True)
 
 

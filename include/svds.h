@@ -186,13 +186,14 @@ typedef struct svds_stats {
   int64_t inner_iters;    /* JD second stage: symmetric-QMR steps (block    */
                           /* steps)                                         */
   /* filled when opts.profile = 1 (zero otherwise): */
-  int64_t gram_calls;     /* one-pass A^T A products timed (their first,    */
-                          /* partial-sum kernel)                            */
-  double gram_seconds;    /* its summed duration (HIP events)               */
-  double gram_bytes;      /* its algorithmic bytes: nnz*(8+4+1) +           */
-                          /* 4*(rows+1) + 8*b*cols + (4 + 8*b)*wsum +       */
-                          /* 20*nblk per call (wsum: the windows' summed    */
-                          /* widths, nblk: row blocks)                      */
+  int64_t gram_calls;     /* one-pass A^T A products timed (the partial-sum */
+                          /* kernel and the window combine together)        */
+  double gram_seconds;    /* their summed duration (HIP events)             */
+  double gram_bytes;      /* the method's bytes of those products: A read   */
+                          /* once, X read and Z written once:               */
+                          /* nnz*(8+4) + 4*(rows+1) + 16*b*cols per call    */
+                          /* (the plan's ranks, column pointers and window  */
+                          /* partial sums are not counted)                  */
   /* filled when opts.profile = 1 (zero otherwise), FP64 iterations: */
   int64_t proj_calls;     /* basis projections timed (the first Gram-      */
                           /* Schmidt pass and the new H columns; the kernel */
@@ -203,6 +204,14 @@ typedef struct svds_stats {
                           /* partial-sum reduction)                         */
   double resid_seconds;   /* their summed duration (HIP events)             */
   double resid_bytes;     /* their algorithmic bytes: 8*N*(2*g + nc)        */
+  double alg_bytes;       /* algorithmic bytes of every call of the         */
+                          /* iterations' streaming kernels (sparse          */
+                          /* products at the bytes above, projections,      */
+                          /* updates, Cholesky QR passes, residuals,        */
+                          /* restarts, corrections; a Gram-Schmidt second   */
+                          /* pass that the device skips is not counted);    */
+                          /* set-up, norm estimate, final Rayleigh-Ritz and */
+                          /* clean-up are not counted (always filled)       */
 } svds_stats;
 
 /* Fill *opts with the defaults above.  Returns SVDS_OK or SVDS_ERR_ARG. */

@@ -53,7 +53,8 @@ class Stats(C.Structure):
                 ("gram_seconds", C.c_double), ("gram_bytes", C.c_double),
                 ("proj_calls", C.c_int64), ("proj_seconds", C.c_double),
                 ("proj_bytes", C.c_double), ("resid_calls", C.c_int64),
-                ("resid_seconds", C.c_double), ("resid_bytes", C.c_double)]
+                ("resid_seconds", C.c_double), ("resid_bytes", C.c_double),
+                ("alg_bytes", C.c_double)]
 
     def to_dict(self):
         return {"nconv": self.nconv, "stage_exit": self.stage_exit,
@@ -68,7 +69,7 @@ class Stats(C.Structure):
                 "gram_bytes": self.gram_bytes, "proj_calls": self.proj_calls,
                 "proj_seconds": self.proj_seconds, "proj_bytes": self.proj_bytes,
                 "resid_calls": self.resid_calls, "resid_seconds": self.resid_seconds,
-                "resid_bytes": self.resid_bytes}
+                "resid_bytes": self.resid_bytes, "alg_bytes": self.alg_bytes}
 
 
 _lib = None

@@ -60,13 +60,12 @@ double now() {
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
-// algorithmic bytes of the one-pass product's partial-sum kernel: CSR rows
-// (row pointers, indices, values) with the one-byte ranks, the gathered X,
-// the column pointers and written partial sums of the windows, the block
-// descriptors
-double gram_partial_bytes(const Csr32& A, const GramPlan& G, int b) {
-  return 13.0 * (double)A.nnz + 4.0 * (double)(A.rows + 1) + 8.0 * b * (double)A.cols +
-         (4.0 + 8.0 * b) * (double)G.wsum + 20.0 * (double)G.nblk;
+// the method's bytes of one product Z = A^T (A X) on n x b blocks: A read
+// once (values, column indices, row pointers), X read and Z written once.
+// The one-pass product's own plan data (ranks, window column pointers, the
+// windows' partial sums) is overhead, not part of this count.
+double gram_method_bytes(const Csr32& A, int b) {
+  return 12.0 * (double)A.nnz + 4.0 * (double)(A.rows + 1) + 16.0 * b * (double)A.cols;
 }
 
 
@@ -241,6 +240,7 @@ class Solver {
   JdCol* jdSt_ = nullptr;
   JdCol* hjd_ = nullptr;  // pinned
   void jd_project(double* Z, int nb) {
+    count(N8() * (2 * nlock_ + 5 * nb));
     Seg q[2] = {Seg{X_, nlock_, ld_}, Seg{jdXb_, nb, ld_}};
     tsgemm_tn(q, 2, N_, Z, ld_, nb, partial_, jdC_, s_);
     ts_update(q, 2, N_, jdC_, nlock_ + nb, Z, ld_, nb, s_);
@@ -250,6 +250,7 @@ class Solver {
   // preconditioner); the Ritz vectors jdXb_ and shifts jdShift_ are set
   void jd_correct(double* T, int nb) {
     const bool pc = o_.precond != SVDS_PC_NONE;
+    count(N8() * nb * (3.0 + (pc ? 4.0 : 0.0) + 4.0));
     gather_precond(R_, ld_, d_->blk, nb, nullptr, N_, jdR_, ld_, s_);
     jd_project(jdR_, nb);
     jd_col_dots(jdR_, nullptr, ld_, N_, nb, partial_, jdN2_, s_);
@@ -264,6 +265,9 @@ class Solver {
     const int maxit = o_.jd_max_inner > 0 ? o_.jd_max_inner : 20;
     const double tol = o_.jd_inner_tol > 0.0 ? o_.jd_inner_tol : 0.1;
     for (int it = 0; it < maxit; ++it) {
+      // packing, the shifted product, the dots, the QMR step (and with a
+      // preconditioner its dots and continuation)
+      count(N8() * nb * (2.0 + 3.0 + 2.0 + 9.0 + (pc && it + 1 < maxit ? 5.0 : 0.0)));
       pack_rows(jdQ_, ld_, nullptr, 0.0, N_, nb, Tc_, s_);
       apply_op(Tc_, Wc_, nb);
       jd_shift(N_, nb, Wc_, jdQ_, ld_, jdShift_, jdW_, s_);
@@ -383,6 +387,11 @@ class Solver {
   std::vector<hipEvent_t> evpool_;                     // every event created by this solve
   size_t evnext_ = 0;                                  // first unused event of the pool
   TimedAcc acc_[kTKinds];
+  // algorithmic bytes of the streaming kernels of the iterations (every call:
+  // sparse products, projections, updates, residuals, restarts, corrections)
+  double algb_ = 0.0;
+  void count(double bytes) { algb_ += bytes; }
+  double N8() const { return 8.0 * (double)N_; }
   double* gramP_ = nullptr;  // partial sums of the one-pass product (wsum x kMaxBlock)
   // profile = 1: one call in kTimeEvery is bracketed by timing events (an
   // event record between two kernels costs a few microseconds of idle time)
@@ -422,6 +431,9 @@ class Solver {
     ev_.clear();
     evnext_ = 0;
   }
+  static double spmm_bytes(const Csr32& Mx, int nb) {
+    return (double)Mx.nnz * 12.0 + 4.0 * (double)(Mx.rows + 1) + 8.0 * nb * (double)(Mx.rows + Mx.cols);
+  }
   template <typename TV>
   void timed_spmm(const Csr32& Mx, int nb, const TV* X, TV* Y) {
     auto run = [&] {
@@ -432,10 +444,10 @@ class Solver {
     // of B) are timed
     const bool t = ((acc_[kTSpmm].seen++ >> 1) % kTimeEvery) == 0;
     const double sv = (double)sizeof(TV);
-    timed(kTSpmm,
-          (double)Mx.nnz * (sv + 4.0) + 4.0 * (double)(Mx.rows + 1) +
-              sv * nb * (double)(Mx.rows + Mx.cols),
-          t, run);
+    const double bytes = (double)Mx.nnz * (sv + 4.0) + 4.0 * (double)(Mx.rows + 1) +
+                         sv * nb * (double)(Mx.rows + Mx.cols);
+    count(bytes);
+    timed(kTSpmm, bytes, t, run);
   }
   void collect_profile(svds_stats* st) {
     harvest_events();
@@ -451,15 +463,19 @@ class Solver {
     st->resid_calls = acc_[kTResid].calls;
     st->resid_seconds = acc_[kTResid].seconds;
     st->resid_bytes = acc_[kTResid].bytes;
+    st->alg_bytes = algb_;
   }
   // Z (n x nb) = A^T (A X) by the one-pass product, Z row-major (ldz = 0) or
-  // column-major with leading dimension ldz; only the first kernel is timed
-  // (the partial sums, which read A)
+  // column-major with leading dimension ldz; both kernels (the partial sums,
+  // which read A, and their combine) are timed as one call
   void timed_gram(int nb, const double* X, double* Z, int64_t ldz) {
     const GramPlan& G = M_->G;
-    timed(kTGram, gram_partial_bytes(A(), G, nb), turn(kTGram),
-          [&] { gram_partial(A(), G, nb, X, gramP_, s_); });
-    gram_combine(G, A().cols, nb, gramP_, Z, ldz, s_);
+    const double bytes = gram_method_bytes(A(), nb);
+    count(bytes);
+    timed(kTGram, bytes, turn(kTGram), [&] {
+      gram_partial(A(), G, nb, X, gramP_, s_);
+      gram_combine(G, A().cols, nb, gramP_, Z, ldz, s_);
+    });
   }
   bool use_gram(int nb) const {
     return o_.fused_gram && M_->G.R > 0 && gram_cheaper(A(), M_->G, nb);
@@ -508,6 +524,7 @@ class Solver {
       for (int i = 0; i < n1; ++i) s1[i] = sb[i];
       s1[n1] = st;
       int nbp = 0;
+      count(N8() * (total + nb));
       timed(kTProj, 8.0 * (double)N_ * (total + nb), turn(kTProj),
             [&] { nbp = tsgemm_tn_partial(s1, n1 + 1, N_, T, ldt, nb, partial_, s_); });
       reduce_partials(partial_, nbp, (total + nb) * nb, d_->C0, s_);
@@ -518,6 +535,8 @@ class Solver {
     } else {
       tsgemm_tn(&st, 1, N_, T, ldt, nb, partial_, d_->G0, s_);
       if (total > 0) tsgemm_tn(sb, n1, N_, T, ldt, nb, partial_, d_->C0, s_);
+      // FP32 basis: both passes always run
+      count(N8() * nb + (total > 0 ? 2.0 * (4.0 * N_ * total + N8() * nb) : 0.0));
       G0 = d_->G0;
       ldg0 = nb;
       ldc0 = total;
@@ -526,11 +545,16 @@ class Solver {
       // second pass only where the device-side test asks for it (FP64 basis);
       // the FP32 basis of the mixed stage always takes both passes
       const int* sk = std::is_same<TB, double>::value ? &d_->skip2 : nullptr;
+      // the first update (the second pass, skipped on the device when the
+      // test says so, is not counted for the FP64 basis)
+      count((double)sizeof(TB) * N_ * total + 2.0 * N8() * nb);
+      if (!std::is_same<TB, double>::value) count((double)sizeof(TB) * N_ * total + 2.0 * N8() * nb);
       ts_update(sb, n1, N_, d_->C0, ldc0, T, ldt, nb, s_);
       tsgemm_tn(sb, n1, N_, T, ldt, nb, partial_, d_->C1, s_, sk);
       ts_update(sb, n1, N_, d_->C1, total, T, ldt, nb, s_, sk);
     }
     // Cholesky QR twice; the Cholesky kernels sum the Gram partial sums themselves
+    count(N8() * nb * (6.0 + (compact ? 1.0 : 0.0)));
     int nbk = tsgemm_tn_partial(&st, 1, N_, T, ldt, nb, partial_, s_);
     small_chol(d_, nb, 1, G0, ldg0, s_, partial_, nbk);
     ts_scale(T, ldt, N_, nb, d_->R1inv, nullptr, s_);
@@ -584,8 +608,10 @@ class Solver {
     } else {
       apply_op(Tc_, Wc_, nb);
       unpack_rows(Wc_, N_, nb, Wcol, ld_, s_);
+      count(2.0 * N8() * nb);
     }
     Seg sv{V_, gc_ + nb, ld_};
+    count(N8() * (gc_ + 2 * nb));
     int nbp = 0;
     timed(kTProj, 8.0 * (double)N_ * (gc_ + 2 * nb), turn(kTProj),
           [&] { nbp = tsgemm_tn_partial(&sv, 1, N_, Wcol, ld_, nb, partial_, s_); });
@@ -596,6 +622,7 @@ class Solver {
       double* Zcol = Q_ + gc_ * ld_;
       pack_rows(Wcol, ld_, Tcol, -tau_, N_, nb, Zc_, s_);
       unpack_rows(Zc_, N_, nb, Zcol, ld_, s_);
+      count(5.0 * N8() * nb);
       Seg sq{Q_, gc_, ld_};
       refined_ortho(Zcol, nb, &sq, gc_ > 0 ? 1 : 0);
       small_rr_append(d_, gc_, nb, gc_, s_);
@@ -620,6 +647,7 @@ class Solver {
   }
 
   void restart_basis(int nr) {
+    count((refined_ ? 3.0 : 2.0) * N8() * (gc_ + nr));
     ts_gemm_nn(V_, ld_, gc_, N_, d_->Yr, kLd, nr, Vt_, ld_, s_);
     ts_gemm_nn(W_, ld_, gc_, N_, d_->Yr, kLd, nr, Wt_, ld_, s_);
     std::swap(V_, Vt_);
@@ -665,6 +693,7 @@ class Solver {
 
   void residual(int nc, int64_t nsplit) {
     int nbr = 0;
+    count(N8() * (2 * gc_ + nc));
     timed(kTResid, 8.0 * (double)N_ * (2 * gc_ + nc), turn(kTResid), [&] {
       nbr = ts_residual(V_, W_, ld_, N_, nsplit, gc_, d_->Y, kLd, d_->theta, nc, R_, ld_,
                         partial_, nullptr, s_);
@@ -727,6 +756,15 @@ class Solver {
   // T (the first n_ rows of nb columns, leading dimension ld_) <- K T with
   // the preconditioner of C (point Jacobi, learned polynomial, block Jacobi)
   void apply_pc(double* T, int nb) {
+    const double n8 = 8.0 * (double)n_;
+    switch (o_.precond) {
+      case SVDS_PC_JACOBI: count(n8 * (2 * nb + 1)); break;
+      case SVDS_PC_BLOCKJACOBI: count(n8 * (bjnb_ + 2 * nb)); break;
+      case SVDS_PC_LEARNED:
+        count(ldeg_ * (spmm_bytes(A(), nb) + spmm_bytes(At(), nb) + 6.0 * n8 * nb));
+        break;
+      default: break;
+    }
     switch (o_.precond) {
       case SVDS_PC_JACOBI: scale_rows(T, ld_, n_, nb, dinv_, s_); break;
       case SVDS_PC_LEARNED: learned_apply(T, nb); break;
@@ -738,6 +776,7 @@ class Solver {
   // preconditioner for the stage-2 block: [K A^T r_u; A K r_v] (pseudo-inverse
   // of B with (A^T A)^-1 ~ K), or the identity
   void precond_stage2(double* T, int nb) {
+    count(2.0 * N8() * nb);
     gather_precond(R_, ld_, d_->blk, nb, nullptr, N_, T, ld_, s_);
     apply_pcB(T, nb);
   }
@@ -745,6 +784,7 @@ class Solver {
   // K_B [y_v; y_u] = [K A^T y_u; A K y_v] of the preconditioner K of C
   void apply_pcB(double* T, int nb) {
     if (o_.precond == SVDS_PC_NONE) return;
+    count(4.0 * N8() * nb + spmm_bytes(A(), nb) + spmm_bytes(At(), nb));
     apply_pc(T, nb);                                        // T_v <- K r_v
     pack_rows(T, ld_, nullptr, 0.0, n_, nb, Tc_, s_);       // K r_v (n x nb)
     pack_rows(T + n_, ld_, nullptr, 0.0, m_, nb, Yc_, s_);  // r_u (m x nb)
@@ -760,6 +800,7 @@ class Solver {
   // the orthonormal FP64 block Tb_ becomes V32[:, gc:gc+nb] and the FP32
   // row-major block for the sparse products
   void commit32(int nb) {
+    count(2.0 * N8() * nb);
     copy_cols_cvt<double, float>(Tb_, ld_, N_, nb, V32_ + gc_ * ld_, ld_, Tc32_, s_);
   }
   void append32(int nb) {
@@ -768,11 +809,13 @@ class Solver {
     mv_ += 2 * nb;
     float* Wcol = W32_ + gc_ * ld_;
     unpack_rows_f32(Wc32_, N_, nb, Wcol, ld_, s_);
+    count(N8() * nb + 4.0 * N_ * (gc_ + 2 * nb));
     proj_bf16x3(V32_, ld_, gc_ + nb, Wcol, ld_, nb, N_, partial_, d_->Hn, s_);
     small_h_append(d_, gc_, nb, s_);
     gc_ += nb;
   }
   void restart32(int nr) {
+    count(2.0 * 4.0 * N_ * (gc_ + nr));
     ts_gemm_nn(V32_, ld_, gc_, N_, d_->Yr, kLd, nr, Vt32_, ld_, s_);
     ts_gemm_nn(W32_, ld_, gc_, N_, d_->Yr, kLd, nr, Wt32_, ld_, s_);
     std::swap(V32_, Vt32_);
@@ -982,8 +1025,10 @@ int Solver::stage1(double* V1, double* U1, double* sig, double* rn, double* taus
     double* T = V_ + gc_ * ld_;
     if (nb == 0) {
       nb = b_;
+      count(N8() * nb);
       fill_random(T, ld_, N_, nb, o_.seed, kStreamBreak + (uint64_t)rand_count_++, 0, s_);
     } else {
+      count(N8() * (2 * nb + (o_.precond == SVDS_PC_JACOBI ? 1 : 0)));
       gather_precond(R_, ld_, d_->blk, nb, o_.precond == SVDS_PC_JACOBI ? dinv_ : nullptr, N_, T,
                      ld_, s_);
       if (o_.precond != SVDS_PC_JACOBI) apply_pc(T, nb);
@@ -1075,6 +1120,7 @@ int Solver::stage2(const double* taus_h, double* V1, double* U1, double* sig, in
     }
     if (c.nlockable > 0) {
       // x = V y for the converged prefix -> locked vectors
+      count(N8() * (gc_ + c.nlockable));
       ts_gemm_nn(V_, ld_, gc_, N_, d_->Y, kLd, c.nlockable, X_ + nlock_ * ld_, ld_, s_);
       nlock_ += c.nlockable;
     }
@@ -1103,6 +1149,7 @@ int Solver::stage2(const double* taus_h, double* V1, double* U1, double* sig, in
     const int nb = c.nblock;
     if (jd_) {
       // Ritz vectors of the block and the shifts, before a restart changes V
+      count(N8() * (gc_ + nb));
       ts_gemm_nn(V_, ld_, gc_, N_, d_->Y, kLd, nb, jdXb_, ld_, s_);
       if (refined_) {
         double sh[kMaxBlock];
@@ -1293,6 +1340,7 @@ int Solver::stage1_mixed(double* V1, double* U1, double* sig, double* rn, double
   int last_nb = 0;
   for (;;) {
     const int nc = std::min(gc_, k_ + b_);
+    count(4.0 * N_ * 2 * gc_ + N8() * nc);
     ts_residual(V32_, W32_, ld_, N_, N_, gc_, d_->Y, kLd, d_->theta, nc, R_, ld_, partial_,
                 d_->sums, s_);
     CtlParams P{};
@@ -1339,8 +1387,10 @@ int Solver::stage1_mixed(double* V1, double* U1, double* sig, double* rn, double
     int nb = c.nblock;
     if (nb == 0) {
       nb = b_;
+      count(N8() * nb);
       fill_random(Tb_, ld_, N_, nb, o_.seed, kStreamBreak + (uint64_t)rand_count_++, 0, s_);
     } else {
+      count(N8() * (2 * nb + (o_.precond == SVDS_PC_JACOBI ? 1 : 0)));
       gather_precond(R_, ld_, d_->blk, nb, o_.precond == SVDS_PC_JACOBI ? dinv_ : nullptr, N_,
                      Tb_, ld_, s_);
       if (o_.precond != SVDS_PC_JACOBI) apply_pc(Tb_, nb);
