@@ -166,7 +166,7 @@ def _gen_batched(i):
     return synth.batched_problem(i)
 
 
-def batched_extra(P, torch, nprob):
+def batched_extra(P, torch, nprob, nworkers=16):
     """Batched workload: nprob independent problems (rows U{5000..200000}, cols rows/2,
     8-12 nnz/row), k = 4 smallest each, block 8, solved by svds_solve_batched
     with 16 workers; the first 16 also one after another for comparison."""
@@ -185,7 +185,7 @@ def batched_extra(P, torch, nprob):
     opts = dict(block_size=8, max_basis_size=35, min_restart_size=14, seed=2004)
     k = 4
     sub = dev[:16]
-    P.solve_batched(sub, k, "smallest", 1e-10, nworkers=16, **opts)  # warm-up and autotune
+    P.solve_batched(sub, k, "smallest", 1e-10, nworkers=nworkers, **opts)  # warm-up and autotune
     torch.cuda.synchronize()
     t = time.perf_counter()
     for d in sub:
@@ -193,11 +193,11 @@ def batched_extra(P, torch, nprob):
     torch.cuda.synchronize()
     serial16 = time.perf_counter() - t
     t = time.perf_counter()
-    P.solve_batched(sub, k, "smallest", 1e-10, nworkers=16, **opts)
+    P.solve_batched(sub, k, "smallest", 1e-10, nworkers=nworkers, **opts)
     torch.cuda.synchronize()
     batched16 = time.perf_counter() - t
     t = time.perf_counter()
-    rc, res = P.solve_batched(dev, k, "smallest", 1e-10, nworkers=16, **opts)
+    rc, res = P.solve_batched(dev, k, "smallest", 1e-10, nworkers=nworkers, **opts)
     torch.cuda.synchronize()
     el = time.perf_counter() - t
     conv = sum(1 for r in res if r[4]["converged"])
@@ -210,7 +210,7 @@ def batched_extra(P, torch, nprob):
             "matvecs_total": int(sum(sum(r[4]["matvecs"]) for r in res)),
             "stage2_problems": int(sum(1 for r in res if r[4]["stage_exit"] == 2)),
             "first16_serial_seconds": serial16, "first16_batched_seconds": batched16,
-            "workers": 16, "generation_seconds": gen}
+            "workers": nworkers, "generation_seconds": gen}
 
 
 def learned_extra(P, torch, full_seconds, replica=True):
@@ -373,6 +373,7 @@ def main():
                          "and the two-product comparison")
     ap.add_argument("--batched", type=int, default=256, help="problems in the batched extra (0: skip)")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--workers", type=int, default=16, help="host workers of the batched extra")
     ap.add_argument("--full-seconds", type=float, default=20.0,
                     help="time budget of each full-size convection-diffusion solve")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
@@ -408,7 +409,7 @@ def main():
         if args.only == "mixed":
             out = mixed_comparison(P, torch)
         elif args.only == "batched":
-            out = batched_extra(P, torch, max(args.batched, 16))
+            out = batched_extra(P, torch, max(args.batched, 16), args.workers)
         elif args.only in ("learned", "learned_full"):
             out, _ = learned_extra(P, torch, args.full_seconds, replica=args.only == "learned")
         elif args.only == "methods":

@@ -524,49 +524,92 @@ template int ts_residual<float>(const float*, const float*, int64_t, int64_t, in
 // small helpers: pack / unpack between column-major and row-major blocks,
 // preconditioned gather, row scaling, column copies
 // ---------------------------------------------------------------------------
+// Conversions between column-major columns and row-major compact blocks (the
+// operand layout of the sparse products).  The block width is a template
+// argument so that each thread issues all of its row's loads before its
+// stores, and a row's B values leave as one contiguous store sequence.
+template <int B>
 __global__ void k_pack(const double* __restrict__ A, int64_t lda, const double* __restrict__ Bm,
-                       double beta, int64_t N, int b, double* __restrict__ out) {
+                       double beta, int64_t N, double* __restrict__ out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < N; i += stride)
-    for (int c = 0; c < b; ++c) {
-      double v = A[i + c * lda];
-      if (Bm) v = fma(beta, Bm[i + c * lda], v);
-      out[i * b + c] = v;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < N; i += stride) {
+    double v[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) v[c] = A[i + c * lda];
+    if (Bm) {
+#pragma unroll
+      for (int c = 0; c < B; ++c) v[c] = fma(beta, Bm[i + c * lda], v[c]);
     }
+#pragma unroll
+    for (int c = 0; c < B; ++c) out[i * B + c] = v[c];
+  }
 }
+
+template <int B>
+__global__ void k_unpack(const double* __restrict__ in, int64_t N, double* __restrict__ A,
+                         int64_t lda) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < N; i += stride) {
+    double v[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) v[c] = in[i * B + c];
+#pragma unroll
+    for (int c = 0; c < B; ++c) A[i + c * lda] = v[c];
+  }
+}
+
+#define SVDS_BLOCK_SWITCH(b, CALL)          \
+  switch (b) {                              \
+    case 1: CALL(1); break;                 \
+    case 2: CALL(2); break;                 \
+    case 3: CALL(3); break;                 \
+    case 4: CALL(4); break;                 \
+    case 5: CALL(5); break;                 \
+    case 6: CALL(6); break;                 \
+    case 7: CALL(7); break;                 \
+    case 8: CALL(8); break;                 \
+    default: throw Error(SVDS_ERR_ARG, "block width must be 1..8"); \
+  }
 
 void pack_rows(const double* A, int64_t lda, const double* B, double beta, int64_t N, int b,
                double* compact, hipStream_t s) {
   int blocks = (int)std::min<int64_t>(8192, (N + 255) / 256);
   if (blocks < 1) return;
-  k_pack<<<blocks, 256, 0, s>>>(A, lda, B, beta, N, b, compact);
+#define SVDS_PACK(BB) k_pack<BB><<<blocks, 256, 0, s>>>(A, lda, B, beta, N, compact)
+  SVDS_BLOCK_SWITCH(b, SVDS_PACK)
+#undef SVDS_PACK
   SVDS_LAUNCH_CHECK();
-}
-
-__global__ void k_unpack(const double* __restrict__ in, int64_t N, int b, double* __restrict__ A,
-                         int64_t lda) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < N; i += stride)
-    for (int c = 0; c < b; ++c) A[i + c * lda] = in[i * b + c];
 }
 
 void unpack_rows(const double* compact, int64_t N, int b, double* A, int64_t lda, hipStream_t s) {
   int blocks = (int)std::min<int64_t>(8192, (N + 255) / 256);
   if (blocks < 1) return;
-  k_unpack<<<blocks, 256, 0, s>>>(compact, N, b, A, lda);
+#define SVDS_UNPACK(BB) k_unpack<BB><<<blocks, 256, 0, s>>>(compact, N, A, lda)
+  SVDS_BLOCK_SWITCH(b, SVDS_UNPACK)
+#undef SVDS_UNPACK
   SVDS_LAUNCH_CHECK();
 }
 
+// T[:, c] = R[:, blk[c]] * dinv for the block's nb columns (blk on the device,
+// read once per workgroup into LDS)
+template <int B>
 __global__ void k_gather(const double* __restrict__ R, int64_t ldr, const int* __restrict__ blk,
-                         int nb, const double* __restrict__ dinv, int64_t N,
-                         double* __restrict__ T, int64_t ldt) {
+                         const double* __restrict__ dinv, int64_t N, double* __restrict__ T,
+                         int64_t ldt) {
+  __shared__ int cols[B];
+  if (threadIdx.x < B) cols[threadIdx.x] = blk[threadIdx.x];
+  __syncthreads();
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; i < N; i += stride) {
     const double d = dinv ? dinv[i] : 1.0;
-    for (int c = 0; c < nb; ++c) T[i + c * ldt] = R[i + (int64_t)blk[c] * ldr] * d;
+    double v[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) v[c] = R[i + (int64_t)cols[c] * ldr];
+#pragma unroll
+    for (int c = 0; c < B; ++c) T[i + c * ldt] = v[c] * d;
   }
 }
 
@@ -574,7 +617,9 @@ void gather_precond(const double* R, int64_t ldr, const int* d_blk, int nb, cons
                     int64_t N, double* T, int64_t ldt, hipStream_t s) {
   int blocks = (int)std::min<int64_t>(8192, (N + 255) / 256);
   if (blocks < 1) return;
-  k_gather<<<blocks, 256, 0, s>>>(R, ldr, d_blk, nb, dinv, N, T, ldt);
+#define SVDS_GATHER(BB) k_gather<BB><<<blocks, 256, 0, s>>>(R, ldr, d_blk, dinv, N, T, ldt)
+  SVDS_BLOCK_SWITCH(nb, SVDS_GATHER)
+#undef SVDS_GATHER
   SVDS_LAUNCH_CHECK();
 }
 

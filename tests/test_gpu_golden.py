@@ -98,3 +98,33 @@ def test_convdiff_256_against_oracle(P, pc):
                   max_seconds=100.0, **kw)
     _check(A, g, out, 10, f"convdiff_256 {pc}")
     M.close()
+
+
+def test_convdiff_256_learned_against_oracle(P):
+    """The learned preconditioner as the timed workload uses it: trained on the
+    GPU from Jacobi-solve residuals of eight 32^2 fields (seeds 5001-5008,
+    200 Adam steps, degree 15), then the held-out field (seed 5000) on the
+    256^2 grid, k = 10 smallest, block 1, against the stored oracle result."""
+    g = _golden("convdiff_256")
+    sets = []
+    for sd in range(5001, 5009):
+        _say("learned training residuals seed", sd)
+        M = P.Matrix.from_scipy(synth.convdiff_workload(ng=32, seed=sd))
+        R, st = P.collect_residuals(M, 10, "smallest", 1e-10, every=4, max_pairs=64, block_size=1,
+                                    seed=1, precond=1)
+        sets.append((M, R))
+    bias = np.full(8, -8.0)
+    bias[7] = 0.0
+    params = P.lpc_init(seed=0, out_bias=bias)
+    _say("learned training 200 steps")
+    hist = P.lpc_train(sets, 15, 200, 1e-2, params)
+    assert hist[-1] < 0.5 * hist[0]
+    A = synth.convdiff_workload(ng=256, seed=5000)
+    _say("golden convdiff_256 k=10 smallest b=1 learned")
+    M = P.Matrix.from_scipy(A)
+    out = M.solve(10, "smallest", 1e-10, block_size=1, seed=1, norm_A=g["norm_A"],
+                  precond=2, pc_model=params, pc_degree=15, max_seconds=100.0)
+    _check(A, g, out, 10, "convdiff_256 learned")
+    M.close()
+    for Ms, _ in sets:
+        Ms.close()
