@@ -168,8 +168,9 @@ def _gen_batched(i):
 
 def batched_extra(P, torch, nprob, nworkers=16):
     """Batched workload: nprob independent problems (rows U{5000..200000}, cols rows/2,
-    8-12 nnz/row), k = 4 smallest each, block 8, solved by svds_solve_batched
-    with 16 workers; the first 16 also one after another for comparison."""
+    8-12 nnz/row), k = 4 smallest each, block 8.  svds_solve_batched with the problems in
+    step (one launch per step of the first-stage iteration for all problems) against
+    `nworkers` host workers with a stream each; the first 16 also one after another."""
     import multiprocessing as mp
     import numpy as np
     workers = max(1, min(16, len(os.sched_getaffinity(0))))
@@ -185,32 +186,52 @@ def batched_extra(P, torch, nprob, nworkers=16):
     opts = dict(block_size=8, max_basis_size=35, min_restart_size=14, seed=2004)
     k = 4
     sub = dev[:16]
-    P.solve_batched(sub, k, "smallest", 1e-10, nworkers=nworkers, **opts)  # warm-up and autotune
+    P.solve_batched(sub, k, "smallest", 1e-10, nworkers=0, **opts)  # warm-up and autotune
     torch.cuda.synchronize()
     t = time.perf_counter()
     for d in sub:
         P.solve(*d, k, "smallest", 1e-10, **opts)
     torch.cuda.synchronize()
     serial16 = time.perf_counter() - t
-    t = time.perf_counter()
-    P.solve_batched(sub, k, "smallest", 1e-10, nworkers=nworkers, **opts)
-    torch.cuda.synchronize()
-    batched16 = time.perf_counter() - t
-    t = time.perf_counter()
-    rc, res = P.solve_batched(dev, k, "smallest", 1e-10, nworkers=nworkers, **opts)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t
+
+    def timed(subset, nw):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = P.solve_batched(subset, k, "smallest", 1e-10, nworkers=nw, **opts)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, out
+
+    step16, _ = timed(sub, 0)
+    workers16, _ = timed(sub, nworkers)
+    el, (rc, res) = timed(dev, 0)
+    log(f"batched: in step {el:.2f} s")
+    elw, (rcw, resw) = timed(dev, nworkers)
+    log(f"batched: {nworkers} workers {elw:.2f} s")
+    same = all(bool((a[0] == b[0]).all()) and a[4]["matvecs"] == b[4]["matvecs"]
+               for a, b in zip(res, resw))
     conv = sum(1 for r in res if r[4]["converged"])
     rmax = max(float(r[3].max()) / r[4]["norm_A_used"] for r in res)
     nnz = int(sum(A.nnz for A in mats))
+    ab = sum(r[4]["alg_bytes"] for r in res)
     return {"workload": f"{nprob} problems, rows U{{5000..200000}}, cols rows/2, 8-12 nnz/row, "
                         "N(0,1); k=4 smallest, block 8, basis 35, restart 14, tol 1e-10",
             "nnz_total": nnz, "seconds": el, "problems_per_second": nprob / el,
+            "mode": "in step: one launch per step of the first-stage iteration for all problems",
             "converged": conv, "status": rc, "max_rnorm_over_normA": rmax,
             "matvecs_total": int(sum(sum(r[4]["matvecs"]) for r in res)),
+            "iters_max": int(max(r[4]["iters"][0] for r in res)),
+            "iters_mean": float(np.mean([r[4]["iters"][0] for r in res])),
             "stage2_problems": int(sum(1 for r in res if r[4]["stage_exit"] == 2)),
-            "first16_serial_seconds": serial16, "first16_batched_seconds": batched16,
-            "workers": nworkers, "generation_seconds": gen}
+            "roofline": {"bound": "hbm", "achieved": ab / el / 1e9, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": ab / el / 1e9 / HBM_PEAK_GBS,
+                         "alg_bytes": ab,
+                         "note": "counted iteration kernels of all problems over the batch's "
+                                 "wall time (set-up, norm estimates, clean-up in the time only)"},
+            "workers_seconds": elw, "workers": nworkers,
+            "workers_problems_per_second": nprob / elw, "workers_status": rcw,
+            "same_results_as_workers": same,
+            "first16_serial_seconds": serial16, "first16_in_step_seconds": step16,
+            "first16_workers_seconds": workers16, "generation_seconds": gen}
 
 
 def learned_extra(P, torch, full_seconds, replica=True):

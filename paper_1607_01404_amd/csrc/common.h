@@ -176,6 +176,68 @@ __device__ __forceinline__ int xcd_block(int bid, int nblocks) {
   return (bid % kXcd) * (nblocks / kXcd) + bid / kXcd;
 }
 
+// ---------------------------------------------------------------------------
+// Batched launches: one launch per step of the iteration for many problems.
+// For each problem p the launch runs exactly the workgroups (x, y), x < gx_p,
+// y < gy_p, of that problem's own launch, with the same arguments, so every
+// problem gets the same bits as from its own launches.  pre[p] is the number
+// of workgroups before problem p (pre[np] = all); a workgroup finds its
+// problem by binary search (the last p with pre[p] <= its index).
+// ---------------------------------------------------------------------------
+struct BTiles {
+  const int* pre;  // np + 1
+  const int* gx;   // np
+  int np;
+};
+
+struct BTile {
+  int p, x, y, gx;
+};
+
+__device__ __forceinline__ BTile batch_tile(const BTiles& t, int bid) {
+  int lo = 0, hi = t.np - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (t.pre[mid] <= bid) lo = mid;
+    else hi = mid - 1;
+  }
+  BTile r;
+  r.p = lo;
+  r.gx = t.gx[lo];
+  const int local = bid - t.pre[lo];
+  r.x = local % r.gx;
+  r.y = local / r.gx;
+  return r;
+}
+
+// Launch arguments of one step for all problems, copied from pinned host
+// staging to device memory on the stream right before the launch.  The
+// staging is reused from the start once the stream has passed the previous
+// round's copies (the caller resets it after reading the round's results).
+class BatchUpload {
+ public:
+  BatchUpload() = default;
+  BatchUpload(const BatchUpload&) = delete;
+  BatchUpload& operator=(const BatchUpload&) = delete;
+  ~BatchUpload();
+  void init(size_t bytes, hipStream_t s);
+  void reset() { used_ = 0; }
+  template <class T>
+  const T* put(const T* v, size_t n) {
+    return static_cast<const T*>(put_bytes(v, sizeof(T) * n));
+  }
+  // tiles of a launch whose problem p has gx[p] x gy[p] workgroups; returns
+  // the total count
+  int tiles(const std::vector<int>& gx, const std::vector<int>& gy, BTiles& t);
+
+ private:
+  const void* put_bytes(const void* v, size_t bytes);
+  char* host_ = nullptr;
+  char* dev_ = nullptr;
+  size_t cap_ = 0, used_ = 0;
+  hipStream_t s_ = nullptr;
+};
+
 // SplitMix64 finaliser (Steele, Lea and Flood 2014) on seed + (counter+1)*gamma;
 // uniform in [-0.5, 0.5) from the top 53 bits.
 __host__ __device__ __forceinline__ double counter_uniform(uint64_t seed, uint64_t stream,
@@ -357,6 +419,99 @@ void invert_diag(const double* d, int64_t n, double* out, hipStream_t s);
 void scale_rows(double* T, int64_t ldt, int64_t N, int b, const double* dinv, hipStream_t s);
 void copy_cols(const double* A, int64_t lda, int64_t N, int b, double* B, int64_t ldb,
                hipStream_t s);
+
+// ---- batched steps: one launch for all jobs, each job computed exactly as
+// the single launch above would compute it (same workgroups, same sums)
+struct BatchProj {  // tsgemm_tn (C = null: partial sums only)
+  Seg segs[3];
+  int nseg;
+  int64_t N;
+  const double* T;
+  int64_t ldt;
+  double* partial;
+  double* C;
+  const int* skip;
+};
+// nblk[j]: workgroups of job j (the partial sums' block count)
+void tsgemm_tn_batch(int b, const std::vector<BatchProj>& jobs, std::vector<int>& nblk,
+                     BatchUpload& up, hipStream_t s);
+struct BatchReduce {
+  const double* P;
+  int nblk, nout;
+  double* out;
+  const int* skip;
+};
+void reduce_partials_batch(const std::vector<BatchReduce>& jobs, BatchUpload& up, hipStream_t s);
+struct BatchUpdate {
+  Seg segs[3];
+  int nseg;
+  int64_t N;
+  const double* C;
+  int ldc;
+  double* T;
+  int64_t ldt;
+  const int* skip;
+};
+void ts_update_batch(int b, const std::vector<BatchUpdate>& jobs, BatchUpload& up, hipStream_t s);
+struct BatchGemm {
+  const double* Q;
+  int64_t ldq;
+  int nq;
+  int64_t N;
+  const double* Y;
+  int64_t ldy;
+  int nout;
+  double* Out;
+  int64_t ldo;
+};
+void ts_gemm_nn_batch(const std::vector<BatchGemm>& jobs, BatchUpload& up, hipStream_t s);
+struct BatchScale {
+  double* T;
+  int64_t ldt, N;
+  const double* Rinv;
+  double* compact;
+};
+void ts_scale_batch(int b, const std::vector<BatchScale>& jobs, BatchUpload& up, hipStream_t s);
+struct BatchResid {  // one sum per candidate (nsplit = N)
+  const double* V;
+  const double* W;
+  int64_t ld, N;
+  int g;
+  const double* Y;
+  int64_t ldy;
+  const double* theta;
+  int nc;
+  double* R;
+  int64_t ldr;
+  double* partial;
+  double* sums;
+};
+void ts_residual_batch(const std::vector<BatchResid>& jobs, BatchUpload& up, hipStream_t s);
+struct BatchGather {
+  const double* R;
+  int64_t ldr;
+  const int* blk;
+  const double* dinv;
+  int64_t N;
+  double* T;
+  int64_t ldt;
+};
+void gather_batch(int nb, const std::vector<BatchGather>& jobs, BatchUpload& up, hipStream_t s);
+struct BatchUnpack {
+  const double* compact;
+  int64_t N;
+  double* A;
+  int64_t lda;
+};
+void unpack_batch(int nb, const std::vector<BatchUnpack>& jobs, BatchUpload& up, hipStream_t s);
+// the products of jobs whose matrices share one merged launch shape (lanes
+// per row, nonzeros per step): Y = A X, row-major blocks of b columns
+struct BatchSpmm {
+  const Csr32* A;
+  const double* X;
+  double* Y;
+};
+void spmm_batch(int b, const std::vector<BatchSpmm>& jobs, BatchUpload& up, hipStream_t s);
 
 // Jacobi-Davidson correction of the second stage: per-column symmetric-QMR state
 struct JdCol {

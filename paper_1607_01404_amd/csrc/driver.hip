@@ -196,12 +196,18 @@ class Solver {
   }
   ~Solver() {
     for (hipEvent_t e : evpool_) (void)hipEventDestroy(e);
+    if (hctl_) (void)hipHostFree(hctl_);
+    if (hbad_) (void)hipHostFree(hbad_);
+    if (hjd_) (void)hipHostFree(hjd_);
   }
   Solver(const Solver&) = delete;
   Solver& operator=(const Solver&) = delete;
 
   int run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, double* rnorm,
           svds_stats* st);
+  void prepare(svds_stats* st);
+  int complete(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, double* rnorm,
+               svds_stats* st, bool stage1_done);
 
   // every device array of the solve, from `a` (the block cache, a caller's
   // workspace, or a count of the bytes); no launch
@@ -709,6 +715,14 @@ class Solver {
   Ctl control(const CtlParams& p) {
     ++seq_;
     small_control(d_, p, s_, dctl_, dseq_, seq_);
+    return control_wait();
+  }
+  // the batched driver launches the control steps of many solvers at once
+  ControlArgs control_args(const CtlParams& p) {
+    ++seq_;
+    return ControlArgs{d_, p, dctl_, dseq_, seq_};
+  }
+  Ctl control_wait() {
     constexpr int nw = (int)(offsetof(Ctl, seq) / sizeof(unsigned int));
     Ctl c;
     // after a short busy spin the poll yields its core (the batched solve runs
@@ -852,6 +866,44 @@ class Solver {
   // ---- stages ------------------------------------------------------------------
   int stage1(double* Vout /*n x k*/, double* Uout /*m x k*/, double* sig, double* rn, double* taus,
              int* ok, int* status1, svds_stats* st);
+  // stage 1 in pieces, which the batched driver runs for many solvers in step
+ public:
+  void s1_start() { s1_begin(); }
+ private:
+  struct S1State {
+    int g = 0, r = 0;
+    int64_t iters = 0, restarts = 0, resets = 0;
+    int since_reset = 0, floor_resets = 0, status = 2, last_nb = 0;
+    double t0 = 0.0;
+    int64_t mv0 = 0;
+  };
+  S1State s1_;
+  void s1_begin();
+  CtlParams s1_params(int nc) const;
+  int s1_decide(const Ctl& c);
+  void s1_expand(const Ctl& c);
+  void s1_restarted(int nr);
+  // the random block of a round with nothing to correct, then its
+  // orthogonalisation, product, H columns and extraction (as s1_expand)
+  void fill_random_block(int nb) {
+    fill_random(V_ + gc_ * ld_, ld_, N_, nb, o_.seed, kStreamBreak + (uint64_t)rand_count_++, 0, s_);
+  }
+  void ortho_and_append(int nb) {
+    Seg sv{V_, gc_, ld_};
+    ortho_enqueue(V_ + gc_ * ld_, ld_, nb, &sv, 1, Tc_);
+    append(nb);
+    s1_.last_nb = nb;
+    extract_stage();
+    ++s1_.iters;
+  }
+  void s1_end(double* V1, double* U1, double* sig, double* rn, double* taus, int* ok,
+              int* status1, svds_stats* st);
+ public:
+  void s1_end_default(int* status1, svds_stats* st) {
+    s1_end(V1_, U1_, sig_, rn1_, taus_, ok_, status1, st);
+  }
+ private:
+  friend struct BatchStage1;
   int stage1_mixed(double* V1, double* U1, double* sig, double* rn, double* taus, int* ok,
                    int* status1, svds_stats* st);
   void final_rr(double* Xk, double* V1, double* U1, double* sig, double* rn, double* taus, int* ok);
@@ -938,15 +990,16 @@ void Solver::estimate_norm() {
 // ---------------------------------------------------------------------------
 // Stage 1: GD+k on C with soft locking (Algorithm 1, first stage)
 // ---------------------------------------------------------------------------
-int Solver::stage1(double* V1, double* U1, double* sig, double* rn, double* taus, int* ok,
-                   int* status1, svds_stats* st) {
+// stage 1 up to the first extraction: small state, random block, Krylov fill
+void Solver::s1_begin() {
   stage_ = 1;
   N_ = n_;
   gc_ = 0;
   nlock_ = 0;
   refined_ = false;
-  const double t0 = now();
-  const int64_t mv0 = mv_;
+  s1_ = S1State{};
+  s1_.t0 = now();
+  s1_.mv0 = mv_;
   // reset the small state
   SVDS_HIP(hipMemsetAsync(d_, 0, sizeof(Small), s_));
   {
@@ -957,13 +1010,13 @@ int Solver::stage1(double* V1, double* U1, double* sig, double* rn, double* taus
     SVDS_HIP(hipMemcpyAsync(&d_->normop, &nc, sizeof(double), hipMemcpyHostToDevice, s_));
     SVDS_HIP(hipStreamSynchronize(s_));
   }
-  const int g = (int)std::min<int64_t>(g_, n_);
-  const int r = std::min(r_, std::max(1, g - b_ - p_));
-  const int fill = std::min(std::max(r, k_ + b_), g - b_);
+  s1_.g = (int)std::min<int64_t>(g_, n_);
+  s1_.r = std::min(r_, std::max(1, s1_.g - b_ - p_));
+  const int fill = std::min(std::max(s1_.r, k_ + b_), s1_.g - b_);
   fill_random(V_, ld_, N_, b_, o_.seed, kStreamInit, 0, s_);
   ortho<double>(V_, ld_, b_, nullptr, 0, Tc_);
   append(b_);
-  while (gc_ < fill && gc_ + b_ <= g) {
+  while (gc_ < fill && gc_ + b_ <= s1_.g) {
     double* T = V_ + gc_ * ld_;
     copy_cols(W_ + (gc_ - b_) * ld_, ld_, N_, b_, T, ld_, s_);
     Seg sv{V_, gc_, ld_};
@@ -971,86 +1024,119 @@ int Solver::stage1(double* V1, double* U1, double* sig, double* rn, double* taus
     append(b_);
   }
   extract_stage();
-  int64_t iters = 0, restarts = 0, resets = 0;
-  int since_reset = 0, floor_resets = 0;
-  int status = 2;
-  int last_nb = 0;
-  for (;;) {
-    const int nc = std::min(gc_, k_ + b_);
-    residual(nc, N_);
-    CtlParams P{};
-    P.stage = 1;
-    P.gc = gc_;
-    P.g = g;
-    P.r = r;
-    P.p = p_;
-    P.b = b_;
-    P.k = k_;
-    P.nc = nc;
-    P.since_reset = since_reset;
-    P.floor_resets = floor_resets;
-    P.budget_hit = over_budget() ? 1 : 0;
-    P.tol = tol1_;
-    P.rel = o_.relative_tol ? 1 : 0;
-    P.normA = normA_;
-    P.eps = kEps;
-    P.gate = kFloorGate * kEps;
-    Ctl c = control(P);
-    trace("s1", (int)iters, c, nc);
-    if (cap_) capture_residual(iters, c);
-    if (c.action == kBreakdown) {
-      Seg sv{V_, gc_, ld_};
-      repair_block(last_nb, c.bad, &sv, 1);
-      continue;
-    }
-    if (c.action == kExitConverged || c.action == kExitFloor || c.action == kExitBudget) {
-      status = c.action == kExitConverged ? 0 : (c.action == kExitFloor ? 1 : 2);
-      normA_ = std::max(normA_, std::sqrt(c.normop));
-      break;
-    }
-    if (c.action == kReset) {
-      reset();
-      ++resets;
-      since_reset = 0;
-      floor_resets += c.floor_reset;
-      extract_stage();
-      continue;
-    }
-    if (c.restart) {
-      restart_basis(c.nr);
-      ++restarts;
-      ++since_reset;
-    }
-    int nb = c.nblock;
-    double* T = V_ + gc_ * ld_;
-    if (nb == 0) {
-      nb = b_;
-      count(N8() * nb);
-      fill_random(T, ld_, N_, nb, o_.seed, kStreamBreak + (uint64_t)rand_count_++, 0, s_);
-    } else {
-      count(N8() * (2 * nb + (o_.precond == SVDS_PC_JACOBI ? 1 : 0)));
-      gather_precond(R_, ld_, d_->blk, nb, o_.precond == SVDS_PC_JACOBI ? dinv_ : nullptr, N_, T,
-                     ld_, s_);
-      if (o_.precond != SVDS_PC_JACOBI) apply_pc(T, nb);
-    }
+}
+
+CtlParams Solver::s1_params(int nc) const {
+  CtlParams P{};
+  P.stage = 1;
+  P.gc = gc_;
+  P.g = s1_.g;
+  P.r = s1_.r;
+  P.p = p_;
+  P.b = b_;
+  P.k = k_;
+  P.nc = nc;
+  P.since_reset = s1_.since_reset;
+  P.floor_resets = s1_.floor_resets;
+  P.budget_hit = over_budget() ? 1 : 0;
+  P.tol = tol1_;
+  P.rel = o_.relative_tol ? 1 : 0;
+  P.normA = normA_;
+  P.eps = kEps;
+  P.gate = kFloorGate * kEps;
+  return P;
+}
+
+// the host's part of a control decision: 1 = stage 1 ends, 2 = the step was
+// a breakdown repair or a reset (done here; the next round starts with the
+// residual), 0 = expand the basis (after a restart when c.restart)
+int Solver::s1_decide(const Ctl& c) {
+  if (c.action == kBreakdown) {
     Seg sv{V_, gc_, ld_};
-    ortho_enqueue(T, ld_, nb, &sv, 1, Tc_);
-    append(nb);
-    last_nb = nb;
-    extract_stage();
-    ++iters;
+    repair_block(s1_.last_nb, c.bad, &sv, 1);
+    return 2;
   }
-  // final Rayleigh-Ritz on A X (Algorithm 1, end of the first stage)
+  if (c.action == kExitConverged || c.action == kExitFloor || c.action == kExitBudget) {
+    s1_.status = c.action == kExitConverged ? 0 : (c.action == kExitFloor ? 1 : 2);
+    normA_ = std::max(normA_, std::sqrt(c.normop));
+    return 1;
+  }
+  if (c.action == kReset) {
+    reset();
+    ++s1_.resets;
+    s1_.since_reset = 0;
+    s1_.floor_resets += c.floor_reset;
+    extract_stage();
+    return 2;
+  }
+  return 0;
+}
+
+// the basis after a restart: V <- V Y_r, W <- W Y_r (the products launched by the caller)
+void Solver::s1_restarted(int nr) {
+  std::swap(V_, Vt_);
+  std::swap(W_, Wt_);
+  gc_ = nr;
+  ++s1_.restarts;
+  ++s1_.since_reset;
+}
+
+void Solver::s1_expand(const Ctl& c) {
+  if (c.restart) {
+    restart_basis(c.nr);
+    ++s1_.restarts;
+    ++s1_.since_reset;
+  }
+  int nb = c.nblock;
+  double* T = V_ + gc_ * ld_;
+  if (nb == 0) {
+    nb = b_;
+    count(N8() * nb);
+    fill_random(T, ld_, N_, nb, o_.seed, kStreamBreak + (uint64_t)rand_count_++, 0, s_);
+  } else {
+    count(N8() * (2 * nb + (o_.precond == SVDS_PC_JACOBI ? 1 : 0)));
+    gather_precond(R_, ld_, d_->blk, nb, o_.precond == SVDS_PC_JACOBI ? dinv_ : nullptr, N_, T,
+                   ld_, s_);
+    if (o_.precond != SVDS_PC_JACOBI) apply_pc(T, nb);
+  }
+  Seg sv{V_, gc_, ld_};
+  ortho_enqueue(T, ld_, nb, &sv, 1, Tc_);
+  append(nb);
+  s1_.last_nb = nb;
+  extract_stage();
+  ++s1_.iters;
+}
+
+// final Rayleigh-Ritz on A X (Algorithm 1, end of the first stage)
+void Solver::s1_end(double* V1, double* U1, double* sig, double* rn, double* taus, int* ok,
+                    int* status1, svds_stats* st) {
   double* Xk = X_;  // n x k (ld ld_)
   ts_gemm_nn(V_, ld_, gc_, N_, d_->Y, kLd, k_, Xk, ld_, s_);
   final_rr(Xk, V1, U1, sig, rn, taus, ok);
   SVDS_HIP(hipStreamSynchronize(s_));
-  st->iters[0] = iters;
-  st->restarts[0] = restarts;
-  st->resets += resets;
-  st->matvecs[0] = mv_ - mv0;
-  st->seconds[0] = now() - t0;
-  *status1 = status;
+  st->iters[0] = s1_.iters;
+  st->restarts[0] = s1_.restarts;
+  st->resets += s1_.resets;
+  st->matvecs[0] = mv_ - s1_.mv0;
+  st->seconds[0] = now() - s1_.t0;
+  *status1 = s1_.status;
+}
+
+int Solver::stage1(double* V1, double* U1, double* sig, double* rn, double* taus, int* ok,
+                   int* status1, svds_stats* st) {
+  s1_begin();
+  for (;;) {
+    const int nc = std::min(gc_, k_ + b_);
+    residual(nc, N_);
+    Ctl c = control(s1_params(nc));
+    trace("s1", (int)s1_.iters, c, nc);
+    if (cap_) capture_residual(s1_.iters, c);
+    const int what = s1_decide(c);
+    if (what == 1) break;
+    if (what == 2) continue;
+    s1_expand(c);
+  }
+  s1_end(V1, U1, sig, rn, taus, ok, status1, st);
   return 0;
 }
 
@@ -1443,7 +1529,8 @@ void Solver::capture_residual(int64_t iters, const Ctl& c) {
 void Solver::allocate(DeviceBuffers& a) {
   const int64_t Nmax = m_ + n_;
   ld_ = round_up(Nmax, 64);
-  const size_t basis = (size_t)ld_ * kGmax;
+  // basis arrays hold g columns (and the 30 of the norm estimate)
+  const size_t basis = (size_t)ld_ * std::min(kGmax, std::max(g_, 30));
   const size_t blk = (size_t)ld_ * kMaxBlock;
   V_ = a.get<double>(basis);
   W_ = a.get<double>(basis);
@@ -1508,14 +1595,13 @@ void Solver::allocate(DeviceBuffers& a) {
   }
 }
 
-int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, double* rnorm,
-                svds_stats* st) {
+// everything before the first stage: the solver's arrays, the pinned control
+// records, the preconditioner, ||A||
+void Solver::prepare(svds_stats* st) {
   std::memset(st, 0, sizeof(*st));
   const double t0 = now();
   run_t0_ = t0;
   allocate(buf_);
-  double *V1 = V1_, *U1 = U1_, *sig = sig_, *rn1 = rn1_, *taus = taus_;
-  int* ok = ok_;
   mixed_ = o_.precision == SVDS_MIXED;
   constexpr size_t kSeqOff = (sizeof(Ctl) + 63) / 64 * 64;
   SVDS_HIP(hipHostMalloc((void**)&hctl_, kSeqOff + 64, hipHostMallocMapped | hipHostMallocCoherent));
@@ -1525,16 +1611,6 @@ int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, d
   __atomic_store_n(hseq_, 0, __ATOMIC_RELEASE);
   SVDS_HIP(hipHostMalloc((void**)&hbad_, sizeof(int), hipHostMallocDefault));
   SVDS_HIP(hipHostMalloc((void**)&hjd_, sizeof(JdCol) * kMaxBlock, hipHostMallocDefault));
-  struct PinnedFree {
-    Ctl* c;
-    int* b;
-    JdCol* j;
-    ~PinnedFree() {
-      (void)hipHostFree(c);
-      (void)hipHostFree(b);
-      (void)hipHostFree(j);
-    }
-  } pf{hctl_, hbad_, hjd_};
   if (o_.precond == SVDS_PC_JACOBI)
     invert_diag(M_->diagC, n_, dinv_, s_);  // 1/diag(C), with 1 where the column is empty
   if (o_.precond == SVDS_PC_LEARNED) setup_learned();
@@ -1548,6 +1624,20 @@ int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, d
     mv_ = 0;
   }
   st->setup_seconds = now() - t0;
+}
+
+int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, double* rnorm,
+                svds_stats* st) {
+  prepare(st);
+  return complete(sigma, U, ldu, V, ldv, rnorm, st, false);
+}
+
+// the stages (stage 1 unless a batched driver already ran it and its end),
+// the clean-up and the statistics
+int Solver::complete(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv,
+                     double* rnorm, svds_stats* st, bool stage1_done) {
+  double *V1 = V1_, *U1 = U1_, *sig = sig_, *rn1 = rn1_, *taus = taus_;
+  int* ok = ok_;
   int nconv = 0;
   if (o_.method == SVDS_METHOD_AUGMENTED) {
     // stage 2 alone (largest values) from one counter-based block [v; u]
@@ -1562,7 +1652,9 @@ int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, d
   } else {
     // ---- stage 1
     int okh = 0, status1 = 2;
-    if (mixed_) {
+    if (stage1_done) {
+      status1 = st->stage1_status;
+    } else if (mixed_) {
       stage1_mixed(V1, U1, sig, rn1, taus, ok, &status1, st);
     } else {
       stage1(V1, U1, sig, rn1, taus, ok, &status1, st);
@@ -1600,6 +1692,311 @@ int Solver::run(double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, d
   if (!finite && good == 0) return SVDS_ERR_BREAKDOWN;
   return good >= k_ ? SVDS_OK : SVDS_NOT_CONVERGED;
 }
+
+// ---------------------------------------------------------------------------
+// Batched launches: argument upload
+// ---------------------------------------------------------------------------
+BatchUpload::~BatchUpload() {
+  if (dev_) stream_free(dev_, s_);
+  if (host_) (void)hipHostFree(host_);
+}
+
+void BatchUpload::init(size_t bytes, hipStream_t s) {
+  s_ = s;
+  cap_ = bytes;
+  SVDS_HIP(hipHostMalloc((void**)&host_, bytes, hipHostMallocDefault));
+  dev_ = static_cast<char*>(stream_alloc(bytes, s));
+}
+
+const void* BatchUpload::put_bytes(const void* v, size_t bytes) {
+  const size_t off = (used_ + 255) & ~static_cast<size_t>(255);
+  if (off + bytes > cap_) throw Error(SVDS_ERR_ARG, "batched launch arguments exceed the staging");
+  std::memcpy(host_ + off, v, bytes);
+  SVDS_HIP(hipMemcpyAsync(dev_ + off, host_ + off, bytes, hipMemcpyHostToDevice, s_));
+  used_ = off + bytes;
+  return dev_ + off;
+}
+
+int BatchUpload::tiles(const std::vector<int>& gx, const std::vector<int>& gy, BTiles& t) {
+  const int np = (int)gx.size();
+  std::vector<int> pre(np + 1, 0), g(np);
+  for (int p = 0; p < np; ++p) {
+    g[p] = std::max(gx[p], 1);
+    pre[p + 1] = pre[p] + (gx[p] > 0 && gy[p] > 0 ? gx[p] * gy[p] : 0);
+  }
+  t.pre = put(pre.data(), pre.size());
+  t.gx = put(g.data(), g.size());
+  t.np = np;
+  return pre[np];
+}
+
+// ---------------------------------------------------------------------------
+// Stage 1 of many solvers in step (svds_solve_batched): every step of an
+// iteration is one launch for all solvers that take it, with each solver's
+// own arguments and launch geometry, so every solver computes exactly what
+// its own stage1() would.  The host reads all control records of a round
+// and takes each solver's decision; breakdown repairs and resets, which
+// synchronise, run per solver.
+// ---------------------------------------------------------------------------
+struct BatchStage1 {
+  std::vector<Solver*> sv;
+  hipStream_t s;
+  BatchUpload up;
+
+  // solvers that can run in step: FP64 stage 1 through two SpMMs with a
+  // merged launch shape, no preconditioner or point Jacobi
+  static bool eligible(const Solver& x) {
+    return x.o_.precision == SVDS_FP64 && x.o_.method != SVDS_METHOD_AUGMENTED &&
+           (x.o_.precond == SVDS_PC_NONE || x.o_.precond == SVDS_PC_JACOBI) &&
+           !(x.o_.fused_gram && x.M_->G.R > 0) && !x.cap_ && !x.o_.profile;
+  }
+
+  void residual(const std::vector<Solver*>& a) {
+    std::vector<BatchResid> jobs;
+    for (Solver* x : a) {
+      const int nc = std::min(x->gc_, x->k_ + x->b_);
+      x->count(x->N8() * (2 * x->gc_ + nc));
+      jobs.push_back(BatchResid{x->V_, x->W_, x->ld_, x->N_, x->gc_, x->d_->Y, kLd,
+                                x->d_->theta, nc, x->R_, x->ld_, x->partial_, x->d_->sums});
+    }
+    ts_residual_batch(jobs, up, s);
+  }
+
+  // products with A then A^T of the compact blocks, grouped by launch shape
+  void products(const std::vector<Solver*>& a, int nb) {
+    for (int pass = 0; pass < 2; ++pass) {
+      std::map<std::pair<int, int>, std::vector<BatchSpmm>> groups;
+      for (Solver* x : a) {
+        const Csr32& M = pass == 0 ? x->A_ : x->At_;
+        const double* X = pass == 0 ? x->Tc_ : x->Yc_;
+        double* Y = pass == 0 ? x->Yc_ : x->Wc_;
+        x->count(Solver::spmm_bytes(M, nb));
+        if (M.merged_bin < 0 || M.merged_bin >= kNumBins - 1) {
+          spmm(M, nb, X, Y, s);  // binned rows: the matrix's own launches
+          continue;
+        }
+        groups[{M.merged_bin, M.unroll}].push_back(BatchSpmm{&M, X, Y});
+      }
+      for (auto& g : groups) spmm_batch(nb, g.second, up, s);
+    }
+    for (Solver* x : a) x->mv_ += 2 * nb;
+  }
+
+  // correction, orthogonalisation, products, H columns, extraction of
+  // solvers with the same block width (their control steps chose expand)
+  void expand(const std::vector<Solver*>& a, int nb) {
+    std::vector<BatchGather> ga;
+    for (Solver* x : a) {
+      const bool jac = x->o_.precond == SVDS_PC_JACOBI;
+      x->count(x->N8() * (2 * nb + (jac ? 1 : 0)));
+      ga.push_back(BatchGather{x->R_, x->ld_, x->d_->blk, jac ? x->dinv_ : nullptr, x->N_,
+                               x->V_ + x->gc_ * x->ld_, x->ld_});
+    }
+    gather_batch(nb, ga, up, s);
+    // classical Gram-Schmidt pass 1 with the block's own Gram matrix appended
+    std::vector<BatchProj> p1;
+    std::vector<Solver*> wb;  // solvers with a basis to project against
+    for (Solver* x : a) {
+      double* T = x->V_ + x->gc_ * x->ld_;
+      BatchProj q{};
+      q.nseg = 0;
+      if (x->gc_ > 0) q.segs[q.nseg++] = Seg{x->V_, x->gc_, x->ld_};
+      q.segs[q.nseg++] = Seg{T, nb, x->ld_};
+      q.N = x->N_;
+      q.T = T;
+      q.ldt = x->ld_;
+      q.partial = x->partial_;
+      p1.push_back(q);
+      x->count(x->N8() * (x->gc_ + nb));
+      if (x->gc_ > 0) wb.push_back(x);
+    }
+    std::vector<int> nblk;
+    tsgemm_tn_batch(nb, p1, nblk, up, s);
+    std::vector<BatchReduce> r1;
+    for (size_t j = 0; j < a.size(); ++j)
+      r1.push_back(BatchReduce{a[j]->partial_, nblk[j], (a[j]->gc_ + nb) * nb, a[j]->d_->C0,
+                               nullptr});
+    reduce_partials_batch(r1, up, s);
+    if (!wb.empty()) {
+      std::vector<DgksArgs> dg;
+      std::vector<BatchUpdate> u1, u2;
+      std::vector<BatchProj> p2;
+      for (Solver* x : wb) {
+        const int total = x->gc_, ldc0 = total + nb;
+        double* T = x->V_ + x->gc_ * x->ld_;
+        dg.push_back(DgksArgs{x->d_, total, nb, x->d_->C0, ldc0});
+        BatchUpdate u{};
+        u.segs[0] = Seg{x->V_, total, x->ld_};
+        u.nseg = 1;
+        u.N = x->N_;
+        u.C = x->d_->C0;
+        u.ldc = ldc0;
+        u.T = T;
+        u.ldt = x->ld_;
+        u.skip = nullptr;
+        u1.push_back(u);
+        BatchProj q{};
+        q.segs[0] = Seg{x->V_, total, x->ld_};
+        q.nseg = 1;
+        q.N = x->N_;
+        q.T = T;
+        q.ldt = x->ld_;
+        q.partial = x->partial_;
+        q.C = x->d_->C1;
+        q.skip = &x->d_->skip2;
+        p2.push_back(q);
+        u.C = x->d_->C1;
+        u.ldc = total;
+        u.skip = &x->d_->skip2;
+        u2.push_back(u);
+        x->count(8.0 * x->N_ * total + 2.0 * x->N8() * nb);
+      }
+      small_dgks_batch(dg, up, s);
+      ts_update_batch(nb, u1, up, s);
+      std::vector<int> nb2;
+      tsgemm_tn_batch(nb, p2, nb2, up, s);
+      ts_update_batch(nb, u2, up, s);
+    }
+    // Cholesky QR twice; the Cholesky kernels sum the Gram partial sums
+    for (int pass = 1; pass <= 2; ++pass) {
+      std::vector<BatchProj> pg;
+      for (Solver* x : a) {
+        double* T = x->V_ + x->gc_ * x->ld_;
+        BatchProj q{};
+        q.segs[0] = Seg{T, nb, x->ld_};
+        q.nseg = 1;
+        q.N = x->N_;
+        q.T = T;
+        q.ldt = x->ld_;
+        q.partial = x->partial_;
+        pg.push_back(q);
+      }
+      std::vector<int> nbk;
+      tsgemm_tn_batch(nb, pg, nbk, up, s);
+      std::vector<CholArgs> ch;
+      std::vector<BatchScale> sc;
+      for (size_t j = 0; j < a.size(); ++j) {
+        Solver* x = a[j];
+        double* T = x->V_ + x->gc_ * x->ld_;
+        const int total = x->gc_;
+        ch.push_back(CholArgs{x->d_, nb, pass, pass == 1 ? x->d_->C0 + total : nullptr,
+                              pass == 1 ? total + nb : 0, x->partial_, nbk[j]});
+        sc.push_back(BatchScale{T, x->ld_, x->N_, pass == 1 ? x->d_->R1inv : x->d_->R2inv,
+                                pass == 2 ? x->Tc_ : nullptr});
+        if (pass == 2) x->count(x->N8() * nb * 7.0);
+      }
+      small_chol_batch(ch, up, s);
+      ts_scale_batch(nb, sc, up, s);
+    }
+    // W's new columns: C T by A then A^T, then into the basis layout
+    products(a, nb);
+    std::vector<BatchUnpack> un;
+    std::vector<BatchProj> ph;
+    for (Solver* x : a) {
+      double* Wcol = x->W_ + x->gc_ * x->ld_;
+      un.push_back(BatchUnpack{x->Wc_, x->N_, Wcol, x->ld_});
+      BatchProj q{};
+      q.segs[0] = Seg{x->V_, x->gc_ + nb, x->ld_};
+      q.nseg = 1;
+      q.N = x->N_;
+      q.T = Wcol;
+      q.ldt = x->ld_;
+      q.partial = x->partial_;
+      ph.push_back(q);
+      x->count(2.0 * x->N8() * nb + x->N8() * (x->gc_ + 2 * nb));
+    }
+    unpack_batch(nb, un, up, s);
+    std::vector<int> nbh;
+    tsgemm_tn_batch(nb, ph, nbh, up, s);
+    std::vector<BatchReduce> rh;
+    std::vector<HAppendArgs> ha;
+    std::vector<ExtractArgs> ex;
+    for (size_t j = 0; j < a.size(); ++j) {
+      Solver* x = a[j];
+      rh.push_back(BatchReduce{x->partial_, nbh[j], (x->gc_ + nb) * nb, x->d_->Hn, nullptr});
+      ha.push_back(HAppendArgs{x->d_, x->gc_, nb});
+    }
+    reduce_partials_batch(rh, up, s);
+    small_h_append_batch(ha, up, s);
+    for (Solver* x : a) {
+      x->gc_ += nb;
+      x->s1_.last_nb = nb;
+      ++x->s1_.iters;
+      ex.push_back(ExtractArgs{x->d_, x->gc_, x->largest_ ? 1 : 0});
+    }
+    small_extract_batch(ex, up, s);
+  }
+
+  // stage 1 of every solver, from s1_begin (done) to the round its control
+  // step ends it
+  void run() {
+    up.init((size_t)64 << 20, s);
+    std::vector<Solver*> act = sv;  // solvers still in stage 1
+    std::vector<Solver*> live = sv; // solvers whose residual and control run this round
+    const bool verbose = std::getenv("SVDS_DEBUG") != nullptr;
+    double t_enq = 0.0, t_wait = 0.0;
+    int64_t rounds = 0;
+    while (!act.empty()) {
+      const double ta = now();
+      ++rounds;
+      residual(live);
+      std::vector<ControlArgs> ca;
+      for (Solver* x : live) ca.push_back(x->control_args(x->s1_params(std::min(x->gc_, x->k_ + x->b_))));
+      small_control_batch(ca, up, s);
+      const double tb = now();
+      t_enq += tb - ta;
+      std::vector<std::pair<Solver*, Ctl>> go;
+      std::vector<Solver*> next;
+      for (Solver* x : live) {
+        const Ctl c = x->control_wait();
+        x->trace("s1b", (int)x->s1_.iters, c, std::min(x->gc_, x->k_ + x->b_));
+        const int what = x->s1_decide(c);
+        if (what == 1) continue;  // stage 1 ends for this solver
+        next.push_back(x);
+        if (what == 0) go.push_back({x, c});
+      }
+      up.reset();  // every copy of this round has executed (the records were read)
+      const double tc = now();
+      t_wait += tc - tb;
+      act = next;
+      // restarts, then the corrections of each block width
+      std::vector<BatchGemm> rs;
+      std::vector<std::pair<Solver*, int>> restarted;
+      for (auto& q : go) {
+        Solver* x = q.first;
+        const Ctl& c = q.second;
+        if (!c.restart) continue;
+        x->count(2.0 * x->N8() * (x->gc_ + c.nr));
+        rs.push_back(BatchGemm{x->V_, x->ld_, x->gc_, x->N_, x->d_->Yr, kLd, c.nr, x->Vt_, x->ld_});
+        rs.push_back(BatchGemm{x->W_, x->ld_, x->gc_, x->N_, x->d_->Yr, kLd, c.nr, x->Wt_, x->ld_});
+        restarted.push_back({x, c.nr});
+      }
+      ts_gemm_nn_batch(rs, up, s);
+      for (auto& q : restarted) q.first->s1_restarted(q.second);
+      std::map<int, std::vector<Solver*>> byb;
+      for (auto& q : go) {
+        Solver* x = q.first;
+        int nb = q.second.nblock;
+        if (nb == 0) {  // nothing left to correct: a random block (rare)
+          nb = x->b_;
+          x->count(x->N8() * nb);
+          x->fill_random_block(nb);
+          x->ortho_and_append(nb);
+          continue;
+        }
+        byb[nb].push_back(x);
+      }
+      for (auto& g : byb) expand(g.second, g.first);
+      live = act;
+      t_enq += now() - tc;
+    }
+    SVDS_HIP(hipStreamSynchronize(s));
+    if (verbose)
+      std::fprintf(stderr, "[svds] in step: %zu solvers, %lld rounds, host %.3f s enqueuing, "
+                           "%.3f s waiting for control records\n",
+                   sv.size(), (long long)rounds, t_enq, t_wait);
+  }
+};
 
 }  // namespace svds
 
@@ -2025,13 +2422,15 @@ int svds_solve(const svds_csr* A, int k, int target, double tol, const svds_opts
   });
 }
 
-int svds_solve_batched(int nprob, const svds_csr* A, int k, int target, double tol,
-                       const svds_opts* opts, double* const* sigma, double* const* U,
-                       const int64_t* ldu, double* const* V, const int64_t* ldv,
-                       double* const* rnorm, svds_stats* stats, int nworkers, void* stream) {
-  if (nprob < 0 || (nprob > 0 && (!A || !sigma || !U || !ldu || !V || !ldv || !rnorm)))
-    return SVDS_ERR_ARG;
-  if (nprob == 0) return SVDS_OK;
+namespace {
+
+// the previous design of the batched solve: host workers, each driving its
+// own stream through whole solves (used when the options do not allow the
+// solves to run in step)
+int solve_batched_workers(int nprob, const svds_csr* A, int k, int target, double tol,
+                          const svds_opts* opts, double* const* sigma, double* const* U,
+                          const int64_t* ldu, double* const* V, const int64_t* ldv,
+                          double* const* rnorm, svds_stats* stats, int nworkers, void* stream) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return SVDS_ERR_HIP;
   const int nw = std::max(1, std::min(nprob, nworkers > 0 ? nworkers : 16));
@@ -2079,6 +2478,96 @@ int svds_solve_batched(int nprob, const svds_csr* A, int k, int target, double t
     (void)hipStreamSynchronize(streams[w]);
     (void)hipStreamDestroy(streams[w]);
   }
+  int worst = SVDS_OK;
+  for (int x : rc) {
+    if (x < 0 && (worst >= 0 || x < worst)) worst = x;
+    else if (worst >= 0 && x > worst) worst = x;
+  }
+  return worst;
+}
+
+// problems solved in step per group: the group's arrays live together
+constexpr int kStepGroup = 128;
+
+// the solves of problems [i0, i1) in step on stream s (their inputs checked);
+// rc: per-problem status
+void solve_in_step(int i0, int i1, const svds_csr* A, int k, int target, double tol,
+                   const svds_opts& o, double* const* sigma, double* const* U,
+                   const int64_t* ldu, double* const* V, const int64_t* ldv,
+                   double* const* rnorm, svds_stats* stats, hipStream_t s, std::vector<int>& rc) {
+  const int np = i1 - i0;
+  std::vector<svds_matrix*> hs(np, nullptr);
+  struct Guard {
+    std::vector<svds_matrix*>& h;
+    ~Guard() {
+      for (svds_matrix* x : h) destroy_matrix(x);
+    }
+  } guard{hs};
+  std::vector<std::unique_ptr<svds::Solver>> sol(np);
+  std::vector<svds_stats> local(np);
+  const int b = o.block_size > 0 ? o.block_size : 1;
+  for (int j = 0; j < np; ++j) {
+    const int i = i0 + j;
+    create_matrix(&A[i], &hs[j], s, true);
+    if (ldu[i] < hs[j]->m || ldv[i] < hs[j]->n)
+      throw Error(SVDS_ERR_ARG, "leading dimension too small");
+    checked_opts(hs[j], k, target, &o);
+    svds::Csr32 a = hs[j]->A, at = hs[j]->At;
+    launch_shapes(hs[j], b, false, o.autotune != 0, a, at, s);
+    sol[j].reset(new svds::Solver(hs[j], a, at, a, at, k, target, tol, o, s));
+    sol[j]->prepare(stats ? &stats[i] : &local[j]);
+  }
+  std::vector<svds::Solver*> step;
+  for (int j = 0; j < np; ++j)
+    if (svds::BatchStage1::eligible(*sol[j])) step.push_back(sol[j].get());
+  for (svds::Solver* x : step) x->s1_start();
+  if (!step.empty()) {
+    svds::BatchStage1 bs;
+    bs.sv = step;
+    bs.s = s;
+    bs.run();
+  }
+  for (int j = 0; j < np; ++j) {
+    const int i = i0 + j;
+    svds_stats* st = stats ? &stats[i] : &local[j];
+    svds::Solver* x = sol[j].get();
+    const bool done = svds::BatchStage1::eligible(*x);
+    if (done) {
+      int status1 = 2;
+      x->s1_end_default(&status1, st);
+      st->stage1_status = status1;
+    }
+    rc[i] = x->complete(sigma[i], U[i], ldu[i], V[i], ldv[i], rnorm[i], st, done);
+  }
+}
+
+}  // namespace
+
+int svds_solve_batched(int nprob, const svds_csr* A, int k, int target, double tol,
+                       const svds_opts* opts, double* const* sigma, double* const* U,
+                       const int64_t* ldu, double* const* V, const int64_t* ldv,
+                       double* const* rnorm, svds_stats* stats, int nworkers, void* stream) {
+  if (nprob < 0 || (nprob > 0 && (!A || !sigma || !U || !ldu || !V || !ldv || !rnorm)))
+    return SVDS_ERR_ARG;
+  if (nprob == 0) return SVDS_OK;
+  const svds_opts o = opts ? *opts : default_opts();
+  // in step: FP64 stage 1 with no preconditioner or point Jacobi, no timing
+  const bool step = nworkers <= 0 && o.precision == SVDS_FP64 &&
+                    o.method != SVDS_METHOD_AUGMENTED &&
+                    (o.precond == SVDS_PC_NONE || o.precond == SVDS_PC_JACOBI) && !o.profile;
+  if (!step)
+    return solve_batched_workers(nprob, A, k, target, tol, opts, sigma, U, ldu, V, ldv, rnorm,
+                                 stats, nworkers, stream);
+  std::vector<int> rc(nprob, SVDS_OK);
+  const int code = guarded([&] {
+    if (target != SVDS_LARGEST && target != SVDS_SMALLEST) throw Error(SVDS_ERR_ARG, "target");
+    if (!(tol > 0.0 && tol < 1.0)) throw Error(SVDS_ERR_ARG, "tol must be in (0, 1)");
+    for (int i0 = 0; i0 < nprob; i0 += kStepGroup)
+      solve_in_step(i0, std::min(nprob, i0 + kStepGroup), A, k, target, tol, o, sigma, U, ldu,
+                    V, ldv, rnorm, stats, (hipStream_t)stream, rc);
+    return SVDS_OK;
+  });
+  if (code != SVDS_OK) return code;
   int worst = SVDS_OK;
   for (int x : rc) {
     if (x < 0 && (worst >= 0 || x < worst)) worst = x;

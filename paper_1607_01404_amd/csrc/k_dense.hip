@@ -4,6 +4,8 @@
 // a wavefront is 64 consecutive doubles.  Reductions over the N rows are done
 // in two fixed-order phases (per-workgroup partials, then a column reduction)
 // so that results do not depend on scheduling.
+#include <type_traits>
+
 #include "common.h"
 
 namespace svds {
@@ -69,16 +71,29 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NA], double* sh
 constexpr int kCPW = 4;   // basis columns per wavefront (16 per workgroup column)
 constexpr int kTU = 8;    // 64-row groups per step: all their loads are issued first
 
+template <typename TB>
+struct TsgemmArgs {
+  Segs3T<TB> segs;
+  int total;
+  int64_t N;
+  const double* T;
+  int64_t ldt, chunk;
+  double* partial;
+  const int* skip;
+};
+
+// workgroup (bx, by) of a launch with gx workgroup columns
 template <int B, typename TB>
-__global__ __launch_bounds__(kThreads) void k_tsgemm_tn(Segs3T<TB> segs, int total, int64_t N,
-                                                        const double* __restrict__ T,
-                                                        int64_t ldt, int64_t chunk,
-                                                        double* __restrict__ partial,
-                                                        const int* __restrict__ skip) {
-  if (skip && *skip) return;  // device-side decision: this pass is not needed (uniform)
+__device__ __forceinline__ void tsgemm_body(const TsgemmArgs<TB>& A, int bx, int by, int gx) {
+  const Segs3T<TB>& segs = A.segs;
+  const int total = A.total;
+  const int64_t N = A.N, ldt = A.ldt, chunk = A.chunk;
+  const double* __restrict__ T = A.T;
+  double* __restrict__ partial = A.partial;
+  if (A.skip && *A.skip) return;  // device-side decision: this pass is not needed (uniform)
   __shared__ double red[4][kCPW * B];
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  const int g0 = blockIdx.y * 4;
+  const int g0 = by * 4;
   const int ncg = min(4, (total + kCPW - 1) / kCPW - g0);  // column groups here, 1..4
   const int spl = 4 / ncg;                                  // wavefronts per group
   const int grp = w % ncg, sub = w / ncg;
@@ -95,7 +110,7 @@ __global__ __launch_bounds__(kThreads) void k_tsgemm_tn(Segs3T<TB> segs, int tot
   double acc[kCPW * B];
 #pragma unroll
   for (int a = 0; a < kCPW * B; ++a) acc[a] = 0.0;
-  const int bid = xcd_block(blockIdx.x, gridDim.x);
+  const int bid = xcd_block(bx, gx);
   const int64_t rb = (int64_t)bid * chunk;
   const int64_t re = (rb + chunk < N) ? rb + chunk : N;
   constexpr int64_t kStep = kWave * kTU;
@@ -133,24 +148,51 @@ __global__ __launch_bounds__(kThreads) void k_tsgemm_tn(Segs3T<TB> segs, int tot
     double v = red[w][lane];
     for (int q = 1; q < spl; ++q) v += red[grp + q * ncg][lane];
     if (c0 + jj < total)
-      partial[((int64_t)c * total + c0 + jj) * gridDim.x + blockIdx.x] = v;
+      partial[((int64_t)c * total + c0 + jj) * gx + bx] = v;
   }
 }
 
+template <int B, typename TB>
+__global__ __launch_bounds__(kThreads) void k_tsgemm_tn(TsgemmArgs<TB> a) {
+  tsgemm_body<B, TB>(a, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+template <int B>
+__global__ __launch_bounds__(kThreads) void k_tsgemm_tn_batch(const TsgemmArgs<double>* a,
+                                                              BTiles t) {
+  const BTile q = batch_tile(t, blockIdx.x);
+  tsgemm_body<B, double>(a[q.p], q.x, q.y, q.gx);
+}
+
 // one wavefront per output: out[o] = sum over blocks of P[o * nblk + block]
+struct ReduceArgs {
+  const double* P;
+  int nblk;
+  double* out;
+  const int* skip;
+};
+
+__device__ __forceinline__ void reduce_body(const ReduceArgs& A, int o) {
+  if (A.skip && *A.skip) {  // the producing pass was skipped: its result is zero
+    if (threadIdx.x == 0) A.out[o] = 0.0;
+    return;
+  }
+  const double* p = A.P + (int64_t)o * A.nblk;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < A.nblk; b += 64) s += p[b];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) A.out[o] = s;
+}
+
 __global__ __launch_bounds__(64) void k_reduce_partials(const double* __restrict__ P, int nblk,
                                                         double* __restrict__ out,
                                                         const int* __restrict__ skip) {
-  const int o = blockIdx.x;
-  if (skip && *skip) {  // the producing pass was skipped: its result is zero
-    if (threadIdx.x == 0) out[o] = 0.0;
-    return;
-  }
-  const double* p = P + (int64_t)o * nblk;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += 64) s += p[b];
-  s = wave_sum(s);
-  if (threadIdx.x == 0) out[o] = s;
+  reduce_body(ReduceArgs{P, nblk, out, skip}, blockIdx.x);
+}
+
+__global__ __launch_bounds__(64) void k_reduce_partials_batch(const ReduceArgs* a, BTiles t) {
+  const BTile q = batch_tile(t, blockIdx.x);
+  reduce_body(a[q.p], q.x);
 }
 
 void reduce_partials(const double* P, int nblk, int nout, double* out, hipStream_t s,
@@ -178,20 +220,28 @@ static Segs3T<TB> make_segs(const SegT<TB>* segs, int nseg, int& total) {
   return s;
 }
 
-template <int B, typename TB>
-static int tsgemm_b(const Segs3T<TB>& sg, int total, int64_t N, const double* T, int64_t ldt,
-                    double* partial, double* C, hipStream_t s, const int* skip) {
-  // one contiguous row range per workgroup column (several 256-row steps
-  // amortise the final wave reductions)
-  int nb = std::min(reduce_blocks(N), 256);
-  int64_t chunk = (N + nb - 1) / nb;
+// launch geometry of the projection: one contiguous row range per workgroup
+// column (several 256-row steps amortise the final wave reductions)
+static void tsgemm_geom(int64_t N, int total, int& nb, int64_t& chunk, int& gy) {
+  nb = std::min(reduce_blocks(N), 256);
+  chunk = (N + nb - 1) / nb;
   chunk = (chunk + kWave * kTU - 1) / (kWave * kTU) * (kWave * kTU);
   nb = (int)((N + chunk - 1) / chunk);
   if (nb >= 64 && nb % 8) {  // whole XCD rounds for the remap
     nb = (nb + 7) / 8 * 8;
   }
-  dim3 grid(nb, (total + 4 * kCPW - 1) / (4 * kCPW));
-  k_tsgemm_tn<B, TB><<<grid, kThreads, 0, s>>>(sg, total, N, T, ldt, chunk, partial, skip);
+  gy = (total + 4 * kCPW - 1) / (4 * kCPW);
+}
+
+template <int B, typename TB>
+static int tsgemm_b(const Segs3T<TB>& sg, int total, int64_t N, const double* T, int64_t ldt,
+                    double* partial, double* C, hipStream_t s, const int* skip) {
+  int nb = 0, gy = 0;
+  int64_t chunk = 0;
+  tsgemm_geom(N, total, nb, chunk, gy);
+  dim3 grid(nb, gy);
+  k_tsgemm_tn<B, TB><<<grid, kThreads, 0, s>>>(
+      TsgemmArgs<TB>{sg, total, N, T, ldt, chunk, partial, skip});
   SVDS_LAUNCH_CHECK();
   if (C) reduce_partials(partial, nb, total * B, C, s, skip);
   return nb;
@@ -236,21 +286,35 @@ template void tsgemm_tn<float>(const SegT<float>*, int, int64_t, const double*, 
 // ---------------------------------------------------------------------------
 // T -= [segs] C      (C: total x b, column-major)
 // ---------------------------------------------------------------------------
+template <typename TB>
+struct UpdateArgs {
+  Segs3T<TB> segs;
+  int total;
+  int64_t N;
+  const double* C;
+  int ldc;
+  double* T;
+  int64_t ldt;
+  const int* skip;
+};
+
 template <int B, typename TB>
-__global__ __launch_bounds__(kThreads) void k_ts_update(Segs3T<TB> segs, int total, int64_t N,
-                                                        const double* __restrict__ C, int ldc,
-                                                        double* __restrict__ T, int64_t ldt,
-                                                        const int* __restrict__ skip) {
-  if (skip && *skip) return;
+__device__ __forceinline__ void update_body(const UpdateArgs<TB>& A, int bx, int gx) {
+  const Segs3T<TB>& segs = A.segs;
+  const int total = A.total, ldc = A.ldc;
+  const int64_t N = A.N, ldt = A.ldt;
+  const double* __restrict__ C = A.C;
+  double* __restrict__ T = A.T;
+  if (A.skip && *A.skip) return;
   __shared__ double cs[kMaxSegCols * B];
   for (int a = threadIdx.x; a < total * B; a += kThreads) {
     int j = a / B, c = a % B;
     cs[a] = C[(int64_t)c * ldc + j];
   }
   __syncthreads();
-  const int bid = xcd_block(blockIdx.x, gridDim.x);
+  const int bid = xcd_block(bx, gx);
   for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < N;
-       i += (int64_t)gridDim.x * kThreads) {
+       i += (int64_t)gx * kThreads) {
     double t[B];
 #pragma unroll
     for (int c = 0; c < B; ++c) t[c] = T[i + c * ldt];
@@ -264,6 +328,18 @@ __global__ __launch_bounds__(kThreads) void k_ts_update(Segs3T<TB> segs, int tot
   }
 }
 
+template <int B, typename TB>
+__global__ __launch_bounds__(kThreads) void k_ts_update(UpdateArgs<TB> a) {
+  update_body<B, TB>(a, blockIdx.x, gridDim.x);
+}
+
+template <int B>
+__global__ __launch_bounds__(kThreads) void k_ts_update_batch(const UpdateArgs<double>* a,
+                                                              BTiles t) {
+  const BTile q = batch_tile(t, blockIdx.x);
+  update_body<B, double>(a[q.p], q.x, q.gx);
+}
+
 template <typename TB>
 void ts_update(const SegT<TB>* segs, int nseg, int64_t N, const double* C, int ldc, double* T,
                int64_t ldt, int b, hipStream_t s, const int* skip) {
@@ -274,7 +350,9 @@ void ts_update(const SegT<TB>* segs, int nseg, int64_t N, const double* C, int l
   int nb = reduce_blocks(N);
   switch (b) {
 #define CASE(BB) \
-  case BB: k_ts_update<BB, TB><<<nb, kThreads, 0, s>>>(sg, total, N, C, ldc, T, ldt, skip); break;
+  case BB:                                                                           \
+    k_ts_update<BB, TB><<<nb, kThreads, 0, s>>>(UpdateArgs<TB>{sg, total, N, C, ldc, T, ldt, skip}); \
+    break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
     default: throw Error(SVDS_ERR_ARG, "ts_update: b must be 1..8");
@@ -292,22 +370,36 @@ template void ts_update<float>(const SegT<float>*, int, int64_t, const double*, 
 constexpr int kOC = 24;
 
 template <typename TI, typename TO>
-__global__ __launch_bounds__(kThreads) void k_gemm_nn(const TI* __restrict__ Q, int64_t ldq,
-                                                      int nq, int64_t N,
-                                                      const double* __restrict__ Y, int64_t ldy,
-                                                      int nout, TO* __restrict__ Out,
-                                                      int64_t ldo) {
+struct GemmArgs {
+  const TI* Q;
+  int64_t ldq;
+  int nq;
+  int64_t N;
+  const double* Y;
+  int64_t ldy;
+  int nout;
+  TO* Out;
+  int64_t ldo;
+};
+
+template <typename TI, typename TO>
+__device__ __forceinline__ void gemm_body(const GemmArgs<TI, TO>& A, int bx, int by, int gx) {
+  const TI* __restrict__ Q = A.Q;
+  const double* __restrict__ Y = A.Y;
+  TO* __restrict__ Out = A.Out;
+  const int64_t ldq = A.ldq, N = A.N, ldy = A.ldy, ldo = A.ldo;
+  const int nq = A.nq, nout = A.nout;
   __shared__ double ys[kMaxBasis * kOC];
-  const int o0 = blockIdx.y * kOC;
+  const int o0 = by * kOC;
   const int no = min(kOC, nout - o0);
   for (int a = threadIdx.x; a < nq * kOC; a += kThreads) {
     int j = a / kOC, o = a % kOC;
     ys[a] = (o < no) ? Y[(int64_t)(o0 + o) * ldy + j] : 0.0;
   }
   __syncthreads();
-  const int bid = xcd_block(blockIdx.x, gridDim.x);
+  const int bid = xcd_block(bx, gx);
   for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < N;
-       i += (int64_t)gridDim.x * kThreads) {
+       i += (int64_t)gx * kThreads) {
     double acc[kOC];
 #pragma unroll
     for (int o = 0; o < kOC; ++o) acc[o] = 0.0;
@@ -333,12 +425,24 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nn(const TI* __restrict__ Q, 
 }
 
 template <typename TI, typename TO>
+__global__ __launch_bounds__(kThreads) void k_gemm_nn(GemmArgs<TI, TO> a) {
+  gemm_body<TI, TO>(a, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+__global__ __launch_bounds__(kThreads) void k_gemm_nn_batch(const GemmArgs<double, double>* a,
+                                                            BTiles t) {
+  const BTile q = batch_tile(t, blockIdx.x);
+  gemm_body<double, double>(a[q.p], q.x, q.y, q.gx);
+}
+
+template <typename TI, typename TO>
 void ts_gemm_nn(const TI* Q, int64_t ldq, int nq, int64_t N, const double* Y, int64_t ldy,
                 int nout, TO* Out, int64_t ldo, hipStream_t s) {
   if (nout <= 0 || N == 0) return;
   if (nq > kMaxBasis) throw Error(SVDS_ERR_ARG, "gemm: inner dimension too large");
   dim3 grid(reduce_blocks(N), (nout + kOC - 1) / kOC);
-  k_gemm_nn<TI, TO><<<grid, kThreads, 0, s>>>(Q, ldq, nq, N, Y, ldy, nout, Out, ldo);
+  k_gemm_nn<TI, TO><<<grid, kThreads, 0, s>>>(
+      GemmArgs<TI, TO>{Q, ldq, nq, N, Y, ldy, nout, Out, ldo});
   SVDS_LAUNCH_CHECK();
 }
 template void ts_gemm_nn<double, double>(const double*, int64_t, int, int64_t, const double*,
@@ -351,16 +455,25 @@ template void ts_gemm_nn<float, double>(const float*, int64_t, int, int64_t, con
 // ---------------------------------------------------------------------------
 // T <- T Rinv (upper triangular b x b, column-major), optional row-major copy
 // ---------------------------------------------------------------------------
+struct ScaleArgs {
+  double* T;
+  int64_t ldt, N;
+  const double* Rinv;
+  double* compact;
+};
+
 template <int B>
-__global__ __launch_bounds__(kThreads) void k_ts_scale(double* __restrict__ T, int64_t ldt,
-                                                       int64_t N, const double* __restrict__ Rinv,
-                                                       double* __restrict__ compact) {
+__device__ __forceinline__ void scale_body(const ScaleArgs& A, int bx, int gx) {
+  double* __restrict__ T = A.T;
+  const int64_t ldt = A.ldt, N = A.N;
+  const double* __restrict__ Rinv = A.Rinv;
+  double* __restrict__ compact = A.compact;
   __shared__ double r[B * B];
   for (int a = threadIdx.x; a < B * B; a += kThreads) r[a] = Rinv[a];
   __syncthreads();
-  const int bid = xcd_block(blockIdx.x, gridDim.x);
+  const int bid = xcd_block(bx, gx);
   for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < N;
-       i += (int64_t)gridDim.x * kThreads) {
+       i += (int64_t)gx * kThreads) {
     double t[B], o[B];
 #pragma unroll
     for (int c = 0; c < B; ++c) t[c] = T[i + c * ldt];
@@ -380,12 +493,23 @@ __global__ __launch_bounds__(kThreads) void k_ts_scale(double* __restrict__ T, i
   }
 }
 
+template <int B>
+__global__ __launch_bounds__(kThreads) void k_ts_scale(ScaleArgs a) {
+  scale_body<B>(a, blockIdx.x, gridDim.x);
+}
+
+template <int B>
+__global__ __launch_bounds__(kThreads) void k_ts_scale_batch(const ScaleArgs* a, BTiles t) {
+  const BTile q = batch_tile(t, blockIdx.x);
+  scale_body<B>(a[q.p], q.x, q.gx);
+}
+
 void ts_scale(double* T, int64_t ldt, int64_t N, int b, const double* Rinv, double* compact,
               hipStream_t s) {
   int nb = reduce_blocks(N);
   switch (b) {
 #define CASE(BB) \
-  case BB: k_ts_scale<BB><<<nb, kThreads, 0, s>>>(T, ldt, N, Rinv, compact); break;
+  case BB: k_ts_scale<BB><<<nb, kThreads, 0, s>>>(ScaleArgs{T, ldt, N, Rinv, compact}); break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
     default: throw Error(SVDS_ERR_ARG, "ts_scale: b must be 1..8");
@@ -399,16 +523,35 @@ void ts_scale(double* T, int64_t ldt, int64_t N, int b, const double* Rinv, doub
 // with lo = rows < nsplit (the v-half on B), hi = the rest (the u-half).
 // One pass over V and W (the "special kernels" of Section 3.3).
 // ---------------------------------------------------------------------------
+template <typename TB>
+struct ResidArgs {
+  const TB* V;
+  const TB* W;
+  int64_t ld, N, nsplit;
+  int g;
+  const double* Y;
+  int64_t ldy;
+  const double* theta;
+  int nc;
+  double* R;
+  int64_t ldr;
+  double* partial;
+};
+
 template <int NCC, int NS, typename TB>
-__global__ __launch_bounds__(kThreads) void k_residual(
-    const TB* __restrict__ V, const TB* __restrict__ W, int64_t ld, int64_t N,
-    int64_t nsplit, int g, const double* __restrict__ Y, int64_t ldy,
-    const double* __restrict__ theta, int nc, double* __restrict__ R, int64_t ldr,
-    double* __restrict__ partial) {
+__device__ __forceinline__ void resid_body(const ResidArgs<TB>& A, int bx, int by, int gx) {
+  const TB* __restrict__ V = A.V;
+  const TB* __restrict__ W = A.W;
+  const int64_t ld = A.ld, N = A.N, nsplit = A.nsplit, ldy = A.ldy, ldr = A.ldr;
+  const int g = A.g, nc = A.nc;
+  const double* __restrict__ Y = A.Y;
+  const double* __restrict__ theta = A.theta;
+  double* __restrict__ R = A.R;
+  double* __restrict__ partial = A.partial;
   __shared__ double ys[kMaxBasis * NCC];
   __shared__ double th[NCC];
   __shared__ double sh[4 * NS * NCC];
-  const int c0 = blockIdx.y * NCC;
+  const int c0 = by * NCC;
   const int ncc = min(NCC, nc - c0);
   for (int a = threadIdx.x; a < g * NCC; a += kThreads) {
     int j = a / NCC, c = a % NCC;
@@ -419,9 +562,9 @@ __global__ __launch_bounds__(kThreads) void k_residual(
   double acc[NS * NCC];
 #pragma unroll
   for (int a = 0; a < NS * NCC; ++a) acc[a] = 0.0;
-  const int bid = xcd_block(blockIdx.x, gridDim.x);
+  const int bid = xcd_block(bx, gx);
   for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < N;
-       i += (int64_t)gridDim.x * kThreads) {
+       i += (int64_t)gx * kThreads) {
     double x[NCC], w[NCC];
 #pragma unroll
     for (int c = 0; c < NCC; ++c) x[c] = w[c] = 0.0;
@@ -483,9 +626,20 @@ __global__ __launch_bounds__(kThreads) void k_residual(
     const int c = a / NS, q = a % NS;
     if (c < ncc) {
       double v = ((sh[a] + sh[NS * NCC + a]) + sh[2 * NS * NCC + a]) + sh[3 * NS * NCC + a];
-      partial[((int64_t)q * nc + c0 + c) * gridDim.x + blockIdx.x] = v;
+      partial[((int64_t)q * nc + c0 + c) * gx + bx] = v;
     }
   }
+}
+
+template <int NCC, int NS, typename TB>
+__global__ __launch_bounds__(kThreads) void k_residual(ResidArgs<TB> a) {
+  resid_body<NCC, NS, TB>(a, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+__global__ __launch_bounds__(kThreads) void k_residual_batch(const ResidArgs<double>* a,
+                                                             BTiles t) {
+  const BTile q = batch_tile(t, blockIdx.x);
+  resid_body<16, 1, double>(a[q.p], q.x, q.y, q.gx);
 }
 
 // nsplit >= N: one sum per candidate (||r||^2 in sums[c]); otherwise the six
@@ -499,15 +653,15 @@ int ts_residual(const TB* V, const TB* W, int64_t ld, int64_t N, int64_t nsplit,
   if (nsplit >= N) {
     constexpr int NCC = 16;
     dim3 grid(nb, (nc + NCC - 1) / NCC);
-    k_residual<NCC, 1, TB><<<grid, kThreads, 0, s>>>(V, W, ld, N, nsplit, g, Y, ldy, theta, nc,
-                                                      R, ldr, partial);
+    k_residual<NCC, 1, TB><<<grid, kThreads, 0, s>>>(
+        ResidArgs<TB>{V, W, ld, N, nsplit, g, Y, ldy, theta, nc, R, ldr, partial});
     SVDS_LAUNCH_CHECK();
     if (sums) reduce_partials(partial, nb, nc, sums, s);
   } else {
     constexpr int NCC = 8;
     dim3 grid(nb, (nc + NCC - 1) / NCC);
-    k_residual<NCC, 6, TB><<<grid, kThreads, 0, s>>>(V, W, ld, N, nsplit, g, Y, ldy, theta, nc,
-                                                      R, ldr, partial);
+    k_residual<NCC, 6, TB><<<grid, kThreads, 0, s>>>(
+        ResidArgs<TB>{V, W, ld, N, nsplit, g, Y, ldy, theta, nc, R, ldr, partial});
     SVDS_LAUNCH_CHECK();
     if (sums) reduce_partials(partial, nb, 6 * nc, sums, s);
   }
@@ -546,11 +700,20 @@ __global__ void k_pack(const double* __restrict__ A, int64_t lda, const double* 
   }
 }
 
+struct UnpackArgs {
+  const double* in;
+  int64_t N;
+  double* A;
+  int64_t lda;
+};
+
 template <int B>
-__global__ void k_unpack(const double* __restrict__ in, int64_t N, double* __restrict__ A,
-                         int64_t lda) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+__device__ __forceinline__ void unpack_body(const UnpackArgs& a, int bx, int gx) {
+  const double* __restrict__ in = a.in;
+  double* __restrict__ A = a.A;
+  const int64_t N = a.N, lda = a.lda;
+  int64_t i = (int64_t)bx * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gx * blockDim.x;
   for (; i < N; i += stride) {
     double v[B];
 #pragma unroll
@@ -558,6 +721,18 @@ __global__ void k_unpack(const double* __restrict__ in, int64_t N, double* __res
 #pragma unroll
     for (int c = 0; c < B; ++c) A[i + c * lda] = v[c];
   }
+}
+
+template <int B>
+__global__ void k_unpack(const double* __restrict__ in, int64_t N, double* __restrict__ A,
+                         int64_t lda) {
+  unpack_body<B>(UnpackArgs{in, N, A, lda}, blockIdx.x, gridDim.x);
+}
+
+template <int B>
+__global__ void k_unpack_batch(const UnpackArgs* a, BTiles t) {
+  const BTile q = batch_tile(t, blockIdx.x);
+  unpack_body<B>(a[q.p], q.x, q.gx);
 }
 
 #define SVDS_BLOCK_SWITCH(b, CALL)          \
@@ -594,15 +769,27 @@ void unpack_rows(const double* compact, int64_t N, int b, double* A, int64_t lda
 
 // T[:, c] = R[:, blk[c]] * dinv for the block's nb columns (blk on the device,
 // read once per workgroup into LDS)
+struct GatherArgs {
+  const double* R;
+  int64_t ldr;
+  const int* blk;
+  const double* dinv;
+  int64_t N;
+  double* T;
+  int64_t ldt;
+};
+
 template <int B>
-__global__ void k_gather(const double* __restrict__ R, int64_t ldr, const int* __restrict__ blk,
-                         const double* __restrict__ dinv, int64_t N, double* __restrict__ T,
-                         int64_t ldt) {
+__device__ __forceinline__ void gather_body(const GatherArgs& a, int bx, int gx) {
+  const double* __restrict__ R = a.R;
+  const double* __restrict__ dinv = a.dinv;
+  double* __restrict__ T = a.T;
+  const int64_t ldr = a.ldr, N = a.N, ldt = a.ldt;
   __shared__ int cols[B];
-  if (threadIdx.x < B) cols[threadIdx.x] = blk[threadIdx.x];
+  if (threadIdx.x < B) cols[threadIdx.x] = a.blk[threadIdx.x];
   __syncthreads();
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)bx * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gx * blockDim.x;
   for (; i < N; i += stride) {
     const double d = dinv ? dinv[i] : 1.0;
     double v[B];
@@ -611,6 +798,19 @@ __global__ void k_gather(const double* __restrict__ R, int64_t ldr, const int* _
 #pragma unroll
     for (int c = 0; c < B; ++c) T[i + c * ldt] = v[c] * d;
   }
+}
+
+template <int B>
+__global__ void k_gather(const double* __restrict__ R, int64_t ldr, const int* __restrict__ blk,
+                         const double* __restrict__ dinv, int64_t N, double* __restrict__ T,
+                         int64_t ldt) {
+  gather_body<B>(GatherArgs{R, ldr, blk, dinv, N, T, ldt}, blockIdx.x, gridDim.x);
+}
+
+template <int B>
+__global__ void k_gather_batch(const GatherArgs* a, BTiles t) {
+  const BTile q = batch_tile(t, blockIdx.x);
+  gather_body<B>(a[q.p], q.x, q.gx);
 }
 
 void gather_precond(const double* R, int64_t ldr, const int* d_blk, int nb, const double* dinv,
@@ -847,6 +1047,209 @@ void sign_factors(const double* V, int64_t ldv, int64_t N, int k, double* partia
   k_colargmax<<<grid, kThreads, 0, s>>>(V, ldv, N, k, pval, pidx);
   SVDS_LAUNCH_CHECK();
   k_sign_flip<<<k, kWave, 0, s>>>(pval, pidx, nb, k, V, ldv, f);
+  SVDS_LAUNCH_CHECK();
+}
+
+}  // namespace svds
+
+// ===========================================================================
+// batched steps
+// ===========================================================================
+namespace svds {
+
+namespace {
+template <class F>
+void block_switch(int b, F&& f) {
+  switch (b) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    case 7: f(std::integral_constant<int, 7>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    default: throw Error(SVDS_ERR_ARG, "batched step: block width must be 1..8");
+  }
+}
+}  // namespace
+
+void tsgemm_tn_batch(int b, const std::vector<BatchProj>& jobs, std::vector<int>& nblk,
+                     BatchUpload& up, hipStream_t s) {
+  const int np = (int)jobs.size();
+  nblk.assign(np, 0);
+  if (np == 0) return;
+  std::vector<TsgemmArgs<double>> args(np);
+  std::vector<int> gx(np), gy(np);
+  std::vector<BatchReduce> red;
+  for (int j = 0; j < np; ++j) {
+    const BatchProj& q = jobs[j];
+    int total = 0;
+    Segs3T<double> sg = make_segs(q.segs, q.nseg, total);
+    if (total > kMaxSegCols) throw Error(SVDS_ERR_ARG, "projection too wide");
+    int nb = 0, g2 = 0;
+    int64_t chunk = 0;
+    if (total > 0) tsgemm_geom(q.N, total, nb, chunk, g2);
+    args[j] = TsgemmArgs<double>{sg, total, q.N, q.T, q.ldt, chunk, q.partial, q.skip};
+    gx[j] = nb;
+    gy[j] = total > 0 ? g2 : 0;
+    nblk[j] = nb;
+    if (q.C && total > 0) red.push_back(BatchReduce{q.partial, nb, total * b, q.C, q.skip});
+  }
+  BTiles t;
+  const int tiles = up.tiles(gx, gy, t);
+  const TsgemmArgs<double>* d = up.put(args.data(), args.size());
+  if (tiles > 0)
+    block_switch(b, [&](auto B) {
+      k_tsgemm_tn_batch<decltype(B)::value><<<tiles, kThreads, 0, s>>>(d, t);
+    });
+  SVDS_LAUNCH_CHECK();
+  if (!red.empty()) reduce_partials_batch(red, up, s);
+}
+
+void reduce_partials_batch(const std::vector<BatchReduce>& jobs, BatchUpload& up, hipStream_t s) {
+  const int np = (int)jobs.size();
+  if (np == 0) return;
+  std::vector<ReduceArgs> args(np);
+  std::vector<int> gx(np), gy(np, 1);
+  for (int j = 0; j < np; ++j) {
+    args[j] = ReduceArgs{jobs[j].P, jobs[j].nblk, jobs[j].out, jobs[j].skip};
+    gx[j] = jobs[j].nout;
+    if (jobs[j].nout <= 0) gy[j] = 0;
+  }
+  BTiles t;
+  const int tiles = up.tiles(gx, gy, t);
+  const ReduceArgs* d = up.put(args.data(), args.size());
+  if (tiles > 0) k_reduce_partials_batch<<<tiles, 64, 0, s>>>(d, t);
+  SVDS_LAUNCH_CHECK();
+}
+
+void ts_update_batch(int b, const std::vector<BatchUpdate>& jobs, BatchUpload& up, hipStream_t s) {
+  const int np = (int)jobs.size();
+  if (np == 0) return;
+  std::vector<UpdateArgs<double>> args(np);
+  std::vector<int> gx(np), gy(np, 1);
+  for (int j = 0; j < np; ++j) {
+    const BatchUpdate& q = jobs[j];
+    int total = 0;
+    Segs3T<double> sg = make_segs(q.segs, q.nseg, total);
+    if (total > kMaxSegCols) throw Error(SVDS_ERR_ARG, "update too wide");
+    args[j] = UpdateArgs<double>{sg, total, q.N, q.C, q.ldc, q.T, q.ldt, q.skip};
+    gx[j] = reduce_blocks(q.N);
+    if (total == 0) gy[j] = 0;
+  }
+  BTiles t;
+  const int tiles = up.tiles(gx, gy, t);
+  const UpdateArgs<double>* d = up.put(args.data(), args.size());
+  if (tiles > 0)
+    block_switch(b, [&](auto B) {
+      k_ts_update_batch<decltype(B)::value><<<tiles, kThreads, 0, s>>>(d, t);
+    });
+  SVDS_LAUNCH_CHECK();
+}
+
+void ts_gemm_nn_batch(const std::vector<BatchGemm>& jobs, BatchUpload& up, hipStream_t s) {
+  const int np = (int)jobs.size();
+  if (np == 0) return;
+  std::vector<GemmArgs<double, double>> args(np);
+  std::vector<int> gx(np), gy(np);
+  for (int j = 0; j < np; ++j) {
+    const BatchGemm& q = jobs[j];
+    if (q.nq > kMaxBasis) throw Error(SVDS_ERR_ARG, "gemm: inner dimension too large");
+    args[j] = GemmArgs<double, double>{q.Q, q.ldq, q.nq, q.N, q.Y, q.ldy, q.nout, q.Out, q.ldo};
+    gx[j] = reduce_blocks(q.N);
+    gy[j] = (q.nout <= 0 || q.N == 0) ? 0 : (q.nout + kOC - 1) / kOC;
+  }
+  BTiles t;
+  const int tiles = up.tiles(gx, gy, t);
+  const GemmArgs<double, double>* d = up.put(args.data(), args.size());
+  if (tiles > 0) k_gemm_nn_batch<<<tiles, kThreads, 0, s>>>(d, t);
+  SVDS_LAUNCH_CHECK();
+}
+
+void ts_scale_batch(int b, const std::vector<BatchScale>& jobs, BatchUpload& up, hipStream_t s) {
+  const int np = (int)jobs.size();
+  if (np == 0) return;
+  std::vector<ScaleArgs> args(np);
+  std::vector<int> gx(np), gy(np, 1);
+  for (int j = 0; j < np; ++j) {
+    const BatchScale& q = jobs[j];
+    args[j] = ScaleArgs{q.T, q.ldt, q.N, q.Rinv, q.compact};
+    gx[j] = reduce_blocks(q.N);
+  }
+  BTiles t;
+  const int tiles = up.tiles(gx, gy, t);
+  const ScaleArgs* d = up.put(args.data(), args.size());
+  if (tiles > 0)
+    block_switch(b, [&](auto B) {
+      k_ts_scale_batch<decltype(B)::value><<<tiles, kThreads, 0, s>>>(d, t);
+    });
+  SVDS_LAUNCH_CHECK();
+}
+
+void ts_residual_batch(const std::vector<BatchResid>& jobs, BatchUpload& up, hipStream_t s) {
+  const int np = (int)jobs.size();
+  if (np == 0) return;
+  constexpr int NCC = 16;
+  std::vector<ResidArgs<double>> args(np);
+  std::vector<int> gx(np), gy(np);
+  std::vector<BatchReduce> red;
+  for (int j = 0; j < np; ++j) {
+    const BatchResid& q = jobs[j];
+    if (q.g > kMaxBasis) throw Error(SVDS_ERR_ARG, "residual: basis too large");
+    args[j] = ResidArgs<double>{q.V, q.W, q.ld, q.N, q.N, q.g, q.Y, q.ldy, q.theta, q.nc,
+                                q.R, q.ldr, q.partial};
+    gx[j] = reduce_blocks(q.N);
+    gy[j] = (q.nc + NCC - 1) / NCC;
+    if (q.sums) red.push_back(BatchReduce{q.partial, gx[j], q.nc, q.sums, nullptr});
+  }
+  BTiles t;
+  const int tiles = up.tiles(gx, gy, t);
+  const ResidArgs<double>* d = up.put(args.data(), args.size());
+  if (tiles > 0) k_residual_batch<<<tiles, kThreads, 0, s>>>(d, t);
+  SVDS_LAUNCH_CHECK();
+  if (!red.empty()) reduce_partials_batch(red, up, s);
+}
+
+void gather_batch(int nb, const std::vector<BatchGather>& jobs, BatchUpload& up, hipStream_t s) {
+  const int np = (int)jobs.size();
+  if (np == 0) return;
+  std::vector<GatherArgs> args(np);
+  std::vector<int> gx(np), gy(np, 1);
+  for (int j = 0; j < np; ++j) {
+    const BatchGather& q = jobs[j];
+    args[j] = GatherArgs{q.R, q.ldr, q.blk, q.dinv, q.N, q.T, q.ldt};
+    gx[j] = (int)std::min<int64_t>(8192, (q.N + 255) / 256);
+    if (gx[j] < 1) gy[j] = 0;
+  }
+  BTiles t;
+  const int tiles = up.tiles(gx, gy, t);
+  const GatherArgs* d = up.put(args.data(), args.size());
+  if (tiles > 0)
+    block_switch(nb, [&](auto B) {
+      k_gather_batch<decltype(B)::value><<<tiles, 256, 0, s>>>(d, t);
+    });
+  SVDS_LAUNCH_CHECK();
+}
+
+void unpack_batch(int nb, const std::vector<BatchUnpack>& jobs, BatchUpload& up, hipStream_t s) {
+  const int np = (int)jobs.size();
+  if (np == 0) return;
+  std::vector<UnpackArgs> args(np);
+  std::vector<int> gx(np), gy(np, 1);
+  for (int j = 0; j < np; ++j) {
+    const BatchUnpack& q = jobs[j];
+    args[j] = UnpackArgs{q.compact, q.N, q.A, q.lda};
+    gx[j] = (int)std::min<int64_t>(8192, (q.N + 255) / 256);
+    if (gx[j] < 1) gy[j] = 0;
+  }
+  BTiles t;
+  const int tiles = up.tiles(gx, gy, t);
+  const UnpackArgs* d = up.put(args.data(), args.size());
+  if (tiles > 0)
+    block_switch(nb, [&](auto B) {
+      k_unpack_batch<decltype(B)::value><<<tiles, 256, 0, s>>>(d, t);
+    });
   SVDS_LAUNCH_CHECK();
 }
 

@@ -743,7 +743,7 @@ void small_svd(int g, const double* R, int ldr, double* s, double* Y, int ldy, d
 // ---------------------------------------------------------------------------
 // projected matrix: append the new columns Hn ((gc+nb) x nb, ld gc+nb)
 // ---------------------------------------------------------------------------
-__global__ void k_h_append(Small* d, int gc, int nb) {
+__device__ __forceinline__ void h_append_body(Small* d, int gc, int nb) {
   const int tot = gc + nb;
   // previous eigenvectors stay a good start: W <- diag(W, I); a projected
   // matrix built from nothing starts from W = I with no diagonal block
@@ -771,11 +771,18 @@ __global__ void k_h_append(Small* d, int gc, int nb) {
   }
 }
 
+__global__ void k_h_append(Small* d, int gc, int nb) { h_append_body(d, gc, nb); }
+__global__ void k_h_append_batch(const HAppendArgs* a) {
+  const HAppendArgs q = a[blockIdx.x];
+  h_append_body(q.d, q.gc, q.nb);
+}
+
 // second-pass test of classical Gram-Schmidt (Daniel, Gragg, Kaufman and
 // Stewart): after one pass against an orthonormal basis a column whose norm
 // fell by less than a factor sqrt(2) is orthogonal to working accuracy, so
 // the second pass is needed only when some column lost more
-__global__ void k_dgks(Small* d, int total, int nb, const double* __restrict__ C0, int ldc0) {
+__device__ __forceinline__ void dgks_body(Small* d, int total, int nb, const double* __restrict__ C0,
+                                          int ldc0) {
   const int lane = threadIdx.x;
   int need = 0;
   for (int c = 0; c < nb; ++c) {
@@ -786,6 +793,14 @@ __global__ void k_dgks(Small* d, int total, int nb, const double* __restrict__ C
     if (!(s <= 0.5 * g0)) need = 1;
   }
   if (lane == 0) d->skip2 = need ? 0 : 1;
+}
+
+__global__ void k_dgks(Small* d, int total, int nb, const double* __restrict__ C0, int ldc0) {
+  dgks_body(d, total, nb, C0, ldc0);
+}
+__global__ void k_dgks_batch(const DgksArgs* a) {
+  const DgksArgs q = a[blockIdx.x];
+  dgks_body(q.d, q.total, q.nb, q.C0, q.ldc0);
 }
 
 __global__ void k_record_bad(Small* d, int step) {
@@ -845,7 +860,7 @@ __device__ void load_sym_h(const Small* d, int g, double* A) {
 // them again and the threshold Jacobi finishes on the exact projection (one
 // active sweep in practice), so the rounding of the warm basis never
 // accumulates from one extraction to the next.  Otherwise Jacobi runs from W.
-__global__ __launch_bounds__(kEigT) void k_extract_rr(Small* d, int gc, int descending) {
+__device__ __forceinline__ void extract_rr_body(Small* d, int gc, int descending) {
   __shared__ double A[kLd * kLs];
   __shared__ double Z[kLd * kLs];
   __shared__ double Mx[kLd * kLs];
@@ -880,6 +895,14 @@ __global__ __launch_bounds__(kEigT) void k_extract_rr(Small* d, int gc, int desc
     d->warm_g = gc;
     d->warm_diag = gc;
   }
+}
+
+__global__ __launch_bounds__(kEigT) void k_extract_rr(Small* d, int gc, int descending) {
+  extract_rr_body(d, gc, descending);
+}
+__global__ __launch_bounds__(kEigT) void k_extract_rr_batch(const ExtractArgs* a) {
+  const ExtractArgs q = a[blockIdx.x];
+  extract_rr_body(q.d, q.gc, q.descending);
 }
 
 __global__ __launch_bounds__(kT) void k_extract_refined(Small* d, int gc) {
@@ -931,9 +954,8 @@ void small_extract(Small* d, int gc, int descending, int refined, hipStream_t s)
 // collapsed during projection against the pre-projection norms stored as the
 // last nb rows of C0), which = 2 writes R2/R2inv.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kCholT) void k_chol(Small* d, int nb, int which, const double* G0,
-                                                int ldg0, const double* __restrict__ P,
-                                                int nblk) {
+__device__ __forceinline__ void chol_body(Small* d, int nb, int which, const double* G0, int ldg0,
+                                          const double* __restrict__ P, int nblk) {
   __shared__ double G[kMaxBlock * kMaxBlock], g0[kMaxBlock];
   __shared__ double R[kMaxBlock * kMaxBlock], Ri[kMaxBlock * kMaxBlock];
   __shared__ int sbad;
@@ -1001,6 +1023,16 @@ __global__ __launch_bounds__(kCholT) void k_chol(Small* d, int nb, int which, co
     if (which == 1) d->bad = sbad;
     else if (sbad) d->bad |= sbad;
   }
+}
+
+__global__ __launch_bounds__(kCholT) void k_chol(Small* d, int nb, int which, const double* G0,
+                                                int ldg0, const double* __restrict__ P,
+                                                int nblk) {
+  chol_body(d, nb, which, G0, ldg0, P, nblk);
+}
+__global__ __launch_bounds__(kCholT) void k_chol_batch(const CholArgs* a) {
+  const CholArgs q = a[blockIdx.x];
+  chol_body(q.d, q.nb, q.which, q.G0, q.ldg0, q.P, q.nblk);
 }
 
 void small_chol(Small* d, int nb, int which, const double* G0, int ldg0, hipStream_t s,
@@ -1421,8 +1453,8 @@ __device__ void control_body(Small* d, const CtlParams& P, Ctl& C) {
 // lanes 1..63 could reach host memory after the sequence word, and a host
 // polling that word could take the new number with words of the previous
 // record.)  The host also checks the checksum before it accepts the record.
-__global__ __launch_bounds__(kT) void k_control(Small* d, CtlParams P, Ctl* host, int* seqp,
-                                               int seq) {
+__device__ __forceinline__ void control_kernel_body(Small* d, const CtlParams& P, Ctl* host,
+                                                    int* seqp, int seq) {
   __shared__ Ctl rec;
   control_body(d, P, rec);
   if (host) {
@@ -1450,6 +1482,15 @@ __global__ __launch_bounds__(kT) void k_control(Small* d, CtlParams P, Ctl* host
   }
 }
 
+__global__ __launch_bounds__(kT) void k_control(Small* d, CtlParams P, Ctl* host, int* seqp,
+                                               int seq) {
+  control_kernel_body(d, P, host, seqp, seq);
+}
+__global__ __launch_bounds__(kT) void k_control_batch(const ControlArgs* a) {
+  const ControlArgs& q = a[blockIdx.x];
+  control_kernel_body(q.d, q.P, q.host, q.seqp, q.seq);
+}
+
 void small_control(Small* d, const CtlParams& p, hipStream_t s, Ctl* host, int* seqp, int seq) {
   if (p.nc > kKmax + 8 || p.gc > kGmax) throw Error(SVDS_ERR_ARG, "control: sizes");
   k_control<<<1, kT, 0, s>>>(d, p, host, seqp, seq);
@@ -1464,4 +1505,40 @@ void small_final_rr(int k, double* G, int ldg, int descending, double* lam, doub
   small_eig(k, G, ldg, descending, lam, Z, ldz, s);
 }
 
+// batched single-workgroup steps
+void small_h_append_batch(const std::vector<HAppendArgs>& a, BatchUpload& up, hipStream_t s) {
+  if (a.empty()) return;
+  k_h_append_batch<<<(unsigned)a.size(), kT, 0, s>>>(up.put(a.data(), a.size()));
+  SVDS_LAUNCH_CHECK();
+}
+
+void small_dgks_batch(const std::vector<DgksArgs>& a, BatchUpload& up, hipStream_t s) {
+  if (a.empty()) return;
+  k_dgks_batch<<<(unsigned)a.size(), kWave, 0, s>>>(up.put(a.data(), a.size()));
+  SVDS_LAUNCH_CHECK();
+}
+
+void small_extract_batch(const std::vector<ExtractArgs>& a, BatchUpload& up, hipStream_t s) {
+  if (a.empty()) return;
+  for (const ExtractArgs& q : a)
+    if (q.gc < 1 || q.gc > kGmax) throw Error(SVDS_ERR_ARG, "extract: basis size");
+  k_extract_rr_batch<<<(unsigned)a.size(), kEigT, 0, s>>>(up.put(a.data(), a.size()));
+  SVDS_LAUNCH_CHECK();
+}
+
+void small_chol_batch(const std::vector<CholArgs>& a, BatchUpload& up, hipStream_t s) {
+  if (a.empty()) return;
+  k_chol_batch<<<(unsigned)a.size(), kCholT, 0, s>>>(up.put(a.data(), a.size()));
+  SVDS_LAUNCH_CHECK();
+}
+
+void small_control_batch(const std::vector<ControlArgs>& a, BatchUpload& up, hipStream_t s) {
+  if (a.empty()) return;
+  for (const ControlArgs& q : a)
+    if (q.P.nc > kKmax + 8 || q.P.gc > kGmax) throw Error(SVDS_ERR_ARG, "control: sizes");
+  k_control_batch<<<(unsigned)a.size(), kT, 0, s>>>(up.put(a.data(), a.size()));
+  SVDS_LAUNCH_CHECK();
+}
+
 }  // namespace svds
+

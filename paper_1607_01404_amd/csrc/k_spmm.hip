@@ -119,18 +119,30 @@ __global__ __launch_bounds__(256) void k_spmm_group(const int32_t* __restrict__ 
 // one coalesced load per step; each group then starts on its row's nonzeros
 // at once instead of waiting for its own row-pointer loads.  Same lane
 // arithmetic and summation order as k_spmm_group.
+template <typename TV>
+struct NatArgs {
+  const int32_t* rp;
+  const int32_t* ci;
+  const TV* val;
+  int64_t nrows;
+  const TV* X;
+  TV* Y;
+};
+
 template <typename TV, int B, int L, int U>
-__global__ __launch_bounds__(256) void k_spmm_nat(const int32_t* __restrict__ rp,
-                                                  const int32_t* __restrict__ ci,
-                                                  const TV* __restrict__ val, int64_t nrows,
-                                                  const TV* __restrict__ X,
-                                                  TV* __restrict__ Y) {
+__device__ __forceinline__ void nat_body(const NatArgs<TV>& A, int bx, int gx) {
+  const int32_t* __restrict__ rp = A.rp;
+  const int32_t* __restrict__ ci = A.ci;
+  const TV* __restrict__ val = A.val;
+  const TV* __restrict__ X = A.X;
+  TV* __restrict__ Y = A.Y;
+  const int64_t nrows = A.nrows;
   constexpr int RPB = 256 / L;
   __shared__ int32_t rps[RPB + 1];
   const int grp = threadIdx.x / L;
   const int lane = threadIdx.x % L;
-  const int bid = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t stride = (int64_t)gridDim.x * RPB;
+  const int bid = xcd_block(bx, gx);
+  const int64_t stride = (int64_t)gx * RPB;
   for (int64_t s0 = (int64_t)bid * RPB; s0 < nrows; s0 += stride) {
     __syncthreads();
     for (int t = threadIdx.x; t <= RPB; t += 256) {
@@ -189,6 +201,21 @@ __global__ __launch_bounds__(256) void k_spmm_nat(const int32_t* __restrict__ rp
       }
     }
   }
+}
+
+template <typename TV, int B, int L, int U>
+__global__ __launch_bounds__(256) void k_spmm_nat(const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ ci,
+                                                  const TV* __restrict__ val, int64_t nrows,
+                                                  const TV* __restrict__ X,
+                                                  TV* __restrict__ Y) {
+  nat_body<TV, B, L, U>(NatArgs<TV>{rp, ci, val, nrows, X, Y}, blockIdx.x, gridDim.x);
+}
+
+template <int B, int L, int U>
+__global__ __launch_bounds__(256) void k_spmm_nat_batch(const NatArgs<double>* a, BTiles t) {
+  const BTile q = batch_tile(t, blockIdx.x);
+  nat_body<double, B, L, U>(a[q.p], q.x, q.gx);
 }
 
 // one workgroup (256 lanes) per row, for rows longer than 4096
@@ -304,6 +331,71 @@ void spmm(const Csr32& A, int b, const double* X, double* Y, hipStream_t s) {
 void spmm_f32(const Csr32& A, int b, const float* X, float* Y, hipStream_t s) {
   if (!A.val32) throw Error(SVDS_ERR_ARG, "spmm_f32: no FP32 values");
   spmm_dispatch<float>(A, b, A.val32, X, Y, s);
+}
+
+// batched products of matrices that share one merged launch shape: each
+// matrix runs the workgroups of its own natural-order launch
+template <int B, int L>
+static void nat_batch_launch(int U, int tiles, const NatArgs<double>* d, const BTiles& t,
+                             hipStream_t s) {
+  switch (U) {
+    case 4: k_spmm_nat_batch<B, L, 4><<<tiles, 256, 0, s>>>(d, t); break;
+    case 2: k_spmm_nat_batch<B, L, 2><<<tiles, 256, 0, s>>>(d, t); break;
+    default: k_spmm_nat_batch<B, L, 1><<<tiles, 256, 0, s>>>(d, t); break;
+  }
+}
+
+template <int B>
+static void nat_batch_b(int bn, int U, int tiles, const NatArgs<double>* d, const BTiles& t,
+                        hipStream_t s) {
+  switch (bn) {
+    case 0: nat_batch_launch<B, 1>(U, tiles, d, t, s); break;
+    case 1: nat_batch_launch<B, 2>(U, tiles, d, t, s); break;
+    case 2: nat_batch_launch<B, 4>(U, tiles, d, t, s); break;
+    case 3: nat_batch_launch<B, 8>(U, tiles, d, t, s); break;
+    case 4: nat_batch_launch<B, 16>(U, tiles, d, t, s); break;
+    case 5: nat_batch_launch<B, 32>(U, tiles, d, t, s); break;
+    default: nat_batch_launch<B, 64>(U, tiles, d, t, s); break;
+  }
+}
+
+void spmm_batch(int b, const std::vector<BatchSpmm>& jobs, BatchUpload& up, hipStream_t s) {
+  const int np = (int)jobs.size();
+  if (np == 0) return;
+  const int bn = jobs[0].A->merged_bin, U = jobs[0].A->unroll;
+  if (bn < 0 || bn >= kNumBins - 1) throw Error(SVDS_ERR_ARG, "spmm_batch: needs a merged shape");
+  std::vector<NatArgs<double>> args(np);
+  std::vector<int> gx(np), gy(np, 1);
+  for (int j = 0; j < np; ++j) {
+    const Csr32& A = *jobs[j].A;
+    if (A.merged_bin != bn || A.unroll != U)
+      throw Error(SVDS_ERR_ARG, "spmm_batch: launch shapes differ");
+    args[j] = NatArgs<double>{A.rp, A.ci, A.val, A.rows, jobs[j].X, jobs[j].Y};
+    // the grid of the matrix's own merged launch (spmm_b)
+    const int64_t rpb = 256 / (1 << bn);
+    const int64_t need = (A.rows + rpb - 1) / rpb;
+    int blocks = (int)std::min<int64_t>(need, 16384);
+    if (blocks >= 64) blocks = (blocks / 8) * 8;
+    gx[j] = blocks;
+    if (A.rows <= 0 || blocks <= 0) gy[j] = 0;
+  }
+  BTiles t;
+  const int tiles = up.tiles(gx, gy, t);
+  const NatArgs<double>* d = up.put(args.data(), args.size());
+  if (tiles > 0) {
+    switch (b) {
+      case 1: nat_batch_b<1>(bn, U, tiles, d, t, s); break;
+      case 2: nat_batch_b<2>(bn, U, tiles, d, t, s); break;
+      case 3: nat_batch_b<3>(bn, U, tiles, d, t, s); break;
+      case 4: nat_batch_b<4>(bn, U, tiles, d, t, s); break;
+      case 5: nat_batch_b<5>(bn, U, tiles, d, t, s); break;
+      case 6: nat_batch_b<6>(bn, U, tiles, d, t, s); break;
+      case 7: nat_batch_b<7>(bn, U, tiles, d, t, s); break;
+      case 8: nat_batch_b<8>(bn, U, tiles, d, t, s); break;
+      default: throw Error(SVDS_ERR_ARG, "spmm_batch: block width must be 1..8");
+    }
+  }
+  SVDS_LAUNCH_CHECK();
 }
 
 }  // namespace svds

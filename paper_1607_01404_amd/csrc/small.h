@@ -121,6 +121,42 @@ void small_rr_append(Small* d, int gc, int nb, int total, hipStream_t s);
 // seq after the record has been written
 void small_control(Small* d, const CtlParams& p, hipStream_t s, Ctl* host = nullptr,
                    int* seqp = nullptr, int seq = 0);
+
+// batched single-workgroup steps: workgroup p runs problem p's step
+struct HAppendArgs {
+  Small* d;
+  int gc, nb;
+};
+struct DgksArgs {
+  Small* d;
+  int total, nb;
+  const double* C0;
+  int ldc0;
+};
+struct ExtractArgs {
+  Small* d;
+  int gc, descending;
+};
+struct CholArgs {
+  Small* d;
+  int nb, which;
+  const double* G0;
+  int ldg0;
+  const double* P;
+  int nblk;
+};
+struct ControlArgs {
+  Small* d;
+  CtlParams P;
+  Ctl* host;
+  int* seqp;
+  int seq;
+};
+void small_h_append_batch(const std::vector<HAppendArgs>& a, BatchUpload& up, hipStream_t s);
+void small_dgks_batch(const std::vector<DgksArgs>& a, BatchUpload& up, hipStream_t s);
+void small_extract_batch(const std::vector<ExtractArgs>& a, BatchUpload& up, hipStream_t s);
+void small_chol_batch(const std::vector<CholArgs>& a, BatchUpload& up, hipStream_t s);
+void small_control_batch(const std::vector<ControlArgs>& a, BatchUpload& up, hipStream_t s);
 void small_rtr_accumulate(const double* C0, int ldc0, const double* C1, int total, int nb,
                           double* Cout, hipStream_t s);
 void small_final_rr(int k, double* G, int ldg, int descending, double* lam, double* Z, int ldz,

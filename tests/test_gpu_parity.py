@@ -292,6 +292,34 @@ def test_batched_matches_single_solves(P):
         _compare(A, *res[i][:4], res[i][4], ref, 1e-10, normA, what=f"batched {i} vs LAPACK")
 
 
+@pytest.mark.parametrize("precond", [0, 1])
+def test_batched_in_step_matches_single_solves(P, precond):
+    """svds_solve_batched with the problems in step (one launch per step of
+    the first-stage iteration for all problems): every problem's result,
+    counts included, is bit-identical to its own svds_solve; the singular
+    values match dense LAPACK."""
+    import torch
+    As = _batch(7, mmin=1500, mmax=7000)
+    dev = [P._lib.to_device(A) + A.shape for A in As]
+    opts = dict(block_size=8, max_basis_size=35, min_restart_size=14, seed=19, autotune=0,
+                precond=precond)
+    _say("batched in step", [A.shape for A in As], "k=4 smallest b=8 precond", precond)
+    rc, res = P.solve_batched(dev, 4, "smallest", 1e-10, nworkers=0, **opts)
+    assert rc == 0, [r[4] for r in res]
+    for i, (A, d) in enumerate(zip(As, dev)):
+        _say("single", i, A.shape)
+        sig, U, V, rn, st = P.solve(*d, 4, "smallest", 1e-10, **opts)
+        assert torch.equal(sig, res[i][0]) and torch.equal(U, res[i][1]) and torch.equal(V, res[i][2])
+        assert torch.equal(rn, res[i][3])
+        for key in ("matvecs", "iters", "restarts", "resets", "stage_exit"):
+            assert res[i][4][key] == st[key], (i, key, res[i][4][key], st[key])
+    for i in range(2):
+        A = As[i]
+        ref = np.sort(np.linalg.svd(A.toarray(), compute_uv=False))[:4]
+        _compare(A, *res[i][:4], res[i][4], ref, 1e-10, res[i][4]["norm_A_used"],
+                 what=f"in-step {i} vs LAPACK")
+
+
 def test_batched_empty_and_arguments(P):
     _say("batched empty")
     rc, res = P.solve_batched([], 4)
