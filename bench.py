@@ -202,13 +202,16 @@ def batched_extra(P, torch, nprob, nworkers=16):
         return time.perf_counter() - t0, out
 
     step16, _ = timed(sub, 0)
-    workers16, _ = timed(sub, nworkers)
     el, (rc, res) = timed(dev, 0)
     log(f"batched: in step {el:.2f} s")
-    elw, (rcw, resw) = timed(dev, nworkers)
-    log(f"batched: {nworkers} workers {elw:.2f} s")
-    same = all(bool((a[0] == b[0]).all()) and a[4]["matvecs"] == b[4]["matvecs"]
-               for a, b in zip(res, resw))
+    if nworkers > 0:  # the same problems on host workers, a stream each
+        workers16, _ = timed(sub, nworkers)
+        elw, (rcw, resw) = timed(dev, nworkers)
+        log(f"batched: {nworkers} workers {elw:.2f} s")
+        same = all(bool((a[0] == b[0]).all()) and a[4]["matvecs"] == b[4]["matvecs"]
+                   for a, b in zip(res, resw))
+    else:
+        workers16 = elw = rcw = same = None
     conv = sum(1 for r in res if r[4]["converged"])
     rmax = max(float(r[3].max()) / r[4]["norm_A_used"] for r in res)
     nnz = int(sum(A.nnz for A in mats))
@@ -228,7 +231,7 @@ def batched_extra(P, torch, nprob, nworkers=16):
                          "note": "counted iteration kernels of all problems over the batch's "
                                  "wall time (set-up, norm estimates, clean-up in the time only)"},
             "workers_seconds": elw, "workers": nworkers,
-            "workers_problems_per_second": nprob / elw, "workers_status": rcw,
+            "workers_problems_per_second": nprob / elw if elw else None, "workers_status": rcw,
             "same_results_as_workers": same,
             "first16_serial_seconds": serial16, "first16_in_step_seconds": step16,
             "first16_workers_seconds": workers16, "generation_seconds": gen}
@@ -394,7 +397,7 @@ def main():
                          "and the two-product comparison")
     ap.add_argument("--batched", type=int, default=256, help="problems in the batched extra (0: skip)")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--workers", type=int, default=16, help="host workers of the batched extra")
+    ap.add_argument("--workers", type=int, default=16, help="host workers of the batched extra's comparison (0: in step only)")
     ap.add_argument("--full-seconds", type=float, default=20.0,
                     help="time budget of each full-size convection-diffusion solve")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
