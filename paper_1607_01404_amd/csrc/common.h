@@ -65,6 +65,12 @@ void* stream_alloc(size_t bytes, hipStream_t s);
 void stream_free(void* p, hipStream_t s);
 // release every block the cache keeps for stream s (before s is destroyed)
 void stream_cache_drop(hipStream_t s);
+// small pinned host blocks (the solvers' control and status records), kept
+// for reuse per (device, size, flags): hipHostMalloc and hipHostFree are slow
+// and synchronise, which a batch of solves would otherwise pay per solver.
+// A block is zeroed when it is handed out.
+void* host_record_get(size_t bytes, unsigned flags);
+void host_record_put(void* p, size_t bytes, unsigned flags);
 
 // stream-ordered device allocations released together at the end of a call
 template <typename T>
@@ -86,11 +92,18 @@ struct DeviceBuffers {
   size_t cap = 0;        // its size in bytes
   size_t used = 0;       // bytes handed out from it (or counted)
   bool count_only = false;
+  void* owned = nullptr;  // one block of the stream-ordered cache holding every array
   explicit DeviceBuffers(hipStream_t st) : s(st) {}
   void use_workspace(void* p, size_t bytes) {
     base = static_cast<char*>(p);
     cap = bytes;
     used = 0;
+  }
+  // every array from one block of `bytes` taken from the stream-ordered
+  // cache (one allocation and one free per solve instead of one per array)
+  void own(size_t bytes) {
+    owned = stream_alloc(bytes, s);
+    use_workspace(owned, bytes);
   }
   template <typename T>
   T* get(size_t n) {
@@ -107,6 +120,7 @@ struct DeviceBuffers {
   }
   ~DeviceBuffers() {
     for (void* p : ptrs) stream_free(p, s);
+    stream_free(owned, s);
   }
 };
 

@@ -7,6 +7,7 @@
 #include <atomic>
 #include <map>
 #include <memory>
+#include <functional>
 #include <mutex>
 #include <chrono>
 #include <thread>
@@ -15,6 +16,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
@@ -142,6 +144,51 @@ void stream_free(void* p, hipStream_t s) {
   (void)hipFreeAsync(p, s);
 }
 
+namespace {
+struct HostRecords {
+  std::mutex mu;
+  std::map<std::tuple<int, size_t, unsigned>, std::vector<void*>> free;
+};
+HostRecords& host_records() {
+  static HostRecords* r = new HostRecords;  // lives until the process ends
+  return *r;
+}
+constexpr size_t kHostRecordsKept = 4096;  // blocks kept per (device, size, flags)
+}  // namespace
+
+void* host_record_get(size_t bytes, unsigned flags) {
+  int dev = 0;
+  SVDS_HIP(hipGetDevice(&dev));
+  void* p = nullptr;
+  {
+    HostRecords& r = host_records();
+    std::lock_guard<std::mutex> lk(r.mu);
+    auto it = r.free.find({dev, bytes, flags});
+    if (it != r.free.end() && !it->second.empty()) {
+      p = it->second.back();
+      it->second.pop_back();
+    }
+  }
+  if (!p) SVDS_HIP(hipHostMalloc(&p, bytes, flags));
+  std::memset(p, 0, bytes);
+  return p;
+}
+
+void host_record_put(void* p, size_t bytes, unsigned flags) {
+  if (!p) return;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    HostRecords& r = host_records();
+    std::lock_guard<std::mutex> lk(r.mu);
+    std::vector<void*>& v = r.free[{dev, bytes, flags}];
+    if (v.size() < kHostRecordsKept) {
+      v.push_back(p);
+      return;
+    }
+  }
+  (void)hipHostFree(p);
+}
+
 void stream_cache_drop(hipStream_t s) {
   BlockCache& c = block_cache();
   std::vector<void*> drop;
@@ -196,9 +243,9 @@ class Solver {
   }
   ~Solver() {
     for (hipEvent_t e : evpool_) (void)hipEventDestroy(e);
-    if (hctl_) (void)hipHostFree(hctl_);
-    if (hbad_) (void)hipHostFree(hbad_);
-    if (hjd_) (void)hipHostFree(hjd_);
+    host_record_put(hctl_, kCtlBytes, kCtlFlags);
+    host_record_put(hbad_, sizeof(int), hipHostMallocDefault);
+    host_record_put(hjd_, sizeof(JdCol) * kMaxBlock, hipHostMallocDefault);
   }
   Solver(const Solver&) = delete;
   Solver& operator=(const Solver&) = delete;
@@ -352,6 +399,11 @@ class Solver {
   double* partial_ = nullptr;
   double* dinv_ = nullptr;  // 1 / diag(A^T A) (ones where zero)
   Small* d_ = nullptr;
+  // the control record and the sequence word after it, in pinned coherent
+  // host memory mapped for the device
+  static constexpr size_t kSeqOff = (sizeof(Ctl) + 63) / 64 * 64;
+  static constexpr size_t kCtlBytes = kSeqOff + 64;
+  static constexpr unsigned kCtlFlags = hipHostMallocMapped | hipHostMallocCoherent;
   Ctl* hctl_ = nullptr;     // pinned, coherent
   Ctl* dctl_ = nullptr;     // its device address
   int* hseq_ = nullptr;     // sequence word beside the record (pinned, coherent)
@@ -869,6 +921,10 @@ class Solver {
   // stage 1 in pieces, which the batched driver runs for many solvers in step
  public:
   void s1_start() { s1_begin(); }
+  // the stream of the solve's launches; the in-step batched solve moves a
+  // prepared solver to its shared stream for stage 1 and back (its arrays
+  // stay with the stream they were allocated on)
+  void set_stream(hipStream_t s) { s_ = s; }
  private:
   struct S1State {
     int g = 0, r = 0;
@@ -1601,16 +1657,16 @@ void Solver::prepare(svds_stats* st) {
   std::memset(st, 0, sizeof(*st));
   const double t0 = now();
   run_t0_ = t0;
+  if (!buf_.base) buf_.own(workspace_bytes());  // no caller workspace: one block
   allocate(buf_);
   mixed_ = o_.precision == SVDS_MIXED;
-  constexpr size_t kSeqOff = (sizeof(Ctl) + 63) / 64 * 64;
-  SVDS_HIP(hipHostMalloc((void**)&hctl_, kSeqOff + 64, hipHostMallocMapped | hipHostMallocCoherent));
+  hctl_ = static_cast<Ctl*>(host_record_get(kCtlBytes, kCtlFlags));
   SVDS_HIP(hipHostGetDevicePointer((void**)&dctl_, hctl_, 0));
   hseq_ = reinterpret_cast<int*>(reinterpret_cast<char*>(hctl_) + kSeqOff);
   dseq_ = reinterpret_cast<int*>(reinterpret_cast<char*>(dctl_) + kSeqOff);
   __atomic_store_n(hseq_, 0, __ATOMIC_RELEASE);
-  SVDS_HIP(hipHostMalloc((void**)&hbad_, sizeof(int), hipHostMallocDefault));
-  SVDS_HIP(hipHostMalloc((void**)&hjd_, sizeof(JdCol) * kMaxBlock, hipHostMallocDefault));
+  hbad_ = static_cast<int*>(host_record_get(sizeof(int), hipHostMallocDefault));
+  hjd_ = static_cast<JdCol*>(host_record_get(sizeof(JdCol) * kMaxBlock, hipHostMallocDefault));
   if (o_.precond == SVDS_PC_JACOBI)
     invert_diag(M_->diagC, n_, dinv_, s_);  // 1/diag(C), with 1 where the column is empty
   if (o_.precond == SVDS_PC_LEARNED) setup_learned();
@@ -2487,15 +2543,43 @@ int solve_batched_workers(int nprob, const svds_csr* A, int k, int target, doubl
 }
 
 // problems solved in step per group: the group's arrays live together
-constexpr int kStepGroup = 128;
+constexpr int kStepGroup = 256;
+// host threads (and streams) of the in-step solve's set-up and clean-up
+constexpr int kStepWorkers = 16;
 
-// the solves of problems [i0, i1) in step on stream s (their inputs checked);
-// rc: per-problem status
+// f(w, j) for problem j of [0, np) on worker w, problems dealt round-robin
+// over nw host threads (worker 0 is the calling thread); the first exception
+// is rethrown after every worker has finished
+void deal(int nw, int np, int dev, const std::function<void(int, int)>& f) {
+  std::mutex mu;
+  std::exception_ptr first;
+  auto work = [&](int w) {
+    try {
+      (void)hipSetDevice(dev);
+      for (int j = w; j < np; j += nw) f(w, j);
+    } catch (...) {
+      std::lock_guard<std::mutex> lk(mu);
+      if (!first) first = std::current_exception();
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int w = 1; w < nw; ++w) pool.emplace_back(work, w);
+  work(0);
+  for (auto& t : pool) t.join();
+  if (first) std::rethrow_exception(first);
+}
+
+// the solves of problems [i0, i1) in step (their inputs checked): matrix
+// set-up, norm estimates and the first block on the worker streams ws, one
+// host thread each; stage 1 of every eligible solver in step on stream s;
+// clean-up again on the worker streams.  rc: per-problem status
 void solve_in_step(int i0, int i1, const svds_csr* A, int k, int target, double tol,
                    const svds_opts& o, double* const* sigma, double* const* U,
                    const int64_t* ldu, double* const* V, const int64_t* ldv,
-                   double* const* rnorm, svds_stats* stats, hipStream_t s, std::vector<int>& rc) {
+                   double* const* rnorm, svds_stats* stats, hipStream_t s,
+                   const std::vector<hipStream_t>& ws, int dev, std::vector<int>& rc) {
   const int np = i1 - i0;
+  const int nw = std::max(1, std::min<int>((int)ws.size(), np));
   std::vector<svds_matrix*> hs(np, nullptr);
   struct Guard {
     std::vector<svds_matrix*>& h;
@@ -2506,31 +2590,40 @@ void solve_in_step(int i0, int i1, const svds_csr* A, int k, int target, double 
   std::vector<std::unique_ptr<svds::Solver>> sol(np);
   std::vector<svds_stats> local(np);
   const int b = o.block_size > 0 ? o.block_size : 1;
-  for (int j = 0; j < np; ++j) {
+  const bool verbose = std::getenv("SVDS_DEBUG") != nullptr;
+  const double t0 = svds::now();
+  deal(nw, np, dev, [&](int w, int j) {
     const int i = i0 + j;
-    create_matrix(&A[i], &hs[j], s, true);
+    create_matrix(&A[i], &hs[j], ws[w], true);
     if (ldu[i] < hs[j]->m || ldv[i] < hs[j]->n)
       throw Error(SVDS_ERR_ARG, "leading dimension too small");
     checked_opts(hs[j], k, target, &o);
     svds::Csr32 a = hs[j]->A, at = hs[j]->At;
-    launch_shapes(hs[j], b, false, o.autotune != 0, a, at, s);
-    sol[j].reset(new svds::Solver(hs[j], a, at, a, at, k, target, tol, o, s));
+    launch_shapes(hs[j], b, false, o.autotune != 0, a, at, ws[w]);
+    sol[j].reset(new svds::Solver(hs[j], a, at, a, at, k, target, tol, o, ws[w]));
     sol[j]->prepare(stats ? &stats[i] : &local[j]);
-  }
+  });
+  for (int w = 0; w < nw; ++w) SVDS_HIP(hipStreamSynchronize(ws[w]));
+  const double t1 = svds::now();
   std::vector<svds::Solver*> step;
   for (int j = 0; j < np; ++j)
     if (svds::BatchStage1::eligible(*sol[j])) step.push_back(sol[j].get());
-  for (svds::Solver* x : step) x->s1_start();
+  for (svds::Solver* x : step) {
+    x->set_stream(s);
+    x->s1_start();
+  }
   if (!step.empty()) {
     svds::BatchStage1 bs;
     bs.sv = step;
     bs.s = s;
-    bs.run();
+    bs.run();  // ends with s synchronised
   }
-  for (int j = 0; j < np; ++j) {
+  const double t2 = svds::now();
+  deal(nw, np, dev, [&](int w, int j) {
     const int i = i0 + j;
     svds_stats* st = stats ? &stats[i] : &local[j];
     svds::Solver* x = sol[j].get();
+    x->set_stream(ws[w]);
     const bool done = svds::BatchStage1::eligible(*x);
     if (done) {
       int status1 = 2;
@@ -2538,7 +2631,18 @@ void solve_in_step(int i0, int i1, const svds_csr* A, int k, int target, double 
       st->stage1_status = status1;
     }
     rc[i] = x->complete(sigma[i], U[i], ldu[i], V[i], ldv[i], rnorm[i], st, done);
+  });
+  for (int w = 0; w < nw; ++w) SVDS_HIP(hipStreamSynchronize(ws[w]));
+  const double t3 = svds::now();
+  sol.clear();  // the solvers' arrays back to their streams' caches
+  for (svds_matrix*& h : hs) {
+    destroy_matrix(h);
+    h = nullptr;
   }
+  if (verbose)
+    std::fprintf(stderr, "[svds] in step group of %d: set-up %.3f s, stage 1 %.3f s, "
+                         "clean-up %.3f s on %d host threads, release %.3f s\n",
+                 np, t1 - t0, t2 - t1, t3 - t2, nw, svds::now() - t3);
 }
 
 }  // namespace
@@ -2562,9 +2666,48 @@ int svds_solve_batched(int nprob, const svds_csr* A, int k, int target, double t
   const int code = guarded([&] {
     if (target != SVDS_LARGEST && target != SVDS_SMALLEST) throw Error(SVDS_ERR_ARG, "target");
     if (!(tol > 0.0 && tol < 1.0)) throw Error(SVDS_ERR_ARG, "tol must be in (0, 1)");
+    int dev = 0;
+    SVDS_HIP(hipGetDevice(&dev));
+    const hipStream_t s = (hipStream_t)stream;
+    // the worker streams of set-up and clean-up; they wait for the caller's
+    // stream (the problems' inputs) and the caller's stream waits for them
+    const int nw = std::min(nprob, kStepWorkers);
+    const bool verbose = std::getenv("SVDS_DEBUG") != nullptr;
+    const double ta = svds::now();
+    struct Streams {
+      std::vector<hipStream_t> v;
+      bool verbose;
+      ~Streams() {
+        const double t = svds::now();
+        for (hipStream_t x : v) {
+          (void)hipStreamSynchronize(x);
+          svds::stream_cache_drop(x);  // blocks kept for a stream that ends here
+          (void)hipStreamSynchronize(x);
+          (void)hipStreamDestroy(x);
+        }
+        if (verbose)
+          std::fprintf(stderr, "[svds] batched: worker streams released in %.3f s\n", svds::now() - t);
+      }
+    } ws{{}, verbose};
+    for (int w = 0; w < nw; ++w) {
+      hipStream_t x = nullptr;
+      SVDS_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+      ws.v.push_back(x);
+    }
+    {
+      hipEvent_t ready;
+      SVDS_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+      (void)hipEventRecord(ready, s);
+      for (hipStream_t x : ws.v) (void)hipStreamWaitEvent(x, ready, 0);
+      (void)hipEventDestroy(ready);
+    }
+    const double tb = svds::now();
     for (int i0 = 0; i0 < nprob; i0 += kStepGroup)
       solve_in_step(i0, std::min(nprob, i0 + kStepGroup), A, k, target, tol, o, sigma, U, ldu,
-                    V, ldv, rnorm, stats, (hipStream_t)stream, rc);
+                    V, ldv, rnorm, stats, s, ws.v, dev, rc);
+    if (verbose)
+      std::fprintf(stderr, "[svds] batched: streams created in %.3f s, groups %.3f s\n", tb - ta,
+                   svds::now() - tb);
     return SVDS_OK;
   });
   if (code != SVDS_OK) return code;

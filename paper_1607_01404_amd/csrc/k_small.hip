@@ -75,7 +75,7 @@ __device__ void make_pairs(int np, unsigned char* pp, unsigned char* pq) {
 
 template <int NT>
 __device__ int jacobi_eig_lds(int n, double* A, double* Z, double* d, double* cs, double* sn,
-                              int* flag, double thr_floor = 0.0) {
+                              int* flag, double thr_floor = 0.0, double thr_rel = 0.25) {
   __shared__ double tt_[kLd / 2 + 1], apq_[kLd / 2 + 1];
   __shared__ int zero_[kLd / 2 + 1];
   __shared__ double red_[NT / kWave];
@@ -111,10 +111,10 @@ __device__ int jacobi_eig_lds(int n, double* A, double* Z, double* d, double* cs
   double fr = 0.0;
   for (int w = 0; w < NT / kWave; ++w) fr += red_[w];
   const double frob = sqrt(fr);
-  // off-diagonal entries below eps*||A||/4 are dropped: they move eigenvalues
-  // and residuals of the Ritz pairs by less than the rounding level of the
-  // projected matrix itself
-  const double thr = fmax(0.25 * kEps * frob, thr_floor);
+  // off-diagonal entries below thr_rel * eps * ||A||_F are dropped (by
+  // default eps ||A|| / 4): they move eigenvalues and residuals of the Ritz
+  // pairs by less than the rounding level of the projected matrix itself
+  const double thr = fmax(thr_rel * kEps * frob, thr_floor);
   // Threshold cyclic Jacobi on active rounds only: each sweep first scans all
   // off-diagonal entries and marks the rounds of the parallel ordering that
   // hold an entry above the threshold; only those rounds are processed.
@@ -296,9 +296,8 @@ __device__ void bordered_eig_lds(int g, int g0, double* A, double* Z, double* d,
       const double zi = (i < n) ? zv[i] : 0.0;
       const double li = (i < n) ? lam[i] : 0.0;
       const double zn = wave_sum(zi * zi);
-      double lm = fabs(li);
-#pragma unroll
-      for (int off = kWave / 2; off > 0; off >>= 1) lm = fmax(lm, __shfl_xor(lm, off, kWave));
+      // the poles are in ascending order: the largest magnitude is at an end
+      const double lm = (n > 0) ? fmax(fabs(lam[0]), fabs(lam[n - 1])) : 0.0;
       const double tol = 8.0 * kEps * fmax(fmax(lm, fabs(alpha)), sqrt(zn));
       const bool keep = i < n && fabs(zi) > tol;
       const unsigned long long kmask = __ballot(keep);
@@ -857,9 +856,14 @@ __device__ void load_sym_h(const Small* d, int g, double* A) {
 // previous eigenvectors, padded with the identity for new columns), where its
 // leading block is diagonal to rounding.  When the dense border is narrow the
 // bordered solver gives eigenvectors W U of that form; H is then projected on
-// them again and the threshold Jacobi finishes on the exact projection (one
-// active sweep in practice), so the rounding of the warm basis never
-// accumulates from one extraction to the next.  Otherwise Jacobi runs from W.
+// them again and the threshold Jacobi finishes on the exact projection, so
+// the rounding of the warm basis never accumulates from one extraction to the
+// next.  That projection, g-term dot products in FP64, carries off-diagonal
+// rounding of about sqrt(g) eps ||H|| by itself, so the finishing Jacobi
+// leaves entries below sqrt(g) eps ||H||_F alone: they are indistinguishable
+// from that rounding, change the Ritz values by their square over the gap and
+// the residuals by about their own size, below the eps ||C|| floor of the
+// convergence test (Section 3.2).  Otherwise Jacobi runs from W to eps/4.
 __device__ __forceinline__ void extract_rr_body(Small* d, int gc, int descending) {
   __shared__ double A[kLd * kLs];
   __shared__ double Z[kLd * kLs];
@@ -878,13 +882,15 @@ __device__ __forceinline__ void extract_rr_body(Small* d, int gc, int descending
   __syncthreads();
   if (warm) project_lds(gc, A, Z, Mx);
   const int g0 = warm ? d->warm_diag : -1;
-  if (warm && g0 >= 0 && g0 <= gc && gc - g0 <= kBordMax) {
+  const bool bordered = warm && g0 >= 0 && g0 <= gc && gc - g0 <= kBordMax;
+  if (bordered) {
     bordered_eig_lds<kEigT>(gc, g0, A, Z, dd, Mx, Vb, Bc);
     load_sym_h(d, gc, A);
     __syncthreads();
     project_lds(gc, A, Z, Mx);
   }
-  const int nsw = jacobi_eig_lds<kEigT>(gc, A, Z, dd, cs, sn, &flag);
+  const int nsw = jacobi_eig_lds<kEigT>(gc, A, Z, dd, cs, sn, &flag, 0.0,
+                                        bordered ? sqrt((double)gc) : 0.25);
   if (t == 0) d->eig_sweeps = nsw;
   sort_pairs(gc, dd, Z, descending, d->theta, d->Y, kLd);
   for (int a = t; a < gc * gc; a += kEigT) {
@@ -1097,12 +1103,22 @@ __device__ void control_body(Small* d, const CtlParams& P, Ctl& C) {
   __shared__ int stall_s[kKmax + 8];
   __shared__ bool conv[kKmax + 8], done[kKmax + 8];
   __shared__ double rn[kKmax + 8];
-  __shared__ double mx_s;
+  __shared__ bool pcf[kKmax + 8];
+  __shared__ double mx_s, s_nop0;
+  __shared__ int s_nprev, s_gprev, s_sweeps;
   {  // the record starts zeroed (C lives in LDS)
     unsigned int* w = reinterpret_cast<unsigned int*>(&C);
     for (int a = t; a < (int)(sizeof(Ctl) / sizeof(unsigned int)); a += kT) w[a] = 0u;
   }
   if (t == 0) s_bad = d->bad;
+  // the scalars of the decision, loaded in parallel with the arrays so that
+  // the serial decision below reads only LDS
+  if (t == kWave) {
+    s_nop0 = d->normop;
+    s_nprev = d->nprev;
+    s_gprev = d->gprev;
+    s_sweeps = d->eig_sweeps;
+  }
   for (int j = t; j < gc; j += kT) th_s[j] = d->theta[j];
   for (int j = t; j < (P.stage == 1 ? nc : 6 * nc); j += kT) sums_s[j] = d->sums[j];
   for (int j = t; j < nc; j += kT) {
@@ -1124,29 +1140,36 @@ __device__ void control_body(Small* d, const CtlParams& P, Ctl& C) {
     }
     return;
   }
+  const double nop = fmax(s_nop0, mx_s);
+  // the convergence tests of the candidates, one thread each
+  for (int c = t; c < nc; c += kT) {
+    const double r = sqrt(fmax(P.stage == 1 ? sums_s[c] : sums_s[0 * nc + c] + sums_s[3 * nc + c], 0.0));
+    rn[c] = r;
+    C.res[c] = r;
+    C.val[c] = th_s[c];
+    bool cv, pc = false;
+    if (P.stage == 1) {
+      const double thr = P.rel ? fmax(P.tol * fabs(th_s[c]), P.eps * nop)
+                               : fmax(sqrt(fabs(th_s[c]) * nop) * P.tol, P.eps * nop);
+      cv = r <= thr;
+      pc = !cv && stall_s[c] >= kStallRestarts && r <= P.gate * nop;
+    } else {
+      cv = false;
+      if (r <= 1.4142135623730951 * nop * P.tol)
+        cv = halves_res(sums_s, nc, c, th_s[c]) < P.normA * P.tol;
+    }
+    conv[c] = cv;
+    pcf[c] = pc;
+    done[c] = cv || pc;
+  }
+  __syncthreads();
   if (t == 0) {
     C.bad = 0;
-    d->normop = fmax(d->normop, mx_s);
-    const double nop = d->normop;
+    d->normop = nop;
     int ncv = 0, npc = 0;
     for (int c = 0; c < nc; ++c) {
-      rn[c] = sqrt(fmax(P.stage == 1 ? sums_s[c] : sums_s[0 * nc + c] + sums_s[3 * nc + c], 0.0));
-      C.res[c] = rn[c];
-      C.val[c] = th_s[c];
-      if (P.stage == 1) {
-        const double thr = P.rel ? fmax(P.tol * fabs(th_s[c]), P.eps * nop)
-                                 : fmax(sqrt(fabs(th_s[c]) * nop) * P.tol, P.eps * nop);
-        conv[c] = rn[c] <= thr;
-        const bool pc = !conv[c] && stall_s[c] >= kStallRestarts && rn[c] <= P.gate * nop;
-        done[c] = conv[c] || pc;
-        npc += pc;
-      } else {
-        conv[c] = false;
-        if (rn[c] <= 1.4142135623730951 * nop * P.tol)
-          conv[c] = halves_res(sums_s, nc, c, th_s[c]) < P.normA * P.tol;
-        done[c] = conv[c];
-      }
       ncv += conv[c];
+      npc += pcf[c];
     }
     int action = kExpand, nblock = 0, restart = 0, reff = 0, off = 0, peff = 0, lock = 0;
     int floor_reset = 0;
@@ -1228,7 +1251,7 @@ __device__ void control_body(Small* d, const CtlParams& P, Ctl& C) {
     }
     if (restart) {
       const int room = max(0, P.g - P.b - reff);
-      peff = (P.p > 0) ? min(min(P.p, d->nprev), room) : 0;
+      peff = (P.p > 0) ? min(min(P.p, s_nprev), room) : 0;
     }
     if (action == kReset) d->nprev = 0;
     {
@@ -1250,7 +1273,7 @@ __device__ void control_body(Small* d, const CtlParams& P, Ctl& C) {
     C.npc = npc;
     C.floor_reset = floor_reset;
     C.normop = nop;
-    C.eig_sweeps = d->eig_sweeps;
+    C.eig_sweeps = s_sweeps;
     C.maxres = maxres;
     C.minres = minres;
   }
@@ -1259,10 +1282,13 @@ __device__ void control_body(Small* d, const CtlParams& P, Ctl& C) {
   const int nblock = s_nblock;
   if (s_restart) {
     const int reff = s_reff, off = s_off, peff = s_peff;
-    // retained extraction vectors
-    for (int a = t; a < gc * reff; a += kT) {
+    // the extraction vectors staged in M (free until H is rotated below),
+    // the retained ones also in Yr
+    for (int a = t; a < gc * gc; a += kT) {
       const int i = a % gc, j = a / gc;
-      Yr[i * kLs + j] = d->Y[(off + j) * kLd + i];
+      const double y = d->Y[j * kLd + i];
+      M[i * kLs + j] = y;
+      if (j >= off && j < off + reff) Yr[i * kLs + (j - off)] = y;
     }
     __syncthreads();
     // +k: previous block coefficient vectors (zero padded), classical
@@ -1272,7 +1298,7 @@ __device__ void control_body(Small* d, const CtlParams& P, Ctl& C) {
     int nr = reff;
     for (int pv = 0; pv < peff; ++pv) {
       for (int i = t; i < kLd; i += kT)
-        yv[i] = (i < gc && i < d->gprev) ? d->yprev[pv * kLd + i] : 0.0;
+        yv[i] = (i < gc && i < s_gprev) ? d->yprev[pv * kLd + i] : 0.0;
       __syncthreads();
       const int nq = off + nr;
       for (int rep = 0; rep < 2; ++rep) {
@@ -1280,7 +1306,7 @@ __device__ void control_body(Small* d, const CtlParams& P, Ctl& C) {
           const int q = a / 16, l = a % 16;
           double acc = 0.0;
           for (int i = l; i < gc; i += 16)
-            acc = fma(yv[i], (q < off) ? d->Y[q * kLd + i] : Yr[i * kLs + (q - off)], acc);
+            acc = fma(yv[i], (q < off) ? M[i * kLs + q] : Yr[i * kLs + (q - off)], acc);
           acc = lane_sum<double, 16>(acc);
           if (l == 0) dots[q] = acc;
         }
@@ -1288,7 +1314,7 @@ __device__ void control_body(Small* d, const CtlParams& P, Ctl& C) {
         for (int i = t; i < gc; i += kT) {
           double y = yv[i];
           for (int q = 0; q < nq; ++q)
-            y -= dots[q] * ((q < off) ? d->Y[q * kLd + i] : Yr[i * kLs + (q - off)]);
+            y -= dots[q] * ((q < off) ? M[i * kLs + q] : Yr[i * kLs + (q - off)]);
           yv[i] = y;
         }
         __syncthreads();

@@ -109,11 +109,14 @@ void autotune_spmm(Csr32& A, int b, bool fp32, hipStream_t s) {
       best = c;
     }
   }
-  A.merged_bin = best.first;
-  A.unroll = best.second;
-  A.tuned_b = b;
+  // the first result stored for a signature is kept, and used by every solve
+  // with it (also by one that tuned at the same time on another stream), so
+  // that equal signatures always get equal launch shapes
   std::lock_guard<std::mutex> lk(g_mu);
-  g_cache.emplace(key, best);  // the first result for a signature is kept
+  const auto kept = g_cache.emplace(key, best).first->second;
+  A.merged_bin = kept.first;
+  A.unroll = kept.second;
+  A.tuned_b = b;
 }
 
 }  // namespace svds
