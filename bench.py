@@ -166,7 +166,7 @@ def _gen_batched(i):
     return synth.batched_problem(i)
 
 
-def batched_extra(P, torch, nprob, nworkers=16):
+def batched_extra(P, torch, nprob, nworkers=16, step_threads=16):
     """Batched workload: nprob independent problems (rows U{5000..200000}, cols rows/2,
     8-12 nnz/row), k = 4 smallest each, block 8.  svds_solve_batched with the problems in
     step (one launch per step of the first-stage iteration for all problems) against
@@ -186,7 +186,7 @@ def batched_extra(P, torch, nprob, nworkers=16):
     opts = dict(block_size=8, max_basis_size=35, min_restart_size=14, seed=2004)
     k = 4
     sub = dev[:16]
-    P.solve_batched(sub, k, "smallest", 1e-10, nworkers=0, **opts)  # warm-up and autotune
+    P.solve_batched(sub, k, "smallest", 1e-10, nworkers=-step_threads, **opts)  # warm-up, autotune
     torch.cuda.synchronize()
     t = time.perf_counter()
     for d in sub:
@@ -201,8 +201,8 @@ def batched_extra(P, torch, nprob, nworkers=16):
         torch.cuda.synchronize()
         return time.perf_counter() - t0, out
 
-    step16, _ = timed(sub, 0)
-    el, (rc, res) = timed(dev, 0)
+    step16, _ = timed(sub, -step_threads)
+    el, (rc, res) = timed(dev, -step_threads)
     log(f"batched: in step {el:.2f} s")
     if nworkers > 0:  # the same problems on host workers, a stream each
         workers16, _ = timed(sub, nworkers)
@@ -219,7 +219,8 @@ def batched_extra(P, torch, nprob, nworkers=16):
     return {"workload": f"{nprob} problems, rows U{{5000..200000}}, cols rows/2, 8-12 nnz/row, "
                         "N(0,1); k=4 smallest, block 8, basis 35, restart 14, tol 1e-10",
             "nnz_total": nnz, "seconds": el, "problems_per_second": nprob / el,
-            "mode": "in step: one launch per step of the first-stage iteration for all problems",
+            "mode": "in step: one launch per step of the first-stage iteration for all problems; "
+                    f"set-up and clean-up on {step_threads} host threads",
             "converged": conv, "status": rc, "max_rnorm_over_normA": rmax,
             "matvecs_total": int(sum(sum(r[4]["matvecs"]) for r in res)),
             "iters_max": int(max(r[4]["iters"][0] for r in res)),
@@ -397,6 +398,8 @@ def main():
                          "and the two-product comparison")
     ap.add_argument("--batched", type=int, default=256, help="problems in the batched extra (0: skip)")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--step-threads", type=int, default=16,
+                    help="host threads of the in-step batched solve's set-up and clean-up")
     ap.add_argument("--workers", type=int, default=16, help="host workers of the batched extra's comparison (0: in step only)")
     ap.add_argument("--full-seconds", type=float, default=20.0,
                     help="time budget of each full-size convection-diffusion solve")
@@ -433,7 +436,7 @@ def main():
         if args.only == "mixed":
             out = mixed_comparison(P, torch)
         elif args.only == "batched":
-            out = batched_extra(P, torch, max(args.batched, 16), args.workers)
+            out = batched_extra(P, torch, max(args.batched, 16), args.workers, args.step_threads)
         elif args.only in ("learned", "learned_full"):
             out, _ = learned_extra(P, torch, args.full_seconds, replica=args.only == "learned")
         elif args.only == "methods":
@@ -562,7 +565,7 @@ def main():
     if not args.no_extras:
         res["mixed_precision"] = mixed_comparison(P, torch)
         if args.batched > 0:
-            res["batched"] = batched_extra(P, torch, args.batched)
+            res["batched"] = batched_extra(P, torch, args.batched, args.workers, args.step_threads)
         params = None
         if not args.no_learned:
             res["learned_preconditioner"], params = learned_extra(P, torch, args.full_seconds)

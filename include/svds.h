@@ -325,20 +325,24 @@ int svds_stream_release(void* stream);
 /* nprob independent problems A[i] with the same k, target, tol and options;
  * outputs per problem as for svds_solve (sigma[i], U[i] with ldu[i], V[i] with
  * ldv[i], rnorm[i]; stats may be NULL or an array of nprob).
- * nworkers = 0: the problems run in step on `stream`, in groups of up to 128:
- * every step of a first-stage iteration (residual, control step,
+ * nworkers <= 0: the problems run in step on `stream`, in groups of up to
+ * 256: every step of a first-stage iteration (residual, control step,
  * restart, correction, both Gram-Schmidt passes, Cholesky QR, the products
  * with A and A^T, the new columns of H, the Rayleigh-Ritz extraction) is one
  * launch for all problems of the group, each problem computing exactly what
  * its own svds_solve computes (the same bits), and the host reads all control
- * records of a round together.  This needs FP64, no preconditioner or point
- * Jacobi, and opts.profile = 0; problems whose matrix has a one-pass plan
- * (svds_matrix_normal) run their own first stage.  The second stage and the
- * clean-up run per problem.  Otherwise, or with nworkers > 0, the problems are
- * distributed over that many (0: 16) host workers, each driving its own HIP
- * stream at default priority, and the caller's stream is made to wait for
- * them.  Returns the worst status over the problems (an error code if any
- * failed, else SVDS_NOT_CONVERGED if any ran out of budget, else SVDS_OK). */
+ * records of a round together.  The set-up before it (checks, transpose,
+ * ||A|| estimate, first block) and the second stage and clean-up after it run
+ * per problem on -nworkers host threads (0: 16), each with a stream of its
+ * own that waits for `stream` first; the call returns after all of it has
+ * finished.  This needs FP64, no preconditioner or point Jacobi, and
+ * opts.profile = 0; problems whose matrix has a one-pass plan
+ * (svds_matrix_normal) run their own first stage.  Otherwise, or with
+ * nworkers > 0, the problems are distributed over that many (0 or negative:
+ * |nworkers| or 16) host workers, each driving its own HIP stream at default
+ * priority, and the caller's stream is made to wait for them.  Returns the
+ * worst status over the problems (an error code if any failed, else
+ * SVDS_NOT_CONVERGED if any ran out of budget, else SVDS_OK). */
 int svds_solve_batched(int nprob, const svds_csr* A, int k, int target, double tol,
                        const svds_opts* opts, double* const* sigma, double* const* U,
                        const int64_t* ldu, double* const* V, const int64_t* ldv,

@@ -194,40 +194,64 @@ __device__ __forceinline__ int xcd_block(int bid, int nblocks) {
 // Batched launches: one launch per step of the iteration for many problems.
 // For each problem p the launch runs exactly the workgroups (x, y), x < gx_p,
 // y < gy_p, of that problem's own launch, with the same arguments, so every
-// problem gets the same bits as from its own launches.  pre[p] is the number
-// of workgroups before problem p (pre[np] = all); a workgroup finds its
-// problem by binary search (the last p with pre[p] <= its index).
+// problem gets the same bits as from its own launches.
+//
+// Placement: workgroup b of a launch runs on XCD b % 8 (the dispatcher deals
+// workgroups to the eight XCDs in turn), as slot b / 8 of that XCD.  The
+// problems' workgroups, in problem order, are cut into eight runs of equal
+// length, run x on XCD x: a problem is on one XCD, or on two or more
+// neighbouring XCDs when it is large, so the data a problem re-reads (the
+// block X of its sparse product, the block T of its projections) stays in
+// the L2 of the XCD that reads it instead of all problems sharing every L2.
+// An XCD's run is a list of segments (problem, first local workgroup,
+// count); a workgroup finds its segment by binary search over the run's
+// prefix counts.  Slots past the end of a run do nothing.
 // ---------------------------------------------------------------------------
+constexpr int kXcds = 8;
+
 struct BTiles {
-  const int* pre;  // np + 1
-  const int* gx;   // np
+  const int* xoff;  // kXcds + 1: first segment of each XCD's run
+  const int* xpre;  // nseg + kXcds: per run, 0 and the prefix of its segment counts
+  const int* sp;    // nseg: problem of each segment
+  const int* sf;    // nseg: its first local workgroup
+  const int* gx;    // np: x extent of each problem's grid
   int np;
 };
 
 struct BTile {
-  int p, x, y, gx;
+  int p, x, y, gx;  // p < 0: an idle slot
 };
 
 __device__ __forceinline__ BTile batch_tile(const BTiles& t, int bid) {
-  int lo = 0, hi = t.np - 1;
+  const int xc = bid % kXcds, slot = bid / kXcds;
+  const int a = t.xoff[xc], n = t.xoff[xc + 1] - a;
+  const int* pre = t.xpre + a + xc;  // n + 1 prefix counts of this run
+  BTile r;
+  if (n <= 0 || slot >= pre[n]) {
+    r.p = -1;
+    r.x = r.y = r.gx = 0;
+    return r;
+  }
+  int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (t.pre[mid] <= bid) lo = mid;
+    if (pre[mid] <= slot) lo = mid;
     else hi = mid - 1;
   }
-  BTile r;
-  r.p = lo;
-  r.gx = t.gx[lo];
-  const int local = bid - t.pre[lo];
+  r.p = t.sp[a + lo];
+  r.gx = t.gx[r.p];
+  const int local = t.sf[a + lo] + (slot - pre[lo]);
   r.x = local % r.gx;
   r.y = local / r.gx;
   return r;
 }
 
-// Launch arguments of one step for all problems, copied from pinned host
-// staging to device memory on the stream right before the launch.  The
-// staging is reused from the start once the stream has passed the previous
-// round's copies (the caller resets it after reading the round's results).
+// Launch arguments of one step for all problems, written to pinned host
+// staging by put() (which returns their device address) and copied to device
+// memory by flush(), one copy of everything put since the last flush, which
+// the launcher calls right before its launch.  The staging is reused from
+// the start once the stream has passed the previous round's copies (the
+// caller resets it after reading the round's results).
 class BatchUpload {
  public:
   BatchUpload() = default;
@@ -235,20 +259,21 @@ class BatchUpload {
   BatchUpload& operator=(const BatchUpload&) = delete;
   ~BatchUpload();
   void init(size_t bytes, hipStream_t s);
-  void reset() { used_ = 0; }
+  void reset() { used_ = sent_ = 0; }
+  void flush();
   template <class T>
   const T* put(const T* v, size_t n) {
     return static_cast<const T*>(put_bytes(v, sizeof(T) * n));
   }
-  // tiles of a launch whose problem p has gx[p] x gy[p] workgroups; returns
-  // the total count
+  // placement of a launch whose problem p has gx[p] x gy[p] workgroups;
+  // returns the grid size (0: nothing to run)
   int tiles(const std::vector<int>& gx, const std::vector<int>& gy, BTiles& t);
 
  private:
   const void* put_bytes(const void* v, size_t bytes);
   char* host_ = nullptr;
   char* dev_ = nullptr;
-  size_t cap_ = 0, used_ = 0;
+  size_t cap_ = 0, used_ = 0, sent_ = 0;
   hipStream_t s_ = nullptr;
 };
 

@@ -1768,22 +1768,59 @@ const void* BatchUpload::put_bytes(const void* v, size_t bytes) {
   const size_t off = (used_ + 255) & ~static_cast<size_t>(255);
   if (off + bytes > cap_) throw Error(SVDS_ERR_ARG, "batched launch arguments exceed the staging");
   std::memcpy(host_ + off, v, bytes);
-  SVDS_HIP(hipMemcpyAsync(dev_ + off, host_ + off, bytes, hipMemcpyHostToDevice, s_));
   used_ = off + bytes;
   return dev_ + off;
 }
 
+void BatchUpload::flush() {
+  if (used_ <= sent_) return;
+  SVDS_HIP(hipMemcpyAsync(dev_ + sent_, host_ + sent_, used_ - sent_, hipMemcpyHostToDevice, s_));
+  sent_ = used_;
+}
+
 int BatchUpload::tiles(const std::vector<int>& gx, const std::vector<int>& gy, BTiles& t) {
   const int np = (int)gx.size();
-  std::vector<int> pre(np + 1, 0), g(np);
+  std::vector<int> g(np), cnt(np);
+  int64_t total = 0;
   for (int p = 0; p < np; ++p) {
     g[p] = std::max(gx[p], 1);
-    pre[p + 1] = pre[p] + (gx[p] > 0 && gy[p] > 0 ? gx[p] * gy[p] : 0);
+    cnt[p] = (gx[p] > 0 && gy[p] > 0) ? gx[p] * gy[p] : 0;
+    total += cnt[p];
   }
-  t.pre = put(pre.data(), pre.size());
+  if (total > (int64_t)INT32_MAX / 2) throw Error(SVDS_ERR_ARG, "batched launch too large");
+  const int per = (int)((total + kXcds - 1) / kXcds);  // run length of each XCD
+  std::vector<int> xoff(kXcds + 1, 0), xpre, sp, sf;
+  int xc = 0, fill = 0;  // current XCD and the workgroups already in its run
+  xpre.push_back(0);
+  for (int p = 0; p < np && per > 0; ++p) {
+    int done = 0;
+    while (done < cnt[p]) {
+      if (fill == per) {  // run full: the next XCD starts its own
+        ++xc;
+        xoff[xc] = (int)sp.size();
+        xpre.push_back(0);
+        fill = 0;
+      }
+      const int take = std::min(cnt[p] - done, per - fill);
+      sp.push_back(p);
+      sf.push_back(done);
+      fill += take;
+      xpre.push_back(fill);
+      done += take;
+    }
+  }
+  for (int x = xc + 1; x <= kXcds; ++x) {
+    xoff[x] = (int)sp.size();
+    if (x < kXcds) xpre.push_back(0);
+  }
+  if (sp.empty()) sp.push_back(0), sf.push_back(0);  // keep the arrays non-empty
+  t.xoff = put(xoff.data(), xoff.size());
+  t.xpre = put(xpre.data(), xpre.size());
+  t.sp = put(sp.data(), sp.size());
+  t.sf = put(sf.data(), sf.size());
   t.gx = put(g.data(), g.size());
   t.np = np;
-  return pre[np];
+  return total > 0 ? per * kXcds : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -2544,7 +2581,8 @@ int solve_batched_workers(int nprob, const svds_csr* A, int k, int target, doubl
 
 // problems solved in step per group: the group's arrays live together
 constexpr int kStepGroup = 256;
-// host threads (and streams) of the in-step solve's set-up and clean-up
+// host threads (and streams) of the in-step solve's set-up and clean-up,
+// unless the caller names a number
 constexpr int kStepWorkers = 16;
 
 // f(w, j) for problem j of [0, np) on worker w, problems dealt round-robin
@@ -2661,7 +2699,7 @@ int svds_solve_batched(int nprob, const svds_csr* A, int k, int target, double t
                     (o.precond == SVDS_PC_NONE || o.precond == SVDS_PC_JACOBI) && !o.profile;
   if (!step)
     return solve_batched_workers(nprob, A, k, target, tol, opts, sigma, U, ldu, V, ldv, rnorm,
-                                 stats, nworkers, stream);
+                                 stats, nworkers < 0 ? -nworkers : nworkers, stream);
   std::vector<int> rc(nprob, SVDS_OK);
   const int code = guarded([&] {
     if (target != SVDS_LARGEST && target != SVDS_SMALLEST) throw Error(SVDS_ERR_ARG, "target");
@@ -2671,7 +2709,7 @@ int svds_solve_batched(int nprob, const svds_csr* A, int k, int target, double t
     const hipStream_t s = (hipStream_t)stream;
     // the worker streams of set-up and clean-up; they wait for the caller's
     // stream (the problems' inputs) and the caller's stream waits for them
-    const int nw = std::min(nprob, kStepWorkers);
+    const int nw = std::min(nprob, nworkers < 0 ? -nworkers : kStepWorkers);
     const bool verbose = std::getenv("SVDS_DEBUG") != nullptr;
     const double ta = svds::now();
     struct Streams {

@@ -161,6 +161,7 @@ template <int B>
 __global__ __launch_bounds__(kThreads) void k_tsgemm_tn_batch(const TsgemmArgs<double>* a,
                                                               BTiles t) {
   const BTile q = batch_tile(t, blockIdx.x);
+  if (q.p < 0) return;  // an idle slot of the placement
   tsgemm_body<B, double>(a[q.p], q.x, q.y, q.gx);
 }
 
@@ -192,6 +193,7 @@ __global__ __launch_bounds__(64) void k_reduce_partials(const double* __restrict
 
 __global__ __launch_bounds__(64) void k_reduce_partials_batch(const ReduceArgs* a, BTiles t) {
   const BTile q = batch_tile(t, blockIdx.x);
+  if (q.p < 0) return;  // an idle slot of the placement
   reduce_body(a[q.p], q.x);
 }
 
@@ -337,6 +339,7 @@ template <int B>
 __global__ __launch_bounds__(kThreads) void k_ts_update_batch(const UpdateArgs<double>* a,
                                                               BTiles t) {
   const BTile q = batch_tile(t, blockIdx.x);
+  if (q.p < 0) return;  // an idle slot of the placement
   update_body<B, double>(a[q.p], q.x, q.gx);
 }
 
@@ -432,6 +435,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nn(GemmArgs<TI, TO> a) {
 __global__ __launch_bounds__(kThreads) void k_gemm_nn_batch(const GemmArgs<double, double>* a,
                                                             BTiles t) {
   const BTile q = batch_tile(t, blockIdx.x);
+  if (q.p < 0) return;  // an idle slot of the placement
   gemm_body<double, double>(a[q.p], q.x, q.y, q.gx);
 }
 
@@ -501,6 +505,7 @@ __global__ __launch_bounds__(kThreads) void k_ts_scale(ScaleArgs a) {
 template <int B>
 __global__ __launch_bounds__(kThreads) void k_ts_scale_batch(const ScaleArgs* a, BTiles t) {
   const BTile q = batch_tile(t, blockIdx.x);
+  if (q.p < 0) return;  // an idle slot of the placement
   scale_body<B>(a[q.p], q.x, q.gx);
 }
 
@@ -639,6 +644,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(ResidArgs<TB> a) {
 __global__ __launch_bounds__(kThreads) void k_residual_batch(const ResidArgs<double>* a,
                                                              BTiles t) {
   const BTile q = batch_tile(t, blockIdx.x);
+  if (q.p < 0) return;  // an idle slot of the placement
   resid_body<16, 1, double>(a[q.p], q.x, q.y, q.gx);
 }
 
@@ -732,6 +738,7 @@ __global__ void k_unpack(const double* __restrict__ in, int64_t N, double* __res
 template <int B>
 __global__ void k_unpack_batch(const UnpackArgs* a, BTiles t) {
   const BTile q = batch_tile(t, blockIdx.x);
+  if (q.p < 0) return;  // an idle slot of the placement
   unpack_body<B>(a[q.p], q.x, q.gx);
 }
 
@@ -810,6 +817,7 @@ __global__ void k_gather(const double* __restrict__ R, int64_t ldr, const int* _
 template <int B>
 __global__ void k_gather_batch(const GatherArgs* a, BTiles t) {
   const BTile q = batch_tile(t, blockIdx.x);
+  if (q.p < 0) return;  // an idle slot of the placement
   gather_body<B>(a[q.p], q.x, q.gx);
 }
 
@@ -1099,6 +1107,7 @@ void tsgemm_tn_batch(int b, const std::vector<BatchProj>& jobs, std::vector<int>
   BTiles t;
   const int tiles = up.tiles(gx, gy, t);
   const TsgemmArgs<double>* d = up.put(args.data(), args.size());
+  up.flush();  // this launch's arguments, one copy
   if (tiles > 0)
     block_switch(b, [&](auto B) {
       k_tsgemm_tn_batch<decltype(B)::value><<<tiles, kThreads, 0, s>>>(d, t);
@@ -1120,6 +1129,7 @@ void reduce_partials_batch(const std::vector<BatchReduce>& jobs, BatchUpload& up
   BTiles t;
   const int tiles = up.tiles(gx, gy, t);
   const ReduceArgs* d = up.put(args.data(), args.size());
+  up.flush();  // this launch's arguments, one copy
   if (tiles > 0) k_reduce_partials_batch<<<tiles, 64, 0, s>>>(d, t);
   SVDS_LAUNCH_CHECK();
 }
@@ -1141,6 +1151,7 @@ void ts_update_batch(int b, const std::vector<BatchUpdate>& jobs, BatchUpload& u
   BTiles t;
   const int tiles = up.tiles(gx, gy, t);
   const UpdateArgs<double>* d = up.put(args.data(), args.size());
+  up.flush();  // this launch's arguments, one copy
   if (tiles > 0)
     block_switch(b, [&](auto B) {
       k_ts_update_batch<decltype(B)::value><<<tiles, kThreads, 0, s>>>(d, t);
@@ -1163,6 +1174,7 @@ void ts_gemm_nn_batch(const std::vector<BatchGemm>& jobs, BatchUpload& up, hipSt
   BTiles t;
   const int tiles = up.tiles(gx, gy, t);
   const GemmArgs<double, double>* d = up.put(args.data(), args.size());
+  up.flush();  // this launch's arguments, one copy
   if (tiles > 0) k_gemm_nn_batch<<<tiles, kThreads, 0, s>>>(d, t);
   SVDS_LAUNCH_CHECK();
 }
@@ -1180,6 +1192,7 @@ void ts_scale_batch(int b, const std::vector<BatchScale>& jobs, BatchUpload& up,
   BTiles t;
   const int tiles = up.tiles(gx, gy, t);
   const ScaleArgs* d = up.put(args.data(), args.size());
+  up.flush();  // this launch's arguments, one copy
   if (tiles > 0)
     block_switch(b, [&](auto B) {
       k_ts_scale_batch<decltype(B)::value><<<tiles, kThreads, 0, s>>>(d, t);
@@ -1206,6 +1219,7 @@ void ts_residual_batch(const std::vector<BatchResid>& jobs, BatchUpload& up, hip
   BTiles t;
   const int tiles = up.tiles(gx, gy, t);
   const ResidArgs<double>* d = up.put(args.data(), args.size());
+  up.flush();  // this launch's arguments, one copy
   if (tiles > 0) k_residual_batch<<<tiles, kThreads, 0, s>>>(d, t);
   SVDS_LAUNCH_CHECK();
   if (!red.empty()) reduce_partials_batch(red, up, s);
@@ -1225,6 +1239,7 @@ void gather_batch(int nb, const std::vector<BatchGather>& jobs, BatchUpload& up,
   BTiles t;
   const int tiles = up.tiles(gx, gy, t);
   const GatherArgs* d = up.put(args.data(), args.size());
+  up.flush();  // this launch's arguments, one copy
   if (tiles > 0)
     block_switch(nb, [&](auto B) {
       k_gather_batch<decltype(B)::value><<<tiles, 256, 0, s>>>(d, t);
@@ -1246,6 +1261,7 @@ void unpack_batch(int nb, const std::vector<BatchUnpack>& jobs, BatchUpload& up,
   BTiles t;
   const int tiles = up.tiles(gx, gy, t);
   const UnpackArgs* d = up.put(args.data(), args.size());
+  up.flush();  // this launch's arguments, one copy
   if (tiles > 0)
     block_switch(nb, [&](auto B) {
       k_unpack_batch<decltype(B)::value><<<tiles, 256, 0, s>>>(d, t);

@@ -1534,13 +1534,17 @@ void small_final_rr(int k, double* G, int ldg, int descending, double* lam, doub
 // batched single-workgroup steps
 void small_h_append_batch(const std::vector<HAppendArgs>& a, BatchUpload& up, hipStream_t s) {
   if (a.empty()) return;
-  k_h_append_batch<<<(unsigned)a.size(), kT, 0, s>>>(up.put(a.data(), a.size()));
+  const auto* d = up.put(a.data(), a.size());
+  up.flush();
+  k_h_append_batch<<<(unsigned)a.size(), kT, 0, s>>>(d);
   SVDS_LAUNCH_CHECK();
 }
 
 void small_dgks_batch(const std::vector<DgksArgs>& a, BatchUpload& up, hipStream_t s) {
   if (a.empty()) return;
-  k_dgks_batch<<<(unsigned)a.size(), kWave, 0, s>>>(up.put(a.data(), a.size()));
+  const auto* d = up.put(a.data(), a.size());
+  up.flush();
+  k_dgks_batch<<<(unsigned)a.size(), kWave, 0, s>>>(d);
   SVDS_LAUNCH_CHECK();
 }
 
@@ -1548,13 +1552,17 @@ void small_extract_batch(const std::vector<ExtractArgs>& a, BatchUpload& up, hip
   if (a.empty()) return;
   for (const ExtractArgs& q : a)
     if (q.gc < 1 || q.gc > kGmax) throw Error(SVDS_ERR_ARG, "extract: basis size");
-  k_extract_rr_batch<<<(unsigned)a.size(), kEigT, 0, s>>>(up.put(a.data(), a.size()));
+  const auto* d = up.put(a.data(), a.size());
+  up.flush();
+  k_extract_rr_batch<<<(unsigned)a.size(), kEigT, 0, s>>>(d);
   SVDS_LAUNCH_CHECK();
 }
 
 void small_chol_batch(const std::vector<CholArgs>& a, BatchUpload& up, hipStream_t s) {
   if (a.empty()) return;
-  k_chol_batch<<<(unsigned)a.size(), kCholT, 0, s>>>(up.put(a.data(), a.size()));
+  const auto* d = up.put(a.data(), a.size());
+  up.flush();
+  k_chol_batch<<<(unsigned)a.size(), kCholT, 0, s>>>(d);
   SVDS_LAUNCH_CHECK();
 }
 
@@ -1562,7 +1570,9 @@ void small_control_batch(const std::vector<ControlArgs>& a, BatchUpload& up, hip
   if (a.empty()) return;
   for (const ControlArgs& q : a)
     if (q.P.nc > kKmax + 8 || q.P.gc > kGmax) throw Error(SVDS_ERR_ARG, "control: sizes");
-  k_control_batch<<<(unsigned)a.size(), kT, 0, s>>>(up.put(a.data(), a.size()));
+  const auto* d = up.put(a.data(), a.size());
+  up.flush();
+  k_control_batch<<<(unsigned)a.size(), kT, 0, s>>>(d);
   SVDS_LAUNCH_CHECK();
 }
 

@@ -215,6 +215,7 @@ __global__ __launch_bounds__(256) void k_spmm_nat(const int32_t* __restrict__ rp
 template <int B, int L, int U>
 __global__ __launch_bounds__(256) void k_spmm_nat_batch(const NatArgs<double>* a, BTiles t) {
   const BTile q = batch_tile(t, blockIdx.x);
+  if (q.p < 0) return;  // an idle slot of the placement
   nat_body<double, B, L, U>(a[q.p], q.x, q.gx);
 }
 
@@ -382,6 +383,7 @@ void spmm_batch(int b, const std::vector<BatchSpmm>& jobs, BatchUpload& up, hipS
   BTiles t;
   const int tiles = up.tiles(gx, gy, t);
   const NatArgs<double>* d = up.put(args.data(), args.size());
+  up.flush();  // this launch's arguments, one copy
   if (tiles > 0) {
     switch (b) {
       case 1: nat_batch_b<1>(bn, U, tiles, d, t, s); break;
