@@ -439,6 +439,17 @@ void proj_bf16x3(const float* V, int64_t ldv, int nv, const float* W, int64_t ld
 // T <- T Rinv (b x b upper), optionally also writes a row-major copy
 void ts_scale(double* T, int64_t ldt, int64_t N, int b, const double* Rinv, double* compact,
               hipStream_t s);
+// one Cholesky QR step: G = T^T T from the partial sums P (P[o * nblk + k],
+// o = c * b + c2), R = chol(G) with the breakdown tests (which = 1: first
+// factor, checked against the squared pre-projection norms G0[j * ldg0 + j],
+// starts *bad; which = 2: adds to *bad), R and R^-1 stored, T <- T R^-1
+// (optionally also row-major into compact) and, when Pout is given, the
+// partial sums of the new T's Gram matrix in Pout; returns their count
+int cholqr_step(const double* P, int nblk, int which, const double* G0, int ldg0, double* R,
+                double* Rinv, int* bad, double* T, int64_t ldt, int64_t N, int b,
+                double* compact, double* Pout, hipStream_t s);
+// the most partial sums cholqr_step leaves per Gram entry
+constexpr int kCholQRMaxBlocks = 256;
 // fused residual for nc candidates: R = W Y - V Y diag(theta); per-candidate
 // sums (rows < nsplit | rows >= nsplit): ||r||^2, x.r, ||x||^2 each
 // (sums = nullptr: the partial sums stay in `partial` as [output][block] and
@@ -511,6 +522,22 @@ struct BatchScale {
   double* compact;
 };
 void ts_scale_batch(int b, const std::vector<BatchScale>& jobs, BatchUpload& up, hipStream_t s);
+struct BatchCholQR {  // cholqr_step
+  const double* P;
+  int nblk, which;
+  const double* G0;
+  int ldg0;
+  double* R;
+  double* Rinv;
+  int* bad;
+  double* T;
+  int64_t ldt, N;
+  double* compact;
+  double* Pout;
+};
+// nblk[j]: the partial sums job j leaves in its Pout
+void cholqr_batch(int b, const std::vector<BatchCholQR>& jobs, std::vector<int>& nblk,
+                  BatchUpload& up, hipStream_t s);
 struct BatchResid {  // one sum per candidate (nsplit = N)
   const double* V;
   const double* W;

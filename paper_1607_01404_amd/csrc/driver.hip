@@ -397,6 +397,7 @@ class Solver {
   double *Q_ = nullptr, *Qt_ = nullptr, *X_ = nullptr, *R_ = nullptr, *Z_ = nullptr;
   double *Tc_ = nullptr, *Yc_ = nullptr, *Wc_ = nullptr, *Zc_ = nullptr;
   double* partial_ = nullptr;
+  double* cqrP_ = nullptr;  // Gram partial sums between the two Cholesky QR steps
   double* dinv_ = nullptr;  // 1 / diag(A^T A) (ones where zero)
   Small* d_ = nullptr;
   // the control record and the sequence word after it, in pinned coherent
@@ -611,14 +612,14 @@ class Solver {
       tsgemm_tn(sb, n1, N_, T, ldt, nb, partial_, d_->C1, s_, sk);
       ts_update(sb, n1, N_, d_->C1, total, T, ldt, nb, s_, sk);
     }
-    // Cholesky QR twice; the Cholesky kernels sum the Gram partial sums themselves
-    count(N8() * nb * (6.0 + (compact ? 1.0 : 0.0)));
-    int nbk = tsgemm_tn_partial(&st, 1, N_, T, ldt, nb, partial_, s_);
-    small_chol(d_, nb, 1, G0, ldg0, s_, partial_, nbk);
-    ts_scale(T, ldt, N_, nb, d_->R1inv, nullptr, s_);
-    nbk = tsgemm_tn_partial(&st, 1, N_, T, ldt, nb, partial_, s_);
-    small_chol(d_, nb, 2, nullptr, 0, s_, partial_, nbk);
-    ts_scale(T, ldt, N_, nb, d_->R2inv, compact, s_);
+    // Cholesky QR twice: the Gram partial sums of T, then two fused steps
+    // (factor, scale, and the first also the partial sums for the second)
+    count(N8() * nb * (5.0 + (compact ? 1.0 : 0.0)));
+    const int nbk = tsgemm_tn_partial(&st, 1, N_, T, ldt, nb, partial_, s_);
+    const int nb2 = cholqr_step(partial_, nbk, 1, G0, ldg0, d_->R1, d_->R1inv, &d_->bad, T, ldt,
+                                N_, nb, nullptr, cqrP_, s_);
+    cholqr_step(cqrP_, nb2, 2, nullptr, 0, d_->R2, d_->R2inv, &d_->bad, T, ldt, N_, nb, compact,
+                nullptr, s_);
   }
 
   // repair after the control step reported a breakdown of the last block:
@@ -1603,6 +1604,7 @@ void Solver::allocate(DeviceBuffers& a) {
   Wc_ = a.get<double>(blk);
   Zc_ = a.get<double>(blk);
   partial_ = a.get<double>((size_t)2048 * 264 * kMaxBlock + 4096);
+  cqrP_ = a.get<double>((size_t)kCholQRMaxBlocks * kMaxBlock * kMaxBlock);
   d_ = a.get<Small>(1);
   vec_ = a.get<double>(16 * kLd * kLd);
   V1_ = a.get<double>((size_t)ld_ * kKmax);
@@ -1950,8 +1952,8 @@ struct BatchStage1 {
       tsgemm_tn_batch(nb, p2, nb2, up, s);
       ts_update_batch(nb, u2, up, s);
     }
-    // Cholesky QR twice; the Cholesky kernels sum the Gram partial sums
-    for (int pass = 1; pass <= 2; ++pass) {
+    // Cholesky QR twice: the Gram partial sums of T, then two fused steps
+    {
       std::vector<BatchProj> pg;
       for (Solver* x : a) {
         double* T = x->V_ + x->gc_ * x->ld_;
@@ -1963,23 +1965,26 @@ struct BatchStage1 {
         q.ldt = x->ld_;
         q.partial = x->partial_;
         pg.push_back(q);
+        x->count(x->N8() * nb * 6.0);
       }
-      std::vector<int> nbk;
+      std::vector<int> nbk, nb2, unused;
       tsgemm_tn_batch(nb, pg, nbk, up, s);
-      std::vector<CholArgs> ch;
-      std::vector<BatchScale> sc;
+      std::vector<BatchCholQR> c1, c2;
       for (size_t j = 0; j < a.size(); ++j) {
         Solver* x = a[j];
         double* T = x->V_ + x->gc_ * x->ld_;
         const int total = x->gc_;
-        ch.push_back(CholArgs{x->d_, nb, pass, pass == 1 ? x->d_->C0 + total : nullptr,
-                              pass == 1 ? total + nb : 0, x->partial_, nbk[j]});
-        sc.push_back(BatchScale{T, x->ld_, x->N_, pass == 1 ? x->d_->R1inv : x->d_->R2inv,
-                                pass == 2 ? x->Tc_ : nullptr});
-        if (pass == 2) x->count(x->N8() * nb * 7.0);
+        c1.push_back(BatchCholQR{x->partial_, nbk[j], 1, x->d_->C0 + total, total + nb, x->d_->R1,
+                                 x->d_->R1inv, &x->d_->bad, T, x->ld_, x->N_, nullptr, x->cqrP_});
       }
-      small_chol_batch(ch, up, s);
-      ts_scale_batch(nb, sc, up, s);
+      cholqr_batch(nb, c1, nb2, up, s);
+      for (size_t j = 0; j < a.size(); ++j) {
+        Solver* x = a[j];
+        double* T = x->V_ + x->gc_ * x->ld_;
+        c2.push_back(BatchCholQR{x->cqrP_, nb2[j], 2, nullptr, 0, x->d_->R2, x->d_->R2inv,
+                                 &x->d_->bad, T, x->ld_, x->N_, x->Tc_, nullptr});
+      }
+      cholqr_batch(nb, c2, unused, up, s);
     }
     // W's new columns: C T by A then A^T, then into the basis layout
     products(a, nb);

@@ -224,6 +224,24 @@ static Segs3T<TB> make_segs(const SegT<TB>* segs, int nseg, int& total) {
 
 // launch geometry of the projection: one contiguous row range per workgroup
 // column (several 256-row steps amortise the final wave reductions)
+namespace {
+// f(std::integral_constant<int, b>) for a block width b of 1..8
+template <class F>
+void block_switch(int b, F&& f) {
+  switch (b) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    case 7: f(std::integral_constant<int, 7>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    default: throw Error(SVDS_ERR_ARG, "block width must be 1..8");
+  }
+}
+}  // namespace
+
 static void tsgemm_geom(int64_t N, int total, int& nb, int64_t& chunk, int& gy) {
   nb = std::min(reduce_blocks(N), 256);
   chunk = (N + nb - 1) / nb;
@@ -520,6 +538,212 @@ void ts_scale(double* T, int64_t ldt, int64_t N, int b, const double* Rinv, doub
     default: throw Error(SVDS_ERR_ARG, "ts_scale: b must be 1..8");
   }
   SVDS_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// One Cholesky QR step on a block T (N x b): the Gram matrix G = T^T T from
+// the partial sums of the preceding pass, its Cholesky factor R and R^-1
+// (with the breakdown tests of the orthogonalisation), then T <- T R^-1 and,
+// for the next step, the partial sums of the new T's Gram matrix.  Every
+// workgroup sums the partials and factors G itself, in the same order, so
+// all of them scale with the same R^-1 and no workgroup waits for another;
+// workgroup 0 stores R, R^-1 and the breakdown record.  The partial sums are
+// few (one b x b matrix per row chunk of the producing pass), so the
+// repeated reads stay in L2.
+// ---------------------------------------------------------------------------
+struct CholQRArgs {
+  const double* P;   // Gram partial sums of T: P[o * nblk + k], o = c * b + c2
+  int nblk;
+  int which;         // 1: first factor (collapse test, starts the record); 2: second
+  const double* G0;  // which == 1: squared pre-projection norms at G0[j * ldg0 + j]
+  int ldg0;
+  double* R;         // b x b factor and its inverse, column-major
+  double* Rinv;
+  int* bad;          // breakdown record: bit j set when column j broke down
+  double* T;
+  int64_t ldt, N, chunk;
+  double* compact;   // optional row-major copy of the result
+  double* Pout;      // optional: Gram partial sums of the result, Pout[o * gx + bx]
+};
+
+template <int B>
+constexpr int cholqr_unroll() { return B <= 4 ? 8 : 4; }  // 64-row groups loaded together
+
+template <int B>
+__device__ __forceinline__ void cholqr_body(const CholQRArgs& A, int bx, int gx) {
+  constexpr int NE = B * B;
+  constexpr int TPE = (kThreads / NE) >= 64 ? 64 : (kThreads / NE) >= 16 ? 16
+                    : (kThreads / NE) >= 4 ? 4 : 1;  // threads per Gram entry
+  constexpr int U = cholqr_unroll<B>();
+  constexpr int NG = B * (B + 1) / 2;
+  __shared__ double part[NE * TPE];
+  __shared__ double G[NE], R[NE], Ri[NE], g0[B];
+  __shared__ double red[4][NG > 0 ? NG : 1];
+  __shared__ int sbad;
+  const int t = threadIdx.x;
+  // the Gram matrix: TPE threads per entry, each a strided share of the
+  // partials, then the shares added in order
+  if (t < NE * TPE) {
+    const int o = t / TPE, sub = t % TPE;
+    const double* p = A.P + (int64_t)o * A.nblk;
+    double acc = 0.0;
+    for (int k = sub; k < A.nblk; k += TPE) acc += p[k];
+    part[t] = acc;
+  }
+  if (t < B) g0[t] = (A.which == 1) ? A.G0[(int64_t)t * A.ldg0 + t] : 0.0;
+  __syncthreads();
+  if (t < NE) {
+    double acc = 0.0;
+    for (int q = 0; q < TPE; ++q) acc += part[t * TPE + q];
+    G[t] = acc;
+    R[t] = 0.0;
+    Ri[t] = 0.0;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int bad = 0;
+    for (int j = 0; j < B; ++j) {
+      const double gjj = G[j * B + j];
+      const double dj = sqrt(fmax(gjj, 0.0));
+      double sres = gjj;
+      for (int i = 0; i < j; ++i) sres -= R[j * B + i] * R[j * B + i];
+      bool ok = (sres > (kBreakRatio * dj) * (kBreakRatio * dj)) && dj > 0.0;
+      if (A.which == 1 && ok) ok = (gjj > (kCollapse * kCollapse) * g0[j]) && g0[j] > 0.0;
+      if (!ok) {
+        bad |= 1 << j;
+        R[j * B + j] = 1.0;  // keep the factor finite; the block is redone
+        continue;
+      }
+      const double rjj = sqrt(sres);
+      R[j * B + j] = rjj;
+      for (int c = j + 1; c < B; ++c) {
+        double v = 0.5 * (G[c * B + j] + G[j * B + c]);
+        for (int i = 0; i < j; ++i) v -= R[j * B + i] * R[c * B + i];
+        R[c * B + j] = v / rjj;  // column-major: R(j, c) at c*B + j
+      }
+    }
+    for (int c = 0; c < B; ++c) {  // inverse of the upper triangular factor
+      Ri[c * B + c] = 1.0 / R[c * B + c];
+      for (int i = c - 1; i >= 0; --i) {
+        double v = 0.0;
+        for (int j = i + 1; j <= c; ++j) v += R[j * B + i] * Ri[c * B + j];
+        Ri[c * B + i] = -v / R[i * B + i];
+      }
+    }
+    sbad = bad;
+  }
+  __syncthreads();
+  if (bx == 0) {
+    if (t < NE) {
+      A.R[t] = R[t];
+      A.Rinv[t] = Ri[t];
+    }
+    // the first factor of a block starts the breakdown record, the second adds to it
+    if (t == 0) {
+      if (A.which == 1) *A.bad = sbad;
+      else if (sbad) *A.bad |= sbad;
+    }
+  }
+  // T <- T R^-1 over this workgroup's row chunk, U row groups per wavefront in flight
+  double* __restrict__ T = A.T;
+  double* __restrict__ compact = A.compact;
+  const int64_t ldt = A.ldt, N = A.N;
+  const int lane = t % kWave, w = t / kWave;
+  const int bid = xcd_block(bx, gx);
+  const int64_t rb = (int64_t)bid * A.chunk;
+  const int64_t re = (rb + A.chunk < N) ? rb + A.chunk : N;
+  double g[NG];
+#pragma unroll
+  for (int a = 0; a < NG; ++a) g[a] = 0.0;
+  for (int64_t base = rb + (int64_t)w * kWave * U; base < re; base += (int64_t)4 * kWave * U) {
+    double tv[U][B];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t row = base + u * kWave + lane;
+#pragma unroll
+      for (int c = 0; c < B; ++c) tv[u][c] = (row < re) ? T[row + c * ldt] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t row = base + u * kWave + lane;
+      double o[B];
+#pragma unroll
+      for (int c = 0; c < B; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j <= c; ++j) acc = fma(tv[u][j], Ri[c * B + j], acc);
+        o[c] = acc;
+      }
+      if (row < re) {
+#pragma unroll
+        for (int c = 0; c < B; ++c) T[row + c * ldt] = o[c];
+        if (compact) {
+#pragma unroll
+          for (int c = 0; c < B; ++c) compact[row * B + c] = o[c];
+        }
+      }
+      if (A.Pout) {  // rows past the end hold zeros and add nothing
+        int a = 0;
+#pragma unroll
+        for (int c = 0; c < B; ++c)
+#pragma unroll
+          for (int c2 = c; c2 < B; ++c2) {
+            g[a] = fma(o[c], o[c2], g[a]);
+            ++a;
+          }
+      }
+    }
+  }
+  if (!A.Pout) return;
+#pragma unroll
+  for (int a = 0; a < NG; ++a) {
+    const double v = wave_sum(g[a]);
+    if (lane == 0) red[w][a] = v;
+  }
+  __syncthreads();
+  if (t < NG) {
+    int c = 0, c2 = 0, a = 0;
+    for (int i = 0; i < B; ++i)
+      for (int j = i; j < B; ++j, ++a)
+        if (a == t) {
+          c = i;
+          c2 = j;
+        }
+    const double v = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+    A.Pout[(int64_t)(c * B + c2) * gx + bx] = v;
+    A.Pout[(int64_t)(c2 * B + c) * gx + bx] = v;
+  }
+}
+
+template <int B>
+__global__ __launch_bounds__(kThreads) void k_cholqr(CholQRArgs a) {
+  cholqr_body<B>(a, blockIdx.x, gridDim.x);
+}
+
+template <int B>
+__global__ __launch_bounds__(kThreads) void k_cholqr_batch(const CholQRArgs* a, BTiles t) {
+  const BTile q = batch_tile(t, blockIdx.x);
+  if (q.p < 0) return;  // an idle slot of the placement
+  cholqr_body<B>(a[q.p], q.x, q.gx);
+}
+
+// the row chunks of a Cholesky QR step on N rows (also the number of partial
+// sums it leaves for the next step)
+static void cholqr_geom(int64_t N, int b, int& nb, int64_t& chunk) {
+  int gy = 0;
+  tsgemm_geom(N, b, nb, chunk, gy);
+}
+
+int cholqr_step(const double* P, int nblk, int which, const double* G0, int ldg0, double* R,
+                double* Rinv, int* bad, double* T, int64_t ldt, int64_t N, int b,
+                double* compact, double* Pout, hipStream_t s) {
+  int nb = 0;
+  int64_t chunk = 0;
+  cholqr_geom(N, b, nb, chunk);
+  const CholQRArgs a{P, nblk, which, G0, ldg0, R, Rinv, bad, T, ldt, N, chunk, compact, Pout};
+  block_switch(b, [&](auto B) { k_cholqr<decltype(B)::value><<<nb, kThreads, 0, s>>>(a); });
+  SVDS_LAUNCH_CHECK();
+  return nb;
 }
 
 // ---------------------------------------------------------------------------
@@ -1065,23 +1289,6 @@ void sign_factors(const double* V, int64_t ldv, int64_t N, int k, double* partia
 // ===========================================================================
 namespace svds {
 
-namespace {
-template <class F>
-void block_switch(int b, F&& f) {
-  switch (b) {
-    case 1: f(std::integral_constant<int, 1>{}); break;
-    case 2: f(std::integral_constant<int, 2>{}); break;
-    case 3: f(std::integral_constant<int, 3>{}); break;
-    case 4: f(std::integral_constant<int, 4>{}); break;
-    case 5: f(std::integral_constant<int, 5>{}); break;
-    case 6: f(std::integral_constant<int, 6>{}); break;
-    case 7: f(std::integral_constant<int, 7>{}); break;
-    case 8: f(std::integral_constant<int, 8>{}); break;
-    default: throw Error(SVDS_ERR_ARG, "batched step: block width must be 1..8");
-  }
-}
-}  // namespace
-
 void tsgemm_tn_batch(int b, const std::vector<BatchProj>& jobs, std::vector<int>& nblk,
                      BatchUpload& up, hipStream_t s) {
   const int np = (int)jobs.size();
@@ -1176,6 +1383,34 @@ void ts_gemm_nn_batch(const std::vector<BatchGemm>& jobs, BatchUpload& up, hipSt
   const GemmArgs<double, double>* d = up.put(args.data(), args.size());
   up.flush();  // this launch's arguments, one copy
   if (tiles > 0) k_gemm_nn_batch<<<tiles, kThreads, 0, s>>>(d, t);
+  SVDS_LAUNCH_CHECK();
+}
+
+void cholqr_batch(int b, const std::vector<BatchCholQR>& jobs, std::vector<int>& nblk,
+                  BatchUpload& up, hipStream_t s) {
+  const int np = (int)jobs.size();
+  nblk.assign(np, 0);
+  if (np == 0) return;
+  std::vector<CholQRArgs> args(np);
+  std::vector<int> gx(np), gy(np, 1);
+  for (int j = 0; j < np; ++j) {
+    const BatchCholQR& q = jobs[j];
+    int nb = 0;
+    int64_t chunk = 0;
+    cholqr_geom(q.N, b, nb, chunk);
+    args[j] = CholQRArgs{q.P, q.nblk, q.which, q.G0, q.ldg0, q.R, q.Rinv, q.bad,
+                         q.T, q.ldt, q.N, chunk, q.compact, q.Pout};
+    gx[j] = nb;
+    nblk[j] = nb;
+  }
+  BTiles t;
+  const int tiles = up.tiles(gx, gy, t);
+  const CholQRArgs* d = up.put(args.data(), args.size());
+  up.flush();  // this launch's arguments, one copy
+  if (tiles > 0)
+    block_switch(b, [&](auto B) {
+      k_cholqr_batch<decltype(B)::value><<<tiles, kThreads, 0, s>>>(d, t);
+    });
   SVDS_LAUNCH_CHECK();
 }
 

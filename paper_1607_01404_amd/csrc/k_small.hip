@@ -1,10 +1,11 @@
 // Single-workgroup FP64 kernels for the small replicated problems of the
-// eigensolver (Section 3.3: "the cost of small matrix operations ... is
-// negligible"): the projected eigenproblem (cyclic two-sided Jacobi), the
-// SVD of the refined R factor (one-sided Jacobi), Cholesky factors of block
-// Gram matrices, Householder QR for the refined restart (Section 3.2), and
-// the control step that applies the convergence tests, picks the block and
-// builds the GD+k restart coefficients.
+// eigensolver (Section 3.3 treats their cost as minor next to the tall
+// products): the projected eigenproblem (bordered secular solver and cyclic
+// two-sided Jacobi), the SVD of the refined R factor (one-sided Jacobi),
+// Householder QR for the refined restart (Section 3.2), and the control step
+// that applies the convergence tests, picks the block and builds the GD+k
+// restart coefficients.  (The Cholesky factors of the block Gram matrices
+// are formed inside the fused Cholesky QR steps of k_dense.hip.)
 #include "small.h"
 
 namespace svds {
@@ -12,7 +13,6 @@ namespace svds {
 constexpr int kT = kSmallThreads;
 constexpr int kLs = kLd + 1;  // padded leading dimension in LDS
 constexpr int kEigT = 1024;   // threads of the eigensolver kernels
-constexpr int kCholT = 1024;  // threads of the block Cholesky (one wavefront per Gram entry)
 
 // round-robin pairing for np (even) indices, round r in [0, np-1)
 __device__ __forceinline__ void rr_pair(int np, int r, int k, int& p, int& q) {
@@ -954,98 +954,6 @@ void small_extract(Small* d, int gc, int descending, int refined, hipStream_t s)
   SVDS_LAUNCH_CHECK();
 }
 
-// ---------------------------------------------------------------------------
-// Cholesky QR factor of the block Gram matrix G (nb x nb) with a named-column
-// breakdown test; which = 1 writes R1/R1inv (and checks for columns that
-// collapsed during projection against the pre-projection norms stored as the
-// last nb rows of C0), which = 2 writes R2/R2inv.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void chol_body(Small* d, int nb, int which, const double* G0, int ldg0,
-                                          const double* __restrict__ P, int nblk) {
-  __shared__ double G[kMaxBlock * kMaxBlock], g0[kMaxBlock];
-  __shared__ double R[kMaxBlock * kMaxBlock], Ri[kMaxBlock * kMaxBlock];
-  __shared__ int sbad;
-  const int t = threadIdx.x;
-  if (P) {
-    // the Gram matrix from the projection's partial sums: one wavefront per
-    // entry, the summation of the separate reduction kernel
-    const int lane = t % kWave, w = t / kWave;
-    for (int o = w; o < nb * nb; o += kCholT / kWave) {
-      double s = 0.0;
-      for (int b = lane; b < nblk; b += kWave) s += P[(int64_t)o * nblk + b];
-      s = wave_sum(s);
-      if (lane == 0) G[o] = s;
-    }
-  } else if (t < nb * nb) {
-    G[t] = d->G[t];
-  }
-  if (t < nb * nb) {
-    R[t] = 0.0;
-    Ri[t] = 0.0;
-  }
-  if (t < nb) g0[t] = (which == 1) ? G0[(int64_t)t * ldg0 + t] : 0.0;
-  __syncthreads();
-  if (t == 0) {
-    int bad = 0;
-    for (int j = 0; j < nb; ++j) {
-      const double gjj = G[j * nb + j];
-      const double dj = sqrt(fmax(gjj, 0.0));
-      double s = gjj;
-      for (int i = 0; i < j; ++i) s -= R[j * nb + i] * R[j * nb + i];
-      bool ok = (s > (kBreakRatio * dj) * (kBreakRatio * dj)) && dj > 0.0;
-      if (which == 1 && ok) ok = (gjj > (kCollapse * kCollapse) * g0[j]) && g0[j] > 0.0;
-      if (!ok) {
-        bad |= 1 << j;
-        R[j * nb + j] = 1.0;  // keep the factor finite; the block is redone
-        continue;
-      }
-      const double rjj = sqrt(s);
-      R[j * nb + j] = rjj;
-      for (int c = j + 1; c < nb; ++c) {
-        double v = 0.5 * (G[c * nb + j] + G[j * nb + c]);
-        for (int i = 0; i < j; ++i) v -= R[j * nb + i] * R[c * nb + i];
-        R[c * nb + j] = v / rjj;  // column-major: R(j, c) at c*nb + j
-      }
-    }
-    for (int c = 0; c < nb; ++c) {  // inverse of the upper triangular factor
-      Ri[c * nb + c] = 1.0 / R[c * nb + c];
-      for (int i = c - 1; i >= 0; --i) {
-        double v = 0.0;
-        for (int j = i + 1; j <= c; ++j) v += R[j * nb + i] * Ri[c * nb + j];
-        Ri[c * nb + i] = -v / R[i * nb + i];
-      }
-    }
-    sbad = bad;
-  }
-  __syncthreads();
-  double* Ro = which == 1 ? d->R1 : d->R2;
-  double* Rio = which == 1 ? d->R1inv : d->R2inv;
-  if (t < nb * nb) {
-    Ro[t] = R[t];
-    Rio[t] = Ri[t];
-  }
-  // the first factor of a block starts the breakdown record, the second adds to it
-  if (t == 0) {
-    if (which == 1) d->bad = sbad;
-    else if (sbad) d->bad |= sbad;
-  }
-}
-
-__global__ __launch_bounds__(kCholT) void k_chol(Small* d, int nb, int which, const double* G0,
-                                                int ldg0, const double* __restrict__ P,
-                                                int nblk) {
-  chol_body(d, nb, which, G0, ldg0, P, nblk);
-}
-__global__ __launch_bounds__(kCholT) void k_chol_batch(const CholArgs* a) {
-  const CholArgs q = a[blockIdx.x];
-  chol_body(q.d, q.nb, q.which, q.G0, q.ldg0, q.P, q.nblk);
-}
-
-void small_chol(Small* d, int nb, int which, const double* G0, int ldg0, hipStream_t s,
-                const double* partial, int nblk) {
-  k_chol<<<1, kCholT, 0, s>>>(d, nb, which, G0, ldg0, partial, nblk);
-  SVDS_LAUNCH_CHECK();
-}
 
 // ---------------------------------------------------------------------------
 // refined factor: Rr[0:gc, gc:gc+nb] = C0 + C1 (projection coefficients),
@@ -1555,14 +1463,6 @@ void small_extract_batch(const std::vector<ExtractArgs>& a, BatchUpload& up, hip
   const auto* d = up.put(a.data(), a.size());
   up.flush();
   k_extract_rr_batch<<<(unsigned)a.size(), kEigT, 0, s>>>(d);
-  SVDS_LAUNCH_CHECK();
-}
-
-void small_chol_batch(const std::vector<CholArgs>& a, BatchUpload& up, hipStream_t s) {
-  if (a.empty()) return;
-  const auto* d = up.put(a.data(), a.size());
-  up.flush();
-  k_chol_batch<<<(unsigned)a.size(), kCholT, 0, s>>>(d);
   SVDS_LAUNCH_CHECK();
 }
 

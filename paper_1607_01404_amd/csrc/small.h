@@ -108,12 +108,6 @@ void small_dgks(Small* d, int total, int nb, const double* C0, int ldc0, hipStre
 // d->stepbad[step] = d->bad (the breakdown record of the last orthogonalisation)
 void small_record_bad(Small* d, int step, hipStream_t s);
 void small_extract(Small* d, int gc, int descending, int refined, hipStream_t s);
-// which = 1: also test columns that collapsed during projection against the
-// pre-projection Gram diagonal G0[j*ldg0 + j].  The Gram matrix is d->G, or,
-// with partial non-null, the sums of the projection's nblk per-workgroup
-// partial sums (partial[o * nblk + block], o = c * nb + j)
-void small_chol(Small* d, int nb, int which, const double* G0, int ldg0, hipStream_t s,
-                const double* partial = nullptr, int nblk = 0);
 void small_rr_append(Small* d, int gc, int nb, int total, hipStream_t s);
 // the control step: its decision record is built in LDS; host (may be null)
 // is the device address of a pinned, coherent host copy that the kernel
@@ -137,14 +131,6 @@ struct ExtractArgs {
   Small* d;
   int gc, descending;
 };
-struct CholArgs {
-  Small* d;
-  int nb, which;
-  const double* G0;
-  int ldg0;
-  const double* P;
-  int nblk;
-};
 struct ControlArgs {
   Small* d;
   CtlParams P;
@@ -155,7 +141,6 @@ struct ControlArgs {
 void small_h_append_batch(const std::vector<HAppendArgs>& a, BatchUpload& up, hipStream_t s);
 void small_dgks_batch(const std::vector<DgksArgs>& a, BatchUpload& up, hipStream_t s);
 void small_extract_batch(const std::vector<ExtractArgs>& a, BatchUpload& up, hipStream_t s);
-void small_chol_batch(const std::vector<CholArgs>& a, BatchUpload& up, hipStream_t s);
 void small_control_batch(const std::vector<ControlArgs>& a, BatchUpload& up, hipStream_t s);
 void small_rtr_accumulate(const double* C0, int ldc0, const double* C1, int total, int nb,
                           double* Cout, hipStream_t s);
