@@ -419,10 +419,14 @@ void tsgemm_tn(const SegT<TB>* segs, int nseg, int64_t N, const double* T, int64
 int tsgemm_tn_partial(const Seg* segs, int nseg, int64_t N, const double* T, int64_t ldt, int b,
                       double* partial, hipStream_t s);
 // T -= [segs] C   (C: total x b, column-major with leading dimension ldc);
-// nothing when the device flag *skip is set
+// nothing when the device flag *skip is set.  With dgks_out, C also holds the
+// block's own Gram matrix in rows total.. (the first Gram-Schmidt pass), and
+// *dgks_out receives the second-pass test: 1 (skip the second pass) when
+// every column kept at least 1/sqrt(2) of its norm, ||c_j||^2 <= G_jj / 2
 template <typename TB>
 void ts_update(const SegT<TB>* segs, int nseg, int64_t N, const double* C, int ldc, double* T,
-               int64_t ldt, int b, hipStream_t s, const int* skip = nullptr);
+               int64_t ldt, int b, hipStream_t s, const int* skip = nullptr,
+               int* dgks_out = nullptr);
 // Out (N x nout) = Q (N x nq) Y (nq x nout, ld ldy); Out may not alias Q
 template <typename TI, typename TO>
 void ts_gemm_nn(const TI* Q, int64_t ldq, int nq, int64_t N, const double* Y, int64_t ldy,
@@ -501,6 +505,7 @@ struct BatchUpdate {
   double* T;
   int64_t ldt;
   const int* skip;
+  int* dgks_out;
 };
 void ts_update_batch(int b, const std::vector<BatchUpdate>& jobs, BatchUpload& up, hipStream_t s);
 struct BatchGemm {

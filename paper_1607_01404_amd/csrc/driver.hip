@@ -590,7 +590,6 @@ class Solver {
       G0 = d_->C0 + total;
       ldg0 = total + nb;
       ldc0 = total + nb;
-      if (total > 0) small_dgks(d_, total, nb, d_->C0, ldc0, s_);
     } else {
       tsgemm_tn(&st, 1, N_, T, ldt, nb, partial_, d_->G0, s_);
       if (total > 0) tsgemm_tn(sb, n1, N_, T, ldt, nb, partial_, d_->C0, s_);
@@ -608,7 +607,9 @@ class Solver {
       // test says so, is not counted for the FP64 basis)
       count((double)sizeof(TB) * N_ * total + 2.0 * N8() * nb);
       if (!std::is_same<TB, double>::value) count((double)sizeof(TB) * N_ * total + 2.0 * N8() * nb);
-      ts_update(sb, n1, N_, d_->C0, ldc0, T, ldt, nb, s_);
+      // the first update also takes the second-pass test (FP64 basis)
+      ts_update(sb, n1, N_, d_->C0, ldc0, T, ldt, nb, s_, nullptr,
+                std::is_same<TB, double>::value ? &d_->skip2 : nullptr);
       tsgemm_tn(sb, n1, N_, T, ldt, nb, partial_, d_->C1, s_, sk);
       ts_update(sb, n1, N_, d_->C1, total, T, ldt, nb, s_, sk);
     }
@@ -674,8 +675,7 @@ class Solver {
     int nbp = 0;
     timed(kTProj, 8.0 * (double)N_ * (gc_ + 2 * nb), turn(kTProj),
           [&] { nbp = tsgemm_tn_partial(&sv, 1, N_, Wcol, ld_, nb, partial_, s_); });
-    reduce_partials(partial_, nbp, (gc_ + nb) * nb, d_->Hn, s_);
-    small_h_append(d_, gc_, nb, s_);
+    small_h_append(d_, gc_, nb, s_, partial_, nbp);  // sums the partials itself
     if (refined_) {
       // Z = W_new - tau T, orthogonalised against Q: new columns of Rr
       double* Zcol = Q_ + gc_ * ld_;
@@ -1913,13 +1913,11 @@ struct BatchStage1 {
                                nullptr});
     reduce_partials_batch(r1, up, s);
     if (!wb.empty()) {
-      std::vector<DgksArgs> dg;
       std::vector<BatchUpdate> u1, u2;
       std::vector<BatchProj> p2;
       for (Solver* x : wb) {
         const int total = x->gc_, ldc0 = total + nb;
         double* T = x->V_ + x->gc_ * x->ld_;
-        dg.push_back(DgksArgs{x->d_, total, nb, x->d_->C0, ldc0});
         BatchUpdate u{};
         u.segs[0] = Seg{x->V_, total, x->ld_};
         u.nseg = 1;
@@ -1929,7 +1927,9 @@ struct BatchStage1 {
         u.T = T;
         u.ldt = x->ld_;
         u.skip = nullptr;
+        u.dgks_out = &x->d_->skip2;  // the first update takes the second-pass test
         u1.push_back(u);
+        u.dgks_out = nullptr;
         BatchProj q{};
         q.segs[0] = Seg{x->V_, total, x->ld_};
         q.nseg = 1;
@@ -1946,7 +1946,6 @@ struct BatchStage1 {
         u2.push_back(u);
         x->count(8.0 * x->N_ * total + 2.0 * x->N8() * nb);
       }
-      small_dgks_batch(dg, up, s);
       ts_update_batch(nb, u1, up, s);
       std::vector<int> nb2;
       tsgemm_tn_batch(nb, p2, nb2, up, s);
@@ -2006,15 +2005,12 @@ struct BatchStage1 {
     unpack_batch(nb, un, up, s);
     std::vector<int> nbh;
     tsgemm_tn_batch(nb, ph, nbh, up, s);
-    std::vector<BatchReduce> rh;
     std::vector<HAppendArgs> ha;
     std::vector<ExtractArgs> ex;
     for (size_t j = 0; j < a.size(); ++j) {
       Solver* x = a[j];
-      rh.push_back(BatchReduce{x->partial_, nbh[j], (x->gc_ + nb) * nb, x->d_->Hn, nullptr});
-      ha.push_back(HAppendArgs{x->d_, x->gc_, nb});
+      ha.push_back(HAppendArgs{x->d_, x->gc_, nb, x->partial_, nbh[j]});
     }
-    reduce_partials_batch(rh, up, s);
     small_h_append_batch(ha, up, s);
     for (Solver* x : a) {
       x->gc_ += nb;

@@ -316,6 +316,13 @@ struct UpdateArgs {
   double* T;
   int64_t ldt;
   const int* skip;
+  // optional: the second-pass test of classical Gram-Schmidt (Daniel, Gragg,
+  // Kaufman and Stewart) on C, the first pass's coefficients with the
+  // block's own Gram matrix in rows total..: after one pass against an
+  // orthonormal basis a column whose norm fell by less than sqrt(2) is
+  // orthogonal to working accuracy.  Workgroup 0 writes 1 when every column
+  // passes (||c_j||^2 <= G_jj / 2), so that the second pass is skipped
+  int* dgks_out;
 };
 
 template <int B, typename TB>
@@ -332,6 +339,18 @@ __device__ __forceinline__ void update_body(const UpdateArgs<TB>& A, int bx, int
     cs[a] = C[(int64_t)c * ldc + j];
   }
   __syncthreads();
+  if (A.dgks_out && bx == 0 && threadIdx.x < kWave) {
+    const int lane = threadIdx.x;
+    int need = 0;
+    for (int c = 0; c < B; ++c) {
+      double sq = 0.0;
+      for (int j = lane; j < total; j += kWave) sq = fma(cs[j * B + c], cs[j * B + c], sq);
+      sq = wave_sum(sq);
+      const double g0 = C[(int64_t)c * ldc + total + c];
+      if (!(sq <= 0.5 * g0)) need = 1;
+    }
+    if (lane == 0) *A.dgks_out = need ? 0 : 1;
+  }
   const int bid = xcd_block(bx, gx);
   for (int64_t i = (int64_t)bid * kThreads + threadIdx.x; i < N;
        i += (int64_t)gx * kThreads) {
@@ -363,7 +382,7 @@ __global__ __launch_bounds__(kThreads) void k_ts_update_batch(const UpdateArgs<d
 
 template <typename TB>
 void ts_update(const SegT<TB>* segs, int nseg, int64_t N, const double* C, int ldc, double* T,
-               int64_t ldt, int b, hipStream_t s, const int* skip) {
+               int64_t ldt, int b, hipStream_t s, const int* skip, int* dgks_out) {
   int total = 0;
   Segs3T<TB> sg = make_segs(segs, nseg, total);
   if (total == 0) return;
@@ -372,7 +391,7 @@ void ts_update(const SegT<TB>* segs, int nseg, int64_t N, const double* C, int l
   switch (b) {
 #define CASE(BB) \
   case BB:                                                                           \
-    k_ts_update<BB, TB><<<nb, kThreads, 0, s>>>(UpdateArgs<TB>{sg, total, N, C, ldc, T, ldt, skip}); \
+    k_ts_update<BB, TB><<<nb, kThreads, 0, s>>>(UpdateArgs<TB>{sg, total, N, C, ldc, T, ldt, skip, dgks_out}); \
     break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
@@ -381,9 +400,9 @@ void ts_update(const SegT<TB>* segs, int nseg, int64_t N, const double* C, int l
   SVDS_LAUNCH_CHECK();
 }
 template void ts_update<double>(const SegT<double>*, int, int64_t, const double*, int, double*,
-                                int64_t, int, hipStream_t, const int*);
+                                int64_t, int, hipStream_t, const int*, int*);
 template void ts_update<float>(const SegT<float>*, int, int64_t, const double*, int, double*,
-                               int64_t, int, hipStream_t, const int*);
+                               int64_t, int, hipStream_t, const int*, int*);
 
 // ---------------------------------------------------------------------------
 // Out = Q Y   (restart V <- V Y, W <- W Y, Q <- Q Q~, locking x = V y)
@@ -581,12 +600,30 @@ __device__ __forceinline__ void cholqr_body(const CholQRArgs& A, int bx, int gx)
   __shared__ double red[4][NG > 0 ? NG : 1];
   __shared__ int sbad;
   const int t = threadIdx.x;
+  // this wavefront's first U row groups are loaded before anything else, so
+  // that their latency passes while the factor is formed
+  double* __restrict__ T = A.T;
+  double* __restrict__ compact = A.compact;
+  const int64_t ldt = A.ldt, N = A.N;
+  const int lane = t % kWave, w = t / kWave;
+  const int bid = xcd_block(bx, gx);
+  const int64_t rb = (int64_t)bid * A.chunk;
+  const int64_t re = (rb + A.chunk < N) ? rb + A.chunk : N;
+  int64_t base = rb + (int64_t)w * kWave * U;
+  double tv[U][B];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t row = base + u * kWave + lane;
+#pragma unroll
+    for (int c = 0; c < B; ++c) tv[u][c] = (row < re) ? T[row + c * ldt] : 0.0;
+  }
   // the Gram matrix: TPE threads per entry, each a strided share of the
   // partials, then the shares added in order
   if (t < NE * TPE) {
     const int o = t / TPE, sub = t % TPE;
     const double* p = A.P + (int64_t)o * A.nblk;
     double acc = 0.0;
+#pragma unroll 8
     for (int k = sub; k < A.nblk; k += TPE) acc += p[k];
     part[t] = acc;
   }
@@ -645,24 +682,10 @@ __device__ __forceinline__ void cholqr_body(const CholQRArgs& A, int bx, int gx)
     }
   }
   // T <- T R^-1 over this workgroup's row chunk, U row groups per wavefront in flight
-  double* __restrict__ T = A.T;
-  double* __restrict__ compact = A.compact;
-  const int64_t ldt = A.ldt, N = A.N;
-  const int lane = t % kWave, w = t / kWave;
-  const int bid = xcd_block(bx, gx);
-  const int64_t rb = (int64_t)bid * A.chunk;
-  const int64_t re = (rb + A.chunk < N) ? rb + A.chunk : N;
   double g[NG];
 #pragma unroll
   for (int a = 0; a < NG; ++a) g[a] = 0.0;
-  for (int64_t base = rb + (int64_t)w * kWave * U; base < re; base += (int64_t)4 * kWave * U) {
-    double tv[U][B];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t row = base + u * kWave + lane;
-#pragma unroll
-      for (int c = 0; c < B; ++c) tv[u][c] = (row < re) ? T[row + c * ldt] : 0.0;
-    }
+  while (base < re) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t row = base + u * kWave + lane;
@@ -692,6 +715,14 @@ __device__ __forceinline__ void cholqr_body(const CholQRArgs& A, int bx, int gx)
             ++a;
           }
       }
+    }
+    base += (int64_t)4 * kWave * U;
+    if (base >= re) break;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t row = base + u * kWave + lane;
+#pragma unroll
+      for (int c = 0; c < B; ++c) tv[u][c] = (row < re) ? T[row + c * ldt] : 0.0;
     }
   }
   if (!A.Pout) return;
@@ -1351,7 +1382,7 @@ void ts_update_batch(int b, const std::vector<BatchUpdate>& jobs, BatchUpload& u
     int total = 0;
     Segs3T<double> sg = make_segs(q.segs, q.nseg, total);
     if (total > kMaxSegCols) throw Error(SVDS_ERR_ARG, "update too wide");
-    args[j] = UpdateArgs<double>{sg, total, q.N, q.C, q.ldc, q.T, q.ldt, q.skip};
+    args[j] = UpdateArgs<double>{sg, total, q.N, q.C, q.ldc, q.T, q.ldt, q.skip, q.dgks_out};
     gx[j] = reduce_blocks(q.N);
     if (total == 0) gy[j] = 0;
   }

@@ -742,8 +742,31 @@ void small_svd(int g, const double* R, int ldr, double* s, double* Y, int ldy, d
 // ---------------------------------------------------------------------------
 // projected matrix: append the new columns Hn ((gc+nb) x nb, ld gc+nb)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void h_append_body(Small* d, int gc, int nb) {
+// P non-null: the new columns are first summed from the projection's nblk
+// per-workgroup partial sums (P[o * nblk + block], o = c * tot + i), 16
+// lanes per entry (64 entries at a time, their loads unrolled), and also
+// stored in d->Hn
+constexpr int kHAppT = 1024;  // threads of the append kernels
+
+__device__ __forceinline__ void h_append_body(Small* d, int gc, int nb, const double* P, int nblk) {
   const int tot = gc + nb;
+  __shared__ double hn[kLd * kMaxBlock];
+  if (P) {
+    const int l = threadIdx.x % 16, grp = threadIdx.x / 16;
+    for (int o = grp; o < tot * nb; o += kHAppT / 16) {  // uniform per 16-lane group
+      const double* p = P + (int64_t)o * nblk;
+      double sum = 0.0;
+#pragma unroll 8
+      for (int k = l; k < nblk; k += 16) sum += p[k];
+      sum = lane_sum<double, 16>(sum);
+      if (l == 0) {
+        hn[o] = sum;
+        d->Hn[o] = sum;
+      }
+    }
+  } else {
+    for (int o = threadIdx.x; o < tot * nb; o += blockDim.x) hn[o] = d->Hn[o];
+  }
   // previous eigenvectors stay a good start: W <- diag(W, I); a projected
   // matrix built from nothing starts from W = I with no diagonal block
   const bool warm = d->warm_g == gc || gc == 0;
@@ -760,46 +783,23 @@ __device__ __forceinline__ void h_append_body(Small* d, int gc, int nb) {
   for (int a = threadIdx.x; a < tot * nb; a += blockDim.x) {
     const int i = a % tot, c = a / tot;
     const int j = gc + c;
-    double v = d->Hn[(int64_t)c * tot + i];
+    double v = hn[c * tot + i];
     if (i >= gc) {  // symmetrise the new diagonal block
       const int ci = i - gc;
-      v = 0.5 * (v + d->Hn[(int64_t)ci * tot + j]);
+      v = 0.5 * (v + hn[ci * tot + j]);
     }
     d->H[j * kLd + i] = v;
     d->H[i * kLd + j] = v;
   }
 }
 
-__global__ void k_h_append(Small* d, int gc, int nb) { h_append_body(d, gc, nb); }
-__global__ void k_h_append_batch(const HAppendArgs* a) {
+__global__ __launch_bounds__(kHAppT) void k_h_append(Small* d, int gc, int nb, const double* P,
+                                                     int nblk) {
+  h_append_body(d, gc, nb, P, nblk);
+}
+__global__ __launch_bounds__(kHAppT) void k_h_append_batch(const HAppendArgs* a) {
   const HAppendArgs q = a[blockIdx.x];
-  h_append_body(q.d, q.gc, q.nb);
-}
-
-// second-pass test of classical Gram-Schmidt (Daniel, Gragg, Kaufman and
-// Stewart): after one pass against an orthonormal basis a column whose norm
-// fell by less than a factor sqrt(2) is orthogonal to working accuracy, so
-// the second pass is needed only when some column lost more
-__device__ __forceinline__ void dgks_body(Small* d, int total, int nb, const double* __restrict__ C0,
-                                          int ldc0) {
-  const int lane = threadIdx.x;
-  int need = 0;
-  for (int c = 0; c < nb; ++c) {
-    double s = 0.0;
-    for (int j = lane; j < total; j += kWave) s = fma(C0[(int64_t)c * ldc0 + j], C0[(int64_t)c * ldc0 + j], s);
-    s = wave_sum(s);
-    const double g0 = C0[(int64_t)c * ldc0 + total + c];
-    if (!(s <= 0.5 * g0)) need = 1;
-  }
-  if (lane == 0) d->skip2 = need ? 0 : 1;
-}
-
-__global__ void k_dgks(Small* d, int total, int nb, const double* __restrict__ C0, int ldc0) {
-  dgks_body(d, total, nb, C0, ldc0);
-}
-__global__ void k_dgks_batch(const DgksArgs* a) {
-  const DgksArgs q = a[blockIdx.x];
-  dgks_body(q.d, q.total, q.nb, q.C0, q.ldc0);
+  h_append_body(q.d, q.gc, q.nb, q.P, q.nblk);
 }
 
 __global__ void k_record_bad(Small* d, int step) {
@@ -812,13 +812,8 @@ void small_record_bad(Small* d, int step, hipStream_t s) {
   SVDS_LAUNCH_CHECK();
 }
 
-void small_dgks(Small* d, int total, int nb, const double* C0, int ldc0, hipStream_t s) {
-  k_dgks<<<1, kWave, 0, s>>>(d, total, nb, C0, ldc0);
-  SVDS_LAUNCH_CHECK();
-}
-
-void small_h_append(Small* d, int gc, int nb, hipStream_t s) {
-  k_h_append<<<1, kT, 0, s>>>(d, gc, nb);
+void small_h_append(Small* d, int gc, int nb, hipStream_t s, const double* partial, int nblk) {
+  k_h_append<<<1, kHAppT, 0, s>>>(d, gc, nb, partial, nblk);
   SVDS_LAUNCH_CHECK();
 }
 
@@ -1444,15 +1439,7 @@ void small_h_append_batch(const std::vector<HAppendArgs>& a, BatchUpload& up, hi
   if (a.empty()) return;
   const auto* d = up.put(a.data(), a.size());
   up.flush();
-  k_h_append_batch<<<(unsigned)a.size(), kT, 0, s>>>(d);
-  SVDS_LAUNCH_CHECK();
-}
-
-void small_dgks_batch(const std::vector<DgksArgs>& a, BatchUpload& up, hipStream_t s) {
-  if (a.empty()) return;
-  const auto* d = up.put(a.data(), a.size());
-  up.flush();
-  k_dgks_batch<<<(unsigned)a.size(), kWave, 0, s>>>(d);
+  k_h_append_batch<<<(unsigned)a.size(), kHAppT, 0, s>>>(d);
   SVDS_LAUNCH_CHECK();
 }
 

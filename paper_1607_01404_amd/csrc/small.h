@@ -100,11 +100,12 @@ void small_eig(int g, const double* H, int ldh, int descending, double* theta, d
                hipStream_t s);
 void small_svd(int g, const double* R, int ldr, double* s, double* Y, int ldy, double* AV,
                int ldav, hipStream_t st);
-void small_h_append(Small* d, int gc, int nb, hipStream_t s);
-// d->skip2 = every column kept at least 1/sqrt(2) of its norm in the first
-// Gram-Schmidt pass: ||c_j||^2 <= G0_jj / 2 with C0 (total x nb, ld ldc0) the
-// coefficients of the pass and G0 = C0 + total the block's own Gram matrix
-void small_dgks(Small* d, int total, int nb, const double* C0, int ldc0, hipStream_t s);
+// H <- [H, Hn; Hn^T] (the new columns Hn, tot = gc + nb by nb, symmetrised
+// in the new diagonal block) and the warm start extended by the identity;
+// with partial non-null, Hn is first summed from the projection's nblk
+// per-workgroup partial sums (partial[o * nblk + block])
+void small_h_append(Small* d, int gc, int nb, hipStream_t s, const double* partial = nullptr,
+                    int nblk = 0);
 // d->stepbad[step] = d->bad (the breakdown record of the last orthogonalisation)
 void small_record_bad(Small* d, int step, hipStream_t s);
 void small_extract(Small* d, int gc, int descending, int refined, hipStream_t s);
@@ -120,12 +121,8 @@ void small_control(Small* d, const CtlParams& p, hipStream_t s, Ctl* host = null
 struct HAppendArgs {
   Small* d;
   int gc, nb;
-};
-struct DgksArgs {
-  Small* d;
-  int total, nb;
-  const double* C0;
-  int ldc0;
+  const double* P;  // null: Hn already summed
+  int nblk;
 };
 struct ExtractArgs {
   Small* d;
@@ -139,7 +136,6 @@ struct ControlArgs {
   int seq;
 };
 void small_h_append_batch(const std::vector<HAppendArgs>& a, BatchUpload& up, hipStream_t s);
-void small_dgks_batch(const std::vector<DgksArgs>& a, BatchUpload& up, hipStream_t s);
 void small_extract_batch(const std::vector<ExtractArgs>& a, BatchUpload& up, hipStream_t s);
 void small_control_batch(const std::vector<ControlArgs>& a, BatchUpload& up, hipStream_t s);
 void small_rtr_accumulate(const double* C0, int ldc0, const double* C1, int total, int nb,
