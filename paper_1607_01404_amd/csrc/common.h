@@ -65,6 +65,20 @@ void* stream_alloc(size_t bytes, hipStream_t s);
 void stream_free(void* p, hipStream_t s);
 // release every block the cache keeps for stream s (before s is destroyed)
 void stream_cache_drop(hipStream_t s);
+// device scratch on a stream, returned to the stream-ordered cache when the
+// scope ends, also when an error unwinds it
+struct StreamScratch {
+  void* p;
+  hipStream_t s;
+  StreamScratch(size_t bytes, hipStream_t st) : p(stream_alloc(bytes, st)), s(st) {}
+  ~StreamScratch() { stream_free(p, s); }
+  StreamScratch(const StreamScratch&) = delete;
+  StreamScratch& operator=(const StreamScratch&) = delete;
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
 // small pinned host blocks (the solvers' control and status records), kept
 // for reuse per (device, size, flags): hipHostMalloc and hipHostFree are slow
 // and synchronise, which a batch of solves would otherwise pay per solver.

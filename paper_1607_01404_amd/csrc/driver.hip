@@ -2122,20 +2122,7 @@ struct MemMode {
   }
 };
 
-// Device scratch on a stream, returned to the stream-ordered cache when the
-// scope ends, also when an error unwinds it.
-struct StreamScratch {
-  void* p;
-  hipStream_t s;
-  StreamScratch(size_t bytes, hipStream_t st) : p(svds::stream_alloc(bytes, st)), s(st) {}
-  ~StreamScratch() { svds::stream_free(p, s); }
-  StreamScratch(const StreamScratch&) = delete;
-  StreamScratch& operator=(const StreamScratch&) = delete;
-  template <class T>
-  T* as() const {
-    return static_cast<T*>(p);
-  }
-};
+using svds::StreamScratch;
 
 void free_csr(svds::Csr32& c, const MemMode& mm) {
   mm.release(c.rp);

@@ -95,10 +95,9 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_add(int32_t* out, const int
 void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   int64_t nb = (n + kScanBlock - 1) / kScanBlock;
-  int32_t* bs = nullptr;
-  int32_t* bso = nullptr;
-  bs = static_cast<int32_t*>(stream_alloc(sizeof(int32_t) * nb, s));
-  bso = static_cast<int32_t*>(stream_alloc(sizeof(int32_t) * nb, s));
+  const StreamScratch sbs(sizeof(int32_t) * nb, s), sbso(sizeof(int32_t) * nb, s);
+  int32_t* bs = sbs.as<int32_t>();
+  int32_t* bso = sbso.as<int32_t>();
   k_scan_local<<<(unsigned)nb, kScanBlock, 0, s>>>(in, out, bs, n);
   SVDS_LAUNCH_CHECK();
   if (nb > 1) {
@@ -106,8 +105,6 @@ void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t 
     k_scan_add<<<(unsigned)nb, kScanBlock, 0, s>>>(out, bso, n);
     SVDS_LAUNCH_CHECK();
   }
-  stream_free(bs, s);
-  stream_free(bso, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -261,10 +258,10 @@ __global__ __launch_bounds__(kBinBlock) void k_bin_scatter(const int32_t* __rest
 void build_bins(Csr32& A, hipStream_t s) {
   int64_t rows = A.rows;
   int64_t nblk = std::max<int64_t>(1, (rows + kBinBlock - 1) / kBinBlock);
-  int32_t* counts = nullptr;
-  int32_t* offs = nullptr;
-  counts = static_cast<int32_t*>(stream_alloc(sizeof(int32_t) * (kNumBins * nblk + 1), s));
-  offs = static_cast<int32_t*>(stream_alloc(sizeof(int32_t) * (kNumBins * nblk + 1), s));
+  const StreamScratch sc(sizeof(int32_t) * (kNumBins * nblk + 1), s);
+  const StreamScratch so(sizeof(int32_t) * (kNumBins * nblk + 1), s);
+  int32_t* counts = sc.as<int32_t>();
+  int32_t* offs = so.as<int32_t>();
   SVDS_HIP(hipMemsetAsync(counts, 0, sizeof(int32_t) * (kNumBins * nblk + 1), s));
   k_bin_hist<<<(unsigned)nblk, kBinBlock, 0, s>>>(A.rp, rows, counts, nblk);
   SVDS_LAUNCH_CHECK();
@@ -295,8 +292,6 @@ void build_bins(Csr32& A, hipStream_t s) {
     A.merged_bin = std::max(lo, std::min(mb, hi));
   }
   A.heuristic_bin = A.merged_bin;
-  stream_free(counts, s);
-  stream_free(offs, s);
 }
 
 // ---------------------------------------------------------------------------
