@@ -238,11 +238,13 @@ def batched_extra(P, torch, nprob, nworkers=16, step_threads=16):
             "first16_workers_seconds": workers16, "generation_seconds": gen}
 
 
-def learned_extra(P, torch, full_seconds, replica=True):
+def learned_extra(P, torch, full_seconds, replica=True, full_runs=None, full_matvecs=0):
     """Learned-preconditioner workload: a preconditioner trained on the GPU from residuals of
     Jacobi solves on eight 32x32 coefficient fields (seeds 5001-5008),
     evaluated against Jacobi and no preconditioning on a held-out field
-    (seed 5000) at 128x128 and at the full 1024x1024 size (budget-capped)."""
+    (seed 5000) at 128x128 and at the full 1024x1024 size (time-capped at
+    full_seconds).  full_runs: the preconditioners run at full size (all when
+    None); full_matvecs > 0 raises the product budget of the full-size solves."""
     import numpy as np
     import synth
     degree = 15
@@ -274,10 +276,17 @@ def learned_extra(P, torch, full_seconds, replica=True):
     sizes = ((("replica_128x128", 128, 60.0),) if replica else ()) + (
         ("full_1024x1024", 1024, full_seconds),)
     for label, ng, cap in sizes:
+        full = ng == 1024
         B = synth.convdiff_workload(ng=ng, seed=5000)
         MB = P.Matrix.from_scipy(B)
         res = {"shape": list(B.shape), "nnz": int(B.nnz), "max_seconds": cap}
         for name, kw in runs:
+            if full and full_runs is not None and name not in full_runs:
+                continue
+            if full and full_matvecs > 0:
+                kw = dict(kw, max_matvecs=full_matvecs)
+            if cap > 60.0:  # long solves print a progress line every 2000 iterations
+                kw = dict(kw, print_level=2)
             log(f"learned extra: {label} {name}")
             torch.cuda.synchronize()
             t = time.perf_counter()
@@ -401,6 +410,11 @@ def main():
     ap.add_argument("--step-threads", type=int, default=16,
                     help="host threads of the in-step batched solve's set-up and clean-up")
     ap.add_argument("--workers", type=int, default=16, help="host workers of the batched extra's comparison (0: in step only)")
+    ap.add_argument("--full-runs", default=None,
+                    help="comma-separated preconditioners of the full-size learned-workload "
+                         "runs (none, jacobi, jacobi_gdk, block_jacobi_128, learned; default all)")
+    ap.add_argument("--full-matvecs", type=int, default=0,
+                    help="product budget of the full-size learned-workload solves (0: default)")
     ap.add_argument("--full-seconds", type=float, default=20.0,
                     help="time budget of each full-size convection-diffusion solve")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
@@ -438,7 +452,9 @@ def main():
         elif args.only == "batched":
             out = batched_extra(P, torch, max(args.batched, 16), args.workers, args.step_threads)
         elif args.only in ("learned", "learned_full"):
-            out, _ = learned_extra(P, torch, args.full_seconds, replica=args.only == "learned")
+            out, _ = learned_extra(P, torch, args.full_seconds, replica=args.only == "learned",
+                                   full_runs=args.full_runs.split(",") if args.full_runs else None,
+                                   full_matvecs=args.full_matvecs)
         elif args.only == "methods":
             out = methods_extra(P, torch, 30.0)
         else:

@@ -132,7 +132,8 @@ typedef struct svds_opts {
                           /* tolerance (testing)                            */
   int two_sided_cleanup;  /* 1 (default): final two-sided Rayleigh-Ritz     */
                           /* (SVD of U^T A V) of the returned vectors       */
-  int print_level;        /* 0 silent .. 5 per-iteration trace on stderr    */
+  int print_level;        /* 0 silent; 2 a progress line every 2000 iterations;
+                             3.. a trace line per iteration, on stderr       */
   int profile;            /* 1: time the sparse products, the basis         */
                           /* projections and the residual with HIP events  */
                           /* on `stream` and report them in svds_stats (one */

@@ -813,8 +813,10 @@ class Solver {
     return c;
   }
 
+  // stderr trace of the control decisions: every iteration from print level
+  // 3, every 2000th at level 2 (progress of long solves)
   void trace(const char* what, int it, const Ctl& c, int nc) {
-    if (o_.print_level < 3) return;
+    if (o_.print_level < 2 || (o_.print_level == 2 && it % 2000 != 0)) return;
     std::fprintf(stderr, "[svds] stage %d %s it %d g %d act %d nb %d rs %d nr %d sweeps %d res0 %.3e maxres %.3e val0 %.12e mv %lld\n",
                  stage_, what, it, gc_, c.action, c.nblock, c.restart, c.nr, c.eig_sweeps,
                  nc > 0 ? c.res[0] : 0.0, c.maxres, nc > 0 ? c.val[0] : 0.0, (long long)mv_);
