@@ -142,8 +142,7 @@ void gram_build(const Csr32& A, const GramPlan& G, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // product
 // ---------------------------------------------------------------------------
-// one workgroup per block.  The window's column pointers and the block's row
-// pointers are staged in LDS together (one round trip to memory for both);
+// one workgroup per block.  The window's column pointers are staged in LDS;
 // then y = A_blk X (kGramL lanes per row, kGramU nonzeros in flight per lane),
 // each value streamed being stored with its local row at its column-order
 // position (column pointer + rank) in LDS; then the window's partial sums
@@ -160,7 +159,6 @@ __global__ __launch_bounds__(kGramT) void k_gram_partial(
   __shared__ double vs[kGramMaxNnz];         // values in column order
   __shared__ uint8_t rs[kGramMaxNnz];        // their local rows
   __shared__ int32_t cpl[kGramMaxWidth + 1];  // the window's column pointers
-  __shared__ int32_t rpl[kGramMaxRows + 1];   // the block's row pointers
   __shared__ double ys[kGramMaxRows * B];
   const int t = threadIdx.x;
   const int64_t b = xcd_block(blockIdx.x, gridDim.x);
@@ -169,11 +167,10 @@ __global__ __launch_bounds__(kGramT) void k_gram_partial(
   const int w = hi[b] - c0 + 1;
   const int32_t* __restrict__ cp = colptr + poff[b] + b;
   for (int c = t; c <= w; c += kGramT) cpl[c] = cp[c];
-  for (int r = t; r <= (int)(r1 - r0); r += kGramT) rpl[r] = rp[r0 + r];
   __syncthreads();
   const int grp = t / L, lane = t % L;
   for (int rr = grp; rr < (int)(r1 - r0); rr += RPP) {
-    const int32_t a = rpl[rr], e = rpl[rr + 1];
+    const int32_t a = rp[r0 + rr], e = rp[r0 + rr + 1];
     double acc[B];
 #pragma unroll
     for (int j = 0; j < B; ++j) acc[j] = 0.0;
