@@ -238,13 +238,15 @@ def batched_extra(P, torch, nprob, nworkers=16, step_threads=16):
             "first16_workers_seconds": workers16, "generation_seconds": gen}
 
 
-def learned_extra(P, torch, full_seconds, replica=True, full_runs=None, full_matvecs=0):
+def learned_extra(P, torch, full_seconds, replica=True, full_runs=None, full_matvecs=0,
+                  full_grid=1024):
     """Learned-preconditioner workload: a preconditioner trained on the GPU from residuals of
     Jacobi solves on eight 32x32 coefficient fields (seeds 5001-5008),
     evaluated against Jacobi and no preconditioning on a held-out field
     (seed 5000) at 128x128 and at the full 1024x1024 size (time-capped at
     full_seconds).  full_runs: the preconditioners run at full size (all when
-    None); full_matvecs > 0 raises the product budget of the full-size solves."""
+    None); full_matvecs > 0 raises the product budget of the full-size solves;
+    full_grid < 1024 runs that leg on a smaller grid instead (scaling runs)."""
     import numpy as np
     import synth
     degree = 15
@@ -274,9 +276,9 @@ def learned_extra(P, torch, full_seconds, replica=True, full_runs=None, full_mat
             ("block_jacobi_128", dict(precond=P.PC_BLOCKJACOBI, pc_block=128)),
             ("learned", dict(precond=P.PC_LEARNED, pc_model=params, pc_degree=degree))]
     sizes = ((("replica_128x128", 128, 60.0),) if replica else ()) + (
-        ("full_1024x1024", 1024, full_seconds),)
+        (f"full_{full_grid}x{full_grid}", full_grid, full_seconds),)
     for label, ng, cap in sizes:
-        full = ng == 1024
+        full = label.startswith("full_")
         B = synth.convdiff_workload(ng=ng, seed=5000)
         MB = P.Matrix.from_scipy(B)
         res = {"shape": list(B.shape), "nnz": int(B.nnz), "max_seconds": cap}
@@ -413,6 +415,8 @@ def main():
     ap.add_argument("--full-runs", default=None,
                     help="comma-separated preconditioners of the full-size learned-workload "
                          "runs (none, jacobi, jacobi_gdk, block_jacobi_128, learned; default all)")
+    ap.add_argument("--full-grid", type=int, default=1024,
+                    help="grid of the full-size learned-workload leg (smaller for scaling runs)")
     ap.add_argument("--full-matvecs", type=int, default=0,
                     help="product budget of the full-size learned-workload solves (0: default)")
     ap.add_argument("--full-seconds", type=float, default=20.0,
@@ -454,7 +458,7 @@ def main():
         elif args.only in ("learned", "learned_full"):
             out, _ = learned_extra(P, torch, args.full_seconds, replica=args.only == "learned",
                                    full_runs=args.full_runs.split(",") if args.full_runs else None,
-                                   full_matvecs=args.full_matvecs)
+                                   full_matvecs=args.full_matvecs, full_grid=args.full_grid)
         elif args.only == "methods":
             out = methods_extra(P, torch, 30.0)
         else:

@@ -940,24 +940,36 @@ template int ts_residual<float>(const float*, const float*, int64_t, int64_t, in
 // preconditioned gather, row scaling, column copies
 // ---------------------------------------------------------------------------
 // Conversions between column-major columns and row-major compact blocks (the
-// operand layout of the sparse products).  The block width is a template
-// argument so that each thread issues all of its row's loads before its
-// stores, and a row's B values leave as one contiguous store sequence.
+// operand layout of the sparse products).  A workgroup moves tiles of 256
+// rows through LDS, so that both the column-major side (one row per lane)
+// and the row-major side (256 x B consecutive values, one per lane and
+// step) are read and written in whole wavefront-wide runs.
+constexpr int kPackRows = 256;  // rows per tile (the workgroup size)
+
 template <int B>
-__global__ void k_pack(const double* __restrict__ A, int64_t lda, const double* __restrict__ Bm,
-                       double beta, int64_t N, double* __restrict__ out) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < N; i += stride) {
-    double v[B];
+__global__ __launch_bounds__(kPackRows) void k_pack(const double* __restrict__ A, int64_t lda,
+                                                    const double* __restrict__ Bm, double beta,
+                                                    int64_t N, double* __restrict__ out) {
+  __shared__ double tile[kPackRows * (B + 1)];  // row stride B + 1 against bank conflicts
+  const int t = threadIdx.x;
+  for (int64_t r0 = (int64_t)blockIdx.x * kPackRows; r0 < N; r0 += (int64_t)gridDim.x * kPackRows) {
+    const int nr = (int)((N - r0 < kPackRows) ? N - r0 : kPackRows);
+    const int64_t i = r0 + t;
+    if (t < nr) {
+      double v[B];
 #pragma unroll
-    for (int c = 0; c < B; ++c) v[c] = A[i + c * lda];
-    if (Bm) {
+      for (int c = 0; c < B; ++c) v[c] = A[i + c * lda];
+      if (Bm) {
 #pragma unroll
-      for (int c = 0; c < B; ++c) v[c] = fma(beta, Bm[i + c * lda], v[c]);
+        for (int c = 0; c < B; ++c) v[c] = fma(beta, Bm[i + c * lda], v[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < B; ++c) tile[t * (B + 1) + c] = v[c];
     }
-#pragma unroll
-    for (int c = 0; c < B; ++c) out[i * B + c] = v[c];
+    __syncthreads();
+    double* __restrict__ o = out + r0 * B;
+    for (int k = t; k < nr * B; k += kPackRows) o[k] = tile[(k / B) * (B + 1) + k % B];
+    __syncthreads();
   }
 }
 
@@ -973,25 +985,29 @@ __device__ __forceinline__ void unpack_body(const UnpackArgs& a, int bx, int gx)
   const double* __restrict__ in = a.in;
   double* __restrict__ A = a.A;
   const int64_t N = a.N, lda = a.lda;
-  int64_t i = (int64_t)bx * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gx * blockDim.x;
-  for (; i < N; i += stride) {
-    double v[B];
+  __shared__ double tile[kPackRows * (B + 1)];  // row stride B + 1 against bank conflicts
+  const int t = threadIdx.x;
+  for (int64_t r0 = (int64_t)bx * kPackRows; r0 < N; r0 += (int64_t)gx * kPackRows) {
+    const int nr = (int)((N - r0 < kPackRows) ? N - r0 : kPackRows);
+    const double* __restrict__ src = in + r0 * B;
+    for (int k = t; k < nr * B; k += kPackRows) tile[(k / B) * (B + 1) + k % B] = src[k];
+    __syncthreads();
+    if (t < nr) {
 #pragma unroll
-    for (int c = 0; c < B; ++c) v[c] = in[i * B + c];
-#pragma unroll
-    for (int c = 0; c < B; ++c) A[i + c * lda] = v[c];
+      for (int c = 0; c < B; ++c) A[r0 + t + c * lda] = tile[t * (B + 1) + c];
+    }
+    __syncthreads();
   }
 }
 
 template <int B>
-__global__ void k_unpack(const double* __restrict__ in, int64_t N, double* __restrict__ A,
-                         int64_t lda) {
+__global__ __launch_bounds__(kPackRows) void k_unpack(const double* __restrict__ in, int64_t N,
+                                                      double* __restrict__ A, int64_t lda) {
   unpack_body<B>(UnpackArgs{in, N, A, lda}, blockIdx.x, gridDim.x);
 }
 
 template <int B>
-__global__ void k_unpack_batch(const UnpackArgs* a, BTiles t) {
+__global__ __launch_bounds__(kPackRows) void k_unpack_batch(const UnpackArgs* a, BTiles t) {
   const BTile q = batch_tile(t, blockIdx.x);
   if (q.p < 0) return;  // an idle slot of the placement
   unpack_body<B>(a[q.p], q.x, q.gx);
