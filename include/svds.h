@@ -29,9 +29,15 @@
  *    by (stream, size), at most 16 GiB for the process, reused by later calls
  *    on the same stream (svds_stream_release() frees the blocks of a stream
  *    before the caller destroys it); a table of SpMM launch shapes keyed by a
- *    matrix signature (autotuner); and in each prepared matrix the launch
- *    shapes its solves use per block width.  Distinct streams may run
- *    distinct solves concurrently, also on one prepared matrix.
+ *    matrix signature (autotuner); in each prepared matrix the launch
+ *    shapes its solves use per block width; up to 4096 small pinned host
+ *    records per (device, size) kept for reuse by later solves (control and
+ *    status records); and the 64 MiB static scratch array of
+ *    svds_matrix_normal_noalloc on every device the library runs on (part
+ *    of the loaded code, held until the process ends).  Distinct streams may
+ *    run distinct solves concurrently, also on one prepared matrix.
+ *  - Environment: SVDS_DEBUG (any value) prints the autotuner's trial
+ *    timings and the batched solve's phase times on stderr.
  */
 #ifndef SVDS_H
 #define SVDS_H
