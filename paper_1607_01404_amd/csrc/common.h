@@ -158,11 +158,6 @@ constexpr uint64_t kStreamInit = 0, kStreamNorm = 1, kStreamBreak = 2;
 // ---------------------------------------------------------------------------
 // device helpers
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
-}
 
 // a value moved between the lanes of a 16-lane row by a DPP pattern
 template <int CTRL>
@@ -193,6 +188,10 @@ __device__ __forceinline__ TV lane_sum(TV v) {
   if constexpr (L >= 64) v += __shfl_xor(v, 32, kWave);
   return v;
 }
+
+// sum over the 64 lanes of a wavefront (every lane ends with the same bits):
+// four DPP levels inside each 16-lane row, then two lane permutes across rows
+__device__ __forceinline__ double wave_sum(double v) { return lane_sum<double, 64>(v); }
 
 // MI355X dispatches consecutive workgroups round-robin over its 8 XCDs.  This
 // maps the hardware block index to a logical one so that logical neighbours

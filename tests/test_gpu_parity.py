@@ -320,6 +320,26 @@ def test_batched_in_step_matches_single_solves(P, precond):
                  what=f"in-step {i} vs LAPACK")
 
 
+def test_batched_in_step_many_problems_few_threads(P):
+    """Twenty problems in step (more than the eight XCD runs of a launch, so
+    runs hold several problems and large problems span runs) with three
+    set-up threads and autotuned launch shapes: every result is
+    bit-identical to its own svds_solve run afterwards."""
+    import torch
+    As = _batch(20, mmin=600, mmax=9000)
+    dev = [P._lib.to_device(A) + A.shape for A in As]
+    opts = dict(block_size=8, max_basis_size=35, min_restart_size=14, seed=23, precond=1)
+    _say("batched in step, 20 problems, 3 set-up threads, autotuned")
+    rc, res = P.solve_batched(dev, 4, "smallest", 1e-10, nworkers=-3, **opts)
+    assert rc == 0, [r[4] for r in res]
+    for i, (A, d) in enumerate(zip(As, dev)):
+        _say("single", i, A.shape)
+        sig, U, V, rn, st = P.solve(*d, 4, "smallest", 1e-10, **opts)
+        assert res[i][4]["converged"]
+        assert torch.equal(sig, res[i][0]) and torch.equal(U, res[i][1]) and torch.equal(V, res[i][2])
+        assert res[i][4]["matvecs"] == st["matvecs"], i
+
+
 def test_batched_empty_and_arguments(P):
     _say("batched empty")
     rc, res = P.solve_batched([], 4)
