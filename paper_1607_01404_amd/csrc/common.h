@@ -193,6 +193,98 @@ __device__ __forceinline__ TV lane_sum(TV v) {
 // four DPP levels inside each 16-lane row, then two lane permutes across rows
 __device__ __forceinline__ double wave_sum(double v) { return lane_sum<double, 64>(v); }
 
+// Sums of NA values (a power of two, 1..64) over the 64 lanes of a
+// wavefront at once, scattered over the lanes: a butterfly whose level j
+// pairs every lane with a partner, keeps half of the values still carried
+// (chosen by one lane bit) and adds the partner's copies of that half, so
+// each level moves half as many values as the one before.  The levels run
+// from the cheap DPP patterns inside a 16-lane row (row mirror, half-row
+// mirror, the two quad swaps) to the two lane permutes across rows, so the
+// permutes carry one value or two; a level's partner always has the same
+// values left as the lane itself.  On return v[0] of lane l holds the sum of
+// value rs_index<NA>(l); lanes that differ only in bits above the split
+// levels hold the same bits, and rs_owner<NA>(l) picks one of them.
+namespace rs_detail {
+constexpr int kBit[6] = {3, 2, 1, 0, 4, 5};  // lane bit that chooses the half, per level
+template <int LEVEL>
+__device__ __forceinline__ double partner(double x) {
+  if constexpr (LEVEL == 0) return dpp_row<0x140>(x);       // row mirror: 15 - i
+  else if constexpr (LEVEL == 1) return dpp_row<0x141>(x);  // half-row mirror: 7 - i
+  else if constexpr (LEVEL == 2) return dpp_row<0x4E>(x);   // quad swap: i ^ 2
+  else if constexpr (LEVEL == 3) return dpp_row<0xB1>(x);   // quad swap: i ^ 1
+  else if constexpr (LEVEL == 4) return __shfl_xor(x, 16, kWave);
+  else return __shfl_xor(x, 32, kWave);
+}
+template <int LEVEL, int S, int NA>
+__device__ __forceinline__ void level(double (&v)[NA], int lane) {
+  if constexpr (LEVEL < 6) {
+    if constexpr (S >= 2) {  // split: keep one half, add the partner's copy of it
+      const bool up = (lane >> kBit[LEVEL]) & 1;
+#pragma unroll
+      for (int k = 0; k < S / 2; ++k) {
+        const double keep = up ? v[k + S / 2] : v[k];
+        const double send = up ? v[k] : v[k + S / 2];
+        v[k] = keep + partner<LEVEL>(send);
+      }
+      level<LEVEL + 1, S / 2, NA>(v, lane);
+    } else {  // one value left: a plain sum with the partner
+      v[0] += partner<LEVEL>(v[0]);
+      level<LEVEL + 1, 1, NA>(v, lane);
+    }
+  }
+}
+}  // namespace rs_detail
+
+template <int NA>
+__device__ __forceinline__ double wave_reduce_scatter(double (&v)[NA]) {
+  static_assert(NA >= 1 && NA <= 64 && (NA & (NA - 1)) == 0, "NA: a power of two up to 64");
+  rs_detail::level<0, NA, NA>(v, (int)(threadIdx.x % kWave));
+  return v[0];
+}
+// the value whose sum lane l holds after wave_reduce_scatter<NA>
+template <int NA>
+__device__ __forceinline__ int rs_index(int lane) {
+  int idx = 0, s = NA;
+  for (int j = 0; j < 6 && s >= 2; ++j, s >>= 1)
+    if ((lane >> rs_detail::kBit[j]) & 1) idx += s / 2;
+  return idx;
+}
+// whether lane l is the one lane that reports its value (the others holding
+// the same value differ from it in the bits of the levels that only added)
+template <int NA>
+__device__ __forceinline__ bool rs_owner(int lane) {
+  int lv = 0;
+  for (int s = NA; s >= 2; s >>= 1) ++lv;
+  for (int j = lv; j < 6; ++j)
+    if ((lane >> rs_detail::kBit[j]) & 1) return false;
+  return true;
+}
+
+constexpr int pow2_at_least(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+// out[a] = the sum over the wavefront's lanes of acc[a], a < NA (any count):
+// reduce-scatters of up to 64 values (zero-padded to a power of two), each
+// sum written once by its owner lane.  acc is consumed.
+template <int NA>
+__device__ __forceinline__ void wave_sums_to(double (&acc)[NA], double* out) {
+  const int lane = (int)(threadIdx.x % kWave);
+#pragma unroll
+  for (int base = 0; base < NA; base += 64) {
+    constexpr int kChunk = NA < 64 ? NA : 64;
+    constexpr int NP = pow2_at_least(kChunk);
+    double v[NP];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) v[a] = (a < kChunk && base + a < NA) ? acc[(base + a < NA) ? base + a : 0] : 0.0;
+    const double r = wave_reduce_scatter<NP>(v);
+    const int idx = rs_index<NP>(lane);
+    if (rs_owner<NP>(lane) && idx < kChunk && base + idx < NA) out[base + idx] = r;
+  }
+}
+
 // MI355X dispatches consecutive workgroups round-robin over its 8 XCDs.  This
 // maps the hardware block index to a logical one so that logical neighbours
 // (adjacent row ranges, which share gathered vector entries) run on the same

@@ -43,12 +43,8 @@ __device__ __forceinline__ const TB* seg_col(const Segs3T<TB>& s, int v) {
 template <int NA>
 __device__ __forceinline__ void block_reduce_store(double (&acc)[NA], double* sh, double* out,
                                                    int64_t stride_out, int nvalid) {
-  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-#pragma unroll
-  for (int a = 0; a < NA; ++a) {
-    double v = wave_sum(acc[a]);
-    if (lane == 0) sh[w * NA + a] = v;
-  }
+  const int w = threadIdx.x / kWave;
+  wave_sums_to<NA>(acc, sh + w * NA);
   __syncthreads();
   for (int a = threadIdx.x; a < NA; a += kThreads) {
     if (a < nvalid) {
@@ -136,11 +132,7 @@ __device__ __forceinline__ void tsgemm_body(const TsgemmArgs<TB>& A, int bx, int
 #pragma unroll
         for (int c = 0; c < B; ++c) acc[jj * B + c] = fma(q[u][jj], tv[u][c], acc[jj * B + c]);
   }
-#pragma unroll
-  for (int a = 0; a < kCPW * B; ++a) {
-    const double v = wave_sum(acc[a]);
-    if (lane == 0) red[w][a] = v;
-  }
+  wave_sums_to<kCPW * B>(acc, red[w]);
   __syncthreads();
   // partial layout: [c * total + col][block]
   if (active && sub == 0 && lane < kCPW * B) {
@@ -726,11 +718,7 @@ __device__ __forceinline__ void cholqr_body(const CholQRArgs& A, int bx, int gx)
     }
   }
   if (!A.Pout) return;
-#pragma unroll
-  for (int a = 0; a < NG; ++a) {
-    const double v = wave_sum(g[a]);
-    if (lane == 0) red[w][a] = v;
-  }
+  wave_sums_to<NG>(g, red[w]);
   __syncthreads();
   if (t < NG) {
     int c = 0, c2 = 0, a = 0;
@@ -875,12 +863,8 @@ __device__ __forceinline__ void resid_body(const ResidArgs<TB>& A, int bx, int b
     }
   }
   // partial layout: [q * nc + cand][block]
-  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-#pragma unroll
-  for (int a = 0; a < NS * NCC; ++a) {
-    double v = wave_sum(acc[a]);
-    if (lane == 0) sh[w * NS * NCC + a] = v;
-  }
+  const int w = threadIdx.x / kWave;
+  wave_sums_to<NS * NCC>(acc, sh + w * NS * NCC);
   __syncthreads();
   for (int a = threadIdx.x; a < NS * NCC; a += kThreads) {
     const int c = a / NS, q = a % NS;

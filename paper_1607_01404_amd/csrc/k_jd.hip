@@ -46,12 +46,7 @@ __global__ __launch_bounds__(kJT) void k_jd_dots(const double* __restrict__ X,
       }
     }
   }
-  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-#pragma unroll
-  for (int j = 0; j < kMaxBlock; ++j) {
-    const double v = wave_sum(acc[j]);
-    if (lane == 0) sh[w][j] = v;
-  }
+  wave_sums_to<kMaxBlock>(acc, sh[threadIdx.x / kWave]);
   __syncthreads();
   if (threadIdx.x < nb) {
     double v = 0.0;
@@ -130,12 +125,7 @@ __global__ __launch_bounds__(kJT) void k_jd_resid(int64_t N, int nb, int64_t ld,
       }
     }
   }
-  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
-#pragma unroll
-  for (int j = 0; j < kMaxBlock; ++j) {
-    const double v = wave_sum(acc[j]);
-    if (lane == 0) sh[wv][j] = v;
-  }
+  wave_sums_to<kMaxBlock>(acc, sh[threadIdx.x / kWave]);
   __syncthreads();
   if (threadIdx.x < nb) {
     double v = 0.0;
