@@ -199,7 +199,9 @@ typedef struct svds_stats {
   double gram_bytes;      /* the method's bytes of those products: A read   */
                           /* once, X read and Z written once:               */
                           /* nnz*(8+4) + 4*(rows+1) + 16*b*cols per call    */
-                          /* (the plan's ranks, column pointers and window  */
+                          /* (the kernel reads a 16-bit window column and   */
+                          /* rank per nonzero in place of the 4-byte column */
+                          /* index; the plan's column pointers and window   */
                           /* partial sums are not counted)                  */
   /* filled when opts.profile = 1 (zero otherwise), FP64 iterations: */
   int64_t proj_calls;     /* basis projections timed (the first Gram-      */
@@ -253,7 +255,7 @@ int svds_matrix_spmm(const svds_matrix* h, int trans, int b, const double* X, do
  *   Z (p x b) = C X (p x b), row-major blocks as for svds_matrix_spmm.
  * The prepared matrix has a one-pass plan when, for some R in 16..128, every
  * block of R consecutive rows of A_w holds at most 2048 nonzeros and touches
- * a window of at most 1024 columns, the windows' first columns never
+ * a window of at most 512 columns, the windows' first columns never
  * decrease, and the windows' summed widths stay within 4 p (banded matrices
  * and other locally coupled ones).  With fused != 0, a plan, and fewer
  * algorithmic bytes than two SpMMs for this b, C X is formed in one read of

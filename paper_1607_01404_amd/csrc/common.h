@@ -427,16 +427,20 @@ struct GramPlan {
   int64_t* poff = nullptr;    // nblk + 1: window offsets, the prefix of the widths
   int32_t* colptr = nullptr;  // wsum + nblk: block-local column pointers; block
                               //   b's w_b + 1 entries start at poff[b] + b
-  uint8_t* rank = nullptr;    // nnz, CSR order: rank of the nonzero among its
-                              //   block's nonzeros in the same column (rows
-                              //   ascending)
+  uint16_t* cidx = nullptr;   // nnz, CSR order: the nonzero's window column
+                              //   (column - lo[b], kGramColBits bits), and
+                              //   above them its rank among the block's
+                              //   nonzeros in the same column (rows ascending)
   int32_t* cover = nullptr;   // cols: first block whose window holds the column
                               //   (nblk: none)
 };
 constexpr int kGramMaxNnz = 2048;    // nonzeros per block (staged in LDS)
-constexpr int kGramMaxWidth = 1024;  // columns per window
+constexpr int kGramMaxWidth = 512;   // columns per window
+constexpr int kGramColBits = 9;      // bits of a window column in GramPlan::cidx
 constexpr int kGramMinRows = 16;     // finest block the windows are measured at
 constexpr int kGramMaxRows = 128;    // tallest block
+static_assert(kGramMaxWidth <= (1 << kGramColBits) && kGramMaxRows <= (1 << (16 - kGramColBits)),
+              "a window column and a rank share 16 bits");
 // whether the one-pass product moves at most 90 % of the algorithmic bytes of
 // the two SpMMs for block width b (the rule of svds_matrix_normal)
 bool gram_cheaper(const Csr32& A, const GramPlan& G, int b);

@@ -45,7 +45,7 @@ void cleanup_finish(int k, const double* s, const double* Yq, int ldy, const dou
 // then A^T by two SpMMs, in algorithmic bytes; taken when it moves at most
 // 90 % of the two products' bytes
 bool gram_cheaper(const Csr32& A, const GramPlan& G, int b) {
-  const double fused = 13.0 * (double)A.nnz + 4.0 * (double)(A.rows + 1) + 8.0 * b * (double)A.cols +
+  const double fused = 10.0 * (double)A.nnz + 4.0 * (double)(A.rows + 1) + 8.0 * b * (double)A.cols +
                        (4.0 + 8.0 * b) * (double)G.wsum + 20.0 * (double)G.nblk +
                        8.0 * b * (double)G.wsum + (4.0 + 8.0 * b) * (double)A.cols;
   const double two = 24.0 * (double)A.nnz + 4.0 * (double)(A.rows + A.cols + 2) +
@@ -63,9 +63,10 @@ double now() {
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 // the method's bytes of one product Z = A^T (A X) on n x b blocks: A read
-// once (values, column indices, row pointers), X read and Z written once.
-// The one-pass product's own plan data (ranks, window column pointers, the
-// windows' partial sums) is overhead, not part of this count.
+// once in CSR (values, 32-bit column indices, row pointers), X read and Z
+// written once.  The one-pass product reads a 16-bit window column and rank
+// per nonzero in place of the column index; its other plan data (window
+// column pointers, the windows' partial sums) is overhead, not counted here.
 double gram_method_bytes(const Csr32& A, int b) {
   return 12.0 * (double)A.nnz + 4.0 * (double)(A.rows + 1) + 16.0 * b * (double)A.cols;
 }
@@ -2151,7 +2152,7 @@ void free_gram(svds::GramPlan& g, const MemMode& mm) {
   mm.release(g.hi);
   mm.release(g.poff);
   mm.release(g.colptr);
-  mm.release(g.rank);
+  mm.release(g.cidx);
   mm.release(g.cover);
   g = svds::GramPlan{};
 }
@@ -2213,7 +2214,7 @@ void build_gram_plan(svds_matrix* h, const MemMode& mm, hipStream_t s) {
     mm.alloc(&g.hi, nb);
     mm.alloc(&g.poff, nb + 1);
     mm.alloc(&g.colptr, g.wsum + nb);
-    mm.alloc(&g.rank, A.nnz);
+    mm.alloc(&g.cidx, A.nnz);
     mm.alloc(&g.cover, A.cols);
     SVDS_HIP(hipMemcpyAsync(g.lo, lo.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s));
     SVDS_HIP(hipMemcpyAsync(g.hi, hi.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s));

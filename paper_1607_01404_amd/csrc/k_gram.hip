@@ -4,8 +4,10 @@
 // column windows (banded matrices, discretised operators in a bandwidth-
 // reducing order), a workgroup takes one block: it forms y = A_blk X in LDS
 // from the block's CSR rows, storing each value it streams in LDS at its
-// position in a block-local column ordering (built once per matrix: a one-byte
-// rank per nonzero), and then A_blk^T y over its window from LDS.
+// position in a block-local column ordering (built once per matrix: per
+// nonzero, 16 bits holding its window column and its rank in that column,
+// read in place of the 32-bit column index), and then A_blk^T y over its
+// window from LDS.
 // A is read from HBM once per product instead of A and its transpose.  The
 // windows of neighbouring blocks overlap; a second kernel adds each column's
 // partial sums in block order.  Every sum has a fixed order, so the results
@@ -51,9 +53,9 @@ void gram_windows(const Csr32& A, int64_t nblk, int32_t* lo, int32_t* hi, int32_
 }
 
 // block-local column ordering: per block, the column pointers of its window
-// and, for each nonzero in CSR order, its rank among the block's nonzeros of
-// the same column (rows ascending), so that column-order position = column
-// pointer + rank.  Each column of the window gets a bit mask of the block's
+// and, for each nonzero in CSR order, its window column and its rank among
+// the block's nonzeros of the same column (rows ascending), packed in 16
+// bits, so that column-order position = column pointer + rank.  Each column of the window gets a bit mask of the block's
 // rows that hold it (set with atomic ORs, whose result does not depend on
 // their order); counts and ranks are population counts of these masks.
 __global__ __launch_bounds__(kGramT) void k_gram_csc(const int32_t* __restrict__ rp,
@@ -62,7 +64,7 @@ __global__ __launch_bounds__(kGramT) void k_gram_csc(const int32_t* __restrict__
                                                      const int32_t* __restrict__ hi,
                                                      const int64_t* __restrict__ poff,
                                                      int32_t* __restrict__ colptr,
-                                                     uint8_t* __restrict__ rank) {
+                                                     uint16_t* __restrict__ cidx) {
   constexpr int MW = kGramMaxRows / 64;  // mask words per column
   __shared__ unsigned long long mask[kGramMaxWidth * MW];
   __shared__ int32_t part[kGramT];
@@ -110,7 +112,7 @@ __global__ __launch_bounds__(kGramT) void k_gram_csc(const int32_t* __restrict__
       int below = 0;
       for (int q = 0; q < r / 64; ++q) below += __popcll(m[q]);
       below += __popcll(m[r / 64] & ((1ull << (r % 64)) - 1ull));
-      rank[k] = (uint8_t)below;
+      cidx[k] = (uint16_t)((ci[k] - c0) | (below << kGramColBits));
     }
 }
 
@@ -131,7 +133,7 @@ __global__ void k_gram_cover(const int32_t* __restrict__ lo, const int32_t* __re
 void gram_build(const Csr32& A, const GramPlan& G, hipStream_t s) {
   if (G.nblk <= 0) return;
   k_gram_csc<<<(unsigned)G.nblk, kGramT, 0, s>>>(A.rp, A.ci, A.rows, G.R, G.lo, G.hi, G.poff,
-                                                 G.colptr, G.rank);
+                                                 G.colptr, G.cidx);
   SVDS_LAUNCH_CHECK();
   k_fill_i32<<<(unsigned)((A.cols + 255) / 256), 256, 0, s>>>(G.cover, A.cols, (int32_t)G.nblk);
   SVDS_LAUNCH_CHECK();
@@ -150,8 +152,8 @@ void gram_build(const Csr32& A, const GramPlan& G, hipStream_t s) {
 // everything from LDS.
 template <int B>
 __global__ __launch_bounds__(kGramT) void k_gram_partial(
-    const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-    const double* __restrict__ val, const uint8_t* __restrict__ rank, int64_t rows, int R,
+    const int32_t* __restrict__ rp, const double* __restrict__ val,
+    const uint16_t* __restrict__ cidx, int64_t rows, int R,
     const double* __restrict__ X, const int32_t* __restrict__ lo,
     const int32_t* __restrict__ hi, const int64_t* __restrict__ poff,
     const int32_t* __restrict__ colptr, double* __restrict__ P) {
@@ -182,9 +184,10 @@ __global__ __launch_bounds__(kGramT) void k_gram_partial(
       for (int u = 0; u < U; ++u) {
         const int32_t k = k0 + u * L;
         const int32_t kk = k < e ? k : e - 1;
-        c[u] = ci[kk];
+        const int p = cidx[kk];
+        c[u] = c0 + (p & ((1 << kGramColBits) - 1));
         v[u] = val[kk];
-        rk[u] = rank[kk];
+        rk[u] = p >> kGramColBits;
       }
       double x[U][B];
 #pragma unroll
@@ -272,7 +275,7 @@ __global__ void k_gram_combine(const int32_t* __restrict__ cover, const int32_t*
 template <int B>
 static void partial_b(const Csr32& A, const GramPlan& G, const double* X, double* P,
                       hipStream_t s) {
-  k_gram_partial<B><<<(unsigned)G.nblk, kGramT, 0, s>>>(A.rp, A.ci, A.val, G.rank, A.rows, G.R,
+  k_gram_partial<B><<<(unsigned)G.nblk, kGramT, 0, s>>>(A.rp, A.val, G.cidx, A.rows, G.R,
                                                        X, G.lo, G.hi, G.poff, G.colptr, P);
 }
 
