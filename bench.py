@@ -35,10 +35,10 @@ SPMM_TRAFFIC = {"workload": "banded_1e6x5e5_k10_smallest", "bytes_per_launch": 2
 
 
 # the same for one product with C by the one-pass A^T A product: its partial-sum
-# kernel (283.5 MB) and its window combine (50.9 MB)
+# kernel (235.3 MB) and its window combine (50.9 MB)
 # (profiles/gram_banded_1e6x5e5_b4_fp64_hbm_traffic.md)
-GRAM_TRAFFIC = {"workload": "banded_1e6x5e5_k10_smallest", "bytes_per_launch": 334.4e6,
-                "source": "paper_1607_01404_amd/csrc/k_gram.hip", "sha256_prefix": "f501ebefc0458d4d"}
+GRAM_TRAFFIC = {"workload": "banded_1e6x5e5_k10_smallest", "bytes_per_launch": 286.2e6,
+                "source": "paper_1607_01404_amd/csrc/k_gram.hip", "sha256_prefix": "f1bd8a92e867a494"}
 
 
 def counted_traffic(t, workload):
