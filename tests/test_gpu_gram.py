@@ -94,6 +94,37 @@ def test_normal_product_wide_and_tiny(P):
         M.close()
 
 
+@pytest.mark.parametrize("h,want", [(192, 1), (193, 0)])
+def test_window_of_512_columns(P, h, want):
+    """Square 5120 x 5120, row i with 16 nonzeros in [i - h, i + h] (both ends
+    always among them).  At h = 192 every 128-row block spans exactly 512
+    columns, the widest window whose column fits the packed index's 9 bits:
+    the one-pass product runs.  At h = 193 the blocks span 514 columns, the
+    64-row blocks' windows add up to more than 4 x the column count, and
+    there is no plan.  Both agree with SciPy.  Block width 2: at 4 the
+    windows' partial sums of so sparse a band would cost more bytes than the
+    two products, and the product would not be taken either way."""
+    import torch
+    n = 128 * 40
+    rng = np.random.default_rng(12)
+    rows, cols = [], []
+    for i in range(n):
+        c = {min(max(i - h, 0), n - 1), min(max(i + h, 0), n - 1), i}
+        while len(c) < 16:
+            c.add(int(np.clip(i + rng.integers(-h, h + 1), 0, n - 1)))
+        rows += [i] * len(c)
+        cols += sorted(c)
+    A = sp.csr_matrix((rng.standard_normal(len(rows)), (rows, cols)), shape=(n, n))
+    A.sort_indices()
+    _say("normal product, windows of", 128 + 2 * h, "columns", A.shape)
+    M = P.Matrix.from_scipy(A)
+    X = np.random.default_rng(4).standard_normal((n, 2))
+    Z, used = M.normal(torch.from_numpy(X).cuda())
+    assert used == want
+    _check(A, X, Z.cpu().numpy())
+    M.close()
+
+
 def test_normal_product_falls_back_for_scattered_rows(P):
     import torch
     A = synth.powerlaw_workload(m=20000, n=10000)
