@@ -70,7 +70,11 @@ extern "C" {
 #define SVDS_MIXED 1            /* stage 1 stores the basis and does SpMM   */
                                 /* in FP32 with BF16 MFMA projections; the  */
                                 /* Rayleigh-Ritz eigenproblem, Gram matrix, */
-                                /* reorthogonalisation and stage 2 are FP64 */
+                                /* reorthogonalisation and stage 2 are FP64, */
+                                /* except that for the largest values the   */
+                                /* JD correction equation's products with B */
+                                /* use FP32 copies of A (the outer residuals */
+                                /* and convergence tests stay FP64)         */
 
 #define SVDS_PC_NONE 0          /* K = I                                     */
 #define SVDS_PC_JACOBI 1        /* K = diag(A^T A)^-1 on C (diag(A A^T) when */

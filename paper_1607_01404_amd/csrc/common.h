@@ -705,9 +705,14 @@ void jd_col_dots(const double* X, const double* Y, int64_t ld, int64_t N, int nb
 // state from ||r_0||^2 (n2) and r_0 . t_0 (rho0; null: n2); q = t_0, d = x = 0
 void jd_start(int64_t N, int nb, int64_t ld, const double* t, const double* n2,
               const double* rho0, JdCol* st, double* q, double* d, double* x, hipStream_t s);
-// w = (B q)_compact - s_j q
+// w = (B q)_compact - s_j q; the product in FP64 or, from the FP32 operator
+// of the mixed-precision correction, in FP32 (widened before the shift)
 void jd_shift(int64_t N, int nb, const double* Wc, const double* q, int64_t ld,
               const double* shift, double* w, hipStream_t s);
+void jd_shift(int64_t N, int nb, const float* Wc, const double* q, int64_t ld,
+              const double* shift, double* w, hipStream_t s);
+// c (row-major N x nb, FP32) = q (column-major, leading dimension ld), rounded
+void jd_pack_f32(const double* q, int64_t ld, int64_t N, int nb, float* c, hipStream_t s);
 // r -= alpha w, the scalar step, d and x; then q = r + beta q (t null) or t = r
 void jd_step(int64_t N, int nb, int64_t ld, double* r, const double* w, double* q, double* d,
              double* x, double* t, const double* sigma, double* rn2, double tol, JdCol* st,

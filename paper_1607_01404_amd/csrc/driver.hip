@@ -322,9 +322,17 @@ class Solver {
       // packing, the shifted product, the dots, the QMR step (and with a
       // preconditioner its dots and continuation)
       count(N8() * nb * (2.0 + 3.0 + 2.0 + 9.0 + (pc && it + 1 < maxit ? 5.0 : 0.0)));
-      pack_rows(jdQ_, ld_, nullptr, 0.0, N_, nb, Tc_, s_);
-      apply_op(Tc_, Wc_, nb);
-      jd_shift(N_, nb, Wc_, jdQ_, ld_, jdShift_, jdW_, s_);
+      if (jd32_) {  // the product with B through the FP32 copies of A and A^T
+        jd_pack_f32(jdQ_, ld_, N_, nb, Tc32_, s_);
+        timed_spmm(At(), nb, Tc32_ + n_ * nb, Wc32_);  // v-half: A^T x_u
+        timed_spmm(A(), nb, Tc32_, Wc32_ + n_ * nb);   // u-half: A x_v
+        mv_ += 2 * nb;
+        jd_shift(N_, nb, Wc32_, jdQ_, ld_, jdShift_, jdW_, s_);
+      } else {
+        pack_rows(jdQ_, ld_, nullptr, 0.0, N_, nb, Tc_, s_);
+        apply_op(Tc_, Wc_, nb);
+        jd_shift(N_, nb, Wc_, jdQ_, ld_, jdShift_, jdW_, s_);
+      }
       jd_project(jdW_, nb);
       jd_col_dots(jdQ_, jdW_, ld_, N_, nb, partial_, jdSig_, s_);
       jd_step(N_, nb, ld_, jdR_, jdW_, jdQ_, jdD_, T, pc ? jdT_ : nullptr, jdSig_, jdRn2_, tol,
@@ -346,6 +354,12 @@ class Solver {
     }
   }
   int64_t jd_inner_ = 0;
+  // mixed precision, largest values: the correction equation's products with
+  // B use the FP32 copies of A and A^T.  The shifts lie far from zero there,
+  // so the FP32 rounding of B (relative 6e-8) is small against the inner
+  // solve's own target (a reduction of 0.1); the outer residuals, the
+  // Rayleigh-Ritz step and every convergence test stay FP64.
+  bool jd32_ = false;
   // block-Jacobi preconditioner: inverses of the diagonal blocks of C
   double* bjK_ = nullptr;
   int bjnb_ = 0;
@@ -1208,6 +1222,7 @@ int Solver::stage2(const double* taus_h, double* V1, double* U1, double* sig, in
                    svds_stats* st) {
   stage_ = 2;
   jd_ = o_.stage2_solver == SVDS_STAGE2_JD;
+  jd32_ = jd_ && mixed_ && largest_;
   N_ = n_ + m_;
   gc_ = 0;
   nlock_ = 0;

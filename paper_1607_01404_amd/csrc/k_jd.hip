@@ -85,14 +85,25 @@ __global__ void k_jd_init_vecs(int64_t N, int nb, int64_t ld, const double* __re
 }
 
 // w = (B q)_compact - s_j q   (the product arrives as a row-major N x nb block)
-__global__ void k_jd_shift(int64_t N, int nb, const double* __restrict__ Wc,
+template <typename TW>
+__global__ void k_jd_shift(int64_t N, int nb, const TW* __restrict__ Wc,
                            const double* __restrict__ q, int64_t ld,
                            const double* __restrict__ shift, double* __restrict__ w) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t i = t / nb;
   const int j = (int)(t % nb);
   if (i >= N) return;
-  w[i + j * ld] = Wc[t] - shift[j] * q[i + j * ld];
+  w[i + j * ld] = (double)Wc[t] - shift[j] * q[i + j * ld];
+}
+
+// the direction block for the FP32 operator: row-major, rounded to FP32
+__global__ void k_jd_pack_f32(const double* __restrict__ q, int64_t ld, int64_t N, int nb,
+                              float* __restrict__ c) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = t / nb;
+  const int j = (int)(t % nb);
+  if (i >= N) return;
+  c[t] = (float)q[i + j * ld];
 }
 
 __device__ inline double step_alpha(const JdCol& c, double sigma) {
@@ -238,7 +249,19 @@ void jd_start(int64_t N, int nb, int64_t ld, const double* t, const double* n2,
 
 void jd_shift(int64_t N, int nb, const double* Wc, const double* q, int64_t ld,
               const double* shift, double* w, hipStream_t s) {
-  k_jd_shift<<<elem_blocks(N * nb), 256, 0, s>>>(N, nb, Wc, q, ld, shift, w);
+  k_jd_shift<double><<<elem_blocks(N * nb), 256, 0, s>>>(N, nb, Wc, q, ld, shift, w);
+  SVDS_LAUNCH_CHECK();
+}
+
+void jd_shift(int64_t N, int nb, const float* Wc, const double* q, int64_t ld,
+              const double* shift, double* w, hipStream_t s) {
+  k_jd_shift<float><<<elem_blocks(N * nb), 256, 0, s>>>(N, nb, Wc, q, ld, shift, w);
+  SVDS_LAUNCH_CHECK();
+}
+
+void jd_pack_f32(const double* q, int64_t ld, int64_t N, int nb, float* c, hipStream_t s) {
+  if (N <= 0 || nb <= 0) return;
+  k_jd_pack_f32<<<elem_blocks(N * nb), 256, 0, s>>>(q, ld, N, nb, c);
   SVDS_LAUNCH_CHECK();
 }
 
