@@ -38,7 +38,7 @@ SPMM_TRAFFIC = {"workload": "banded_1e6x5e5_k10_smallest", "bytes_per_launch": 2
 # kernel (235.3 MB) and its window combine (50.9 MB)
 # (profiles/gram_banded_1e6x5e5_b4_fp64_hbm_traffic.md)
 GRAM_TRAFFIC = {"workload": "banded_1e6x5e5_k10_smallest", "bytes_per_launch": 286.2e6,
-                "source": "paper_1607_01404_amd/csrc/k_gram.hip", "sha256_prefix": "f1bd8a92e867a494"}
+                "source": "paper_1607_01404_amd/csrc/k_gram.hip", "sha256_prefix": "76b9b564500f50c6"}
 
 
 def counted_traffic(t, workload):

@@ -55,9 +55,10 @@ void gram_windows(const Csr32& A, int64_t nblk, int32_t* lo, int32_t* hi, int32_
 // block-local column ordering: per block, the column pointers of its window
 // and, for each nonzero in CSR order, its window column and its rank among
 // the block's nonzeros of the same column (rows ascending), packed in 16
-// bits, so that column-order position = column pointer + rank.  Each column of the window gets a bit mask of the block's
-// rows that hold it (set with atomic ORs, whose result does not depend on
-// their order); counts and ranks are population counts of these masks.
+// bits, so that column-order position = column pointer + rank.  Each column
+// of the window gets a bit mask of the block's rows that hold it (set with
+// atomic ORs, whose result does not depend on their order); counts and ranks
+// are population counts of these masks.
 __global__ __launch_bounds__(kGramT) void k_gram_csc(const int32_t* __restrict__ rp,
                                                      const int32_t* __restrict__ ci, int64_t rows,
                                                      int R, const int32_t* __restrict__ lo,
