@@ -887,6 +887,10 @@ __global__ __launch_bounds__(kThreads) void k_residual_batch(const ResidArgs<dou
   resid_body<16, 1, double>(a[q.p], q.x, q.y, q.gx);
 }
 
+// workgroups of a residual launch on N rows: at most 512 (each thread then
+// takes several rows), so that the norm sums leave few partial sums
+static int resid_blocks(int64_t N) { return std::min(reduce_blocks(N), 512); }
+
 // nsplit >= N: one sum per candidate (||r||^2 in sums[c]); otherwise the six
 // sums of the two halves in sums[q*nc + c]
 template <typename TB>
@@ -894,7 +898,7 @@ int ts_residual(const TB* V, const TB* W, int64_t ld, int64_t N, int64_t nsplit,
                  const double* Y, int64_t ldy, const double* theta, int nc, double* R,
                  int64_t ldr, double* partial, double* sums, hipStream_t s) {
   if (g > kMaxBasis) throw Error(SVDS_ERR_ARG, "residual: basis too large");
-  int nb = reduce_blocks(N);
+  const int nb = resid_blocks(N);
   if (nsplit >= N) {
     constexpr int NCC = 16;
     dim3 grid(nb, (nc + NCC - 1) / NCC);
@@ -1478,7 +1482,7 @@ void ts_residual_batch(const std::vector<BatchResid>& jobs, BatchUpload& up, hip
     if (q.g > kMaxBasis) throw Error(SVDS_ERR_ARG, "residual: basis too large");
     args[j] = ResidArgs<double>{q.V, q.W, q.ld, q.N, q.N, q.g, q.Y, q.ldy, q.theta, q.nc,
                                 q.R, q.ldr, q.partial};
-    gx[j] = reduce_blocks(q.N);
+    gx[j] = resid_blocks(q.N);
     gy[j] = (q.nc + NCC - 1) / NCC;
     if (q.sums) red.push_back(BatchReduce{q.partial, gx[j], q.nc, q.sums, nullptr});
   }
