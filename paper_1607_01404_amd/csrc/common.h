@@ -466,6 +466,10 @@ struct svds_matrix {
   // then released with stream-ordered frees on the same stream
   hipStream_t owner = nullptr;
   bool stream_ordered = false;
+  // the device blocks every array above is carved from: the two matrices
+  // with diagC, and the plan G
+  void* block = nullptr;
+  void* gram_block = nullptr;
 };
 
 namespace svds {

@@ -2140,36 +2140,32 @@ struct MemMode {
   }
 };
 
+// Arrays carved, 256-byte aligned and in request order, from one block: a
+// first pass with no block only sums the sizes, a second hands out pointers.
+// A handle's arrays live in two blocks (the matrices with diag(C), the
+// one-pass product's plan), one allocation and one release each.
+struct Carve {
+  char* base = nullptr;
+  size_t used = 0;
+  template <class T>
+  void take(T** p, size_t count) {
+    const size_t off = (used + 255) & ~static_cast<size_t>(255);
+    used = off + sizeof(T) * std::max<size_t>(count, 1);
+    *p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+  }
+};
+
 using svds::StreamScratch;
 
-void free_csr(svds::Csr32& c, const MemMode& mm) {
-  mm.release(c.rp);
-  mm.release(c.ci);
-  mm.release(c.val);
-  mm.release(c.val32);
-  mm.release(c.binrows);
-  c = svds::Csr32{};
-}
-
-void alloc_csr(svds::Csr32& c, int64_t rows, int64_t cols, int64_t nnz, const MemMode& mm) {
+void carve_csr(svds::Csr32& c, int64_t rows, int64_t cols, int64_t nnz, Carve& k) {
   c.rows = rows;
   c.cols = cols;
   c.nnz = nnz;
-  mm.alloc(&c.rp, rows + 1);
-  mm.alloc(&c.ci, nnz);
-  mm.alloc(&c.val, nnz);
-  mm.alloc(&c.binrows, rows);
-  mm.alloc(&c.val32, nnz);
-}
-
-void free_gram(svds::GramPlan& g, const MemMode& mm) {
-  mm.release(g.lo);
-  mm.release(g.hi);
-  mm.release(g.poff);
-  mm.release(g.colptr);
-  mm.release(g.cidx);
-  mm.release(g.cover);
-  g = svds::GramPlan{};
+  k.take(&c.rp, rows + 1);
+  k.take(&c.ci, nnz);
+  k.take(&c.val, nnz);
+  k.take(&c.binrows, rows);
+  k.take(&c.val32, nnz);
 }
 
 // Plan of the one-pass A^T A product (k_gram.hip).  The windows are measured
@@ -2225,12 +2221,20 @@ void build_gram_plan(svds_matrix* h, const MemMode& mm, hipStream_t s) {
     g.R = R;
     g.nblk = nb;
     g.wsum = poff[nb];
-    mm.alloc(&g.lo, nb);
-    mm.alloc(&g.hi, nb);
-    mm.alloc(&g.poff, nb + 1);
-    mm.alloc(&g.colptr, g.wsum + nb);
-    mm.alloc(&g.cidx, A.nnz);
-    mm.alloc(&g.cover, A.cols);
+    auto lay = [&](Carve& c) {
+      c.take(&g.lo, nb);
+      c.take(&g.hi, nb);
+      c.take(&g.poff, nb + 1);
+      c.take(&g.colptr, g.wsum + nb);
+      c.take(&g.cidx, A.nnz);
+      c.take(&g.cover, A.cols);
+    };
+    Carve size;
+    lay(size);
+    Carve c;
+    mm.alloc(&c.base, size.used);
+    h->gram_block = c.base;
+    lay(c);
     SVDS_HIP(hipMemcpyAsync(g.lo, lo.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s));
     SVDS_HIP(hipMemcpyAsync(g.hi, hi.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s));
     SVDS_HIP(hipMemcpyAsync(g.poff, poff.data(), sizeof(int64_t) * (nb + 1),
@@ -2244,10 +2248,8 @@ void build_gram_plan(svds_matrix* h, const MemMode& mm, hipStream_t s) {
 void destroy_matrix(svds_matrix* h) {
   if (!h) return;
   const MemMode mm{h->stream_ordered, h->owner};
-  free_csr(h->A, mm);
-  free_csr(h->At, mm);
-  free_gram(h->G, mm);
-  mm.release(h->diagC);
+  mm.release(h->block);
+  mm.release(h->gram_block);
   delete h;
 }
 
@@ -2286,8 +2288,18 @@ int create_matrix(const svds_csr* A, svds_matrix** out, hipStream_t s, bool stre
     // into A_w and A_w^T at the end
     svds::Csr32& a = h->A;
     svds::Csr32& at = h->At;
-    alloc_csr(a, A->m, A->n, A->nnz, mm);
-    alloc_csr(at, A->n, A->m, A->nnz, mm);
+    double* diag = nullptr;  // diag(A_w^T A_w): A_w has min(m, n) columns
+    auto lay = [&](Carve& k) {
+      carve_csr(a, A->m, A->n, A->nnz, k);
+      carve_csr(at, A->n, A->m, A->nnz, k);
+      k.take(&diag, std::min(A->m, A->n));
+    };
+    Carve size;
+    lay(size);
+    Carve k;
+    mm.alloc(&k.base, size.used);
+    h->block = k.base;
+    lay(k);
     svds::copy_csr_arrays(*A, a, s);
     {
       const StreamScratch cursor(sizeof(int32_t) * (A->n + 1), s);
@@ -2299,7 +2311,7 @@ int create_matrix(const svds_csr* A, svds_matrix** out, hipStream_t s, bool stre
     svds::to_fp32(a.val, a.val32, A->nnz, s);
     svds::to_fp32(at.val, at.val32, A->nnz, s);
     if (h->transposed) std::swap(h->A, h->At);
-    mm.alloc(&h->diagC, h->A.cols);
+    h->diagC = diag;
     svds::row_sqnorms(h->At, h->diagC, s);  // rows of A_w^T = columns of A_w
     build_gram_plan(h, mm, s);
     SVDS_HIP(hipStreamSynchronize(s));
